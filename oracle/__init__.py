@@ -1,0 +1,37 @@
+"""FP64 CPU oracle for the shrink-and-expand block eigensolvers (arXiv 2409.05572).
+
+TEST INFRASTRUCTURE ONLY. Only ``tests/``, ``__graft_entry__.smoke()`` and the
+``cpu_baseline`` leg of ``bench.py`` may import this package. The product path
+(the HIP library and its Python binding) never calls it, and this package never
+imports the product path.
+
+The oracle is a plain, slow, readable restatement of the paper's algorithms in
+numpy/scipy FP64. It deliberately uses different factorizations from the GPU
+path (Householder QR instead of Cholesky-QR, LAPACK ``eigh`` instead of the
+GPU's tridiagonal solver) and recomputes every ``A S`` product with a fresh
+sparse product, so that agreement tests mathematics rather than shared code.
+
+Modules:
+* ``strategy`` - the ``fix`` / ``slope`` / ``slopek`` shrink-and-expand
+  decisions (Algorithms 6 and 7, Section 3.2) with the warm-up rule.
+* ``solvers``  - convergence measures (eqs. (conv) and (rk), Section 6.1),
+  LOBPCG with soft locking and the Hetmaniuk-Lehoucq basis (Algorithm 3),
+  and subspace iteration (Algorithm 1), both with shrink-and-expand
+  (Algorithm 5).
+
+Pins: see ``tests/test_oracle_*.py``. Parity unpinned (no closed form, checked
+only by invariants and by agreement with brute force at small sizes): the
+Anderson and Chung-Lu eigenvalues, and every iteration count / shrink-expand
+schedule produced on a matrix.
+"""
+from .strategy import SEParams, SEController  # noqa: F401
+from .solvers import (  # noqa: F401
+    SolveResult,
+    residual_measures,
+    orth,
+    rayleigh_ritz,
+    hl_basis,
+    si_step,
+    lobpcg,
+    subspace_iteration,
+)

@@ -1,0 +1,328 @@
+"""Block eigensolvers with shrink-and-expand, plain FP64 (oracle; test infrastructure only).
+
+Follows the paper (arXiv 2409.05572):
+* subspace iteration, Algorithm 1 (Section 2.1);
+* LOBPCG, Algorithm 3 (Section 2.3), with soft locking and the improved
+  Hetmaniuk-Lehoucq choice of P (Section 2.3 text), preconditioner T = I as in
+  the experiments (Section 6.2);
+* the shrink-and-expand framework, Algorithm 5 (Section 3.1), with the
+  strategies of Section 3.2 (see ``strategy.py``);
+* the per-pair stopping test, eq. (conv), and the overall relative residual
+  r(j), eq. (rk) (Section 6.1).
+
+Readings of points the paper leaves open (each also listed in the design notes):
+* Stopping test: a pair i <= n_ev is converged when
+  ``||A x_i - lambda_i x_i|| <= tol ||A|| ||x_i||``, which implies eq. (conv);
+  r(j) for the strategies is eq. (rk) over i <= n_ev.
+* Ordering: Ritz values are kept algebraically ascending.
+* Subspace iteration operator: one shifted power step ``X <- sigma X - A X``
+  with ``sigma >= lambda_max`` replaces the shift-invert solve of Algorithm 1,
+  so the dominant eigenvectors of ``sigma I - A`` are the smallest of ``A``;
+  Rayleigh-Ritz is done with ``A`` itself. Any other operator can be passed.
+* Soft locking: pairs i <= n_ev that pass the stopping test are locked; they
+  stay in X for the Rayleigh-Ritz step but leave W and P. The lock set is
+  re-evaluated at every iteration.
+* Hetmaniuk-Lehoucq basis: with S = [X, P, W] orthonormal and A_p = Z Theta Z^T,
+  X_new = S Z1 (Z1 = first k columns). In coefficient space the old active X
+  columns are unit vectors E; their part orthogonal to Z1 is Z2 (Z2^T E), so
+  P_new = S Z2 Q_B with Q_B an orthonormal basis of range(Z2^T E). Then
+  [X_new, P_new] is an orthonormal basis of span{X_new, X_old(active)}.
+* LOBPCG expansion: S_drop = [X_drop, P_drop] is orthogonalized against S and
+  orthonormalized; columns that come from X_drop go to X, the rest to P.
+* Orthogonalization drops columns whose norm after projection falls below
+  ``drop_tol`` times their norm before it.
+"""
+from __future__ import annotations
+
+import time
+from dataclasses import dataclass, field
+
+import numpy as np
+
+from .strategy import SEController, SEParams
+
+
+@dataclass
+class SolveResult:
+    lam: np.ndarray
+    V: np.ndarray
+    iterations: int
+    converged: bool
+    history: list = field(default_factory=list)
+    n_shrinks: int = 0
+    n_expands: int = 0
+    max_stop_ratio: float = np.inf
+    max_paper_ratio: float = np.inf
+
+
+def _apply(A, X):
+    """Sparse (or dense) matrix times block; a library product."""
+    return A @ X
+
+
+def residual_measures(A, X, lam, anorm):
+    """Residual block R = A X - X diag(lam) and the two per-column ratios.
+
+    ``stop``:  ||r_i|| / (||A|| ||x_i||)                 (stopping test)
+    ``paper``: ||r_i|| / (||A|| ||x_i|| + ||x_i|| |lam_i|) (eq. (conv) / (rk))
+    """
+    AX = _apply(A, X)
+    R = AX - X * lam[None, :]
+    rn = np.linalg.norm(R, axis=0)
+    xn = np.linalg.norm(X, axis=0)
+    stop = rn / (anorm * xn)
+    paper = rn / (anorm * xn + xn * np.abs(lam))
+    return R, stop, paper
+
+
+def orth(Y, drop_tol=1e-12):
+    """Orthonormal basis of range(Y), column order kept, dependent columns dropped.
+
+    Returns (Q, kept) where ``kept`` lists the columns of Y that contributed.
+    Fast path: Householder QR when no column is numerically dependent.
+    Otherwise: classical Gram-Schmidt applied twice per column, dropping a
+    column whose projected norm is below ``drop_tol`` times its own norm.
+    """
+    k = Y.shape[1]
+    if k == 0:
+        return Y.copy(), np.zeros(0, dtype=np.int64)
+    norms = np.linalg.norm(Y, axis=0)
+    Q, R = np.linalg.qr(Y, mode="reduced")
+    if np.all(np.abs(np.diag(R)) > drop_tol * norms) and np.all(norms > 0):
+        return Q, np.arange(k)
+    basis = []
+    kept = []
+    for i in range(k):
+        v = Y[:, i].copy()
+        if norms[i] == 0.0:
+            continue
+        for _ in range(2):
+            if basis:
+                Bm = np.stack(basis, axis=1)
+                v -= Bm @ (Bm.T @ v)
+        nv = np.linalg.norm(v)
+        if nv > drop_tol * norms[i]:
+            basis.append(v / nv)
+            kept.append(i)
+    if not basis:
+        return Y[:, :0].copy(), np.zeros(0, dtype=np.int64)
+    return np.stack(basis, axis=1), np.asarray(kept, dtype=np.int64)
+
+
+def rayleigh_ritz(S, AS):
+    """Ritz pairs of A on range(S) for orthonormal S: A_p = S^T (A S) = Z Theta Z^T.
+
+    Theta ascending (LAPACK ``eigh``); returns (theta, Z).
+    """
+    Ap = S.T @ AS
+    Ap = 0.5 * (Ap + Ap.T)
+    theta, Z = np.linalg.eigh(Ap)
+    return theta, Z
+
+
+def si_step(apply_op, A, X):
+    """One subspace-iteration step (Algorithm 1 body without shrink/expand).
+
+    X <- op(X); orthogonalize; Rayleigh-Ritz with A. Returns (theta, X_new).
+    """
+    Y = apply_op(X)
+    Q, _ = orth(Y)
+    theta, Z = rayleigh_ritz(Q, _apply(A, Q))
+    return theta, Q @ Z
+
+
+def hl_basis(Z, k, active, drop_tol=1e-12):
+    """Coefficients [Z1, C_P] of the improved Hetmaniuk-Lehoucq basis (Section 2.3).
+
+    ``Z`` (m x m) are the Ritz vectors of A_p in the basis S, ``k`` the width of
+    X and ``active`` the positions (within the first k columns of S) of the old
+    X columns that are not locked. Returns (Z1, C_P) with C_P = Z2 Q_B, where
+    Q_B is an orthonormal basis of range(Z2^T E).
+    """
+    Z1 = Z[:, :k]
+    Z2 = Z[:, k:]
+    B = Z2[np.asarray(active, dtype=np.int64), :].T
+    QB, _ = orth(B, drop_tol)
+    return Z1, Z2 @ QB
+
+
+def _se_enabled(params: SEParams, n_ev: int, n_es, nb: int) -> bool:
+    return params.strategy != "none" and n_es is not None and n_ev <= n_es < nb
+
+
+def lobpcg(
+    A,
+    X0,
+    n_ev,
+    anorm,
+    tol=1e-8,
+    n_es=None,
+    se: SEParams | None = None,
+    max_iter=1000,
+    soft_lock=True,
+    drop_tol=1e-12,
+    time_limit_s=None,
+):
+    """LOBPCG with soft locking, HL basis and shrink-and-expand (Algorithm 3)."""
+    se = se or SEParams()
+    nb = X0.shape[1]
+    ctl = SEController(se if _se_enabled(se, n_ev, n_es, nb) else SEParams("none"))
+    t0 = time.perf_counter()
+
+    # Initial Rayleigh-Ritz on the orthogonalized starting block.
+    X, _ = orth(np.asarray(X0, dtype=np.float64), drop_tol)
+    theta, Z = rayleigh_ritz(X, _apply(A, X))
+    X = X @ Z
+    lam = theta
+    P = X[:, :0]
+    Xdrop = Pdrop = None
+    history = []
+    n_shr = n_exp = 0
+    stop = paper = None
+
+    for j in range(1, max_iter + 1):
+        R, stop, paper = residual_measures(A, X, lam, anorm)
+        r_j = float(np.max(paper[:n_ev]))
+        ctl.observe(j, r_j)
+        conv = stop[:n_ev] <= tol
+        rec = dict(j=j, r=r_j, max_stop=float(np.max(stop[:n_ev])), k=X.shape[1],
+                   p=P.shape[1], locked=0, a=0, expand=False, shrink=False)
+        history.append(rec)
+        if np.all(conv):
+            return SolveResult(lam[:n_ev].copy(), X[:, :n_ev].copy(), j, True, history,
+                               n_shr, n_exp, float(np.max(stop[:n_ev])), r_j)
+        if time_limit_s is not None and time.perf_counter() - t0 > time_limit_s:
+            break
+
+        k = X.shape[1]
+        locked = np.zeros(k, dtype=bool)
+        if soft_lock:
+            locked[:n_ev] = conv
+        active = np.flatnonzero(~locked)
+        expand = ctl.ifexpand(j)
+
+        # W <- T R with T = I, restricted to the active columns; orthogonalize
+        # against [X, P] (projection applied twice) and orthonormalize.
+        W = R[:, active]
+        XP = np.hstack([X, P])
+        for _ in range(2):
+            W = W - XP @ (XP.T @ W)
+        W, _ = orth(W, drop_tol)
+
+        if expand and Xdrop is not None:
+            S = np.hstack([X, P, W])
+            Sd = np.hstack([Xdrop, Pdrop])
+            d = Xdrop.shape[1]
+            for _ in range(2):
+                Sd = Sd - S @ (S.T @ Sd)
+            Sd, kept = orth(Sd, drop_tol)
+            to_x = kept < d
+            new_x = np.arange(k, k + int(np.count_nonzero(to_x)))
+            X = np.hstack([X, Sd[:, to_x]])
+            P = np.hstack([P, Sd[:, ~to_x]])
+            active = np.concatenate([active, new_x])
+            Xdrop = Pdrop = None
+            ctl.did_expand(j)
+            n_exp += 1
+            rec["expand"] = True
+
+        S = np.hstack([X, P, W])
+        k = X.shape[1]
+        theta, Z = rayleigh_ritz(S, _apply(A, S))
+        Z1, CP = hl_basis(Z, k, active, drop_tol)
+        X = S @ Z1
+        P = S @ CP
+        lam = theta[:k].copy()
+        rec.update(locked=int(np.count_nonzero(locked)), a=W.shape[1],
+                   theta=lam[:n_ev].copy())
+
+        if ctl.ifshrink(j):
+            Xdrop = X[:, n_es:]
+            Pdrop = P[:, n_es:]
+            X = X[:, :n_es]
+            P = P[:, :n_es]
+            lam = lam[:n_es]
+            ctl.did_shrink(j)
+            n_shr += 1
+            rec["shrink"] = True
+
+    ms = float(np.max(stop[:n_ev])) if stop is not None else np.inf
+    mp = float(np.max(paper[:n_ev])) if paper is not None else np.inf
+    return SolveResult(lam[:n_ev].copy(), X[:, :n_ev].copy(), len(history), False, history,
+                       n_shr, n_exp, ms, mp)
+
+
+def subspace_iteration(
+    A,
+    X0,
+    n_ev,
+    anorm,
+    sigma=None,
+    tol=1e-8,
+    n_es=None,
+    se: SEParams | None = None,
+    max_iter=20000,
+    apply_op=None,
+    drop_tol=1e-12,
+    time_limit_s=None,
+):
+    """Subspace iteration with Rayleigh-Ritz and shrink-and-expand (Algorithm 1).
+
+    ``apply_op`` defaults to the shifted power step X -> sigma X - A X with
+    ``sigma = anorm`` when not given.
+    """
+    se = se or SEParams()
+    nb = X0.shape[1]
+    ctl = SEController(se if _se_enabled(se, n_ev, n_es, nb) else SEParams("none"))
+    if apply_op is None:
+        s = anorm if sigma is None else sigma
+        apply_op = lambda Y: s * Y - _apply(A, Y)  # noqa: E731
+    t0 = time.perf_counter()
+
+    X, _ = orth(np.asarray(X0, dtype=np.float64), drop_tol)
+    theta, Z = rayleigh_ritz(X, _apply(A, X))
+    X = X @ Z
+    lam = theta
+    Xdrop = None
+    history = []
+    n_shr = n_exp = 0
+    stop = paper = None
+
+    for j in range(1, max_iter + 1):
+        _, stop, paper = residual_measures(A, X, lam, anorm)
+        r_j = float(np.max(paper[:n_ev]))
+        ctl.observe(j, r_j)
+        rec = dict(j=j, r=r_j, max_stop=float(np.max(stop[:n_ev])), k=X.shape[1],
+                   expand=False, shrink=False)
+        history.append(rec)
+        if np.all(stop[:n_ev] <= tol):
+            return SolveResult(lam[:n_ev].copy(), X[:, :n_ev].copy(), j, True, history,
+                               n_shr, n_exp, float(np.max(stop[:n_ev])), r_j)
+        if time_limit_s is not None and time.perf_counter() - t0 > time_limit_s:
+            break
+
+        Y = apply_op(X)
+        if ctl.ifexpand(j) and Xdrop is not None:
+            Y = np.hstack([Y, Xdrop])
+            Xdrop = None
+            ctl.did_expand(j)
+            n_exp += 1
+            rec["expand"] = True
+        X, _ = orth(Y, drop_tol)
+        theta, Z = rayleigh_ritz(X, _apply(A, X))
+        X = X @ Z
+        lam = theta.copy()
+        rec["theta"] = lam[:n_ev].copy()
+
+        if ctl.ifshrink(j):
+            Xdrop = X[:, n_es:]
+            X = X[:, :n_es]
+            lam = lam[:n_es]
+            ctl.did_shrink(j)
+            n_shr += 1
+            rec["shrink"] = True
+
+    ms = float(np.max(stop[:n_ev])) if stop is not None else np.inf
+    mp = float(np.max(paper[:n_ev])) if paper is not None else np.inf
+    return SolveResult(lam[:n_ev].copy(), X[:, :n_ev].copy(), len(history), False, history,
+                       n_shr, n_exp, ms, mp)

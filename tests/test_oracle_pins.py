@@ -1,0 +1,223 @@
+"""The FP64 oracle against facts fixed by the paper and by mathematics (CPU only)."""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+import oracle as O
+import workloads as W
+from tests import _pins as pins
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _golden(name):
+    with open(os.path.join(GOLDEN, name)) as f:
+        return json.load(f)
+
+
+# --- Section 4 worked example (3 x 3), values printed in the paper -----------
+
+def _inverse_op(A):
+    return lambda X: np.linalg.solve(A, X)
+
+
+def test_worked_example_si_step_matches_printed_values():
+    g = _golden("worked_example_3x3.json")
+    A = np.diag(g["A_diag"])
+    X0 = np.array(g["X0"])
+    theta, X1 = O.si_step(_inverse_op(A), A, X0)
+    X1 = pins.normalize_signs(X1)
+    printed = np.array(g["si_step_X1"])
+    for v, p in zip(X1.ravel(), printed.ravel()):
+        assert pins.matches_printed(v, p), (v, p)
+    assert np.all(np.diff(theta) > 0)
+    assert pins.matches_printed(pins.prop1_rate(A, X1[:, 0]), g["si_step_rho_x1"])
+
+
+def test_worked_example_power_step_and_rate():
+    g = _golden("worked_example_3x3.json")
+    A = np.diag(g["A_diag"])
+    x0 = np.array(g["X0"])[:, :1]
+    _, x1 = O.si_step(_inverse_op(A), A, x0)
+    x1 = pins.normalize_signs(x1)[:, 0]
+    ref = np.array(g["power_step_x1_times_sqrt10101"]) / math.sqrt(10101.0)
+    assert np.allclose(x1, ref, rtol=1e-14, atol=1e-16)
+    assert pins.matches_printed(pins.prop1_rate(A, x1), g["power_step_rho"], digits=3)
+
+
+def test_worked_example_expanded_step_matches_printed_values():
+    g = _golden("worked_example_3x3.json")
+    A = np.diag(g["A_diag"])
+    X0 = np.array(g["X0"])
+    _, x1 = O.si_step(_inverse_op(A), A, X0[:, :1])
+    Xexp = np.hstack([x1, X0[:, 1:2]])
+    _, X2 = O.si_step(_inverse_op(A), A, Xexp)
+    X2 = pins.normalize_signs(X2)
+    printed = np.array(g["expanded_step_X2"])
+    for v, p in zip(X2.ravel(), printed.ravel()):
+        assert pins.matches_printed(v, p), (v, p)
+    rho = pins.prop1_rate(A, X2[:, 0])
+    assert pins.matches_printed(rho, g["expanded_step_rho_x1"])
+    assert rho < 0.5 * g["asymptotic_rate"]
+
+
+# --- Closed-form spectra ------------------------------------------------------
+
+def _check(res, A, exact, tol=1e-8, lam_rtol=1e-10):
+    return pins.eigen_failures(res.lam, res.V, A.to_scipy(), A.anorm, exact, tol, lam_rtol)
+
+
+def test_config1_lobpcg_matches_closed_form():
+    A = W.laplacian_2d(32)
+    X0 = W.gaussian_block(A.n, 16, 201)
+    res = O.lobpcg(A.to_scipy(), X0, 8, A.anorm, tol=1e-8)
+    assert res.converged
+    assert _check(res, A, pins.laplacian_spectrum(32, 2, 8)) == []
+
+
+def test_config1_subspace_iteration_matches_closed_form():
+    A = W.laplacian_2d(32)
+    X0 = W.gaussian_block(A.n, 16, 201)
+    res = O.subspace_iteration(A.to_scipy(), X0, 8, A.anorm, tol=1e-8)
+    assert res.converged
+    # |dlambda| <~ ||r||^2 / gap with ||r|| <= 1e-8 ||A||; gap(lam_8, lam_17) ~ 0.11
+    assert _check(res, A, pins.laplacian_spectrum(32, 2, 8), lam_rtol=1e-9) == []
+
+
+@pytest.mark.parametrize("strategy", ["none", "fix", "slope", "slopek"])
+def test_lobpcg_shrink_expand_matches_closed_form_3d(strategy):
+    m, n_ev, nb, n_es = 14, 24, 36, 29
+    A = W.laplacian_3d(m)
+    X0 = W.gaussian_block(A.n, nb, 11)
+    res = O.lobpcg(A.to_scipy(), X0, n_ev, A.anorm, tol=1e-8, n_es=n_es,
+                   se=O.SEParams(strategy))
+    assert res.converged
+    assert _check(res, A, pins.laplacian_spectrum(m, 3, n_ev), lam_rtol=1e-9) == []
+    if strategy != "none":
+        assert res.n_shrinks >= 1
+
+
+@pytest.mark.parametrize("strategy", ["fix", "slopek"])
+def test_si_shrink_expand_matches_closed_form(strategy):
+    m, n_ev, nb = 20, 6, 12
+    A = W.laplacian_2d(m)
+    X0 = W.gaussian_block(A.n, nb, 5)
+    res = O.subspace_iteration(A.to_scipy(), X0, n_ev, A.anorm, tol=1e-8, n_es=n_ev + 2,
+                               se=O.SEParams(strategy))
+    assert res.converged
+    assert res.n_shrinks >= 1
+    assert _check(res, A, pins.laplacian_spectrum(m, 2, n_ev), lam_rtol=1e-9) == []
+
+
+# --- Invariants -----------------------------------------------------------------
+
+def test_lobpcg_ritz_values_bound_from_above_and_decrease():
+    """Courant-Fischer: theta_i >= lambda_i; the LOBPCG space keeps all of X, so
+    theta_i never increases (shrink keeps the first n_es, expansion only adds)."""
+    m, n_ev = 12, 16
+    A = W.laplacian_3d(m)
+    exact = pins.laplacian_spectrum(m, 3, n_ev)
+    X0 = W.gaussian_block(A.n, 24, 3)
+    res = O.lobpcg(A.to_scipy(), X0, n_ev, A.anorm, tol=1e-9, n_es=n_ev + 3,
+                   se=O.SEParams("fix", r_warm=1e-2))
+    assert res.converged and res.n_shrinks >= 1
+    thetas = [h["theta"] for h in res.history if "theta" in h]
+    for t in thetas:
+        assert np.all(t >= exact * (1 - 1e-13) - 1e-15)
+    for a, b in zip(thetas, thetas[1:]):
+        assert np.all(b <= a + 1e-13 * np.abs(a))
+
+
+def test_si_ritz_values_bound_from_above():
+    A = W.laplacian_2d(16)
+    exact = pins.laplacian_spectrum(16, 2, 4)
+    X0 = W.gaussian_block(A.n, 8, 2)
+    res = O.subspace_iteration(A.to_scipy(), X0, 4, A.anorm, tol=1e-8)
+    for h in res.history:
+        if "theta" in h:
+            assert np.all(h["theta"] >= exact * (1 - 1e-13))
+
+
+def test_orth_is_orthonormal_and_spans_input():
+    rng = np.random.default_rng(0)
+    Y = rng.standard_normal((500, 12)) @ np.diag(np.logspace(0, -9, 12))
+    Q, kept = O.orth(Y)
+    assert kept.tolist() == list(range(12))
+    assert np.abs(Q.T @ Q - np.eye(12)).max() < 1e-12
+    assert np.linalg.norm(Y - Q @ (Q.T @ Y)) < 1e-12 * np.linalg.norm(Y)
+
+
+def test_orth_drops_dependent_columns_in_order():
+    rng = np.random.default_rng(1)
+    B = rng.standard_normal((300, 4))
+    Y = np.hstack([B[:, :2], B[:, :1] * 3 - B[:, 1:2], B[:, 2:]])  # column 2 dependent
+    Q, kept = O.orth(Y)
+    assert kept.tolist() == [0, 1, 3, 4]
+    assert np.abs(Q.T @ Q - np.eye(4)).max() < 1e-12
+    assert np.linalg.norm(Y - Q @ (Q.T @ Y)) < 1e-11 * np.linalg.norm(Y)
+
+
+def test_hl_basis_spans_new_and_old_active_x():
+    """[Z1, C_P] orthonormal and its span equals span{Z1, E_active} (Section 2.3)."""
+    rng = np.random.default_rng(2)
+    m, k = 30, 8
+    Z, _ = np.linalg.qr(rng.standard_normal((m, m)))
+    active = np.array([1, 2, 4, 5, 7])
+    Z1, CP = O.hl_basis(Z, k, active)
+    assert CP.shape == (m, active.size)
+    C = np.hstack([Z1, CP])
+    assert np.abs(C.T @ C - np.eye(C.shape[1])).max() < 1e-13
+    E = np.eye(m)[:, active]
+    # E lies in span(C), and span(C) has exactly dim k + |active|
+    assert np.linalg.norm(E - C @ (C.T @ E)) < 1e-12
+    assert np.linalg.matrix_rank(np.hstack([Z1, E]), tol=1e-10) == C.shape[1]
+
+
+# --- Brute force on tiny inputs ----------------------------------------------------
+
+@pytest.mark.parametrize("seed", [0, 1])
+def test_brute_force_random_sparse_spd(seed):
+    A = W.random_sparse_spd(150, 0.05, seed)
+    dense = A.to_scipy().toarray()
+    exact = np.linalg.eigvalsh(dense)[:6]
+    X0 = W.gaussian_block(A.n, 10, 100 + seed)
+    for res in (
+        O.lobpcg(A.to_scipy(), X0, 6, A.anorm, tol=1e-10),
+        O.lobpcg(A.to_scipy(), X0, 6, A.anorm, tol=1e-10, n_es=8,
+                 se=O.SEParams("slopek", r_warm=1e-1)),
+        O.subspace_iteration(A.to_scipy(), X0, 6, A.anorm, tol=1e-10, max_iter=50000),
+    ):
+        assert res.converged
+        assert pins.eigen_failures(res.lam, res.V, dense, A.anorm, exact, 1e-10, 1e-9) == []
+
+
+# --- Theorem 1 (Section 5, eq. (convergerate)) on random SPD matrices -----------------
+
+@pytest.mark.parametrize("seed", range(5))
+def test_theorem1_rate_bound_for_one_si_step(seed):
+    rng = np.random.default_rng(seed)
+    n, k, l = 40, 3, 7
+    V, _ = np.linalg.qr(rng.standard_normal((n, n)))
+    sig = np.sort(rng.uniform(0.1, 10.0, size=n))[::-1]
+    B = (V * sig) @ V.T
+    X, _ = np.linalg.qr(rng.standard_normal((n, k)))
+    _, Xn = O.si_step(lambda Y: B @ Y, B, X)
+    lhs = pins.tan_angle(V[:, :k], V[:, k:], Xn) / pins.tan_angle(V[:, :k], V[:, k:], X)
+    rhs = pins.theorem1_bound(sig, V.T @ X, k, l)
+    assert lhs <= rhs * (1 + 1e-10)
+
+
+# --- Shrink-and-expand leaves the answer unchanged ------------------------------------
+
+def test_shrink_expand_does_not_change_the_answer():
+    A = W.laplacian_3d(12)
+    X0 = W.gaussian_block(A.n, 24, 9)
+    base = O.lobpcg(A.to_scipy(), X0, 16, A.anorm, tol=1e-9)
+    for s in ("fix", "slope", "slopek"):
+        r = O.lobpcg(A.to_scipy(), X0, 16, A.anorm, tol=1e-9, n_es=19, se=O.SEParams(s))
+        assert r.converged
+        assert np.max(np.abs(r.lam - base.lam) / base.lam) < 1e-10

@@ -1,0 +1,214 @@
+"""Seeded synthetic inputs for the shrink-and-expand eigensolvers.
+
+This module is shared by the FP64 oracle, the tests and the benchmark. It only
+builds inputs: sparse symmetric matrices in CSR form, an upper bound on their
+2-norm (the ``||A||_2`` that the per-pair stopping test of the paper's
+numerical section scales the residual by), and seeded Gaussian starting blocks.
+It contains none of the eigensolver arithmetic.
+
+Matrix families (shapes of the workloads the solvers are measured on):
+
+* ``laplacian_2d(m)``: 5-point Dirichlet Laplacian on an m x m grid,
+  ``T_m (x) I + I (x) T_m`` with ``T_m = tridiag(-1, 2, -1)``, lexicographic
+  order with the first grid index fastest.
+* ``laplacian_3d(m)``: 7-point Dirichlet Laplacian on an m^3 grid, same order.
+* ``anderson_3d(m, w, seed)``: ``laplacian_3d(m)`` plus a diagonal potential
+  drawn uniformly from [-w, w] (Anderson-type model, indefinite for w > 0).
+* ``chung_lu_laplacian(n, mean_degree, exponent, seed)``: normalized graph
+  Laplacian ``I - D^{-1/2} A_g D^{-1/2}`` of a connected Chung-Lu power-law
+  graph with unit weights.
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass
+
+import numpy as np
+import scipy.sparse as sp
+
+
+@dataclass
+class CSRMatrix:
+    """Real symmetric sparse matrix in CSR form with its full pattern stored."""
+
+    n: int
+    rowptr: np.ndarray  # int64, n + 1
+    colind: np.ndarray  # int32, nnz, sorted within each row
+    val: np.ndarray  # float64, nnz
+    anorm: float  # an upper bound of ||A||_2 (exact where a closed form exists)
+    name: str = ""
+
+    @property
+    def nnz(self) -> int:
+        return int(self.rowptr[-1])
+
+    def to_scipy(self) -> sp.csr_matrix:
+        return sp.csr_matrix(
+            (self.val, self.colind.astype(np.int64), self.rowptr), shape=(self.n, self.n)
+        )
+
+
+def _from_scipy(a: sp.spmatrix, anorm: float, name: str) -> CSRMatrix:
+    a = sp.csr_matrix(a, dtype=np.float64)
+    a.sum_duplicates()
+    a.sort_indices()
+    return CSRMatrix(
+        n=a.shape[0],
+        rowptr=np.ascontiguousarray(a.indptr, dtype=np.int64),
+        colind=np.ascontiguousarray(a.indices, dtype=np.int32),
+        val=np.ascontiguousarray(a.data, dtype=np.float64),
+        anorm=float(anorm),
+        name=name,
+    )
+
+
+def _second_difference(m: int) -> sp.csr_matrix:
+    off = -np.ones(m - 1)
+    return sp.diags([off, 2.0 * np.ones(m), off], [-1, 0, 1], format="csr")
+
+
+def dirichlet_laplacian_max_eig(m: int, dim: int) -> float:
+    """Largest eigenvalue of the dim-dimensional m-point Dirichlet Laplacian.
+
+    Used as the exact ``||A||_2`` input of the stopping test.
+    """
+    return dim * (2.0 - 2.0 * math.cos(m * math.pi / (m + 1)))
+
+
+def laplacian_2d(m: int) -> CSRMatrix:
+    t = _second_difference(m)
+    eye = sp.identity(m, format="csr")
+    a = sp.kron(eye, t) + sp.kron(t, eye)
+    return _from_scipy(a, dirichlet_laplacian_max_eig(m, 2), f"laplace2d_{m}x{m}")
+
+
+def laplacian_3d(m: int) -> CSRMatrix:
+    t = _second_difference(m)
+    eye = sp.identity(m, format="csr")
+    a = (
+        sp.kron(eye, sp.kron(eye, t))
+        + sp.kron(eye, sp.kron(t, eye))
+        + sp.kron(t, sp.kron(eye, eye))
+    )
+    return _from_scipy(a, dirichlet_laplacian_max_eig(m, 3), f"laplace3d_{m}^3")
+
+
+def anderson_3d(m: int, w: float, seed: int) -> CSRMatrix:
+    """3-D 7-point Laplacian plus a uniform random diagonal potential in [-w, w].
+
+    ``anorm`` is the Gershgorin bound 12 + w.
+    """
+    base = laplacian_3d(m).to_scipy()
+    rng = np.random.default_rng(seed)
+    pot = rng.uniform(-w, w, size=base.shape[0])
+    a = base + sp.diags(pot, 0, format="csr")
+    return _from_scipy(a, 12.0 + w, f"anderson3d_{m}^3_w{w:g}")
+
+
+def potential_laplacian(m: int, dim: int, w: float, seed: int) -> CSRMatrix:
+    """2-D or 3-D Dirichlet Laplacian plus a uniform diagonal potential in [-w, w]."""
+    base = (laplacian_2d(m) if dim == 2 else laplacian_3d(m)).to_scipy()
+    rng = np.random.default_rng(seed)
+    pot = rng.uniform(-w, w, size=base.shape[0])
+    a = base + sp.diags(pot, 0, format="csr")
+    return _from_scipy(a, 4.0 * dim + w, f"laplace{dim}d_{m}_w{w:g}")
+
+
+def chung_lu_laplacian(n: int, mean_degree: float, exponent: float, seed: int) -> CSRMatrix:
+    """Normalized Laplacian of a connected Chung-Lu graph with power-law degrees.
+
+    Expected degrees ``w_i = c (i + i0)^(-1/(exponent-1))`` are scaled to the
+    requested mean, with ``i0`` chosen so that ``max w <= sqrt(sum w)``. Each
+    unordered pair {i, j} is an edge with probability ``min(1, w_i w_j / sum w)``,
+    sampled per row with geometric skips (Miller and Hagberg, 2011). Self loops
+    and duplicates are dropped. Every vertex outside the largest connected
+    component is then joined by one edge to a uniformly chosen vertex of it, so
+    the graph is connected and the Laplacian has a simple zero eigenvalue with
+    eigenvector ``D^{1/2} 1``. Spectrum lies in [0, 2]; ``anorm`` = 2.
+    """
+    from scipy.sparse.csgraph import connected_components
+
+    rng = np.random.default_rng(seed)
+    gamma = 1.0 / (exponent - 1.0)
+    # choose i0 so that the largest expected degree stays below sqrt(sum w)
+    i0 = 1.0
+    for _ in range(60):
+        idx = np.arange(n, dtype=np.float64) + i0
+        w = idx ** (-gamma)
+        w *= mean_degree * n / w.sum()
+        if w[0] <= math.sqrt(w.sum()):
+            break
+        i0 *= 1.5
+    total = w.sum()
+    rows: list[np.ndarray] = []
+    cols: list[np.ndarray] = []
+    # weights are non-increasing in i, so p_ij <= w_i w_i' / total for j >= i'
+    for i in range(n - 1):
+        j = i + 1
+        p = min(1.0, w[i] * w[j] / total)
+        out_j = []
+        while j < n and p > 0.0:
+            if p < 1.0:
+                r = rng.random()
+                j += int(math.floor(math.log(r) / math.log1p(-p)))
+            if j >= n:
+                break
+            q = min(1.0, w[i] * w[j] / total)
+            if rng.random() < q / p:
+                out_j.append(j)
+            p = q
+            j += 1
+        if out_j:
+            rows.append(np.full(len(out_j), i, dtype=np.int64))
+            cols.append(np.asarray(out_j, dtype=np.int64))
+    r = np.concatenate(rows) if rows else np.zeros(0, np.int64)
+    c = np.concatenate(cols) if cols else np.zeros(0, np.int64)
+    g = sp.coo_matrix((np.ones(r.size), (r, c)), shape=(n, n)).tocsr()
+    g = g + g.T
+    g.data[:] = 1.0
+    ncomp, labels = connected_components(g, directed=False)
+    if ncomp > 1:
+        big = np.bincount(labels).argmax()
+        inside = np.flatnonzero(labels == big)
+        outside = np.flatnonzero(labels != big)
+        targets = inside[rng.integers(0, inside.size, size=outside.size)]
+        extra = sp.coo_matrix(
+            (np.ones(outside.size), (outside, targets)), shape=(n, n)
+        ).tocsr()
+        g = g + extra + extra.T
+        g.data[:] = 1.0
+    deg = np.asarray(g.sum(axis=1)).ravel()
+    dinv = 1.0 / np.sqrt(deg)
+    lap = sp.identity(n, format="csr") - sp.diags(dinv) @ g @ sp.diags(dinv)
+    return _from_scipy(lap, 2.0, f"chunglu_{n}_d{mean_degree:g}_b{exponent:g}")
+
+
+def gaussian_block(n: int, nb: int, seed: int) -> np.ndarray:
+    """Seeded N(0, 1) starting block, n x nb, Fortran (column-major) order."""
+    rng = np.random.default_rng(seed)
+    return np.asfortranarray(rng.standard_normal((nb, n)).T)
+
+
+def random_sparse_spd(n: int, density: float, seed: int) -> CSRMatrix:
+    """Small random sparse symmetric positive definite matrix (diagonally dominant)."""
+    rng = np.random.default_rng(seed)
+    b = sp.random(n, n, density=density, random_state=rng, format="csr")
+    b = b + b.T
+    absrow = np.asarray(abs(b).sum(axis=1)).ravel()
+    a = b + sp.diags(absrow + rng.uniform(0.1, 1.0, size=n))
+    dense = a.toarray()
+    bound = float(np.max(np.abs(dense).sum(axis=1)))
+    return _from_scipy(a, bound, f"rand_spd_{n}")
+
+
+# Named workloads. Each entry gives the matrix builder and the solver shape.
+WORKLOADS = {
+    "laplace2d_32": dict(build=lambda: laplacian_2d(32), n_ev=8, n_extra=8, x0_seed=201),
+    "laplace3d_128": dict(build=lambda: laplacian_3d(128), n_ev=64, n_extra=32, x0_seed=202),
+    "anderson3d_100": dict(
+        build=lambda: anderson_3d(100, 4.0, 103), n_ev=200, n_extra=50, x0_seed=203
+    ),
+    "chunglu_500k": dict(
+        build=lambda: chung_lu_laplacian(500_000, 16.0, 2.5, 104), n_ev=32, n_extra=16, x0_seed=204
+    ),
+}
