@@ -1,0 +1,207 @@
+/*
+ * se.h - shrink-and-expand block eigensolvers for MI355X (gfx950).
+ *
+ * Computes the n_ev algebraically smallest eigenpairs A V = V Lambda of a large
+ * sparse real symmetric matrix A (the problem statement of arXiv 2409.05572,
+ * Section 1) with LOBPCG (Algorithm 3, Section 2.3) or subspace iteration
+ * (Algorithm 1, Section 2.1), optionally shrinking and expanding the block
+ * between iterations (Algorithm 5, Section 3.1) by the fix / slope / slopek
+ * strategies (Algorithms 6 and 7, Section 3.2).
+ *
+ * Conventions for every call:
+ *   - Return value se_status: 0 = SE_OK, > 0 warning (outputs valid),
+ *     < 0 error (output buffers untouched unless stated otherwise).
+ *   - No call aborts or exits the process; no C++ exception crosses this ABI.
+ *   - "device pointer" means memory on the context's GPU (hipMalloc or any
+ *     allocator of the same HIP runtime); "host pointer" means pageable or
+ *     pinned host memory.
+ *   - All work is enqueued on the context's stream. Calls that return results
+ *     to the caller (se_solve) synchronize that stream before returning.
+ *   - A context is not thread-safe: one host thread uses a context at a time.
+ *     Different contexts are independent.
+ */
+#ifndef SE_H
+#define SE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int se_status;
+
+#define SE_OK 0
+#define SE_NOT_CONVERGED 1      /* max_iter or time limit reached; best iterate returned */
+#define SE_ERR_INVALID_ARG (-1) /* bad sizes, malformed CSR, non-finite values, NULL */
+#define SE_ERR_OOM (-2)         /* device allocation failed */
+#define SE_ERR_HIP (-3)         /* a HIP runtime call failed (see se_info.hip_error) */
+#define SE_ERR_BREAKDOWN (-4)   /* orthogonalization lost every column */
+#define SE_ERR_REJECTED (-5)    /* request larger than the configured memory budget */
+#define SE_ERR_UNSUPPORTED (-6) /* option not available in this build */
+
+typedef struct se_ctx se_ctx;
+typedef struct se_matrix se_matrix;
+
+/* Solvers. */
+#define SE_LOBPCG 0 /* Algorithm 3 with soft locking and the Hetmaniuk-Lehoucq basis */
+#define SE_SI 1     /* Algorithm 1 with the shifted power step X <- sigma X - A X */
+
+/* Shrink-and-expand strategies (Section 3.2). */
+#define SE_STRAT_NONE 0
+#define SE_STRAT_FIX 1    /* Algorithm 6 */
+#define SE_STRAT_SLOPE 2  /* Algorithm 7 with eq. (ckslope) */
+#define SE_STRAT_SLOPEK 3 /* Algorithm 7 with eq. (ckslopek) */
+
+/* Arithmetic of the bulk (n-length) work. */
+#define SE_FP64 0
+
+/* Where X0, V and lambda of se_solve live. */
+#define SE_PTR_HOST 0
+#define SE_PTR_DEVICE 1
+
+/* se_matrix_create_csr flags. */
+#define SE_MATRIX_HOST 0x0   /* rowptr/colind/val are host pointers */
+#define SE_MATRIX_DEVICE 0x1 /* rowptr/colind/val are device pointers */
+
+/* Columns of one history row (se_params.history). */
+#define SE_HISTORY_FIELDS 8
+/* j, r(j) by eq. (rk), max stop ratio, width k, width p, active a, locked, flags
+ * (bit 0 = expanded this iteration, bit 1 = shrunk this iteration) */
+
+typedef struct se_params {
+    int32_t solver;      /* SE_LOBPCG or SE_SI */
+    int32_t strategy;    /* SE_STRAT_* */
+    int32_t precision;   /* SE_FP64 */
+    int32_t ptr_mode;    /* SE_PTR_HOST or SE_PTR_DEVICE for X0, V, lambda */
+    int32_t n_ev;        /* wanted eigenpairs, >= 1 */
+    int32_t n_extra;     /* extra block columns: block size nb = n_ev + n_extra <= n */
+    int32_t n_es;        /* width kept at a shrink; 0 = n_ev + min(5, n_extra - 1) */
+    int32_t soft_lock;   /* LOBPCG: 1 = lock converged pairs (Section 6.2 setting) */
+    int32_t j_e;         /* fix: expansion period (paper: 12) */
+    int32_t j_s;         /* iterations from an expansion to the next shrink (paper: 2) */
+    int32_t j_p;         /* slopek averaging window (paper: 10) */
+    int32_t j_warm;      /* warm-up: first shrink not before iteration j_warm (paper: 5) */
+    int32_t max_iter;    /* iteration cap (default 1000 LOBPCG, 20000 SI) */
+    int32_t profile;     /* 1 = time each phase with HIP events (adds syncs) */
+    double mu;           /* slope threshold (paper: 1.1) */
+    double r_warm;       /* warm-up: first shrink once r(j) <= r_warm (paper: 1e-4) */
+    double tol;          /* stop when ||A x_i - lambda_i x_i|| <= tol ||A|| ||x_i||, i <= n_ev */
+    double sigma;        /* SI shift, must bound lambda_max from above; 0 = ||A|| */
+    double time_limit_s; /* wall-clock cap; <= 0 = none */
+    uint64_t seed;       /* reserved for generated starting blocks */
+    double* history;     /* optional host buffer of history_cap x SE_HISTORY_FIELDS doubles */
+    int32_t history_cap; /* rows available in history */
+    int32_t reserved;
+} se_params;
+
+typedef struct se_info {
+    int32_t iterations;     /* iterations performed */
+    int32_t converged;      /* 1 if every pair i <= n_ev met the stopping test */
+    int32_t n_shrinks;
+    int32_t n_expands;
+    double max_stop_ratio;  /* max_i ||A x_i - lambda_i x_i|| / (||A|| ||x_i||), fresh product */
+    double max_paper_ratio; /* eq. (rk) on the returned pairs, fresh product */
+    double time_ms;         /* wall time of the solve on the stream */
+    double phase_ms[8];     /* spmm, residual, orthogonalize W, A_p Gram, eigensolve,
+                               basis update, expansion, small dense (profile = 1 only) */
+    uint64_t workspace_bytes; /* device workspace held by the context after the call */
+    int32_t hip_error;      /* first failing hipError_t, 0 if none */
+    int32_t history_len;    /* rows written to params.history */
+} se_info;
+
+/* Fill *p with the defaults of the paper's experiments (Section 6.1-6.2):
+ * LOBPCG, no strategy, soft locking on, j_e = 12, j_s = 2, mu = 1.1, j_p = 10,
+ * j_warm = 5, r_warm = 1e-4, tol = 1e-8, max_iter = 1000, host pointers. */
+void se_params_default(se_params* p);
+
+/* Create a context bound to HIP device `device` and stream `stream`
+ * (a hipStream_t; NULL = the device's null stream). The stream is borrowed:
+ * it must outlive the context. Errors: SE_ERR_INVALID_ARG (bad device or
+ * out == NULL), SE_ERR_HIP. */
+se_status se_ctx_create(int device, void* stream, se_ctx** out);
+/* Release the context and its workspace. NULL is ignored. */
+void se_ctx_destroy(se_ctx* ctx);
+
+/* Create a real symmetric CSR matrix on the context's device (Section 1: the
+ * Hermitian A; real case). The full symmetric pattern must be stored.
+ *   n      rows (= columns), >= 1
+ *   nnz    stored entries, rowptr[n] == nnz
+ *   rowptr n + 1 int64 offsets, non-decreasing, rowptr[0] == 0
+ *   colind nnz int32 column indices in [0, n)
+ *   val    nnz finite doubles
+ *   anorm  ||A||_2 or an upper bound of it (used by the stopping test and as
+ *          the default SI shift); must be > 0
+ * The library copies the arrays (host or device per `flags`); the caller's
+ * buffers may be freed after the call. Offsets, index range and finiteness are
+ * validated on the host in both modes (device arrays are copied back for it).
+ * Errors: SE_ERR_INVALID_ARG, SE_ERR_OOM, SE_ERR_HIP. */
+se_status se_matrix_create_csr(se_ctx* ctx, int64_t n, int64_t nnz, const int64_t* rowptr,
+                               const int32_t* colind, const double* val, uint32_t flags,
+                               double anorm, se_matrix** out);
+void se_matrix_destroy(se_matrix* m);
+int64_t se_matrix_n(const se_matrix* m);
+
+/* Solve for the n_ev smallest eigenpairs (Algorithms 1 / 3 with Algorithm 5).
+ *   X0     n x nb starting block, column-major, leading dimension n,
+ *          nb = n_ev + n_extra; must have full column rank
+ *   V      output n x n_ev eigenvectors, column-major, leading dimension n
+ *   lambda output n_ev eigenvalues, ascending
+ * X0, V and lambda are host or device pointers per params->ptr_mode and are
+ * owned by the caller. info may be NULL. Returns SE_OK when converged,
+ * SE_NOT_CONVERGED with the best iterate in V/lambda when max_iter or the time
+ * limit is reached, or an error (< 0) with V/lambda untouched. */
+se_status se_solve(se_ctx* ctx, const se_matrix* A, const se_params* params, const double* X0,
+                   double* V, double* lambda, se_info* info);
+
+/* ---- Building blocks of one Rayleigh-Ritz step (device pointers, FP64) ----
+ * Blocks are row-major: element (i, c) of an n x w block B with leading
+ * dimension ld is B[i * ld + c]; ld must be even and >= w, pointers 16-byte
+ * aligned. These calls enqueue on the context's stream and do not synchronize
+ * except where a host output is written. */
+
+/* Y = A X: the sparse-times-block product behind A_p = S^T A S (Algorithm 3)
+ * and the SI update (Algorithm 1). X and Y are n x w, w in [1, 256]. */
+se_status se_op_spmm(se_ctx* ctx, const se_matrix* A, const double* X, int64_t ldx, double* Y,
+                     int64_t ldy, int32_t w);
+
+/* C = U^T V (mu x mv, row-major, leading dimension mv), the tall-skinny Gram
+ * products of the orthogonalization and projection steps. U is n x mu, V is
+ * n x mv, 1 <= mu, mv <= 1024. Summation order is fixed (deterministic). */
+se_status se_op_gram(se_ctx* ctx, int64_t n, const double* U, int64_t ldu, int32_t mu,
+                     const double* V, int64_t ldv, int32_t mv, double* C);
+
+/* Out = beta * Out + U C: the basis updates X <- S Z, W <- W - [X,P] G and the
+ * Cholesky-QR apply. U is n x K, C is K x N row-major (leading dimension N),
+ * Out is n x N; 1 <= K, N <= 1024; beta is 0 or 1; Out must not overlap U. */
+se_status se_op_update(se_ctx* ctx, int64_t n, const double* U, int64_t ldu, int32_t K,
+                       const double* C, int32_t N, double* Out, int64_t ldo, double beta);
+
+/* Symmetric eigendecomposition A = Z diag(w) Z^T of an m x m matrix (the
+ * spectral decomposition of A_p in Algorithms 1 and 3), 1 <= m <= 1024.
+ * A (row-major, symmetric) is overwritten; w ascending; Z row-major with
+ * eigenvector c in column c. Synchronizes the stream. */
+se_status se_op_syev(se_ctx* ctx, int32_t m, double* A, double* w, double* Z);
+
+/* Orthonormalize the w columns of the n x w block W in place by Cholesky-QR
+ * applied twice, dropping numerically dependent columns (the "orthogonalize"
+ * step of Algorithms 1 and 3). *rank receives the number of columns kept;
+ * they are compacted to the front. Synchronizes the stream. */
+se_status se_op_cholqr(se_ctx* ctx, int64_t n, double* W, int64_t ldw, int32_t w, int32_t* rank);
+
+/* Replay the shrink-and-expand controller (the strategy and warm-up rule of
+ * Section 3.2 selected in params) on a scripted sequence r(1..count) of
+ * eq. (rk) values, without a matrix or a GPU. flags[j-1] receives bit 0 when
+ * iteration j expands and bit 1 when it shrinks. Host-only. */
+se_status se_strategy_replay(const se_params* params, int32_t count, const double* r,
+                             int32_t* flags);
+
+/* Static description of a status code. */
+const char* se_status_string(se_status s);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SE_H */

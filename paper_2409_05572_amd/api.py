@@ -1,0 +1,204 @@
+"""Python binding of the C ABI: argument marshalling only.
+
+Device memory comes from torch (ROCm build); the solver, every n-length
+operation and every small dense step run in the HIP library. Nothing here
+computes any part of the method.
+"""
+from __future__ import annotations
+
+import ctypes as C
+from dataclasses import dataclass, field
+
+import numpy as np
+
+from . import _lib
+from ._lib import SeInfo, SeParams, check, lib
+
+
+def _ptr(x) -> int:
+    """Raw address of a numpy array or a torch tensor."""
+    if isinstance(x, np.ndarray):
+        return x.ctypes.data
+    return x.data_ptr()
+
+
+class Context:
+    """Library context bound to one device and one stream (torch stream or raw)."""
+
+    def __init__(self, device: int = 0, stream=None):
+        import torch
+
+        self.device = device
+        if stream is None:
+            stream = torch.cuda.current_stream(device)
+        self._stream = stream
+        raw = stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream or 0)
+        h = C.c_void_p()
+        check(lib().se_ctx_create(device, C.c_void_p(raw), C.byref(h)), "se_ctx_create")
+        self._h = h
+
+    @property
+    def handle(self):
+        return self._h
+
+    def close(self):
+        if self._h:
+            lib().se_ctx_destroy(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Matrix:
+    """Symmetric CSR matrix copied to the device (se_matrix_create_csr)."""
+
+    def __init__(self, ctx: Context, n, rowptr, colind, val, anorm, on_device=False):
+        self.ctx = ctx
+        self.n = int(n)
+        if not on_device:
+            rowptr = np.ascontiguousarray(rowptr, dtype=np.int64)
+            colind = np.ascontiguousarray(colind, dtype=np.int32)
+            val = np.ascontiguousarray(val, dtype=np.float64)
+        self._keep = (rowptr, colind, val)
+        h = C.c_void_p()
+        flags = _lib.SE_MATRIX_DEVICE if on_device else _lib.SE_MATRIX_HOST
+        nnz = int(rowptr[-1]) if not on_device else int(colind.numel())
+        check(lib().se_matrix_create_csr(ctx.handle, self.n, nnz, C.c_void_p(_ptr(rowptr)),
+                                         C.c_void_p(_ptr(colind)), C.c_void_p(_ptr(val)), flags,
+                                         float(anorm), C.byref(h)), "se_matrix_create_csr")
+        self._h = h
+        self._keep = None
+        self.anorm = float(anorm)
+
+    @classmethod
+    def from_csr(cls, ctx: Context, csr) -> "Matrix":
+        """From any object with n, rowptr, colind, val and anorm attributes."""
+        return cls(ctx, csr.n, csr.rowptr, csr.colind, csr.val, csr.anorm)
+
+    @property
+    def handle(self):
+        return self._h
+
+    def close(self):
+        if self._h:
+            lib().se_matrix_destroy(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+@dataclass
+class SolveInfo:
+    status: int
+    iterations: int
+    converged: bool
+    n_shrinks: int
+    n_expands: int
+    max_stop_ratio: float
+    max_paper_ratio: float
+    time_ms: float
+    workspace_bytes: int
+    history: np.ndarray = field(default_factory=lambda: np.zeros((0, 8)))
+
+
+def params(n_ev, n_extra, solver="lobpcg", strategy="none", tol=1e-8, n_es=0, max_iter=None,
+           soft_lock=True, sigma=0.0, time_limit_s=0.0, **strategy_params) -> SeParams:
+    p = SeParams()
+    lib().se_params_default(C.byref(p))
+    p.solver = _lib.SE_SI if solver == "si" else _lib.SE_LOBPCG
+    p.strategy = _lib.STRATEGIES[strategy]
+    p.n_ev, p.n_extra, p.n_es = int(n_ev), int(n_extra), int(n_es)
+    p.tol = float(tol)
+    p.soft_lock = 1 if soft_lock else 0
+    p.sigma = float(sigma)
+    p.time_limit_s = float(time_limit_s)
+    p.max_iter = int(max_iter if max_iter is not None else (20000 if solver == "si" else 1000))
+    for k, v in strategy_params.items():
+        setattr(p, k, v)
+    return p
+
+
+def solve(ctx: Context, A: Matrix, X0, n_ev, n_extra, history_cap=0, **kw):
+    """Run se_solve.
+
+    X0 is either a host numpy array (n, nb) in Fortran order, or a torch device
+    tensor of shape (nb, n) (column-major n x nb). Returns (lam, V, info) with V
+    on the same side as X0: numpy (n, n_ev) or a torch (n_ev, n) tensor whose
+    transpose is the eigenvector block.
+    """
+    p = params(n_ev, n_extra, **kw)
+    hist = np.zeros((max(history_cap, 0), _lib.SE_HISTORY_FIELDS), dtype=np.float64)
+    if history_cap > 0:
+        p.history = hist.ctypes.data_as(C.POINTER(C.c_double))
+        p.history_cap = history_cap
+    info = SeInfo()
+    n = A.n
+    if isinstance(X0, np.ndarray):
+        X0 = np.asfortranarray(X0, dtype=np.float64)
+        assert X0.shape == (n, n_ev + n_extra)
+        V = np.zeros((n, n_ev), dtype=np.float64, order="F")
+        lam = np.zeros(n_ev, dtype=np.float64)
+        p.ptr_mode = _lib.SE_PTR_HOST
+    else:
+        import torch
+
+        assert X0.dtype == torch.float64 and X0.is_contiguous() and X0.shape == (n_ev + n_extra, n)
+        V = torch.empty((n_ev, n), dtype=torch.float64, device=X0.device)
+        lam = torch.empty(n_ev, dtype=torch.float64, device=X0.device)
+        p.ptr_mode = _lib.SE_PTR_DEVICE
+    st = lib().se_solve(ctx.handle, A.handle, C.byref(p), C.c_void_p(_ptr(X0)),
+                        C.c_void_p(_ptr(V)), C.c_void_p(_ptr(lam)), C.byref(info))
+    check(st, "se_solve")
+    out = SolveInfo(st, info.iterations, bool(info.converged), info.n_shrinks, info.n_expands,
+                    info.max_stop_ratio, info.max_paper_ratio, info.time_ms,
+                    int(info.workspace_bytes), hist[: info.history_len].copy())
+    return lam, V, out
+
+
+# ---- building blocks (device tensors, row-major blocks) ----
+
+def spmm(ctx: Context, A: Matrix, X, Y, w: int):
+    check(lib().se_op_spmm(ctx.handle, A.handle, C.c_void_p(_ptr(X)), X.stride(0),
+                           C.c_void_p(_ptr(Y)), Y.stride(0), int(w)), "se_op_spmm")
+
+
+def gram(ctx: Context, U, mu: int, V, mv: int, out):
+    check(lib().se_op_gram(ctx.handle, U.shape[0], C.c_void_p(_ptr(U)), U.stride(0), int(mu),
+                           C.c_void_p(_ptr(V)), V.stride(0), int(mv), C.c_void_p(_ptr(out))),
+          "se_op_gram")
+
+
+def update(ctx: Context, U, K: int, Cm, N: int, Out, beta: float = 0.0):
+    check(lib().se_op_update(ctx.handle, U.shape[0], C.c_void_p(_ptr(U)), U.stride(0), int(K),
+                             C.c_void_p(_ptr(Cm)), int(N), C.c_void_p(_ptr(Out)), Out.stride(0),
+                             float(beta)), "se_op_update")
+
+
+def syev(ctx: Context, A, w, Z):
+    check(lib().se_op_syev(ctx.handle, A.shape[0], C.c_void_p(_ptr(A)), C.c_void_p(_ptr(w)),
+                           C.c_void_p(_ptr(Z))), "se_op_syev")
+
+
+def cholqr(ctx: Context, W, w: int) -> int:
+    r = C.c_int32()
+    check(lib().se_op_cholqr(ctx.handle, W.shape[0], C.c_void_p(_ptr(W)), W.stride(0), int(w),
+                             C.byref(r)), "se_op_cholqr")
+    return r.value
+
+
+def strategy_replay(strategy: str, rs, **kw) -> np.ndarray:
+    """Replay the library's shrink/expand controller on scripted r(j) values (host only)."""
+    p = params(1, 0, strategy=strategy, **kw)
+    r = np.ascontiguousarray(rs, dtype=np.float64)
+    flags = np.zeros(r.size, dtype=np.int32)
+    check(lib().se_strategy_replay(C.byref(p), r.size, r.ctypes.data_as(C.POINTER(C.c_double)),
+                                   flags.ctypes.data_as(C.POINTER(C.c_int32))), "se_strategy_replay")
+    return flags

@@ -1,0 +1,102 @@
+// Internal declarations shared by the HIP kernels and the host engine.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace se {
+
+// Up to four column segments of row-major n-row blocks that share one leading
+// dimension. Segment s covers logical columns [off[s], off[s] + w[s]) and
+// element (i, c) of it lives at p[s][i * ld + (c - off[s])].
+struct Segs {
+    const double* p[4];
+    int w[4];
+    int off[5];
+    int nseg;
+    long long ld;
+};
+
+inline Segs make_segs(long long ld) {
+    Segs s{};
+    s.nseg = 0;
+    s.ld = ld;
+    s.off[0] = 0;
+    return s;
+}
+inline void push_seg(Segs& s, const double* p, int w) {
+    if (w <= 0) return;
+    s.p[s.nseg] = p;
+    s.w[s.nseg] = w;
+    s.off[s.nseg + 1] = s.off[s.nseg] + w;
+    s.nseg++;
+}
+inline int segs_width(const Segs& s) { return s.off[s.nseg]; }
+
+// ---- bulk kernels (bulk.hip) ----
+// Y[:, 0:w] = A X[:, 0:w] for CSR A with int32 row offsets.
+hipError_t launch_spmm(hipStream_t st, int n, const int* rowptr, const int* col, const double* val,
+                       const double* X, long long ldx, double* Y, long long ldy, int w);
+
+// Per-column sums over rows of (AX - lam X)^2 and X^2 for columns [0, k):
+// out[c] = ||r_c||^2, out[k + c] = ||x_c||^2. part is scratch of
+// gram_partial_doubles(n, 2k) doubles.
+hipError_t launch_resid_norms(hipStream_t st, long long n, const double* X, const double* AX,
+                              long long ld, int k, const double* lam, double* part, double* out);
+
+// W[:, jj] = AX[:, act[jj]] - lam[act[jj]] X[:, act[jj]], jj < a.
+hipError_t launch_form_w(hipStream_t st, long long n, const double* X, const double* AX,
+                         long long ld, const double* lam, const int* act, int a, double* W,
+                         long long ldw);
+
+// X[:, c] = sigma X[:, c] - AX[:, c] for c < k.
+hipError_t launch_shift_sub(hipStream_t st, long long n, double* X, const double* AX, long long ld,
+                            int k, double sigma);
+
+// dst[:, dc + c] = src[:, sc + c] for c < w.
+hipError_t launch_copy_cols(hipStream_t st, long long n, const double* src, long long lds, int sc,
+                            double* dst, long long ldd, int dc, int w);
+
+// Column-major (leading dimension ldc) <-> row-major (leading dimension ldr).
+hipError_t launch_colmajor_to_rowmajor(hipStream_t st, long long n, int w, const double* src,
+                                       long long ldc, double* dst, long long ldr);
+hipError_t launch_rowmajor_to_colmajor(hipStream_t st, long long n, int w, const double* src,
+                                       long long ldr, double* dst, long long ldc);
+
+// Gram product C = U^T V (mu x mv row-major). With sym != 0 the result is
+// taken as symmetric (mu == mv): only upper tiles are formed, the lower
+// triangle mirrors the upper and diagonal tiles are averaged with their
+// transpose. part is scratch of gram_scratch_doubles(n, mu, mv) doubles.
+size_t gram_scratch_doubles(long long n, int mu, int mv);
+hipError_t launch_gram(hipStream_t st, long long n, const Segs& U, const Segs& V, int sym,
+                       double* part, double* C);
+
+// Out = beta Out + alpha U C with C (K x N row-major, leading dimension N).
+// Out segments must not alias U segments.
+hipError_t launch_update(hipStream_t st, long long n, const Segs& U, const double* C, int N,
+                         const Segs& Out, double alpha, double beta);
+
+// ---- small dense kernels (small.hip), one matrix per call, FP64 ----
+// Cholesky-QR transform with column drop: given G = W^T W (a x a), writes T
+// (a x r, leading dimension r) such that W T has orthonormal columns, r into
+// info_i[0] and the kept input columns (ascending) into info_i[1..r], the
+// smallest scaled pivot into info_d[0]. Columns whose scaled pivot falls below
+// drop_tol2 are dropped (zero rows of T).
+// work needs 2 a^2 + 2 a doubles.
+hipError_t launch_chol_drop(hipStream_t st, int a, const double* G, double* T, double* work,
+                            int* info_i, double* info_d, double drop_tol2);
+
+// Symmetric eigensolver: A (m x m row-major) overwritten; w ascending; Z
+// row-major (eigenvector c in column c). work needs syev_work_doubles(m).
+size_t syev_work_doubles(int m);
+hipError_t launch_syev(hipStream_t st, int m, double* A, double* w, double* Z, double* work);
+
+// Hetmaniuk-Lehoucq coefficients: from Z (m x m) and the positions act[0..a)
+// of the unlocked old X columns within the first k basis vectors, writes
+// C (m x (k + r), leading dimension k + r) = [Z1 | Z2 Q_B] and r to info_i[0].
+// work needs (m - k) * (a + 1) + 4 * a doubles.
+hipError_t launch_hl(hipStream_t st, int m, int k, const double* Z, const int* act, int a,
+                     double* C, double* work, int* info_i, double drop_tol);
+
+}  // namespace se

@@ -1,0 +1,144 @@
+// Host-side engine: context, matrix, workspace and the solver drivers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+#include <vector>
+
+#include "../../include/se.h"
+#include "common.h"
+
+namespace se {
+
+// Grow-only device buffer.
+struct DevBuf {
+    void* p = nullptr;
+    size_t bytes = 0;
+    hipError_t ensure(size_t want) {
+        if (want <= bytes) return hipSuccess;
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        bytes = 0;
+        hipError_t e = hipMalloc(&p, want < 256 ? 256 : want);
+        if (e == hipSuccess) bytes = want;
+        return e;
+    }
+    void release() {
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        bytes = 0;
+    }
+    template <class T>
+    T* as() const {
+        return static_cast<T*>(p);
+    }
+};
+
+// Grow-only pinned host buffer.
+struct HostBuf {
+    void* p = nullptr;
+    size_t bytes = 0;
+    hipError_t ensure(size_t want) {
+        if (want <= bytes) return hipSuccess;
+        if (p) (void)hipHostFree(p);
+        p = nullptr;
+        bytes = 0;
+        hipError_t e = hipHostMalloc(&p, want < 256 ? 256 : want, hipHostMallocDefault);
+        if (e == hipSuccess) bytes = want;
+        return e;
+    }
+    void release() {
+        if (p) (void)hipHostFree(p);
+        p = nullptr;
+        bytes = 0;
+    }
+    template <class T>
+    T* as() const {
+        return static_cast<T*>(p);
+    }
+};
+
+constexpr int kNumPanels = 14;
+
+struct Workspace {
+    DevBuf panel[kNumPanels];  // n x ld blocks
+    DevBuf gram_part, G, T, Z, theta, C, small_work, syev_work, lam, act, act_hl, norms, info;
+    HostBuf h_norms, h_info, h_act, h_act_hl, h_theta;
+    size_t device_bytes() const {
+        size_t s = 0;
+        for (const auto& b : panel) s += b.bytes;
+        const DevBuf* all[] = {&gram_part, &G, &T, &Z, &theta, &C, &small_work, &syev_work,
+                               &lam, &act, &act_hl, &norms, &info};
+        for (auto* b : all) s += b->bytes;
+        return s;
+    }
+    void release() {
+        for (auto& b : panel) b.release();
+        DevBuf* all[] = {&gram_part, &G, &T, &Z, &theta, &C, &small_work, &syev_work,
+                         &lam, &act, &act_hl, &norms, &info};
+        for (auto* b : all) b->release();
+        h_norms.release();
+        h_info.release();
+        h_act.release();
+        h_act_hl.release();
+        h_theta.release();
+    }
+};
+
+// Shrink-and-expand controller (Section 3.2): fix / slope / slopek with the
+// warm-up rule. Readings: Algorithm 7's shrink test uses j_s (iterations
+// since the last expansion); its expansion test c_max / c > mu is taken as
+// mu * c < c_max so that it also fires when the residual grows; c_max is the
+// largest slope since the last shrink, current iteration included.
+struct Strategy {
+    int kind = SE_STRAT_NONE;
+    int j_e = 12, j_s = 2, j_p = 10, j_warm = 5;
+    double mu = 1.1, r_warm = 1e-4;
+    bool shrunk = false, warm_done = false;
+    int j_last_expand = -1000000000;
+    double c_max = -INFINITY;
+    std::vector<double> logr;     // logr[j] = log10 r(j)
+    std::vector<char> have;       // have[j] = r(j) recorded
+
+    bool enabled() const {
+        return kind == SE_STRAT_FIX || kind == SE_STRAT_SLOPE || kind == SE_STRAT_SLOPEK;
+    }
+    void observe(int j, double r);
+    bool slope(int j, double* c) const;
+    bool ifexpand(int j);
+    bool ifshrink(int j) const;
+    void did_expand(int j) {
+        shrunk = false;
+        j_last_expand = j;
+    }
+    void did_shrink(int) {
+        shrunk = true;
+        warm_done = true;
+        c_max = -INFINITY;
+    }
+};
+
+}  // namespace se
+
+struct se_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    se::Workspace ws;
+    int last_hip_error = 0;
+};
+
+struct se_matrix {
+    se_ctx* ctx = nullptr;
+    int64_t n = 0, nnz = 0;
+    int* rowptr = nullptr;  // int32 offsets on the device
+    int* col = nullptr;
+    double* val = nullptr;
+    double anorm = 0.0;
+};
+
+namespace se {
+se_status solve(se_ctx* ctx, const se_matrix* A, const se_params* p, const double* X0, double* V,
+                double* lambda, se_info* info);
+}

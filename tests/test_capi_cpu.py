@@ -1,0 +1,82 @@
+"""C-ABI library on the CPU: it loads, exports every declared entry point, and
+its host-side shrink-and-expand controller matches the oracle's (no GPU use)."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2409_05572_amd import _lib, api
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared_functions():
+    src = open(os.path.join(ROOT, "include", "se.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(se_[a-z_]+)\s*\(", src)))
+
+
+def test_library_exports_every_declared_symbol():
+    h = _lib.lib()
+    names = _declared_functions()
+    assert "se_solve" in names and "se_op_spmm" in names
+    for name in names:
+        assert hasattr(h, name), name
+    assert set(names) == set(_lib.PROTOTYPES), set(names) ^ set(_lib.PROTOTYPES)
+
+
+def test_params_defaults_are_the_papers():
+    p = api.params(8, 8)
+    assert (p.j_e, p.j_s, p.j_p, p.j_warm) == (12, 2, 10, 5)
+    assert p.mu == pytest.approx(1.1) and p.r_warm == pytest.approx(1e-4)
+    assert p.tol == pytest.approx(1e-8) and p.soft_lock == 1 and p.max_iter == 1000
+    assert ctypes.sizeof(_lib.SeParams) == 14 * 4 + 5 * 8 + 8 + 8 + 8
+    assert ctypes.sizeof(_lib.SeInfo) == 4 * 4 + 3 * 8 + 8 * 8 + 8 + 8
+
+
+def test_status_strings():
+    h = _lib.lib()
+    assert h.se_status_string(0) == b"ok"
+    assert b"invalid" in h.se_status_string(-1)
+
+
+def _oracle_flags(strategy, rs, **kw):
+    ctl = O.SEController(O.SEParams(strategy, **kw))
+    out = []
+    for j, r in enumerate(rs, start=1):
+        f = 0
+        ctl.observe(j, r)
+        if ctl.ifexpand(j):
+            ctl.did_expand(j)
+            f |= 1
+        if ctl.ifshrink(j):
+            ctl.did_shrink(j)
+            f |= 2
+        out.append(f)
+    return np.array(out, dtype=np.int32)
+
+
+def test_strategy_fix_schedule_hand_derived():
+    f = api.strategy_replay("fix", [0.5**j for j in range(1, 63)])
+    assert list(np.flatnonzero(f & 1) + 1) == [24, 36, 48, 60]
+    assert list(np.flatnonzero(f & 2) + 1) == [14, 26, 38, 50, 62]
+
+
+@pytest.mark.parametrize("strategy", ["none", "fix", "slope", "slopek"])
+@pytest.mark.parametrize("seed", range(6))
+def test_strategy_matches_oracle_on_random_histories(strategy, seed):
+    rng = np.random.default_rng(seed)
+    steps = rng.normal(-0.25, 0.35, size=200)  # noisy decay with increases
+    rs = 10.0 ** np.cumsum(steps)
+    kw = dict(r_warm=10.0 ** rng.uniform(-4, -1), j_warm=int(rng.integers(2, 8)))
+    assert np.array_equal(api.strategy_replay(strategy, rs, **kw), _oracle_flags(strategy, rs, **kw))
+
+
+def test_no_cpu_fallback_when_library_missing(monkeypatch, tmp_path):
+    monkeypatch.setattr(_lib, "_lib", None)
+    monkeypatch.setattr(_lib, "LIB_PATH", str(tmp_path / "missing.so"))
+    with pytest.raises(RuntimeError, match="no CPU fallback"):
+        _lib.lib()

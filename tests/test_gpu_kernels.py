@@ -1,0 +1,185 @@
+"""HIP building blocks of the Rayleigh-Ritz step against their definitions (GPU)."""
+import numpy as np
+import pytest
+
+import oracle.solvers as OS
+import workloads as W
+from tests.gpu_util import gpu_ctx, to_dev
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    return gpu_ctx()
+
+
+def _row_major(n, w, ld, seed):
+    rng = np.random.default_rng(seed)
+    X = np.zeros((n, ld))
+    X[:, :w] = rng.standard_normal((n, w))
+    return X
+
+
+def _matrix_with_empty_and_dense_rows():
+    import scipy.sparse as sp
+
+    n = 3000
+    rng = np.random.default_rng(7)
+    a = sp.random(n, n, density=0.002, random_state=rng, format="lil")
+    a[5, :] = rng.standard_normal(n)  # one dense (hub) row
+    a[:, 5] = a[5, :].T
+    for r in (0, 17, 2999):  # empty rows and columns
+        a[r, :] = 0
+        a[:, r] = 0
+    a = sp.csr_matrix(a + a.T)
+    a.sort_indices()
+    return W.CSRMatrix(n, a.indptr.astype(np.int64), a.indices.astype(np.int32), a.data, 1.0)
+
+
+@pytest.mark.parametrize("w", [1, 2, 7, 16, 17, 48, 69, 96, 129, 250])
+def test_spmm_matches_oracle_product(ctx, w):
+    from paper_2409_05572_amd import api
+
+    A = W.laplacian_3d(20)
+    M = api.Matrix.from_csr(ctx, A)
+    ld = w + (w % 2)
+    X = _row_major(A.n, w, ld, w)
+    Xd = to_dev(X)
+    Yd = to_dev(np.full((A.n, ld), np.nan))
+    api.spmm(ctx, M, Xd, Yd, w)
+    Y = Yd.cpu().numpy()
+    ref = OS._apply(A.to_scipy(), X[:, :w])
+    bound = 1e-15 * 16 * (abs(A.to_scipy()) @ np.abs(X[:, :w]))
+    assert np.all(np.abs(Y[:, :w] - ref) <= bound + 1e-300)
+
+
+def test_spmm_empty_rows_and_hub_row(ctx):
+    from paper_2409_05572_amd import api
+
+    A = _matrix_with_empty_and_dense_rows()
+    M = api.Matrix.from_csr(ctx, A)
+    X = _row_major(A.n, 33, 34, 3)
+    Yd = to_dev(np.full((A.n, 34), np.nan))
+    api.spmm(ctx, M, to_dev(X), Yd, 33)
+    Y = Yd.cpu().numpy()[:, :33]
+    ref = OS._apply(A.to_scipy(), X[:, :33])
+    assert np.all(Y[[0, 17, 2999]] == 0.0)
+    assert np.allclose(Y, ref, rtol=1e-13, atol=1e-12)
+
+
+def test_spmm_full_config2_sampled_rows(ctx):
+    """3-D 128^3 Laplacian, 96 columns: the launch the solver uses, checked on
+    2000 sampled rows against the oracle's sparse product."""
+    import torch
+    from paper_2409_05572_amd import api
+
+    A = W.laplacian_3d(128)
+    M = api.Matrix.from_csr(ctx, A)
+    g = torch.Generator(device="cuda").manual_seed(5)
+    Xd = torch.randn((A.n, 96), generator=g, device="cuda", dtype=torch.float64)
+    Yd = torch.empty_like(Xd)
+    api.spmm(ctx, M, Xd, Yd, 96)
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(0)
+    rows = np.unique(np.concatenate([rng.integers(0, A.n, 1995), [0, 1, A.n - 1, 16383, 16384]]))
+    S = A.to_scipy()[rows]
+    cols = np.unique(S.indices)
+    Xs = Xd[torch.from_numpy(cols).cuda()].cpu().numpy()
+    ref = OS._apply(S[:, cols], Xs)
+    got = Yd[torch.from_numpy(rows).cuda()].cpu().numpy()
+    assert np.allclose(got, ref, rtol=0, atol=1e-13 * 12 * np.abs(Xs).max())
+
+
+@pytest.mark.parametrize("n,mu,mv", [(1, 1, 1), (1000, 1, 1), (4097, 17, 33), (20000, 96, 96),
+                                     (50001, 288, 96), (3001, 250, 250), (777, 300, 7)])
+def test_gram_matches_definition(ctx, n, mu, mv):
+    from paper_2409_05572_amd import api
+
+    U = _row_major(n, mu, mu + mu % 2, 1)
+    V = _row_major(n, mv, mv + mv % 2 + 2, 2)
+    Cd = to_dev(np.full((mu, mv), np.nan))
+    api.gram(ctx, to_dev(U), mu, to_dev(V), mv, Cd)
+    C = Cd.cpu().numpy()
+    ref = U[:, :mu].T @ V[:, :mv]
+    bound = 4 * n * 1.2e-16 * (np.abs(U[:, :mu]).T @ np.abs(V[:, :mv]))
+    assert np.all(np.abs(C - ref) <= bound + 1e-300)
+
+
+def test_gram_is_deterministic(ctx):
+    from paper_2409_05572_amd import api
+
+    U = to_dev(_row_major(100003, 96, 96, 4))
+    outs = []
+    for _ in range(2):
+        Cd = to_dev(np.zeros((96, 96)))
+        api.gram(ctx, U, 96, U, 96, Cd)
+        outs.append(Cd.cpu().numpy())
+    assert np.array_equal(outs[0], outs[1])
+
+
+@pytest.mark.parametrize("n,K,N,beta", [(1, 1, 1, 0.0), (1000, 1, 1, 1.0), (4097, 37, 69, 0.0),
+                                        (20000, 288, 192, 0.0), (5003, 250, 250, 1.0),
+                                        (64, 96, 97, 1.0)])
+def test_update_matches_definition(ctx, n, K, N, beta):
+    from paper_2409_05572_amd import api
+
+    rng = np.random.default_rng(K + N)
+    U = _row_major(n, K, K + K % 2, 5)
+    Cm = rng.standard_normal((K, N))
+    O0 = _row_major(n, N, N + N % 2, 6)
+    Od = to_dev(O0)
+    api.update(ctx, to_dev(U), K, to_dev(Cm), N, Od, beta)
+    got = Od.cpu().numpy()[:, :N]
+    ref = beta * O0[:, :N] + U[:, :K] @ Cm
+    bound = 4 * (K + 1) * 1.2e-16 * (beta * np.abs(O0[:, :N]) + np.abs(U[:, :K]) @ np.abs(Cm))
+    assert np.all(np.abs(got - ref) <= bound + 1e-300)
+
+
+def _sym_with_spectrum(m, seed, clustered):
+    rng = np.random.default_rng(seed)
+    Q, _ = np.linalg.qr(rng.standard_normal((m, m)))
+    if clustered:
+        lam = np.sort(np.concatenate([np.full(m // 3, 0.01), np.full(m // 4, 0.0100000001),
+                                      rng.uniform(-3, 12, m - m // 3 - m // 4)]))
+    else:
+        lam = np.sort(rng.uniform(-5, 12, m))
+    A = (Q * lam) @ Q.T
+    return 0.5 * (A + A.T)
+
+
+@pytest.mark.parametrize("m", [1, 2, 3, 16, 48, 97, 192, 288, 750])
+@pytest.mark.parametrize("clustered", [False, True])
+def test_syev_matches_definition(ctx, m, clustered):
+    from paper_2409_05572_amd import api
+
+    A = _sym_with_spectrum(m, m, clustered)
+    Ad = to_dev(A.copy())
+    wd = to_dev(np.zeros(m))
+    Zd = to_dev(np.zeros((m, m)))
+    api.syev(ctx, Ad, wd, Zd)
+    w = wd.cpu().numpy()
+    Z = Zd.cpu().numpy()
+    nrm = np.linalg.norm(A, 2)
+    ref = np.linalg.eigvalsh(A)
+    assert np.all(np.diff(w) >= 0)
+    assert np.max(np.abs(w - ref)) <= 1e-13 * max(nrm, 1.0) * 8
+    assert np.linalg.norm(A @ Z - Z * w, 2) <= 1e-12 * max(nrm, 1.0) * 8
+    assert np.abs(Z.T @ Z - np.eye(m)).max() <= 1e-12
+
+
+def test_cholqr_orthonormalizes_and_drops_dependent_columns(ctx):
+    from paper_2409_05572_amd import api
+
+    rng = np.random.default_rng(11)
+    n, w = 20001, 24
+    U, _ = np.linalg.qr(rng.standard_normal((n, w)))
+    Vt, _ = np.linalg.qr(rng.standard_normal((w, w)))
+    Wm = U @ np.diag(np.logspace(0, -5, w)) @ Vt
+    Wm[:, 10] = 2 * Wm[:, 3] - Wm[:, 4]  # exactly dependent column
+    Wd = to_dev(Wm)
+    r = api.cholqr(ctx, Wd, w)
+    Q = Wd.cpu().numpy()[:, :r]
+    assert r == w - 1
+    assert np.abs(Q.T @ Q - np.eye(r)).max() <= 1e-13
+    assert np.linalg.norm(Wm - Q @ (Q.T @ Wm)) <= 1e-9 * np.linalg.norm(Wm)

@@ -1,0 +1,168 @@
+"""Whole solves on the GPU against the FP64 oracle and closed forms (GPU).
+
+Eigenvalues are compared one to one; eigenvectors through principal angles of
+complete clusters (repeated eigenvalues make single vectors non-unique) and
+through the stopping test recomputed on the host with the oracle's product.
+"""
+import numpy as np
+import pytest
+
+import oracle as O
+import workloads as W
+from tests import _pins as pins
+from tests.gpu_util import cluster_angles, gpu_ctx, to_dev
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    return gpu_ctx()
+
+
+def _residual_ratio(A, lam, V):
+    R = O.solvers._apply(A.to_scipy(), V) - V * lam[None, :]
+    return np.linalg.norm(R, axis=0) / (A.anorm * np.linalg.norm(V, axis=0))
+
+
+def _gpu_solve(ctx, A, X0, n_ev, n_extra, **kw):
+    from paper_2409_05572_amd import api
+
+    M = api.Matrix.from_csr(ctx, A)
+    return api.solve(ctx, M, X0, n_ev, n_extra, history_cap=4000, **kw)
+
+
+def _assert_parity(A, lam, V, ref, exact=None, tol=1e-8, lam_rtol=1e-10):
+    assert np.max(np.abs(lam - ref.lam) / np.abs(ref.lam)) <= lam_rtol
+    if exact is not None:
+        assert np.max(np.abs(lam - exact) / np.abs(exact)) <= lam_rtol
+    assert np.max(_residual_ratio(A, lam, V)) <= tol * 1.0001
+    assert np.abs(V.T @ V - np.eye(V.shape[1])).max() <= 1e-12
+    assert cluster_angles(lam, V, ref.V) <= 1e-6
+
+
+def test_config1_lobpcg_matches_oracle(ctx):
+    A = W.laplacian_2d(32)
+    X0 = W.gaussian_block(A.n, 16, 201)
+    lam, V, info = _gpu_solve(ctx, A, X0, 8, 8)
+    ref = O.lobpcg(A.to_scipy(), X0, 8, A.anorm, tol=1e-8)
+    assert info.converged and info.status == 0
+    assert info.max_stop_ratio <= 1e-8
+    _assert_parity(A, lam, V, ref, pins.laplacian_spectrum(32, 2, 8))
+    assert abs(info.iterations - ref.iterations) <= max(3, ref.iterations // 10)
+
+
+def test_config1_subspace_iteration_matches_oracle(ctx):
+    A = W.laplacian_2d(32)
+    X0 = W.gaussian_block(A.n, 16, 201)
+    lam, V, info = _gpu_solve(ctx, A, X0, 8, 8, solver="si")
+    ref = O.subspace_iteration(A.to_scipy(), X0, 8, A.anorm, tol=1e-8)
+    assert info.converged
+    _assert_parity(A, lam, V, ref, pins.laplacian_spectrum(32, 2, 8), lam_rtol=1e-9)
+    assert abs(info.iterations - ref.iterations) <= max(3, ref.iterations // 20)
+
+
+@pytest.mark.parametrize("strategy", ["none", "fix", "slope", "slopek"])
+def test_lobpcg_shrink_expand_3d_matches_oracle(ctx, strategy):
+    m, n_ev, n_extra = 16, 32, 16
+    A = W.laplacian_3d(m)
+    X0 = W.gaussian_block(A.n, n_ev + n_extra, 7)
+    lam, V, info = _gpu_solve(ctx, A, X0, n_ev, n_extra, strategy=strategy)
+    ref = O.lobpcg(A.to_scipy(), X0, n_ev, A.anorm, tol=1e-8, n_es=n_ev + 5,
+                   se=O.SEParams(strategy))
+    assert info.converged
+    _assert_parity(A, lam, V, ref, pins.laplacian_spectrum(m, 3, n_ev), lam_rtol=1e-9)
+    if strategy != "none":
+        assert info.n_shrinks >= 1
+        hist = info.history
+        assert np.any(hist[:, 7].astype(int) & 2)
+        assert hist[:, 3].min() == n_ev + 5
+
+
+@pytest.mark.parametrize("strategy", ["fix", "slopek"])
+def test_si_shrink_expand_matches_oracle(ctx, strategy):
+    m, n_ev, n_extra = 20, 6, 6
+    A = W.laplacian_2d(m)
+    X0 = W.gaussian_block(A.n, n_ev + n_extra, 5)
+    lam, V, info = _gpu_solve(ctx, A, X0, n_ev, n_extra, solver="si", strategy=strategy,
+                              n_es=n_ev + 2)
+    ref = O.subspace_iteration(A.to_scipy(), X0, n_ev, A.anorm, tol=1e-8, n_es=n_ev + 2,
+                               se=O.SEParams(strategy))
+    assert info.converged and info.n_shrinks >= 1
+    _assert_parity(A, lam, V, ref, pins.laplacian_spectrum(m, 2, n_ev), lam_rtol=1e-9)
+
+
+def test_anderson_small_matches_oracle(ctx):
+    """Indefinite Anderson matrix (parity unpinned by closed form): oracle agreement."""
+    A = W.anderson_3d(14, 4.0, 103)
+    X0 = W.gaussian_block(A.n, 30, 8)
+    lam, V, info = _gpu_solve(ctx, A, X0, 20, 10, strategy="fix")
+    ref = O.lobpcg(A.to_scipy(), X0, 20, A.anorm, tol=1e-8, n_es=25, se=O.SEParams("fix"))
+    assert info.converged and ref.converged
+    assert np.max(np.abs(lam - ref.lam) / np.maximum(np.abs(ref.lam), 1e-3 * A.anorm)) <= 1e-10
+    assert np.max(_residual_ratio(A, lam, V)) <= 1e-8 * 1.0001
+
+
+def test_device_pointers_give_identical_result(ctx):
+    import torch
+
+    A = W.laplacian_2d(24)
+    X0 = W.gaussian_block(A.n, 12, 3)
+    lam_h, V_h, _ = _gpu_solve(ctx, A, X0, 6, 6, strategy="fix")
+    X0d = to_dev(X0.T.copy())
+    lam_d, V_d, info = _gpu_solve(ctx, A, X0d, 6, 6, strategy="fix")
+    torch.cuda.synchronize()
+    assert np.array_equal(lam_h, lam_d.cpu().numpy())
+    assert np.array_equal(V_h, V_d.cpu().numpy().T)
+
+
+def test_solves_are_bitwise_deterministic(ctx):
+    A = W.laplacian_3d(12)
+    X0 = W.gaussian_block(A.n, 24, 4)
+    a = _gpu_solve(ctx, A, X0, 16, 8, strategy="slopek")
+    b = _gpu_solve(ctx, A, X0, 16, 8, strategy="slopek")
+    assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+    assert a[2].iterations == b[2].iterations
+
+
+def test_not_converged_returns_best_iterate(ctx):
+    A = W.laplacian_2d(16)
+    X0 = W.gaussian_block(A.n, 8, 1)
+    lam, V, info = _gpu_solve(ctx, A, X0, 4, 4, max_iter=2)
+    assert info.status == 1 and not info.converged and info.iterations == 2
+    assert np.all(np.isfinite(lam)) and np.abs(V.T @ V - np.eye(4)).max() < 1e-10
+
+
+def test_invalid_arguments_are_rejected(ctx):
+    from paper_2409_05572_amd import api
+    from paper_2409_05572_amd._lib import SeError
+
+    A = W.laplacian_2d(8)
+    with pytest.raises(SeError, match="invalid"):
+        _gpu_solve(ctx, A, W.gaussian_block(A.n, 70, 1), 60, 10)  # nb > n
+    bad = W.laplacian_2d(8)
+    bad.colind = bad.colind.copy()
+    bad.colind[3] = 10**6
+    with pytest.raises(SeError, match="invalid"):
+        api.Matrix.from_csr(ctx, bad)
+    nanm = W.laplacian_2d(8)
+    nanm.val = nanm.val.copy()
+    nanm.val[0] = np.nan
+    with pytest.raises(SeError, match="invalid"):
+        api.Matrix.from_csr(ctx, nanm)
+
+
+def test_full_config2_lobpcg_shrink_expand(ctx):
+    """3-D 128^3 Laplacian, 64 wanted + 32 extra, fix strategy, at full size:
+    every eigenvalue against the closed form; the stopping test recomputed on
+    the host with the oracle's product for sampled eigenvectors."""
+    A = W.laplacian_3d(128)
+    X0 = W.gaussian_block(A.n, 96, 202)
+    lam, V, info = _gpu_solve(ctx, A, X0, 64, 32, strategy="fix")
+    assert info.converged and info.n_shrinks >= 1
+    exact = pins.laplacian_spectrum(128, 3, 64)
+    assert np.max(np.abs(lam - exact) / exact) <= 1e-9
+    cols = np.array([0, 1, 17, 40, 63])
+    r = _residual_ratio(A, lam[cols], V[:, cols])
+    assert np.max(r) <= 1e-8 * 1.0001
+    assert np.abs(V.T @ V - np.eye(64)).max() <= 1e-11
