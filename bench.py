@@ -1,0 +1,204 @@
+"""Time-to-solution of the shrink-and-expand LOBPCG on one MI355X.
+
+Workload (default): 3-D 7-point Dirichlet Laplacian on a 128^3 grid
+(n = 2,097,152, 14,581,760 nonzeros, FP64 CSR), the 64 smallest eigenpairs
+with 32 extra block columns (block 96, n_es = 69), tol 1e-8, Gaussian starting
+block from a fixed seed. One step = one complete solve with the `fix`
+shrink-and-expand strategy (inputs resident in HBM before timing). The
+fixed-block solve (no strategy) on the same input is timed beside it.
+
+Prints one JSON line (see the contract in the repository's design notes).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "time-to-solution & HBM GB/s, shrink-expand vs fixed block; p50/p99 latency"
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--grid", type=int, default=128, help="3-D grid side m (n = m^3)")
+    ap.add_argument("--n-ev", type=int, default=64)
+    ap.add_argument("--n-extra", type=int, default=32)
+    ap.add_argument("--strategy", default="fix")
+    ap.add_argument("--no-fixed", action="store_true", help="skip the fixed-block comparison")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=20.0)
+    return ap.parse_args()
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1",
+                          "n_gpus": args.gpus}), flush=True)
+        sys.exit(2)
+
+    import torch
+
+    import workloads as W
+    from paper_2409_05572_amd import api
+
+    def log(msg):
+        print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+    t = time.time()
+    A = W.laplacian_3d(args.grid)
+    nb = args.n_ev + args.n_extra
+    X0 = W.gaussian_block(A.n, nb, 202)
+    log(f"inputs n={A.n} nnz={A.nnz} nb={nb} built in {time.time() - t:.1f}s")
+
+    ctx = api.Context(0)
+    M = api.Matrix.from_csr(ctx, A)
+    X0d = torch.from_numpy(np.ascontiguousarray(X0.T)).cuda()
+    torch.cuda.synchronize()
+
+    def run(strategy, profile=0):
+        return api.solve(ctx, M, X0d, args.n_ev, args.n_extra, strategy=strategy, tol=1e-8,
+                         history_cap=5000, profile=profile)
+
+    for i in range(args.warmup):
+        lam, V, info = run(args.strategy)
+        log(f"warmup {i}: {info.time_ms / 1e3:.3f}s iters={info.iterations} conv={info.converged}")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    infos = []
+    for i in range(args.steps):
+        lam, V, info = run(args.strategy, profile=1)
+        infos.append(info)
+    torch.cuda.synchronize()
+    wall = (time.perf_counter() - t0) / max(args.steps, 1)
+    log(f"timed {args.steps} solve(s): {wall:.3f}s each, iters={infos[-1].iterations}")
+
+    out = {
+        "metric": METRIC,
+        "value": round(wall, 4),
+        "unit": "s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(wall * 1e3, 2),
+        "higher_is_better": False,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": f"laplace3d_{args.grid}^3 LOBPCG n_ev={args.n_ev} n_extra={args.n_extra} "
+                        f"strategy={args.strategy} tol=1e-8",
+            "n": A.n, "nnz": A.nnz, "n_ev": args.n_ev, "block": nb,
+        },
+        "shrink_expand": {
+            "iterations": infos[-1].iterations, "n_shrinks": infos[-1].n_shrinks,
+            "n_expands": infos[-1].n_expands, "max_stop_ratio": infos[-1].max_stop_ratio,
+        },
+    }
+    lam_np = lam.cpu().numpy()
+    m = args.grid
+    one = 2.0 - 2.0 * np.cos(np.arange(1, m + 1) * np.pi / (m + 1))
+    ex = np.sort((one[:, None, None] + one[None, :, None] + one[None, None, :]).ravel())[: args.n_ev]
+    out["parity"] = {"max_eig_rel_err_vs_closed_form": float(np.max(np.abs(lam_np - ex) / ex)),
+                     "max_stop_ratio": infos[-1].max_stop_ratio}
+
+    if not args.no_fixed:
+        t1 = time.perf_counter()
+        _, _, finfo = run("none")
+        torch.cuda.synchronize()
+        fwall = time.perf_counter() - t1
+        out["fixed_block"] = {"time_s": round(fwall, 4), "iterations": finfo.iterations}
+        out["speedup_vs_fixed"] = round(fwall / wall, 3)
+        log(f"fixed block: {fwall:.3f}s iters={finfo.iterations}")
+
+    out["roofline"], out["kernels"] = roofline(infos)
+    out["cpu_baseline"] = None
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(A, X0, args, infos[-1].iterations, log)
+    print(json.dumps(out), flush=True)
+
+
+# Published MI355X peaks: HBM3E 8 TB/s; FP64 vector and matrix 78.6 TFLOP/s.
+HBM_PEAK_GBS = 8000.0
+FP64_PEAK_TFS = 78.6
+
+
+def roofline(infos):
+    """Per kernel class: device time summed from HIP events around every
+    launch in the timed solves, algorithmic bytes and flops. The dominant
+    class (largest time) is reported against its roof."""
+    from paper_2409_05572_amd._lib import KERNEL_CLASSES
+
+    ms = np.zeros(8)
+    by = np.zeros(8)
+    fl = np.zeros(8)
+    calls = np.zeros(8, dtype=np.int64)
+    for info in infos:
+        ms += np.array(info.kern_ms)
+        by += np.array(info.kern_bytes)
+        fl += np.array(info.kern_flops)
+        calls += np.array(info.kern_calls)
+    table = {}
+    for c, name in enumerate(KERNEL_CLASSES):
+        if calls[c] == 0:
+            continue
+        sec = ms[c] / 1e3
+        table[name] = {"ms_per_solve": round(ms[c] / len(infos), 2), "calls": int(calls[c]),
+                       "avg_us": round(1e3 * ms[c] / calls[c], 1),
+                       "GB_s": round(by[c] / sec / 1e9, 1), "TFLOP_s": round(fl[c] / sec / 1e12, 2)}
+    dom = int(np.argmax(ms))
+    sec = ms[dom] / 1e3
+    name = KERNEL_CLASSES[dom]
+    intensity = fl[dom] / max(by[dom], 1.0)
+    if name in ("spmm", "resid", "copy") or intensity < FP64_PEAK_TFS * 1e12 / (HBM_PEAK_GBS * 1e9):
+        ach = by[dom] / sec / 1e9
+        roof = {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(ach / HBM_PEAK_GBS, 4)}
+    else:
+        ach = fl[dom] / sec / 1e12
+        roof = {"bound": "alu", "achieved": round(ach, 2), "peak": FP64_PEAK_TFS, "unit": "TFLOP/s",
+                "frac": round(ach / FP64_PEAK_TFS, 4)}
+    roof.update({"kernel": name, "launches": int(calls[dom]),
+                 "avg_launch_us": round(1e3 * ms[dom] / calls[dom], 1), "traffic": None})
+    return roof, table
+
+
+def cpu_baseline(A, X0, args, gpu_iters, log):
+    """The FP64 oracle on the host cores, bounded sample of the same solve."""
+    import oracle as O
+
+    try:
+        from threadpoolctl import threadpool_info
+
+        cores = max((d.get("num_threads", 1) for d in threadpool_info()), default=os.cpu_count())
+    except Exception:
+        cores = os.cpu_count()
+    t = time.perf_counter()
+    res = O.lobpcg(A.to_scipy(), X0, args.n_ev, A.anorm, tol=1e-8, n_es=args.n_ev + 5,
+                   se=O.SEParams(args.strategy), time_limit_s=args.cpu_seconds)
+    el = time.perf_counter() - t
+    done = max(res.iterations - 1, 1)  # the last recorded iteration stopped at its check
+    per_iter = el / done
+    est = per_iter * gpu_iters
+    log(f"cpu oracle: {done} iteration(s) in {el:.1f}s on {cores} threads")
+    return {"value": round(est, 1), "unit": "s", "cores": int(cores), "kind": "oracle",
+            "sample": f"initial Rayleigh-Ritz + {done} LOBPCG iteration(s) of the same workload in "
+                      f"{el:.1f}s; time-to-solution extrapolated as {per_iter:.2f}s/iteration x "
+                      f"{gpu_iters} iterations (GPU count)",
+            "extrapolated": True}
+
+
+if __name__ == "__main__":
+    main()

@@ -70,6 +70,16 @@ typedef struct se_matrix se_matrix;
 /* j, r(j) by eq. (rk), max stop ratio, width k, width p, active a, locked, flags
  * (bit 0 = expanded this iteration, bit 1 = shrunk this iteration) */
 
+/* Kernel classes of se_info.kern_* */
+#define SE_K_SPMM 0   /* CSR sparse x block */
+#define SE_K_GRAM 1   /* tall-skinny Gram products and their fixed-order reduction */
+#define SE_K_UPDATE 2 /* basis updates X <- S C, W <- W - [X,P] G, Cholesky-QR apply */
+#define SE_K_RESID 3  /* residual norms, forming W, shifted power step */
+#define SE_K_EIG 4    /* dense eigensolve of the projected matrix */
+#define SE_K_SMALL 5  /* Cholesky-QR transform and Hetmaniuk-Lehoucq coefficients */
+#define SE_K_COPY 6   /* layout changes and column copies */
+#define SE_K_CLASSES 8
+
 typedef struct se_params {
     int32_t solver;      /* SE_LOBPCG or SE_SI */
     int32_t strategy;    /* SE_STRAT_* */
@@ -84,7 +94,7 @@ typedef struct se_params {
     int32_t j_p;         /* slopek averaging window (paper: 10) */
     int32_t j_warm;      /* warm-up: first shrink not before iteration j_warm (paper: 5) */
     int32_t max_iter;    /* iteration cap (default 1000 LOBPCG, 20000 SI) */
-    int32_t profile;     /* 1 = time each phase with HIP events (adds syncs) */
+    int32_t profile;     /* 1 = time every kernel launch with HIP events (se_info.kern_*) */
     double mu;           /* slope threshold (paper: 1.1) */
     double r_warm;       /* warm-up: first shrink once r(j) <= r_warm (paper: 1e-4) */
     double tol;          /* stop when ||A x_i - lambda_i x_i|| <= tol ||A|| ||x_i||, i <= n_ev */
@@ -104,8 +114,13 @@ typedef struct se_info {
     double max_stop_ratio;  /* max_i ||A x_i - lambda_i x_i|| / (||A|| ||x_i||), fresh product */
     double max_paper_ratio; /* eq. (rk) on the returned pairs, fresh product */
     double time_ms;         /* wall time of the solve on the stream */
-    double phase_ms[8];     /* spmm, residual, orthogonalize W, A_p Gram, eigensolve,
-                               basis update, expansion, small dense (profile = 1 only) */
+    /* Per kernel class SE_K_* (filled when params.profile = 1): summed device
+     * time from HIP events around each launch, launch count, and algorithmic
+     * HBM bytes / flops (every operand read and written exactly once). */
+    double kern_ms[SE_K_CLASSES];
+    double kern_bytes[SE_K_CLASSES];
+    double kern_flops[SE_K_CLASSES];
+    int32_t kern_calls[SE_K_CLASSES];
     uint64_t workspace_bytes; /* device workspace held by the context after the call */
     int32_t hip_error;      /* first failing hipError_t, 0 if none */
     int32_t history_len;    /* rows written to params.history */

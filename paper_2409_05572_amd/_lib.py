@@ -22,6 +22,7 @@ SE_FP64 = 0
 SE_PTR_HOST, SE_PTR_DEVICE = 0, 1
 SE_MATRIX_HOST, SE_MATRIX_DEVICE = 0, 1
 SE_HISTORY_FIELDS = 8
+KERNEL_CLASSES = ["spmm", "gram", "update", "resid", "eig", "small", "copy", "other"]
 
 
 class SeParams(C.Structure):
@@ -43,7 +44,9 @@ class SeInfo(C.Structure):
         ("iterations", C.c_int32), ("converged", C.c_int32), ("n_shrinks", C.c_int32),
         ("n_expands", C.c_int32), ("max_stop_ratio", C.c_double),
         ("max_paper_ratio", C.c_double), ("time_ms", C.c_double),
-        ("phase_ms", C.c_double * 8), ("workspace_bytes", C.c_uint64),
+        ("kern_ms", C.c_double * 8), ("kern_bytes", C.c_double * 8),
+        ("kern_flops", C.c_double * 8), ("kern_calls", C.c_int32 * 8),
+        ("workspace_bytes", C.c_uint64),
         ("hip_error", C.c_int32), ("history_len", C.c_int32),
     ]
 

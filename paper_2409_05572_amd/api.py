@@ -107,6 +107,10 @@ class SolveInfo:
     time_ms: float
     workspace_bytes: int
     history: np.ndarray = field(default_factory=lambda: np.zeros((0, 8)))
+    kern_ms: tuple = ()
+    kern_bytes: tuple = ()
+    kern_flops: tuple = ()
+    kern_calls: tuple = ()
 
 
 def params(n_ev, n_extra, solver="lobpcg", strategy="none", tol=1e-8, n_es=0, max_iter=None,
@@ -159,7 +163,9 @@ def solve(ctx: Context, A: Matrix, X0, n_ev, n_extra, history_cap=0, **kw):
     check(st, "se_solve")
     out = SolveInfo(st, info.iterations, bool(info.converged), info.n_shrinks, info.n_expands,
                     info.max_stop_ratio, info.max_paper_ratio, info.time_ms,
-                    int(info.workspace_bytes), hist[: info.history_len].copy())
+                    int(info.workspace_bytes), hist[: info.history_len].copy(),
+                    tuple(info.kern_ms), tuple(info.kern_bytes), tuple(info.kern_flops),
+                    tuple(info.kern_calls))
     return lam, V, out
 
 

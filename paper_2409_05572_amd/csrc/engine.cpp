@@ -90,6 +90,17 @@ struct Solver {
     Strategy ctl;
     std::chrono::steady_clock::time_point t0;
 
+    // Per-launch timing (params.profile): events recorded around launches on
+    // the solver stream, summed per kernel class at the end of the solve.
+    struct ProfRec {
+        int cls;
+        hipEvent_t a, b;
+        double bytes, flops;
+    };
+    std::vector<ProfRec> prof;
+    size_t ev_next = 0;
+    hipEvent_t open_ev = nullptr;
+
     Solver(se_ctx* c, const se_matrix* a, const se_params& prm)
         : ctx(c), A(a), p(prm), st(c->stream), ws(c->ws), n(a->n) {}
 
@@ -156,10 +167,47 @@ struct Solver {
         return SE_OK;
     }
 
+    hipEvent_t next_event() {
+        if (ev_next == ws.events.size()) {
+            hipEvent_t e = nullptr;
+            if (hipEventCreate(&e) != hipSuccess) return nullptr;
+            ws.events.push_back(e);
+        }
+        return ws.events[ev_next++];
+    }
+    se_status tic() {
+        if (!p.profile) return SE_OK;
+        open_ev = next_event();
+        if (open_ev) HC(hipEventRecord(open_ev, st));
+        return SE_OK;
+    }
+    se_status toc(int cls, double bytes, double flops) {
+        if (!p.profile || !open_ev) return SE_OK;
+        hipEvent_t b = next_event();
+        if (!b) return SE_OK;
+        HC(hipEventRecord(b, st));
+        prof.push_back({cls, open_ev, b, bytes, flops});
+        open_ev = nullptr;
+        return SE_OK;
+    }
+    void summarize(se_info* info) {
+        if (!info || !p.profile) return;
+        (void)hipStreamSynchronize(st);
+        for (const ProfRec& r : prof) {
+            float ms = 0.f;
+            if (hipEventElapsedTime(&ms, r.a, r.b) != hipSuccess) continue;
+            info->kern_ms[r.cls] += ms;
+            info->kern_bytes[r.cls] += r.bytes;
+            info->kern_flops[r.cls] += r.flops;
+            info->kern_calls[r.cls] += 1;
+        }
+    }
+
     // ------------------------------------------------------------ kernels --
     se_status spmm(const double* Xs, double* Ys, int w) {
+        ST(tic());
         HC(launch_spmm(st, (int)n, A->rowptr, A->col, A->val, Xs, ld, Ys, ld, w));
-        return SE_OK;
+        return toc(SE_K_SPMM, 12.0 * A->nnz + 4.0 * (n + 1) + 16.0 * n * w, 2.0 * A->nnz * w);
     }
     se_status gram(const Segs& U, const Segs& V, int sym, double* C) {
         const size_t need = sizeof(double) * gram_scratch_doubles(n, segs_width(U), segs_width(V));
@@ -167,12 +215,18 @@ struct Solver {
             ST(sync());  // the old scratch may still be in use by queued kernels
             HC(ws.gram_part.ensure(need));
         }
+        ST(tic());
         HC(launch_gram(st, n, U, V, sym, ws.gram_part.as<double>(), C));
-        return SE_OK;
+        const double mu = segs_width(U), mv = segs_width(V);
+        const double fl = (sym && mu == mv) ? n * mu * (mu + 1.0) : 2.0 * n * mu * mv;
+        const bool same = sym && U.nseg == 1 && V.nseg == 1 && U.p[0] == V.p[0];
+        return toc(SE_K_GRAM, 8.0 * n * (same ? mu : mu + mv), fl);
     }
     se_status update(const Segs& U, const double* C, int N, const Segs& O, double alpha, double beta) {
+        ST(tic());
         HC(launch_update(st, n, U, C, N, O, alpha, beta));
-        return SE_OK;
+        const double K = segs_width(U);
+        return toc(SE_K_UPDATE, 8.0 * n * (K + N * (beta != 0.0 ? 2.0 : 1.0)), 2.0 * n * K * N);
     }
 
     // Cholesky-QR applied twice (a third time after a tiny pivot) with column
@@ -188,8 +242,10 @@ struct Solver {
             ST(gram(Ws, Ws, 1, ws.G.as<double>()));
             int* info_i = ws.info.as<int>();
             double* info_d = ws.info.as<double>() + (w + 8) / 2 + 4;
+            ST(tic());
             HC(launch_chol_drop(st, w, ws.G.as<double>(), ws.T.as<double>(), ws.small_work.as<double>(),
                                 info_i, info_d, 1e-13));
+            ST(toc(SE_K_SMALL, 16.0 * w * w, w * w * (double)w));
             HC(hipMemcpyAsync(ws.h_info.p, ws.info.p, sizeof(double) * (w + 16), hipMemcpyDeviceToHost,
                               st));
             ST(sync());
@@ -219,8 +275,10 @@ struct Solver {
     // Rayleigh-Ritz on the k columns of X (with AX): X <- X Z, AX <- AX Z.
     se_status rr_plain(int k) {
         ST(gram(seg1(X, k), seg1(AX, k), 1, ws.G.as<double>()));
+        ST(tic());
         HC(launch_syev(st, k, ws.G.as<double>(), ws.theta.as<double>(), ws.Z.as<double>(),
                        ws.syev_work.as<double>()));
+        ST(toc(SE_K_EIG, 16.0 * k * k, 4.0 * k * k * (double)k));
         ST(update(seg1(X, k), ws.Z.as<double>(), k, seg1(Xn, k), 1.0, 0.0));
         ST(update(seg1(AX, k), ws.Z.as<double>(), k, seg1(AXn, k), 1.0, 0.0));
         std::swap(X, Xn);
@@ -243,8 +301,10 @@ struct Solver {
     // ratios of the stopping test and of eq. (rk).
     se_status check(const double* Xp, const double* AXp, int k, std::vector<double>& stop,
                     std::vector<double>& paper, std::vector<double>& lam) {
+        ST(tic());
         HC(launch_resid_norms(st, n, Xp, AXp, ld, k, ws.theta.as<double>(), ws.gram_part.as<double>(),
                               ws.norms.as<double>()));
+        ST(toc(SE_K_RESID, 16.0 * n * k, 5.0 * n * k));
         HC(hipMemcpyAsync(ws.h_norms.p, ws.norms.p, sizeof(double) * 2 * k, hipMemcpyDeviceToHost, st));
         HC(hipMemcpyAsync(ws.h_theta.p, ws.theta.p, sizeof(double) * k, hipMemcpyDeviceToHost, st));
         ST(sync());
@@ -334,7 +394,9 @@ struct Solver {
             int a = (int)act.size();
             std::memcpy(ws.h_act.p, act.data(), sizeof(int) * a);
             HC(hipMemcpyAsync(ws.act.p, ws.h_act.p, sizeof(int) * a, hipMemcpyHostToDevice, st));
+            ST(tic());
             HC(launch_form_w(st, n, X, AX, ld, ws.theta.as<double>(), ws.act.as<int>(), a, W, ld));
+            ST(toc(SE_K_RESID, 24.0 * n * a, 2.0 * n * a));
             for (int pass = 0; pass < 2; ++pass) {
                 const Segs XP = seg3(X, k, P, pw, nullptr, 0);
                 ST(gram(XP, seg1(W, a), 0, ws.G.as<double>()));
@@ -377,13 +439,17 @@ struct Solver {
             const Segs S = seg3(X, k, P, pw, W, a);
             const Segs AS = seg3(AX, k, AP, pw, AW, a);
             ST(gram(S, AS, 1, ws.G.as<double>()));
+            ST(tic());
             HC(launch_syev(st, m, ws.G.as<double>(), ws.theta.as<double>(), ws.Z.as<double>(),
                            ws.syev_work.as<double>()));
+            ST(toc(SE_K_EIG, 16.0 * m * m, 4.0 * m * m * (double)m));
             const int ahl = (int)act_hl.size();
             std::memcpy(ws.h_act_hl.p, act_hl.data(), sizeof(int) * ahl);
             HC(hipMemcpyAsync(ws.act_hl.p, ws.h_act_hl.p, sizeof(int) * ahl, hipMemcpyHostToDevice, st));
+            ST(tic());
             HC(launch_hl(st, m, k, ws.Z.as<double>(), ws.act_hl.as<int>(), ahl, ws.C.as<double>(),
                          ws.small_work.as<double>(), ws.info.as<int>(), 1e-12));
+            ST(toc(SE_K_SMALL, 16.0 * m * m, 4.0 * m * ahl * (double)(m - k)));
             HC(hipMemcpyAsync(ws.h_info.p, ws.info.p, sizeof(int) * 4, hipMemcpyDeviceToHost, st));
             ST(sync());
             const int rP = ws.h_info.as<int>()[0];
@@ -457,7 +523,9 @@ struct Solver {
             int flags = 0;
             const bool want_expand = ctl.ifexpand(j);
             // Y <- sigma X - A X (AX is current), then append X_drop.
+            ST(tic());
             HC(launch_shift_sub(st, n, X, AX, ld, k, sigma));
+            ST(toc(SE_K_RESID, 24.0 * n * k, 2.0 * n * k));
             if (want_expand && have_drop) {
                 HC(launch_copy_cols(st, n, Sd, ld, 0, X, ld, k, dx));
                 k += dx;
@@ -545,6 +613,7 @@ se_status solve(se_ctx* ctx, const se_matrix* A, const se_params* prm, const dou
     (void)hipEventRecord(e0, ctx->stream);
     se_status st = (prm->solver == SE_SI) ? s.si(X0) : s.lobpcg(X0);
     if (st >= 0) st = s.finish(V, lambda, info);
+    s.summarize(info);
     (void)hipEventRecord(e1, ctx->stream);
     (void)hipEventSynchronize(e1);
     float ms = 0.f;
@@ -558,7 +627,6 @@ se_status solve(se_ctx* ctx, const se_matrix* A, const se_params* prm, const dou
         info->n_shrinks = s.n_shr;
         info->n_expands = s.n_exp;
         info->time_ms = ms;
-        for (double& v : info->phase_ms) v = 0.0;
         info->workspace_bytes = ctx->ws.device_bytes();
         info->hip_error = (int)s.herr;
         info->history_len = s.hist_len;

@@ -66,6 +66,7 @@ struct Workspace {
     DevBuf panel[kNumPanels];  // n x ld blocks
     DevBuf gram_part, G, T, Z, theta, C, small_work, syev_work, lam, act, act_hl, norms, info;
     HostBuf h_norms, h_info, h_act, h_act_hl, h_theta;
+    std::vector<hipEvent_t> events;  // pool for per-launch timing
     size_t device_bytes() const {
         size_t s = 0;
         for (const auto& b : panel) s += b.bytes;
@@ -84,6 +85,8 @@ struct Workspace {
         h_act.release();
         h_act_hl.release();
         h_theta.release();
+        for (hipEvent_t e : events) (void)hipEventDestroy(e);
+        events.clear();
     }
 };
 

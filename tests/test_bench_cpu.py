@@ -1,0 +1,31 @@
+"""bench.py host logic on the CPU: argument contract and roofline arithmetic."""
+import subprocess
+import sys
+
+import numpy as np
+
+import bench
+from paper_2409_05572_amd.api import SolveInfo
+
+
+def _info(ms, by, fl, calls):
+    return SolveInfo(0, 10, True, 1, 1, 1e-9, 1e-9, 100.0, 0, np.zeros((0, 8)),
+                     tuple(ms), tuple(by), tuple(fl), tuple(calls))
+
+
+def test_more_than_one_gpu_is_refused():
+    r = subprocess.run([sys.executable, "bench.py", "--gpus", "4"], capture_output=True, text=True)
+    assert r.returncode == 2 and "one GPU" in r.stdout
+
+
+def test_roofline_picks_dominant_class_and_divides_correctly():
+    ms = [1.0, 2.0, 10.0, 0.5, 3.0, 1.0, 0.1, 0.0]
+    by = [8e9, 1e9, 2e9, 1e9, 0, 0, 0, 0]
+    fl = [1e9, 1e11, 5e11, 0, 0, 0, 0, 0]
+    calls = [2, 4, 10, 2, 1, 1, 1, 0]
+    roof, table = bench.roofline([_info(ms, by, fl, calls)])
+    assert roof["kernel"] == "update" and roof["bound"] == "alu"
+    assert abs(roof["achieved"] - 5e11 / 1e-2 / 1e12) < 1e-9
+    assert abs(roof["frac"] - roof["achieved"] / 78.6) < 1e-4
+    assert roof["launches"] == 10 and abs(roof["avg_launch_us"] - 1000.0) < 1e-9
+    assert abs(table["spmm"]["GB_s"] - 8e9 / 1e-3 / 1e9) < 1e-6
