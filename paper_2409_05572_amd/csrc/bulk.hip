@@ -47,7 +47,62 @@ inline int grid_for(long long work, int per_block, int cap = 1 << 20) {
 
 // ---------------------------------------------------------------------------
 // CSR x block. LPR lanes cooperate on one matrix row; each lane owns two
-// adjacent columns (one 16-byte load per gathered row of X).
+// adjacent columns (one 16-byte load per gathered row of X). A lane group
+// walks SPR consecutive rows two at a time. For each batch it first loads the
+// column indices and values of up to eight nonzeros of both rows, then issues
+// all sixteen row gathers, then accumulates: a 7-point row needs two memory
+// round trips, not fourteen. Slots past the end of a row gather the row
+// itself with weight zero (always a valid address). With an odd width the
+// last lane also reads the padding column (ld >= w + 1) and stores only its
+// first value.
+constexpr int SPR = 8;  // rows per lane group
+constexpr int SB = 8;   // nonzeros per row per batch
+
+__device__ __forceinline__ void spmm_row_pair(int ra, int rb, const int* __restrict__ rowptr,
+                                              const int* __restrict__ col,
+                                              const double* __restrict__ val,
+                                              const double* __restrict__ X, long long ldx,
+                                              double* __restrict__ Y, long long ldy, int c0,
+                                              bool pair_col) {
+    const int ba = rowptr[ra], ea = rowptr[ra + 1];
+    const bool hasb = rb >= 0;
+    const int rbs = hasb ? rb : ra;
+    const int bb = hasb ? rowptr[rbs] : 0, eb = hasb ? rowptr[rbs + 1] : 0;
+    double a0 = 0.0, a1 = 0.0, b0 = 0.0, b1 = 0.0;
+    for (int pa = ba, pb = bb; pa < ea || pb < eb; pa += SB, pb += SB) {
+        int ja[SB], jb[SB];
+        double va[SB], vb[SB];
+#pragma unroll
+        for (int u = 0; u < SB; ++u) {
+            const bool oka = pa + u < ea, okb = pb + u < eb;
+            ja[u] = oka ? col[pa + u] : ra;
+            va[u] = oka ? val[pa + u] : 0.0;
+            jb[u] = okb ? col[pb + u] : rbs;
+            vb[u] = okb ? val[pb + u] : 0.0;
+        }
+        double2 xa[SB], xb[SB];
+#pragma unroll
+        for (int u = 0; u < SB; ++u) {
+            xa[u] = *reinterpret_cast<const double2*>(X + (long long)ja[u] * ldx + c0);
+            xb[u] = *reinterpret_cast<const double2*>(X + (long long)jb[u] * ldx + c0);
+        }
+#pragma unroll
+        for (int u = 0; u < SB; ++u) {
+            a0 = fma(va[u], xa[u].x, a0);
+            a1 = fma(va[u], xa[u].y, a1);
+            b0 = fma(vb[u], xb[u].x, b0);
+            b1 = fma(vb[u], xb[u].y, b1);
+        }
+    }
+    if (pair_col) {
+        *reinterpret_cast<double2*>(Y + (long long)ra * ldy + c0) = make_double2(a0, a1);
+        if (hasb) *reinterpret_cast<double2*>(Y + (long long)rb * ldy + c0) = make_double2(b0, b1);
+    } else {
+        Y[(long long)ra * ldy + c0] = a0;
+        if (hasb) Y[(long long)rb * ldy + c0] = b0;
+    }
+}
+
 template <int LPR>
 __global__ __launch_bounds__(kThreads) void spmm_kernel(int n, const int* __restrict__ rowptr,
                                                         const int* __restrict__ col,
@@ -55,47 +110,25 @@ __global__ __launch_bounds__(kThreads) void spmm_kernel(int n, const int* __rest
                                                         const double* __restrict__ X, long long ldx,
                                                         double* __restrict__ Y, long long ldy,
                                                         int w) {
-    constexpr int RPB = kThreads / LPR;
+    constexpr int GPB = kThreads / LPR;  // lane groups per workgroup
     const int blk = xcd_remap(blockIdx.x, gridDim.x);
     const int sub = threadIdx.x / LPR;
     const int lane = threadIdx.x % LPR;
-    const int row = blk * RPB + sub;
-    if (row >= n) return;
-    const int beg = rowptr[row];
-    const int end = rowptr[row + 1];
+    const int rbeg = (blk * GPB + sub) * SPR;
+    if (rbeg >= n) return;
+    const int rend = min(n, rbeg + SPR);
     for (int c0 = 2 * lane; c0 < w; c0 += 2 * LPR) {
-        double a0 = 0.0, a1 = 0.0;
-        if (c0 + 1 < w) {
-            int e = beg;
-            for (; e + 2 <= end; e += 2) {
-                const int j0 = col[e], j1 = col[e + 1];
-                const double v0 = val[e], v1 = val[e + 1];
-                const double2 x0 = *reinterpret_cast<const double2*>(X + (long long)j0 * ldx + c0);
-                const double2 x1 = *reinterpret_cast<const double2*>(X + (long long)j1 * ldx + c0);
-                a0 = fma(v0, x0.x, a0);
-                a1 = fma(v0, x0.y, a1);
-                a0 = fma(v1, x1.x, a0);
-                a1 = fma(v1, x1.y, a1);
-            }
-            if (e < end) {
-                const int j0 = col[e];
-                const double v0 = val[e];
-                const double2 x0 = *reinterpret_cast<const double2*>(X + (long long)j0 * ldx + c0);
-                a0 = fma(v0, x0.x, a0);
-                a1 = fma(v0, x0.y, a1);
-            }
-            *reinterpret_cast<double2*>(Y + (long long)row * ldy + c0) = make_double2(a0, a1);
-        } else {
-            for (int e = beg; e < end; ++e) a0 = fma(val[e], X[(long long)col[e] * ldx + c0], a0);
-            Y[(long long)row * ldy + c0] = a0;
-        }
+        const bool pair_col = c0 + 1 < w;
+        for (int r = rbeg; r < rend; r += 2)
+            spmm_row_pair(r, r + 1 < rend ? r + 1 : -1, rowptr, col, val, X, ldx, Y, ldy, c0,
+                          pair_col);
     }
 }
 
 template <int LPR>
 hipError_t spmm_launch(hipStream_t st, int n, const int* rowptr, const int* col, const double* val,
                        const double* X, long long ldx, double* Y, long long ldy, int w) {
-    constexpr int RPB = kThreads / LPR;
+    constexpr int RPB = (kThreads / LPR) * SPR;
     const int grid = (n + RPB - 1) / RPB;
     hipLaunchKernelGGL(spmm_kernel<LPR>, dim3(grid), dim3(kThreads), 0, st, n, rowptr, col, val, X,
                        ldx, Y, ldy, w);
@@ -247,11 +280,22 @@ __global__ void r2c_kernel(long long n, int w, const double* __restrict__ src, l
 }
 
 // ---------------------------------------------------------------------------
-// Gram product C = U^T V. Workgroup = (row chunk, 96 x 96 output tile); each
-// thread keeps a 6 x 6 register tile; 16 rows of U and V are staged in LDS
-// per step. Partials per chunk are reduced by gram_reduce_kernel.
+// FP64 matrix cores. v_mfma_f64_16x16x4 computes D[16x16] += A[16x4] B[4x16];
+// lane l supplies A[l % 16][l / 16] and B[l / 16][l % 16], and holds
+// D[l / 16 + 4 r][l % 16] in accumulator register r (checked on gfx950).
+typedef double d4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ d4 mfma16(double a, double b, d4 c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+// ---------------------------------------------------------------------------
+// Gram product C = U^T V. Workgroup = (row chunk, 96 x 96 output tile); the
+// four waves split the tile 2 x 2 and each accumulates 3 x 3 MFMA tiles. Rows
+// are the contraction index: 16 rows of U and V are staged in LDS per step.
+// Per-chunk partials are summed by gram_reduce_kernel in a fixed order.
 constexpr int GT = 96;
-constexpr int GK = 16;
+constexpr int GK = 32;
 
 __device__ __forceinline__ void tile_decode(int t, int nt_v, int sym, int& ti, int& tj) {
     if (!sym) {
@@ -268,12 +312,46 @@ __device__ __forceinline__ void tile_decode(int t, int nt_v, int sym, int& ti, i
     tj = i + t;
 }
 
-__global__ __launch_bounds__(kThreads) void gram_kernel(long long n, Segs U, Segs V, int mu, int mv,
+__device__ __forceinline__ const double* seg_col(const Segs& S, int c, bool& ok) {
+    ok = c < S.off[S.nseg];
+    if (!ok) return S.p[0];
+    const double* p = S.p[0];
+    int o = 0;
+    if (S.nseg > 1 && c >= S.off[1]) { p = S.p[1]; o = S.off[1]; }
+    if (S.nseg > 2 && c >= S.off[2]) { p = S.p[2]; o = S.off[2]; }
+    if (S.nseg > 3 && c >= S.off[3]) { p = S.p[3]; o = S.off[3]; }
+    return p + (c - o);
+}
+
+// MFMA work of one stage for a wave whose 48 x 48 block has NI x NJ tiles
+// with data (the others are skipped).
+template <int NI, int NJ>
+__device__ __forceinline__ void gram_compute(const double (*Ts)[2 * GT + 4], d4 (&acc)[3][3], int lr,
+                                             int lc, int wy, int wx) {
+#pragma unroll
+    for (int ks = 0; ks < GK; ks += 4) {
+        double a[NI], b[NJ];
+#pragma unroll
+        for (int i = 0; i < NI; ++i) a[i] = Ts[ks + lr][wy * 48 + i * 16 + lc];
+#pragma unroll
+        for (int j = 0; j < NJ; ++j) b[j] = Ts[ks + lr][GT + wx * 48 + j * 16 + lc];
+#pragma unroll
+        for (int i = 0; i < NI; ++i)
+#pragma unroll
+            for (int j = 0; j < NJ; ++j) acc[i][j] = mfma16(a[i], b[j], acc[i][j]);
+    }
+}
+
+// Loads of one stage: the U tile (GK rows x 96) and the V tile (GK x 96) form
+// a GK x 192 array. Thread t owns columns t%64, t%64+64, t%64+128 and rows
+// t/64 + 4i, so its three column pointers are fixed for the whole chunk and a
+// wave reads 64 consecutive columns of one row.
+__global__ __launch_bounds__(kThreads, 2) void gram_kernel(long long n, Segs U, Segs V, int mu, int mv,
                                                         int nt_v, int sym, int ntiles,
                                                         long long rows_per_chunk,
                                                         double* __restrict__ part) {
-    __shared__ double Us[GK][GT + 2];
-    __shared__ double Vs[GK][GT + 2];
+    constexpr int RPT = GK / 4;  // rows per thread per stage (8)
+    __shared__ double Ts[GK][2 * GT + 4];  // [row][0..95 U | 96..191 V]
     const int lin = xcd_remap(blockIdx.x, gridDim.x);
     const int chunk = lin / ntiles;
     const int tile = lin % ntiles;
@@ -281,54 +359,89 @@ __global__ __launch_bounds__(kThreads) void gram_kernel(long long n, Segs U, Seg
     tile_decode(tile, nt_v, sym, ti, tj);
     const long long r0 = (long long)chunk * rows_per_chunk;
     const long long r1 = min(n, r0 + rows_per_chunk);
-    const int tx = threadIdx.x % 16, ty = threadIdx.x / 16;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int wy = wv >> 1, wx = wv & 1;
     const int cu0 = ti * GT, cv0 = tj * GT;
-    double acc[6][6];
-#pragma unroll
-    for (int i = 0; i < 6; ++i)
-#pragma unroll
-        for (int j = 0; j < 6; ++j) acc[i][j] = 0.0;
+    const int lr = lane >> 4, lc = lane & 15;
+    const int niv = max(0, min(3, (mu - cu0 - wy * 48 + 15) / 16));
+    const int njv = max(0, min(3, (mv - cv0 - wx * 48 + 15) / 16));
+    const int shape = niv * 4 + njv;
 
+    // fixed column pointers of this thread (c < 96: U, else V)
+    const double* cp[3];
+    bool cok[3];
+    long long cld[3];
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+        const int c = lane + 64 * q;
+        if (c < GT) {
+            cp[q] = seg_col(U, cu0 + c, cok[q]);
+            cld[q] = U.ld;
+        } else {
+            cp[q] = seg_col(V, cv0 + c - GT, cok[q]);
+            cld[q] = V.ld;
+        }
+    }
+    d4 acc[3][3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) acc[i][j] = d4{0.0, 0.0, 0.0, 0.0};
+    double rg[RPT][3];
+
+    auto fetch = [&](long long rb) {
+#pragma unroll
+        for (int i = 0; i < RPT; ++i) {
+            const long long r = rb + wv + 4 * i;
+            const bool rok = r < r1;
+#pragma unroll
+            for (int q = 0; q < 3; ++q) rg[i][q] = (rok && cok[q]) ? cp[q][r * cld[q]] : 0.0;
+        }
+    };
+    auto stash = [&]() {
+#pragma unroll
+        for (int i = 0; i < RPT; ++i)
+#pragma unroll
+            for (int q = 0; q < 3; ++q) Ts[wv + 4 * i][lane + 64 * q] = rg[i][q];
+    };
+
+    if (r0 < r1) {
+        fetch(r0);
+        stash();
+    }
+    __syncthreads();
     for (long long rb = r0; rb < r1; rb += GK) {
-#pragma unroll
-        for (int q = 0; q < (GK * GT) / kThreads; ++q) {
-            const int e = threadIdx.x + kThreads * q;
-            const int kk = e / GT, c = e % GT;
-            const long long r = rb + kk;
-            double u = 0.0, v = 0.0;
-            if (r < r1) {
-                if (cu0 + c < mu) u = *seg_addr(U, r, cu0 + c);
-                if (cv0 + c < mv) v = *seg_addr(V, r, cv0 + c);
-            }
-            Us[kk][c] = u;
-            Vs[kk][c] = v;
+        const bool more = rb + GK < r1;
+        if (more) fetch(rb + GK);
+        switch (shape) {  // uniform per wave: skip MFMA tiles without data
+            case 15: gram_compute<3, 3>(Ts, acc, lr, lc, wy, wx); break;
+            case 14: gram_compute<3, 2>(Ts, acc, lr, lc, wy, wx); break;
+            case 13: gram_compute<3, 1>(Ts, acc, lr, lc, wy, wx); break;
+            case 11: gram_compute<2, 3>(Ts, acc, lr, lc, wy, wx); break;
+            case 10: gram_compute<2, 2>(Ts, acc, lr, lc, wy, wx); break;
+            case 9: gram_compute<2, 1>(Ts, acc, lr, lc, wy, wx); break;
+            case 7: gram_compute<1, 3>(Ts, acc, lr, lc, wy, wx); break;
+            case 6: gram_compute<1, 2>(Ts, acc, lr, lc, wy, wx); break;
+            case 5: gram_compute<1, 1>(Ts, acc, lr, lc, wy, wx); break;
+            default: break;
         }
         __syncthreads();
-#pragma unroll
-        for (int kk = 0; kk < GK; ++kk) {
-            double a[6], b[6];
-#pragma unroll
-            for (int i = 0; i < 6; ++i) a[i] = Us[kk][ty * 6 + i];
-#pragma unroll
-            for (int j = 0; j < 6; ++j) b[j] = Vs[kk][tx * 6 + j];
-#pragma unroll
-            for (int i = 0; i < 6; ++i)
-#pragma unroll
-                for (int j = 0; j < 6; ++j) acc[i][j] = fma(a[i], b[j], acc[i][j]);
+        if (more) {
+            stash();
+            __syncthreads();
         }
-        __syncthreads();
     }
     double* P = part + (long long)chunk * mu * mv;
 #pragma unroll
-    for (int i = 0; i < 6; ++i) {
-        const int gi = cu0 + ty * 6 + i;
-        if (gi >= mu) continue;
+    for (int i = 0; i < 3; ++i)
 #pragma unroll
-        for (int j = 0; j < 6; ++j) {
-            const int gj = cv0 + tx * 6 + j;
-            if (gj < mv) P[(long long)gi * mv + gj] = acc[i][j];
-        }
-    }
+        for (int j = 0; j < 3; ++j)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int gi = cu0 + wy * 48 + i * 16 + lr + 4 * r;
+                const int gj = cv0 + wx * 48 + j * 16 + lc;
+                if (gi < mu && gj < mv) P[(long long)gi * mv + gj] = acc[i][j][r];
+            }
 }
 
 __global__ __launch_bounds__(kThreads) void gram_reduce_kernel(int mu, int mv, int nchunks, int sym,
@@ -338,11 +451,19 @@ __global__ __launch_bounds__(kThreads) void gram_reduce_kernel(int mu, int mv, i
     if (idx >= (long long)mu * mv) return;
     const int i = (int)(idx / mv), j = (int)(idx % mv);
     const long long stride = (long long)mu * mv;
+    // four interleaved partial sums combined in a fixed order (deterministic)
     auto sum = [&](int a, int b) {
-        double s = 0.0;
         const double* p = part + (long long)a * mv + b;
-        for (int c = 0; c < nchunks; ++c) s += p[c * stride];
-        return s;
+        double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+        int c = 0;
+        for (; c + 4 <= nchunks; c += 4) {
+            s0 += p[(c + 0) * stride];
+            s1 += p[(c + 1) * stride];
+            s2 += p[(c + 2) * stride];
+            s3 += p[(c + 3) * stride];
+        }
+        for (; c < nchunks; ++c) s0 += p[c * stride];
+        return (s0 + s1) + (s2 + s3);
     };
     double v;
     if (!sym) {
@@ -364,8 +485,8 @@ void gram_plan(long long n, int mu, int mv, int sym, int& ntiles, int& nt_v, int
     const int nt_u = (mu + GT - 1) / GT;
     nt_v = (mv + GT - 1) / GT;
     ntiles = sym ? nt_u * (nt_u + 1) / 2 : nt_u * nt_v;
-    long long want = (2048 + ntiles - 1) / ntiles;
-    const long long maxc = (n + GK - 1) / GK;
+    long long want = (640 + ntiles - 1) / ntiles;  // ~2.5 workgroups per CU
+    const long long maxc = (n + 255) / 256;        // at least 256 rows per chunk
     if (want > maxc) want = maxc;
     if (want < 1) want = 1;
     rows = (n + want - 1) / want;
@@ -376,73 +497,103 @@ void gram_plan(long long n, int mu, int mv, int sym, int& ntiles, int& nt_v, int
 }
 
 // ---------------------------------------------------------------------------
-// Basis update Out = beta Out + alpha U C. Workgroup = 64 rows x 96 output columns;
-// each thread keeps a 4 x 6 register tile; K is streamed through LDS in steps
-// of 16 together with the matching rows of C.
+// Basis update Out = beta Out + alpha U C. Workgroup = 64 rows x (16 NT)
+// output columns; wave w owns rows 16w..16w+15 and NT MFMA tiles along N. K is
+// streamed through LDS 32 at a time with the matching rows of C; the global
+// loads of the next stage are issued into registers before the MFMAs of the
+// current stage, so their latency overlaps the matrix-core work.
 constexpr int UM = 64;
-constexpr int UN = 96;
-constexpr int UK = 16;
+constexpr int UK = 32;
 
-__global__ __launch_bounds__(kThreads) void update_kernel(long long n, Segs U, int K,
+template <int NT>
+__global__ __launch_bounds__(kThreads, (NT > 8 ? 1 : 2)) void update_kernel(long long n, Segs U, int K,
                                                           const double* __restrict__ C, int N,
                                                           Segs O, double alpha, double beta,
                                                           int ntn) {
-    __shared__ double Us[UK][UM + 2];
-    __shared__ double Cs[UK][UN + 2];
+    constexpr int BN = 16 * NT;
+    constexpr int UQ = (UM * UK) / kThreads;  // U elements per thread per stage (8)
+    constexpr int CQ = (UK * BN) / kThreads;  // C elements per thread per stage (2 NT)
+    __shared__ double Us[UK][UM + 4];
+    __shared__ double Cs[UK][BN + 4];
     const int lin = xcd_remap(blockIdx.x, gridDim.x);
     const int rb = lin / ntn, tn = lin % ntn;
     const long long r0 = (long long)rb * UM;
-    const int n0 = tn * UN;
-    const int tx = threadIdx.x % 16, ty = threadIdx.x / 16;
-    double acc[4][6];
+    const int n0 = tn * BN;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int lr = lane >> 4, lc = lane & 15;
+    d4 acc[NT];
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
-#pragma unroll
-        for (int j = 0; j < 6; ++j) acc[i][j] = 0.0;
+    for (int t = 0; t < NT; ++t) acc[t] = d4{0.0, 0.0, 0.0, 0.0};
+    double ru[UQ], rc[CQ];
 
+    // U loads: thread t owns k-column t % UK and rows t / UK + 8 i of a stage;
+    // its segment pointer is resolved once per stage.
+    auto fetch = [&](int k0) {
+        bool ok;
+        const double* up = seg_col(U, k0 + (int)(threadIdx.x % UK), ok);
+#pragma unroll
+        for (int q = 0; q < UQ; ++q) {
+            const long long r = r0 + threadIdx.x / UK + (kThreads / UK) * q;
+            ru[q] = (ok && r < n) ? up[r * U.ld] : 0.0;
+        }
+#pragma unroll
+        for (int q = 0; q < CQ; ++q) {
+            const int e = threadIdx.x + kThreads * q;
+            const int kk = e / BN, c = e % BN;
+            const int kc = k0 + kk;
+            rc[q] = (kc < K && n0 + c < N) ? C[(long long)kc * N + n0 + c] : 0.0;
+        }
+    };
+    auto stash = [&]() {
+#pragma unroll
+        for (int q = 0; q < UQ; ++q)
+            Us[threadIdx.x % UK][threadIdx.x / UK + (kThreads / UK) * q] = ru[q];
+#pragma unroll
+        for (int q = 0; q < CQ; ++q) {
+            const int e = threadIdx.x + kThreads * q;
+            Cs[e / BN][e % BN] = rc[q];
+        }
+    };
+
+    fetch(0);
+    stash();
+    __syncthreads();
     for (int k0 = 0; k0 < K; k0 += UK) {
+        const bool more = k0 + UK < K;
+        if (more) fetch(k0 + UK);
 #pragma unroll
-        for (int q = 0; q < (UM * UK) / kThreads; ++q) {
-            const int e = threadIdx.x + kThreads * q;
-            const int row = e / UK, kk = e % UK;
-            const long long r = r0 + row;
-            const int kc = k0 + kk;
-            Us[kk][row] = (r < n && kc < K) ? *seg_addr(U, r, kc) : 0.0;
-        }
+        for (int ks = 0; ks < UK; ks += 4) {
+            const double a = Us[ks + lr][wv * 16 + lc];
 #pragma unroll
-        for (int q = 0; q < (UK * UN) / kThreads; ++q) {
-            const int e = threadIdx.x + kThreads * q;
-            const int kk = e / UN, c = e % UN;
-            const int kc = k0 + kk;
-            Cs[kk][c] = (kc < K && n0 + c < N) ? C[(long long)kc * N + n0 + c] : 0.0;
+            for (int t = 0; t < NT; ++t) acc[t] = mfma16(a, Cs[ks + lr][t * 16 + lc], acc[t]);
         }
         __syncthreads();
-#pragma unroll
-        for (int kk = 0; kk < UK; ++kk) {
-            double a[4], b[6];
-#pragma unroll
-            for (int i = 0; i < 4; ++i) a[i] = Us[kk][ty * 4 + i];
-#pragma unroll
-            for (int j = 0; j < 6; ++j) b[j] = Cs[kk][tx * 6 + j];
-#pragma unroll
-            for (int i = 0; i < 4; ++i)
-#pragma unroll
-                for (int j = 0; j < 6; ++j) acc[i][j] = fma(a[i], b[j], acc[i][j]);
-        }
-        __syncthreads();
-    }
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-        const long long r = r0 + ty * 4 + i;
-        if (r >= n) continue;
-#pragma unroll
-        for (int j = 0; j < 6; ++j) {
-            const int c = n0 + tx * 6 + j;
-            if (c >= N) continue;
-            double* p = const_cast<double*>(seg_addr(O, r, c));
-            *p = (beta != 0.0) ? fma(beta, *p, alpha * acc[i][j]) : alpha * acc[i][j];
+        if (more) {
+            stash();
+            __syncthreads();
         }
     }
+#pragma unroll
+    for (int t = 0; t < NT; ++t)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const long long row = r0 + wv * 16 + lr + 4 * r;
+            const int c = n0 + t * 16 + lc;
+            if (row < n && c < N) {
+                double* p = const_cast<double*>(seg_addr(O, row, c));
+                *p = (beta != 0.0) ? fma(beta, *p, alpha * acc[t][r]) : alpha * acc[t][r];
+            }
+        }
+}
+
+template <int NT>
+void update_launch(hipStream_t st, long long n, const Segs& U, int K, const double* C, int N,
+                   const Segs& O, double alpha, double beta) {
+    constexpr int BN = 16 * NT;
+    const int ntn = (N + BN - 1) / BN;
+    const long long nrb = (n + UM - 1) / UM;
+    hipLaunchKernelGGL(update_kernel<NT>, dim3((unsigned)(nrb * ntn)), dim3(kThreads), 0, st, n, U, K,
+                       C, N, O, alpha, beta, ntn);
 }
 
 }  // namespace
@@ -556,10 +707,20 @@ hipError_t launch_update(hipStream_t st, long long n, const Segs& U, const doubl
                          const Segs& O, double alpha, double beta) {
     const int K = segs_width(U);
     if (N <= 0 || n <= 0) return hipSuccess;
-    const int ntn = (N + UN - 1) / UN;
-    const long long nrb = (n + UM - 1) / UM;
-    hipLaunchKernelGGL(update_kernel, dim3((unsigned)(nrb * ntn)), dim3(kThreads), 0, st, n, U, K, C, N,
-                       O, alpha, beta, ntn);
+    // Column tiles of 16 NT columns: the fewest tiles with NT <= 8 (which
+    // keeps two workgroups per CU), NT as small as that tile count allows.
+    const int need = (N + 15) / 16;
+    const int nct = (need + 7) / 8;
+    switch ((need + nct - 1) / nct) {
+        case 1: update_launch<1>(st, n, U, K, C, N, O, alpha, beta); break;
+        case 2: update_launch<2>(st, n, U, K, C, N, O, alpha, beta); break;
+        case 3: update_launch<3>(st, n, U, K, C, N, O, alpha, beta); break;
+        case 4: update_launch<4>(st, n, U, K, C, N, O, alpha, beta); break;
+        case 5: update_launch<5>(st, n, U, K, C, N, O, alpha, beta); break;
+        case 6: update_launch<6>(st, n, U, K, C, N, O, alpha, beta); break;
+        case 7: update_launch<7>(st, n, U, K, C, N, O, alpha, beta); break;
+        default: update_launch<8>(st, n, U, K, C, N, O, alpha, beta); break;
+    }
     return hipGetLastError();
 }
 

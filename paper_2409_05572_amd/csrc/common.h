@@ -87,16 +87,19 @@ hipError_t launch_update(hipStream_t st, long long n, const Segs& U, const doubl
 hipError_t launch_chol_drop(hipStream_t st, int a, const double* G, double* T, double* work,
                             int* info_i, double* info_d, double drop_tol2);
 
-// Symmetric eigensolver: A (m x m row-major) overwritten; w ascending; Z
-// row-major (eigenvector c in column c). work needs syev_work_doubles(m).
+// Symmetric eigensolver for the k algebraically smallest eigenpairs of the
+// m x m matrix A (row-major, overwritten): w[0..k) ascending, Z row-major
+// m x k (leading dimension k, eigenvector c in column c). work needs
+// syev_work_doubles(m). launch_syev is the k = m case.
 size_t syev_work_doubles(int m);
+hipError_t launch_syev_lowest(hipStream_t st, int m, int k, double* A, double* w, double* Z,
+                              double* work);
 hipError_t launch_syev(hipStream_t st, int m, double* A, double* w, double* Z, double* work);
 
-// Hetmaniuk-Lehoucq coefficients: from Z (m x m) and the positions act[0..a)
-// of the unlocked old X columns within the first k basis vectors, writes
-// C (m x (k + r), leading dimension k + r) = [Z1 | Z2 Q_B] and r to info_i[0].
-// work needs (m - k) * (a + 1) + 4 * a doubles.
-hipError_t launch_hl(hipStream_t st, int m, int k, const double* Z, const int* act, int a,
-                     double* C, double* work, int* info_i, double drop_tol);
+// Hetmaniuk-Lehoucq start block from Z1 (m x k, ld k) and the positions
+// act[0..a) of the unlocked old X columns: B (m x a, ld a) = unit columns
+// e_{act[c]}, Y (k x a, ld a) = rows act[c] of Z1, transposed.
+hipError_t launch_hl_init(hipStream_t st, int m, int k, const double* Z1, const int* act, int a,
+                          double* B, double* Y);
 
 }  // namespace se

@@ -150,6 +150,10 @@ struct Solver {
         HC(ws.syev_work.ensure(sizeof(double) * syev_work_doubles(mmax)));
         HC(ws.gram_part.ensure(sizeof(double) * std::max(gram_scratch_doubles(n, mmax, mmax),
                                                          (size_t)4096 * 2 * mmax)));
+        HC(ws.hlB.ensure(sizeof(double) * mm));
+        HC(ws.hlY.ensure(sizeof(double) * mm));
+        HC(ws.hlG.ensure(sizeof(double) * mm));
+        HC(ws.hlQ.ensure(sizeof(double) * mm));
         HC(ws.act.ensure(sizeof(int) * (mmax + 8)));
         HC(ws.act_hl.ensure(sizeof(int) * (mmax + 8)));
         HC(ws.norms.ensure(sizeof(double) * (2 * mmax + 8)));
@@ -227,6 +231,67 @@ struct Solver {
         HC(launch_update(st, n, U, C, N, O, alpha, beta));
         const double K = segs_width(U);
         return toc(SE_K_UPDATE, 8.0 * n * (K + N * (beta != 0.0 ? 2.0 : 1.0)), 2.0 * n * K * N);
+    }
+
+    // Products on small row counts (coefficient space of the Rayleigh-Ritz
+    // basis); each Segs carries its own leading dimension.
+    static Segs segx(const double* p_, int w, long long ldx) {
+        Segs s = make_segs(ldx);
+        push_seg(s, p_, w);
+        return s;
+    }
+    se_status gram_rows(long long rows, const Segs& U, const Segs& V, int sym, double* C) {
+        HC(launch_gram(st, rows, U, V, sym, ws.gram_part.as<double>(), C));
+        return SE_OK;
+    }
+    se_status update_rows(long long rows, const Segs& U, const double* C, int N, const Segs& O,
+                          double alpha, double beta) {
+        HC(launch_update(st, rows, U, C, N, O, alpha, beta));
+        return SE_OK;
+    }
+
+    // Coefficients C = [Z1 | C_P] (m x (k + r), leading dimension k + r) of the
+    // Hetmaniuk-Lehoucq basis: C_P is an orthonormal basis of the part of the
+    // unlocked old X columns (unit vectors E) orthogonal to Z1, i.e. of
+    // (I - Z1 Z1^T) E, which equals Z2 Z2^T E. The projection is applied twice
+    // before and once after the first Cholesky-QR, so C_P is orthogonal to Z1
+    // to working precision; columns that lose their independent part are
+    // dropped. Returns r through rP.
+    se_status hl_coefficients(int m, int k, int a, int& rP) {
+        const double* Z1 = ws.Z.as<double>();
+        double* B = ws.hlB.as<double>();
+        double* Y = ws.hlY.as<double>();
+        double* G2 = ws.hlG.as<double>();
+        double* Q = ws.hlQ.as<double>();
+        double* C = ws.C.as<double>();
+        rP = 0;
+        if (a > 0) {
+            HC(launch_hl_init(st, m, k, Z1, ws.act_hl.as<int>(), a, B, Y));
+            const Segs Zs = segx(Z1, k, k);
+            ST(update_rows(m, Zs, Y, a, segx(B, a, a), -1.0, 1.0));
+            ST(gram_rows(m, Zs, segx(B, a, a), 0, G2));
+            ST(update_rows(m, Zs, G2, a, segx(B, a, a), -1.0, 1.0));
+            ST(gram_rows(m, segx(B, a, a), segx(B, a, a), 1, ws.G.as<double>()));
+            int* info_i = ws.info.as<int>();
+            double* info_d = ws.info.as<double>() + (a + 8) / 2 + 4;
+            HC(launch_chol_drop(st, a, ws.G.as<double>(), ws.T.as<double>(), ws.small_work.as<double>(),
+                                info_i, info_d, 1e-13));
+            HC(hipMemcpyAsync(ws.h_info.p, ws.info.p, sizeof(int) * 4, hipMemcpyDeviceToHost, st));
+            ST(sync());
+            const int r = ws.h_info.as<int>()[0];
+            if (r > 0) {
+                ST(update_rows(m, segx(B, a, a), ws.T.as<double>(), r, segx(Q, r, r), 1.0, 0.0));
+                ST(gram_rows(m, Zs, segx(Q, r, r), 0, G2));
+                ST(update_rows(m, Zs, G2, r, segx(Q, r, r), -1.0, 1.0));
+                ST(gram_rows(m, segx(Q, r, r), segx(Q, r, r), 1, ws.G.as<double>()));
+                HC(launch_chol_drop(st, r, ws.G.as<double>(), ws.T.as<double>(),
+                                    ws.small_work.as<double>(), info_i, info_d, -1.0));
+                ST(update_rows(m, segx(Q, r, r), ws.T.as<double>(), r, segx(C + k, r, k + r), 1.0, 0.0));
+            }
+            rP = r;
+        }
+        HC(launch_copy_cols(st, m, Z1, k, 0, C, k + rP, 0, k));
+        return SE_OK;
     }
 
     // Cholesky-QR applied twice (a third time after a tiny pivot) with column
@@ -440,19 +505,17 @@ struct Solver {
             const Segs AS = seg3(AX, k, AP, pw, AW, a);
             ST(gram(S, AS, 1, ws.G.as<double>()));
             ST(tic());
-            HC(launch_syev(st, m, ws.G.as<double>(), ws.theta.as<double>(), ws.Z.as<double>(),
-                           ws.syev_work.as<double>()));
-            ST(toc(SE_K_EIG, 16.0 * m * m, 4.0 * m * m * (double)m));
+            HC(launch_syev_lowest(st, m, k, ws.G.as<double>(), ws.theta.as<double>(), ws.Z.as<double>(),
+                                  ws.syev_work.as<double>()));
+            ST(toc(SE_K_EIG, 8.0 * m * m, 4.0 * m * m * (double)m / 3.0));
             const int ahl = (int)act_hl.size();
             std::memcpy(ws.h_act_hl.p, act_hl.data(), sizeof(int) * ahl);
             HC(hipMemcpyAsync(ws.act_hl.p, ws.h_act_hl.p, sizeof(int) * ahl, hipMemcpyHostToDevice, st));
+            int rPv = 0;
             ST(tic());
-            HC(launch_hl(st, m, k, ws.Z.as<double>(), ws.act_hl.as<int>(), ahl, ws.C.as<double>(),
-                         ws.small_work.as<double>(), ws.info.as<int>(), 1e-12));
-            ST(toc(SE_K_SMALL, 16.0 * m * m, 4.0 * m * ahl * (double)(m - k)));
-            HC(hipMemcpyAsync(ws.h_info.p, ws.info.p, sizeof(int) * 4, hipMemcpyDeviceToHost, st));
-            ST(sync());
-            const int rP = ws.h_info.as<int>()[0];
+            ST(hl_coefficients(m, k, ahl, rPv));
+            ST(toc(SE_K_SMALL, 16.0 * m * (k + ahl), 8.0 * m * (double)k * ahl));
+            const int rP = rPv;
             Segs O = make_segs(ld);
             push_seg(O, Xn, k);
             push_seg(O, Pn, rP);

@@ -65,20 +65,21 @@ constexpr int kNumPanels = 14;
 struct Workspace {
     DevBuf panel[kNumPanels];  // n x ld blocks
     DevBuf gram_part, G, T, Z, theta, C, small_work, syev_work, lam, act, act_hl, norms, info;
+    DevBuf hlB, hlY, hlG, hlQ;
     HostBuf h_norms, h_info, h_act, h_act_hl, h_theta;
     std::vector<hipEvent_t> events;  // pool for per-launch timing
     size_t device_bytes() const {
         size_t s = 0;
         for (const auto& b : panel) s += b.bytes;
         const DevBuf* all[] = {&gram_part, &G, &T, &Z, &theta, &C, &small_work, &syev_work,
-                               &lam, &act, &act_hl, &norms, &info};
+                               &lam, &act, &act_hl, &norms, &info, &hlB, &hlY, &hlG, &hlQ};
         for (auto* b : all) s += b->bytes;
         return s;
     }
     void release() {
         for (auto& b : panel) b.release();
         DevBuf* all[] = {&gram_part, &G, &T, &Z, &theta, &C, &small_work, &syev_work,
-                         &lam, &act, &act_hl, &norms, &info};
+                         &lam, &act, &act_hl, &norms, &info, &hlB, &hlY, &hlG, &hlQ};
         for (auto* b : all) b->release();
         h_norms.release();
         h_info.release();

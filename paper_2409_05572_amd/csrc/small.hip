@@ -1,7 +1,8 @@
-// Small dense FP64 kernels of the Rayleigh-Ritz step: Cholesky-QR transform,
-// the spectral decomposition of the projected matrix A_p, and the
-// Hetmaniuk-Lehoucq coefficients. Each works on one matrix of order <= 1024
-// that lives in global memory (L2-resident at these sizes).
+// Small dense FP64 kernels of the Rayleigh-Ritz step: the Cholesky-QR
+// transform, the spectral decomposition of the projected matrix A_p (only the
+// lowest k eigenpairs are formed), and the Hetmaniuk-Lehoucq start block. Each
+// works on one matrix of order <= 1024, kept in LDS when it fits and in global
+// memory (L2-resident) otherwise.
 #include <cfloat>
 
 #include "common.h"
@@ -10,82 +11,91 @@ namespace se {
 
 namespace {
 
-constexpr int kBig = 1024;  // threads of the single-workgroup kernels
-constexpr int kWaves = kBig / 64;
-
-// Sum over the whole workgroup in a fixed order. `sh` holds >= kWaves doubles.
-__device__ double block_sum(double v, double* sh) {
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
-    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-    __syncthreads();
-    if (lane == 0) sh[wid] = v;
-    __syncthreads();
-    double s = 0.0;
-    const int nw = (blockDim.x + 63) >> 6;
-    for (int q = 0; q < nw; ++q) s += sh[q];
-    __syncthreads();
-    return s;
-}
+constexpr int kSmall = 512;  // threads of the single-workgroup kernels
+constexpr int kSWaves = kSmall / 64;
+constexpr int kLdsDoubles = 12800;  // 100 KB of dynamic LDS for an in-LDS matrix
 
 __device__ __forceinline__ double wave_sum(double v) {
     for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
     return __shfl(v, 0, 64);
 }
 
-// ---------------------------------------------------------------------------
-// Cholesky-QR transform with column drop. Columns are first scaled to unit
-// norm (G -> D G D) so that the pivots measure the part of each column that is
-// independent of the previous ones; a column whose pivot is below drop_tol2 is
-// dropped. T = D R^{-1} restricted to the kept columns, written a x r with
-// leading dimension r.
-__global__ __launch_bounds__(kBig) void chol_drop_kernel(int a, const double* __restrict__ G,
-                                                         double* __restrict__ T,
-                                                         double* __restrict__ work,
-                                                         int* __restrict__ info_i,
-                                                         double* __restrict__ info_d,
-                                                         double drop_tol2) {
-    double* L = work;               // a x a, lower triangle used
-    double* D = work + (size_t)a * a;  // a
-    double* Rinv = D + a;           // a x a (r x r used), row-major ld a
-    __shared__ int s_pos[kBig];
-    __shared__ int s_kept[kBig];
-    __shared__ double s_red[kWaves];
-    const int t = threadIdx.x;
+// Workgroup sum in a fixed order; `sh` holds kSWaves doubles. Two barriers.
+__device__ double block_sum(double v, double* sh) {
+    v = wave_sum(v);
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    if (lane == 0) sh[wid] = v;
+    __syncthreads();
+    double s = 0.0;
+#pragma unroll
+    for (int q = 0; q < kSWaves; ++q) s += sh[q];
+    __syncthreads();
+    return s;
+}
 
-    for (int i = t; i < a; i += kBig) {
+// ---------------------------------------------------------------------------
+// Cholesky-QR transform. Columns are scaled to unit norm (G -> D G D) so the
+// pivots measure the part of each column independent of the previous ones.
+// With drop_tol2 >= 0 a column whose pivot falls below drop_tol2 is dropped;
+// with drop_tol2 < 0 nothing is dropped and tiny pivots are floored (used for
+// bases known to be full rank). T = D R^{-1} restricted to the kept columns,
+// a x r with leading dimension r. The factor lives in one a x a array: L in
+// the lower triangle, R^{-1} in the upper one, their diagonals apart.
+__global__ __launch_bounds__(kSmall) void chol_drop_kernel(int a, const double* __restrict__ G,
+                                                           double* __restrict__ T,
+                                                           double* __restrict__ work,
+                                                           int* __restrict__ info_i,
+                                                           double* __restrict__ info_d,
+                                                           double drop_tol2) {
+    extern __shared__ double dyn[];
+    __shared__ int s_pos[1024];
+    __shared__ int s_kept[1024];
+    __shared__ double s_D[1024];
+    __shared__ double s_dl[1024];  // diagonal of L
+    __shared__ double s_dr[1024];  // diagonal of R^{-1}
+    __shared__ int s_r;
+    double* F = ((size_t)a * a <= (size_t)kLdsDoubles) ? dyn : work;  // a x a
+    const int t = threadIdx.x;
+    const bool can_drop = drop_tol2 >= 0.0;
+
+    for (int i = t; i < a; i += kSmall) {
         const double g = G[(size_t)i * a + i];
-        D[i] = (g > 0.0) ? 1.0 / sqrt(g) : 0.0;
+        s_D[i] = (g > 0.0) ? 1.0 / sqrt(g) : 0.0;
     }
     __syncthreads();
-    for (size_t e = t; e < (size_t)a * a; e += kBig) {
+    for (size_t e = t; e < (size_t)a * a; e += kSmall) {
         const int i = (int)(e / a), j = (int)(e % a);
-        if (j <= i) L[e] = G[e] * D[i] * D[j];
+        if (j <= i) F[e] = G[e] * s_D[i] * s_D[j];
     }
     __syncthreads();
 
     double minpiv = DBL_MAX;
     for (int j = 0; j < a; ++j) {
-        const double d = L[(size_t)j * a + j];
-        const bool drop = !(d > drop_tol2) || D[j] == 0.0;
-        __syncthreads();
+        double d = F[(size_t)j * a + j];
+        const bool drop = can_drop && (!(d > drop_tol2) || s_D[j] == 0.0);
+        if (!can_drop && !(d > 1e-300)) d = 1e-300;
         if (drop) {
-            for (int i = j + t; i < a; i += kBig) L[(size_t)i * a + j] = 0.0;
-            if (t == 0) s_pos[j] = -1;
+            for (int i = j + 1 + t; i < a; i += kSmall) F[(size_t)i * a + j] = 0.0;
+            if (t == 0) {
+                s_pos[j] = -1;
+                s_dl[j] = 0.0;
+            }
             __syncthreads();
             continue;
         }
         const double piv = sqrt(d);
+        const double inv = 1.0 / piv;
         minpiv = fmin(minpiv, d);
-        for (int i = j + 1 + t; i < a; i += kBig) L[(size_t)i * a + j] /= piv;
+        const int rem = a - j - 1;
+        for (int i = j + 1 + t; i < a; i += kSmall) F[(size_t)i * a + j] *= inv;
         if (t == 0) {
-            L[(size_t)j * a + j] = piv;
+            s_dl[j] = piv;
             s_pos[j] = 0;
         }
         __syncthreads();
-        const int rem = a - j - 1;
-        for (size_t e = t; e < (size_t)rem * rem; e += kBig) {
+        for (size_t e = t; e < (size_t)rem * rem; e += kSmall) {
             const int i = j + 1 + (int)(e / rem), i2 = j + 1 + (int)(e % rem);
-            if (i2 <= i) L[(size_t)i * a + i2] -= L[(size_t)i * a + j] * L[(size_t)i2 * a + j];
+            if (i2 <= i) F[(size_t)i * a + i2] -= F[(size_t)i * a + j] * F[(size_t)i2 * a + j];
         }
         __syncthreads();
     }
@@ -99,57 +109,73 @@ __global__ __launch_bounds__(kBig) void chol_drop_kernel(int a, const double* __
                 ++r;
             }
         }
+        s_r = r;
         info_i[0] = r;
+        info_d[0] = minpiv;
     }
     __syncthreads();
-    const int r = info_i[0];
-    // Back substitution per column q of R^{-1}, R[p][q] = L[kept q][kept p].
-    for (int q = t; q < r; q += kBig) {
+    const int r = s_r;
+    // R^{-1} by back substitution, one column per thread: with R[p][u] =
+    // L[kept u][kept p], X[p][q] = -(sum_{u=p+1..q} R[p][u] X[u][q]) / R[p][p].
+    // X[u][q] (u < q) is stored at F[kept u][kept q] (upper triangle).
+    for (int q = t; q < r; q += kSmall) {
         const int kq = s_kept[q];
-        Rinv[(size_t)q * a + q] = 1.0 / L[(size_t)kq * a + kq];
+        s_dr[q] = 1.0 / s_dl[kq];
         for (int p = q - 1; p >= 0; --p) {
             const int kp = s_kept[p];
-            double s = 0.0;
-            for (int u = p + 1; u <= q; ++u) s += L[(size_t)s_kept[u] * a + kp] * Rinv[(size_t)u * a + q];
-            Rinv[(size_t)p * a + q] = -s / L[(size_t)kp * a + kp];
+            double s = F[(size_t)kq * a + kp] * s_dr[q];
+            for (int u = p + 1; u < q; ++u) {
+                const int ku = s_kept[u];
+                s += F[(size_t)ku * a + kp] * F[(size_t)ku * a + kq];
+            }
+            F[(size_t)kp * a + kq] = -s / s_dl[kp];
         }
     }
     __syncthreads();
-    for (size_t e = t; e < (size_t)a * r; e += kBig) {
+    for (size_t e = t; e < (size_t)a * r; e += kSmall) {
         const int i = (int)(e / r), q = (int)(e % r);
         const int p = s_pos[i];
-        T[e] = (p >= 0 && p <= q) ? D[i] * Rinv[(size_t)p * a + q] : 0.0;
+        double v = 0.0;
+        if (p >= 0 && p <= q) v = s_D[i] * ((p == q) ? s_dr[q] : F[(size_t)i * a + s_kept[q]]);
+        T[e] = v;
     }
-    // smallest pivot over the workgroup (only thread-local copies differ)
-    __syncthreads();
-    if (t == 0) s_red[0] = minpiv;
-    __syncthreads();
-    if (t == 0) info_d[0] = s_red[0];
 }
 
 // ---------------------------------------------------------------------------
 // Householder tridiagonalization of the symmetric m x m matrix A (row-major,
-// both triangles kept up to date). Reflector k acts on rows/columns k+1..m-1:
-// H_k = I - tau_k v_k v_k^T with v_k stored in Vh row k from column k+1
-// (leading 1 explicit). d = diagonal, e = off-diagonal of the result.
-__global__ __launch_bounds__(kBig) void tridiag_kernel(int m, double* __restrict__ A,
-                                                       double* __restrict__ d,
-                                                       double* __restrict__ e,
-                                                       double* __restrict__ tau,
-                                                       double* __restrict__ Vh) {
-    __shared__ double sv[kBig];
-    __shared__ double sw[kBig];
-    __shared__ double sp[kBig];
-    __shared__ double sred[kWaves];
+// both triangles kept up to date; copied into LDS when it fits). Reflector k
+// acts on rows/columns k+1..m-1: H_k = I - tau_k v_k v_k^T with v_k stored in
+// Vh row k from column k+1 (leading 1 explicit). d / e = diagonal /
+// off-diagonal of the result.
+__global__ __launch_bounds__(kSmall) void tridiag_kernel(int m, double* __restrict__ Ag,
+                                                         double* __restrict__ d,
+                                                         double* __restrict__ e,
+                                                         double* __restrict__ tau,
+                                                         double* __restrict__ Vh) {
+    extern __shared__ double dyn[];
+    __shared__ double sv[1024];
+    __shared__ double sw[1024];
+    __shared__ double sp[kSmall];
+    __shared__ double sred[kSWaves];
     __shared__ double s_scal[4];
     const int t = threadIdx.x;
+    const bool in_lds = (size_t)m * m <= (size_t)kLdsDoubles;
+    double* A = in_lds ? dyn : Ag;
+    if (in_lds) {
+        for (size_t q = t; q < (size_t)m * m; q += kSmall) dyn[q] = Ag[q];
+        __syncthreads();
+    }
     for (int k = 0; k + 2 < m; ++k) {
         const int L = m - k - 1;
         const double* row = A + (size_t)k * m + (k + 1);
         double part = 0.0;
-        for (int i = 1 + t; i < L; i += kBig) part += row[i] * row[i];
-        const double sigma2 = block_sum(part, sred);
+        for (int i = 1 + t; i < L; i += kSmall) part += row[i] * row[i];
+        part = wave_sum(part);
+        if ((t & 63) == 0) sred[t >> 6] = part;
+        __syncthreads();
         if (t == 0) {
+            double sigma2 = 0.0;
+            for (int q = 0; q < kSWaves; ++q) sigma2 += sred[q];
             const double alpha = row[0];
             double tk = 0.0, beta = alpha, scale = 0.0;
             if (sigma2 > 0.0) {
@@ -165,41 +191,41 @@ __global__ __launch_bounds__(kBig) void tridiag_kernel(int m, double* __restrict
         }
         __syncthreads();
         const double tk = s_scal[0], scale = s_scal[1];
-        for (int i = t; i < L; i += kBig) {
+        for (int i = t; i < L; i += kSmall) {
             const double v = (i == 0) ? 1.0 : (tk != 0.0 ? row[i] * scale : 0.0);
             sv[i] = v;
             Vh[(size_t)k * m + k + 1 + i] = v;
         }
         __syncthreads();
         if (tk == 0.0) continue;
-        // p = tau * A22 v, A22 = A[k+1:, k+1:]
-        const int G = kBig / L;  // >= 1 because L < m <= 1024
-        {
-            const int i = t % L, g = t / L;
-            double s = 0.0;
-            if (g < G) {
-                const double* base = A + (size_t)(k + 1) * m + (k + 1) + i;
-                for (int jj = g; jj < L; jj += G) s = fma(base[(size_t)jj * m], sv[jj], s);
+        // p = tau * A22 v, A22 = A[k+1:, k+1:]; columns in chunks of up to
+        // kSmall, each column summed by G row groups.
+        const int W = L < kSmall ? L : kSmall;  // columns per chunk
+        const int G = kSmall / W;               // row groups per column (>= 1)
+        for (int base = 0; base < L; base += W) {
+            const int i = base + t % W, g = t / W;
+            if (i < L && g < G) {
+                double s = 0.0;
+                const double* colp = A + (size_t)(k + 1) * m + (k + 1) + i;
+                for (int jj = g; jj < L; jj += G) s = fma(colp[(size_t)jj * m], sv[jj], s);
+                sp[g * W + (i - base)] = s;
             }
-            if (g < G) sp[g * L + i] = s;
+            __syncthreads();
+            if (t < W && base + t < L) {
+                double s = 0.0;
+                for (int q = 0; q < G; ++q) s += sp[q * W + t];
+                sw[base + t] = s * tk;
+            }
+            __syncthreads();
         }
-        __syncthreads();
         double pv = 0.0;
-        for (int i = t; i < L; i += kBig) {
-            double s = 0.0;
-            for (int g = 0; g < G; ++g) s += sp[g * L + i];
-            s *= tk;
-            sw[i] = s;
-            pv += s * sv[i];
-        }
+        for (int i = t; i < L; i += kSmall) pv += sw[i] * sv[i];
         const double Kc = 0.5 * tk * block_sum(pv, sred);
-        for (int i = t; i < L; i += kBig) sw[i] -= Kc * sv[i];
+        for (int i = t; i < L; i += kSmall) sw[i] -= Kc * sv[i];
         __syncthreads();
-        // A22 -= v w^T + w v^T
-        for (size_t q = t; q < (size_t)L * L; q += kBig) {
+        for (size_t q = t; q < (size_t)L * L; q += kSmall) {
             const int jj = (int)(q / L), i = (int)(q % L);
-            double* p = A + (size_t)(k + 1 + jj) * m + (k + 1 + i);
-            *p -= sv[jj] * sw[i] + sw[jj] * sv[i];
+            A[(size_t)(k + 1 + jj) * m + (k + 1 + i)] -= sv[jj] * sw[i] + sw[jj] * sv[i];
         }
         __syncthreads();
     }
@@ -213,9 +239,9 @@ __global__ __launch_bounds__(kBig) void tridiag_kernel(int m, double* __restrict
 }
 
 // ---------------------------------------------------------------------------
-// Eigenvalues of the symmetric tridiagonal (d, e) by multisection: one wave
-// per eigenvalue, each lane evaluates the Sturm count at one of 64 interior
-// points of the current bracket, so the bracket shrinks 65x per round.
+// The k smallest eigenvalues of the symmetric tridiagonal (d, e) by
+// multisection: one wave per eigenvalue, each lane evaluates the Sturm count
+// at one of 64 interior points of the bracket, so it shrinks 65x per round.
 __device__ __forceinline__ int sturm_count(int m, const double* d, const double* e2, double x,
                                            double pivmin) {
     double q = d[0] - x;
@@ -229,13 +255,13 @@ __device__ __forceinline__ int sturm_count(int m, const double* d, const double*
     return cnt;
 }
 
-__global__ __launch_bounds__(256) void bisect_kernel(int m, const double* __restrict__ dg,
+__global__ __launch_bounds__(256) void bisect_kernel(int m, int k, const double* __restrict__ dg,
                                                      const double* __restrict__ eg,
                                                      double* __restrict__ w,
                                                      double* __restrict__ scal) {
-    __shared__ double d[kBig];
-    __shared__ double e2[kBig];
-    __shared__ double s_gl[4], s_gu[4], s_pm[4];
+    __shared__ double d[1024];
+    __shared__ double e2[1024];
+    __shared__ double s_gl[1], s_gu[1], s_pm[1];
     for (int i = threadIdx.x; i < m; i += 256) {
         d[i] = dg[i];
         if (i + 1 < m) e2[i] = eg[i] * eg[i];
@@ -261,7 +287,7 @@ __global__ __launch_bounds__(256) void bisect_kernel(int m, const double* __rest
     __syncthreads();
     const int lane = threadIdx.x & 63;
     const int idx = blockIdx.x * 4 + (threadIdx.x >> 6);
-    if (idx >= m) return;
+    if (idx >= k) return;
     double lo = s_gl[0], hi = s_gu[0];
     const double pivmin = s_pm[0];
     for (int it = 0; it < 40; ++it) {
@@ -286,10 +312,12 @@ __global__ __launch_bounds__(256) void bisect_kernel(int m, const double* __rest
 }
 
 // ---------------------------------------------------------------------------
-// Eigenvectors of the tridiagonal by inverse iteration (one thread per
-// eigenvalue, LU with partial pivoting of T - lambda I), followed by
-// classical Gram-Schmidt twice within clusters of close eigenvalues.
-// ZT[j * m + i] = component j of eigenvector i.
+// Eigenvectors of the tridiagonal for the k computed eigenvalues by inverse
+// iteration (one thread per eigenvalue, two steps from a pseudo-random start,
+// LU with partial pivoting of T - shift I). Shifts that coincide to a few ulps
+// are separated slightly so that a degenerate cluster yields independent
+// vectors; the caller orthonormalizes the block afterwards.
+// ZT[j * k + i] = component j of eigenvector i.
 __device__ __forceinline__ double hash_unit(unsigned i, unsigned j) {
     unsigned h = i * 0x9E3779B1u ^ (j + 0x7F4A7C15u) * 0x85EBCA77u;
     h ^= h >> 15;
@@ -300,237 +328,149 @@ __device__ __forceinline__ double hash_unit(unsigned i, unsigned j) {
     return (double)(h & 0xFFFFFF) / 8388608.0 - 1.0;
 }
 
-__global__ __launch_bounds__(kBig) void invit_kernel(int m, const double* __restrict__ dg,
-                                                     const double* __restrict__ eg,
-                                                     const double* __restrict__ w,
-                                                     const double* __restrict__ scal,
-                                                     double* __restrict__ ZT,
-                                                     double* __restrict__ work) {
-    __shared__ double sred[kWaves];
-    __shared__ double scoef[kBig];
-    __shared__ int s_c0[1];
-    const int M = m;
+__global__ __launch_bounds__(256) void invit_kernel(int m, int k, const double* __restrict__ dg,
+                                                    const double* __restrict__ eg,
+                                                    const double* __restrict__ w,
+                                                    const double* __restrict__ scal,
+                                                    double* __restrict__ ZT,
+                                                    double* __restrict__ work) {
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i >= k) return;
     double* DL = work;
-    double* DD = DL + (size_t)M * M;
-    double* DU = DD + (size_t)M * M;
-    double* DU2 = DU + (size_t)M * M;
-    int* IP = reinterpret_cast<int*>(DU2 + (size_t)M * M);
+    double* DD = DL + (size_t)m * k;
+    double* DU = DD + (size_t)m * k;
+    double* DU2 = DU + (size_t)m * k;
+    int* IP = reinterpret_cast<int*>(DU2 + (size_t)m * k);
     const double tnorm = fmax(scal[0], DBL_MIN);
     const double tiny = DBL_EPSILON * tnorm;
-
-    for (int i = threadIdx.x; i < m; i += kBig) {
-        const double lam = w[i];
-#define AT(arr, j) arr[(size_t)(j) * M + i]
-        // factor T - lam I
-        for (int j = 0; j < m; ++j) {
-            AT(DD, j) = dg[j] - lam;
-            if (j + 1 < m) {
-                AT(DL, j) = eg[j];
-                AT(DU, j) = eg[j];
-            }
-            if (j + 2 < m) AT(DU2, j) = 0.0;
+    const double sep = 10.0 * DBL_EPSILON * tnorm;
+    int run = 0;
+    for (int q = i; q > 0 && w[q] - w[q - 1] <= sep; --q) ++run;
+    const double lam = w[i] + run * sep;
+#define AT(arr, j) arr[(size_t)(j) * k + i]
+    for (int j = 0; j < m; ++j) {
+        AT(DD, j) = dg[j] - lam;
+        if (j + 1 < m) {
+            AT(DL, j) = eg[j];
+            AT(DU, j) = eg[j];
         }
-        for (int j = 0; j + 1 < m; ++j) {
-            const double dj = AT(DD, j), lj = AT(DL, j);
-            if (fabs(dj) >= fabs(lj)) {
-                AT(IP, j) = j;
-                if (dj != 0.0) {
-                    const double f = lj / dj;
-                    AT(DL, j) = f;
-                    AT(DD, j + 1) -= f * AT(DU, j);
-                }
-            } else {
-                const double f = dj / lj;
-                AT(DD, j) = lj;
+        if (j + 2 < m) AT(DU2, j) = 0.0;
+    }
+    for (int j = 0; j + 1 < m; ++j) {
+        const double dj = AT(DD, j), lj = AT(DL, j);
+        if (fabs(dj) >= fabs(lj)) {
+            AT(IP, j) = j;
+            if (dj != 0.0) {
+                const double f = lj / dj;
                 AT(DL, j) = f;
-                const double tmp = AT(DU, j);
-                AT(DU, j) = AT(DD, j + 1);
-                AT(DD, j + 1) = tmp - f * AT(DD, j + 1);
-                if (j + 2 < m) {
-                    AT(DU2, j) = AT(DU, j + 1);
-                    AT(DU, j + 1) = -f * AT(DU, j + 1);
-                }
-                AT(IP, j) = j + 1;
+                AT(DD, j + 1) -= f * AT(DU, j);
+            }
+        } else {
+            const double f = dj / lj;
+            AT(DD, j) = lj;
+            AT(DL, j) = f;
+            const double tmp = AT(DU, j);
+            AT(DU, j) = AT(DD, j + 1);
+            AT(DD, j + 1) = tmp - f * AT(DD, j + 1);
+            if (j + 2 < m) {
+                AT(DU2, j) = AT(DU, j + 1);
+                AT(DU, j + 1) = -f * AT(DU, j + 1);
+            }
+            AT(IP, j) = j + 1;
+        }
+    }
+    for (int j = 0; j < m; ++j)
+        if (fabs(AT(DD, j)) < tiny) AT(DD, j) = copysign(tiny, AT(DD, j) == 0.0 ? 1.0 : AT(DD, j));
+    for (int j = 0; j < m; ++j) AT(ZT, j) = hash_unit((unsigned)i, (unsigned)j);
+    for (int it = 0; it < 2; ++it) {
+        for (int j = 0; j + 1 < m; ++j) {
+            const double bj = AT(ZT, j), bj1 = AT(ZT, j + 1);
+            if (AT(IP, j) == j) {
+                AT(ZT, j + 1) = bj1 - AT(DL, j) * bj;
+            } else {
+                AT(ZT, j) = bj1;
+                AT(ZT, j + 1) = bj - AT(DL, j) * bj1;
             }
         }
-        for (int j = 0; j < m; ++j)
-            if (fabs(AT(DD, j)) < tiny) AT(DD, j) = copysign(tiny, AT(DD, j) == 0.0 ? 1.0 : AT(DD, j));
-        // start vector
-        for (int j = 0; j < m; ++j) AT(ZT, j) = hash_unit((unsigned)i, (unsigned)j);
-        for (int it = 0; it < 3; ++it) {
-            for (int j = 0; j + 1 < m; ++j) {
-                const double bj = AT(ZT, j), bj1 = AT(ZT, j + 1);
-                if (AT(IP, j) == j) {
-                    AT(ZT, j + 1) = bj1 - AT(DL, j) * bj;
-                } else {
-                    AT(ZT, j) = bj1;
-                    AT(ZT, j + 1) = bj - AT(DL, j) * bj1;
-                }
-            }
-            AT(ZT, m - 1) /= AT(DD, m - 1);
-            if (m >= 2) AT(ZT, m - 2) = (AT(ZT, m - 2) - AT(DU, m - 2) * AT(ZT, m - 1)) / AT(DD, m - 2);
-            for (int j = m - 3; j >= 0; --j)
-                AT(ZT, j) = (AT(ZT, j) - AT(DU, j) * AT(ZT, j + 1) - AT(DU2, j) * AT(ZT, j + 2)) / AT(DD, j);
-            double mx = 0.0;
-            for (int j = 0; j < m; ++j) mx = fmax(mx, fabs(AT(ZT, j)));
-            const double sc = (mx > 0.0) ? 1.0 / mx : 1.0;
-            double nr = 0.0;
-            for (int j = 0; j < m; ++j) {
-                const double v = AT(ZT, j) * sc;
-                AT(ZT, j) = v;
-                nr += v * v;
-            }
-            if (it == 2) {
-                const double inv = 1.0 / sqrt(nr);
-                for (int j = 0; j < m; ++j) AT(ZT, j) *= inv;
-            }
+        AT(ZT, m - 1) /= AT(DD, m - 1);
+        if (m >= 2) AT(ZT, m - 2) = (AT(ZT, m - 2) - AT(DU, m - 2) * AT(ZT, m - 1)) / AT(DD, m - 2);
+        for (int j = m - 3; j >= 0; --j)
+            AT(ZT, j) = (AT(ZT, j) - AT(DU, j) * AT(ZT, j + 1) - AT(DU2, j) * AT(ZT, j + 2)) / AT(DD, j);
+        double mx = 0.0;
+        for (int j = 0; j < m; ++j) mx = fmax(mx, fabs(AT(ZT, j)));
+        const double sc = (mx > 0.0) ? 1.0 / mx : 1.0;
+        double nr = 0.0;
+        for (int j = 0; j < m; ++j) {
+            const double v = AT(ZT, j) * sc;
+            AT(ZT, j) = v;
+            nr += v * v;
         }
+        if (it == 1) {
+            const double inv = 1.0 / sqrt(nr);
+            for (int j = 0; j < m; ++j) AT(ZT, j) *= inv;
+        }
+    }
 #undef AT
-    }
-    __syncthreads();
-
-    // Re-orthogonalize within clusters (gap <= 1e-3 ||T||).
-    const double ortol = 1e-3 * tnorm;
-    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-    int c0 = 0;
-    for (int q = 1; q < m; ++q) {
-        if (w[q] - w[q - 1] > ortol) {
-            c0 = q;
-            continue;
-        }
-        for (int pass = 0; pass < 2; ++pass) {
-            // coef[l] = z_l . z_q for l in [c0, q): one wave per l
-            for (int l = c0 + wid; l < q; l += kWaves) {
-                double s = 0.0;
-                for (int j = lane; j < m; j += 64) s += ZT[(size_t)j * M + l] * ZT[(size_t)j * M + q];
-                s = wave_sum(s);
-                if (lane == 0) scoef[l - c0] = s;
-            }
-            __syncthreads();
-            for (int j = threadIdx.x; j < m; j += kBig) {
-                double v = ZT[(size_t)j * M + q];
-                for (int l = c0; l < q; ++l) v -= scoef[l - c0] * ZT[(size_t)j * M + l];
-                ZT[(size_t)j * M + q] = v;
-            }
-            __syncthreads();
-        }
-        double part = 0.0;
-        for (int j = threadIdx.x; j < m; j += kBig) {
-            const double v = ZT[(size_t)j * M + q];
-            part += v * v;
-        }
-        const double nr = block_sum(part, sred);
-        const double inv = nr > 0.0 ? 1.0 / sqrt(nr) : 0.0;
-        for (int j = threadIdx.x; j < m; j += kBig) ZT[(size_t)j * M + q] *= inv;
-        __syncthreads();
-    }
-    (void)s_c0;
 }
 
 // Z = Q ZT with Q = H_0 H_1 ... H_{m-3}; one wave per eigenvector, kept in
-// registers (m <= 1024 -> 16 values per lane).
-__global__ __launch_bounds__(256) void backtransform_kernel(int m, const double* __restrict__ tau,
+// registers (m <= 1024 -> 16 values per lane). ZT and Z are m x k (ld k).
+__global__ __launch_bounds__(256) void backtransform_kernel(int m, int k, const double* __restrict__ tau,
                                                             const double* __restrict__ Vh,
                                                             const double* __restrict__ ZT,
                                                             double* __restrict__ Z) {
-    constexpr int MAXQ = kBig / 64;
+    constexpr int MAXQ = 1024 / 64;
     const int lane = threadIdx.x & 63;
     const int i = blockIdx.x * 4 + (threadIdx.x >> 6);
-    if (i >= m) return;
+    if (i >= k) return;
     double z[MAXQ];
 #pragma unroll
     for (int q = 0; q < MAXQ; ++q) {
         const int j = lane + 64 * q;
-        z[q] = (j < m) ? ZT[(size_t)j * m + i] : 0.0;
+        z[q] = (j < m) ? ZT[(size_t)j * k + i] : 0.0;
     }
-    for (int k = m - 3; k >= 0; --k) {
-        const double tk = tau[k];
+    for (int kk = m - 3; kk >= 0; --kk) {
+        const double tk = tau[kk];
         if (tk == 0.0) continue;
-        const double* v = Vh + (size_t)k * m;  // v[j] valid for j >= k + 1
+        const double* v = Vh + (size_t)kk * m;  // v[j] valid for j >= kk + 1
         double s = 0.0;
 #pragma unroll
         for (int q = 0; q < MAXQ; ++q) {
             const int j = lane + 64 * q;
-            if (j > k && j < m) s = fma(v[j], z[q], s);
+            if (j > kk && j < m) s = fma(v[j], z[q], s);
         }
         s = wave_sum(s) * tk;
 #pragma unroll
         for (int q = 0; q < MAXQ; ++q) {
             const int j = lane + 64 * q;
-            if (j > k && j < m) z[q] = fma(-s, v[j], z[q]);
+            if (j > kk && j < m) z[q] = fma(-s, v[j], z[q]);
         }
     }
 #pragma unroll
     for (int q = 0; q < MAXQ; ++q) {
         const int j = lane + 64 * q;
-        if (j < m) Z[(size_t)j * m + i] = z[q];
+        if (j < m) Z[(size_t)j * k + i] = z[q];
     }
 }
 
 // ---------------------------------------------------------------------------
-// Hetmaniuk-Lehoucq coefficients. Column c of B is row act[c] of Z2 = Z[:, k:];
-// Q_B is built by classical Gram-Schmidt applied twice per column, dropping
-// columns whose remaining norm is below drop_tol times their own norm.
-// C = [Z1 | Z2 Q_B].
-__global__ __launch_bounds__(kBig) void hl_kernel(int m, int k, const double* __restrict__ Z,
-                                                  const int* __restrict__ act, int a,
-                                                  double* __restrict__ C,
-                                                  double* __restrict__ work,
-                                                  int* __restrict__ info_i, double drop_tol) {
-    __shared__ double sv[kBig];
-    __shared__ double scoef[kBig];
-    __shared__ double sred[kWaves];
-    const int L = m - k;
-    double* Q = work;  // column l at Q[l * L + t]
-    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-    int r = 0;
-    for (int c = 0; c < a; ++c) {
-        const int row = act[c];
-        double part = 0.0;
-        for (int t = threadIdx.x; t < L; t += kBig) {
-            const double v = Z[(size_t)row * m + k + t];
-            sv[t] = v;
-            part += v * v;
+// Hetmaniuk-Lehoucq start block: B[:, c] = e_{act[c]} (unit vector in
+// S-coefficients) and Y[:, c] = Z1[act[c], :]^T, so that B - Z1 Y is the part
+// of the old active X columns orthogonal to the new X = S Z1.
+__global__ __launch_bounds__(256) void hl_init_kernel(int m, int k, const double* __restrict__ Z1,
+                                                      const int* __restrict__ act, int a,
+                                                      double* __restrict__ B,
+                                                      double* __restrict__ Y) {
+    const int total = m * a + k * a;
+    for (int q = blockIdx.x * 256 + threadIdx.x; q < total; q += gridDim.x * 256) {
+        if (q < m * a) {
+            const int i = q / a, c = q % a;
+            B[q] = (i == act[c]) ? 1.0 : 0.0;
+        } else {
+            const int r = q - m * a;
+            const int tt = r / a, c = r % a;
+            Y[r] = Z1[(size_t)act[c] * k + tt];
         }
-        const double n0 = sqrt(block_sum(part, sred));
-        for (int pass = 0; pass < 2 && r > 0; ++pass) {
-            for (int l = wid; l < r; l += kWaves) {
-                double s = 0.0;
-                for (int t = lane; t < L; t += 64) s += Q[(size_t)l * L + t] * sv[t];
-                s = wave_sum(s);
-                if (lane == 0) scoef[l] = s;
-            }
-            __syncthreads();
-            for (int t = threadIdx.x; t < L; t += kBig) {
-                double v = sv[t];
-                for (int l = 0; l < r; ++l) v -= scoef[l] * Q[(size_t)l * L + t];
-                sv[t] = v;
-            }
-            __syncthreads();
-        }
-        part = 0.0;
-        for (int t = threadIdx.x; t < L; t += kBig) part += sv[t] * sv[t];
-        const double n1 = sqrt(block_sum(part, sred));
-        if (n0 > 0.0 && n1 > drop_tol * n0) {
-            const double inv = 1.0 / n1;
-            for (int t = threadIdx.x; t < L; t += kBig) Q[(size_t)r * L + t] = sv[t] * inv;
-            ++r;
-        }
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) info_i[0] = r;
-    const int ldo = k + r;  // C is written compactly: m x (k + r)
-    for (size_t e = threadIdx.x; e < (size_t)m * k; e += kBig) {
-        const int i = (int)(e / k), j = (int)(e % k);
-        C[(size_t)i * ldo + j] = Z[(size_t)i * m + j];
-    }
-    for (size_t e = threadIdx.x; e < (size_t)m * r; e += kBig) {
-        const int i = (int)(e / r), l = (int)(e % r);
-        double s = 0.0;
-        const double* zrow = Z + (size_t)i * m + k;
-        const double* ql = Q + (size_t)l * L;
-        for (int t = 0; t < L; ++t) s = fma(zrow[t], ql[t], s);
-        C[(size_t)i * ldo + k + l] = s;
     }
 }
 
@@ -538,38 +478,79 @@ __global__ __launch_bounds__(kBig) void hl_kernel(int m, int k, const double* __
 
 hipError_t launch_chol_drop(hipStream_t st, int a, const double* G, double* T, double* work,
                             int* info_i, double* info_d, double drop_tol2) {
-    if (a <= 0 || a > kBig) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(chol_drop_kernel, dim3(1), dim3(kBig), 0, st, a, G, T, work, info_i, info_d,
+    if (a <= 0 || a > 1024) return hipErrorInvalidValue;
+    const size_t lds = ((size_t)a * a <= (size_t)kLdsDoubles) ? sizeof(double) * (size_t)a * a : 0;
+    hipLaunchKernelGGL(chol_drop_kernel, dim3(1), dim3(kSmall), lds, st, a, G, T, work, info_i, info_d,
                        drop_tol2);
     return hipGetLastError();
 }
 
 size_t syev_work_doubles(int m) {
-    // d, e, tau, scal (4m) + Vh (m^2) + ZT (m^2) + inverse-iteration factors (4 m^2 + m^2/2 ints)
-    return (size_t)4 * m + 8 + (size_t)m * m * 2 + (size_t)m * m * 5;
+    // d, e, tau, scal (4m + 16), Vh (m^2), two eigenvector blocks (2 m^2),
+    // inverse-iteration factors (4 m^2 doubles + m^2 ints), the Gram matrix
+    // and transform of the orthonormalization (2 m^2), its Gram scratch, the
+    // Cholesky work (2 m^2 + 2m) and info words.
+    const size_t mm = (size_t)m * m;
+    return 4 * (size_t)m + 16 + mm + 2 * mm + 5 * mm + 2 * mm + gram_scratch_doubles(m, m, m) +
+           2 * mm + 2 * (size_t)m + 2 * (size_t)m + 64;
 }
 
-hipError_t launch_syev(hipStream_t st, int m, double* A, double* w, double* Z, double* work) {
-    if (m <= 0 || m > kBig) return hipErrorInvalidValue;
+hipError_t launch_syev_lowest(hipStream_t st, int m, int k, double* A, double* w, double* Z,
+                              double* work) {
+    if (m <= 0 || m > 1024 || k <= 0 || k > m) return hipErrorInvalidValue;
+    const size_t mm = (size_t)m * m;
     double* d = work;
     double* e = d + m;
     double* tau = e + m;
     double* scal = tau + m;
-    double* Vh = scal + m + 8;
-    double* ZT = Vh + (size_t)m * m;
-    double* fac = ZT + (size_t)m * m;
-    hipLaunchKernelGGL(tridiag_kernel, dim3(1), dim3(kBig), 0, st, m, A, d, e, tau, Vh);
-    hipLaunchKernelGGL(bisect_kernel, dim3((m + 3) / 4), dim3(256), 0, st, m, d, e, w, scal);
-    hipLaunchKernelGGL(invit_kernel, dim3(1), dim3(kBig), 0, st, m, d, e, w, scal, ZT, fac);
-    hipLaunchKernelGGL(backtransform_kernel, dim3((m + 3) / 4), dim3(256), 0, st, m, tau, Vh, ZT, Z);
+    double* Vh = scal + m + 16;
+    double* ZT = Vh + mm;
+    double* ZT2 = ZT + mm;
+    double* fac = ZT2 + mm;
+    double* Gk = fac + 5 * mm;
+    double* Tk = Gk + mm;
+    double* gpart = Tk + mm;
+    double* cwork = gpart + gram_scratch_doubles(m, m, m);
+    double* infod = cwork + 2 * mm + 2 * (size_t)m;
+    int* infoi = reinterpret_cast<int*>(infod + 8);
+    const size_t lds = (mm <= (size_t)kLdsDoubles) ? sizeof(double) * mm : 0;
+    hipLaunchKernelGGL(tridiag_kernel, dim3(1), dim3(kSmall), lds, st, m, A, d, e, tau, Vh);
+    hipLaunchKernelGGL(bisect_kernel, dim3((k + 3) / 4), dim3(256), 0, st, m, k, d, e, w, scal);
+    hipLaunchKernelGGL(invit_kernel, dim3((k + 255) / 256), dim3(256), 0, st, m, k, d, e, w, scal, ZT,
+                       fac);
+    // Orthonormalize the k vectors (an m x k block whose rows are vector
+    // components): two Cholesky-QR passes without column drop.
+    double* cur = ZT;
+    double* nxt = ZT2;
+    for (int pass = 0; pass < 2; ++pass) {
+        Segs Zs = make_segs(k);
+        push_seg(Zs, cur, k);
+        hipError_t err = launch_gram(st, m, Zs, Zs, 1, gpart, Gk);
+        if (err != hipSuccess) return err;
+        err = launch_chol_drop(st, k, Gk, Tk, cwork, infoi, infod, -1.0);
+        if (err != hipSuccess) return err;
+        Segs Os = make_segs(k);
+        push_seg(Os, nxt, k);
+        err = launch_update(st, m, Zs, Tk, k, Os, 1.0, 0.0);
+        if (err != hipSuccess) return err;
+        double* tmp = cur;
+        cur = nxt;
+        nxt = tmp;
+    }
+    hipLaunchKernelGGL(backtransform_kernel, dim3((k + 3) / 4), dim3(256), 0, st, m, k, tau, Vh, cur, Z);
     return hipGetLastError();
 }
 
-hipError_t launch_hl(hipStream_t st, int m, int k, const double* Z, const int* act, int a, double* C,
-                     double* work, int* info_i, double drop_tol) {
-    if (m <= 0 || m > kBig || k < 0 || k > m) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(hl_kernel, dim3(1), dim3(kBig), 0, st, m, k, Z, act, a, C, work, info_i,
-                       drop_tol);
+hipError_t launch_syev(hipStream_t st, int m, double* A, double* w, double* Z, double* work) {
+    return launch_syev_lowest(st, m, m, A, w, Z, work);
+}
+
+hipError_t launch_hl_init(hipStream_t st, int m, int k, const double* Z1, const int* act, int a,
+                          double* B, double* Y) {
+    if (a <= 0) return hipSuccess;
+    const int total = m * a + k * a;
+    hipLaunchKernelGGL(hl_init_kernel, dim3((total + 255) / 256), dim3(256), 0, st, m, k, Z1, act, a,
+                       B, Y);
     return hipGetLastError();
 }
 
