@@ -199,6 +199,13 @@ se_status se_op_update(se_ctx* ctx, int64_t n, const double* U, int64_t ldu, int
  * eigenvector c in column c. Synchronizes the stream. */
 se_status se_op_syev(se_ctx* ctx, int32_t m, double* A, double* w, double* Z);
 
+/* The k lowest eigenpairs of a symmetric m x m matrix (Algorithm 3 keeps only
+ * the n_es lowest Ritz pairs of A_p), 1 <= k <= m <= 1024. A (row-major,
+ * symmetric) is overwritten; w (k) ascending; Z row-major m x k with
+ * eigenvector c in column c, orthonormal columns also inside degenerate
+ * eigenvalue clusters. Synchronizes the stream. */
+se_status se_op_syev_lowest(se_ctx* ctx, int32_t m, int32_t k, double* A, double* w, double* Z);
+
 /* Orthonormalize the w columns of the n x w block W in place by Cholesky-QR
  * applied twice, dropping numerically dependent columns (the "orthogonalize"
  * step of Algorithms 1 and 3). *rank receives the number of columns kept;

@@ -72,6 +72,8 @@ PROTOTYPES = {
     "se_op_update": (C.c_int, [C.c_void_p, C.c_int64, C.c_void_p, C.c_int64, C.c_int32,
                                C.c_void_p, C.c_int32, C.c_void_p, C.c_int64, C.c_double]),
     "se_op_syev": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p]),
+    "se_op_syev_lowest": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_void_p, C.c_void_p,
+                                    C.c_void_p]),
     "se_op_cholqr": (C.c_int, [C.c_void_p, C.c_int64, C.c_void_p, C.c_int64, C.c_int32,
                                C.POINTER(C.c_int32)]),
     "se_strategy_replay": (C.c_int, [C.POINTER(SeParams), C.c_int32, C.POINTER(C.c_double),

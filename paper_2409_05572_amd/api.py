@@ -160,7 +160,11 @@ def solve(ctx: Context, A: Matrix, X0, n_ev, n_extra, history_cap=0, **kw):
         p.ptr_mode = _lib.SE_PTR_DEVICE
     st = lib().se_solve(ctx.handle, A.handle, C.byref(p), C.c_void_p(_ptr(X0)),
                         C.c_void_p(_ptr(V)), C.c_void_p(_ptr(lam)), C.byref(info))
-    check(st, "se_solve")
+    if st < 0:
+        err = _lib.SeError(st, f"se_solve (hip_error {info.hip_error}, {info.iterations} iterations)")
+        err.hip_error = info.hip_error
+        err.history = hist[: info.history_len].copy()
+        raise err
     out = SolveInfo(st, info.iterations, bool(info.converged), info.n_shrinks, info.n_expands,
                     info.max_stop_ratio, info.max_paper_ratio, info.time_ms,
                     int(info.workspace_bytes), hist[: info.history_len].copy(),
@@ -191,6 +195,12 @@ def update(ctx: Context, U, K: int, Cm, N: int, Out, beta: float = 0.0):
 def syev(ctx: Context, A, w, Z):
     check(lib().se_op_syev(ctx.handle, A.shape[0], C.c_void_p(_ptr(A)), C.c_void_p(_ptr(w)),
                            C.c_void_p(_ptr(Z))), "se_op_syev")
+
+
+def syev_lowest(ctx: Context, A, k: int, w, Z):
+    """The k lowest eigenpairs of the m x m matrix A (overwritten); Z is m x k."""
+    check(lib().se_op_syev_lowest(ctx.handle, A.shape[0], int(k), C.c_void_p(_ptr(A)),
+                                  C.c_void_p(_ptr(w)), C.c_void_p(_ptr(Z))), "se_op_syev_lowest")
 
 
 def cholqr(ctx: Context, W, w: int) -> int:

@@ -232,6 +232,16 @@ se_status se_op_syev(se_ctx* ctx, int32_t m, double* A, double* w, double* Z) {
     return SE_OK;
 }
 
+se_status se_op_syev_lowest(se_ctx* ctx, int32_t m, int32_t k, double* A, double* w, double* Z) {
+    if (!ctx || !A || !w || !Z || m < 1 || m > 1024 || k < 1 || k > m) return SE_ERR_INVALID_ARG;
+    CAPI_HC(ctx, hipSetDevice(ctx->device));
+    CAPI_HC(ctx, hipStreamSynchronize(ctx->stream));
+    CAPI_HC(ctx, ctx->ws.syev_work.ensure(sizeof(double) * se::syev_work_doubles(m)));
+    CAPI_HC(ctx, se::launch_syev_lowest(ctx->stream, m, k, A, w, Z, ctx->ws.syev_work.as<double>()));
+    CAPI_HC(ctx, hipStreamSynchronize(ctx->stream));
+    return SE_OK;
+}
+
 se_status se_op_cholqr(se_ctx* ctx, int64_t n, double* W, int64_t ldw, int32_t w, int32_t* rank) {
     if (!ctx || !W || !rank || n < 1 || w < 1 || w > 1024 || !valid_ld(ldw, w)) return SE_ERR_INVALID_ARG;
     CAPI_HC(ctx, hipSetDevice(ctx->device));

@@ -82,10 +82,12 @@ hipError_t launch_update(hipStream_t st, long long n, const Segs& U, const doubl
 // (a x r, leading dimension r) such that W T has orthonormal columns, r into
 // info_i[0] and the kept input columns (ascending) into info_i[1..r], the
 // smallest scaled pivot into info_d[0]. Columns whose scaled pivot falls below
-// drop_tol2 are dropped (zero rows of T).
+// drop_tol2 are dropped (zero rows of T); drop_tol2 < 0 drops nothing.
+// ns_tol > 0: when ||G - I||_F <= ns_tol the kernel writes the Newton-Schulz
+// transform T = (3 I - G) / 2 instead (r = a, info_d[0] = 1 - ||G - I||_F).
 // work needs 2 a^2 + 2 a doubles.
 hipError_t launch_chol_drop(hipStream_t st, int a, const double* G, double* T, double* work,
-                            int* info_i, double* info_d, double drop_tol2);
+                            int* info_i, double* info_d, double drop_tol2, double ns_tol = 0.0);
 
 // Symmetric eigensolver for the k algebraically smallest eigenpairs of the
 // m x m matrix A (row-major, overwritten): w[0..k) ascending, Z row-major

@@ -255,8 +255,11 @@ struct Solver {
     // unlocked old X columns (unit vectors E) orthogonal to Z1, i.e. of
     // (I - Z1 Z1^T) E, which equals Z2 Z2^T E. The projection is applied twice
     // before and once after the first Cholesky-QR, so C_P is orthogonal to Z1
-    // to working precision; columns that lose their independent part are
-    // dropped. Returns r through rP.
+    // to working precision. Both Cholesky-QR passes may drop columns: a
+    // column kept by the first pass with a pivot near the threshold is mostly
+    // amplified rounding, and the reprojection can leave it dependent on the
+    // others, which a pass without drop would turn into a non-orthonormal
+    // C_P. Returns the final rank through rP.
     se_status hl_coefficients(int m, int k, int a, int& rP) {
         const double* Z1 = ws.Z.as<double>();
         double* B = ws.hlB.as<double>();
@@ -279,16 +282,24 @@ struct Solver {
             HC(hipMemcpyAsync(ws.h_info.p, ws.info.p, sizeof(int) * 4, hipMemcpyDeviceToHost, st));
             ST(sync());
             const int r = ws.h_info.as<int>()[0];
+            int r2 = 0;
             if (r > 0) {
                 ST(update_rows(m, segx(B, a, a), ws.T.as<double>(), r, segx(Q, r, r), 1.0, 0.0));
                 ST(gram_rows(m, Zs, segx(Q, r, r), 0, G2));
                 ST(update_rows(m, Zs, G2, r, segx(Q, r, r), -1.0, 1.0));
                 ST(gram_rows(m, segx(Q, r, r), segx(Q, r, r), 1, ws.G.as<double>()));
-                HC(launch_chol_drop(st, r, ws.G.as<double>(), ws.T.as<double>(),
-                                    ws.small_work.as<double>(), info_i, info_d, -1.0));
-                ST(update_rows(m, segx(Q, r, r), ws.T.as<double>(), r, segx(C + k, r, k + r), 1.0, 0.0));
+                // second pass: a Newton-Schulz step if Q is orthonormal to
+                // 1e-8, else Cholesky-QR with drop (decided on the device)
+                HC(launch_chol_drop(st, r, ws.G.as<double>(), ws.T.as<double>(), ws.small_work.as<double>(),
+                                    info_i, info_d, 1e-13, 1e-8));
+                HC(hipMemcpyAsync(ws.h_info.p, ws.info.p, sizeof(int) * 4, hipMemcpyDeviceToHost, st));
+                ST(sync());
+                r2 = ws.h_info.as<int>()[0];
+                if (r2 > 0)
+                    ST(update_rows(m, segx(Q, r, r), ws.T.as<double>(), r2, segx(C + k, r2, k + r2), 1.0,
+                                   0.0));
             }
-            rP = r;
+            rP = r2;
         }
         HC(launch_copy_cols(st, m, Z1, k, 0, C, k + rP, 0, k));
         return SE_OK;
@@ -297,16 +308,38 @@ struct Solver {
     // Cholesky-QR applied twice (a third time after a tiny pivot) with column
     // drop. The panel pointer `w_panel` (and `companion`, which receives the
     // same transform) is swapped with a spare. kept_out: original indices of
-    // the surviving columns.
-    se_status cholqr(double*& w_panel, int& w, double** companion, std::vector<int>* kept_out) {
+    // the surviving columns. A pass that follows one whose smallest scaled
+    // pivot was >= 1e-8 and that dropped nothing cannot drop a column either;
+    // it runs without a read-back and takes a Newton-Schulz step when the
+    // block is already orthonormal to 1e-8 (decided on the device).
+    // `against` (with images `against_img` for the companion): blocks the
+    // panel was made orthogonal to; after a pass with a pivot below 1e-8 the
+    // kept columns carry amplified rounding along them, so the projection is
+    // repeated before the next pass.
+    se_status cholqr(double*& w_panel, int& w, double** companion, std::vector<int>* kept_out,
+                     const Segs* against = nullptr, const Segs* against_img = nullptr) {
         std::vector<int> map(w);
         for (int i = 0; i < w; ++i) map[i] = i;
         int passes = 2;
+        bool full_rank = false;  // the previous pass kept every column with a healthy pivot
         for (int pass = 0; pass < passes && w > 0; ++pass) {
             const Segs Ws = seg1(w_panel, w);
             ST(gram(Ws, Ws, 1, ws.G.as<double>()));
             int* info_i = ws.info.as<int>();
             double* info_d = ws.info.as<double>() + (w + 8) / 2 + 4;
+            if (full_rank) {
+                ST(tic());
+                HC(launch_chol_drop(st, w, ws.G.as<double>(), ws.T.as<double>(), ws.small_work.as<double>(),
+                                    info_i, info_d, -1.0, 1e-8));
+                ST(toc(SE_K_SMALL, 16.0 * w * w, w * w * (double)w));
+                ST(update(Ws, ws.T.as<double>(), w, seg1(T1, w), 1.0, 0.0));
+                std::swap(w_panel, T1);
+                if (companion) {
+                    ST(update(seg1(*companion, w), ws.T.as<double>(), w, seg1(T2, w), 1.0, 0.0));
+                    std::swap(*companion, T2);
+                }
+                continue;
+            }
             ST(tic());
             HC(launch_chol_drop(st, w, ws.G.as<double>(), ws.T.as<double>(), ws.small_work.as<double>(),
                                 info_i, info_d, 1e-13));
@@ -331,7 +364,14 @@ struct Solver {
                 std::swap(*companion, T2);
             }
             if (pass == 0 && (minpiv < 1e-8 || r < w)) passes = 3;
+            full_rank = minpiv >= 1e-8 && r == w;
             w = r;
+            if (against && minpiv < 1e-8 && pass + 1 < passes) {
+                ST(gram(*against, seg1(w_panel, w), 0, ws.G.as<double>()));
+                ST(update(*against, ws.G.as<double>(), w, seg1(w_panel, w), -1.0, 1.0));
+                if (companion && against_img)
+                    ST(update(*against_img, ws.G.as<double>(), w, seg1(*companion, w), -1.0, 1.0));
+            }
         }
         if (kept_out) *kept_out = map;
         return SE_OK;
@@ -462,12 +502,12 @@ struct Solver {
             ST(tic());
             HC(launch_form_w(st, n, X, AX, ld, ws.theta.as<double>(), ws.act.as<int>(), a, W, ld));
             ST(toc(SE_K_RESID, 24.0 * n * a, 2.0 * n * a));
+            const Segs XP = seg3(X, k, P, pw, nullptr, 0);
             for (int pass = 0; pass < 2; ++pass) {
-                const Segs XP = seg3(X, k, P, pw, nullptr, 0);
                 ST(gram(XP, seg1(W, a), 0, ws.G.as<double>()));
                 ST(update(XP, ws.G.as<double>(), a, seg1(W, a), -1.0, 1.0));
             }
-            ST(cholqr(W, a, nullptr, nullptr));
+            ST(cholqr(W, a, nullptr, nullptr, &XP));
             if (a > 0) ST(spmm(W, AW, a));
 
             act_hl = act;
@@ -482,7 +522,9 @@ struct Solver {
                     ST(update(S, ws.G.as<double>(), d0, seg1(Sd, d0), -1.0, 1.0));
                     ST(update(AS, ws.G.as<double>(), d0, seg1(ASd, d0), -1.0, 1.0));
                 }
-                ST(cholqr(Sd, d0, &ASd, &kept));
+                const Segs S = seg3(X, k, P, pw, W, a);
+                const Segs AS = seg3(AX, k, AP, pw, AW, a);
+                ST(cholqr(Sd, d0, &ASd, &kept, &S, &AS));
                 int dxk = 0;
                 for (int v : kept) dxk += (v < dx);
                 const int dpk = d0 - dxk;

@@ -12,6 +12,7 @@ namespace se {
 namespace {
 
 constexpr int kSmall = 512;  // threads of the single-workgroup kernels
+constexpr int kTri = 1024;   // threads of the global-memory tridiagonalization
 constexpr int kSWaves = kSmall / 64;
 constexpr int kLdsDoubles = 12800;  // 100 KB of dynamic LDS for an in-LDS matrix
 
@@ -41,29 +42,56 @@ __device__ double block_sum(double v, double* sh) {
 // bases known to be full rank). T = D R^{-1} restricted to the kept columns,
 // a x r with leading dimension r. The factor lives in one a x a array: L in
 // the lower triangle, R^{-1} in the upper one, their diagonals apart.
+//
+// With ns_tol > 0 the kernel first measures ||G - I||_F. When it is at most
+// ns_tol the block is already orthonormal to that level and one Newton-Schulz
+// step T = (3 I - G) / 2 replaces the factorization: the Gram matrix of W T
+// is I - (3/4) E^2 - (1/4) E^3 with E = G - I, so ns_tol = 1e-8 leaves an
+// error below rounding. The decision is taken on the device, so a caller can
+// chain passes without reading anything back.
 __global__ __launch_bounds__(kSmall) void chol_drop_kernel(int a, const double* __restrict__ G,
                                                            double* __restrict__ T,
                                                            double* __restrict__ work,
                                                            int* __restrict__ info_i,
                                                            double* __restrict__ info_d,
-                                                           double drop_tol2) {
+                                                           double drop_tol2, double ns_tol) {
     extern __shared__ double dyn[];
     __shared__ int s_pos[1024];
     __shared__ int s_kept[1024];
     __shared__ double s_D[1024];
     __shared__ double s_dl[1024];  // diagonal of L
     __shared__ double s_dr[1024];  // diagonal of R^{-1}
+    __shared__ double s_red[kSWaves];
     __shared__ int s_r;
     double* F = ((size_t)a * a <= (size_t)kLdsDoubles) ? dyn : work;  // a x a
     const int t = threadIdx.x;
     const bool can_drop = drop_tol2 >= 0.0;
 
-    for (int i = t; i < a; i += kSmall) {
+    const int nth = blockDim.x;
+    if (ns_tol > 0.0) {
+        double s = 0.0;
+        for (size_t e = t; e < (size_t)a * a; e += nth) {
+            const double v = G[e] - ((e / a == e % a) ? 1.0 : 0.0);
+            s += v * v;
+        }
+        s = block_sum(s, s_red);  // identical in every thread
+        if (s <= ns_tol * ns_tol) {
+            for (size_t e = t; e < (size_t)a * a; e += nth)
+                T[e] = ((e / a == e % a) ? 1.5 : 0.0) - 0.5 * G[e];
+            for (int i = t; i < a; i += nth) info_i[1 + i] = i;
+            if (t == 0) {
+                info_i[0] = a;
+                info_d[0] = 1.0 - sqrt(s);
+            }
+            return;
+        }
+    }
+    for (int i = t; i < a; i += nth) {
         const double g = G[(size_t)i * a + i];
         s_D[i] = (g > 0.0) ? 1.0 / sqrt(g) : 0.0;
     }
     __syncthreads();
-    for (size_t e = t; e < (size_t)a * a; e += kSmall) {
+    for (size_t e = t; e < (size_t)a * a; e += nth) {
         const int i = (int)(e / a), j = (int)(e % a);
         if (j <= i) F[e] = G[e] * s_D[i] * s_D[j];
     }
@@ -75,7 +103,7 @@ __global__ __launch_bounds__(kSmall) void chol_drop_kernel(int a, const double* 
         const bool drop = can_drop && (!(d > drop_tol2) || s_D[j] == 0.0);
         if (!can_drop && !(d > 1e-300)) d = 1e-300;
         if (drop) {
-            for (int i = j + 1 + t; i < a; i += kSmall) F[(size_t)i * a + j] = 0.0;
+            for (int i = j + 1 + t; i < a; i += nth) F[(size_t)i * a + j] = 0.0;
             if (t == 0) {
                 s_pos[j] = -1;
                 s_dl[j] = 0.0;
@@ -87,13 +115,13 @@ __global__ __launch_bounds__(kSmall) void chol_drop_kernel(int a, const double* 
         const double inv = 1.0 / piv;
         minpiv = fmin(minpiv, d);
         const int rem = a - j - 1;
-        for (int i = j + 1 + t; i < a; i += kSmall) F[(size_t)i * a + j] *= inv;
+        for (int i = j + 1 + t; i < a; i += nth) F[(size_t)i * a + j] *= inv;
         if (t == 0) {
             s_dl[j] = piv;
             s_pos[j] = 0;
         }
         __syncthreads();
-        for (size_t e = t; e < (size_t)rem * rem; e += kSmall) {
+        for (size_t e = t; e < (size_t)rem * rem; e += nth) {
             const int i = j + 1 + (int)(e / rem), i2 = j + 1 + (int)(e % rem);
             if (i2 <= i) F[(size_t)i * a + i2] -= F[(size_t)i * a + j] * F[(size_t)i2 * a + j];
         }
@@ -118,7 +146,7 @@ __global__ __launch_bounds__(kSmall) void chol_drop_kernel(int a, const double* 
     // R^{-1} by back substitution, one column per thread: with R[p][u] =
     // L[kept u][kept p], X[p][q] = -(sum_{u=p+1..q} R[p][u] X[u][q]) / R[p][p].
     // X[u][q] (u < q) is stored at F[kept u][kept q] (upper triangle).
-    for (int q = t; q < r; q += kSmall) {
+    for (int q = t; q < r; q += nth) {
         const int kq = s_kept[q];
         s_dr[q] = 1.0 / s_dl[kq];
         for (int p = q - 1; p >= 0; --p) {
@@ -132,7 +160,7 @@ __global__ __launch_bounds__(kSmall) void chol_drop_kernel(int a, const double* 
         }
     }
     __syncthreads();
-    for (size_t e = t; e < (size_t)a * r; e += kSmall) {
+    for (size_t e = t; e < (size_t)a * r; e += nth) {
         const int i = (int)(e / r), q = (int)(e % r);
         const int p = s_pos[i];
         double v = 0.0;
@@ -147,35 +175,38 @@ __global__ __launch_bounds__(kSmall) void chol_drop_kernel(int a, const double* 
 // acts on rows/columns k+1..m-1: H_k = I - tau_k v_k v_k^T with v_k stored in
 // Vh row k from column k+1 (leading 1 explicit). d / e = diagonal /
 // off-diagonal of the result.
-__global__ __launch_bounds__(kSmall) void tridiag_kernel(int m, double* __restrict__ Ag,
-                                                         double* __restrict__ d,
-                                                         double* __restrict__ e,
-                                                         double* __restrict__ tau,
-                                                         double* __restrict__ Vh) {
+__global__ __launch_bounds__(kTri) void tridiag_kernel(int m, int kend, double* __restrict__ Ag,
+                                                       double* __restrict__ d,
+                                                       double* __restrict__ e,
+                                                       double* __restrict__ tau,
+                                                       double* __restrict__ Vh) {
+    constexpr int NTH = kTri;
+    constexpr int NW = NTH / 64;
     extern __shared__ double dyn[];
     __shared__ double sv[1024];
     __shared__ double sw[1024];
-    __shared__ double sp[kSmall];
-    __shared__ double sred[kSWaves];
+    __shared__ double sp[NTH];
+    __shared__ double sred[NW];
     __shared__ double s_scal[4];
     const int t = threadIdx.x;
     const bool in_lds = (size_t)m * m <= (size_t)kLdsDoubles;
     double* A = in_lds ? dyn : Ag;
     if (in_lds) {
-        for (size_t q = t; q < (size_t)m * m; q += kSmall) dyn[q] = Ag[q];
+        for (size_t q = t; q < (size_t)m * m; q += NTH) dyn[q] = Ag[q];
         __syncthreads();
     }
-    for (int k = 0; k + 2 < m; ++k) {
+    const int klast = min(kend, m - 2);
+    for (int k = 0; k < klast; ++k) {
         const int L = m - k - 1;
         const double* row = A + (size_t)k * m + (k + 1);
         double part = 0.0;
-        for (int i = 1 + t; i < L; i += kSmall) part += row[i] * row[i];
+        for (int i = 1 + t; i < L; i += NTH) part += row[i] * row[i];
         part = wave_sum(part);
         if ((t & 63) == 0) sred[t >> 6] = part;
         __syncthreads();
         if (t == 0) {
             double sigma2 = 0.0;
-            for (int q = 0; q < kSWaves; ++q) sigma2 += sred[q];
+            for (int q = 0; q < NW; ++q) sigma2 += sred[q];
             const double alpha = row[0];
             double tk = 0.0, beta = alpha, scale = 0.0;
             if (sigma2 > 0.0) {
@@ -191,51 +222,188 @@ __global__ __launch_bounds__(kSmall) void tridiag_kernel(int m, double* __restri
         }
         __syncthreads();
         const double tk = s_scal[0], scale = s_scal[1];
-        for (int i = t; i < L; i += kSmall) {
+        for (int i = t; i < L; i += NTH) {
             const double v = (i == 0) ? 1.0 : (tk != 0.0 ? row[i] * scale : 0.0);
             sv[i] = v;
             Vh[(size_t)k * m + k + 1 + i] = v;
         }
         __syncthreads();
         if (tk == 0.0) continue;
-        // p = tau * A22 v, A22 = A[k+1:, k+1:]; columns in chunks of up to
-        // kSmall, each column summed by G row groups.
-        const int W = L < kSmall ? L : kSmall;  // columns per chunk
-        const int G = kSmall / W;               // row groups per column (>= 1)
-        for (int base = 0; base < L; base += W) {
-            const int i = base + t % W, g = t / W;
-            if (i < L && g < G) {
+        // p = tau * A22 v, A22 = A[k+1:, k+1:]; each column summed by G row
+        // groups (G >= 1 since L < m <= 1024)
+        const int G = NTH / L;
+        {
+            const int i = t % L, g = t / L;
+            if (g < G) {
                 double s = 0.0;
                 const double* colp = A + (size_t)(k + 1) * m + (k + 1) + i;
                 for (int jj = g; jj < L; jj += G) s = fma(colp[(size_t)jj * m], sv[jj], s);
-                sp[g * W + (i - base)] = s;
+                sp[g * L + i] = s;
             }
-            __syncthreads();
-            if (t < W && base + t < L) {
-                double s = 0.0;
-                for (int q = 0; q < G; ++q) s += sp[q * W + t];
-                sw[base + t] = s * tk;
-            }
-            __syncthreads();
         }
-        double pv = 0.0;
-        for (int i = t; i < L; i += kSmall) pv += sw[i] * sv[i];
-        const double Kc = 0.5 * tk * block_sum(pv, sred);
-        for (int i = t; i < L; i += kSmall) sw[i] -= Kc * sv[i];
         __syncthreads();
-        for (size_t q = t; q < (size_t)L * L; q += kSmall) {
+        double pv = 0.0;
+        for (int i = t; i < L; i += NTH) {
+            double s = 0.0;
+            for (int q = 0; q < G; ++q) s += sp[q * L + i];
+            s *= tk;
+            sw[i] = s;
+            pv += s * sv[i];
+        }
+        pv = wave_sum(pv);
+        if ((t & 63) == 0) sred[t >> 6] = pv;
+        __syncthreads();
+        double pvs = 0.0;
+        for (int q = 0; q < NW; ++q) pvs += sred[q];
+        const double Kc = 0.5 * tk * pvs;
+        for (int i = t; i < L; i += NTH) sw[i] -= Kc * sv[i];
+        __syncthreads();
+        for (size_t q = t; q < (size_t)L * L; q += NTH) {
             const int jj = (int)(q / L), i = (int)(q % L);
             A[(size_t)(k + 1 + jj) * m + (k + 1 + i)] -= sv[jj] * sw[i] + sw[jj] * sv[i];
         }
         __syncthreads();
     }
-    if (t == 0) {
+    if (klast == m - 2 && t == 0) {
         if (m >= 2) {
             d[m - 2] = A[(size_t)(m - 2) * m + (m - 2)];
             e[m - 2] = A[(size_t)(m - 1) * m + (m - 2)];
         }
         d[m - 1] = A[(size_t)(m - 1) * m + (m - 1)];
     }
+}
+
+// ---------------------------------------------------------------------------
+// Register-resident Householder tridiagonalization for m <= min(16 RR, 32 RC).
+// 512 threads form a 16 x 32 grid; thread (ty, tx) owns the elements (r, c)
+// with r = 16 i + ty, c = 32 j + tx (i < RR, j < RC) in registers. Per
+// reflector: the owners of column k publish it to LDS (barrier), every wave
+// reduces the Householder scalars itself, each thread forms its share of
+// p = tau A22 v and the 32 lanes of a row combine it by shuffles (barrier),
+// every wave reduces K = tau/2 p.v itself, and each thread applies the rank-2
+// update to its own registers. LDS vectors are double-buffered by step
+// parity, so three barriers per reflector suffice. Output as tridiag_kernel.
+template <int RR, int RC>
+__global__ __launch_bounds__(512) void tridiag_reg_kernel(int mfull, int k0,
+                                                          const double* __restrict__ Ag,
+                                                          double* __restrict__ dg,
+                                                          double* __restrict__ eg,
+                                                          double* __restrict__ taug,
+                                                          double* __restrict__ Vhg) {
+    // Works on the trailing block A[k0:, k0:] (order m); outputs go to the
+    // global positions k0 + k.
+    const int m = mfull - k0;
+    double* d = dg + k0;
+    double* e = eg + k0;
+    double* tau = taug + k0;
+    constexpr int NT = 512;
+    __shared__ double sx[2][32 * RC];  // column k (rows > k)
+    __shared__ double sp[2][32 * RC];  // tau * A22 v
+    __shared__ double rowpart[16 * RR][33];  // per-thread row partials of A22 v
+    const int t = threadIdx.x;
+    const int tx = t & 31, ty = t >> 5;
+    const int lane = t & 63;
+    double a[RR][RC];
+#pragma unroll
+    for (int i = 0; i < RR; ++i)
+#pragma unroll
+        for (int j = 0; j < RC; ++j) {
+            const int r = 16 * i + ty, c = 32 * j + tx;
+            a[i][j] = (r < m && c < m) ? Ag[(size_t)(k0 + r) * mfull + (k0 + c)] : 0.0;
+        }
+    for (int k = 0; k + 2 < m; ++k) {
+        const int par = k & 1;
+        const int kj = k >> 5;
+        // (1) column k and the diagonal element
+        if (tx == (k & 31)) {
+#pragma unroll
+            for (int i = 0; i < RR; ++i) {
+                const int r = 16 * i + ty;
+                double x = 0.0;
+#pragma unroll
+                for (int j = 0; j < RC; ++j)
+                    if (j == kj) x = a[i][j];
+                if (r > k && r < m) sx[par][r] = x;
+                if (r == k) d[k] = x;
+            }
+        }
+        __syncthreads();
+        // (2) Householder scalars, reduced redundantly by every wave
+        const int L = m - k - 1;
+        double part = 0.0;
+        for (int r = k + 2 + lane; r < m; r += 64) part += sx[par][r] * sx[par][r];
+        const double sigma2 = wave_sum(part);
+        const double alpha = sx[par][k + 1];
+        double tk = 0.0, beta = alpha, scale = 0.0;
+        if (sigma2 > 0.0) {
+            beta = -copysign(sqrt(alpha * alpha + sigma2), alpha);
+            tk = (beta - alpha) / beta;
+            scale = 1.0 / (alpha - beta);
+        }
+        if (t == 0) {
+            e[k] = beta;
+            tau[k] = tk;
+        }
+        for (int q = t; q < L; q += NT) {
+            const int r = k + 1 + q;
+            Vhg[(size_t)(k0 + k) * mfull + (k0 + r)] = (q == 0) ? 1.0 : (tk != 0.0 ? sx[par][r] * scale : 0.0);
+        }
+        if (tk == 0.0) continue;  // uniform; the next step uses the other buffers
+        // (3) p = tau A22 v: row partials over this thread's columns, then a
+        // 32-lane reduction per row
+        double vc[RC];
+#pragma unroll
+        for (int j = 0; j < RC; ++j) {
+            const int c = 32 * j + tx;
+            vc[j] = (c > k && c < m) ? ((c == k + 1) ? 1.0 : sx[par][c] * scale) : 0.0;
+        }
+#pragma unroll
+        for (int i = 0; i < RR; ++i) {
+            double sacc = 0.0;
+#pragma unroll
+            for (int j = 0; j < RC; ++j) sacc = fma(a[i][j], vc[j], sacc);
+            rowpart[16 * i + ty][tx] = sacc;
+        }
+        __syncthreads();
+        for (int r = k + 1 + t; r < m; r += NT) {
+            double sacc = 0.0;
+#pragma unroll
+            for (int q = 0; q < 32; ++q) sacc += rowpart[r][q];
+            sp[par][r] = tk * sacc;
+        }
+        __syncthreads();
+        // (4) K = tau/2 p.v, reduced redundantly by every wave
+        double pv = 0.0;
+        for (int r = k + 1 + lane; r < m; r += 64)
+            pv += sp[par][r] * ((r == k + 1) ? 1.0 : sx[par][r] * scale);
+        const double Kc = 0.5 * tk * wave_sum(pv);
+        // (5) A22 -= v w^T + w v^T with w = p - K v (w_c re-read from LDS per
+        // element to keep the register block within budget)
+#pragma unroll
+        for (int i = 0; i < RR; ++i) {
+            const int r = 16 * i + ty;
+            if (r > k && r < m) {
+                const double vr = (r == k + 1) ? 1.0 : sx[par][r] * scale;
+                const double wr = sp[par][r] - Kc * vr;
+#pragma unroll
+                for (int j = 0; j < RC; ++j) {
+                    const int c = 32 * j + tx;
+                    const double wcj = (c > k && c < m) ? sp[par][c] - Kc * vc[j] : 0.0;
+                    a[i][j] -= vr * wcj + wr * vc[j];
+                }
+            }
+        }
+    }
+    // last 2 x 2 block
+#pragma unroll
+    for (int i = 0; i < RR; ++i)
+#pragma unroll
+        for (int j = 0; j < RC; ++j) {
+            const int r = 16 * i + ty, c = 32 * j + tx;
+            if (m >= 2 && r == m - 2 && c == m - 2) d[m - 2] = a[i][j];
+            if (m >= 2 && r == m - 1 && c == m - 2) e[m - 2] = a[i][j];
+            if (r == m - 1 && c == m - 1) d[m - 1] = a[i][j];
+        }
 }
 
 // ---------------------------------------------------------------------------
@@ -356,6 +524,7 @@ __global__ __launch_bounds__(256) void invit_kernel(int m, int k, const double* 
         }
         if (j + 2 < m) AT(DU2, j) = 0.0;
     }
+#pragma unroll 4
     for (int j = 0; j + 1 < m; ++j) {
         const double dj = AT(DD, j), lj = AT(DL, j);
         if (fabs(dj) >= fabs(lj)) {
@@ -383,6 +552,7 @@ __global__ __launch_bounds__(256) void invit_kernel(int m, int k, const double* 
         if (fabs(AT(DD, j)) < tiny) AT(DD, j) = copysign(tiny, AT(DD, j) == 0.0 ? 1.0 : AT(DD, j));
     for (int j = 0; j < m; ++j) AT(ZT, j) = hash_unit((unsigned)i, (unsigned)j);
     for (int it = 0; it < 2; ++it) {
+#pragma unroll 8
         for (int j = 0; j + 1 < m; ++j) {
             const double bj = AT(ZT, j), bj1 = AT(ZT, j + 1);
             if (AT(IP, j) == j) {
@@ -394,6 +564,7 @@ __global__ __launch_bounds__(256) void invit_kernel(int m, int k, const double* 
         }
         AT(ZT, m - 1) /= AT(DD, m - 1);
         if (m >= 2) AT(ZT, m - 2) = (AT(ZT, m - 2) - AT(DU, m - 2) * AT(ZT, m - 1)) / AT(DD, m - 2);
+#pragma unroll 8
         for (int j = m - 3; j >= 0; --j)
             AT(ZT, j) = (AT(ZT, j) - AT(DU, j) * AT(ZT, j + 1) - AT(DU2, j) * AT(ZT, j + 2)) / AT(DD, j);
         double mx = 0.0;
@@ -477,11 +648,11 @@ __global__ __launch_bounds__(256) void hl_init_kernel(int m, int k, const double
 }  // namespace
 
 hipError_t launch_chol_drop(hipStream_t st, int a, const double* G, double* T, double* work,
-                            int* info_i, double* info_d, double drop_tol2) {
+                            int* info_i, double* info_d, double drop_tol2, double ns_tol) {
     if (a <= 0 || a > 1024) return hipErrorInvalidValue;
     const size_t lds = ((size_t)a * a <= (size_t)kLdsDoubles) ? sizeof(double) * (size_t)a * a : 0;
     hipLaunchKernelGGL(chol_drop_kernel, dim3(1), dim3(kSmall), lds, st, a, G, T, work, info_i, info_d,
-                       drop_tol2);
+                       drop_tol2, ns_tol);
     return hipGetLastError();
 }
 
@@ -514,20 +685,39 @@ hipError_t launch_syev_lowest(hipStream_t st, int m, int k, double* A, double* w
     double* infod = cwork + 2 * mm + 2 * (size_t)m;
     int* infoi = reinterpret_cast<int*>(infod + 8);
     const size_t lds = (mm <= (size_t)kLdsDoubles) ? sizeof(double) * mm : 0;
-    hipLaunchKernelGGL(tridiag_kernel, dim3(1), dim3(kSmall), lds, st, m, A, d, e, tau, Vh);
+    if (m <= 112) {
+        hipLaunchKernelGGL(tridiag_kernel, dim3(1), dim3(kTri), lds, st, m, m, A, d, e, tau, Vh);
+    } else {
+        // the first m - 224 reflectors in L2, the trailing block (order <= 224)
+        // in registers
+        const int k0 = m > 224 ? m - 224 : 0;
+        if (k0 > 0) hipLaunchKernelGGL(tridiag_kernel, dim3(1), dim3(kTri), 0, st, m, k0, A, d, e, tau, Vh);
+        switch ((m - k0 + 15) / 16) {
+            case 8: hipLaunchKernelGGL((tridiag_reg_kernel<8, 4>), dim3(1), dim3(512), 0, st, m, k0, A, d, e, tau, Vh); break;
+            case 9: hipLaunchKernelGGL((tridiag_reg_kernel<9, 5>), dim3(1), dim3(512), 0, st, m, k0, A, d, e, tau, Vh); break;
+            case 10: hipLaunchKernelGGL((tridiag_reg_kernel<10, 5>), dim3(1), dim3(512), 0, st, m, k0, A, d, e, tau, Vh); break;
+            case 11: hipLaunchKernelGGL((tridiag_reg_kernel<11, 6>), dim3(1), dim3(512), 0, st, m, k0, A, d, e, tau, Vh); break;
+            case 12: hipLaunchKernelGGL((tridiag_reg_kernel<12, 6>), dim3(1), dim3(512), 0, st, m, k0, A, d, e, tau, Vh); break;
+            case 13: hipLaunchKernelGGL((tridiag_reg_kernel<13, 7>), dim3(1), dim3(512), 0, st, m, k0, A, d, e, tau, Vh); break;
+            default: hipLaunchKernelGGL((tridiag_reg_kernel<14, 7>), dim3(1), dim3(512), 0, st, m, k0, A, d, e, tau, Vh); break;
+        }
+    }
     hipLaunchKernelGGL(bisect_kernel, dim3((k + 3) / 4), dim3(256), 0, st, m, k, d, e, w, scal);
     hipLaunchKernelGGL(invit_kernel, dim3((k + 255) / 256), dim3(256), 0, st, m, k, d, e, w, scal, ZT,
                        fac);
     // Orthonormalize the k vectors (an m x k block whose rows are vector
-    // components): two Cholesky-QR passes without column drop.
+    // components): one Cholesky-QR pass without column drop, then two passes
+    // that take a Newton-Schulz step when the block is orthonormal to 1e-8
+    // and another Cholesky-QR pass otherwise (vectors of a degenerate cluster
+    // can leave inverse iteration nearly dependent).
     double* cur = ZT;
     double* nxt = ZT2;
-    for (int pass = 0; pass < 2; ++pass) {
+    for (int pass = 0; pass < 3; ++pass) {
         Segs Zs = make_segs(k);
         push_seg(Zs, cur, k);
         hipError_t err = launch_gram(st, m, Zs, Zs, 1, gpart, Gk);
         if (err != hipSuccess) return err;
-        err = launch_chol_drop(st, k, Gk, Tk, cwork, infoi, infod, -1.0);
+        err = launch_chol_drop(st, k, Gk, Tk, cwork, infoi, infod, -1.0, pass == 0 ? 0.0 : 1e-8);
         if (err != hipSuccess) return err;
         Segs Os = make_segs(k);
         push_seg(Os, nxt, k);
