@@ -38,6 +38,8 @@ def parse():
     ap.add_argument("--no-fixed", action="store_true", help="skip the fixed-block comparison")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="run one plain 1 GiB device copy first (the reference for HBM counters)")
     return ap.parse_args()
 
 
@@ -61,6 +63,16 @@ def main():
     nb = args.n_ev + args.n_extra
     X0 = W.gaussian_block(A.n, nb, 202)
     log(f"inputs n={A.n} nnz={A.nnz} nb={nb} built in {time.time() - t:.1f}s")
+
+    if args.calibrate_copy:
+        # one elementwise copy of 2^27 doubles (1 GiB read + 1 GiB written):
+        # the known-size reference that scales FETCH_SIZE / WRITE_SIZE
+        src = torch.ones(1 << 27, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        torch.mul(src, 1.0, out=dst)
+        torch.cuda.synchronize()
+        del src, dst
+        log("copy calibration: 1 GiB read + 1 GiB written in one elementwise kernel")
 
     ctx = api.Context(0)
     M = api.Matrix.from_csr(ctx, A)
@@ -123,7 +135,7 @@ def main():
         out["speedup_vs_fixed"] = round(fwall / wall, 3)
         log(f"fixed block: {fwall:.3f}s iters={finfo.iterations}")
 
-    out["roofline"], out["kernels"] = roofline(infos)
+    out["roofline"], out["kernels"] = roofline(infos, f"laplace3d_{args.grid}_fp64")
     out["cpu_baseline"] = None
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(A, X0, args, infos[-1].iterations, log)
@@ -133,9 +145,33 @@ def main():
 # Published MI355X peaks: HBM3E 8 TB/s; FP64 vector and matrix 78.6 TFLOP/s.
 HBM_PEAK_GBS = 8000.0
 FP64_PEAK_TFS = 78.6
+# kernel classes whose launches are FP64 MFMA contractions
+MFMA_CLASSES = ("gram", "update")
 
 
-def roofline(infos):
+def measured_traffic(name, workload):
+    """HBM bytes per launch of kernel class `name` on `workload` from the
+    committed counter summary, if it was taken on the current kernel source
+    (else None)."""
+    import hashlib
+    import re
+
+    path = os.path.join(ROOT, "profiles", f"{name}_{workload}_hbm_traffic.md")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        text = f.read()
+    fields = dict(re.findall(r"^(source|source_sha256|bytes_per_launch): (\S+)$", text, re.M))
+    if len(fields) != 3:
+        return None
+    with open(os.path.join(ROOT, "paper_2409_05572_amd", "csrc", fields["source"]), "rb") as f:
+        digest = hashlib.sha256(f.read()).hexdigest()
+    if digest != fields["source_sha256"]:
+        return None
+    return float(fields["bytes_per_launch"])
+
+
+def roofline(infos, workload=None):
     """Per kernel class: device time summed from HIP events around every
     launch in the timed solves, algorithmic bytes and flops. The dominant
     class (largest time) is reported against its roof."""
@@ -168,10 +204,13 @@ def roofline(infos):
                 "frac": round(ach / HBM_PEAK_GBS, 4)}
     else:
         ach = fl[dom] / sec / 1e12
-        roof = {"bound": "alu", "achieved": round(ach, 2), "peak": FP64_PEAK_TFS, "unit": "TFLOP/s",
-                "frac": round(ach / FP64_PEAK_TFS, 4)}
-    roof.update({"kernel": name, "launches": int(calls[dom]),
-                 "avg_launch_us": round(1e3 * ms[dom] / calls[dom], 1), "traffic": None})
+        roof = {"bound": "mfma" if name in MFMA_CLASSES else "alu", "achieved": round(ach, 2),
+                "peak": FP64_PEAK_TFS, "unit": "TFLOP/s", "frac": round(ach / FP64_PEAK_TFS, 4)}
+    traffic = measured_traffic(name, workload) if workload else None
+    roof.update({"traffic": None if traffic is None else round(traffic), "kernel": name,
+                 "launches": int(calls[dom]), "avg_launch_us": round(1e3 * ms[dom] / calls[dom], 1),
+                 "algorithmic_bytes_per_launch": round(by[dom] / calls[dom]),
+                 "algorithmic_flops_per_launch": round(fl[dom] / calls[dom])})
     return roof, table
 
 

@@ -24,8 +24,28 @@ def test_roofline_picks_dominant_class_and_divides_correctly():
     fl = [1e9, 1e11, 5e11, 0, 0, 0, 0, 0]
     calls = [2, 4, 10, 2, 1, 1, 1, 0]
     roof, table = bench.roofline([_info(ms, by, fl, calls)])
-    assert roof["kernel"] == "update" and roof["bound"] == "alu"
+    assert roof["kernel"] == "update" and roof["bound"] == "mfma"
     assert abs(roof["achieved"] - 5e11 / 1e-2 / 1e12) < 1e-9
     assert abs(roof["frac"] - roof["achieved"] / 78.6) < 1e-4
     assert roof["launches"] == 10 and abs(roof["avg_launch_us"] - 1000.0) < 1e-9
     assert abs(table["spmm"]["GB_s"] - 8e9 / 1e-3 / 1e9) < 1e-6
+
+
+def test_traffic_figure_only_for_unchanged_kernel_source(tmp_path, monkeypatch):
+    import hashlib
+
+    import bench
+
+    csrc = tmp_path / "paper_2409_05572_amd" / "csrc"
+    csrc.mkdir(parents=True)
+    (tmp_path / "profiles").mkdir()
+    src = csrc / "k.hip"
+    src.write_text("kernel v1\n")
+    sha = hashlib.sha256(b"kernel v1\n").hexdigest()
+    (tmp_path / "profiles" / "update_w_hbm_traffic.md").write_text(
+        f"# t\n\nsource: k.hip\nsource_sha256: {sha}\nbytes_per_launch: 1234\n")
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    assert bench.measured_traffic("update", "w") == 1234.0
+    src.write_text("kernel v2\n")
+    assert bench.measured_traffic("update", "w") is None
+    assert bench.measured_traffic("gram", "w") is None
