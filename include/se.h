@@ -56,6 +56,8 @@ typedef struct se_matrix se_matrix;
 
 /* Arithmetic of the bulk (n-length) work. */
 #define SE_FP64 0
+#define SE_FP32_MIXED 1 /* FP32 panels until r(j) <= r_switch, then FP64 */
+#define SE_BF16_MIXED 2 /* BF16 panels until r(j) <= r_switch, then FP64 */
 
 /* Where X0, V and lambda of se_solve live. */
 #define SE_PTR_HOST 0
@@ -68,7 +70,8 @@ typedef struct se_matrix se_matrix;
 /* Columns of one history row (se_params.history). */
 #define SE_HISTORY_FIELDS 8
 /* j, r(j) by eq. (rk), max stop ratio, width k, width p, active a, locked, flags
- * (bit 0 = expanded this iteration, bit 1 = shrunk this iteration) */
+ * (bit 0 = expanded this iteration, bit 1 = shrunk this iteration, bit 2 = iteration of
+ * the low-precision phase of a mixed-precision solve) */
 
 /* Kernel classes of se_info.kern_* */
 #define SE_K_SPMM 0   /* CSR sparse x block */
@@ -83,7 +86,7 @@ typedef struct se_matrix se_matrix;
 typedef struct se_params {
     int32_t solver;      /* SE_LOBPCG or SE_SI */
     int32_t strategy;    /* SE_STRAT_* */
-    int32_t precision;   /* SE_FP64 */
+    int32_t precision;   /* SE_FP64, SE_FP32_MIXED or SE_BF16_MIXED */
     int32_t ptr_mode;    /* SE_PTR_HOST or SE_PTR_DEVICE for X0, V, lambda */
     int32_t n_ev;        /* wanted eigenpairs, >= 1 */
     int32_t n_extra;     /* extra block columns: block size nb = n_ev + n_extra <= n */
@@ -100,6 +103,8 @@ typedef struct se_params {
     double tol;          /* stop when ||A x_i - lambda_i x_i|| <= tol ||A|| ||x_i||, i <= n_ev */
     double sigma;        /* SI shift, must bound lambda_max from above; 0 = ||A|| */
     double time_limit_s; /* wall-clock cap; <= 0 = none */
+    double r_switch;     /* mixed precision: leave the low-precision phase once r(j) <= r_switch
+                            (or r(j) stops improving); 0 = 1e-6 (FP32), 1e-3 (BF16) */
     uint64_t seed;       /* reserved for generated starting blocks */
     double* history;     /* optional host buffer of history_cap x SE_HISTORY_FIELDS doubles */
     int32_t history_cap; /* rows available in history */
@@ -124,6 +129,8 @@ typedef struct se_info {
     uint64_t workspace_bytes; /* device workspace held by the context after the call */
     int32_t hip_error;      /* first failing hipError_t, 0 if none */
     int32_t history_len;    /* rows written to params.history */
+    int32_t lp_iterations;  /* mixed precision: iterations of the low-precision phase */
+    int32_t lp_reserved;
 } se_info;
 
 /* Fill *p with the defaults of the paper's experiments (Section 6.1-6.2):
@@ -192,6 +199,22 @@ se_status se_op_gram(se_ctx* ctx, int64_t n, const double* U, int64_t ldu, int32
  * Out is n x N; 1 <= K, N <= 1024; beta is 0 or 1; Out must not overlap U. */
 se_status se_op_update(se_ctx* ctx, int64_t n, const double* U, int64_t ldu, int32_t K,
                        const double* C, int32_t N, double* Out, int64_t ldo, double beta);
+
+/* ---- Low-precision building blocks (the bulk steps of the mixed-precision
+ * phase) ----
+ * precision SE_FP32_MIXED: the blocks hold float; SE_BF16_MIXED: bfloat16
+ * stored as 16-bit patterns. Arithmetic is FP32 (matrix cores for Gram and
+ * update), every reduction over n is FP64, and the outputs are rounded to the
+ * block format (C of the Gram product is FP64). ld must be a multiple of 8 and
+ * >= w rounded up to 8; pointers 16-byte aligned. Same semantics and limits as
+ * the FP64 calls above; the matrix's FP32 copy of its values is made on first
+ * use and freed with the matrix. */
+se_status se_op_spmm_lp(se_ctx* ctx, int32_t precision, const se_matrix* A, const void* X, int64_t ldx,
+                        void* Y, int64_t ldy, int32_t w);
+se_status se_op_gram_lp(se_ctx* ctx, int32_t precision, int64_t n, const void* U, int64_t ldu,
+                        int32_t mu, const void* V, int64_t ldv, int32_t mv, double* C);
+se_status se_op_update_lp(se_ctx* ctx, int32_t precision, int64_t n, const void* U, int64_t ldu,
+                          int32_t K, const double* C, int32_t N, void* Out, int64_t ldo, double beta);
 
 /* Symmetric eigendecomposition A = Z diag(w) Z^T of an m x m matrix (the
  * spectral decomposition of A_p in Algorithms 1 and 3), 1 <= m <= 1024.

@@ -19,6 +19,8 @@ SE_ERR_UNSUPPORTED = -6
 SE_LOBPCG, SE_SI = 0, 1
 STRATEGIES = {"none": 0, "fix": 1, "slope": 2, "slopek": 3}
 SE_FP64 = 0
+SE_FP32_MIXED = 1
+SE_BF16_MIXED = 2
 SE_PTR_HOST, SE_PTR_DEVICE = 0, 1
 SE_MATRIX_HOST, SE_MATRIX_DEVICE = 0, 1
 SE_HISTORY_FIELDS = 8
@@ -33,7 +35,7 @@ class SeParams(C.Structure):
         ("j_s", C.c_int32), ("j_p", C.c_int32), ("j_warm", C.c_int32),
         ("max_iter", C.c_int32), ("profile", C.c_int32), ("mu", C.c_double),
         ("r_warm", C.c_double), ("tol", C.c_double), ("sigma", C.c_double),
-        ("time_limit_s", C.c_double), ("seed", C.c_uint64),
+        ("time_limit_s", C.c_double), ("r_switch", C.c_double), ("seed", C.c_uint64),
         ("history", C.POINTER(C.c_double)), ("history_cap", C.c_int32),
         ("reserved", C.c_int32),
     ]
@@ -48,6 +50,7 @@ class SeInfo(C.Structure):
         ("kern_flops", C.c_double * 8), ("kern_calls", C.c_int32 * 8),
         ("workspace_bytes", C.c_uint64),
         ("hip_error", C.c_int32), ("history_len", C.c_int32),
+        ("lp_iterations", C.c_int32), ("lp_reserved", C.c_int32),
     ]
 
 
@@ -72,6 +75,12 @@ PROTOTYPES = {
     "se_op_update": (C.c_int, [C.c_void_p, C.c_int64, C.c_void_p, C.c_int64, C.c_int32,
                                C.c_void_p, C.c_int32, C.c_void_p, C.c_int64, C.c_double]),
     "se_op_syev": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p]),
+    "se_op_spmm_lp": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p,
+                                C.c_int64, C.c_int32]),
+    "se_op_gram_lp": (C.c_int, [C.c_void_p, C.c_int32, C.c_int64, C.c_void_p, C.c_int64, C.c_int32,
+                                C.c_void_p, C.c_int64, C.c_int32, C.c_void_p]),
+    "se_op_update_lp": (C.c_int, [C.c_void_p, C.c_int32, C.c_int64, C.c_void_p, C.c_int64, C.c_int32,
+                                  C.c_void_p, C.c_int32, C.c_void_p, C.c_int64, C.c_double]),
     "se_op_syev_lowest": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_void_p, C.c_void_p,
                                     C.c_void_p]),
     "se_op_cholqr": (C.c_int, [C.c_void_p, C.c_int64, C.c_void_p, C.c_int64, C.c_int32,

@@ -111,13 +111,20 @@ class SolveInfo:
     kern_bytes: tuple = ()
     kern_flops: tuple = ()
     kern_calls: tuple = ()
+    lp_iterations: int = 0
+
+
+PRECISIONS = {"fp64": _lib.SE_FP64, "fp32": _lib.SE_FP32_MIXED, "bf16": _lib.SE_BF16_MIXED}
 
 
 def params(n_ev, n_extra, solver="lobpcg", strategy="none", tol=1e-8, n_es=0, max_iter=None,
-           soft_lock=True, sigma=0.0, time_limit_s=0.0, **strategy_params) -> SeParams:
+           soft_lock=True, sigma=0.0, time_limit_s=0.0, precision="fp64", r_switch=0.0,
+           **strategy_params) -> SeParams:
     p = SeParams()
     lib().se_params_default(C.byref(p))
     p.solver = _lib.SE_SI if solver == "si" else _lib.SE_LOBPCG
+    p.precision = PRECISIONS[precision]
+    p.r_switch = float(r_switch)
     p.strategy = _lib.STRATEGIES[strategy]
     p.n_ev, p.n_extra, p.n_es = int(n_ev), int(n_extra), int(n_es)
     p.tol = float(tol)
@@ -169,7 +176,7 @@ def solve(ctx: Context, A: Matrix, X0, n_ev, n_extra, history_cap=0, **kw):
                     info.max_stop_ratio, info.max_paper_ratio, info.time_ms,
                     int(info.workspace_bytes), hist[: info.history_len].copy(),
                     tuple(info.kern_ms), tuple(info.kern_bytes), tuple(info.kern_flops),
-                    tuple(info.kern_calls))
+                    tuple(info.kern_calls), info.lp_iterations)
     return lam, V, out
 
 
@@ -190,6 +197,36 @@ def update(ctx: Context, U, K: int, Cm, N: int, Out, beta: float = 0.0):
     check(lib().se_op_update(ctx.handle, U.shape[0], C.c_void_p(_ptr(U)), U.stride(0), int(K),
                              C.c_void_p(_ptr(Cm)), int(N), C.c_void_p(_ptr(Out)), Out.stride(0),
                              float(beta)), "se_op_update")
+
+
+def _lp_code(t):
+    import torch
+
+    if t.dtype == torch.float32:
+        return _lib.SE_FP32_MIXED
+    if t.dtype == torch.bfloat16:
+        return _lib.SE_BF16_MIXED
+    raise TypeError(f"low-precision blocks are float32 or bfloat16, not {t.dtype}")
+
+
+def spmm_lp(ctx: Context, A: Matrix, X, Y, w: int):
+    """Y = A X on float32 or bfloat16 blocks (FP32 arithmetic)."""
+    check(lib().se_op_spmm_lp(ctx.handle, _lp_code(X), A.handle, C.c_void_p(_ptr(X)), X.stride(0),
+                              C.c_void_p(_ptr(Y)), Y.stride(0), int(w)), "se_op_spmm_lp")
+
+
+def gram_lp(ctx: Context, U, mu: int, V, mv: int, out):
+    """out (float64) = U^T V for float32 or bfloat16 blocks."""
+    check(lib().se_op_gram_lp(ctx.handle, _lp_code(U), U.shape[0], C.c_void_p(_ptr(U)), U.stride(0),
+                              int(mu), C.c_void_p(_ptr(V)), V.stride(0), int(mv), C.c_void_p(_ptr(out))),
+          "se_op_gram_lp")
+
+
+def update_lp(ctx: Context, U, K: int, Cm, N: int, Out, beta: float = 0.0):
+    """Out = beta Out + U Cm on float32 or bfloat16 blocks (Cm float64)."""
+    check(lib().se_op_update_lp(ctx.handle, _lp_code(U), U.shape[0], C.c_void_p(_ptr(U)), U.stride(0),
+                                int(K), C.c_void_p(_ptr(Cm)), int(N), C.c_void_p(_ptr(Out)),
+                                Out.stride(0), float(beta)), "se_op_update_lp")
 
 
 def syev(ctx: Context, A, w, Z):

@@ -294,8 +294,8 @@ __device__ __forceinline__ d4 mfma16(double a, double b, d4 c) {
 // four waves split the tile 2 x 2 and each accumulates 3 x 3 MFMA tiles. Rows
 // are the contraction index: 16 rows of U and V are staged in LDS per step.
 // Per-chunk partials are summed by gram_reduce_kernel in a fixed order.
-constexpr int GT = 96;
-constexpr int GK = 32;
+constexpr int GT = kGramTile;
+constexpr int GK = kGramRows;
 
 __device__ __forceinline__ void tile_decode(int t, int nt_v, int sym, int& ti, int& tj) {
     if (!sym) {
@@ -480,6 +480,8 @@ __global__ __launch_bounds__(kThreads) void gram_reduce_kernel(int mu, int mv, i
     C[idx] = v;
 }
 
+}  // namespace
+
 void gram_plan(long long n, int mu, int mv, int sym, int& ntiles, int& nt_v, int& nchunks,
                long long& rows) {
     const int nt_u = (mu + GT - 1) / GT;
@@ -495,6 +497,8 @@ void gram_plan(long long n, int mu, int mv, int sym, int& ntiles, int& nt_v, int
     nchunks = (int)((n + rows - 1) / rows);
     if (nchunks < 1) nchunks = 1;
 }
+
+namespace {
 
 // ---------------------------------------------------------------------------
 // Basis update Out = beta Out + alpha U C. Workgroup = 64 rows x (16 NT)
@@ -668,6 +672,22 @@ hipError_t launch_rowmajor_to_colmajor(hipStream_t st, long long n, int w, const
     if (w <= 0 || n <= 0) return hipSuccess;
     dim3 grid((unsigned)((n + 31) / 32), (unsigned)((w + 31) / 32));
     hipLaunchKernelGGL(r2c_kernel, grid, dim3(32, 8), 0, st, n, w, src, ldr, dst, ldc);
+    return hipGetLastError();
+}
+
+hipError_t launch_sum_partials(hipStream_t st, int L, int nchunks, const double* part, double* out) {
+    if (L <= 0) return hipSuccess;
+    hipLaunchKernelGGL(sum_partials_kernel, dim3((L + kThreads - 1) / kThreads), dim3(kThreads), 0, st, L,
+                       nchunks, part, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_gram_reduce(hipStream_t st, int mu, int mv, int nchunks, int sym, const double* part,
+                              double* C) {
+    const long long total = (long long)mu * mv;
+    if (total <= 0) return hipSuccess;
+    hipLaunchKernelGGL(gram_reduce_kernel, dim3((unsigned)((total + kThreads - 1) / kThreads)),
+                       dim3(kThreads), 0, st, mu, mv, nchunks, sym, part, C);
     return hipGetLastError();
 }
 

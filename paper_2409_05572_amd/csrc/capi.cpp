@@ -1,4 +1,5 @@
 // extern "C" boundary of the library (declared in include/se.h).
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <new>
@@ -22,6 +23,35 @@ se_status hip_fail(se_ctx* ctx, hipError_t e) {
 bool valid_ld(int64_t ld, int32_t w) { return ld >= w && ld % 2 == 0; }
 bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0; }
 
+}  // namespace
+
+namespace {
+bool valid_ld_lp(int64_t ld, int32_t w) { return ld % 8 == 0 && ld >= (int64_t)((w + 7) / 8 * 8); }
+bool lp_precision(int32_t pr) { return pr == SE_FP32_MIXED || pr == SE_BF16_MIXED; }
+hipError_t ensure_val32(se_ctx* ctx, const se_matrix* A) {
+    if (A->val32) return hipSuccess;
+    float* v = nullptr;
+    hipError_t e = hipMalloc(&v, sizeof(float) * (size_t)std::max<int64_t>(A->nnz, 1));
+    if (e != hipSuccess) return e;
+    A->val32 = v;
+    return se::launch_f64_to_f32(ctx->stream, A->nnz, A->val, v);
+}
+template <class T>
+hipError_t gram_lp_call(se_ctx* ctx, int64_t n, const void* U, int64_t ldu, int32_t mu, const void* V,
+                        int64_t ldv, int32_t mv, double* C) {
+    se::SegsT<T> Us = se::make_segs_t<T>(ldu), Vs = se::make_segs_t<T>(ldv);
+    se::push_seg_t(Us, static_cast<const T*>(U), mu);
+    se::push_seg_t(Vs, static_cast<const T*>(V), mv);
+    return se::launch_gram_lp<T>(ctx->stream, n, Us, Vs, 0, ctx->ws.gram_part.as<double>(), C);
+}
+template <class T>
+hipError_t update_lp_call(se_ctx* ctx, int64_t n, const void* U, int64_t ldu, int32_t K, const double* C,
+                          int32_t N, void* Out, int64_t ldo, double beta) {
+    se::SegsT<T> Us = se::make_segs_t<T>(ldu), Os = se::make_segs_t<T>(ldo);
+    se::push_seg_t(Us, static_cast<const T*>(U), K);
+    se::push_seg_t(Os, static_cast<const T*>(Out), N);
+    return se::launch_update_lp<T>(ctx->stream, n, Us, C, N, Os, 1.0, beta);
+}
 }  // namespace
 
 extern "C" {
@@ -143,6 +173,7 @@ void se_matrix_destroy(se_matrix* m) {
     if (!m) return;
     if (m->ctx) (void)hipSetDevice(m->ctx->device);
     if (m->rowptr) (void)hipFree(m->rowptr);
+    if (m->val32) (void)hipFree(m->val32);
     if (m->col) (void)hipFree(m->col);
     if (m->val) (void)hipFree(m->val);
     delete m;
@@ -156,7 +187,9 @@ se_status se_solve(se_ctx* ctx, const se_matrix* A, const se_params* p, const do
     if (A->ctx != ctx) return SE_ERR_INVALID_ARG;
     if (p->solver != SE_LOBPCG && p->solver != SE_SI) return SE_ERR_INVALID_ARG;
     if (p->strategy < SE_STRAT_NONE || p->strategy > SE_STRAT_SLOPEK) return SE_ERR_INVALID_ARG;
-    if (p->precision != SE_FP64) return SE_ERR_UNSUPPORTED;
+    if (p->precision != SE_FP64 && p->precision != SE_FP32_MIXED && p->precision != SE_BF16_MIXED)
+        return SE_ERR_UNSUPPORTED;
+    if (p->precision != SE_FP64 && !(p->r_switch >= 0.0)) return SE_ERR_INVALID_ARG;
     if (p->ptr_mode != SE_PTR_HOST && p->ptr_mode != SE_PTR_DEVICE) return SE_ERR_INVALID_ARG;
     const int64_t nb = (int64_t)p->n_ev + p->n_extra;
     if (p->n_ev < 1 || p->n_extra < 0 || nb > A->n) return SE_ERR_INVALID_ARG;
@@ -219,6 +252,65 @@ se_status se_op_update(se_ctx* ctx, int64_t n, const double* U, int64_t ldu, int
     se::push_seg(Us, U, K);
     se::push_seg(Os, Out, N);
     CAPI_HC(ctx, se::launch_update(ctx->stream, n, Us, C, N, Os, 1.0, beta));
+    return SE_OK;
+}
+
+
+se_status se_op_spmm_lp(se_ctx* ctx, int32_t precision, const se_matrix* A, const void* X, int64_t ldx,
+                        void* Y, int64_t ldy, int32_t w) {
+    if (!ctx || !A || !X || !Y || w < 1 || w > 1024 || !lp_precision(precision)) return SE_ERR_INVALID_ARG;
+    if (!valid_ld_lp(ldx, w) || !valid_ld_lp(ldy, w) || !aligned16(X) || !aligned16(Y))
+        return SE_ERR_INVALID_ARG;
+    CAPI_HC(ctx, hipSetDevice(ctx->device));
+    CAPI_HC(ctx, ensure_val32(ctx, A));
+    if (precision == SE_FP32_MIXED)
+        CAPI_HC(ctx, se::launch_spmm_lp<float>(ctx->stream, (int)A->n, A->rowptr, A->col, A->val32,
+                                               static_cast<const float*>(X), ldx, static_cast<float*>(Y),
+                                               ldy, w));
+    else
+        CAPI_HC(ctx, se::launch_spmm_lp<se::bf16_t>(ctx->stream, (int)A->n, A->rowptr, A->col, A->val32,
+                                                     static_cast<const se::bf16_t*>(X), ldx,
+                                                     static_cast<se::bf16_t*>(Y), ldy, w));
+    return SE_OK;
+}
+
+se_status se_op_gram_lp(se_ctx* ctx, int32_t precision, int64_t n, const void* U, int64_t ldu,
+                        int32_t mu, const void* V, int64_t ldv, int32_t mv, double* C) {
+    if (!ctx || !U || !V || !C || n < 1 || mu < 1 || mv < 1 || mu > 1024 || mv > 1024 ||
+        !lp_precision(precision))
+        return SE_ERR_INVALID_ARG;
+    if (!valid_ld_lp(ldu, mu) || !valid_ld_lp(ldv, mv)) return SE_ERR_INVALID_ARG;
+    CAPI_HC(ctx, hipSetDevice(ctx->device));
+    const size_t need = sizeof(double) * se::gram_scratch_doubles(n, mu, mv);
+    if (need > ctx->ws.gram_part.bytes) {
+        CAPI_HC(ctx, hipStreamSynchronize(ctx->stream));
+        CAPI_HC(ctx, ctx->ws.gram_part.ensure(need));
+    }
+    if (precision == SE_FP32_MIXED)
+        CAPI_HC(ctx, gram_lp_call<float>(ctx, n, U, ldu, mu, V, ldv, mv, C));
+    else
+        CAPI_HC(ctx, gram_lp_call<se::bf16_t>(ctx, n, U, ldu, mu, V, ldv, mv, C));
+    return SE_OK;
+}
+
+se_status se_op_update_lp(se_ctx* ctx, int32_t precision, int64_t n, const void* U, int64_t ldu,
+                          int32_t K, const double* C, int32_t N, void* Out, int64_t ldo, double beta) {
+    if (!ctx || !U || !C || !Out || n < 1 || K < 1 || N < 1 || K > 1024 || N > 1024 ||
+        !lp_precision(precision))
+        return SE_ERR_INVALID_ARG;
+    if (!valid_ld_lp(ldu, K) || !valid_ld_lp(ldo, N) || !(beta == 0.0 || beta == 1.0))
+        return SE_ERR_INVALID_ARG;
+    const size_t es = precision == SE_FP32_MIXED ? 4 : 2;
+    const char* u0 = reinterpret_cast<const char*>(U);
+    const char* u1 = u0 + es * (size_t)((n - 1) * ldu + K);
+    const char* o0 = reinterpret_cast<const char*>(Out);
+    const char* o1 = o0 + es * (size_t)((n - 1) * ldo + N);
+    if (o0 < u1 && u0 < o1) return SE_ERR_INVALID_ARG;  // Out must not overlap U
+    CAPI_HC(ctx, hipSetDevice(ctx->device));
+    if (precision == SE_FP32_MIXED)
+        CAPI_HC(ctx, update_lp_call<float>(ctx, n, U, ldu, K, C, N, Out, ldo, beta));
+    else
+        CAPI_HC(ctx, update_lp_call<se::bf16_t>(ctx, n, U, ldu, K, C, N, Out, ldo, beta));
     return SE_OK;
 }
 

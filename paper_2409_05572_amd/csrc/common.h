@@ -34,6 +34,41 @@ inline void push_seg(Segs& s, const double* p, int w) {
 }
 inline int segs_width(const Segs& s) { return s.off[s.nseg]; }
 
+// Low-precision panels: BF16 values are stored as the upper 16 bits of the
+// FP32 pattern (rounded to nearest even).
+using bf16_t = uint16_t;
+
+// The same column-segment view over FP32 or BF16 panels.
+template <class T>
+struct SegsT {
+    const T* p[4];
+    int w[4];
+    int off[5];
+    int nseg;
+    long long ld;
+};
+
+template <class T>
+inline SegsT<T> make_segs_t(long long ld) {
+    SegsT<T> s{};
+    s.nseg = 0;
+    s.ld = ld;
+    s.off[0] = 0;
+    return s;
+}
+template <class T>
+inline void push_seg_t(SegsT<T>& s, const T* p, int w) {
+    if (w <= 0) return;
+    s.p[s.nseg] = p;
+    s.w[s.nseg] = w;
+    s.off[s.nseg + 1] = s.off[s.nseg] + w;
+    s.nseg++;
+}
+template <class T>
+inline int segs_width(const SegsT<T>& s) {
+    return s.off[s.nseg];
+}
+
 // ---- bulk kernels (bulk.hip) ----
 // Y[:, 0:w] = A X[:, 0:w] for CSR A with int32 row offsets.
 hipError_t launch_spmm(hipStream_t st, int n, const int* rowptr, const int* col, const double* val,
@@ -76,6 +111,56 @@ hipError_t launch_gram(hipStream_t st, long long n, const Segs& U, const Segs& V
 // Out segments must not alias U segments.
 hipError_t launch_update(hipStream_t st, long long n, const Segs& U, const double* C, int N,
                          const Segs& Out, double alpha, double beta);
+
+// Fixed-order sum of per-chunk partial vectors: out[i] = sum_c part[c L + i].
+hipError_t launch_sum_partials(hipStream_t st, int L, int nchunks, const double* part, double* out);
+
+// Gram output tile (columns of U and of V per workgroup) and rows per stage,
+// shared by the FP64 and low-precision Gram kernels.
+constexpr int kGramTile = 96;
+constexpr int kGramRows = 32;
+
+// Row-chunk plan shared by the FP64 and low-precision Gram kernels, and the
+// fixed-order FP64 sum of their per-chunk partials (C is mu x mv; with sym
+// the lower tile triangle mirrors the upper one).
+void gram_plan(long long n, int mu, int mv, int sym, int& ntiles, int& nt_v, int& nchunks,
+               long long& rows);
+hipError_t launch_gram_reduce(hipStream_t st, int mu, int mv, int nchunks, int sym, const double* part,
+                              double* C);
+
+// ---- low-precision bulk kernels (bulk_lp.hip), T = float or bf16_t ----
+// Storage is T, arithmetic FP32 (matrix cores for Gram and update), and every
+// reduction over n leaves the workgroup in FP64. Leading dimensions must be
+// multiples of 8 and at least the width rounded up to 8.
+template <class T>
+hipError_t launch_spmm_lp(hipStream_t st, int n, const int* rowptr, const int* col, const float* val,
+                          const T* X, long long ldx, T* Y, long long ldy, int w);
+template <class T>
+hipError_t launch_resid_norms_lp(hipStream_t st, long long n, const T* X, const T* AX, long long ld,
+                                 int k, const double* lam, double* part, double* out);
+template <class T>
+hipError_t launch_form_w_lp(hipStream_t st, long long n, const T* X, const T* AX, long long ld,
+                            const double* lam, const int* act, int a, T* W, long long ldw);
+template <class T>
+hipError_t launch_shift_sub_lp(hipStream_t st, long long n, T* X, const T* AX, long long ld, int k,
+                               double sigma);
+template <class T>
+hipError_t launch_copy_cols_lp(hipStream_t st, long long n, const T* src, long long lds, int sc, T* dst,
+                               long long ldd, int dc, int w);
+// FP64 column-major (ldc) -> T row-major (ldr), and T row-major -> FP64 row-major.
+template <class T>
+hipError_t launch_colmajor_to_rows_lp(hipStream_t st, long long n, int w, const double* src,
+                                      long long ldc, T* dst, long long ldr);
+template <class T>
+hipError_t launch_rows_lp_to_f64(hipStream_t st, long long n, int w, const T* src, long long lds,
+                                 double* dst, long long ldd);
+template <class T>
+hipError_t launch_gram_lp(hipStream_t st, long long n, const SegsT<T>& U, const SegsT<T>& V, int sym,
+                          double* part, double* C);
+template <class T>
+hipError_t launch_update_lp(hipStream_t st, long long n, const SegsT<T>& U, const double* C, int N,
+                            const SegsT<T>& O, double alpha, double beta);
+hipError_t launch_f64_to_f32(hipStream_t st, long long count, const double* src, float* dst);
 
 // ---- small dense kernels (small.hip), one matrix per call, FP64 ----
 // Cholesky-QR transform with column drop: given G = W^T W (a x a), writes T

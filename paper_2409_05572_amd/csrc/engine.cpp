@@ -85,6 +85,9 @@ struct Solver {
     double *Sd = nullptr, *ASd = nullptr, *T1 = nullptr, *T2 = nullptr;
 
     int iters = 0, n_shr = 0, n_exp = 0, hist_len = 0;
+    int j_off = 0;       // iterations of an earlier (low-precision) phase
+    int lp_iters = 0;    // iterations of the low-precision phase
+    bool lp_done = false;  // the low-precision phase met the stopping test itself
     bool converged = false;
     double last_r = INFINITY, last_stop = INFINITY;
     Strategy ctl;
@@ -154,6 +157,10 @@ struct Solver {
         HC(ws.hlY.ensure(sizeof(double) * mm));
         HC(ws.hlG.ensure(sizeof(double) * mm));
         HC(ws.hlQ.ensure(sizeof(double) * mm));
+        if (p.precision != SE_FP64) {
+            DevBuf* lpb[] = {&ws.lpM, &ws.lpT, &ws.lpQ, &ws.lpB, &ws.lpE, &ws.lpC};
+            for (DevBuf* b : lpb) HC(b->ensure(sizeof(double) * mm));
+        }
         HC(ws.act.ensure(sizeof(int) * (mmax + 8)));
         HC(ws.act_hl.ensure(sizeof(int) * (mmax + 8)));
         HC(ws.norms.ensure(sizeof(double) * (2 * mmax + 8)));
@@ -261,15 +268,22 @@ struct Solver {
     // others, which a pass without drop would turn into a non-orthonormal
     // C_P. Returns the final rank through rP.
     se_status hl_coefficients(int m, int k, int a, int& rP) {
-        const double* Z1 = ws.Z.as<double>();
-        double* B = ws.hlB.as<double>();
-        double* Y = ws.hlY.as<double>();
+        if (a > 0)
+            HC(launch_hl_init(st, m, k, ws.Z.as<double>(), ws.act_hl.as<int>(), a, ws.hlB.as<double>(),
+                              ws.hlY.as<double>()));
+        return hl_tail(m, k, a, ws.Z.as<double>(), ws.hlB.as<double>(), ws.hlY.as<double>(),
+                       ws.C.as<double>(), rP);
+    }
+
+    // The HL basis from an explicit start block: B (m x a) holds E and Y
+    // (k x a) holds Z1^T E; writes C = [Z1 | C_P] (leading dimension k + rP).
+    // Uses ws.G, ws.T, ws.hlG and ws.hlQ.
+    se_status hl_tail(int m, int k, int a, const double* Z1, double* B, const double* Y, double* C,
+                      int& rP) {
         double* G2 = ws.hlG.as<double>();
         double* Q = ws.hlQ.as<double>();
-        double* C = ws.C.as<double>();
         rP = 0;
         if (a > 0) {
-            HC(launch_hl_init(st, m, k, Z1, ws.act_hl.as<int>(), a, B, Y));
             const Segs Zs = segx(Z1, k, k);
             ST(update_rows(m, Zs, Y, a, segx(B, a, a), -1.0, 1.0));
             ST(gram_rows(m, Zs, segx(B, a, a), 0, G2));
@@ -410,6 +424,13 @@ struct Solver {
         HC(launch_resid_norms(st, n, Xp, AXp, ld, k, ws.theta.as<double>(), ws.gram_part.as<double>(),
                               ws.norms.as<double>()));
         ST(toc(SE_K_RESID, 16.0 * n * k, 5.0 * n * k));
+        return check_host(k, stop, paper, lam);
+    }
+
+    // Reads back the norms and Ritz values of a residual check and forms the
+    // per-column ratios.
+    se_status check_host(int k, std::vector<double>& stop, std::vector<double>& paper,
+                         std::vector<double>& lam) {
         HC(hipMemcpyAsync(ws.h_norms.p, ws.norms.p, sizeof(double) * 2 * k, hipMemcpyDeviceToHost, st));
         HC(hipMemcpyAsync(ws.h_theta.p, ws.theta.p, sizeof(double) * k, hipMemcpyDeviceToHost, st));
         ST(sync());
@@ -430,7 +451,7 @@ struct Solver {
     void record(int j, double r, double mstop, int k, int pw, int a, int locked, int flags) {
         if (!p.history || hist_len >= p.history_cap) return;
         double* h = p.history + (size_t)hist_len * SE_HISTORY_FIELDS;
-        h[0] = j;
+        h[0] = j + j_off;
         h[1] = r;
         h[2] = mstop;
         h[3] = k;
@@ -453,11 +474,13 @@ struct Solver {
     }
 
     // ------------------------------------------------------------- LOBPCG --
-    se_status lobpcg(const double* X0) {
+    // X0: FP64 column-major start block; k0 >= 0: the X panel already holds
+    // k0 start columns (row-major), e.g. from the low-precision phase.
+    se_status lobpcg(const double* X0, int k0 = -1) {
         ST(alloc_panels(14));
         ST(alloc_small(3 * nb));
-        ST(load_x0(X0));
-        int k = nb;
+        if (k0 < 0) ST(load_x0(X0));
+        int k = k0 < 0 ? nb : k0;
         ST(cholqr(X, k, nullptr, nullptr));
         if (k < n_ev) return SE_ERR_BREAKDOWN;
         ST(spmm(X, AX, k));
@@ -477,7 +500,7 @@ struct Solver {
                 ms = std::max(ms, stop[i]);
                 all = all && (stop[i] <= p.tol);
             }
-            iters = j;
+            iters = j + j_off;
             last_r = r;
             last_stop = ms;
             ctl.observe(j, r);
@@ -593,12 +616,12 @@ struct Solver {
     }
 
     // ------------------------------------------------- subspace iteration --
-    se_status si(const double* X0) {
+    se_status si(const double* X0, int k0 = -1) {
         ST(alloc_panels(14));
         ST(alloc_small(nb));
-        ST(load_x0(X0));
+        if (k0 < 0) ST(load_x0(X0));
         const double sigma = (p.sigma > 0.0) ? p.sigma : A->anorm;
-        int k = nb;
+        int k = k0 < 0 ? nb : k0;
         ST(cholqr(X, k, nullptr, nullptr));
         if (k < n_ev) return SE_ERR_BREAKDOWN;
         ST(spmm(X, AX, k));
@@ -615,7 +638,7 @@ struct Solver {
                 ms = std::max(ms, stop[i]);
                 all = all && (stop[i] <= p.tol);
             }
-            iters = j;
+            iters = j + j_off;
             last_r = r;
             last_stop = ms;
             ctl.observe(j, r);
@@ -655,6 +678,404 @@ struct Solver {
             amend_flags(flags);
         }
         return SE_OK;
+    }
+
+    // ----------------------------------------------------- mixed precision --
+    // The low-precision phase keeps every n-length block in FP32 or BF16
+    // panels and does its arithmetic in FP32 with FP64 reductions; all small
+    // dense work stays FP64. Its basis is orthonormal only to the storage
+    // precision, so the Rayleigh-Ritz step solves A_p z = theta M z with
+    // M = S^T S (grr). Once r(j) <= r_switch, or r(j) has not improved for
+    // kStall iterations, the current X (with X_drop when shrunk) is widened to
+    // FP64 and the FP64 solver continues from it with P reset.
+    static constexpr int kStall = 15;
+    void* lp[kNumLpPanels] = {};
+
+    template <class T>
+    SegsT<T> lseg1(const T* a, int wa) const {
+        SegsT<T> s = make_segs_t<T>(ld);
+        push_seg_t(s, a, wa);
+        return s;
+    }
+    template <class T>
+    SegsT<T> lseg3(const T* a, int wa, const T* b, int wb, const T* c, int wc) const {
+        SegsT<T> s = make_segs_t<T>(ld);
+        push_seg_t(s, a, wa);
+        push_seg_t(s, b, wb);
+        push_seg_t(s, c, wc);
+        return s;
+    }
+    // Unit roundoff of the storage format.
+    template <class T>
+    static double unit_roundoff() {
+        return sizeof(T) == 4 ? 5.9604644775390625e-8 : 3.90625e-3;
+    }
+
+    template <class T>
+    se_status lp_alloc() {
+        const size_t bytes = sizeof(T) * (size_t)n * ld;
+        for (int i = 0; i < kNumLpPanels; ++i) {
+            HC(ws.lp_panel[i].ensure(bytes));
+            lp[i] = ws.lp_panel[i].p;
+        }
+        if (!A->val32) {
+            float* v = nullptr;
+            HC(hipMalloc(&v, sizeof(float) * (size_t)std::max<long long>(A->nnz, 1)));
+            A->val32 = v;
+            HC(launch_f64_to_f32(st, A->nnz, A->val, v));
+        }
+        return SE_OK;
+    }
+    template <class T>
+    se_status lp_spmm(const T* Xs, T* Ys, int w) {
+        ST(tic());
+        HC(launch_spmm_lp<T>(st, (int)n, A->rowptr, A->col, A->val32, Xs, ld, Ys, ld, w));
+        return toc(SE_K_SPMM, 8.0 * A->nnz + 4.0 * (n + 1) + 2.0 * sizeof(T) * n * w, 2.0 * A->nnz * w);
+    }
+    template <class T>
+    se_status lp_gram(const SegsT<T>& U, const SegsT<T>& V, int sym, double* C) {
+        const size_t need = sizeof(double) * gram_scratch_doubles(n, segs_width(U), segs_width(V));
+        if (need > ws.gram_part.bytes) {
+            ST(sync());
+            HC(ws.gram_part.ensure(need));
+        }
+        ST(tic());
+        HC(launch_gram_lp<T>(st, n, U, V, sym, ws.gram_part.as<double>(), C));
+        const double mu = segs_width(U), mv = segs_width(V);
+        const double fl = (sym && mu == mv) ? n * mu * (mu + 1.0) : 2.0 * n * mu * mv;
+        const bool same = sym && U.nseg == V.nseg && U.p[0] == V.p[0];
+        return toc(SE_K_GRAM, (double)sizeof(T) * n * (same ? mu : mu + mv), fl);
+    }
+    template <class T>
+    se_status lp_update(const SegsT<T>& U, const double* C, int N, const SegsT<T>& O, double alpha,
+                        double beta) {
+        ST(tic());
+        HC(launch_update_lp<T>(st, n, U, C, N, O, alpha, beta));
+        const double K = segs_width(U);
+        return toc(SE_K_UPDATE, (double)sizeof(T) * n * (K + N * (beta != 0.0 ? 2.0 : 1.0)),
+                   2.0 * n * K * N);
+    }
+    template <class T>
+    se_status lp_check(const T* Xp, const T* AXp, int k, std::vector<double>& stop,
+                       std::vector<double>& paper, std::vector<double>& lam) {
+        ST(tic());
+        HC(launch_resid_norms_lp<T>(st, n, Xp, AXp, ld, k, ws.theta.as<double>(), ws.gram_part.as<double>(),
+                                    ws.norms.as<double>()));
+        ST(toc(SE_K_RESID, 2.0 * sizeof(T) * n * k, 5.0 * n * k));
+        return check_host(k, stop, paper, lam);
+    }
+
+    // Generalized Rayleigh-Ritz on m basis columns: M = ws.lpM and
+    // A_p = ws.G (both FP64, m x m). The scaled Cholesky factor of M, with
+    // columns dropped below drop2, gives T_M (m x r) with T_M^T M T_M = I; the
+    // k lowest pairs of T_M^T A_p T_M give theta and Y (r x k). With ahl > 0
+    // the HL basis is built in the whitened coordinates from the old X columns
+    // act_hl, whose coordinates there are E' = T_M^T M E. Output: the
+    // coefficients C = T_M [Y | C_P'] in ws.lpC (m x (k + rP)); k is lowered
+    // to r if fewer columns survive.
+    se_status grr(int m, int& k, int ahl, double drop2, int& rP) {
+        double* M = ws.lpM.as<double>();
+        double* TM = ws.lpT.as<double>();
+        double* Q = ws.lpQ.as<double>();
+        double* Ar = ws.lpB.as<double>();
+        int* info_i = ws.info.as<int>();
+        double* info_d = ws.info.as<double>() + (m + 8) / 2 + 4;
+        ST(tic());
+        HC(launch_chol_drop(st, m, M, TM, ws.small_work.as<double>(), info_i, info_d, drop2));
+        HC(hipMemcpyAsync(ws.h_info.p, ws.info.p, sizeof(int) * 4, hipMemcpyDeviceToHost, st));
+        ST(sync());
+        const int r = ws.h_info.as<int>()[0];
+        if (r < n_ev) return SE_ERR_BREAKDOWN;
+        k = std::min(k, r);
+        ST(update_rows(m, segx(ws.G.as<double>(), m, m), TM, r, segx(Q, r, r), 1.0, 0.0));
+        ST(gram_rows(m, segx(TM, r, r), segx(Q, r, r), 1, Ar));
+        HC(launch_syev_lowest(st, r, k, Ar, ws.theta.as<double>(), ws.Z.as<double>(),
+                              ws.syev_work.as<double>()));
+        double* Cr = ws.C.as<double>();
+        rP = 0;
+        if (ahl > 0) {
+            // E' (r x a): rows act_hl of M T_M, transposed; then Y^T E'.
+            ST(update_rows(m, segx(M, m, m), TM, r, segx(Q, r, r), 1.0, 0.0));
+            HC(launch_hl_init(st, m, r, Q, ws.act_hl.as<int>(), ahl, ws.hlQ.as<double>(),
+                              ws.lpE.as<double>()));
+            ST(gram_rows(r, segx(ws.Z.as<double>(), k, k), segx(ws.lpE.as<double>(), ahl, ahl), 0,
+                         ws.hlY.as<double>()));
+            ST(hl_tail(r, k, ahl, ws.Z.as<double>(), ws.lpE.as<double>(), ws.hlY.as<double>(), Cr, rP));
+        } else {
+            HC(launch_copy_cols(st, r, ws.Z.as<double>(), k, 0, Cr, k, 0, k));
+        }
+        ST(update_rows(m, segx(TM, r, r), Cr, k + rP, segx(ws.lpC.as<double>(), k + rP, k + rP), 1.0, 0.0));
+        return toc(SE_K_EIG, 8.0 * m * m, 4.0 * m * m * (double)m);
+    }
+
+    double r_switch_value(double u) const {
+        if (p.r_switch > 0.0) return p.r_switch;
+        return u < 1e-6 ? 1e-6 : 1e-3;
+    }
+
+    // Widens the low-precision X (and X_drop) into the FP64 X panel; returns
+    // the number of start columns.
+    template <class T>
+    se_status lp_to_f64(const T* Xl, int k, const T* Sdl, int dx, int& k0) {
+        ST(alloc_panels(14));
+        HC(launch_rows_lp_to_f64<T>(st, n, k, Xl, ld, X, ld));
+        if (dx > 0) HC(launch_rows_lp_to_f64<T>(st, n, dx, Sdl, ld, X + k, ld));
+        k0 = k + dx;
+        return SE_OK;
+    }
+
+    // LOBPCG (Algorithm 3) with shrink-and-expand on low-precision panels.
+    // No soft locking (the low-precision residuals stop above tol); W is
+    // R(:, all) and is not orthogonalized separately: the Cholesky factor of
+    // M removes its dependence on [X, P] and scales it.
+    template <class T>
+    se_status lobpcg_lp(const double* X0, int& k0) {
+        ST(alloc_panels(14));
+        ST(alloc_small(3 * nb));
+        ST(lp_alloc<T>());
+        T* L[kNumLpPanels];
+        for (int i = 0; i < kNumLpPanels; ++i) L[i] = static_cast<T*>(lp[i]);
+        T *Xl = L[0], *Pl = L[1], *Wl = L[2], *AXl = L[3], *APl = L[4], *AWl = L[5];
+        T *Xnl = L[6], *Pnl = L[7], *AXnl = L[8], *APnl = L[9], *Sdl = L[10], *ASdl = L[11];
+        const double u = unit_roundoff<T>();
+        const double drop2 = 100.0 * u * u;
+        const double rsw = r_switch_value(u);
+        if (p.ptr_mode == SE_PTR_HOST) {
+            HC(hipMemcpyAsync(T1, X0, sizeof(double) * (size_t)n * nb, hipMemcpyHostToDevice, st));
+            HC(launch_colmajor_to_rows_lp<T>(st, n, nb, T1, n, Xl, ld));
+        } else {
+            HC(launch_colmajor_to_rows_lp<T>(st, n, nb, X0, n, Xl, ld));
+        }
+        int k = nb;
+        ST(lp_spmm(Xl, AXl, k));
+        {
+            const SegsT<T> Xs = lseg1(Xl, k);
+            ST(lp_gram(Xs, Xs, 1, ws.lpM.as<double>()));
+            ST(lp_gram(Xs, lseg1(AXl, k), 1, ws.G.as<double>()));
+            int kk = k, rP = 0;
+            ST(grr(k, kk, 0, drop2, rP));
+            ST(lp_update(Xs, ws.lpC.as<double>(), kk, lseg1(Xnl, kk), 1.0, 0.0));
+            ST(lp_update(lseg1(AXl, k), ws.lpC.as<double>(), kk, lseg1(AXnl, kk), 1.0, 0.0));
+            std::swap(Xl, Xnl);
+            std::swap(AXl, AXnl);
+            k = kk;
+        }
+        int pw = 0, dx = 0, dp = 0;
+        bool have_drop = false;
+        double best = INFINITY;
+        int j_best = 0;
+        std::vector<double> stop, paper, lam;
+        std::vector<int> act, act_hl;
+        for (int j = 1; j <= p.max_iter; ++j) {
+            ST(lp_check(Xl, AXl, k, stop, paper, lam));
+            double r = 0.0, ms = 0.0;
+            bool all = true;
+            for (int i = 0; i < n_ev; ++i) {
+                r = std::max(r, paper[i]);
+                ms = std::max(ms, stop[i]);
+                all = all && (stop[i] <= p.tol);
+            }
+            iters = j;
+            lp_iters = j;
+            last_r = r;
+            last_stop = ms;
+            ctl.observe(j, r);
+            record(j, r, ms, k, pw, k, 0, 4);
+            if (r < best) {
+                best = r;
+                j_best = j;
+            }
+            if (all) {
+                lp_done = true;
+                break;
+            }
+            if (r <= rsw || j - j_best >= kStall || out_of_time()) break;
+            const bool want_expand = ctl.ifexpand(j);
+            int flags = 4;
+
+            const int a = k;
+            act.resize(a);
+            for (int i = 0; i < a; ++i) act[i] = i;
+            std::memcpy(ws.h_act.p, act.data(), sizeof(int) * a);
+            HC(hipMemcpyAsync(ws.act.p, ws.h_act.p, sizeof(int) * a, hipMemcpyHostToDevice, st));
+            ST(tic());
+            HC(launch_form_w_lp<T>(st, n, Xl, AXl, ld, ws.theta.as<double>(), ws.act.as<int>(), a, Wl, ld));
+            ST(toc(SE_K_RESID, 3.0 * sizeof(T) * n * a, 2.0 * n * a));
+            ST(lp_spmm(Wl, AWl, a));
+            act_hl = act;
+            if (want_expand && have_drop) {
+                HC(launch_copy_cols_lp<T>(st, n, Sdl, ld, 0, Xl, ld, k, dx));
+                HC(launch_copy_cols_lp<T>(st, n, ASdl, ld, 0, AXl, ld, k, dx));
+                HC(launch_copy_cols_lp<T>(st, n, Sdl, ld, dx, Pl, ld, pw, dp));
+                HC(launch_copy_cols_lp<T>(st, n, ASdl, ld, dx, APl, ld, pw, dp));
+                for (int q = 0; q < dx; ++q) act_hl.push_back(k + q);
+                k += dx;
+                pw += dp;
+                ctl.did_expand(j);
+                have_drop = false;
+                ++n_exp;
+                flags |= 1;
+            }
+            const int m = k + pw + a;
+            const SegsT<T> S = lseg3(Xl, k, Pl, pw, Wl, a);
+            const SegsT<T> AS = lseg3(AXl, k, APl, pw, AWl, a);
+            ST(lp_gram(S, S, 1, ws.lpM.as<double>()));
+            ST(lp_gram(S, AS, 1, ws.G.as<double>()));
+            const int ahl = (int)act_hl.size();
+            std::memcpy(ws.h_act_hl.p, act_hl.data(), sizeof(int) * ahl);
+            HC(hipMemcpyAsync(ws.act_hl.p, ws.h_act_hl.p, sizeof(int) * ahl, hipMemcpyHostToDevice, st));
+            int kk = k, rP = 0;
+            ST(grr(m, kk, ahl, drop2, rP));
+            SegsT<T> O = make_segs_t<T>(ld);
+            push_seg_t(O, (const T*)Xnl, kk);
+            push_seg_t(O, (const T*)Pnl, rP);
+            ST(lp_update(S, ws.lpC.as<double>(), kk + rP, O, 1.0, 0.0));
+            SegsT<T> AO = make_segs_t<T>(ld);
+            push_seg_t(AO, (const T*)AXnl, kk);
+            push_seg_t(AO, (const T*)APnl, rP);
+            ST(lp_update(AS, ws.lpC.as<double>(), kk + rP, AO, 1.0, 0.0));
+            std::swap(Xl, Xnl);
+            std::swap(Pl, Pnl);
+            std::swap(AXl, AXnl);
+            std::swap(APl, APnl);
+            k = kk;
+            pw = rP;
+            if (ctl.ifshrink(j) && k > n_es) {
+                dx = k - n_es;
+                dp = std::max(0, pw - n_es);
+                dp = std::min(dp, ld - dx);
+                HC(launch_copy_cols_lp<T>(st, n, Xl, ld, n_es, Sdl, ld, 0, dx));
+                HC(launch_copy_cols_lp<T>(st, n, AXl, ld, n_es, ASdl, ld, 0, dx));
+                HC(launch_copy_cols_lp<T>(st, n, Pl, ld, n_es, Sdl, ld, dx, dp));
+                HC(launch_copy_cols_lp<T>(st, n, APl, ld, n_es, ASdl, ld, dx, dp));
+                k = n_es;
+                pw = std::min(pw, n_es);
+                have_drop = true;
+                ctl.did_shrink(j);
+                ++n_shr;
+                flags |= 2;
+            }
+            amend_flags(flags);
+        }
+        if (lp_done) {  // X leaves in FP64 with its Ritz values (finish re-checks)
+            ST(lp_to_f64(Xl, k, Sdl, 0, k0));
+            return SE_OK;
+        }
+        return lp_to_f64(Xl, k, Sdl, have_drop ? std::min(dx, nb - k) : 0, k0);
+    }
+
+    // Subspace iteration (Algorithm 1) with shrink-and-expand on
+    // low-precision panels: Y = sigma X - A X (plus X_drop at an expansion),
+    // then the generalized Rayleigh-Ritz step on span(Y).
+    template <class T>
+    se_status si_lp(const double* X0, int& k0) {
+        ST(alloc_panels(14));
+        ST(alloc_small(nb));
+        ST(lp_alloc<T>());
+        T* Xl = static_cast<T*>(lp[0]);
+        T* AXl = static_cast<T*>(lp[3]);
+        T* Xnl = static_cast<T*>(lp[6]);
+        T* AXnl = static_cast<T*>(lp[8]);
+        T* Sdl = static_cast<T*>(lp[10]);
+        const double u = unit_roundoff<T>();
+        const double drop2 = 100.0 * u * u;
+        const double rsw = r_switch_value(u);
+        const double sigma = (p.sigma > 0.0) ? p.sigma : A->anorm;
+        if (p.ptr_mode == SE_PTR_HOST) {
+            HC(hipMemcpyAsync(T1, X0, sizeof(double) * (size_t)n * nb, hipMemcpyHostToDevice, st));
+            HC(launch_colmajor_to_rows_lp<T>(st, n, nb, T1, n, Xl, ld));
+        } else {
+            HC(launch_colmajor_to_rows_lp<T>(st, n, nb, X0, n, Xl, ld));
+        }
+        int k = nb, dx = 0;
+        bool have_drop = false;
+        double best = INFINITY;
+        int j_best = 0;
+        std::vector<double> stop, paper, lam;
+        // Rayleigh-Ritz on span(X): AX, M, A_p, grr, X <- X C, AX <- AX C.
+        auto rr = [&]() -> se_status {
+            ST(lp_spmm(Xl, AXl, k));
+            const SegsT<T> Xs = lseg1(Xl, k);
+            ST(lp_gram(Xs, Xs, 1, ws.lpM.as<double>()));
+            ST(lp_gram(Xs, lseg1(AXl, k), 1, ws.G.as<double>()));
+            int kk = k, rP = 0;
+            ST(grr(k, kk, 0, drop2, rP));
+            ST(lp_update(Xs, ws.lpC.as<double>(), kk, lseg1(Xnl, kk), 1.0, 0.0));
+            ST(lp_update(lseg1(AXl, k), ws.lpC.as<double>(), kk, lseg1(AXnl, kk), 1.0, 0.0));
+            std::swap(Xl, Xnl);
+            std::swap(AXl, AXnl);
+            k = kk;
+            return SE_OK;
+        };
+        ST(rr());
+        for (int j = 1; j <= p.max_iter; ++j) {
+            ST(lp_check(Xl, AXl, k, stop, paper, lam));
+            double r = 0.0, ms = 0.0;
+            bool all = true;
+            for (int i = 0; i < n_ev; ++i) {
+                r = std::max(r, paper[i]);
+                ms = std::max(ms, stop[i]);
+                all = all && (stop[i] <= p.tol);
+            }
+            iters = j;
+            lp_iters = j;
+            last_r = r;
+            last_stop = ms;
+            ctl.observe(j, r);
+            record(j, r, ms, k, 0, k, 0, 4);
+            if (r < best) {
+                best = r;
+                j_best = j;
+            }
+            if (all) {
+                lp_done = true;
+                break;
+            }
+            if (r <= rsw || j - j_best >= kStall || out_of_time()) break;
+            int flags = 4;
+            const bool want_expand = ctl.ifexpand(j);
+            ST(tic());
+            HC(launch_shift_sub_lp<T>(st, n, Xl, AXl, ld, k, sigma));
+            ST(toc(SE_K_RESID, 3.0 * sizeof(T) * n * k, 2.0 * n * k));
+            if (want_expand && have_drop) {
+                HC(launch_copy_cols_lp<T>(st, n, Sdl, ld, 0, Xl, ld, k, dx));
+                k += dx;
+                have_drop = false;
+                ctl.did_expand(j);
+                ++n_exp;
+                flags |= 1;
+            }
+            ST(rr());
+            if (ctl.ifshrink(j) && k > n_es) {
+                dx = k - n_es;
+                HC(launch_copy_cols_lp<T>(st, n, Xl, ld, n_es, Sdl, ld, 0, dx));
+                k = n_es;
+                have_drop = true;
+                ctl.did_shrink(j);
+                ++n_shr;
+                flags |= 2;
+            }
+            amend_flags(flags);
+        }
+        if (lp_done) return lp_to_f64(Xl, k, Sdl, 0, k0);
+        return lp_to_f64(Xl, k, Sdl, have_drop ? std::min(dx, nb - k) : 0, k0);
+    }
+
+    // Mixed precision: the low-precision phase, then the FP64 solver from its
+    // X (a fresh shrink-and-expand controller, history rows continuing).
+    template <class T>
+    se_status mixed(const double* X0) {
+        const Strategy ctl0 = ctl;
+        int k0 = 0;
+        ST(p.solver == SE_SI ? si_lp<T>(X0, k0) : lobpcg_lp<T>(X0, k0));
+        if (lp_done) {
+            converged = true;
+            return SE_OK;
+        }
+        if (k0 < n_ev) return SE_ERR_BREAKDOWN;
+        ctl = ctl0;
+        j_off = lp_iters;
+        return p.solver == SE_SI ? si(nullptr, k0) : lobpcg(nullptr, k0);
     }
 
     // Fresh residual of the returned pairs, then write V and lambda.
@@ -716,7 +1137,13 @@ se_status solve(se_ctx* ctx, const se_matrix* A, const se_params* prm, const dou
     (void)hipEventCreate(&e0);
     (void)hipEventCreate(&e1);
     (void)hipEventRecord(e0, ctx->stream);
-    se_status st = (prm->solver == SE_SI) ? s.si(X0) : s.lobpcg(X0);
+    se_status st;
+    if (prm->precision == SE_FP32_MIXED)
+        st = s.mixed<float>(X0);
+    else if (prm->precision == SE_BF16_MIXED)
+        st = s.mixed<bf16_t>(X0);
+    else
+        st = (prm->solver == SE_SI) ? s.si(X0) : s.lobpcg(X0);
     if (st >= 0) st = s.finish(V, lambda, info);
     s.summarize(info);
     (void)hipEventRecord(e1, ctx->stream);
@@ -735,6 +1162,7 @@ se_status solve(se_ctx* ctx, const se_matrix* A, const se_params* prm, const dou
         info->workspace_bytes = ctx->ws.device_bytes();
         info->hip_error = (int)s.herr;
         info->history_len = s.hist_len;
+        info->lp_iterations = s.lp_iters;
         if (st < 0) {
             info->max_stop_ratio = s.last_stop;
             info->max_paper_ratio = s.last_r;

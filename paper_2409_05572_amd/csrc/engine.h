@@ -61,25 +61,32 @@ struct HostBuf {
 };
 
 constexpr int kNumPanels = 14;
+constexpr int kNumLpPanels = 12;
 
 struct Workspace {
-    DevBuf panel[kNumPanels];  // n x ld blocks
+    DevBuf panel[kNumPanels];       // n x ld FP64 blocks
+    DevBuf lp_panel[kNumLpPanels];  // n x ld FP32 / BF16 blocks (mixed precision)
     DevBuf gram_part, G, T, Z, theta, C, small_work, syev_work, lam, act, act_hl, norms, info;
     DevBuf hlB, hlY, hlG, hlQ;
+    DevBuf lpM, lpT, lpQ, lpB, lpE, lpC;  // generalized Rayleigh-Ritz (m x m each)
     HostBuf h_norms, h_info, h_act, h_act_hl, h_theta;
     std::vector<hipEvent_t> events;  // pool for per-launch timing
     size_t device_bytes() const {
         size_t s = 0;
         for (const auto& b : panel) s += b.bytes;
+        for (const auto& b : lp_panel) s += b.bytes;
         const DevBuf* all[] = {&gram_part, &G, &T, &Z, &theta, &C, &small_work, &syev_work,
-                               &lam, &act, &act_hl, &norms, &info, &hlB, &hlY, &hlG, &hlQ};
+                               &lam, &act, &act_hl, &norms, &info, &hlB, &hlY, &hlG, &hlQ,
+                               &lpM, &lpT, &lpQ, &lpB, &lpE, &lpC};
         for (auto* b : all) s += b->bytes;
         return s;
     }
     void release() {
         for (auto& b : panel) b.release();
+        for (auto& b : lp_panel) b.release();
         DevBuf* all[] = {&gram_part, &G, &T, &Z, &theta, &C, &small_work, &syev_work,
-                         &lam, &act, &act_hl, &norms, &info, &hlB, &hlY, &hlG, &hlQ};
+                         &lam, &act, &act_hl, &norms, &info, &hlB, &hlY, &hlG, &hlQ,
+                         &lpM, &lpT, &lpQ, &lpB, &lpE, &lpC};
         for (auto* b : all) b->release();
         h_norms.release();
         h_info.release();
@@ -139,6 +146,7 @@ struct se_matrix {
     int* rowptr = nullptr;  // int32 offsets on the device
     int* col = nullptr;
     double* val = nullptr;
+    mutable float* val32 = nullptr;  // FP32 copy for the mixed-precision phase, made on first use
     double anorm = 0.0;
 };
 

@@ -1,0 +1,197 @@
+"""Mixed precision on the GPU (FP32 / BF16 panels, FP64 reductions and
+refinement): the low-precision bulk kernels against FP64 products of the same
+stored values, and whole solves against closed forms and the FP64 oracle.
+
+Error bounds of the kernels follow from their arithmetic: FP32 products and
+FP32 accumulation runs of at most 64 terms (folded into FP64 after that),
+the FP64 coefficient matrix of an update rounded to FP32, and one rounding of
+every output to its storage format.
+"""
+import numpy as np
+import pytest
+
+import oracle as O
+import workloads as W
+from tests import _pins as pins
+from tests.gpu_util import gpu_ctx, to_dev
+
+pytestmark = pytest.mark.gpu
+
+U32 = 2.0 ** -24
+UNIT = {"fp32": 2.0 ** -24, "bf16": 2.0 ** -8}
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    return gpu_ctx()
+
+
+def _dtype(fmt):
+    import torch
+
+    return torch.float32 if fmt == "fp32" else torch.bfloat16
+
+
+def _block(a, fmt, ld=None):
+    """Device block of the given format with leading dimension ld (padding
+    columns hold garbage on purpose); returns (tensor, stored values as
+    float64)."""
+    import torch
+
+    n, w = a.shape
+    ld = ld or (w + 7) // 8 * 8
+    full = np.full((n, ld), 7.0e3)
+    full[:, :w] = a
+    t = torch.from_numpy(full.astype(np.float32)).to(_dtype(fmt)).cuda()
+    return t, t[:, :w].float().double().cpu().numpy()
+
+
+def _read(t, w):
+    return t[:, :w].float().double().cpu().numpy()
+
+
+@pytest.mark.parametrize("fmt", ["fp32", "bf16"])
+@pytest.mark.parametrize("w", [1, 3, 4, 16, 48, 69, 96, 250])
+def test_spmm_lp_matches_product_of_stored_values(ctx, fmt, w):
+    import torch
+
+    from paper_2409_05572_amd import api
+
+    A = W.anderson_3d(11, 4.0, 7)  # non-integer diagonal: FP32 rounding of A matters
+    rng = np.random.default_rng(w)
+    X, Xs = _block(rng.standard_normal((A.n, w)), fmt)
+    Y = torch.zeros_like(X)
+    M = api.Matrix.from_csr(ctx, A)
+    api.spmm_lp(ctx, M, X, Y, w)
+    got = _read(Y, w)
+    A32 = A.to_scipy().astype(np.float32).astype(np.float64)
+    ref = A32 @ Xs
+    absA = abs(A32)
+    nnz_row = int(np.diff(A.rowptr).max())
+    bound = (nnz_row + 2) * U32 * (absA @ abs(Xs)) + UNIT[fmt] * abs(ref) + 1e-300
+    assert np.all(np.abs(got - ref) <= bound)
+    assert np.all(Y[:, w:].float().cpu().numpy() == 0.0)  # padding columns untouched
+
+
+@pytest.mark.parametrize("fmt", ["fp32", "bf16"])
+@pytest.mark.parametrize("n,mu,mv", [(1000, 1, 1), (1000, 17, 5), (20001, 96, 96), (20001, 150, 250),
+                                     (70001, 250, 250), (5000, 750, 33)])
+def test_gram_lp_within_fp32_accumulation_bound(ctx, fmt, n, mu, mv):
+    import torch
+
+    from paper_2409_05572_amd import api
+
+    rng = np.random.default_rng(n + mu + mv)
+    U, Us = _block(rng.standard_normal((n, mu)), fmt)
+    V, Vs = _block(rng.standard_normal((n, mv)), fmt)
+    C = torch.zeros((mu, mv), dtype=torch.float64, device="cuda")
+    api.gram_lp(ctx, U, mu, V, mv, C)
+    ref = Us.T @ Vs
+    bound = 70 * U32 * (abs(Us).T @ abs(Vs))
+    assert np.all(np.abs(C.cpu().numpy() - ref) <= bound)
+
+
+def test_gram_lp_is_deterministic(ctx):
+    import torch
+
+    from paper_2409_05572_amd import api
+
+    rng = np.random.default_rng(3)
+    U, _ = _block(rng.standard_normal((300001, 96)), "fp32")
+    C1 = torch.zeros((96, 96), dtype=torch.float64, device="cuda")
+    C2 = torch.zeros_like(C1)
+    api.gram_lp(ctx, U, 96, U, 96, C1)
+    api.gram_lp(ctx, U, 96, U, 96, C2)
+    assert torch.equal(C1, C2)
+
+
+@pytest.mark.parametrize("fmt", ["fp32", "bf16"])
+@pytest.mark.parametrize("n,K,N,beta", [(20001, 1, 1, 0.0), (20001, 33, 16, 1.0), (20001, 250, 69, 0.0),
+                                        (5003, 750, 250, 1.0), (64, 96, 96, 0.0)])
+def test_update_lp_within_bound(ctx, fmt, n, K, N, beta):
+    from paper_2409_05572_amd import api
+
+    rng = np.random.default_rng(K * 1000 + N)
+    U, Us = _block(rng.standard_normal((n, K)), fmt)
+    Cm = rng.standard_normal((K, N))
+    Out, Olds = _block(rng.standard_normal((n, N)), fmt)
+    api.update_lp(ctx, U, K, to_dev(Cm), N, Out, beta)
+    got = _read(Out, N)
+    ref = beta * Olds + Us @ Cm
+    bound = 72 * U32 * (abs(Us) @ abs(Cm) + beta * abs(Olds)) + UNIT[fmt] * abs(ref) + 1e-300
+    assert np.all(np.abs(got - ref) <= bound)
+
+
+def _solve(ctx, A, X0, n_ev, n_extra, **kw):
+    from paper_2409_05572_amd import api
+
+    M = api.Matrix.from_csr(ctx, A)
+    return api.solve(ctx, M, X0, n_ev, n_extra, history_cap=6000, **kw)
+
+
+def _check_result(A, lam, V, info, exact, lam_rtol=1e-10):
+    assert info.converged and info.status == 0
+    assert info.max_stop_ratio <= 1e-8
+    assert np.max(np.abs(lam - exact) / np.abs(exact)) <= lam_rtol
+    R = A.to_scipy() @ V - V * lam[None, :]
+    assert np.max(np.linalg.norm(R, axis=0) / (A.anorm * np.linalg.norm(V, axis=0))) <= 1e-8 * 1.0001
+    assert np.abs(V.T @ V - np.eye(V.shape[1])).max() <= 1e-12
+
+
+@pytest.mark.parametrize("fmt", ["fp32", "bf16"])
+@pytest.mark.parametrize("solver", ["lobpcg", "si"])
+def test_config1_mixed_matches_closed_form(ctx, fmt, solver):
+    A = W.laplacian_2d(32)
+    X0 = W.gaussian_block(A.n, 16, 201)
+    lam, V, info = _solve(ctx, A, X0, 8, 8, solver=solver, precision=fmt)
+    _check_result(A, lam, V, info, pins.laplacian_spectrum(32, 2, 8))
+    h = info.history
+    lp_rows = (h[:, 7].astype(int) & 4) != 0
+    assert info.lp_iterations >= 1 and lp_rows.sum() == info.lp_iterations
+    assert np.all(lp_rows[: info.lp_iterations]) and not lp_rows[info.lp_iterations:].any()
+    # the low-precision phase got r(j) down to r_switch or stalled there
+    r_lp = h[lp_rows, 1]
+    assert r_lp.min() <= (1e-6 if fmt == "fp32" else 1e-3) * 100
+
+
+@pytest.mark.parametrize("fmt,strategy", [("fp32", "fix"), ("fp32", "slopek"), ("bf16", "fix")])
+def test_3d_laplacian_mixed_with_shrink_expand(ctx, fmt, strategy):
+    m = 16
+    A = W.laplacian_3d(m)
+    X0 = W.gaussian_block(A.n, 48, 203)
+    lam, V, info = _solve(ctx, A, X0, 32, 16, precision=fmt, strategy=strategy)
+    _check_result(A, lam, V, info, pins.laplacian_spectrum(m, 3, 32))
+    assert info.n_shrinks >= 1
+    if fmt == "fp32":  # r(j) passes r_warm inside the FP32 phase, so it shrinks there too
+        lp = (info.history[:, 7].astype(int) & 4) != 0
+        assert ((info.history[lp, 7].astype(int) & 2) != 0).any()
+
+
+def test_anderson_fp32_mixed_matches_fp64_oracle(ctx):
+    A = W.anderson_3d(14, 4.0, 103)
+    X0 = W.gaussian_block(A.n, 30, 204)
+    lam, V, info = _solve(ctx, A, X0, 20, 10, precision="fp32", strategy="fix")
+    ref = O.lobpcg(A.to_scipy(), X0, 20, A.anorm, tol=1e-8)
+    assert info.converged
+    scale = np.maximum(np.abs(ref.lam), 1e-3 * A.anorm)
+    assert np.max(np.abs(lam - ref.lam) / scale) <= 1e-9
+    R = A.to_scipy() @ V - V * lam[None, :]
+    assert np.max(np.linalg.norm(R, axis=0) / (A.anorm * np.linalg.norm(V, axis=0))) <= 1e-8 * 1.0001
+
+
+def test_mixed_solve_is_bitwise_reproducible(ctx):
+    A = W.laplacian_3d(12)
+    X0 = W.gaussian_block(A.n, 24, 205)
+    lam1, V1, i1 = _solve(ctx, A, X0, 16, 8, precision="fp32", strategy="fix")
+    lam2, V2, i2 = _solve(ctx, A, X0, 16, 8, precision="fp32", strategy="fix")
+    assert i1.iterations == i2.iterations and i1.lp_iterations == i2.lp_iterations
+    assert np.array_equal(lam1, lam2) and np.array_equal(V1, V2)
+
+
+def test_mixed_rejects_negative_switch_threshold(ctx):
+    from paper_2409_05572_amd._lib import SeError
+
+    A = W.laplacian_2d(8)
+    X0 = W.gaussian_block(A.n, 6, 1)
+    with pytest.raises(SeError):
+        _solve(ctx, A, X0, 3, 3, precision="fp32", r_switch=-1.0)
