@@ -26,21 +26,49 @@ if ROOT not in sys.path:
 METRIC = "time-to-solution & HBM GB/s, shrink-expand vs fixed block; p50/p99 latency"
 
 
+# Workloads: matrix family and default sizes (n_ev, n_extra, solver, precision).
+WORKLOADS = {
+    "laplace3d": dict(grid=128, n_ev=64, n_extra=32, x0_seed=202),
+    "anderson": dict(grid=100, n_ev=200, n_extra=50, x0_seed=203),
+    "chunglu": dict(nodes=500000, n_ev=32, n_extra=16, x0_seed=204),
+}
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=2)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--grid", type=int, default=128, help="3-D grid side m (n = m^3)")
-    ap.add_argument("--n-ev", type=int, default=64)
-    ap.add_argument("--n-extra", type=int, default=32)
+    ap.add_argument("--workload", default="laplace3d", choices=sorted(WORKLOADS))
+    ap.add_argument("--grid", type=int, default=None, help="3-D grid side m (n = m^3)")
+    ap.add_argument("--nodes", type=int, default=None, help="Chung-Lu graph size")
+    ap.add_argument("--n-ev", type=int, default=None)
+    ap.add_argument("--n-extra", type=int, default=None)
+    ap.add_argument("--solver", default="lobpcg", choices=["lobpcg", "si"])
+    ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32", "bf16"])
+    ap.add_argument("--max-iter", type=int, default=None)
     ap.add_argument("--strategy", default="fix")
     ap.add_argument("--no-fixed", action="store_true", help="skip the fixed-block comparison")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run one plain 1 GiB device copy first (the reference for HBM counters)")
-    return ap.parse_args()
+    args = ap.parse_args()
+    for key, val in WORKLOADS[args.workload].items():
+        if key != "x0_seed" and getattr(args, key, None) is None:
+            setattr(args, key, val)
+    args.x0_seed = WORKLOADS[args.workload]["x0_seed"]
+    return args
+
+
+def build_matrix(args):
+    import workloads as W
+
+    if args.workload == "laplace3d":
+        return W.laplacian_3d(args.grid), f"laplace3d_{args.grid}^3"
+    if args.workload == "anderson":
+        return W.anderson_3d(args.grid, 4.0, 103), f"anderson3d_{args.grid}^3_w4"
+    return W.chung_lu_laplacian(args.nodes, 16.0, 2.5, 104), f"chunglu_n{args.nodes}_d16_b2.5"
 
 
 def main():
@@ -59,9 +87,9 @@ def main():
         print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
     t = time.time()
-    A = W.laplacian_3d(args.grid)
+    A, wname = build_matrix(args)
     nb = args.n_ev + args.n_extra
-    X0 = W.gaussian_block(A.n, nb, 202)
+    X0 = W.gaussian_block(A.n, nb, args.x0_seed)
     log(f"inputs n={A.n} nnz={A.nnz} nb={nb} built in {time.time() - t:.1f}s")
 
     if args.calibrate_copy:
@@ -79,9 +107,12 @@ def main():
     X0d = torch.from_numpy(np.ascontiguousarray(X0.T)).cuda()
     torch.cuda.synchronize()
 
+    extra = {} if args.max_iter is None else {"max_iter": args.max_iter}
+
     def run(strategy, profile=0):
         return api.solve(ctx, M, X0d, args.n_ev, args.n_extra, strategy=strategy, tol=1e-8,
-                         history_cap=5000, profile=profile)
+                         history_cap=30000, profile=profile, solver=args.solver,
+                         precision=args.precision, **extra)
 
     for i in range(args.warmup):
         lam, V, info = run(args.strategy)
@@ -107,35 +138,43 @@ def main():
         "higher_is_better": False,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": {"fp64": "f64", "fp32": "f32+f64", "bf16": "bf16+f64"}[args.precision],
         "data": "synthetic",
         "config": {
-            "workload": f"laplace3d_{args.grid}^3 LOBPCG n_ev={args.n_ev} n_extra={args.n_extra} "
-                        f"strategy={args.strategy} tol=1e-8",
+            "workload": f"{wname} {args.solver.upper()} n_ev={args.n_ev} n_extra={args.n_extra} "
+                        f"strategy={args.strategy} precision={args.precision} tol=1e-8",
             "n": A.n, "nnz": A.nnz, "n_ev": args.n_ev, "block": nb,
         },
         "shrink_expand": {
             "iterations": infos[-1].iterations, "n_shrinks": infos[-1].n_shrinks,
             "n_expands": infos[-1].n_expands, "max_stop_ratio": infos[-1].max_stop_ratio,
+            "converged": infos[-1].converged, "low_precision_iterations": infos[-1].lp_iterations,
         },
     }
     lam_np = lam.cpu().numpy()
-    m = args.grid
-    one = 2.0 - 2.0 * np.cos(np.arange(1, m + 1) * np.pi / (m + 1))
-    ex = np.sort((one[:, None, None] + one[None, :, None] + one[None, None, :]).ravel())[: args.n_ev]
-    out["parity"] = {"max_eig_rel_err_vs_closed_form": float(np.max(np.abs(lam_np - ex) / ex)),
-                     "max_stop_ratio": infos[-1].max_stop_ratio}
+    out["parity"] = {"max_stop_ratio": infos[-1].max_stop_ratio}
+    if args.workload == "laplace3d":
+        m = args.grid
+        one = 2.0 - 2.0 * np.cos(np.arange(1, m + 1) * np.pi / (m + 1))
+        ex = np.sort((one[:, None, None] + one[None, :, None] + one[None, None, :]).ravel())[: args.n_ev]
+        out["parity"]["max_eig_rel_err_vs_closed_form"] = float(np.max(np.abs(lam_np - ex) / ex))
+    out["lambda_head"] = [float(v) for v in lam_np[:4]]
+    out["lambda_tail"] = [float(v) for v in lam_np[-2:]]
 
     if not args.no_fixed:
         t1 = time.perf_counter()
         _, _, finfo = run("none")
         torch.cuda.synchronize()
         fwall = time.perf_counter() - t1
-        out["fixed_block"] = {"time_s": round(fwall, 4), "iterations": finfo.iterations}
+        out["fixed_block"] = {"time_s": round(fwall, 4), "iterations": finfo.iterations,
+                              "converged": finfo.converged,
+                              "low_precision_iterations": finfo.lp_iterations}
         out["speedup_vs_fixed"] = round(fwall / wall, 3)
         log(f"fixed block: {fwall:.3f}s iters={finfo.iterations}")
 
-    out["roofline"], out["kernels"] = roofline(infos, f"laplace3d_{args.grid}_fp64")
+    tag = {"laplace3d": f"laplace3d_{args.grid}", "anderson": f"anderson_{args.grid}",
+           "chunglu": f"chunglu_{args.nodes}"}[args.workload]
+    out["roofline"], out["kernels"] = roofline(infos, f"{tag}_{args.precision}", args.precision)
     out["cpu_baseline"] = None
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(A, X0, args, infos[-1].iterations, log)
@@ -145,6 +184,7 @@ def main():
 # Published MI355X peaks: HBM3E 8 TB/s; FP64 vector and matrix 78.6 TFLOP/s.
 HBM_PEAK_GBS = 8000.0
 FP64_PEAK_TFS = 78.6
+FP32_PEAK_TFS = 157.3  # FP32 vector and matrix
 # kernel classes whose launches are FP64 MFMA contractions
 MFMA_CLASSES = ("gram", "update")
 
@@ -171,10 +211,12 @@ def measured_traffic(name, workload):
     return float(fields["bytes_per_launch"])
 
 
-def roofline(infos, workload=None):
+def roofline(infos, workload=None, precision="fp64"):
     """Per kernel class: device time summed from HIP events around every
     launch in the timed solves, algorithmic bytes and flops. The dominant
-    class (largest time) is reported against its roof."""
+    class (largest time) is reported against its roof: FP64 MFMA for FP64
+    solves; FP32 MFMA for mixed-precision ones (their classes also hold the
+    FP64 refinement launches, so the fraction is approximate there)."""
     from paper_2409_05572_amd._lib import KERNEL_CLASSES
 
     ms = np.zeros(8)
@@ -198,14 +240,15 @@ def roofline(infos, workload=None):
     sec = ms[dom] / 1e3
     name = KERNEL_CLASSES[dom]
     intensity = fl[dom] / max(by[dom], 1.0)
-    if name in ("spmm", "resid", "copy") or intensity < FP64_PEAK_TFS * 1e12 / (HBM_PEAK_GBS * 1e9):
+    peak = FP64_PEAK_TFS if precision == "fp64" else FP32_PEAK_TFS
+    if name in ("spmm", "resid", "copy") or intensity < peak * 1e12 / (HBM_PEAK_GBS * 1e9):
         ach = by[dom] / sec / 1e9
         roof = {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(ach / HBM_PEAK_GBS, 4)}
     else:
         ach = fl[dom] / sec / 1e12
         roof = {"bound": "mfma" if name in MFMA_CLASSES else "alu", "achieved": round(ach, 2),
-                "peak": FP64_PEAK_TFS, "unit": "TFLOP/s", "frac": round(ach / FP64_PEAK_TFS, 4)}
+                "peak": peak, "unit": "TFLOP/s", "frac": round(ach / peak, 4)}
     traffic = measured_traffic(name, workload) if workload else None
     roof.update({"traffic": None if traffic is None else round(traffic), "kernel": name,
                  "launches": int(calls[dom]), "avg_launch_us": round(1e3 * ms[dom] / calls[dom], 1),
@@ -225,15 +268,17 @@ def cpu_baseline(A, X0, args, gpu_iters, log):
     except Exception:
         cores = os.cpu_count()
     t = time.perf_counter()
-    res = O.lobpcg(A.to_scipy(), X0, args.n_ev, A.anorm, tol=1e-8, n_es=args.n_ev + 5,
-                   se=O.SEParams(args.strategy), time_limit_s=args.cpu_seconds)
+    solver = O.subspace_iteration if args.solver == "si" else O.lobpcg
+    res = solver(A.to_scipy(), X0, args.n_ev, A.anorm, tol=1e-8,
+                 n_es=args.n_ev + min(5, args.n_extra - 1), se=O.SEParams(args.strategy),
+                 time_limit_s=args.cpu_seconds)
     el = time.perf_counter() - t
     done = max(res.iterations - 1, 1)  # the last recorded iteration stopped at its check
     per_iter = el / done
     est = per_iter * gpu_iters
     log(f"cpu oracle: {done} iteration(s) in {el:.1f}s on {cores} threads")
     return {"value": round(est, 1), "unit": "s", "cores": int(cores), "kind": "oracle",
-            "sample": f"initial Rayleigh-Ritz + {done} LOBPCG iteration(s) of the same workload in "
+            "sample": f"initial Rayleigh-Ritz + {done} FP64 {args.solver.upper()} iteration(s) of the same workload in "
                       f"{el:.1f}s; time-to-solution extrapolated as {per_iter:.2f}s/iteration x "
                       f"{gpu_iters} iterations (GPU count)",
             "extrapolated": True}

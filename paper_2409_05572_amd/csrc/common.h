@@ -178,6 +178,13 @@ hipError_t launch_chol_drop(hipStream_t st, int a, const double* G, double* T, d
 // m x m matrix A (row-major, overwritten): w[0..k) ascending, Z row-major
 // m x k (leading dimension k, eigenvector c in column c). work needs
 // syev_work_doubles(m). launch_syev is the k = m case.
+// Small dense helpers: Y = alpha X + beta Y over count entries; A[i][i] +=
+// alpha for i < m; fill a rows x cols block; out[0] = sum of squares.
+hipError_t launch_axpby(hipStream_t st, long long count, double alpha, const double* X, double beta, double* Y);
+hipError_t launch_add_diag(hipStream_t st, int m, double* A, long long ld, double alpha);
+hipError_t launch_fill(hipStream_t st, int rows, int cols, double* A, long long ld, double v);
+hipError_t launch_sumsq(hipStream_t st, long long count, const double* X, double* out);
+
 size_t syev_work_doubles(int m);
 hipError_t launch_syev_lowest(hipStream_t st, int m, int k, double* A, double* w, double* Z,
                               double* work);

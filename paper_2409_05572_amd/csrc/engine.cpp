@@ -765,26 +765,100 @@ struct Solver {
         return check_host(k, stop, paper, lam);
     }
 
+    // Whitening of the basis for the generalized Rayleigh-Ritz step: writes
+    // T_M (m x r, ws.lpT, leading dimension r) with T_M^T M T_M = I for
+    // M = ws.lpM, dropping dependent columns (scaled pivots below drop2).
+    // When the first q columns are orthonormal up to E = M11 - I with
+    // ||E||_F <= 1e-2 (the X and P columns that leave every Rayleigh-Ritz
+    // step whitened, rounded to the storage format), only the Schur
+    // complement of the other a2 = m - q columns is factorized:
+    //   B = -M11^{-1} M12 (Neumann series to E^3), S22 = M22 + M12^T B,
+    //   S22 = R^T R (scaled, with drop) -> T22 = R^{-1},
+    //   T11 = M11^{-1/2} = I - E/2 + 3E^2/8 - 5E^3/16,
+    //   T_M = [[T11, B T22], [0, T22]].
+    // Otherwise (or when the check fails) the whole of M is factorized.
+    se_status whiten(int m, int q, double drop2, int& r) {
+        double* M = ws.lpM.as<double>();
+        double* TM = ws.lpT.as<double>();
+        int* info_i = ws.info.as<int>();
+        const int doff = (m + 8) / 2 + 4;
+        double* info_d = ws.info.as<double>() + doff;
+        const size_t rb = sizeof(double) * (doff + 2);
+        const int a2 = m - q;
+        if (q > 0 && a2 > 0) {
+            double* E = ws.hlB.as<double>();    // q x q
+            double* M12 = ws.hlY.as<double>();  // q x a2
+            double* Fa = ws.hlG.as<double>();   // q x a2
+            double* Fb = ws.hlQ.as<double>();   // q x a2
+            double* S22 = ws.lpQ.as<double>();  // a2 x a2
+            double* G22 = ws.lpB.as<double>();  // a2 x a2
+            double* H = ws.lpE.as<double>();    // q x q
+            double* T11 = ws.lpC.as<double>();  // q x q
+            double* BT = ws.C.as<double>();     // q x r2
+            double* T22 = ws.T.as<double>();    // a2 x r2
+            const long long qq = (long long)q * q;
+            const Segs Es = segx(E, q, q);
+            HC(launch_copy_cols(st, q, M, m, 0, E, q, 0, q));
+            HC(launch_add_diag(st, q, E, q, -1.0));
+            HC(launch_sumsq(st, qq, E, info_d + 1));
+            HC(launch_copy_cols(st, q, M, m, q, M12, a2, 0, a2));
+            // F = M12 - E (M12 - E (M12 - E M12)) = M11^{-1} M12 + O(E^4)
+            HC(launch_copy_cols(st, q, M12, a2, 0, Fa, a2, 0, a2));
+            ST(update_rows(q, Es, M12, a2, segx(Fa, a2, a2), -1.0, 1.0));
+            HC(launch_copy_cols(st, q, M12, a2, 0, Fb, a2, 0, a2));
+            ST(update_rows(q, Es, Fa, a2, segx(Fb, a2, a2), -1.0, 1.0));
+            HC(launch_copy_cols(st, q, M12, a2, 0, Fa, a2, 0, a2));
+            ST(update_rows(q, Es, Fb, a2, segx(Fa, a2, a2), -1.0, 1.0));
+            HC(launch_axpby(st, (long long)q * a2, 0.0, Fa, -1.0, Fa));  // B = -F
+            HC(launch_copy_cols(st, a2, M + (size_t)q * m, m, q, S22, a2, 0, a2));
+            ST(gram_rows(q, segx(M12, a2, a2), segx(Fa, a2, a2), 0, G22));
+            HC(launch_axpby(st, (long long)a2 * a2, 1.0, G22, 1.0, S22));
+            HC(launch_chol_drop(st, a2, S22, T22, ws.small_work.as<double>(), info_i, info_d, drop2));
+            // T11 = I + E (-1/2 I + E (3/8 I - 5/16 E))
+            HC(launch_copy_cols(st, q, E, q, 0, H, q, 0, q));
+            HC(launch_axpby(st, qq, 0.0, E, -5.0 / 16.0, H));
+            HC(launch_add_diag(st, q, H, q, 3.0 / 8.0));
+            ST(update_rows(q, Es, H, q, segx(T11, q, q), 1.0, 0.0));
+            HC(launch_add_diag(st, q, T11, q, -0.5));
+            ST(update_rows(q, Es, T11, q, segx(H, q, q), 1.0, 0.0));
+            HC(launch_add_diag(st, q, H, q, 1.0));
+            HC(hipMemcpyAsync(ws.h_info.p, ws.info.p, rb, hipMemcpyDeviceToHost, st));
+            ST(sync());
+            const int r2 = ws.h_info.as<int>()[0];
+            const double e2 = ws.h_info.as<double>()[doff + 1];
+            if (e2 <= 1e-4) {
+                r = q + r2;
+                if (r2 > 0) ST(update_rows(q, segx(Fa, a2, a2), T22, r2, segx(BT, r2, r2), 1.0, 0.0));
+                HC(launch_copy_cols(st, q, H, q, 0, TM, r, 0, q));
+                HC(launch_copy_cols(st, q, BT, r2, 0, TM, r, q, r2));
+                HC(launch_fill(st, a2, q, TM + (size_t)q * r, r, 0.0));
+                HC(launch_copy_cols(st, a2, T22, r2, 0, TM + (size_t)q * r, r, q, r2));
+                return SE_OK;
+            }
+        }
+        HC(launch_chol_drop(st, m, M, TM, ws.small_work.as<double>(), info_i, info_d, drop2));
+        HC(hipMemcpyAsync(ws.h_info.p, ws.info.p, sizeof(int) * 4, hipMemcpyDeviceToHost, st));
+        ST(sync());
+        r = ws.h_info.as<int>()[0];
+        return SE_OK;
+    }
+
     // Generalized Rayleigh-Ritz on m basis columns: M = ws.lpM and
-    // A_p = ws.G (both FP64, m x m). The scaled Cholesky factor of M, with
-    // columns dropped below drop2, gives T_M (m x r) with T_M^T M T_M = I; the
-    // k lowest pairs of T_M^T A_p T_M give theta and Y (r x k). With ahl > 0
+    // A_p = ws.G (both FP64, m x m); the first q columns are the whitened X
+    // and P of the previous step (see whiten). With T_M from whiten, the k
+    // lowest pairs of T_M^T A_p T_M give theta and Y (r x k). With ahl > 0
     // the HL basis is built in the whitened coordinates from the old X columns
-    // act_hl, whose coordinates there are E' = T_M^T M E. Output: the
-    // coefficients C = T_M [Y | C_P'] in ws.lpC (m x (k + rP)); k is lowered
-    // to r if fewer columns survive.
-    se_status grr(int m, int& k, int ahl, double drop2, int& rP) {
+    // act_hl (indices into S), whose coordinates there are E' = T_M^T M E.
+    // Output: the coefficients C = T_M [Y | C_P'] in ws.lpC (m x (k + rP));
+    // k is lowered to r if fewer columns survive.
+    se_status grr(int m, int q, int& k, int ahl, double drop2, int& rP) {
         double* M = ws.lpM.as<double>();
         double* TM = ws.lpT.as<double>();
         double* Q = ws.lpQ.as<double>();
         double* Ar = ws.lpB.as<double>();
-        int* info_i = ws.info.as<int>();
-        double* info_d = ws.info.as<double>() + (m + 8) / 2 + 4;
         ST(tic());
-        HC(launch_chol_drop(st, m, M, TM, ws.small_work.as<double>(), info_i, info_d, drop2));
-        HC(hipMemcpyAsync(ws.h_info.p, ws.info.p, sizeof(int) * 4, hipMemcpyDeviceToHost, st));
-        ST(sync());
-        const int r = ws.h_info.as<int>()[0];
+        int r = 0;
+        ST(whiten(m, q, drop2, r));
         if (r < n_ev) return SE_ERR_BREAKDOWN;
         k = std::min(k, r);
         ST(update_rows(m, segx(ws.G.as<double>(), m, m), TM, r, segx(Q, r, r), 1.0, 0.0));
@@ -853,7 +927,7 @@ struct Solver {
             ST(lp_gram(Xs, Xs, 1, ws.lpM.as<double>()));
             ST(lp_gram(Xs, lseg1(AXl, k), 1, ws.G.as<double>()));
             int kk = k, rP = 0;
-            ST(grr(k, kk, 0, drop2, rP));
+            ST(grr(k, 0, kk, 0, drop2, rP));
             ST(lp_update(Xs, ws.lpC.as<double>(), kk, lseg1(Xnl, kk), 1.0, 0.0));
             ST(lp_update(lseg1(AXl, k), ws.lpC.as<double>(), kk, lseg1(AXnl, kk), 1.0, 0.0));
             std::swap(Xl, Xnl);
@@ -902,30 +976,37 @@ struct Solver {
             HC(launch_form_w_lp<T>(st, n, Xl, AXl, ld, ws.theta.as<double>(), ws.act.as<int>(), a, Wl, ld));
             ST(toc(SE_K_RESID, 3.0 * sizeof(T) * n * a, 2.0 * n * a));
             ST(lp_spmm(Wl, AWl, a));
+            // S = [X, P, S_drop (at an expansion), W]: X and P leave the
+            // previous step whitened, so they lead (q columns); S_drop joins
+            // the block that is factorized, and its X part is kept with X.
             act_hl = act;
-            if (want_expand && have_drop) {
-                HC(launch_copy_cols_lp<T>(st, n, Sdl, ld, 0, Xl, ld, k, dx));
-                HC(launch_copy_cols_lp<T>(st, n, ASdl, ld, 0, AXl, ld, k, dx));
-                HC(launch_copy_cols_lp<T>(st, n, Sdl, ld, dx, Pl, ld, pw, dp));
-                HC(launch_copy_cols_lp<T>(st, n, ASdl, ld, dx, APl, ld, pw, dp));
-                for (int q = 0; q < dx; ++q) act_hl.push_back(k + q);
-                k += dx;
-                pw += dp;
+            const bool expand = want_expand && have_drop;
+            const int dd = expand ? dx + dp : 0;
+            if (expand) {
+                for (int q = 0; q < dx; ++q) act_hl.push_back(k + pw + q);
                 ctl.did_expand(j);
                 have_drop = false;
                 ++n_exp;
                 flags |= 1;
             }
-            const int m = k + pw + a;
-            const SegsT<T> S = lseg3(Xl, k, Pl, pw, Wl, a);
-            const SegsT<T> AS = lseg3(AXl, k, APl, pw, AWl, a);
+            const int q = k + pw;
+            const int m = q + dd + a;
+            SegsT<T> S = make_segs_t<T>(ld), AS = make_segs_t<T>(ld);
+            push_seg_t(S, (const T*)Xl, k);
+            push_seg_t(S, (const T*)Pl, pw);
+            push_seg_t(S, (const T*)Sdl, dd);
+            push_seg_t(S, (const T*)Wl, a);
+            push_seg_t(AS, (const T*)AXl, k);
+            push_seg_t(AS, (const T*)APl, pw);
+            push_seg_t(AS, (const T*)ASdl, dd);
+            push_seg_t(AS, (const T*)AWl, a);
             ST(lp_gram(S, S, 1, ws.lpM.as<double>()));
             ST(lp_gram(S, AS, 1, ws.G.as<double>()));
             const int ahl = (int)act_hl.size();
             std::memcpy(ws.h_act_hl.p, act_hl.data(), sizeof(int) * ahl);
             HC(hipMemcpyAsync(ws.act_hl.p, ws.h_act_hl.p, sizeof(int) * ahl, hipMemcpyHostToDevice, st));
-            int kk = k, rP = 0;
-            ST(grr(m, kk, ahl, drop2, rP));
+            int kk = k + (expand ? dx : 0), rP = 0;
+            ST(grr(m, q, kk, ahl, drop2, rP));
             SegsT<T> O = make_segs_t<T>(ld);
             push_seg_t(O, (const T*)Xnl, kk);
             push_seg_t(O, (const T*)Pnl, rP);
@@ -999,7 +1080,7 @@ struct Solver {
             ST(lp_gram(Xs, Xs, 1, ws.lpM.as<double>()));
             ST(lp_gram(Xs, lseg1(AXl, k), 1, ws.G.as<double>()));
             int kk = k, rP = 0;
-            ST(grr(k, kk, 0, drop2, rP));
+            ST(grr(k, 0, kk, 0, drop2, rP));
             ST(lp_update(Xs, ws.lpC.as<double>(), kk, lseg1(Xnl, kk), 1.0, 0.0));
             ST(lp_update(lseg1(AXl, k), ws.lpC.as<double>(), kk, lseg1(AXnl, kk), 1.0, 0.0));
             std::swap(Xl, Xnl);

@@ -5,6 +5,8 @@
 // memory (L2-resident) otherwise.
 #include <cfloat>
 
+#include <algorithm>
+
 #include "common.h"
 
 namespace se {
@@ -645,6 +647,36 @@ __global__ __launch_bounds__(256) void hl_init_kernel(int m, int k, const double
     }
 }
 
+// Elementwise helpers on small dense matrices.
+__global__ __launch_bounds__(256) void axpby_kernel(long long count, double alpha, const double* __restrict__ X,
+                                                    double beta, double* __restrict__ Y) {
+    for (long long e = (long long)blockIdx.x * 256 + threadIdx.x; e < count; e += (long long)gridDim.x * 256)
+        Y[e] = alpha * X[e] + beta * Y[e];
+}
+
+__global__ __launch_bounds__(256) void add_diag_kernel(int m, double* __restrict__ A, long long ld,
+                                                       double alpha) {
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i < m) A[(long long)i * ld + i] += alpha;
+}
+
+__global__ __launch_bounds__(256) void fill_kernel(int rows, int cols, double* __restrict__ A, long long ld,
+                                                   double v) {
+    const long long total = (long long)rows * cols;
+    for (long long e = (long long)blockIdx.x * 256 + threadIdx.x; e < total; e += (long long)gridDim.x * 256)
+        A[(e / cols) * ld + e % cols] = v;
+}
+
+// out[0] = sum of squares of the count entries of X (one workgroup, fixed order).
+__global__ __launch_bounds__(kSmall) void sumsq_kernel(long long count, const double* __restrict__ X,
+                                                       double* __restrict__ out) {
+    __shared__ double sh[kSWaves];
+    double s = 0.0;
+    for (long long e = threadIdx.x; e < count; e += kSmall) s = fma(X[e], X[e], s);
+    s = block_sum(s, sh);
+    if (threadIdx.x == 0) out[0] = s;
+}
+
 }  // namespace
 
 hipError_t launch_chol_drop(hipStream_t st, int a, const double* G, double* T, double* work,
@@ -653,6 +685,35 @@ hipError_t launch_chol_drop(hipStream_t st, int a, const double* G, double* T, d
     const size_t lds = ((size_t)a * a <= (size_t)kLdsDoubles) ? sizeof(double) * (size_t)a * a : 0;
     hipLaunchKernelGGL(chol_drop_kernel, dim3(1), dim3(kSmall), lds, st, a, G, T, work, info_i, info_d,
                        drop_tol2, ns_tol);
+    return hipGetLastError();
+}
+
+static int small_grid(long long count) {
+    long long g = (count + 255) / 256;
+    return (int)std::max(1LL, std::min(g, 4096LL));
+}
+
+hipError_t launch_axpby(hipStream_t st, long long count, double alpha, const double* X, double beta, double* Y) {
+    if (count <= 0) return hipSuccess;
+    hipLaunchKernelGGL(axpby_kernel, dim3(small_grid(count)), dim3(256), 0, st, count, alpha, X, beta, Y);
+    return hipGetLastError();
+}
+
+hipError_t launch_add_diag(hipStream_t st, int m, double* A, long long ld, double alpha) {
+    if (m <= 0) return hipSuccess;
+    hipLaunchKernelGGL(add_diag_kernel, dim3((m + 255) / 256), dim3(256), 0, st, m, A, ld, alpha);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill(hipStream_t st, int rows, int cols, double* A, long long ld, double v) {
+    if (rows <= 0 || cols <= 0) return hipSuccess;
+    hipLaunchKernelGGL(fill_kernel, dim3(small_grid((long long)rows * cols)), dim3(256), 0, st, rows, cols, A,
+                       ld, v);
+    return hipGetLastError();
+}
+
+hipError_t launch_sumsq(hipStream_t st, long long count, const double* X, double* out) {
+    hipLaunchKernelGGL(sumsq_kernel, dim3(1), dim3(kSmall), 0, st, count, X, out);
     return hipGetLastError();
 }
 
