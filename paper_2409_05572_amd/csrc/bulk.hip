@@ -64,10 +64,16 @@ __device__ __forceinline__ void spmm_row_pair(int ra, int rb, const int* __restr
                                               const double* __restrict__ X, long long ldx,
                                               double* __restrict__ Y, long long ldy, int c0,
                                               bool pair_col) {
-    const int ba = rowptr[ra], ea = rowptr[ra + 1];
-    const bool hasb = rb >= 0;
-    const int rbs = hasb ? rb : ra;
-    const int bb = hasb ? rowptr[rbs] : 0, eb = hasb ? rowptr[rbs + 1] : 0;
+    const int ba = rowptr[ra];
+    int ea = rowptr[ra + 1];
+    const bool heavy_a = ea - ba > kHeavyRow;  // computed by spmm_heavy_kernel
+    if (heavy_a) ea = ba;
+    const bool hasb0 = rb >= 0;
+    const int rbs = hasb0 ? rb : ra;
+    const int bb = hasb0 ? rowptr[rbs] : 0;
+    int eb = hasb0 ? rowptr[rbs + 1] : 0;
+    if (eb - bb > kHeavyRow) eb = bb;
+    const bool hasb = hasb0 && rowptr[rbs + 1] - bb <= kHeavyRow;
     double a0 = 0.0, a1 = 0.0, b0 = 0.0, b1 = 0.0;
     for (int pa = ba, pb = bb; pa < ea || pb < eb; pa += SB, pb += SB) {
         int ja[SB], jb[SB];
@@ -95,11 +101,64 @@ __device__ __forceinline__ void spmm_row_pair(int ra, int rb, const int* __restr
         }
     }
     if (pair_col) {
-        *reinterpret_cast<double2*>(Y + (long long)ra * ldy + c0) = make_double2(a0, a1);
+        if (!heavy_a) *reinterpret_cast<double2*>(Y + (long long)ra * ldy + c0) = make_double2(a0, a1);
         if (hasb) *reinterpret_cast<double2*>(Y + (long long)rb * ldy + c0) = make_double2(b0, b1);
     } else {
-        Y[(long long)ra * ldy + c0] = a0;
+        if (!heavy_a) Y[(long long)ra * ldy + c0] = a0;
         if (hasb) Y[(long long)rb * ldy + c0] = b0;
+    }
+}
+
+// One long row per workgroup: the kThreads / LPR lane groups take batches of
+// SB nonzeros in turn (same column mapping as spmm_kernel), and group 0 sums
+// the partial rows from LDS in a fixed order.
+template <int LPR>
+__global__ __launch_bounds__(kThreads) void spmm_heavy_kernel(const int* __restrict__ heavy,
+                                                              const int* __restrict__ rowptr,
+                                                              const int* __restrict__ col,
+                                                              const double* __restrict__ val,
+                                                              const double* __restrict__ X, long long ldx,
+                                                              double* __restrict__ Y, long long ldy, int w) {
+    constexpr int G = kThreads / LPR;
+    __shared__ double2 red[G][LPR];
+    const int row = heavy[blockIdx.x];
+    const int g = threadIdx.x / LPR, lane = threadIdx.x % LPR;
+    const int b = rowptr[row], e = rowptr[row + 1];
+    for (int cb = 0; cb < w; cb += 2 * LPR) {
+        const int c0 = cb + 2 * lane;
+        double a0 = 0.0, a1 = 0.0;
+        if (c0 < w) {
+            for (int p = b + g * SB; p < e; p += G * SB) {
+                int j[SB];
+                double v[SB];
+#pragma unroll
+                for (int u = 0; u < SB; ++u) {
+                    const bool ok = p + u < e;
+                    j[u] = ok ? col[p + u] : row;
+                    v[u] = ok ? val[p + u] : 0.0;
+                }
+                double2 x[SB];
+#pragma unroll
+                for (int u = 0; u < SB; ++u) x[u] = *reinterpret_cast<const double2*>(X + (long long)j[u] * ldx + c0);
+#pragma unroll
+                for (int u = 0; u < SB; ++u) {
+                    a0 = fma(v[u], x[u].x, a0);
+                    a1 = fma(v[u], x[u].y, a1);
+                }
+            }
+        }
+        red[g][lane] = make_double2(a0, a1);
+        __syncthreads();
+        if (g == 0 && c0 < w) {
+            double s0 = 0.0, s1 = 0.0;
+            for (int q = 0; q < G; ++q) {
+                s0 += red[q][lane].x;
+                s1 += red[q][lane].y;
+            }
+            Y[(long long)row * ldy + c0] = s0;
+            if (c0 + 1 < w) Y[(long long)row * ldy + c0 + 1] = s1;
+        }
+        __syncthreads();
     }
 }
 
@@ -127,11 +186,15 @@ __global__ __launch_bounds__(kThreads) void spmm_kernel(int n, const int* __rest
 
 template <int LPR>
 hipError_t spmm_launch(hipStream_t st, int n, const int* rowptr, const int* col, const double* val,
-                       const double* X, long long ldx, double* Y, long long ldy, int w) {
+                       const double* X, long long ldx, double* Y, long long ldy, int w, const int* heavy,
+                       int n_heavy) {
     constexpr int RPB = (kThreads / LPR) * SPR;
     const int grid = (n + RPB - 1) / RPB;
     hipLaunchKernelGGL(spmm_kernel<LPR>, dim3(grid), dim3(kThreads), 0, st, n, rowptr, col, val, X,
                        ldx, Y, ldy, w);
+    if (n_heavy > 0)
+        hipLaunchKernelGGL(spmm_heavy_kernel<LPR>, dim3(n_heavy), dim3(kThreads), 0, st, heavy, rowptr, col,
+                           val, X, ldx, Y, ldy, w);
     return hipGetLastError();
 }
 
@@ -604,16 +667,19 @@ void update_launch(hipStream_t st, long long n, const Segs& U, int K, const doub
 
 // ---------------------------------------------------------------------------
 hipError_t launch_spmm(hipStream_t st, int n, const int* rowptr, const int* col, const double* val,
-                       const double* X, long long ldx, double* Y, long long ldy, int w) {
+                       const double* X, long long ldx, double* Y, long long ldy, int w, const int* heavy,
+                       int n_heavy) {
     if (n <= 0 || w <= 0) return hipSuccess;
     const int half = (w + 1) / 2;
-    if (half <= 1) return spmm_launch<1>(st, n, rowptr, col, val, X, ldx, Y, ldy, w);
-    if (half <= 2) return spmm_launch<2>(st, n, rowptr, col, val, X, ldx, Y, ldy, w);
-    if (half <= 4) return spmm_launch<4>(st, n, rowptr, col, val, X, ldx, Y, ldy, w);
-    if (half <= 8) return spmm_launch<8>(st, n, rowptr, col, val, X, ldx, Y, ldy, w);
-    if (half <= 16) return spmm_launch<16>(st, n, rowptr, col, val, X, ldx, Y, ldy, w);
-    if (half <= 32) return spmm_launch<32>(st, n, rowptr, col, val, X, ldx, Y, ldy, w);
-    return spmm_launch<64>(st, n, rowptr, col, val, X, ldx, Y, ldy, w);
+#define SE_SPMM(L) return spmm_launch<L>(st, n, rowptr, col, val, X, ldx, Y, ldy, w, heavy, n_heavy)
+    if (half <= 1) SE_SPMM(1);
+    if (half <= 2) SE_SPMM(2);
+    if (half <= 4) SE_SPMM(4);
+    if (half <= 8) SE_SPMM(8);
+    if (half <= 16) SE_SPMM(16);
+    if (half <= 32) SE_SPMM(32);
+    SE_SPMM(64);
+#undef SE_SPMM
 }
 
 hipError_t launch_resid_norms(hipStream_t st, long long n, const double* X, const double* AX,

@@ -116,10 +116,16 @@ __device__ __forceinline__ void spmm_rows(int ra, int rb, const int* __restrict_
                                           const int* __restrict__ col, const float* __restrict__ val,
                                           const T* __restrict__ X, long long ldx, T* __restrict__ Y,
                                           long long ldy, int c0, int w) {
-    const int ba = rowptr[ra], ea = rowptr[ra + 1];
-    const bool hasb = rb >= 0;
-    const int rbs = hasb ? rb : ra;
-    const int bb = hasb ? rowptr[rbs] : 0, eb = hasb ? rowptr[rbs + 1] : 0;
+    const int ba = rowptr[ra];
+    int ea = rowptr[ra + 1];
+    const bool heavy_a = ea - ba > kHeavyRow;  // computed by spmm_lp_heavy_kernel
+    if (heavy_a) ea = ba;
+    const bool hasb0 = rb >= 0;
+    const int rbs = hasb0 ? rb : ra;
+    const int bb = hasb0 ? rowptr[rbs] : 0;
+    int eb = hasb0 ? rowptr[rbs + 1] : 0;
+    if (eb - bb > kHeavyRow) eb = bb;
+    const bool hasb = hasb0 && rowptr[rbs + 1] - bb <= kHeavyRow;
     float a[4] = {0.f, 0.f, 0.f, 0.f}, b[4] = {0.f, 0.f, 0.f, 0.f};
     for (int pa = ba, pb = bb; pa < ea || pb < eb; pa += SB, pb += SB) {
         int ja[SB], jb[SB];
@@ -146,8 +152,60 @@ __device__ __forceinline__ void spmm_rows(int ra, int rb, const int* __restrict_
                 b[q] = fmaf(vb[u], xb[u][q], b[q]);
             }
     }
-    store_cols(Y + (long long)ra * ldy + c0, a, c0, w);
+    if (!heavy_a) store_cols(Y + (long long)ra * ldy + c0, a, c0, w);
     if (hasb) store_cols(Y + (long long)rb * ldy + c0, b, c0, w);
+}
+
+// One long row per workgroup (see the FP64 heavy-row kernel): lane groups
+// take batches of SB nonzeros in turn, group 0 sums the partials in order.
+template <class T, int LPR>
+__global__ __launch_bounds__(kThreads) void spmm_lp_heavy_kernel(const int* __restrict__ heavy,
+                                                                 const int* __restrict__ rowptr,
+                                                                 const int* __restrict__ col,
+                                                                 const float* __restrict__ val,
+                                                                 const T* __restrict__ X, long long ldx,
+                                                                 T* __restrict__ Y, long long ldy, int w) {
+    constexpr int G = kThreads / LPR;
+    __shared__ float4 red[G][LPR];
+    const int row = heavy[blockIdx.x];
+    const int g = threadIdx.x / LPR, lane = threadIdx.x % LPR;
+    const int b = rowptr[row], e = rowptr[row + 1];
+    for (int cb = 0; cb < w; cb += 4 * LPR) {
+        const int c0 = cb + 4 * lane;
+        float acc[4] = {0.f, 0.f, 0.f, 0.f};
+        if (c0 < w) {
+            for (int p = b + g * SB; p < e; p += G * SB) {
+                int j[SB];
+                float v[SB];
+#pragma unroll
+                for (int u = 0; u < SB; ++u) {
+                    const bool ok = p + u < e;
+                    j[u] = ok ? col[p + u] : row;
+                    v[u] = ok ? val[p + u] : 0.f;
+                }
+                float x[SB][4];
+#pragma unroll
+                for (int u = 0; u < SB; ++u) ld4(X + (long long)j[u] * ldx + c0, x[u]);
+#pragma unroll
+                for (int u = 0; u < SB; ++u)
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) acc[q] = fmaf(v[u], x[u][q], acc[q]);
+            }
+        }
+        red[g][lane] = make_float4(acc[0], acc[1], acc[2], acc[3]);
+        __syncthreads();
+        if (g == 0 && c0 < w) {
+            float s[4] = {0.f, 0.f, 0.f, 0.f};
+            for (int q = 0; q < G; ++q) {
+                s[0] += red[q][lane].x;
+                s[1] += red[q][lane].y;
+                s[2] += red[q][lane].z;
+                s[3] += red[q][lane].w;
+            }
+            store_cols(Y + (long long)row * ldy + c0, s, c0, w);
+        }
+        __syncthreads();
+    }
 }
 
 template <class T, int LPR>
@@ -170,11 +228,15 @@ __global__ __launch_bounds__(kThreads) void spmm_lp_kernel(int n, const int* __r
 
 template <class T, int LPR>
 hipError_t spmm_lp_launch(hipStream_t st, int n, const int* rowptr, const int* col, const float* val,
-                          const T* X, long long ldx, T* Y, long long ldy, int w) {
+                          const T* X, long long ldx, T* Y, long long ldy, int w, const int* heavy,
+                          int n_heavy) {
     constexpr int RPB = (kThreads / LPR) * SPR;
     const int grid = (n + RPB - 1) / RPB;
     hipLaunchKernelGGL((spmm_lp_kernel<T, LPR>), dim3(grid), dim3(kThreads), 0, st, n, rowptr, col, val, X,
                        ldx, Y, ldy, w);
+    if (n_heavy > 0)
+        hipLaunchKernelGGL((spmm_lp_heavy_kernel<T, LPR>), dim3(n_heavy), dim3(kThreads), 0, st, heavy, rowptr,
+                           col, val, X, ldx, Y, ldy, w);
     return hipGetLastError();
 }
 
@@ -610,17 +672,20 @@ bool ld_ok(long long ld, int w) { return ld % 8 == 0 && ld >= (long long)((w + 7
 // ---------------------------------------------------------------------------
 template <class T>
 hipError_t launch_spmm_lp(hipStream_t st, int n, const int* rowptr, const int* col, const float* val,
-                          const T* X, long long ldx, T* Y, long long ldy, int w) {
+                          const T* X, long long ldx, T* Y, long long ldy, int w, const int* heavy,
+                          int n_heavy) {
     if (n <= 0 || w <= 0) return hipSuccess;
     if (!ld_ok(ldx, w) || !ld_ok(ldy, w)) return hipErrorInvalidValue;
     const int quads = (w + 3) / 4;
-    if (quads <= 1) return spmm_lp_launch<T, 1>(st, n, rowptr, col, val, X, ldx, Y, ldy, w);
-    if (quads <= 2) return spmm_lp_launch<T, 2>(st, n, rowptr, col, val, X, ldx, Y, ldy, w);
-    if (quads <= 4) return spmm_lp_launch<T, 4>(st, n, rowptr, col, val, X, ldx, Y, ldy, w);
-    if (quads <= 8) return spmm_lp_launch<T, 8>(st, n, rowptr, col, val, X, ldx, Y, ldy, w);
-    if (quads <= 16) return spmm_lp_launch<T, 16>(st, n, rowptr, col, val, X, ldx, Y, ldy, w);
-    if (quads <= 32) return spmm_lp_launch<T, 32>(st, n, rowptr, col, val, X, ldx, Y, ldy, w);
-    return spmm_lp_launch<T, 64>(st, n, rowptr, col, val, X, ldx, Y, ldy, w);
+#define SE_SPMM(L) return spmm_lp_launch<T, L>(st, n, rowptr, col, val, X, ldx, Y, ldy, w, heavy, n_heavy)
+    if (quads <= 1) SE_SPMM(1);
+    if (quads <= 2) SE_SPMM(2);
+    if (quads <= 4) SE_SPMM(4);
+    if (quads <= 8) SE_SPMM(8);
+    if (quads <= 16) SE_SPMM(16);
+    if (quads <= 32) SE_SPMM(32);
+    SE_SPMM(64);
+#undef SE_SPMM
 }
 
 template <class T>
@@ -732,7 +797,7 @@ hipError_t launch_f64_to_f32(hipStream_t st, long long count, const double* src,
 
 #define SE_LP_INSTANTIATE(T)                                                                            \
     template hipError_t launch_spmm_lp<T>(hipStream_t, int, const int*, const int*, const float*, const T*, \
-                                          long long, T*, long long, int);                                \
+                                          long long, T*, long long, int, const int*, int);               \
     template hipError_t launch_resid_norms_lp<T>(hipStream_t, long long, const T*, const T*, long long, int, \
                                                  const double*, double*, double*);                        \
     template hipError_t launch_form_w_lp<T>(hipStream_t, long long, const T*, const T*, long long,         \

@@ -148,6 +148,9 @@ se_status se_matrix_create_csr(se_ctx* ctx, int64_t n, int64_t nnz, const int64_
     }
     std::vector<int> rp32(n + 1);
     for (int64_t i = 0; i <= n; ++i) rp32[i] = (int)rp64[i];
+    std::vector<int> heavy;
+    for (int64_t i = 0; i < n; ++i)
+        if (rp64[i + 1] - rp64[i] > se::kHeavyRow) heavy.push_back((int)i);
     se_matrix* m = new (std::nothrow) se_matrix();
     if (!m) return SE_ERR_OOM;
     m->ctx = ctx;
@@ -161,6 +164,12 @@ se_status se_matrix_create_csr(se_ctx* ctx, int64_t n, int64_t nnz, const int64_
     if (e == hipSuccess) e = hipMemcpy(m->rowptr, rp32.data(), sizeof(int) * (n + 1), hipMemcpyHostToDevice);
     if (e == hipSuccess && nnz > 0) e = hipMemcpy(m->col, colind, sizeof(int) * nnz, kind);
     if (e == hipSuccess && nnz > 0) e = hipMemcpy(m->val, val, sizeof(double) * nnz, kind);
+    if (e == hipSuccess && !heavy.empty()) {
+        e = hipMalloc(&m->heavy, sizeof(int) * heavy.size());
+        if (e == hipSuccess)
+            e = hipMemcpy(m->heavy, heavy.data(), sizeof(int) * heavy.size(), hipMemcpyHostToDevice);
+        m->n_heavy = (int)heavy.size();
+    }
     if (e != hipSuccess) {
         se_matrix_destroy(m);
         return hip_fail(ctx, e);
@@ -174,6 +183,7 @@ void se_matrix_destroy(se_matrix* m) {
     if (m->ctx) (void)hipSetDevice(m->ctx->device);
     if (m->rowptr) (void)hipFree(m->rowptr);
     if (m->val32) (void)hipFree(m->val32);
+    if (m->heavy) (void)hipFree(m->heavy);
     if (m->col) (void)hipFree(m->col);
     if (m->val) (void)hipFree(m->val);
     delete m;
@@ -214,7 +224,8 @@ se_status se_op_spmm(se_ctx* ctx, const se_matrix* A, const double* X, int64_t l
         return SE_ERR_INVALID_ARG;
     if (!aligned16(X) || !aligned16(Y)) return SE_ERR_INVALID_ARG;
     CAPI_HC(ctx, hipSetDevice(ctx->device));
-    CAPI_HC(ctx, se::launch_spmm(ctx->stream, (int)A->n, A->rowptr, A->col, A->val, X, ldx, Y, ldy, w));
+    CAPI_HC(ctx, se::launch_spmm(ctx->stream, (int)A->n, A->rowptr, A->col, A->val, X, ldx, Y, ldy, w, A->heavy,
+                                 A->n_heavy));
     return SE_OK;
 }
 
@@ -266,11 +277,12 @@ se_status se_op_spmm_lp(se_ctx* ctx, int32_t precision, const se_matrix* A, cons
     if (precision == SE_FP32_MIXED)
         CAPI_HC(ctx, se::launch_spmm_lp<float>(ctx->stream, (int)A->n, A->rowptr, A->col, A->val32,
                                                static_cast<const float*>(X), ldx, static_cast<float*>(Y),
-                                               ldy, w));
+                                               ldy, w, A->heavy, A->n_heavy));
     else
         CAPI_HC(ctx, se::launch_spmm_lp<se::bf16_t>(ctx->stream, (int)A->n, A->rowptr, A->col, A->val32,
                                                      static_cast<const se::bf16_t*>(X), ldx,
-                                                     static_cast<se::bf16_t*>(Y), ldy, w));
+                                                     static_cast<se::bf16_t*>(Y), ldy, w, A->heavy,
+                                                     A->n_heavy));
     return SE_OK;
 }
 

@@ -70,9 +70,15 @@ inline int segs_width(const SegsT<T>& s) {
 }
 
 // ---- bulk kernels (bulk.hip) ----
+// Rows with more than kHeavyRow nonzeros (power-law graphs) are listed in
+// `heavy` and computed by one workgroup each; the row-per-lane-group kernel
+// skips them.
+constexpr int kHeavyRow = 64;
+
 // Y[:, 0:w] = A X[:, 0:w] for CSR A with int32 row offsets.
 hipError_t launch_spmm(hipStream_t st, int n, const int* rowptr, const int* col, const double* val,
-                       const double* X, long long ldx, double* Y, long long ldy, int w);
+                       const double* X, long long ldx, double* Y, long long ldy, int w,
+                       const int* heavy, int n_heavy);
 
 // Per-column sums over rows of (AX - lam X)^2 and X^2 for columns [0, k):
 // out[c] = ||r_c||^2, out[k + c] = ||x_c||^2. part is scratch of
@@ -134,7 +140,8 @@ hipError_t launch_gram_reduce(hipStream_t st, int mu, int mv, int nchunks, int s
 // multiples of 8 and at least the width rounded up to 8.
 template <class T>
 hipError_t launch_spmm_lp(hipStream_t st, int n, const int* rowptr, const int* col, const float* val,
-                          const T* X, long long ldx, T* Y, long long ldy, int w);
+                          const T* X, long long ldx, T* Y, long long ldy, int w, const int* heavy,
+                          int n_heavy);
 template <class T>
 hipError_t launch_resid_norms_lp(hipStream_t st, long long n, const T* X, const T* AX, long long ld,
                                  int k, const double* lam, double* part, double* out);

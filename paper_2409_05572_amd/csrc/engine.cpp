@@ -217,7 +217,7 @@ struct Solver {
     // ------------------------------------------------------------ kernels --
     se_status spmm(const double* Xs, double* Ys, int w) {
         ST(tic());
-        HC(launch_spmm(st, (int)n, A->rowptr, A->col, A->val, Xs, ld, Ys, ld, w));
+        HC(launch_spmm(st, (int)n, A->rowptr, A->col, A->val, Xs, ld, Ys, ld, w, A->heavy, A->n_heavy));
         return toc(SE_K_SPMM, 12.0 * A->nnz + 4.0 * (n + 1) + 16.0 * n * w, 2.0 * A->nnz * w);
     }
     se_status gram(const Segs& U, const Segs& V, int sym, double* C) {
@@ -729,7 +729,7 @@ struct Solver {
     template <class T>
     se_status lp_spmm(const T* Xs, T* Ys, int w) {
         ST(tic());
-        HC(launch_spmm_lp<T>(st, (int)n, A->rowptr, A->col, A->val32, Xs, ld, Ys, ld, w));
+        HC(launch_spmm_lp<T>(st, (int)n, A->rowptr, A->col, A->val32, Xs, ld, Ys, ld, w, A->heavy, A->n_heavy));
         return toc(SE_K_SPMM, 8.0 * A->nnz + 4.0 * (n + 1) + 2.0 * sizeof(T) * n * w, 2.0 * A->nnz * w);
     }
     template <class T>

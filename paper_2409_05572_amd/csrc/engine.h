@@ -147,6 +147,8 @@ struct se_matrix {
     int* col = nullptr;
     double* val = nullptr;
     mutable float* val32 = nullptr;  // FP32 copy for the mixed-precision phase, made on first use
+    int* heavy = nullptr;  // rows with more than kHeavyRow nonzeros (one workgroup each in SpMM)
+    int n_heavy = 0;
     double anorm = 0.0;
 };
 

@@ -68,6 +68,26 @@ def test_spmm_empty_rows_and_hub_row(ctx):
     assert np.allclose(Y, ref, rtol=1e-13, atol=1e-12)
 
 
+@pytest.mark.parametrize("w", [1, 5, 48, 69, 130])
+def test_spmm_power_law_rows(ctx, w):
+    """Normalized Laplacian of a Chung-Lu graph: rows from a few to hundreds of
+    nonzeros, the long ones computed one workgroup per row."""
+    from paper_2409_05572_amd import api
+
+    A = W.chung_lu_laplacian(20000, 16.0, 2.5, 11)
+    deg = np.diff(A.rowptr)
+    assert deg.max() > 64 and (deg > 64).sum() >= 50  # both row kernels take part
+    M = api.Matrix.from_csr(ctx, A)
+    ld = w + (w % 2)
+    X = _row_major(A.n, w, ld, w + 1)
+    Yd = to_dev(np.full((A.n, ld), np.nan))
+    api.spmm(ctx, M, to_dev(X), Yd, w)
+    Y = Yd.cpu().numpy()
+    ref = OS._apply(A.to_scipy(), X[:, :w])
+    bound = 1e-15 * (deg.max() + 2) * (abs(A.to_scipy()) @ np.abs(X[:, :w]))
+    assert np.all(np.abs(Y[:, :w] - ref) <= bound + 1e-300)
+
+
 def test_spmm_full_config2_sampled_rows(ctx):
     """3-D 128^3 Laplacian, 96 columns: the launch the solver uses, checked on
     2000 sampled rows against the oracle's sparse product."""

@@ -74,6 +74,25 @@ def test_spmm_lp_matches_product_of_stored_values(ctx, fmt, w):
 
 
 @pytest.mark.parametrize("fmt", ["fp32", "bf16"])
+@pytest.mark.parametrize("w", [3, 48, 130])
+def test_spmm_lp_power_law_rows(ctx, fmt, w):
+    import torch
+
+    from paper_2409_05572_amd import api
+
+    A = W.chung_lu_laplacian(20000, 16.0, 2.5, 11)
+    deg = np.diff(A.rowptr)
+    rng = np.random.default_rng(w)
+    X, Xs = _block(rng.standard_normal((A.n, w)), fmt)
+    Y = torch.zeros_like(X)
+    api.spmm_lp(ctx, api.Matrix.from_csr(ctx, A), X, Y, w)
+    A32 = A.to_scipy().astype(np.float32).astype(np.float64)
+    ref = A32 @ Xs
+    bound = (deg.max() + 2) * U32 * (abs(A32) @ abs(Xs)) + UNIT[fmt] * abs(ref) + 1e-300
+    assert np.all(np.abs(_read(Y, w) - ref) <= bound)
+
+
+@pytest.mark.parametrize("fmt", ["fp32", "bf16"])
 @pytest.mark.parametrize("n,mu,mv", [(1000, 1, 1), (1000, 17, 5), (20001, 96, 96), (20001, 150, 250),
                                      (70001, 250, 250), (5000, 750, 33)])
 def test_gram_lp_within_fp32_accumulation_bound(ctx, fmt, n, mu, mv):
