@@ -104,7 +104,7 @@ typedef struct se_params {
     double sigma;        /* SI shift, must bound lambda_max from above; 0 = ||A|| */
     double time_limit_s; /* wall-clock cap; <= 0 = none */
     double r_switch;     /* mixed precision: leave the low-precision phase once r(j) <= r_switch
-                            (or r(j) stops improving); 0 = 1e-6 (FP32), 1e-3 (BF16) */
+                            (or r(j) stops improving); 0 = 1e-5 (FP32), 1e-3 (BF16) */
     uint64_t seed;       /* reserved for generated starting blocks */
     double* history;     /* optional host buffer of history_cap x SE_HISTORY_FIELDS doubles */
     int32_t history_cap; /* rows available in history */

@@ -476,7 +476,9 @@ struct Solver {
     // ------------------------------------------------------------- LOBPCG --
     // X0: FP64 column-major start block; k0 >= 0: the X panel already holds
     // k0 start columns (row-major), e.g. from the low-precision phase.
-    se_status lobpcg(const double* X0, int k0 = -1) {
+    // p0 > 0: the P panel holds p0 search directions to continue with (they
+    // are orthogonalized against the new X and multiplied by A here).
+    se_status lobpcg(const double* X0, int k0 = -1, int p0 = 0) {
         ST(alloc_panels(14));
         ST(alloc_small(3 * nb));
         if (k0 < 0) ST(load_x0(X0));
@@ -486,6 +488,16 @@ struct Solver {
         ST(spmm(X, AX, k));
         ST(rr_plain(k));
         int pw = 0;  // width of P
+        if (p0 > 0) {
+            const Segs Xs = seg1(X, k);
+            for (int pass = 0; pass < 2; ++pass) {
+                ST(gram(Xs, seg1(P, p0), 0, ws.G.as<double>()));
+                ST(update(Xs, ws.G.as<double>(), p0, seg1(P, p0), -1.0, 1.0));
+            }
+            ST(cholqr(P, p0, nullptr, nullptr, &Xs));
+            if (p0 > 0) ST(spmm(P, AP, p0));
+            pw = p0;
+        }
         bool have_drop = false;
         int dx = 0, dp = 0;
         std::vector<double> stop, paper, lam;
@@ -685,9 +697,10 @@ struct Solver {
     // panels and does its arithmetic in FP32 with FP64 reductions; all small
     // dense work stays FP64. Its basis is orthonormal only to the storage
     // precision, so the Rayleigh-Ritz step solves A_p z = theta M z with
-    // M = S^T S (grr). Once r(j) <= r_switch, or r(j) has not improved for
-    // kStall iterations, the current X (with X_drop when shrunk) is widened to
-    // FP64 and the FP64 solver continues from it with P reset.
+    // M = S^T S (grr). Once r(j) <= r_switch, r(j) rises above ten times its
+    // best value (the low-precision iteration has reached its floor) or has
+    // not improved for kStall iterations, the current X (with X_drop when
+    // shrunk) and P are widened to FP64 and the FP64 solver continues.
     static constexpr int kStall = 15;
     void* lp[kNumLpPanels] = {};
 
@@ -710,6 +723,13 @@ struct Solver {
     static double unit_roundoff() {
         return sizeof(T) == 4 ? 5.9604644775390625e-8 : 3.90625e-3;
     }
+    // Drop threshold of the whitening (scaled Cholesky pivots of M or of its
+    // Schur complement). The Gram matrices of the stored panels are exact
+    // products rounded only by FP32 accumulation (u32 = 2^-24; BF16 products
+    // are exact in FP32), and a pivot delta^2 carries a relative error of
+    // about u32 / delta^2, so pivots below 450 u32 are dropped: the FP64
+    // path's ratio (1e-13 ~ 450 u64).
+    static constexpr double kLpDrop2 = 450.0 * 5.9604644775390625e-8;
 
     template <class T>
     se_status lp_alloc() {
@@ -884,17 +904,19 @@ struct Solver {
 
     double r_switch_value(double u) const {
         if (p.r_switch > 0.0) return p.r_switch;
-        return u < 1e-6 ? 1e-6 : 1e-3;
+        return u < 1e-6 ? 1e-5 : 1e-3;
     }
 
-    // Widens the low-precision X (and X_drop) into the FP64 X panel; returns
-    // the number of start columns.
+    // Widens the low-precision X (and X_drop) into the FP64 X panel and the
+    // search directions P into the FP64 P panel; returns the column counts.
     template <class T>
-    se_status lp_to_f64(const T* Xl, int k, const T* Sdl, int dx, int& k0) {
+    se_status lp_to_f64(const T* Xl, int k, const T* Sdl, int dx, const T* Pl, int pw, int& k0, int& p0) {
         ST(alloc_panels(14));
         HC(launch_rows_lp_to_f64<T>(st, n, k, Xl, ld, X, ld));
         if (dx > 0) HC(launch_rows_lp_to_f64<T>(st, n, dx, Sdl, ld, X + k, ld));
+        if (pw > 0) HC(launch_rows_lp_to_f64<T>(st, n, pw, Pl, ld, P, ld));
         k0 = k + dx;
+        p0 = pw;
         return SE_OK;
     }
 
@@ -903,7 +925,7 @@ struct Solver {
     // R(:, all) and is not orthogonalized separately: the Cholesky factor of
     // M removes its dependence on [X, P] and scales it.
     template <class T>
-    se_status lobpcg_lp(const double* X0, int& k0) {
+    se_status lobpcg_lp(const double* X0, int& k0, int& p0) {
         ST(alloc_panels(14));
         ST(alloc_small(3 * nb));
         ST(lp_alloc<T>());
@@ -912,7 +934,7 @@ struct Solver {
         T *Xl = L[0], *Pl = L[1], *Wl = L[2], *AXl = L[3], *APl = L[4], *AWl = L[5];
         T *Xnl = L[6], *Pnl = L[7], *AXnl = L[8], *APnl = L[9], *Sdl = L[10], *ASdl = L[11];
         const double u = unit_roundoff<T>();
-        const double drop2 = 100.0 * u * u;
+        const double drop2 = kLpDrop2;
         const double rsw = r_switch_value(u);
         if (p.ptr_mode == SE_PTR_HOST) {
             HC(hipMemcpyAsync(T1, X0, sizeof(double) * (size_t)n * nb, hipMemcpyHostToDevice, st));
@@ -963,7 +985,7 @@ struct Solver {
                 lp_done = true;
                 break;
             }
-            if (r <= rsw || j - j_best >= kStall || out_of_time()) break;
+            if (r <= rsw || r > 10.0 * best || j - j_best >= kStall || out_of_time()) break;
             const bool want_expand = ctl.ifexpand(j);
             int flags = 4;
 
@@ -1038,11 +1060,10 @@ struct Solver {
             }
             amend_flags(flags);
         }
-        if (lp_done) {  // X leaves in FP64 with its Ritz values (finish re-checks)
-            ST(lp_to_f64(Xl, k, Sdl, 0, k0));
-            return SE_OK;
-        }
-        return lp_to_f64(Xl, k, Sdl, have_drop ? std::min(dx, nb - k) : 0, k0);
+        if (lp_done)  // X leaves in FP64 with its Ritz values (finish re-checks)
+            return lp_to_f64(Xl, k, Sdl, 0, Pl, 0, k0, p0);
+        const int dxk = have_drop ? std::min(dx, nb - k) : 0;
+        return lp_to_f64(Xl, k, Sdl, dxk, Pl, std::min(pw, ld), k0, p0);
     }
 
     // Subspace iteration (Algorithm 1) with shrink-and-expand on
@@ -1050,6 +1071,7 @@ struct Solver {
     // then the generalized Rayleigh-Ritz step on span(Y).
     template <class T>
     se_status si_lp(const double* X0, int& k0) {
+        int p0 = 0;
         ST(alloc_panels(14));
         ST(alloc_small(nb));
         ST(lp_alloc<T>());
@@ -1059,7 +1081,7 @@ struct Solver {
         T* AXnl = static_cast<T*>(lp[8]);
         T* Sdl = static_cast<T*>(lp[10]);
         const double u = unit_roundoff<T>();
-        const double drop2 = 100.0 * u * u;
+        const double drop2 = kLpDrop2;
         const double rsw = r_switch_value(u);
         const double sigma = (p.sigma > 0.0) ? p.sigma : A->anorm;
         if (p.ptr_mode == SE_PTR_HOST) {
@@ -1112,7 +1134,7 @@ struct Solver {
                 lp_done = true;
                 break;
             }
-            if (r <= rsw || j - j_best >= kStall || out_of_time()) break;
+            if (r <= rsw || r > 10.0 * best || j - j_best >= kStall || out_of_time()) break;
             int flags = 4;
             const bool want_expand = ctl.ifexpand(j);
             ST(tic());
@@ -1138,8 +1160,8 @@ struct Solver {
             }
             amend_flags(flags);
         }
-        if (lp_done) return lp_to_f64(Xl, k, Sdl, 0, k0);
-        return lp_to_f64(Xl, k, Sdl, have_drop ? std::min(dx, nb - k) : 0, k0);
+        if (lp_done) return lp_to_f64(Xl, k, Sdl, 0, Xl, 0, k0, p0);
+        return lp_to_f64(Xl, k, Sdl, have_drop ? std::min(dx, nb - k) : 0, Xl, 0, k0, p0);
     }
 
     // Mixed precision: the low-precision phase, then the FP64 solver from its
@@ -1147,8 +1169,8 @@ struct Solver {
     template <class T>
     se_status mixed(const double* X0) {
         const Strategy ctl0 = ctl;
-        int k0 = 0;
-        ST(p.solver == SE_SI ? si_lp<T>(X0, k0) : lobpcg_lp<T>(X0, k0));
+        int k0 = 0, p0 = 0;
+        ST(p.solver == SE_SI ? si_lp<T>(X0, k0) : lobpcg_lp<T>(X0, k0, p0));
         if (lp_done) {
             converged = true;
             return SE_OK;
@@ -1156,7 +1178,7 @@ struct Solver {
         if (k0 < n_ev) return SE_ERR_BREAKDOWN;
         ctl = ctl0;
         j_off = lp_iters;
-        return p.solver == SE_SI ? si(nullptr, k0) : lobpcg(nullptr, k0);
+        return p.solver == SE_SI ? si(nullptr, k0) : lobpcg(nullptr, k0, p0);
     }
 
     // Fresh residual of the returned pairs, then write V and lambda.

@@ -170,7 +170,7 @@ def test_config1_mixed_matches_closed_form(ctx, fmt, solver):
     assert np.all(lp_rows[: info.lp_iterations]) and not lp_rows[info.lp_iterations:].any()
     # the low-precision phase got r(j) down to r_switch or stalled there
     r_lp = h[lp_rows, 1]
-    assert r_lp.min() <= (1e-6 if fmt == "fp32" else 1e-3) * 100
+    assert r_lp.min() <= (1e-5 if fmt == "fp32" else 1e-3) * 100
 
 
 @pytest.mark.parametrize("fmt,strategy", [("fp32", "fix"), ("fp32", "slopek"), ("bf16", "fix")])
