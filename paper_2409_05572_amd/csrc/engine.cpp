@@ -697,10 +697,11 @@ struct Solver {
     // panels and does its arithmetic in FP32 with FP64 reductions; all small
     // dense work stays FP64. Its basis is orthonormal only to the storage
     // precision, so the Rayleigh-Ritz step solves A_p z = theta M z with
-    // M = S^T S (grr). Once r(j) <= r_switch, r(j) rises above ten times its
-    // best value (the low-precision iteration has reached its floor) or has
-    // not improved for kStall iterations, the current X (with X_drop when
-    // shrunk) and P are widened to FP64 and the FP64 solver continues.
+    // M = S^T S (grr). Once r(j) <= r_switch, or - with the best r(j) within
+    // 100 r_switch - r(j) rises above ten times its best value (the
+    // low-precision iteration has reached its floor) or has not improved for
+    // kStall iterations, the current X (with X_drop when shrunk) and P are
+    // widened to FP64 and the FP64 solver continues.
     static constexpr int kStall = 15;
     void* lp[kNumLpPanels] = {};
 
@@ -985,7 +986,9 @@ struct Solver {
                 lp_done = true;
                 break;
             }
-            if (r <= rsw || r > 10.0 * best || j - j_best >= kStall || out_of_time()) break;
+            const bool near_floor = best <= 100.0 * rsw;  // early iterations may rise and stall
+            if (r <= rsw || (near_floor && (r > 10.0 * best || j - j_best >= kStall)) || out_of_time())
+                break;
             const bool want_expand = ctl.ifexpand(j);
             int flags = 4;
 
@@ -1134,7 +1137,9 @@ struct Solver {
                 lp_done = true;
                 break;
             }
-            if (r <= rsw || r > 10.0 * best || j - j_best >= kStall || out_of_time()) break;
+            const bool near_floor = best <= 100.0 * rsw;  // early iterations may rise and stall
+            if (r <= rsw || (near_floor && (r > 10.0 * best || j - j_best >= kStall)) || out_of_time())
+                break;
             int flags = 4;
             const bool want_expand = ctl.ifexpand(j);
             ST(tic());
