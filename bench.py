@@ -31,6 +31,7 @@ WORKLOADS = {
     "laplace3d": dict(grid=128, n_ev=64, n_extra=32, x0_seed=202),
     "anderson": dict(grid=100, n_ev=200, n_extra=50, x0_seed=203),
     "chunglu": dict(nodes=500000, n_ev=32, n_extra=16, x0_seed=204),
+    "serving": dict(x0_seed=305),
 }
 
 
@@ -51,6 +52,10 @@ def parse():
     ap.add_argument("--no-fixed", action="store_true", help="skip the fixed-block comparison")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
+    ap.add_argument("--requests", type=int, default=200, help="serving: measured requests")
+    ap.add_argument("--pilot", type=int, default=20, help="serving: warm-up requests (closed loop)")
+    ap.add_argument("--load", type=float, default=0.7, help="serving: arrival rate / saturated rate")
+    ap.add_argument("--slots", type=int, default=4, help="serving: concurrent solves")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run one plain 1 GiB device copy first (the reference for HBM counters)")
     args = ap.parse_args()
@@ -85,6 +90,10 @@ def main():
 
     def log(msg):
         print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+    if args.workload == "serving":
+        print(json.dumps(serving(args, log)), flush=True)
+        return
 
     t = time.time()
     A, wname = build_matrix(args)
@@ -282,6 +291,95 @@ def cpu_baseline(A, X0, args, gpu_iters, log):
                       f"{el:.1f}s; time-to-solution extrapolated as {per_iter:.2f}s/iteration x "
                       f"{gpu_iters} iterations (GPU count)",
             "extrapolated": True}
+
+
+def serving(args, log):
+    """Continuous-batching service: a stream of 2-D / 3-D Laplacians with a
+    random potential (n log-uniform in [1e4, 1e6], n_ev ~ U{4..64}); a
+    closed-loop pilot on the warm-up requests measures the saturated rate,
+    then the measured requests arrive as a Poisson process at args.load times
+    that rate. Latency = arrival to completion."""
+    import torch
+
+    import workloads as W
+    from paper_2409_05572_amd import api
+
+    total = args.pilot + args.requests
+    specs = W.serving_requests(total, seed=305)
+    t = time.time()
+    ctx = api.Context(0)
+    mats = []
+    for sp in specs:
+        A = W.potential_laplacian(sp["m"], sp["dim"], 2.0, sp["pot_seed"])
+        mats.append(api.Matrix.from_csr(ctx, A))
+    log(f"{total} matrices built and uploaded in {time.time() - t:.1f}s "
+        f"(n {min(x['n'] for x in specs)}..{max(x['n'] for x in specs)})")
+    free, _ = torch.cuda.mem_get_info()
+    budget = int(free * 0.6)
+    srv = api.Server(ctx, hbm_budget_bytes=budget, max_slots=args.slots)
+
+    def submit(i):
+        sp = specs[i]
+        nb = sp["n_ev"] + sp["n_extra"]
+        t_arr = time.perf_counter()
+        g = torch.Generator(device="cuda").manual_seed(1000 + i)
+        x0 = torch.randn((nb, sp["n"]), generator=g, device="cuda", dtype=torch.float64)
+        torch.cuda.synchronize()
+        tk, lam, V = srv.submit(mats[i], x0, sp["n_ev"], sp["n_extra"], strategy="fix", tol=1e-8)
+        return t_arr, time.perf_counter(), tk, x0
+
+    def collect(subs):
+        out = []
+        for i, (t_arr, t_sub, tk, x0) in subs:
+            info, q_ms, run_ms = srv.wait(tk)
+            done = t_sub + (q_ms + run_ms) / 1e3
+            out.append({"i": i, "arrival": t_arr, "done": done, "lat_ms": (done - t_arr) * 1e3,
+                        "converged": info.converged, "stop": info.max_stop_ratio, "iters": info.iterations})
+            del x0
+        return out
+
+    t0 = time.perf_counter()
+    pilot = collect([(i, submit(i)) for i in range(args.pilot)])
+    t_pilot = max(r["done"] for r in pilot) - t0
+    sat = args.pilot / t_pilot
+    rate = args.load * sat
+    log(f"pilot: {args.pilot} requests closed-loop in {t_pilot:.2f}s -> {sat:.2f} solves/s; "
+        f"arrival rate {rate:.2f}/s")
+    gaps = W.poisson_gaps(args.requests, rate, seed=306)
+    subs = []
+    t_next = time.perf_counter()
+    for k in range(args.requests):
+        t_next += gaps[k]
+        delay = t_next - time.perf_counter()
+        if delay > 0:
+            time.sleep(delay)
+        subs.append((args.pilot + k, submit(args.pilot + k)))
+        if (k + 1) % 50 == 0:
+            log(f"submitted {k + 1}/{args.requests}")
+    res = collect(subs)
+    srv.close()
+    lat = np.array([r["lat_ms"] for r in res])
+    span = max(r["done"] for r in res) - min(r["arrival"] for r in res)
+    ok = all(r["converged"] and r["stop"] <= 1e-8 for r in res + pilot)
+    log(f"measured: p50 {np.percentile(lat, 50):.1f} ms, p99 {np.percentile(lat, 99):.1f} ms, "
+        f"{len(res) / span:.2f} solves/s, all converged: {ok}")
+    return {
+        "metric": METRIC, "value": round(float(np.percentile(lat, 50)), 2), "unit": "ms (p50 latency)",
+        "n_gpus": 1, "steps": args.requests, "warmup": args.pilot,
+        "ms_per_step": round(span * 1e3 / len(res), 2), "higher_is_better": False, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"serving: {args.requests} Poisson requests at {args.load:g}x saturation, "
+                               "2-D/3-D Laplacian + U[-2,2] potential, n log-uniform 1e4..1e6, "
+                               "n_ev U{4..64}, n_extra n_ev/2, LOBPCG fix, tol 1e-8",
+                   "slots": args.slots, "hbm_budget_bytes": budget},
+        "serving": {"p50_ms": round(float(np.percentile(lat, 50)), 2),
+                    "p99_ms": round(float(np.percentile(lat, 99)), 2),
+                    "mean_ms": round(float(lat.mean()), 2), "solves_per_s": round(len(res) / span, 3),
+                    "saturated_solves_per_s": round(sat, 3), "arrival_rate_per_s": round(rate, 3),
+                    "all_converged": ok,
+                    "max_stop_ratio": max(r["stop"] for r in res)},
+        "roofline": None, "cpu_baseline": None,
+    }
 
 
 if __name__ == "__main__":

@@ -242,6 +242,47 @@ se_status se_op_cholqr(se_ctx* ctx, int64_t n, double* W, int64_t ldw, int32_t w
 se_status se_strategy_replay(const se_params* params, int32_t count, const double* r,
                              int32_t* flags);
 
+/* ---- Serving: many solves resident on one GPU ----
+ * A server runs up to max_slots solves at once, each on its own stream,
+ * workspace and host worker thread, and starts queued requests as soon as a
+ * slot is free (continuous batching, first come first served). Admission is by
+ * HBM footprint: a request starts only if the device workspace held by all
+ * slots, after the chosen slot grows to the request's footprint
+ * (se_solve_footprint), stays within hbm_budget_bytes; slots keep their
+ * workspace between requests. Results are the same as se_solve's on the same
+ * inputs (FP64 solves are bitwise identical alone and in a mix).
+ * The matrix of a request must have been created on a context of the server's
+ * device and must outlive the request; X0, V, lambda (and params.history) are
+ * the caller's and must stay valid until se_wait returns. */
+typedef struct se_server se_server;
+typedef uint64_t se_ticket;
+
+/* Device memory a solve of this shape allocates: panels, small dense
+ * workspace and, for mixed precision, the FP32 copy of the matrix values. */
+uint64_t se_solve_footprint(int64_t n, int64_t nnz, int32_t n_ev, int32_t n_extra, int32_t precision,
+                            int32_t solver);
+
+/* 1 <= max_slots <= 16; hbm_budget_bytes > 0. The server uses ctx's device. */
+se_status se_server_create(se_ctx* ctx, uint64_t hbm_budget_bytes, int32_t max_slots, se_server** out);
+
+/* Queue one solve; never blocks on the GPU. Returns SE_ERR_INVALID_ARG like
+ * se_solve, SE_ERR_REJECTED when its footprint alone exceeds the budget. */
+se_status se_submit(se_server* srv, const se_matrix* A, const se_params* params, const double* X0,
+                    double* V, double* lambda, se_ticket* ticket);
+
+/* *done = 1 once the request has finished. */
+se_status se_poll(se_server* srv, se_ticket ticket, int32_t* done);
+
+/* Block until the request finishes; fills info (may be NULL) with its
+ * se_info, queue_ms (submit to start) and run_ms (start to end, host clock;
+ * either may be NULL) and returns the solve's status. The ticket is
+ * released. */
+se_status se_wait(se_server* srv, se_ticket ticket, se_info* info, double* queue_ms, double* run_ms);
+
+/* Finish the running solves, fail the queued ones with SE_ERR_REJECTED (their
+ * tickets stay waitable until destroy), release every slot. NULL is ignored. */
+void se_server_destroy(se_server* srv);
+
 /* Static description of a status code. */
 const char* se_status_string(se_status s);
 

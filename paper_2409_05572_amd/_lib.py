@@ -85,6 +85,15 @@ PROTOTYPES = {
                                     C.c_void_p]),
     "se_op_cholqr": (C.c_int, [C.c_void_p, C.c_int64, C.c_void_p, C.c_int64, C.c_int32,
                                C.POINTER(C.c_int32)]),
+    "se_solve_footprint": (C.c_uint64, [C.c_int64, C.c_int64, C.c_int32, C.c_int32, C.c_int32,
+                                        C.c_int32]),
+    "se_server_create": (C.c_int, [C.c_void_p, C.c_uint64, C.c_int32, C.POINTER(C.c_void_p)]),
+    "se_submit": (C.c_int, [C.c_void_p, C.c_void_p, C.POINTER(SeParams), C.c_void_p, C.c_void_p,
+                            C.c_void_p, C.POINTER(C.c_uint64)]),
+    "se_poll": (C.c_int, [C.c_void_p, C.c_uint64, C.POINTER(C.c_int32)]),
+    "se_wait": (C.c_int, [C.c_void_p, C.c_uint64, C.POINTER(SeInfo), C.POINTER(C.c_double),
+                          C.POINTER(C.c_double)]),
+    "se_server_destroy": (None, [C.c_void_p]),
     "se_strategy_replay": (C.c_int, [C.POINTER(SeParams), C.c_int32, C.POINTER(C.c_double),
                                      C.POINTER(C.c_int32)]),
     "se_status_string": (C.c_char_p, [C.c_int]),

@@ -180,6 +180,78 @@ def solve(ctx: Context, A: Matrix, X0, n_ev, n_extra, history_cap=0, **kw):
     return lam, V, out
 
 
+def footprint(n, nnz, n_ev, n_extra, precision="fp64", solver="lobpcg") -> int:
+    """Device bytes a solve of this shape allocates (the serving admission size)."""
+    return int(lib().se_solve_footprint(int(n), int(nnz), int(n_ev), int(n_extra), PRECISIONS[precision],
+                                        _lib.SE_SI if solver == "si" else _lib.SE_LOBPCG))
+
+
+def _info_of(st, info, hist):
+    return SolveInfo(st, info.iterations, bool(info.converged), info.n_shrinks, info.n_expands,
+                     info.max_stop_ratio, info.max_paper_ratio, info.time_ms,
+                     int(info.workspace_bytes), hist[: info.history_len].copy(),
+                     tuple(info.kern_ms), tuple(info.kern_bytes), tuple(info.kern_flops),
+                     tuple(info.kern_calls), info.lp_iterations)
+
+
+class Server:
+    """Continuous-batching solver service on one GPU (se_server_*).
+
+    submit() queues a solve on device tensors and returns a ticket at once;
+    wait() blocks for its result. The caller keeps the matrix, X0 and the
+    output tensors alive until wait() returns.
+    """
+
+    def __init__(self, ctx: Context, hbm_budget_bytes: int, max_slots: int = 4):
+        self._h = C.c_void_p()
+        check(lib().se_server_create(ctx.handle, int(hbm_budget_bytes), int(max_slots), C.byref(self._h)),
+              "se_server_create")
+        self._keep = {}
+
+    def submit(self, A: Matrix, X0, n_ev, n_extra, **kw):
+        """X0: torch (nb, n) float64 device tensor. Returns (ticket, lam, V)."""
+        import torch
+
+        n = A.n
+        assert X0.dtype == torch.float64 and X0.is_contiguous() and X0.shape == (n_ev + n_extra, n)
+        p = params(n_ev, n_extra, **kw)
+        p.ptr_mode = _lib.SE_PTR_DEVICE
+        V = torch.empty((n_ev, n), dtype=torch.float64, device=X0.device)
+        lam = torch.empty(n_ev, dtype=torch.float64, device=X0.device)
+        t = C.c_uint64()
+        check(lib().se_submit(self._h, A.handle, C.byref(p), C.c_void_p(_ptr(X0)), C.c_void_p(_ptr(V)),
+                              C.c_void_p(_ptr(lam)), C.byref(t)), "se_submit")
+        self._keep[t.value] = (A, X0, V, lam)
+        return t.value, lam, V
+
+    def poll(self, ticket) -> bool:
+        d = C.c_int32()
+        check(lib().se_poll(self._h, C.c_uint64(ticket), C.byref(d)), "se_poll")
+        return bool(d.value)
+
+    def wait(self, ticket):
+        """Returns (SolveInfo, queue_ms, run_ms); raises SeError on a failed solve."""
+        info = SeInfo()
+        q, r = C.c_double(), C.c_double()
+        st = lib().se_wait(self._h, C.c_uint64(ticket), C.byref(info), C.byref(q), C.byref(r))
+        self._keep.pop(ticket, None)
+        if st < 0:
+            raise _lib.SeError(st, "se_wait")
+        return _info_of(st, info, np.zeros((0, _lib.SE_HISTORY_FIELDS))), q.value, r.value
+
+    def close(self):
+        if self._h:
+            lib().se_server_destroy(self._h)
+            self._h = C.c_void_p()
+            self._keep.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 # ---- building blocks (device tensors, row-major blocks) ----
 
 def spmm(ctx: Context, A: Matrix, X, Y, w: int):

@@ -1221,6 +1221,25 @@ struct Solver {
 
 }  // namespace
 
+// Device workspace a solve of this shape allocates (the sizes of
+// Solver::alloc_panels, alloc_small and lp_alloc), plus the FP32 copy of the
+// matrix values for mixed precision.
+size_t solve_workspace_bytes(long long n, long long nnz, int nb, int precision, int solver) {
+    const long long ld = round_up(nb, 8);
+    const int mmax = solver == SE_SI ? nb : 3 * nb;
+    const size_t mm = (size_t)mmax * mmax;
+    size_t bytes = sizeof(double) * (size_t)kNumPanels * n * ld;
+    size_t small = 4 * mm + (mmax + 8) + (2 * mm + 8 * (size_t)mmax + 64) + syev_work_doubles(mmax) +
+                   std::max(gram_scratch_doubles(n, mmax, mmax), (size_t)4096 * 2 * mmax) + 4 * mm +
+                   3 * (2 * (size_t)mmax + 16);
+    if (precision != SE_FP64) {
+        const size_t es = precision == SE_FP32_MIXED ? 4 : 2;
+        bytes += es * (size_t)kNumLpPanels * n * ld + sizeof(float) * (size_t)nnz;
+        small += 6 * mm;
+    }
+    return bytes + sizeof(double) * small;
+}
+
 se_status solve(se_ctx* ctx, const se_matrix* A, const se_params* prm, const double* X0, double* V,
                 double* lambda, se_info* info) {
     Solver s(ctx, A, *prm);

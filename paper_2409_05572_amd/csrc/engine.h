@@ -155,4 +155,6 @@ struct se_matrix {
 namespace se {
 se_status solve(se_ctx* ctx, const se_matrix* A, const se_params* p, const double* X0, double* V,
                 double* lambda, se_info* info);
+size_t solve_workspace_bytes(long long n, long long nnz, int nb, int precision, int solver);
+se_status validate_solve(const se_matrix* A, const se_params* p);
 }

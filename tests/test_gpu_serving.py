@@ -1,0 +1,132 @@
+"""The serving runtime (se_server_*) on the GPU: admission by HBM footprint,
+results identical to a lone se_solve, queueing under a tight budget."""
+import numpy as np
+import pytest
+
+import workloads as W
+from tests.gpu_util import gpu_ctx
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    return gpu_ctx()
+
+
+def _x0(n, nb, seed):
+    import torch
+
+    return torch.from_numpy(np.ascontiguousarray(W.gaussian_block(n, nb, seed).T)).cuda()
+
+
+def _requests():
+    specs = W.serving_requests(7, seed=77, n_min=2e3, n_max=4e4, ev_min=4, ev_max=24)
+    return [(W.potential_laplacian(s["m"], s["dim"], 2.0, s["pot_seed"]), s) for s in specs]
+
+
+def test_footprint_covers_the_workspace_of_a_solve(ctx):
+    from paper_2409_05572_amd import api
+
+    for prec in ("fp64", "fp32"):
+        c = api.Context(0)  # fresh workspace
+        A = W.potential_laplacian(30, 2, 2.0, 5)
+        M = api.Matrix.from_csr(c, A)
+        _, _, info = api.solve(c, M, _x0(A.n, 12, 3), 8, 4, strategy="fix", precision=prec)
+        fp = api.footprint(A.n, A.nnz, 8, 4, precision=prec)
+        assert info.workspace_bytes <= fp <= 1.3 * info.workspace_bytes + (1 << 20)
+
+
+def test_results_identical_alone_and_in_the_mix(ctx):
+    import torch
+
+    from paper_2409_05572_amd import api
+
+    reqs = _requests()
+    mats = [api.Matrix.from_csr(ctx, A) for A, _ in reqs]
+    alone = []
+    for M, (A, s) in zip(mats, reqs):
+        lam, V, info = api.solve(ctx, M, _x0(A.n, s["n_ev"] + s["n_extra"], s["pot_seed"]), s["n_ev"],
+                                 s["n_extra"], strategy="fix")
+        assert info.converged
+        alone.append((lam.cpu().numpy(), V.cpu().numpy()))
+    srv = api.Server(ctx, hbm_budget_bytes=64 << 30, max_slots=3)
+    try:
+        tickets = []
+        for M, (A, s) in zip(mats, reqs):
+            x0 = _x0(A.n, s["n_ev"] + s["n_extra"], s["pot_seed"])
+            torch.cuda.synchronize()
+            tickets.append(srv.submit(M, x0, s["n_ev"], s["n_extra"], strategy="fix"))
+        for (t, lam, V), (lam0, V0) in zip(tickets, alone):
+            info, q_ms, run_ms = srv.wait(t)
+            assert info.converged and info.max_stop_ratio <= 1e-8 and run_ms > 0 and q_ms >= 0
+            assert np.array_equal(lam.cpu().numpy(), lam0) and np.array_equal(V.cpu().numpy(), V0)
+    finally:
+        srv.close()
+
+
+def test_tight_budget_queues_and_oversized_request_is_rejected(ctx):
+    import torch
+
+    from paper_2409_05572_amd import api
+    from paper_2409_05572_amd._lib import SeError
+
+    reqs = _requests()[:4]
+    fps = [api.footprint(A.n, A.nnz, s["n_ev"], s["n_extra"]) for A, s in reqs]
+    budget = int(max(fps) * 1.05)  # room for one request at a time (slots keep their workspace)
+    srv = api.Server(ctx, hbm_budget_bytes=budget, max_slots=4)
+    try:
+        mats = [api.Matrix.from_csr(ctx, A) for A, _ in reqs]
+        tickets = []
+        for M, (A, s) in zip(mats, reqs):
+            x0 = _x0(A.n, s["n_ev"] + s["n_extra"], s["pot_seed"])
+            torch.cuda.synchronize()
+            tickets.append(srv.submit(M, x0, s["n_ev"], s["n_extra"]))
+        waits = [srv.wait(t[0]) for t in tickets]
+        assert all(w[0].converged for w in waits)
+        assert max(w[1] for w in waits[1:]) > 0.0  # later requests waited for memory
+        big = W.potential_laplacian(60, 3, 2.0, 1)
+        Mb = api.Matrix.from_csr(ctx, big)
+        with pytest.raises(SeError):
+            srv.submit(Mb, _x0(big.n, 48, 1), 32, 16)
+    finally:
+        srv.close()
+
+
+def test_mixed_precision_requests_share_the_server(ctx):
+    import torch
+
+    from paper_2409_05572_amd import api
+
+    reqs = _requests()[:4]
+    srv = api.Server(ctx, hbm_budget_bytes=32 << 30, max_slots=2)
+    try:
+        out = []
+        for i, (A, s) in enumerate(reqs):
+            M = api.Matrix.from_csr(ctx, A)
+            x0 = _x0(A.n, s["n_ev"] + s["n_extra"], s["pot_seed"])
+            torch.cuda.synchronize()
+            out.append((M, x0, srv.submit(M, x0, s["n_ev"], s["n_extra"], strategy="fix",
+                                          precision="fp32" if i % 2 else "fp64")))
+        for M, x0, (t, lam, V) in out:
+            info, _, _ = srv.wait(t)
+            assert info.converged and info.max_stop_ratio <= 1e-8
+    finally:
+        srv.close()
+
+
+def test_destroy_with_queued_requests_returns(ctx):
+    import torch
+
+    from paper_2409_05572_amd import api
+
+    reqs = _requests()[:3]
+    srv = api.Server(ctx, hbm_budget_bytes=64 << 30, max_slots=1)
+    keep = []
+    for A, s in reqs:
+        M = api.Matrix.from_csr(ctx, A)
+        x0 = _x0(A.n, s["n_ev"] + s["n_extra"], s["pot_seed"])
+        torch.cuda.synchronize()
+        keep.append((M, x0, srv.submit(M, x0, s["n_ev"], s["n_extra"])))
+    srv.close()  # finishes the running solve, drops the queued ones
+    torch.cuda.synchronize()

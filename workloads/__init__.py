@@ -212,3 +212,32 @@ WORKLOADS = {
         build=lambda: chung_lu_laplacian(500_000, 16.0, 2.5, 104), n_ev=32, n_extra=16, x0_seed=204
     ),
 }
+
+
+def serving_requests(count: int, seed: int = 305, n_min: float = 1e4, n_max: float = 1e6,
+                     ev_min: int = 4, ev_max: int = 64) -> list:
+    """A stream of eigenproblem requests for the serving workload.
+
+    Each request is a 2-D or 3-D Dirichlet Laplacian (probability 1/2 each)
+    with a diagonal potential U[-2, 2]; the target size is log-uniform in
+    [n_min, n_max] and the grid side is round(n^(1/dim)), so n = m^dim;
+    n_ev ~ U{ev_min..ev_max} and n_extra = n_ev // 2. Returns dicts with dim,
+    m, n, n_ev, n_extra and the potential's seed (built by
+    ``potential_laplacian``).
+    """
+    rng = np.random.default_rng(seed)
+    out = []
+    for i in range(count):
+        dim = 2 if rng.random() < 0.5 else 3
+        target = float(np.exp(rng.uniform(np.log(n_min), np.log(n_max))))
+        m = max(4, int(round(target ** (1.0 / dim))))
+        n_ev = int(rng.integers(ev_min, ev_max + 1))
+        out.append({"dim": dim, "m": m, "n": m ** dim, "n_ev": n_ev, "n_extra": n_ev // 2,
+                    "pot_seed": 10000 + i})
+    return out
+
+
+def poisson_gaps(count: int, rate: float, seed: int = 306) -> np.ndarray:
+    """Inter-arrival gaps (seconds) of a Poisson process of the given rate."""
+    rng = np.random.default_rng(seed)
+    return rng.exponential(1.0 / rate, size=count)
