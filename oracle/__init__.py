@@ -18,6 +18,9 @@ Modules:
   LOBPCG with soft locking and the Hetmaniuk-Lehoucq basis (Algorithm 3),
   and subspace iteration (Algorithm 1), both with shrink-and-expand
   (Algorithm 5).
+* ``mixed``    - the same solvers with a low-precision phase (blocks stored in
+  FP32 or BF16, Rayleigh-Ritz with the FP64 Gram matrix M = S^T S) followed by
+  the FP64 solver.
 
 Pins: see ``tests/test_oracle_*.py``. Parity unpinned (no closed form, checked
 only by invariants and by agreement with brute force at small sizes): the
@@ -35,3 +38,4 @@ from .solvers import (  # noqa: F401
     lobpcg,
     subspace_iteration,
 )
+from . import mixed  # noqa: F401,E402

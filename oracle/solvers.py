@@ -162,8 +162,13 @@ def lobpcg(
     soft_lock=True,
     drop_tol=1e-12,
     time_limit_s=None,
+    P0=None,
 ):
-    """LOBPCG with soft locking, HL basis and shrink-and-expand (Algorithm 3)."""
+    """LOBPCG with soft locking, HL basis and shrink-and-expand (Algorithm 3).
+
+    ``P0``: search directions to continue with (e.g. after a low-precision
+    phase); they are orthogonalized against the starting X.
+    """
     se = se or SEParams()
     nb = X0.shape[1]
     ctl = SEController(se if _se_enabled(se, n_ev, n_es, nb) else SEParams("none"))
@@ -175,6 +180,11 @@ def lobpcg(
     X = X @ Z
     lam = theta
     P = X[:, :0]
+    if P0 is not None and P0.shape[1] > 0:
+        P = np.asarray(P0, dtype=np.float64)
+        for _ in range(2):
+            P = P - X @ (X.T @ P)
+        P, _ = orth(P, drop_tol)
     Xdrop = Pdrop = None
     history = []
     n_shr = n_exp = 0

@@ -214,3 +214,21 @@ def test_mixed_rejects_negative_switch_threshold(ctx):
     X0 = W.gaussian_block(A.n, 6, 1)
     with pytest.raises(SeError):
         _solve(ctx, A, X0, 3, 3, precision="fp32", r_switch=-1.0)
+
+
+@pytest.mark.parametrize("fmt,solver", [("fp32", "lobpcg"), ("bf16", "lobpcg"), ("fp32", "si")])
+def test_mixed_matches_mixed_oracle(ctx, fmt, solver):
+    """Same scheme on both sides (different whitening factorizations): the
+    final pairs agree to the FP64 bar and the low-precision phases have
+    comparable lengths."""
+    from tests.gpu_util import cluster_angles
+
+    A = W.laplacian_2d(32)
+    X0 = W.gaussian_block(A.n, 16, 201)
+    lam, V, info = _solve(ctx, A, X0, 8, 8, solver=solver, precision=fmt)
+    run = O.mixed.lobpcg_mixed if solver == "lobpcg" else O.mixed.subspace_iteration_mixed
+    ref, lp_ref, _ = run(A.to_scipy(), X0, 8, A.anorm, fmt=fmt)
+    assert info.converged and ref.converged
+    assert np.max(np.abs(lam - ref.lam) / np.abs(ref.lam)) <= 1e-10
+    assert cluster_angles(lam, V, ref.V) <= 1e-6
+    assert abs(info.lp_iterations - lp_ref) <= max(5, 0.3 * lp_ref)

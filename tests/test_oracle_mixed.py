@@ -1,0 +1,115 @@
+"""Pins of the mixed-precision oracle (CPU).
+
+Storage rounding is checked against hand-derived values; the generalized
+Rayleigh-Ritz step against SciPy's generalized symmetric eigensolver and
+against plain Rayleigh-Ritz on an orthonormalized basis; the HL directions
+against their defining properties; whole solves against the closed-form
+Laplacian spectrum. A planted mistake (ignoring M) must fail the checks.
+"""
+import numpy as np
+import pytest
+import scipy.linalg as sla
+
+import oracle as O
+import workloads as W
+from tests import _pins as pins
+
+M_ = O.mixed
+
+
+def test_bf16_rounding_hand_values():
+    x = np.array([1.0, 1.0 + 2.0 ** -8, 1.0 + 3.0 * 2.0 ** -9, 1.0 + 2.0 ** -7 + 2.0 ** -8, -2.5,
+                  3.14159265, 65504.0, 2.0 ** -130])
+    # 1 + 2^-8 is halfway between 1 and 1 + 2^-7: ties go to the even mantissa (1.0);
+    # 1 + 3*2^-9 is above halfway; 1 + 2^-7 + 2^-8 is halfway and rounds up to
+    # the even 1 + 2^-6; pi has 8 significant bits 1.1001001 (x 2) = 3.140625.
+    want = np.array([1.0, 1.0, 1.0 + 2.0 ** -7, 1.0 + 2.0 ** -6, -2.5, 3.140625, 65536.0,
+                     2.0 ** -130])
+    assert np.array_equal(M_.round_to(x, "bf16"), want)
+    assert M_.round_to(np.array([0.1]), "fp32")[0] == 0.100000001490116119384765625
+    assert np.array_equal(M_.round_to(x, "fp64"), x)
+
+
+def _basis(n, m, seed, fmt):
+    rng = np.random.default_rng(seed)
+    Q, _ = np.linalg.qr(rng.standard_normal((n, m)))
+    return M_.round_to(Q @ (np.eye(m) + 0.05 * rng.standard_normal((m, m))), fmt)
+
+
+@pytest.mark.parametrize("fmt", ["fp32", "bf16"])
+def test_generalized_rr_equals_library_generalized_eigensolver(fmt):
+    A = W.laplacian_2d(20).to_scipy()
+    S = _basis(A.shape[0], 24, 3, fmt)
+    AS = A @ S
+    theta, CX, _ = M_.generalized_rr(S, AS, 10)
+    ref = sla.eigh(S.T @ AS, S.T @ S, eigvals_only=True)[:10]
+    assert np.max(np.abs(theta - ref)) <= 1e-12 * np.abs(ref).max()
+    # and plain Rayleigh-Ritz on an orthonormal basis of the same space
+    Q, _ = np.linalg.qr(S)
+    assert np.max(np.abs(theta - np.linalg.eigvalsh(Q.T @ (A @ Q))[:10])) <= 1e-12 * np.abs(ref).max()
+    X = S @ CX  # M-orthonormal coefficients give orthonormal Ritz vectors
+    assert np.abs(X.T @ X - np.eye(10)).max() <= 1e-12
+
+
+def test_generalized_rr_drops_a_dependent_column():
+    A = W.laplacian_2d(16).to_scipy()
+    S = _basis(A.shape[0], 12, 4, "fp32")
+    S2 = np.hstack([S, S[:, 3:4]])  # exactly dependent
+    theta, CX, _ = M_.generalized_rr(S2, A @ S2, 6)
+    Q, _ = np.linalg.qr(S)
+    ref = np.linalg.eigvalsh(Q.T @ (A @ Q))[:6]
+    assert np.max(np.abs(theta - ref)) <= 1e-12 * np.abs(ref).max()
+    assert M_.whiten(S2.T @ S2).shape[1] == 12
+
+
+def test_hl_directions_in_whitened_coordinates():
+    A = W.laplacian_2d(16).to_scipy()
+    S = _basis(A.shape[0], 18, 5, "bf16")
+    k, active = 6, [0, 2, 3, 5]
+    theta, CX, CP = M_.generalized_rr(S, A @ S, k, active)
+    XN, PN = S @ CX, S @ CP
+    B = np.hstack([XN, PN])
+    assert np.abs(B.T @ B - np.eye(B.shape[1])).max() <= 1e-11  # orthonormal
+    old = S[:, active]
+    resid = old - B @ (B.T @ old)  # span{X_new, P_new} contains the old X columns
+    assert np.linalg.norm(resid) <= 1e-10 * np.linalg.norm(old)
+    assert PN.shape[1] <= len(active)
+
+
+def test_ignoring_m_is_caught(monkeypatch):
+    """Planted mistake: treat the stored basis as orthonormal (B = I)."""
+    A = W.laplacian_2d(20).to_scipy()
+    S = _basis(A.shape[0], 24, 6, "bf16")
+    AS = A @ S
+    ref = sla.eigh(S.T @ AS, S.T @ S, eigvals_only=True)[:10]
+    monkeypatch.setattr(M_, "whiten", lambda M, drop=M_.DROP: np.eye(M.shape[0]))
+    theta, _, _ = M_.generalized_rr(S, AS, 10)
+    assert np.max(np.abs(theta - ref)) > 1e-4 * np.abs(ref).max()
+
+
+@pytest.mark.parametrize("fmt", ["fp32", "bf16"])
+def test_mixed_lobpcg_reaches_closed_form(fmt):
+    A = W.laplacian_2d(32)
+    X0 = W.gaussian_block(A.n, 16, 201)
+    res, lp, hist = M_.lobpcg_mixed(A.to_scipy(), X0, 8, A.anorm, fmt=fmt)
+    ex = pins.laplacian_spectrum(32, 2, 8)
+    assert res.converged and lp >= 1
+    assert np.max(np.abs(res.lam - ex) / ex) <= 1e-10
+    _, stop, _ = O.residual_measures(A.to_scipy(), res.V, res.lam, A.anorm)
+    assert stop.max() <= 1e-8
+    r = np.array([h["r"] for h in hist])
+    assert r.min() <= 100 * M_.DEFAULT_SWITCH[fmt]  # left at r_switch or at its floor near it
+
+
+def test_mixed_lobpcg_with_shrink_expand_and_si():
+    A = W.laplacian_3d(12)
+    X0 = W.gaussian_block(A.n, 24, 205)
+    res, lp, _ = M_.lobpcg_mixed(A.to_scipy(), X0, 16, A.anorm, fmt="fp32", n_es=21,
+                                 se=O.SEParams("fix"))
+    ex = pins.laplacian_spectrum(12, 3, 16)
+    assert res.converged and np.max(np.abs(res.lam - ex) / ex) <= 1e-10
+    A2 = W.laplacian_2d(32)
+    X2 = W.gaussian_block(A2.n, 16, 201)
+    res2, lp2, _ = M_.subspace_iteration_mixed(A2.to_scipy(), X2, 8, A2.anorm, fmt="fp32")
+    ex2 = pins.laplacian_spectrum(32, 2, 8)
+    assert res2.converged and lp2 >= 1 and np.max(np.abs(res2.lam - ex2) / ex2) <= 1e-10
