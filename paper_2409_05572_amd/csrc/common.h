@@ -191,6 +191,11 @@ hipError_t launch_axpby(hipStream_t st, long long count, double alpha, const dou
 hipError_t launch_add_diag(hipStream_t st, int m, double* A, long long ld, double alpha);
 hipError_t launch_fill(hipStream_t st, int rows, int cols, double* A, long long ld, double v);
 hipError_t launch_sumsq(hipStream_t st, long long count, const double* X, double* out);
+// A_p from its known leading q x q block Axp and G = S^T (A W) (m x (m - q)),
+// symmetrized; and the symmetric gather out[a][b] = in[idx[a]][idx[b]].
+hipError_t launch_assemble_ap(hipStream_t st, int m, int q, const double* Axp, const double* G, double* Ap);
+hipError_t launch_gather_sym(hipStream_t st, int r, const int* idx, const double* in, long long ld,
+                             double* out);
 
 size_t syev_work_doubles(int m);
 hipError_t launch_syev_lowest(hipStream_t st, int m, int k, double* A, double* w, double* Z,

@@ -157,6 +157,11 @@ struct Solver {
         HC(ws.hlY.ensure(sizeof(double) * mm));
         HC(ws.hlG.ensure(sizeof(double) * mm));
         HC(ws.hlQ.ensure(sizeof(double) * mm));
+        {
+            DevBuf* cb[] = {&ws.apc, &ws.axp, &ws.axq, &ws.gw};
+            for (DevBuf* b : cb) HC(b->ensure(sizeof(double) * mm));
+            HC(ws.idx.ensure(sizeof(int) * (mmax + 8)));
+        }
         if (p.precision != SE_FP64) {
             DevBuf* lpb[] = {&ws.lpM, &ws.lpT, &ws.lpQ, &ws.lpB, &ws.lpE, &ws.lpC};
             for (DevBuf* b : lpb) HC(b->ensure(sizeof(double) * mm));
@@ -474,6 +479,9 @@ struct Solver {
     }
 
     // ------------------------------------------------------------- LOBPCG --
+    // Every kAxpRefresh iterations the whole of A_p is recomputed over n, so
+    // rounding in the carried [X, P] block cannot accumulate.
+    static constexpr int kAxpRefresh = 10;
     // X0: FP64 column-major start block; k0 >= 0: the X panel already holds
     // k0 start columns (row-major), e.g. from the low-precision phase.
     // p0 > 0: the P panel holds p0 search directions to continue with (they
@@ -487,7 +495,8 @@ struct Solver {
         if (k < n_ev) return SE_ERR_BREAKDOWN;
         ST(spmm(X, AX, k));
         ST(rr_plain(k));
-        int pw = 0;  // width of P
+        int pw = 0;      // width of P
+        int axp_q = -1;  // order of the carried [X, P]^T A [X, P] (ws.axp), -1 = none
         if (p0 > 0) {
             const Segs Xs = seg1(X, k);
             for (int pass = 0; pass < 2; ++pass) {
@@ -576,11 +585,20 @@ struct Solver {
                 flags |= 1;
             }
 
-            // Rayleigh-Ritz on S = [X, P, W].
+            // Rayleigh-Ritz on S = [X, P, W]. Outside expansions the
+            // [X, P] block of A_p is the carried C^T A_p C of the previous
+            // step (Axp), so only S^T (A W) is a product over n.
             const int m = k + pw + a;
             const Segs S = seg3(X, k, P, pw, W, a);
             const Segs AS = seg3(AX, k, AP, pw, AW, a);
-            ST(gram(S, AS, 1, ws.G.as<double>()));
+            if (axp_q == k + pw && !(flags & 1) && a > 0 && j % kAxpRefresh != 0) {
+                ST(gram(S, seg1(AW, a), 0, ws.gw.as<double>()));
+                HC(launch_assemble_ap(st, m, axp_q, ws.axp.as<double>(), ws.gw.as<double>(),
+                                      ws.G.as<double>()));
+            } else {
+                ST(gram(S, AS, 1, ws.G.as<double>()));
+            }
+            HC(launch_copy_cols(st, m, ws.G.as<double>(), m, 0, ws.apc.as<double>(), m, 0, m));
             ST(tic());
             HC(launch_syev_lowest(st, m, k, ws.G.as<double>(), ws.theta.as<double>(), ws.Z.as<double>(),
                                   ws.syev_work.as<double>()));
@@ -606,6 +624,15 @@ struct Solver {
             std::swap(AX, AXn);
             std::swap(AP, APn);
             pw = rP;
+            // carried [X, P]^T A [X, P] = C^T A_p C (small products)
+            {
+                const int q = k + rP;
+                ST(update_rows(m, segx(ws.apc.as<double>(), m, m), ws.C.as<double>(), q,
+                               segx(ws.axq.as<double>(), q, q), 1.0, 0.0));
+                ST(gram_rows(m, segx(ws.C.as<double>(), q, q), segx(ws.axq.as<double>(), q, q), 1,
+                             ws.axp.as<double>()));
+                axp_q = q;
+            }
 
             if (ctl.ifshrink(j)) {
                 dx = k - n_es;
@@ -615,8 +642,20 @@ struct Solver {
                 HC(launch_copy_cols(st, n, AX, ld, n_es, ASd, ld, 0, dx));
                 HC(launch_copy_cols(st, n, P, ld, n_es, Sd, ld, dx, dp));
                 HC(launch_copy_cols(st, n, AP, ld, n_es, ASd, ld, dx, dp));
+                // keep the rows and columns of X(:, 0:n_es) and P(:, 0:pw') in Axp
+                const int pk = std::min(pw, n_es);
+                std::vector<int> keep;
+                for (int i = 0; i < n_es; ++i) keep.push_back(i);
+                for (int i = 0; i < pk; ++i) keep.push_back(k + i);
+                const int q = (int)keep.size();
+                std::memcpy(ws.h_act.p, keep.data(), sizeof(int) * q);
+                HC(hipMemcpyAsync(ws.idx.p, ws.h_act.p, sizeof(int) * q, hipMemcpyHostToDevice, st));
+                HC(launch_gather_sym(st, q, ws.idx.as<int>(), ws.axp.as<double>(), axp_q,
+                                     ws.axq.as<double>()));
+                HC(launch_copy_cols(st, q, ws.axq.as<double>(), q, 0, ws.axp.as<double>(), q, 0, q));
+                axp_q = q;
                 k = n_es;
-                pw = std::min(pw, n_es);
+                pw = pk;
                 have_drop = true;
                 ctl.did_shrink(j);
                 ++n_shr;
@@ -1231,7 +1270,7 @@ size_t solve_workspace_bytes(long long n, long long nnz, int nb, int precision, 
     size_t bytes = sizeof(double) * (size_t)kNumPanels * n * ld;
     size_t small = 4 * mm + (mmax + 8) + (2 * mm + 8 * (size_t)mmax + 64) + syev_work_doubles(mmax) +
                    std::max(gram_scratch_doubles(n, mmax, mmax), (size_t)4096 * 2 * mmax) + 4 * mm +
-                   3 * (2 * (size_t)mmax + 16);
+                   3 * (2 * (size_t)mmax + 16) + 4 * mm + (size_t)mmax + 8;
     if (precision != SE_FP64) {
         const size_t es = precision == SE_FP32_MIXED ? 4 : 2;
         bytes += es * (size_t)kNumLpPanels * n * ld + sizeof(float) * (size_t)nnz;

@@ -69,6 +69,7 @@ struct Workspace {
     DevBuf gram_part, G, T, Z, theta, C, small_work, syev_work, lam, act, act_hl, norms, info;
     DevBuf hlB, hlY, hlG, hlQ;
     DevBuf lpM, lpT, lpQ, lpB, lpE, lpC;  // generalized Rayleigh-Ritz (m x m each)
+    DevBuf apc, axp, axq, gw, idx;        // carried [X, P]^T A [X, P] (m x m each; idx ints)
     HostBuf h_norms, h_info, h_act, h_act_hl, h_theta;
     std::vector<hipEvent_t> events;  // pool for per-launch timing
     size_t device_bytes() const {
@@ -77,7 +78,7 @@ struct Workspace {
         for (const auto& b : lp_panel) s += b.bytes;
         const DevBuf* all[] = {&gram_part, &G, &T, &Z, &theta, &C, &small_work, &syev_work,
                                &lam, &act, &act_hl, &norms, &info, &hlB, &hlY, &hlG, &hlQ,
-                               &lpM, &lpT, &lpQ, &lpB, &lpE, &lpC};
+                               &lpM, &lpT, &lpQ, &lpB, &lpE, &lpC, &apc, &axp, &axq, &gw, &idx};
         for (auto* b : all) s += b->bytes;
         return s;
     }
@@ -86,7 +87,7 @@ struct Workspace {
         for (auto& b : lp_panel) b.release();
         DevBuf* all[] = {&gram_part, &G, &T, &Z, &theta, &C, &small_work, &syev_work,
                          &lam, &act, &act_hl, &norms, &info, &hlB, &hlY, &hlG, &hlQ,
-                         &lpM, &lpT, &lpQ, &lpB, &lpE, &lpC};
+                         &lpM, &lpT, &lpQ, &lpB, &lpE, &lpC, &apc, &axp, &axq, &gw, &idx};
         for (auto* b : all) b->release();
         h_norms.release();
         h_info.release();

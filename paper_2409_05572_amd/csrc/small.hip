@@ -667,6 +667,41 @@ __global__ __launch_bounds__(256) void fill_kernel(int rows, int cols, double* _
         A[(e / cols) * ld + e % cols] = v;
 }
 
+// A_p (m x m) from the known block of the leading q columns (Axp, q x q)
+// and the product G = S^T (A W) (m x a, a = m - q): A_p[i][j] = Axp[i][j]
+// for i, j < q; G[i][j - q] and its mirror for one index >= q; the average
+// of G[i][j - q] and G[j][i - q] for both >= q (W^T A W, symmetrized).
+__global__ __launch_bounds__(256) void assemble_ap_kernel(int m, int q, const double* __restrict__ Axp,
+                                                          const double* __restrict__ G,
+                                                          double* __restrict__ Ap) {
+    const int a = m - q;
+    const long long total = (long long)m * m;
+    for (long long e = (long long)blockIdx.x * 256 + threadIdx.x; e < total; e += (long long)gridDim.x * 256) {
+        const int i = (int)(e / m), j = (int)(e % m);
+        double v;
+        if (i < q && j < q)
+            v = Axp[(long long)i * q + j];
+        else if (j >= q && i < q)
+            v = G[(long long)i * a + (j - q)];
+        else if (i >= q && j < q)
+            v = G[(long long)j * a + (i - q)];
+        else
+            v = 0.5 * (G[(long long)i * a + (j - q)] + G[(long long)j * a + (i - q)]);
+        Ap[e] = v;
+    }
+}
+
+// out (r x r) = in[idx[a]][idx[b]] for a, b < r (in has leading dimension ld).
+__global__ __launch_bounds__(256) void gather_sym_kernel(int r, const int* __restrict__ idx,
+                                                         const double* __restrict__ in, long long ld,
+                                                         double* __restrict__ out) {
+    const long long total = (long long)r * r;
+    for (long long e = (long long)blockIdx.x * 256 + threadIdx.x; e < total; e += (long long)gridDim.x * 256) {
+        const int a = (int)(e / r), b = (int)(e % r);
+        out[e] = in[(long long)idx[a] * ld + idx[b]];
+    }
+}
+
 // out[0] = sum of squares of the count entries of X (one workgroup, fixed order).
 __global__ __launch_bounds__(kSmall) void sumsq_kernel(long long count, const double* __restrict__ X,
                                                        double* __restrict__ out) {
@@ -709,6 +744,21 @@ hipError_t launch_fill(hipStream_t st, int rows, int cols, double* A, long long 
     if (rows <= 0 || cols <= 0) return hipSuccess;
     hipLaunchKernelGGL(fill_kernel, dim3(small_grid((long long)rows * cols)), dim3(256), 0, st, rows, cols, A,
                        ld, v);
+    return hipGetLastError();
+}
+
+hipError_t launch_assemble_ap(hipStream_t st, int m, int q, const double* Axp, const double* G, double* Ap) {
+    if (m <= 0) return hipSuccess;
+    hipLaunchKernelGGL(assemble_ap_kernel, dim3(small_grid((long long)m * m)), dim3(256), 0, st, m, q, Axp, G,
+                       Ap);
+    return hipGetLastError();
+}
+
+hipError_t launch_gather_sym(hipStream_t st, int r, const int* idx, const double* in, long long ld,
+                             double* out) {
+    if (r <= 0) return hipSuccess;
+    hipLaunchKernelGGL(gather_sym_kernel, dim3(small_grid((long long)r * r)), dim3(256), 0, st, r, idx, in, ld,
+                       out);
     return hipGetLastError();
 }
 
