@@ -7,6 +7,8 @@
 
 #include <algorithm>
 
+#include <hip/hip_cooperative_groups.h>
+
 #include "common.h"
 
 namespace se {
@@ -517,60 +519,76 @@ __global__ __launch_bounds__(256) void invit_kernel(int m, int k, const double* 
     int run = 0;
     for (int q = i; q > 0 && w[q] - w[q - 1] <= sep; --q) ++run;
     const double lam = w[i] + run * sep;
+    auto guard = [&](double x) { return fabs(x) < tiny ? copysign(tiny, x == 0.0 ? 1.0 : x) : x; };
 #define AT(arr, j) arr[(size_t)(j) * k + i]
-    for (int j = 0; j < m; ++j) {
-        AT(DD, j) = dg[j] - lam;
-        if (j + 1 < m) {
-            AT(DL, j) = eg[j];
-            AT(DU, j) = eg[j];
-        }
-        if (j + 2 < m) AT(DU2, j) = 0.0;
-    }
+    // LU factorization with partial pivoting of T - lam I. The diagonal and
+    // superdiagonal entries that step j modifies for row j + 1 are carried in
+    // registers, so every load reads an input (no store-to-load chain through
+    // memory) and each factor entry is stored once.
+    double dcur = dg[0] - lam;
+    double ucur = (m > 1) ? eg[0] : 0.0;
 #pragma unroll 4
     for (int j = 0; j + 1 < m; ++j) {
-        const double dj = AT(DD, j), lj = AT(DL, j);
-        if (fabs(dj) >= fabs(lj)) {
+        const double lj = eg[j];
+        const double dn = dg[j + 1] - lam;
+        const double un = (j + 2 < m) ? eg[j + 1] : 0.0;
+        if (fabs(dcur) >= fabs(lj)) {
+            const double f = (dcur != 0.0) ? lj / dcur : 0.0;
             AT(IP, j) = j;
-            if (dj != 0.0) {
-                const double f = lj / dj;
-                AT(DL, j) = f;
-                AT(DD, j + 1) -= f * AT(DU, j);
-            }
+            AT(DL, j) = (dcur != 0.0) ? f : lj;
+            AT(DD, j) = guard(dcur);
+            AT(DU, j) = ucur;
+            AT(DU2, j) = 0.0;
+            dcur = (dcur != 0.0) ? dn - f * ucur : dn;
+            ucur = un;
         } else {
-            const double f = dj / lj;
-            AT(DD, j) = lj;
-            AT(DL, j) = f;
-            const double tmp = AT(DU, j);
-            AT(DU, j) = AT(DD, j + 1);
-            AT(DD, j + 1) = tmp - f * AT(DD, j + 1);
-            if (j + 2 < m) {
-                AT(DU2, j) = AT(DU, j + 1);
-                AT(DU, j + 1) = -f * AT(DU, j + 1);
-            }
+            const double f = dcur / lj;
             AT(IP, j) = j + 1;
+            AT(DD, j) = guard(lj);
+            AT(DL, j) = f;
+            AT(DU, j) = dn;
+            AT(DU2, j) = un;
+            dcur = ucur - f * dn;
+            ucur = -f * un;
         }
     }
-    for (int j = 0; j < m; ++j)
-        if (fabs(AT(DD, j)) < tiny) AT(DD, j) = copysign(tiny, AT(DD, j) == 0.0 ? 1.0 : AT(DD, j));
+    AT(DD, m - 1) = guard(dcur);
     for (int j = 0; j < m; ++j) AT(ZT, j) = hash_unit((unsigned)i, (unsigned)j);
     for (int it = 0; it < 2; ++it) {
+        // forward: apply the row interchanges and L^{-1} (carrying the row
+        // being eliminated)
+        double bcur = AT(ZT, 0);
 #pragma unroll 8
         for (int j = 0; j + 1 < m; ++j) {
-            const double bj = AT(ZT, j), bj1 = AT(ZT, j + 1);
+            const double bn = AT(ZT, j + 1);
+            const double l = AT(DL, j);
             if (AT(IP, j) == j) {
-                AT(ZT, j + 1) = bj1 - AT(DL, j) * bj;
+                AT(ZT, j) = bcur;
+                bcur = bn - l * bcur;
             } else {
-                AT(ZT, j) = bj1;
-                AT(ZT, j + 1) = bj - AT(DL, j) * bj1;
+                AT(ZT, j) = bn;
+                bcur = bcur - l * bn;
             }
         }
-        AT(ZT, m - 1) /= AT(DD, m - 1);
-        if (m >= 2) AT(ZT, m - 2) = (AT(ZT, m - 2) - AT(DU, m - 2) * AT(ZT, m - 1)) / AT(DD, m - 2);
+        // back substitution with U (diagonal, first and second superdiagonal)
+        double z1 = bcur / AT(DD, m - 1);
+        AT(ZT, m - 1) = z1;
+        double z2 = 0.0;
+        if (m >= 2) {
+            const double zz = (AT(ZT, m - 2) - AT(DU, m - 2) * z1) / AT(DD, m - 2);
+            AT(ZT, m - 2) = zz;
+            z2 = z1;
+            z1 = zz;
+        }
+        double mx = fmax(fabs(z1), fabs(z2));
 #pragma unroll 8
-        for (int j = m - 3; j >= 0; --j)
-            AT(ZT, j) = (AT(ZT, j) - AT(DU, j) * AT(ZT, j + 1) - AT(DU2, j) * AT(ZT, j + 2)) / AT(DD, j);
-        double mx = 0.0;
-        for (int j = 0; j < m; ++j) mx = fmax(mx, fabs(AT(ZT, j)));
+        for (int j = m - 3; j >= 0; --j) {
+            const double zz = (AT(ZT, j) - AT(DU, j) * z1 - AT(DU2, j) * z2) / AT(DD, j);
+            AT(ZT, j) = zz;
+            z2 = z1;
+            z1 = zz;
+            mx = fmax(mx, fabs(zz));
+        }
         const double sc = (mx > 0.0) ? 1.0 / mx : 1.0;
         double nr = 0.0;
         for (int j = 0; j < m; ++j) {
@@ -602,28 +620,166 @@ __global__ __launch_bounds__(256) void backtransform_kernel(int m, int k, const 
         const int j = lane + 64 * q;
         z[q] = (j < m) ? ZT[(size_t)j * k + i] : 0.0;
     }
-    for (int kk = m - 3; kk >= 0; --kk) {
-        const double tk = tau[kk];
-        if (tk == 0.0) continue;
+    // Reflector rows are prefetched one step ahead into registers, so their
+    // load latency overlaps the previous reflector's dot product and update.
+    double vc[MAXQ], vn[MAXQ];
+    auto load_v = [&](int kk, double (&dst)[MAXQ]) {
         const double* v = Vh + (size_t)kk * m;  // v[j] valid for j >= kk + 1
-        double s = 0.0;
 #pragma unroll
         for (int q = 0; q < MAXQ; ++q) {
             const int j = lane + 64 * q;
-            if (j > kk && j < m) s = fma(v[j], z[q], s);
+            dst[q] = (j > kk && j < m) ? v[j] : 0.0;
         }
-        s = wave_sum(s) * tk;
+    };
+    if (m >= 3) load_v(m - 3, vc);
+    for (int kk = m - 3; kk >= 0; --kk) {
+        if (kk > 0) load_v(kk - 1, vn);
+        const double tk = tau[kk];
+        if (tk != 0.0) {
+            double s = 0.0;
 #pragma unroll
-        for (int q = 0; q < MAXQ; ++q) {
-            const int j = lane + 64 * q;
-            if (j > kk && j < m) z[q] = fma(-s, v[j], z[q]);
+            for (int q = 0; q < MAXQ; ++q) s = fma(vc[q], z[q], s);
+            s = wave_sum(s) * tk;
+#pragma unroll
+            for (int q = 0; q < MAXQ; ++q) z[q] = fma(-s, vc[q], z[q]);
         }
+#pragma unroll
+        for (int q = 0; q < MAXQ; ++q) vc[q] = vn[q];
     }
 #pragma unroll
     for (int q = 0; q < MAXQ; ++q) {
         const int j = lane + 64 * q;
         if (j < m) Z[(size_t)j * k + i] = z[q];
     }
+}
+
+// ---------------------------------------------------------------------------
+// Householder tridiagonalization by G cooperating workgroups (a cooperative
+// launch, all resident): workgroup g keeps rows [g R, g R + R) of the matrix
+// in its LDS, so the trailing matrix is never re-read from memory. Per
+// reflector k:
+//   A. every workgroup publishes its part of column k (xcol) and of
+//      sigma^2 = sum_{i >= k+2} a_ik^2 (partA[g]);        grid barrier
+//   B. every workgroup forms the same Householder scalars and v (from xcol,
+//      partials summed in order), then p_i = tau (A22 v)_i for its rows
+//      (xp) and its part of p^T v (partB[g]);             grid barrier
+//   C. w = p - (tau/2)(p^T v) v, and each workgroup applies
+//      A22 -= v w^T + w v^T to its own rows.
+// Every workgroup runs the same number of barriers. Outputs as tridiag_kernel.
+constexpr int kCoopThreads = 1024;
+
+__device__ double block_sum_1024(double v, double* sh) {
+    v = wave_sum(v);
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    if (lane == 0) sh[wid] = v;
+    __syncthreads();
+    double s = 0.0;
+#pragma unroll
+    for (int q = 0; q < kCoopThreads / 64; ++q) s += sh[q];
+    __syncthreads();
+    return s;
+}
+
+__global__ __launch_bounds__(kCoopThreads) void tridiag_coop_kernel(int m, int R, const double* __restrict__ Ag,
+                                                                    double* __restrict__ d, double* __restrict__ e,
+                                                                    double* __restrict__ tau,
+                                                                    double* __restrict__ Vh,
+                                                                    double* __restrict__ xcol,
+                                                                    double* __restrict__ xp,
+                                                                    double* __restrict__ partA,
+                                                                    double* __restrict__ partB) {
+    namespace cg = cooperative_groups;
+    extern __shared__ double lds[];
+    __shared__ double sred[kCoopThreads / 64];
+    cg::grid_group grid = cg::this_grid();
+    const int g = blockIdx.x, G = gridDim.x, t = threadIdx.x;
+    const int r0 = g * R, r1 = min(m, r0 + R), nr = max(0, r1 - r0);
+    double* Al = lds;                    // nr x m, row-major
+    double* v = Al + (size_t)R * m;      // m
+    double* w = v + m;                   // m
+    for (size_t q = t; q < (size_t)nr * m; q += kCoopThreads) Al[q] = Ag[(size_t)r0 * m + q];
+    __syncthreads();
+    const int row_sub = t >> 5, lane32 = t & 31;  // 32 row groups of 32 lanes
+    for (int k = 0; k + 2 < m; ++k) {
+        // A: column k of my rows below the diagonal, partial sigma^2
+        double s = 0.0;
+        for (int i = max(r0, k + 1) + t; i < r1; i += kCoopThreads) {
+            const double x = Al[(size_t)(i - r0) * m + k];
+            xcol[i] = x;
+            if (i >= k + 2) s = fma(x, x, s);
+        }
+        s = block_sum_1024(s, sred);
+        if (t == 0) {
+            partA[g] = s;
+            if (k >= r0 && k < r1) d[k] = Al[(size_t)(k - r0) * m + k];
+        }
+        __threadfence();
+        grid.sync();
+        // B: scalars, v, p = tau A22 v on my rows
+        double sigma2 = 0.0;
+        for (int q = 0; q < G; ++q) sigma2 += partA[q];
+        const double alpha = xcol[k + 1];
+        double tk = 0.0, beta = alpha, scale = 0.0;
+        if (sigma2 > 0.0) {
+            beta = -copysign(sqrt(alpha * alpha + sigma2), alpha);
+            tk = (beta - alpha) / beta;
+            scale = 1.0 / (alpha - beta);
+        }
+        for (int i = k + 1 + t; i < m; i += kCoopThreads)
+            v[i] = (i == k + 1) ? 1.0 : (tk != 0.0 ? xcol[i] * scale : 0.0);
+        __syncthreads();
+        if (g == 0) {
+            if (t == 0) {
+                e[k] = beta;
+                tau[k] = tk;
+            }
+            for (int i = k + 1 + t; i < m; i += kCoopThreads) Vh[(size_t)k * m + i] = v[i];
+        }
+        double pv = 0.0;
+        const int rb = max(r0, k + 1);
+        for (int i0 = rb; i0 < r1; i0 += 32) {
+            const int i = i0 + row_sub;
+            double acc = 0.0;
+            if (i < r1 && tk != 0.0) {
+                const double* arow = Al + (size_t)(i - r0) * m;
+                for (int j = k + 1 + lane32; j < m; j += 32) acc = fma(arow[j], v[j], acc);
+            }
+#pragma unroll
+            for (int o = 16; o > 0; o >>= 1) acc += __shfl_down(acc, o, 32);
+            if (lane32 == 0 && i < r1) {
+                const double pi = tk * acc;
+                xp[i] = pi;
+                pv = fma(pi, v[i], pv);
+            }
+        }
+        pv = block_sum_1024(pv, sred);
+        if (t == 0) partB[g] = pv;
+        __threadfence();
+        grid.sync();
+        // C: w = p - K v and the rank-2 update of my rows
+        if (tk != 0.0) {
+            double pvs = 0.0;
+            for (int q = 0; q < G; ++q) pvs += partB[q];
+            const double Kc = 0.5 * tk * pvs;
+            for (int j = k + 1 + t; j < m; j += kCoopThreads) w[j] = xp[j] - Kc * v[j];
+            __syncthreads();
+            // 32 x 32 thread tile over (my rows, columns > k)
+            for (int i = rb + row_sub; i < r1; i += 32) {
+                const double vi = v[i], wi = w[i];
+                double* arow = Al + (size_t)(i - r0) * m;
+                for (int j = k + 1 + lane32; j < m; j += 32) arow[j] -= vi * w[j] + wi * v[j];
+            }
+        }
+        __syncthreads();
+    }
+    if (t == 0 && m >= 2) {
+        if (m - 2 >= r0 && m - 2 < r1) d[m - 2] = Al[(size_t)(m - 2 - r0) * m + (m - 2)];
+        if (m - 1 >= r0 && m - 1 < r1) {
+            e[m - 2] = Al[(size_t)(m - 1 - r0) * m + (m - 2)];
+            d[m - 1] = Al[(size_t)(m - 1 - r0) * m + (m - 1)];
+        }
+    }
+    if (t == 0 && m == 1) d[0] = Al[0];
 }
 
 // ---------------------------------------------------------------------------
@@ -773,8 +929,9 @@ size_t syev_work_doubles(int m) {
     // and transform of the orthonormalization (2 m^2), its Gram scratch, the
     // Cholesky work (2 m^2 + 2m) and info words.
     const size_t mm = (size_t)m * m;
+    // + the cooperative tridiagonalization's exchange vectors (2m + 2 x 128)
     return 4 * (size_t)m + 16 + mm + 2 * mm + 5 * mm + 2 * mm + gram_scratch_doubles(m, m, m) +
-           2 * mm + 2 * (size_t)m + 2 * (size_t)m + 64;
+           2 * mm + 2 * (size_t)m + 2 * (size_t)m + 64 + 2 * (size_t)m + 256;
 }
 
 hipError_t launch_syev_lowest(hipStream_t st, int m, int k, double* A, double* w, double* Z,
@@ -796,7 +953,26 @@ hipError_t launch_syev_lowest(hipStream_t st, int m, int k, double* A, double* w
     double* infod = cwork + 2 * mm + 2 * (size_t)m;
     int* infoi = reinterpret_cast<int*>(infod + 8);
     const size_t lds = (mm <= (size_t)kLdsDoubles) ? sizeof(double) * mm : 0;
-    if (m <= 112) {
+    bool done = false;
+    if (m > 288) {
+        // Rows per workgroup so that R m + 2m doubles fit 150 KB of LDS.
+        const int R = std::max(1, (int)((150 * 1024 / sizeof(double) - 2 * (size_t)m) / m));
+        const int G = (m + R - 1) / R;
+        double* xcol = infod + 64;
+        double* xp = xcol + m;
+        double* partA = xp + m;
+        double* partB = partA + 128;
+        if (G <= 128) {
+            const size_t clds = sizeof(double) * ((size_t)R * m + 2 * (size_t)m);
+            int mm_i = m, R_i = R;
+            void* args[] = {&mm_i, &R_i, &A, &d, &e, &tau, &Vh, &xcol, &xp, &partA, &partB};
+            done = hipLaunchCooperativeKernel((void*)tridiag_coop_kernel, dim3(G), dim3(kCoopThreads), args, clds,
+                                              st) == hipSuccess;
+            if (!done) (void)hipGetLastError();  // fall back to the single-workgroup kernels
+        }
+    }
+    if (done) {
+    } else if (m <= 112) {
         hipLaunchKernelGGL(tridiag_kernel, dim3(1), dim3(kTri), lds, st, m, m, A, d, e, tau, Vh);
     } else {
         // the first m - 224 reflectors in L2, the trailing block (order <= 224)
