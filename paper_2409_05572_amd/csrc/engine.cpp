@@ -495,8 +495,9 @@ struct Solver {
         if (k < n_ev) return SE_ERR_BREAKDOWN;
         ST(spmm(X, AX, k));
         ST(rr_plain(k));
-        int pw = 0;      // width of P
-        int axp_q = -1;  // order of the carried [X, P]^T A [X, P] (ws.axp), -1 = none
+        int pw = 0;            // width of P
+        int axp_q = -1;        // order of the carried [X, P]^T A [X, P] (ws.axp), -1 = none
+        bool ap_valid = true;  // AP = A P for the current P
         if (p0 > 0) {
             const Segs Xs = seg1(X, k);
             for (int pass = 0; pass < 2; ++pass) {
@@ -556,22 +557,21 @@ struct Solver {
 
             act_hl = act;
             if (want_expand && have_drop) {
-                // S_drop <- S_drop - S (S^T S_drop), twice; orthonormalize; the
-                // stored images A S_drop receive the same transforms.
+                // S_drop <- S_drop - S (S^T S_drop), twice; orthonormalize;
+                // then its images A S_drop by one SpMM.
                 int d0 = dx + dp;
+                const Segs S = seg3(X, k, P, pw, W, a);
                 for (int pass = 0; pass < 2; ++pass) {
-                    const Segs S = seg3(X, k, P, pw, W, a);
-                    const Segs AS = seg3(AX, k, AP, pw, AW, a);
                     ST(gram(S, seg1(Sd, d0), 0, ws.G.as<double>()));
                     ST(update(S, ws.G.as<double>(), d0, seg1(Sd, d0), -1.0, 1.0));
-                    ST(update(AS, ws.G.as<double>(), d0, seg1(ASd, d0), -1.0, 1.0));
                 }
-                const Segs S = seg3(X, k, P, pw, W, a);
-                const Segs AS = seg3(AX, k, AP, pw, AW, a);
-                ST(cholqr(Sd, d0, &ASd, &kept, &S, &AS));
+                ST(cholqr(Sd, d0, nullptr, &kept, &S));
                 int dxk = 0;
                 for (int v : kept) dxk += (v < dx);
                 const int dpk = d0 - dxk;
+                if (d0 > 0) ST(spmm(Sd, ASd, d0));
+                if (!ap_valid && pw > 0) ST(spmm(P, AP, pw));
+                ap_valid = true;
                 HC(launch_copy_cols(st, n, Sd, ld, 0, X, ld, k, dxk));
                 HC(launch_copy_cols(st, n, ASd, ld, 0, AX, ld, k, dxk));
                 HC(launch_copy_cols(st, n, Sd, ld, dxk, P, ld, pw, dpk));
@@ -596,6 +596,8 @@ struct Solver {
                 HC(launch_assemble_ap(st, m, axp_q, ws.axp.as<double>(), ws.gw.as<double>(),
                                       ws.G.as<double>()));
             } else {
+                if (!ap_valid && pw > 0) ST(spmm(P, AP, pw));
+                ap_valid = true;
                 ST(gram(S, AS, 1, ws.G.as<double>()));
             }
             HC(launch_copy_cols(st, m, ws.G.as<double>(), m, 0, ws.apc.as<double>(), m, 0, m));
@@ -611,19 +613,18 @@ struct Solver {
             ST(hl_coefficients(m, k, ahl, rPv));
             ST(toc(SE_K_SMALL, 16.0 * m * (k + ahl), 8.0 * m * (double)k * ahl));
             const int rP = rPv;
+            // New basis over n; its image A X by one SpMM (no carried images:
+            // as cheap as updating them for sparse A, and exact each step).
+            // A P is formed only when a whole A_p or an expansion needs it.
             Segs O = make_segs(ld);
             push_seg(O, Xn, k);
             push_seg(O, Pn, rP);
             ST(update(S, ws.C.as<double>(), k + rP, O, 1.0, 0.0));
-            Segs AO = make_segs(ld);
-            push_seg(AO, AXn, k);
-            push_seg(AO, APn, rP);
-            ST(update(AS, ws.C.as<double>(), k + rP, AO, 1.0, 0.0));
             std::swap(X, Xn);
             std::swap(P, Pn);
-            std::swap(AX, AXn);
-            std::swap(AP, APn);
             pw = rP;
+            ST(spmm(X, AX, k));
+            ap_valid = false;
             // carried [X, P]^T A [X, P] = C^T A_p C (small products)
             {
                 const int q = k + rP;
@@ -639,9 +640,7 @@ struct Solver {
                 dp = std::max(0, pw - n_es);
                 dp = std::min(dp, ld - dx);  // S_drop must fit one panel
                 HC(launch_copy_cols(st, n, X, ld, n_es, Sd, ld, 0, dx));
-                HC(launch_copy_cols(st, n, AX, ld, n_es, ASd, ld, 0, dx));
                 HC(launch_copy_cols(st, n, P, ld, n_es, Sd, ld, dx, dp));
-                HC(launch_copy_cols(st, n, AP, ld, n_es, ASd, ld, dx, dp));
                 // keep the rows and columns of X(:, 0:n_es) and P(:, 0:pw') in Axp
                 const int pk = std::min(pw, n_es);
                 std::vector<int> keep;
@@ -1075,16 +1074,14 @@ struct Solver {
             push_seg_t(O, (const T*)Xnl, kk);
             push_seg_t(O, (const T*)Pnl, rP);
             ST(lp_update(S, ws.lpC.as<double>(), kk + rP, O, 1.0, 0.0));
-            SegsT<T> AO = make_segs_t<T>(ld);
-            push_seg_t(AO, (const T*)AXnl, kk);
-            push_seg_t(AO, (const T*)APnl, rP);
-            ST(lp_update(AS, ws.lpC.as<double>(), kk + rP, AO, 1.0, 0.0));
             std::swap(Xl, Xnl);
             std::swap(Pl, Pnl);
-            std::swap(AXl, AXnl);
-            std::swap(APl, APnl);
             k = kk;
             pw = rP;
+            // images of the new X and P by SpMM (cheaper than updating them
+            // with the m-column coefficient matrix for sparse A)
+            ST(lp_spmm(Xl, AXl, k));
+            if (pw > 0) ST(lp_spmm(Pl, APl, pw));
             if (ctl.ifshrink(j) && k > n_es) {
                 dx = k - n_es;
                 dp = std::max(0, pw - n_es);

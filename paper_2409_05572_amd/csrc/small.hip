@@ -102,6 +102,11 @@ __global__ __launch_bounds__(kSmall) void chol_drop_kernel(int a, const double* 
     __syncthreads();
 
     double minpiv = DBL_MAX;
+    // Right-looking elimination. The scaled pivot column is staged in LDS
+    // (s_col), and the rank-1 update of the lower triangle runs as wave-rows
+    // over contiguous column ranges: one load and one store per element.
+    double* s_col = s_dr;  // reused: R^{-1}'s diagonal is formed after the loop
+    const int lane = t & 63, wrow = t >> 6, nwave = nth >> 6;
     for (int j = 0; j < a; ++j) {
         double d = F[(size_t)j * a + j];
         const bool drop = can_drop && (!(d > drop_tol2) || s_D[j] == 0.0);
@@ -118,16 +123,20 @@ __global__ __launch_bounds__(kSmall) void chol_drop_kernel(int a, const double* 
         const double piv = sqrt(d);
         const double inv = 1.0 / piv;
         minpiv = fmin(minpiv, d);
-        const int rem = a - j - 1;
-        for (int i = j + 1 + t; i < a; i += nth) F[(size_t)i * a + j] *= inv;
+        for (int i = j + 1 + t; i < a; i += nth) {
+            const double l = F[(size_t)i * a + j] * inv;
+            F[(size_t)i * a + j] = l;
+            s_col[i] = l;
+        }
         if (t == 0) {
             s_dl[j] = piv;
             s_pos[j] = 0;
         }
         __syncthreads();
-        for (size_t e = t; e < (size_t)rem * rem; e += nth) {
-            const int i = j + 1 + (int)(e / rem), i2 = j + 1 + (int)(e % rem);
-            if (i2 <= i) F[(size_t)i * a + i2] -= F[(size_t)i * a + j] * F[(size_t)i2 * a + j];
+        for (int i = j + 1 + wrow; i < a; i += nwave) {
+            const double li = s_col[i];
+            double* frow = F + (size_t)i * a;
+            for (int i2 = j + 1 + lane; i2 <= i; i2 += 64) frow[i2] -= li * s_col[i2];
         }
         __syncthreads();
     }
