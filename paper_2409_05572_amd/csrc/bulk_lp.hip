@@ -215,7 +215,7 @@ __global__ __launch_bounds__(kThreads) void spmm_lp_kernel(int n, const int* __r
                                                            const T* __restrict__ X, long long ldx,
                                                            T* __restrict__ Y, long long ldy, int w) {
     constexpr int GPB = kThreads / LPR;
-    const int blk = xcd_remap(blockIdx.x, gridDim.x);
+    const int blk = blockIdx.x;  // round-robin over XCDs, as in the FP64 product
     const int sub = threadIdx.x / LPR;
     const int lane = threadIdx.x % LPR;
     const int rbeg = (blk * GPB + sub) * SPR;

@@ -140,7 +140,8 @@ def test_gram_is_deterministic(ctx):
 
 @pytest.mark.parametrize("n,K,N,beta", [(1, 1, 1, 0.0), (1000, 1, 1, 1.0), (4097, 37, 69, 0.0),
                                         (20000, 288, 192, 0.0), (5003, 250, 250, 1.0),
-                                        (64, 96, 97, 1.0)])
+                                        (64, 96, 97, 1.0), (70001, 96, 96, 1.0), (65601, 250, 69, 0.0),
+                                        (66000, 5, 3, 1.0), (65536, 288, 128, 0.0)])
 def test_update_matches_definition(ctx, n, K, N, beta):
     from paper_2409_05572_amd import api
 
