@@ -158,6 +158,7 @@ def main():
             "iterations": infos[-1].iterations, "n_shrinks": infos[-1].n_shrinks,
             "n_expands": infos[-1].n_expands, "max_stop_ratio": infos[-1].max_stop_ratio,
             "converged": infos[-1].converged, "low_precision_iterations": infos[-1].lp_iterations,
+            "reprojections": infos[-1].n_reprojections,
         },
     }
     lam_np = lam.cpu().numpy()

@@ -130,7 +130,9 @@ typedef struct se_info {
     int32_t hip_error;      /* first failing hipError_t, 0 if none */
     int32_t history_len;    /* rows written to params.history */
     int32_t lp_iterations;  /* mixed precision: iterations of the low-precision phase */
-    int32_t lp_reserved;
+    int32_t n_reprojections; /* LOBPCG: iterations whose residual block needed a second
+                                projection against [X, P] (a column kept < 1/2 of its
+                                squared norm after the first) */
 } se_info;
 
 /* Fill *p with the defaults of the paper's experiments (Section 6.1-6.2):

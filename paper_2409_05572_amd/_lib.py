@@ -50,7 +50,7 @@ class SeInfo(C.Structure):
         ("kern_flops", C.c_double * 8), ("kern_calls", C.c_int32 * 8),
         ("workspace_bytes", C.c_uint64),
         ("hip_error", C.c_int32), ("history_len", C.c_int32),
-        ("lp_iterations", C.c_int32), ("lp_reserved", C.c_int32),
+        ("lp_iterations", C.c_int32), ("n_reprojections", C.c_int32),
     ]
 
 

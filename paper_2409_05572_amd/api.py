@@ -112,6 +112,7 @@ class SolveInfo:
     kern_flops: tuple = ()
     kern_calls: tuple = ()
     lp_iterations: int = 0
+    n_reprojections: int = 0
 
 
 PRECISIONS = {"fp64": _lib.SE_FP64, "fp32": _lib.SE_FP32_MIXED, "bf16": _lib.SE_BF16_MIXED}
@@ -176,7 +177,7 @@ def solve(ctx: Context, A: Matrix, X0, n_ev, n_extra, history_cap=0, **kw):
                     info.max_stop_ratio, info.max_paper_ratio, info.time_ms,
                     int(info.workspace_bytes), hist[: info.history_len].copy(),
                     tuple(info.kern_ms), tuple(info.kern_bytes), tuple(info.kern_flops),
-                    tuple(info.kern_calls), info.lp_iterations)
+                    tuple(info.kern_calls), info.lp_iterations, info.n_reprojections)
     return lam, V, out
 
 
@@ -191,7 +192,7 @@ def _info_of(st, info, hist):
                      info.max_stop_ratio, info.max_paper_ratio, info.time_ms,
                      int(info.workspace_bytes), hist[: info.history_len].copy(),
                      tuple(info.kern_ms), tuple(info.kern_bytes), tuple(info.kern_flops),
-                     tuple(info.kern_calls), info.lp_iterations)
+                     tuple(info.kern_calls), info.lp_iterations, info.n_reprojections)
 
 
 class Server:

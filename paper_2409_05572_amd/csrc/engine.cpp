@@ -84,7 +84,7 @@ struct Solver {
     double *Xn = nullptr, *Pn = nullptr, *AXn = nullptr, *APn = nullptr;
     double *Sd = nullptr, *ASd = nullptr, *T1 = nullptr, *T2 = nullptr;
 
-    int iters = 0, n_shr = 0, n_exp = 0, hist_len = 0;
+    int iters = 0, n_shr = 0, n_exp = 0, hist_len = 0, n_reproj = 0;
     int j_off = 0;       // iterations of an earlier (low-precision) phase
     int lp_iters = 0;    // iterations of the low-precision phase
     bool lp_done = false;  // the low-precision phase met the stopping test itself
@@ -175,6 +175,7 @@ struct Solver {
         HC(ws.h_info.ensure(sizeof(double) * (mmax + 16)));
         HC(ws.h_act.ensure(sizeof(int) * (mmax + 8)));
         HC(ws.h_act_hl.ensure(sizeof(int) * (mmax + 8)));
+        HC(ws.h_diag.ensure(sizeof(double) * (mmax + 8)));
         return SE_OK;
     }
 
@@ -335,8 +336,15 @@ struct Solver {
     // panel was made orthogonal to; after a pass with a pivot below 1e-8 the
     // kept columns carry amplified rounding along them, so the projection is
     // repeated before the next pass.
+    // `ref_norm2` (with `reproject`): squared column norms of the panel before
+    // its one projection against `against`. If a column kept less than half of
+    // its squared norm, one projection is not enough (the criterion of Kahan
+    // and Parlett for classical Gram-Schmidt): *reproject is set and the call
+    // returns with the panel untouched, for the caller to project again.
     se_status cholqr(double*& w_panel, int& w, double** companion, std::vector<int>* kept_out,
-                     const Segs* against = nullptr, const Segs* against_img = nullptr) {
+                     const Segs* against = nullptr, const Segs* against_img = nullptr,
+                     const double* ref_norm2 = nullptr, bool* reproject = nullptr) {
+        if (reproject) *reproject = false;
         std::vector<int> map(w);
         for (int i = 0; i < w; ++i) map[i] = i;
         int passes = 2;
@@ -365,7 +373,19 @@ struct Solver {
             ST(toc(SE_K_SMALL, 16.0 * w * w, w * w * (double)w));
             HC(hipMemcpyAsync(ws.h_info.p, ws.info.p, sizeof(double) * (w + 16), hipMemcpyDeviceToHost,
                               st));
+            const bool test_norms = ref_norm2 && reproject && pass == 0;
+            if (test_norms)
+                HC(hipMemcpy2DAsync(ws.h_diag.p, sizeof(double), ws.G.as<double>(), sizeof(double) * (w + 1),
+                                    sizeof(double), w, hipMemcpyDeviceToHost, st));
             ST(sync());
+            if (test_norms) {
+                const double* dg = ws.h_diag.as<double>();
+                for (int q = 0; q < w; ++q)
+                    if (dg[q] < 0.5 * ref_norm2[q]) {
+                        *reproject = true;
+                        return SE_OK;
+                    }
+            }
             const int* hi = ws.h_info.as<int>();
             const double minpiv = ws.h_info.as<double>()[(w + 8) / 2 + 4];
             const int r = hi[0];
@@ -547,12 +567,26 @@ struct Solver {
             ST(tic());
             HC(launch_form_w(st, n, X, AX, ld, ws.theta.as<double>(), ws.act.as<int>(), a, W, ld));
             ST(toc(SE_K_RESID, 24.0 * n * a, 2.0 * n * a));
+            // By the Galerkin condition of the last Rayleigh-Ritz step R is
+            // orthogonal to [X, P] up to rounding, so one projection usually
+            // suffices; a second one runs when a column lost more than half of
+            // its squared norm (its squared norm is the residual norm above).
             const Segs XP = seg3(X, k, P, pw, nullptr, 0);
-            for (int pass = 0; pass < 2; ++pass) {
-                ST(gram(XP, seg1(W, a), 0, ws.G.as<double>()));
-                ST(update(XP, ws.G.as<double>(), a, seg1(W, a), -1.0, 1.0));
+            ST(gram(XP, seg1(W, a), 0, ws.G.as<double>()));
+            ST(update(XP, ws.G.as<double>(), a, seg1(W, a), -1.0, 1.0));
+            {
+                const double* nr = ws.h_norms.as<double>();
+                std::vector<double> wn2(a);
+                for (int q = 0; q < a; ++q) wn2[q] = nr[act[q]];
+                bool again = false;
+                ST(cholqr(W, a, nullptr, nullptr, &XP, nullptr, wn2.data(), &again));
+                if (again) {
+                    ++n_reproj;
+                    ST(gram(XP, seg1(W, a), 0, ws.G.as<double>()));
+                    ST(update(XP, ws.G.as<double>(), a, seg1(W, a), -1.0, 1.0));
+                    ST(cholqr(W, a, nullptr, nullptr, &XP));
+                }
             }
-            ST(cholqr(W, a, nullptr, nullptr, &XP));
             if (a > 0) ST(spmm(W, AW, a));
 
             act_hl = act;
@@ -1326,6 +1360,7 @@ se_status solve(se_ctx* ctx, const se_matrix* A, const se_params* prm, const dou
         info->hip_error = (int)s.herr;
         info->history_len = s.hist_len;
         info->lp_iterations = s.lp_iters;
+        info->n_reprojections = s.n_reproj;
         if (st < 0) {
             info->max_stop_ratio = s.last_stop;
             info->max_paper_ratio = s.last_r;

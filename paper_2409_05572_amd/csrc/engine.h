@@ -70,7 +70,7 @@ struct Workspace {
     DevBuf hlB, hlY, hlG, hlQ;
     DevBuf lpM, lpT, lpQ, lpB, lpE, lpC;  // generalized Rayleigh-Ritz (m x m each)
     DevBuf apc, axp, axq, gw, idx;        // carried [X, P]^T A [X, P] (m x m each; idx ints)
-    HostBuf h_norms, h_info, h_act, h_act_hl, h_theta;
+    HostBuf h_norms, h_info, h_act, h_act_hl, h_theta, h_diag;
     std::vector<hipEvent_t> events;  // pool for per-launch timing
     size_t device_bytes() const {
         size_t s = 0;
@@ -94,6 +94,7 @@ struct Workspace {
         h_act.release();
         h_act_hl.release();
         h_theta.release();
+        h_diag.release();
         for (hipEvent_t e : events) (void)hipEventDestroy(e);
         events.clear();
     }
