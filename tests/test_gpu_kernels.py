@@ -141,7 +141,10 @@ def test_gram_is_deterministic(ctx):
 @pytest.mark.parametrize("n,K,N,beta", [(1, 1, 1, 0.0), (1000, 1, 1, 1.0), (4097, 37, 69, 0.0),
                                         (20000, 288, 192, 0.0), (5003, 250, 250, 1.0),
                                         (64, 96, 97, 1.0), (70001, 96, 96, 1.0), (65601, 250, 69, 0.0),
-                                        (66000, 5, 3, 1.0), (65536, 288, 128, 0.0)])
+                                        (66000, 5, 3, 1.0), (65536, 288, 128, 0.0),
+                                        # tall panels, ragged last row block
+                                        (600001, 96, 96, 1.0), (300001, 250, 69, 0.0),
+                                        (600001, 5, 3, 1.0), (300007, 288, 192, 0.0)])
 def test_update_matches_definition(ctx, n, K, N, beta):
     from paper_2409_05572_amd import api
 
@@ -155,6 +158,30 @@ def test_update_matches_definition(ctx, n, K, N, beta):
     ref = beta * O0[:, :N] + U[:, :K] @ Cm
     bound = 4 * (K + 1) * 1.2e-16 * (beta * np.abs(O0[:, :N]) + np.abs(U[:, :K]) @ np.abs(Cm))
     assert np.all(np.abs(got - ref) <= bound + 1e-300)
+
+
+@pytest.mark.parametrize("K,N,beta", [(96, 96, 1.0), (288, 192, 0.0), (37, 5, 1.0), (250, 69, 1.0)])
+def test_update_rows_do_not_depend_on_the_row_range(ctx, K, N, beta):
+    """A tall update and the same rows updated on their own (other row-block
+    boundaries, other grid) agree bitwise: every output has one fixed
+    summation order."""
+    import torch
+
+    from paper_2409_05572_amd import api
+
+    n, h = 600001, 5000
+    g = torch.Generator(device="cuda").manual_seed(K * 7 + N)
+    ldu, ldo = K + 3 + (K + 3) % 2, N + 1 + (N + 1) % 2  # even leading dimensions, padded
+    U = torch.randn((n, ldu), dtype=torch.float64, device="cuda", generator=g)
+    Cm = torch.randn((K, N), dtype=torch.float64, device="cuda", generator=g)
+    O0 = torch.randn((n, ldo), dtype=torch.float64, device="cuda", generator=g)
+    full = O0.clone()
+    api.update(ctx, U, K, Cm, N, full, beta)
+    for sl in (slice(0, h), slice(n - h, n), slice(123456, 123456 + 77)):
+        part = O0[sl].clone()
+        api.update(ctx, U[sl], K, Cm, N, part, beta)
+        assert torch.equal(part[:, :N], full[sl][:, :N])
+    assert torch.equal(full[:, N:], O0[:, N:])  # padding columns untouched
 
 
 def _sym_with_spectrum(m, seed, clustered):
