@@ -203,23 +203,46 @@ hipError_t spmm_launch(hipStream_t st, int n, const int* rowptr, const int* col,
 
 // ---------------------------------------------------------------------------
 // Fixed-order sum of per-chunk partial vectors: out[i] = sum_c part[c * L + i].
+// out[i] = sum_c part[c L + i]. 32 threads per output, 8 outputs per
+// workgroup (consecutive threads take consecutive outputs, so each chunk's
+// read is contiguous): thread g sums chunks g, g + 32, ... in increasing
+// order and a fixed tree combines the 32 sums (deterministic).
+constexpr int kSumG = 32;
 __global__ __launch_bounds__(kThreads) void sum_partials_kernel(int L, int nchunks,
                                                                 const double* __restrict__ part,
                                                                 double* __restrict__ out) {
-    const int i = blockIdx.x * kThreads + threadIdx.x;
-    if (i >= L) return;
-    double s = 0.0;
-    for (int c = 0; c < nchunks; ++c) s += part[(long long)c * L + i];
-    out[i] = s;
+    constexpr int OPB = kThreads / kSumG;
+    __shared__ double sh[kThreads];
+    const int o = threadIdx.x % OPB, g = threadIdx.x / OPB;
+    const int i = blockIdx.x * OPB + o;
+    double s0 = 0.0, s1 = 0.0;
+    if (i < L) {
+        int c = g;
+        for (; c + kSumG < nchunks; c += 2 * kSumG) {
+            s0 += part[(long long)c * L + i];
+            s1 += part[(long long)(c + kSumG) * L + i];
+        }
+        if (c < nchunks) s0 += part[(long long)c * L + i];
+    }
+    sh[threadIdx.x] = s0 + s1;
+    __syncthreads();
+#pragma unroll
+    for (int h = kSumG / 2; h > 0; h >>= 1) {
+        if (g < h) sh[g * OPB + o] += sh[(g + h) * OPB + o];
+        __syncthreads();
+    }
+    if (g == 0 && i < L) out[i] = sh[o];
 }
 
 // Residual and column norms: per chunk of rows, sum (ax - lam x)^2 and x^2.
+// With R != nullptr the residual rows are written there as well.
 __global__ __launch_bounds__(kThreads) void resid_norms_kernel(long long n, const double* __restrict__ X,
                                                                const double* __restrict__ AX,
                                                                long long ld, int k,
                                                                const double* __restrict__ lam,
                                                                long long rows_per_chunk,
-                                                               double* __restrict__ part) {
+                                                               double* __restrict__ part,
+                                                               double* __restrict__ R, long long ldr) {
     __shared__ double sr[kThreads];
     __shared__ double sx[kThreads];
     const int chunk = blockIdx.x;
@@ -236,6 +259,7 @@ __global__ __launch_bounds__(kThreads) void resid_norms_kernel(long long n, cons
             for (long long r = r0 + g; r < r1; r += ngrp) {
                 const double x = X[r * ld + c];
                 const double y = AX[r * ld + c] - l * x;
+                if (R) R[r * ldr + c] = y;
                 ar = fma(y, y, ar);
                 axx = fma(x, x, axx);
             }
@@ -259,6 +283,7 @@ __global__ __launch_bounds__(kThreads) void resid_norms_kernel(long long n, cons
             for (long long r = r0; r < r1; ++r) {
                 const double x = X[r * ld + c];
                 const double y = AX[r * ld + c] - l * x;
+                if (R) R[r * ldr + c] = y;
                 ar = fma(y, y, ar);
                 axx = fma(x, x, axx);
             }
@@ -280,6 +305,19 @@ __global__ __launch_bounds__(kThreads) void form_w_kernel(long long n, const dou
         const int jj = (int)(e - r * a);
         const int c = act[jj];
         W[r * ldw + jj] = AX[r * ld + c] - lam[c] * X[r * ld + c];
+    }
+}
+
+__global__ __launch_bounds__(kThreads) void gather_cols_kernel(long long n, const double* __restrict__ src,
+                                                               long long lds, const int* __restrict__ idx,
+                                                               int a, double* __restrict__ dst,
+                                                               long long ldd) {
+    const long long total = n * a;
+    for (long long e = (long long)blockIdx.x * kThreads + threadIdx.x; e < total;
+         e += (long long)gridDim.x * kThreads) {
+        const long long r = e / a;
+        const int q = (int)(e - r * a);
+        dst[r * ldd + q] = src[r * lds + idx[q]];
     }
 }
 
@@ -510,40 +548,53 @@ __global__ __launch_bounds__(kThreads, 2) void gram_kernel(long long n, Segs U, 
             }
 }
 
+// C = sum over chunks of the partial Gram products. 16 threads per output
+// and 16 outputs per workgroup (consecutive threads on consecutive outputs):
+// thread g sums chunks g, g + 16, ... in increasing order and a fixed tree
+// combines the 16 sums (deterministic). Symmetric products: outputs of lower
+// tiles take the mirrored upper-tile sum, diagonal tiles average (i, j) and
+// (j, i).
+constexpr int kRedG = 16;
 __global__ __launch_bounds__(kThreads) void gram_reduce_kernel(int mu, int mv, int nchunks, int sym,
                                                                const double* __restrict__ part,
                                                                double* __restrict__ C) {
-    const long long idx = (long long)blockIdx.x * kThreads + threadIdx.x;
-    if (idx >= (long long)mu * mv) return;
-    const int i = (int)(idx / mv), j = (int)(idx % mv);
-    const long long stride = (long long)mu * mv;
-    // four interleaved partial sums combined in a fixed order (deterministic)
-    auto sum = [&](int a, int b) {
-        const double* p = part + (long long)a * mv + b;
-        double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
-        int c = 0;
-        for (; c + 4 <= nchunks; c += 4) {
-            s0 += p[(c + 0) * stride];
-            s1 += p[(c + 1) * stride];
-            s2 += p[(c + 2) * stride];
-            s3 += p[(c + 3) * stride];
+    constexpr int OPB = kThreads / kRedG;
+    __shared__ double sa[kThreads];
+    __shared__ double sb[kThreads];
+    const int o = threadIdx.x % OPB, g = threadIdx.x / OPB;
+    const long long total = (long long)mu * mv;
+    const long long idx = (long long)blockIdx.x * OPB + o;
+    const bool valid = idx < total;
+    int mode = 0;  // 0: sum (i, j); 1: sum (j, i); 2: average of both
+    long long p1 = idx, p2 = idx;
+    if (valid) {
+        const int i = (int)(idx / mv), j = (int)(idx % mv);
+        if (sym) {
+            const int ti = i / GT, tj = j / GT;
+            mode = ti < tj ? 0 : (ti > tj ? 1 : 2);
+            p2 = (long long)j * mv + i;
+            if (mode == 1) p1 = p2;
         }
-        for (; c < nchunks; ++c) s0 += p[c * stride];
-        return (s0 + s1) + (s2 + s3);
-    };
-    double v;
-    if (!sym) {
-        v = sum(i, j);
-    } else {
-        const int ti = i / GT, tj = j / GT;
-        if (ti < tj)
-            v = sum(i, j);
-        else if (ti > tj)
-            v = sum(j, i);
-        else
-            v = 0.5 * (sum(i, j) + sum(j, i));
     }
-    C[idx] = v;
+    double s1 = 0.0, s2 = 0.0;
+    if (valid) {
+        for (int c = g; c < nchunks; c += kRedG) {
+            s1 += part[(long long)c * total + p1];
+            if (mode == 2) s2 += part[(long long)c * total + p2];
+        }
+    }
+    sa[threadIdx.x] = s1;
+    sb[threadIdx.x] = s2;
+    __syncthreads();
+#pragma unroll
+    for (int h = kRedG / 2; h > 0; h >>= 1) {
+        if (g < h) {
+            sa[g * OPB + o] += sa[(g + h) * OPB + o];
+            sb[g * OPB + o] += sb[(g + h) * OPB + o];
+        }
+        __syncthreads();
+    }
+    if (g == 0 && valid) C[idx] = (mode == 2) ? 0.5 * (sa[o] + sb[o]) : sa[o];
 }
 
 }  // namespace
@@ -686,7 +737,8 @@ hipError_t launch_spmm(hipStream_t st, int n, const int* rowptr, const int* col,
 }
 
 hipError_t launch_resid_norms(hipStream_t st, long long n, const double* X, const double* AX,
-                              long long ld, int k, const double* lam, double* part, double* out) {
+                              long long ld, int k, const double* lam, double* part, double* out, double* R,
+                              long long ldr) {
     if (k <= 0) return hipSuccess;
     long long rows = 2048;
     long long nchunks = (n + rows - 1) / rows;
@@ -697,9 +749,15 @@ hipError_t launch_resid_norms(hipStream_t st, long long n, const double* X, cons
     }
     if (nchunks < 1) nchunks = 1;
     hipLaunchKernelGGL(resid_norms_kernel, dim3((int)nchunks), dim3(kThreads), 0, st, n, X, AX, ld, k,
-                       lam, rows, part);
-    hipLaunchKernelGGL(sum_partials_kernel, dim3((2 * k + kThreads - 1) / kThreads), dim3(kThreads), 0,
-                       st, 2 * k, (int)nchunks, part, out);
+                       lam, rows, part, R, ldr);
+    return launch_sum_partials(st, 2 * k, (int)nchunks, part, out);
+}
+
+hipError_t launch_gather_cols(hipStream_t st, long long n, const double* src, long long lds, const int* idx,
+                              int a, double* dst, long long ldd) {
+    if (a <= 0 || n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(gather_cols_kernel, dim3(grid_for(n * a, kThreads, 16384)), dim3(kThreads), 0, st, n,
+                       src, lds, idx, a, dst, ldd);
     return hipGetLastError();
 }
 
@@ -746,8 +804,9 @@ hipError_t launch_rowmajor_to_colmajor(hipStream_t st, long long n, int w, const
 
 hipError_t launch_sum_partials(hipStream_t st, int L, int nchunks, const double* part, double* out) {
     if (L <= 0) return hipSuccess;
-    hipLaunchKernelGGL(sum_partials_kernel, dim3((L + kThreads - 1) / kThreads), dim3(kThreads), 0, st, L,
-                       nchunks, part, out);
+    constexpr int OPB = kThreads / kSumG;
+    hipLaunchKernelGGL(sum_partials_kernel, dim3((L + OPB - 1) / OPB), dim3(kThreads), 0, st, L, nchunks, part,
+                       out);
     return hipGetLastError();
 }
 
@@ -755,8 +814,9 @@ hipError_t launch_gram_reduce(hipStream_t st, int mu, int mv, int nchunks, int s
                               double* C) {
     const long long total = (long long)mu * mv;
     if (total <= 0) return hipSuccess;
-    hipLaunchKernelGGL(gram_reduce_kernel, dim3((unsigned)((total + kThreads - 1) / kThreads)),
-                       dim3(kThreads), 0, st, mu, mv, nchunks, sym, part, C);
+    constexpr int OPB = kThreads / kRedG;
+    hipLaunchKernelGGL(gram_reduce_kernel, dim3((unsigned)((total + OPB - 1) / OPB)), dim3(kThreads), 0, st, mu,
+                       mv, nchunks, sym, part, C);
     return hipGetLastError();
 }
 
@@ -787,8 +847,9 @@ hipError_t launch_gram(hipStream_t st, long long n, const Segs& U, const Segs& V
     hipLaunchKernelGGL(gram_kernel, dim3(nchunks * ntiles), dim3(kThreads), 0, st, n, U, V, mu, mv,
                        nt_v, sym, ntiles, rows, part);
     const long long total = (long long)mu * mv;
-    hipLaunchKernelGGL(gram_reduce_kernel, dim3((unsigned)((total + kThreads - 1) / kThreads)),
-                       dim3(kThreads), 0, st, mu, mv, nchunks, sym, part, C);
+    constexpr int OPB = kThreads / kRedG;
+    hipLaunchKernelGGL(gram_reduce_kernel, dim3((unsigned)((total + OPB - 1) / OPB)), dim3(kThreads), 0, st, mu,
+                       mv, nchunks, sym, part, C);
     return hipGetLastError();
 }
 

@@ -82,9 +82,16 @@ hipError_t launch_spmm(hipStream_t st, int n, const int* rowptr, const int* col,
 
 // Per-column sums over rows of (AX - lam X)^2 and X^2 for columns [0, k):
 // out[c] = ||r_c||^2, out[k + c] = ||x_c||^2. part is scratch of
-// gram_partial_doubles(n, 2k) doubles.
+// gram_partial_doubles(n, 2k) doubles. With R != nullptr the residual block
+// R = AX - X diag(lam) is also written (n x k, leading dimension ldr) in the
+// same pass.
 hipError_t launch_resid_norms(hipStream_t st, long long n, const double* X, const double* AX,
-                              long long ld, int k, const double* lam, double* part, double* out);
+                              long long ld, int k, const double* lam, double* part, double* out,
+                              double* R = nullptr, long long ldr = 0);
+
+// dst[:, q] = src[:, idx[q]] for q < a (dst must not overlap src).
+hipError_t launch_gather_cols(hipStream_t st, long long n, const double* src, long long lds, const int* idx,
+                              int a, double* dst, long long ldd);
 
 // W[:, jj] = AX[:, act[jj]] - lam[act[jj]] X[:, act[jj]], jj < a.
 hipError_t launch_form_w(hipStream_t st, long long n, const double* X, const double* AX,

@@ -442,13 +442,15 @@ struct Solver {
     }
 
     // Residual check of the current (X, AX, theta) for k columns: per-column
-    // ratios of the stopping test and of eq. (rk).
+    // ratios of the stopping test and of eq. (rk). With R != nullptr the
+    // residual block AX - X Theta is written there (leading dimension ld) in
+    // the same pass over X and AX.
     se_status check(const double* Xp, const double* AXp, int k, std::vector<double>& stop,
-                    std::vector<double>& paper, std::vector<double>& lam) {
+                    std::vector<double>& paper, std::vector<double>& lam, double* R = nullptr) {
         ST(tic());
         HC(launch_resid_norms(st, n, Xp, AXp, ld, k, ws.theta.as<double>(), ws.gram_part.as<double>(),
-                              ws.norms.as<double>()));
-        ST(toc(SE_K_RESID, 16.0 * n * k, 5.0 * n * k));
+                              ws.norms.as<double>(), R, ld));
+        ST(toc(SE_K_RESID, (R ? 24.0 : 16.0) * n * k, 5.0 * n * k));
         return check_host(k, stop, paper, lam);
     }
 
@@ -534,7 +536,8 @@ struct Solver {
         std::vector<int> act, act_hl, kept;
 
         for (int j = 1; j <= p.max_iter; ++j) {
-            ST(check(X, AX, k, stop, paper, lam));
+            // W (dead since the last basis update) receives R = AX - X Theta.
+            ST(check(X, AX, k, stop, paper, lam, W));
             double r = 0.0, ms = 0.0;
             bool all = true;
             for (int i = 0; i < n_ev; ++i) {
@@ -560,13 +563,17 @@ struct Solver {
             const bool want_expand = ctl.ifexpand(j);
             int flags = 0;
 
-            // W <- R(:, active) (T = I), orthogonalized against [X, P] twice.
+            // W <- R(:, active) (T = I): R is already in W; locked columns
+            // are gathered out.
             int a = (int)act.size();
-            std::memcpy(ws.h_act.p, act.data(), sizeof(int) * a);
-            HC(hipMemcpyAsync(ws.act.p, ws.h_act.p, sizeof(int) * a, hipMemcpyHostToDevice, st));
-            ST(tic());
-            HC(launch_form_w(st, n, X, AX, ld, ws.theta.as<double>(), ws.act.as<int>(), a, W, ld));
-            ST(toc(SE_K_RESID, 24.0 * n * a, 2.0 * n * a));
+            if (a < k) {
+                std::memcpy(ws.h_act.p, act.data(), sizeof(int) * a);
+                HC(hipMemcpyAsync(ws.act.p, ws.h_act.p, sizeof(int) * a, hipMemcpyHostToDevice, st));
+                ST(tic());
+                HC(launch_gather_cols(st, n, W, ld, ws.act.as<int>(), a, T1, ld));
+                ST(toc(SE_K_RESID, 16.0 * n * a, 0.0));
+                std::swap(W, T1);
+            }
             // By the Galerkin condition of the last Rayleigh-Ritz step R is
             // orthogonal to [X, P] up to rounding, so one projection usually
             // suffices; a second one runs when a column lost more than half of

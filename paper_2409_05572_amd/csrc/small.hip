@@ -53,6 +53,10 @@ __device__ double block_sum(double v, double* sh) {
 // is I - (3/4) E^2 - (1/4) E^3 with E = G - I, so ns_tol = 1e-8 leaves an
 // error below rounding. The decision is taken on the device, so a caller can
 // chain passes without reading anything back.
+// kLds: the a x a work matrix lives in dynamic LDS (a^2 <= kLdsDoubles), else
+// in `work`; fixed at compile time so every access is a plain LDS or global
+// instruction rather than a generic (flat) one.
+template <bool kLds>
 __global__ __launch_bounds__(kSmall) void chol_drop_kernel(int a, const double* __restrict__ G,
                                                            double* __restrict__ T,
                                                            double* __restrict__ work,
@@ -67,7 +71,7 @@ __global__ __launch_bounds__(kSmall) void chol_drop_kernel(int a, const double* 
     __shared__ double s_dr[1024];  // diagonal of R^{-1}
     __shared__ double s_red[kSWaves];
     __shared__ int s_r;
-    double* F = ((size_t)a * a <= (size_t)kLdsDoubles) ? dyn : work;  // a x a
+    double* F = kLds ? dyn : work;  // a x a
     const int t = threadIdx.x;
     const bool can_drop = drop_tol2 >= 0.0;
 
@@ -188,6 +192,7 @@ __global__ __launch_bounds__(kSmall) void chol_drop_kernel(int a, const double* 
 // acts on rows/columns k+1..m-1: H_k = I - tau_k v_k v_k^T with v_k stored in
 // Vh row k from column k+1 (leading 1 explicit). d / e = diagonal /
 // off-diagonal of the result.
+template <bool kInLds>  // the matrix is copied into dynamic LDS (m^2 <= kLdsDoubles)
 __global__ __launch_bounds__(kTri) void tridiag_kernel(int m, int kend, double* __restrict__ Ag,
                                                        double* __restrict__ d,
                                                        double* __restrict__ e,
@@ -202,9 +207,8 @@ __global__ __launch_bounds__(kTri) void tridiag_kernel(int m, int kend, double* 
     __shared__ double sred[NW];
     __shared__ double s_scal[4];
     const int t = threadIdx.x;
-    const bool in_lds = (size_t)m * m <= (size_t)kLdsDoubles;
-    double* A = in_lds ? dyn : Ag;
-    if (in_lds) {
+    double* A = kInLds ? dyn : Ag;
+    if (kInLds) {
         for (size_t q = t; q < (size_t)m * m; q += NTH) dyn[q] = Ag[q];
         __syncthreads();
     }
@@ -882,9 +886,12 @@ __global__ __launch_bounds__(kSmall) void sumsq_kernel(long long count, const do
 hipError_t launch_chol_drop(hipStream_t st, int a, const double* G, double* T, double* work,
                             int* info_i, double* info_d, double drop_tol2, double ns_tol) {
     if (a <= 0 || a > 1024) return hipErrorInvalidValue;
-    const size_t lds = ((size_t)a * a <= (size_t)kLdsDoubles) ? sizeof(double) * (size_t)a * a : 0;
-    hipLaunchKernelGGL(chol_drop_kernel, dim3(1), dim3(kSmall), lds, st, a, G, T, work, info_i, info_d,
-                       drop_tol2, ns_tol);
+    if ((size_t)a * a <= (size_t)kLdsDoubles)
+        hipLaunchKernelGGL(chol_drop_kernel<true>, dim3(1), dim3(kSmall), sizeof(double) * (size_t)a * a, st, a,
+                           G, T, work, info_i, info_d, drop_tol2, ns_tol);
+    else
+        hipLaunchKernelGGL(chol_drop_kernel<false>, dim3(1), dim3(kSmall), 0, st, a, G, T, work, info_i, info_d,
+                           drop_tol2, ns_tol);
     return hipGetLastError();
 }
 
@@ -982,12 +989,13 @@ hipError_t launch_syev_lowest(hipStream_t st, int m, int k, double* A, double* w
     }
     if (done) {
     } else if (m <= 112) {
-        hipLaunchKernelGGL(tridiag_kernel, dim3(1), dim3(kTri), lds, st, m, m, A, d, e, tau, Vh);
+        hipLaunchKernelGGL(tridiag_kernel<true>, dim3(1), dim3(kTri), lds, st, m, m, A, d, e, tau, Vh);
     } else {
         // the first m - 224 reflectors in L2, the trailing block (order <= 224)
         // in registers
         const int k0 = m > 224 ? m - 224 : 0;
-        if (k0 > 0) hipLaunchKernelGGL(tridiag_kernel, dim3(1), dim3(kTri), 0, st, m, k0, A, d, e, tau, Vh);
+        if (k0 > 0)
+            hipLaunchKernelGGL(tridiag_kernel<false>, dim3(1), dim3(kTri), 0, st, m, k0, A, d, e, tau, Vh);
         switch ((m - k0 + 15) / 16) {
             case 8: hipLaunchKernelGGL((tridiag_reg_kernel<8, 4>), dim3(1), dim3(512), 0, st, m, k0, A, d, e, tau, Vh); break;
             case 9: hipLaunchKernelGGL((tridiag_reg_kernel<9, 5>), dim3(1), dim3(512), 0, st, m, k0, A, d, e, tau, Vh); break;
