@@ -192,7 +192,10 @@ se_status se_op_spmm(se_ctx* ctx, const se_matrix* A, const double* X, int64_t l
 
 /* C = U^T V (mu x mv, row-major, leading dimension mv), the tall-skinny Gram
  * products of the orthogonalization and projection steps. U is n x mu, V is
- * n x mv, 1 <= mu, mv <= 1024. Summation order is fixed (deterministic). */
+ * n x mv, 1 <= mu, mv <= 1024. Summation order is fixed (deterministic).
+ * When V is U (same pointer, leading dimension and width) the product is
+ * formed as symmetric: blocks on and above the diagonal are computed and
+ * mirrored, so C is exactly symmetric. */
 se_status se_op_gram(se_ctx* ctx, int64_t n, const double* U, int64_t ldu, int32_t mu,
                      const double* V, int64_t ldv, int32_t mv, double* C);
 

@@ -187,6 +187,74 @@ __global__ __launch_bounds__(kThreads) void spmm_kernel(int n, const int* __rest
     }
 }
 
+// CSR x block for matrices without heavy rows: one wave per run of
+// kStreamRows consecutive rows walks the run's nonzeros in order, NB at a
+// time. Their column indices and values are uniform over the wave (scalar
+// loads; the arrays are padded by kCsrPad entries), all NB row gathers of X
+// (16 bytes per lane) are issued before any is used, and the accumulator
+// moves to the next row, storing the finished one, at each row boundary, so
+// NB gathers are in flight whatever the row lengths. The run's row offsets
+// sit one per lane and are read with readlane. Lane l owns columns
+// cb + 2l, cb + 2l + 1 of each 128-column block (an odd width reads the
+// padding column, ld >= w + 1, and stores one value).
+constexpr int kStreamRows = 32;
+
+template <int NB>
+__global__ __launch_bounds__(kThreads) void spmm_stream_kernel(int n, const int* __restrict__ rowptr,
+                                                               const int* __restrict__ col,
+                                                               const double* __restrict__ val,
+                                                               const double* __restrict__ X, long long ldx,
+                                                               double* __restrict__ Y, long long ldy, int w) {
+    const int lane = threadIdx.x & 63;
+    const int wid = __builtin_amdgcn_readfirstlane((int)blockIdx.x * (kThreads / 64) + (int)(threadIdx.x >> 6));
+    if ((long long)wid * kStreamRows >= n) return;
+    const int r0 = wid * kStreamRows;
+    const int r1 = min(n, r0 + kStreamRows);
+    const int rp = rowptr[min(r0 + lane, r1)];  // lane q: offset of row r0 + q, q <= r1 - r0
+    const int pbeg = __builtin_amdgcn_readlane(rp, 0);
+    const int pend = __builtin_amdgcn_readlane(rp, r1 - r0);
+    for (int cb = 0; cb < w; cb += 128) {
+        const int c0 = cb + 2 * lane;
+        const bool has0 = c0 < w, has1 = c0 + 1 < w;
+        const long long cc = has0 ? c0 : cb;  // lanes without columns read a valid address
+        int r = r0;
+        int rend = __builtin_amdgcn_readlane(rp, 1);
+        double a0 = 0.0, a1 = 0.0;
+        auto flush = [&]() {
+            double* y = Y + (long long)r * ldy + c0;
+            if (has1)
+                *reinterpret_cast<double2*>(y) = make_double2(a0, a1);
+            else if (has0)
+                *y = a0;
+            a0 = 0.0;
+            a1 = 0.0;
+            ++r;
+            if (r < r1) rend = __builtin_amdgcn_readlane(rp, r - r0 + 1);
+        };
+        for (int p = pbeg; p < pend; p += NB) {
+            int j[NB];
+            double v[NB];
+#pragma unroll
+            for (int u = 0; u < NB; ++u) {
+                j[u] = col[p + u];
+                v[u] = val[p + u];
+            }
+            double2 x[NB];
+#pragma unroll
+            for (int u = 0; u < NB; ++u) x[u] = *reinterpret_cast<const double2*>(X + (long long)j[u] * ldx + cc);
+#pragma unroll
+            for (int u = 0; u < NB; ++u) {
+                if (p + u < pend) {
+                    while (p + u >= rend) flush();
+                    a0 = fma(v[u], x[u].x, a0);
+                    a1 = fma(v[u], x[u].y, a1);
+                }
+            }
+        }
+        while (r < r1) flush();
+    }
+}
+
 template <int LPR>
 hipError_t spmm_launch(hipStream_t st, int n, const int* rowptr, const int* col, const double* val,
                        const double* X, long long ldx, double* Y, long long ldy, int w, const int* heavy,
@@ -446,6 +514,54 @@ __device__ __forceinline__ void gram_compute(const double (*Ts)[2 * GT + 4], d4 
     }
 }
 
+// Diagonal tiles of symmetric products: only the 21 upper 16 x 16 MFMA tiles
+// (I <= J) of the 6 x 6 grid are formed, 6/5/5/5 per wave by tile rows
+// (wave 0: row 0; 1: row 1; 2: rows 2 and 5; 3: rows 3 and 4). Tile (I, J0 + q)
+// accumulates in slot S0 + q of acc; nv = tile rows/columns holding data.
+template <int I, int J0, int NJ, int S0>
+__device__ __forceinline__ void gram_diag_row(const double (*Ts)[2 * GT + 4], d4 (&acc)[3][3], int ks, int lr,
+                                              int lc, int nv) {
+    if (I >= nv) return;
+    const double a = Ts[ks + lr][I * 16 + lc];
+#pragma unroll
+    for (int q = 0; q < NJ; ++q) {
+        if (J0 + q < nv) {
+            const double b = Ts[ks + lr][GT + (J0 + q) * 16 + lc];
+            acc[(S0 + q) / 3][(S0 + q) % 3] = mfma16(a, b, acc[(S0 + q) / 3][(S0 + q) % 3]);
+        }
+    }
+}
+
+template <int WV>
+__device__ __forceinline__ void gram_diag_stage(const double (*Ts)[2 * GT + 4], d4 (&acc)[3][3], int lr, int lc,
+                                                int nv) {
+#pragma unroll
+    for (int ks = 0; ks < GK; ks += 4) {
+        if (WV == 0) gram_diag_row<0, 0, 6, 0>(Ts, acc, ks, lr, lc, nv);
+        if (WV == 1) gram_diag_row<1, 1, 5, 0>(Ts, acc, ks, lr, lc, nv);
+        if (WV == 2) {
+            gram_diag_row<2, 2, 4, 0>(Ts, acc, ks, lr, lc, nv);
+            gram_diag_row<5, 5, 1, 4>(Ts, acc, ks, lr, lc, nv);
+        }
+        if (WV == 3) {
+            gram_diag_row<3, 3, 3, 0>(Ts, acc, ks, lr, lc, nv);
+            gram_diag_row<4, 4, 2, 3>(Ts, acc, ks, lr, lc, nv);
+        }
+    }
+}
+
+// (I, J) of slot s of wave wv in a diagonal tile; false if the slot is unused.
+__device__ __forceinline__ bool gram_diag_slot(int wv, int s, int& I, int& J) {
+    if (wv == 0) { I = 0; J = s; return s < 6; }
+    if (wv == 1) { I = 1; J = 1 + s; return s < 5; }
+    if (wv == 2) {
+        if (s < 4) { I = 2; J = 2 + s; return true; }
+        I = 5; J = 5; return s == 4;
+    }
+    if (s < 3) { I = 3; J = 3 + s; return true; }
+    I = 4; J = 4 + (s - 3); return s < 5;
+}
+
 // Loads of one stage: the U tile (GK rows x 96) and the V tile (GK x 96) form
 // a GK x 192 array. Thread t owns columns t%64, t%64+64, t%64+128 and rows
 // t/64 + 4i, so its three column pointers are fixed for the whole chunk and a
@@ -469,7 +585,10 @@ __global__ __launch_bounds__(kThreads, 2) void gram_kernel(long long n, Segs U, 
     const int lr = lane >> 4, lc = lane & 15;
     const int niv = max(0, min(3, (mu - cu0 - wy * 48 + 15) / 16));
     const int njv = max(0, min(3, (mv - cv0 - wx * 48 + 15) / 16));
-    const int shape = niv * 4 + njv;
+    // symmetric diagonal tile: triangular split (shape -1 .. -4 = wave 0 .. 3)
+    const bool diag = sym && ti == tj;
+    const int nv = min(6, (mu - cu0 + 15) / 16);
+    const int shape = diag ? -1 - wv : niv * 4 + njv;
 
     // fixed column pointers of this thread (c < 96: U, else V)
     const double* cp[3];
@@ -527,6 +646,10 @@ __global__ __launch_bounds__(kThreads, 2) void gram_kernel(long long n, Segs U, 
             case 7: gram_compute<1, 3>(Ts, acc, lr, lc, wy, wx); break;
             case 6: gram_compute<1, 2>(Ts, acc, lr, lc, wy, wx); break;
             case 5: gram_compute<1, 1>(Ts, acc, lr, lc, wy, wx); break;
+            case -1: gram_diag_stage<0>(Ts, acc, lr, lc, nv); break;
+            case -2: gram_diag_stage<1>(Ts, acc, lr, lc, nv); break;
+            case -3: gram_diag_stage<2>(Ts, acc, lr, lc, nv); break;
+            case -4: gram_diag_stage<3>(Ts, acc, lr, lc, nv); break;
             default: break;
         }
         __syncthreads();
@@ -536,6 +659,20 @@ __global__ __launch_bounds__(kThreads, 2) void gram_kernel(long long n, Segs U, 
         }
     }
     double* P = part + (long long)chunk * mu * mv;
+    if (diag) {
+#pragma unroll
+        for (int sl = 0; sl < 9; ++sl) {
+            int I, J;
+            if (!gram_diag_slot(wv, sl, I, J)) continue;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int gi = cu0 + I * 16 + lr + 4 * r;
+                const int gj = cv0 + J * 16 + lc;
+                if (gi < mu && gj < mv) P[(long long)gi * mv + gj] = acc[sl / 3][sl % 3][r];
+            }
+        }
+        return;
+    }
 #pragma unroll
     for (int i = 0; i < 3; ++i)
 #pragma unroll
@@ -551,9 +688,10 @@ __global__ __launch_bounds__(kThreads, 2) void gram_kernel(long long n, Segs U, 
 // C = sum over chunks of the partial Gram products. 16 threads per output
 // and 16 outputs per workgroup (consecutive threads on consecutive outputs):
 // thread g sums chunks g, g + 16, ... in increasing order and a fixed tree
-// combines the 16 sums (deterministic). Symmetric products: outputs of lower
-// tiles take the mirrored upper-tile sum, diagonal tiles average (i, j) and
-// (j, i).
+// combines the 16 sums (deterministic). Symmetric products (partials hold
+// at least every 16 x 16 block on or above the diagonal): outputs below the
+// diagonal blocks take the mirrored sum, diagonal 16 x 16 blocks average
+// (i, j) and (j, i).
 constexpr int kRedG = 16;
 __global__ __launch_bounds__(kThreads) void gram_reduce_kernel(int mu, int mv, int nchunks, int sym,
                                                                const double* __restrict__ part,
@@ -570,7 +708,7 @@ __global__ __launch_bounds__(kThreads) void gram_reduce_kernel(int mu, int mv, i
     if (valid) {
         const int i = (int)(idx / mv), j = (int)(idx % mv);
         if (sym) {
-            const int ti = i / GT, tj = j / GT;
+            const int ti = i / 16, tj = j / 16;
             mode = ti < tj ? 0 : (ti > tj ? 1 : 2);
             p2 = (long long)j * mv + i;
             if (mode == 1) p1 = p2;
@@ -724,6 +862,13 @@ hipError_t launch_spmm(hipStream_t st, int n, const int* rowptr, const int* col,
                        const double* X, long long ldx, double* Y, long long ldy, int w, const int* heavy,
                        int n_heavy) {
     if (n <= 0 || w <= 0) return hipSuccess;
+    if (n_heavy == 0) {
+        const long long waves = ((long long)n + kStreamRows - 1) / kStreamRows;
+        const int grid = (int)((waves + kThreads / 64 - 1) / (kThreads / 64));
+        hipLaunchKernelGGL(spmm_stream_kernel<16>, dim3(grid), dim3(kThreads), 0, st, n, rowptr, col, val, X,
+                           ldx, Y, ldy, w);
+        return hipGetLastError();
+    }
     const int half = (w + 1) / 2;
 #define SE_SPMM(L) return spmm_launch<L>(st, n, rowptr, col, val, X, ldx, Y, ldy, w, heavy, n_heavy)
     if (half <= 1) SE_SPMM(1);

@@ -182,8 +182,10 @@ se_status se_matrix_create_csr(se_ctx* ctx, int64_t n, int64_t nnz, const int64_
     m->nnz = nnz;
     m->anorm = anorm;
     hipError_t e = hipMalloc(&m->rowptr, sizeof(int) * (n + 1));
-    if (e == hipSuccess) e = hipMalloc(&m->col, sizeof(int) * (nnz > 0 ? nnz : 1));
-    if (e == hipSuccess) e = hipMalloc(&m->val, sizeof(double) * (nnz > 0 ? nnz : 1));
+    if (e == hipSuccess) e = hipMalloc(&m->col, sizeof(int) * (nnz + se::kCsrPad));
+    if (e == hipSuccess) e = hipMalloc(&m->val, sizeof(double) * (nnz + se::kCsrPad));
+    if (e == hipSuccess) e = hipMemset(m->col + nnz, 0, sizeof(int) * se::kCsrPad);
+    if (e == hipSuccess) e = hipMemset(m->val + nnz, 0, sizeof(double) * se::kCsrPad);
     const hipMemcpyKind kind = on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
     if (e == hipSuccess) e = hipMemcpy(m->rowptr, rp32.data(), sizeof(int) * (n + 1), hipMemcpyHostToDevice);
     if (e == hipSuccess && nnz > 0) e = hipMemcpy(m->col, colind, sizeof(int) * nnz, kind);
@@ -252,7 +254,8 @@ se_status se_op_gram(se_ctx* ctx, int64_t n, const double* U, int64_t ldu, int32
     se::Segs Us = se::make_segs(ldu), Vs = se::make_segs(ldv);
     se::push_seg(Us, U, mu);
     se::push_seg(Vs, V, mv);
-    CAPI_HC(ctx, se::launch_gram(ctx->stream, n, Us, Vs, 0, ctx->ws.gram_part.as<double>(), C));
+    const int sym = (U == V && ldu == ldv && mu == mv) ? 1 : 0;
+    CAPI_HC(ctx, se::launch_gram(ctx->stream, n, Us, Vs, sym, ctx->ws.gram_part.as<double>(), C));
     return SE_OK;
 }
 

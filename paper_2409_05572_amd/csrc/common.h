@@ -74,6 +74,10 @@ inline int segs_width(const SegsT<T>& s) {
 // `heavy` and computed by one workgroup each; the row-per-lane-group kernel
 // skips them.
 constexpr int kHeavyRow = 64;
+// The matrix's column and value arrays carry kCsrPad trailing entries
+// (column 0, value 0) so that batched loads past the last nonzero stay in
+// bounds and name a valid row.
+constexpr int kCsrPad = 64;
 
 // Y[:, 0:w] = A X[:, 0:w] for CSR A with int32 row offsets.
 hipError_t launch_spmm(hipStream_t st, int n, const int* rowptr, const int* col, const double* val,

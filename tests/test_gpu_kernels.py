@@ -68,6 +68,44 @@ def test_spmm_empty_rows_and_hub_row(ctx):
     assert np.allclose(Y, ref, rtol=1e-13, atol=1e-12)
 
 
+def _matrix_with_empty_runs():
+    """Rows of 1-12 nonzeros with empty rows at the start and end of 32-row
+    runs, a fully empty run, an empty last row, n not a multiple of 32."""
+    import scipy.sparse as sp
+
+    n = 3001
+    rng = np.random.default_rng(17)
+    deg = rng.integers(1, 13, n)
+    empty = [0, 31, 32, 63, 2999, 3000] + list(range(64, 130))
+    deg[empty] = 0
+    rows = np.repeat(np.arange(n), deg)
+    cols = rng.integers(0, n, deg.sum())
+    a = sp.csr_matrix((rng.standard_normal(deg.sum()), (rows, cols)), shape=(n, n))
+    a.sum_duplicates()
+    a.sort_indices()
+    return W.CSRMatrix(n, a.indptr.astype(np.int64), a.indices.astype(np.int32), a.data, 1.0)
+
+
+@pytest.mark.parametrize("w", [1, 2, 3, 64, 96, 127, 128, 129, 250])
+def test_spmm_empty_rows_without_heavy_rows(ctx, w):
+    from paper_2409_05572_amd import api
+
+    A = _matrix_with_empty_runs()
+    assert np.diff(A.rowptr).max() <= 64  # no heavy rows: the streaming kernel alone
+    M = api.Matrix.from_csr(ctx, A)
+    ld = w + (w % 2)
+    X = _row_major(A.n, w, ld, w + 3)
+    Yd = to_dev(np.full((A.n, ld), np.nan))
+    api.spmm(ctx, M, to_dev(X), Yd, w)
+    Y = Yd.cpu().numpy()
+    ref = OS._apply(A.to_scipy(), X[:, :w])
+    assert np.all(Y[np.diff(A.rowptr) == 0, :w] == 0.0)
+    bound = 1e-15 * 16 * (abs(A.to_scipy()) @ np.abs(X[:, :w]))
+    assert np.all(np.abs(Y[:, :w] - ref) <= bound + 1e-300)
+    if ld > w:
+        assert np.all(np.isnan(Y[:, w:]))  # padding column untouched
+
+
 @pytest.mark.parametrize("w", [1, 5, 48, 69, 130])
 def test_spmm_power_law_rows(ctx, w):
     """Normalized Laplacian of a Chung-Lu graph: rows from a few to hundreds of
@@ -124,6 +162,24 @@ def test_gram_matches_definition(ctx, n, mu, mv):
     ref = U[:, :mu].T @ V[:, :mv]
     bound = 4 * n * 1.2e-16 * (np.abs(U[:, :mu]).T @ np.abs(V[:, :mv]))
     assert np.all(np.abs(C - ref) <= bound + 1e-300)
+
+
+@pytest.mark.parametrize("n,m", [(1, 1), (1000, 17), (4097, 69), (20000, 96), (20001, 97), (7777, 150),
+                                 (50001, 288), (3001, 300)])
+def test_symmetric_gram_matches_definition(ctx, n, m):
+    """U^T U through the symmetric path (triangular diagonal tiles, mirrored
+    blocks): within the summation bound and exactly symmetric."""
+    from paper_2409_05572_amd import api
+
+    U = _row_major(n, m, m + m % 2, 3)
+    Ud = to_dev(U)
+    Cd = to_dev(np.full((m, m), np.nan))
+    api.gram(ctx, Ud, m, Ud, m, Cd)
+    C = Cd.cpu().numpy()
+    ref = U[:, :m].T @ U[:, :m]
+    bound = 4 * n * 1.2e-16 * (np.abs(U[:, :m]).T @ np.abs(U[:, :m]))
+    assert np.all(np.abs(C - ref) <= bound + 1e-300)
+    assert np.array_equal(C, C.T)
 
 
 def test_gram_is_deterministic(ctx):
