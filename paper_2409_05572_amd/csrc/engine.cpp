@@ -158,7 +158,7 @@ struct Solver {
         HC(ws.hlG.ensure(sizeof(double) * mm));
         HC(ws.hlQ.ensure(sizeof(double) * mm));
         {
-            DevBuf* cb[] = {&ws.apc, &ws.axp, &ws.axq, &ws.gw};
+            DevBuf* cb[] = {&ws.apc, &ws.axp, &ws.axq, &ws.gw, &ws.wfold, &ws.cfold};
             for (DevBuf* b : cb) HC(b->ensure(sizeof(double) * mm));
             HC(ws.idx.ensure(sizeof(int) * (mmax + 8)));
         }
@@ -263,6 +263,30 @@ struct Solver {
         return SE_OK;
     }
 
+    // With the W block held as W T (T = ws.wfold, a x a; S = [X, P, W] has
+    // m = q + a columns): gw (m x a, the Gram S^T (A W)) becomes
+    // diag(I_q, T^T) gw T, the Gram of the orthonormal basis.
+    se_status fold_gram(int m, int q, int a) {
+        double* gw = ws.gw.as<double>();
+        double* tmp = ws.axq.as<double>();  // free until the carried A_p is formed
+        const double* T = ws.wfold.as<double>();
+        ST(update_rows(m, segx(gw, a, a), T, a, segx(tmp, a, a), 1.0, 0.0));
+        HC(launch_copy_cols(st, q, tmp, a, 0, gw, a, 0, a));
+        ST(gram_rows(a, segx(T, a, a), segx(tmp + (size_t)q * a, a, a), 0, gw + (size_t)q * a));
+        return SE_OK;
+    }
+    // ws.cfold = diag(I_q, T) ws.C (m x N, leading dimension N): the update
+    // coefficients for S = [X, P, W] when the orthonormal block is W T.
+    se_status fold_coefficients(int m, int q, int a, int N) {
+        const double* C = ws.C.as<double>();
+        double* CF = ws.cfold.as<double>();
+        HC(launch_copy_cols(st, q, C, N, 0, CF, N, 0, N));
+        ST(update_rows(a, segx(ws.wfold.as<double>(), a, a), C + (size_t)q * N, N,
+                       segx(CF + (size_t)q * N, N, N), 1.0, 0.0));
+        (void)m;
+        return SE_OK;
+    }
+
     // Coefficients C = [Z1 | C_P] (m x (k + r), leading dimension k + r) of the
     // Hetmaniuk-Lehoucq basis: C_P is an orthonormal basis of the part of the
     // unlocked old X columns (unit vectors E) orthogonal to Z1, i.e. of
@@ -341,10 +365,16 @@ struct Solver {
     // its squared norm, one projection is not enough (the criterion of Kahan
     // and Parlett for classical Gram-Schmidt): *reproject is set and the call
     // returns with the panel untouched, for the caller to project again.
+    // `fold_T` (with `folded`): when the last pass keeps every column, its
+    // transform T (w x w) is written there instead of being applied, so the
+    // orthonormal block is panel * T; the caller carries T in coefficient
+    // space. Not with a companion.
     se_status cholqr(double*& w_panel, int& w, double** companion, std::vector<int>* kept_out,
                      const Segs* against = nullptr, const Segs* against_img = nullptr,
-                     const double* ref_norm2 = nullptr, bool* reproject = nullptr) {
+                     const double* ref_norm2 = nullptr, bool* reproject = nullptr, double* fold_T = nullptr,
+                     bool* folded = nullptr) {
         if (reproject) *reproject = false;
+        if (folded) *folded = false;
         std::vector<int> map(w);
         for (int i = 0; i < w; ++i) map[i] = i;
         int passes = 2;
@@ -355,10 +385,16 @@ struct Solver {
             int* info_i = ws.info.as<int>();
             double* info_d = ws.info.as<double>() + (w + 8) / 2 + 4;
             if (full_rank) {
+                const bool fold = fold_T && folded && !companion && pass == passes - 1;
+                double* Tp = fold ? fold_T : ws.T.as<double>();
                 ST(tic());
-                HC(launch_chol_drop(st, w, ws.G.as<double>(), ws.T.as<double>(), ws.small_work.as<double>(),
-                                    info_i, info_d, -1.0, 1e-8));
+                HC(launch_chol_drop(st, w, ws.G.as<double>(), Tp, ws.small_work.as<double>(), info_i, info_d,
+                                    -1.0, 1e-8));
                 ST(toc(SE_K_SMALL, 16.0 * w * w, w * w * (double)w));
+                if (fold) {
+                    *folded = true;
+                    continue;
+                }
                 ST(update(Ws, ws.T.as<double>(), w, seg1(T1, w), 1.0, 0.0));
                 std::swap(w_panel, T1);
                 if (companion) {
@@ -581,17 +617,25 @@ struct Solver {
             const Segs XP = seg3(X, k, P, pw, nullptr, 0);
             ST(gram(XP, seg1(W, a), 0, ws.G.as<double>()));
             ST(update(XP, ws.G.as<double>(), a, seg1(W, a), -1.0, 1.0));
+            // In iterations that take the carried-A_p path (no expansion, no
+            // refresh), the last Cholesky-QR transform T of W is not applied:
+            // the orthonormal block is W T, and T enters the Gram S^T (A W) and
+            // the coefficients of the basis update instead.
+            const bool carried_path =
+                axp_q == k + pw && !(want_expand && have_drop) && j % kAxpRefresh != 0;
+            bool folded = false;
+            double* fold_T = carried_path ? ws.wfold.as<double>() : nullptr;
             {
                 const double* nr = ws.h_norms.as<double>();
                 std::vector<double> wn2(a);
                 for (int q = 0; q < a; ++q) wn2[q] = nr[act[q]];
                 bool again = false;
-                ST(cholqr(W, a, nullptr, nullptr, &XP, nullptr, wn2.data(), &again));
+                ST(cholqr(W, a, nullptr, nullptr, &XP, nullptr, wn2.data(), &again, fold_T, &folded));
                 if (again) {
                     ++n_reproj;
                     ST(gram(XP, seg1(W, a), 0, ws.G.as<double>()));
                     ST(update(XP, ws.G.as<double>(), a, seg1(W, a), -1.0, 1.0));
-                    ST(cholqr(W, a, nullptr, nullptr, &XP));
+                    ST(cholqr(W, a, nullptr, nullptr, &XP, nullptr, nullptr, nullptr, fold_T, &folded));
                 }
             }
             if (a > 0) ST(spmm(W, AW, a));
@@ -634,6 +678,7 @@ struct Solver {
             const Segs AS = seg3(AX, k, AP, pw, AW, a);
             if (axp_q == k + pw && !(flags & 1) && a > 0 && j % kAxpRefresh != 0) {
                 ST(gram(S, seg1(AW, a), 0, ws.gw.as<double>()));
+                if (folded) ST(fold_gram(m, k + pw, a));
                 HC(launch_assemble_ap(st, m, axp_q, ws.axp.as<double>(), ws.gw.as<double>(),
                                       ws.G.as<double>()));
             } else {
@@ -660,7 +705,12 @@ struct Solver {
             Segs O = make_segs(ld);
             push_seg(O, Xn, k);
             push_seg(O, Pn, rP);
-            ST(update(S, ws.C.as<double>(), k + rP, O, 1.0, 0.0));
+            if (folded) {
+                ST(fold_coefficients(m, k + pw, a, k + rP));
+                ST(update(S, ws.cfold.as<double>(), k + rP, O, 1.0, 0.0));
+            } else {
+                ST(update(S, ws.C.as<double>(), k + rP, O, 1.0, 0.0));
+            }
             std::swap(X, Xn);
             std::swap(P, Pn);
             pw = rP;
@@ -1308,7 +1358,7 @@ size_t solve_workspace_bytes(long long n, long long nnz, int nb, int precision, 
     size_t bytes = sizeof(double) * (size_t)kNumPanels * n * ld;
     size_t small = 4 * mm + (mmax + 8) + (2 * mm + 8 * (size_t)mmax + 64) + syev_work_doubles(mmax) +
                    std::max(gram_scratch_doubles(n, mmax, mmax), (size_t)4096 * 2 * mmax) + 4 * mm +
-                   3 * (2 * (size_t)mmax + 16) + 4 * mm + (size_t)mmax + 8;
+                   3 * (2 * (size_t)mmax + 16) + 6 * mm + (size_t)mmax + 8;
     if (precision != SE_FP64) {
         const size_t es = precision == SE_FP32_MIXED ? 4 : 2;
         bytes += es * (size_t)kNumLpPanels * n * ld + sizeof(float) * (size_t)nnz;

@@ -70,6 +70,7 @@ struct Workspace {
     DevBuf hlB, hlY, hlG, hlQ;
     DevBuf lpM, lpT, lpQ, lpB, lpE, lpC;  // generalized Rayleigh-Ritz (m x m each)
     DevBuf apc, axp, axq, gw, idx;        // carried [X, P]^T A [X, P] (m x m each; idx ints)
+    DevBuf wfold, cfold;                  // last Cholesky-QR transform of W, folded coefficients
     HostBuf h_norms, h_info, h_act, h_act_hl, h_theta, h_diag;
     std::vector<hipEvent_t> events;  // pool for per-launch timing
     size_t device_bytes() const {
@@ -78,7 +79,8 @@ struct Workspace {
         for (const auto& b : lp_panel) s += b.bytes;
         const DevBuf* all[] = {&gram_part, &G, &T, &Z, &theta, &C, &small_work, &syev_work,
                                &lam, &act, &act_hl, &norms, &info, &hlB, &hlY, &hlG, &hlQ,
-                               &lpM, &lpT, &lpQ, &lpB, &lpE, &lpC, &apc, &axp, &axq, &gw, &idx};
+                               &lpM, &lpT, &lpQ, &lpB, &lpE, &lpC, &apc, &axp, &axq, &gw, &idx,
+                               &wfold, &cfold};
         for (auto* b : all) s += b->bytes;
         return s;
     }
@@ -87,7 +89,8 @@ struct Workspace {
         for (auto& b : lp_panel) b.release();
         DevBuf* all[] = {&gram_part, &G, &T, &Z, &theta, &C, &small_work, &syev_work,
                          &lam, &act, &act_hl, &norms, &info, &hlB, &hlY, &hlG, &hlQ,
-                         &lpM, &lpT, &lpQ, &lpB, &lpE, &lpC, &apc, &axp, &axq, &gw, &idx};
+                         &lpM, &lpT, &lpQ, &lpB, &lpE, &lpC, &apc, &axp, &axq, &gw, &idx,
+                         &wfold, &cfold};
         for (auto* b : all) b->release();
         h_norms.release();
         h_info.release();
