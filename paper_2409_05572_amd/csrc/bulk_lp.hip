@@ -226,6 +226,88 @@ __global__ __launch_bounds__(kThreads) void spmm_lp_kernel(int n, const int* __r
             spmm_rows(r, r + 1 < rend ? r + 1 : -1, rowptr, col, val, X, ldx, Y, ldy, c0, w);
 }
 
+// Two consecutive elements (8-byte FP32 or 4-byte BF16 access).
+__device__ __forceinline__ void ld2(const float* p, float& a, float& b) {
+    const float2 q = *reinterpret_cast<const float2*>(p);
+    a = q.x;
+    b = q.y;
+}
+__device__ __forceinline__ void ld2(const bf16_t* p, float& a, float& b) {
+    const uint32_t q = *reinterpret_cast<const uint32_t*>(p);
+    a = bf2f(q & 0xFFFFu);
+    b = bf2f(q >> 16);
+}
+__device__ __forceinline__ void st2(float* p, float a, float b) {
+    *reinterpret_cast<float2*>(p) = make_float2(a, b);
+}
+__device__ __forceinline__ void st2(bf16_t* p, float a, float b) {
+    *reinterpret_cast<uint32_t*>(p) = f2bf(a) | (f2bf(b) << 16);
+}
+
+// CSR x block for matrices without heavy rows (the FP64 streaming product
+// with FP32 values and arithmetic): one wave per run of kStreamRows rows walks
+// the run's nonzeros NB at a time with wave-uniform indices and values, all
+// NB gathers in flight, the accumulator moved at row boundaries. Lane l owns
+// columns cb + 2l, cb + 2l + 1 of each 128-column block; per row the sum runs
+// over the nonzeros in order, as in spmm_lp_kernel.
+constexpr int kStreamRows = 32;
+
+template <class T, int NB>
+__global__ __launch_bounds__(kThreads) void spmm_lp_stream_kernel(int n, const int* __restrict__ rowptr,
+                                                                  const int* __restrict__ col,
+                                                                  const float* __restrict__ val,
+                                                                  const T* __restrict__ X, long long ldx,
+                                                                  T* __restrict__ Y, long long ldy, int w) {
+    const int lane = threadIdx.x & 63;
+    const int wid = __builtin_amdgcn_readfirstlane((int)blockIdx.x * (kThreads / 64) + (int)(threadIdx.x >> 6));
+    if ((long long)wid * kStreamRows >= n) return;
+    const int r0 = wid * kStreamRows;
+    const int r1 = min(n, r0 + kStreamRows);
+    const int rp = rowptr[min(r0 + lane, r1)];
+    const int pbeg = __builtin_amdgcn_readlane(rp, 0);
+    const int pend = __builtin_amdgcn_readlane(rp, r1 - r0);
+    for (int cb = 0; cb < w; cb += 128) {
+        const int c0 = cb + 2 * lane;
+        const bool has0 = c0 < w, has1 = c0 + 1 < w;
+        const long long cc = has0 ? c0 : cb;
+        int r = r0;
+        int rend = __builtin_amdgcn_readlane(rp, 1);
+        float a0 = 0.f, a1 = 0.f;
+        auto flush = [&]() {
+            T* y = Y + (long long)r * ldy + c0;
+            if (has1)
+                st2(y, a0, a1);
+            else if (has0)
+                st1(y, a0);
+            a0 = 0.f;
+            a1 = 0.f;
+            ++r;
+            if (r < r1) rend = __builtin_amdgcn_readlane(rp, r - r0 + 1);
+        };
+        for (int p = pbeg; p < pend; p += NB) {
+            int j[NB];
+            float v[NB];
+#pragma unroll
+            for (int u = 0; u < NB; ++u) {
+                j[u] = col[p + u];
+                v[u] = val[p + u];
+            }
+            float x0[NB], x1[NB];
+#pragma unroll
+            for (int u = 0; u < NB; ++u) ld2(X + (long long)j[u] * ldx + cc, x0[u], x1[u]);
+#pragma unroll
+            for (int u = 0; u < NB; ++u) {
+                if (p + u < pend) {
+                    while (p + u >= rend) flush();
+                    a0 = fmaf(v[u], x0[u], a0);
+                    a1 = fmaf(v[u], x1[u], a1);
+                }
+            }
+        }
+        while (r < r1) flush();
+    }
+}
+
 template <class T, int LPR>
 hipError_t spmm_lp_launch(hipStream_t st, int n, const int* rowptr, const int* col, const float* val,
                           const T* X, long long ldx, T* Y, long long ldy, int w, const int* heavy,
@@ -676,6 +758,13 @@ hipError_t launch_spmm_lp(hipStream_t st, int n, const int* rowptr, const int* c
                           int n_heavy) {
     if (n <= 0 || w <= 0) return hipSuccess;
     if (!ld_ok(ldx, w) || !ld_ok(ldy, w)) return hipErrorInvalidValue;
+    if (n_heavy == 0) {
+        const long long waves = ((long long)n + kStreamRows - 1) / kStreamRows;
+        const int grid = (int)((waves + kThreads / 64 - 1) / (kThreads / 64));
+        hipLaunchKernelGGL((spmm_lp_stream_kernel<T, 16>), dim3(grid), dim3(kThreads), 0, st, n, rowptr, col, val,
+                           X, ldx, Y, ldy, w);
+        return hipGetLastError();
+    }
     const int quads = (w + 3) / 4;
 #define SE_SPMM(L) return spmm_lp_launch<T, L>(st, n, rowptr, col, val, X, ldx, Y, ldy, w, heavy, n_heavy)
     if (quads <= 1) SE_SPMM(1);

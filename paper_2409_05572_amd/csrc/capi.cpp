@@ -28,14 +28,7 @@ bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15u) ==
 namespace {
 bool valid_ld_lp(int64_t ld, int32_t w) { return ld % 8 == 0 && ld >= (int64_t)((w + 7) / 8 * 8); }
 bool lp_precision(int32_t pr) { return pr == SE_FP32_MIXED || pr == SE_BF16_MIXED; }
-hipError_t ensure_val32(se_ctx* ctx, const se_matrix* A) {
-    if (A->val32) return hipSuccess;
-    float* v = nullptr;
-    hipError_t e = hipMalloc(&v, sizeof(float) * (size_t)std::max<int64_t>(A->nnz, 1));
-    if (e != hipSuccess) return e;
-    A->val32 = v;
-    return se::launch_f64_to_f32(ctx->stream, A->nnz, A->val, v);
-}
+hipError_t ensure_val32(se_ctx* ctx, const se_matrix* A) { return se::make_val32(ctx->stream, A); }
 template <class T>
 hipError_t gram_lp_call(se_ctx* ctx, int64_t n, const void* U, int64_t ldu, int32_t mu, const void* V,
                         int64_t ldv, int32_t mv, double* C) {

@@ -868,12 +868,7 @@ struct Solver {
             HC(ws.lp_panel[i].ensure(bytes));
             lp[i] = ws.lp_panel[i].p;
         }
-        if (!A->val32) {
-            float* v = nullptr;
-            HC(hipMalloc(&v, sizeof(float) * (size_t)std::max<long long>(A->nnz, 1)));
-            A->val32 = v;
-            HC(launch_f64_to_f32(st, A->nnz, A->val, v));
-        }
+        HC(make_val32(st, A));
         return SE_OK;
     }
     template <class T>
@@ -1351,6 +1346,22 @@ struct Solver {
 // Device workspace a solve of this shape allocates (the sizes of
 // Solver::alloc_panels, alloc_small and lp_alloc), plus the FP32 copy of the
 // matrix values for mixed precision.
+hipError_t make_val32(hipStream_t st, const se_matrix* A) {
+    if (A->val32) return hipSuccess;
+    float* v = nullptr;
+    hipError_t e = hipMalloc(&v, sizeof(float) * ((size_t)A->nnz + kCsrPad));
+    if (e != hipSuccess) return e;
+    e = hipMemsetAsync(v + A->nnz, 0, sizeof(float) * kCsrPad, st);
+    if (e == hipSuccess) e = launch_f64_to_f32(st, A->nnz, A->val, v);
+    if (e != hipSuccess) {
+        (void)hipStreamSynchronize(st);
+        (void)hipFree(v);
+        return e;
+    }
+    A->val32 = v;
+    return hipSuccess;
+}
+
 size_t solve_workspace_bytes(long long n, long long nnz, int nb, int precision, int solver) {
     const long long ld = round_up(nb, 8);
     const int mmax = solver == SE_SI ? nb : 3 * nb;
@@ -1361,7 +1372,7 @@ size_t solve_workspace_bytes(long long n, long long nnz, int nb, int precision, 
                    3 * (2 * (size_t)mmax + 16) + 6 * mm + (size_t)mmax + 8;
     if (precision != SE_FP64) {
         const size_t es = precision == SE_FP32_MIXED ? 4 : 2;
-        bytes += es * (size_t)kNumLpPanels * n * ld + sizeof(float) * (size_t)nnz;
+        bytes += es * (size_t)kNumLpPanels * n * ld + sizeof(float) * ((size_t)nnz + kCsrPad);
         small += 6 * mm;
     }
     return bytes + sizeof(double) * small;

@@ -161,5 +161,8 @@ namespace se {
 se_status solve(se_ctx* ctx, const se_matrix* A, const se_params* p, const double* X0, double* V,
                 double* lambda, se_info* info);
 size_t solve_workspace_bytes(long long n, long long nnz, int nb, int precision, int solver);
+// FP32 copy of the matrix values (A->val32, with kCsrPad zero entries after
+// the last), made once per matrix, ordered on `st`.
+hipError_t make_val32(hipStream_t st, const se_matrix* A);
 se_status validate_solve(const se_matrix* A, const se_params* p);
 }

@@ -176,15 +176,9 @@ se_status se_submit(se_server* srv, const se_matrix* A, const se_params* params,
     if (params->precision != SE_FP64 && !A->val32) {
         // the FP32 copy of the values is made here, once, not by concurrent solves
         if (hipSetDevice(srv->device) != hipSuccess) return SE_ERR_HIP;
-        float* v32 = nullptr;
-        if (hipMalloc(&v32, sizeof(float) * (size_t)std::max<int64_t>(A->nnz, 1)) != hipSuccess)
-            return SE_ERR_OOM;
-        if (se::launch_f64_to_f32(nullptr, A->nnz, A->val, v32) != hipSuccess ||
-            hipStreamSynchronize(nullptr) != hipSuccess) {
-            (void)hipFree(v32);
-            return SE_ERR_HIP;
-        }
-        A->val32 = v32;
+        const hipError_t e = se::make_val32(nullptr, A);
+        if (e == hipErrorOutOfMemory) return SE_ERR_OOM;
+        if (e != hipSuccess || hipStreamSynchronize(nullptr) != hipSuccess) return SE_ERR_HIP;
     }
     std::lock_guard<std::mutex> lk(srv->mu);
     if (srv->stop) return SE_ERR_REJECTED;

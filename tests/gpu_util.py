@@ -37,3 +37,24 @@ def cluster_angles(lam, V, W, rtol=1e-6):
             worst = max(worst, float(np.sqrt(max(0.0, 1.0 - min(1.0, s.min()) ** 2))))
         i = j
     return worst
+
+
+def matrix_with_empty_runs():
+    """Rows of 1-12 nonzeros with empty rows at the start and end of 32-row
+    runs, a fully empty run, an empty last row, n not a multiple of 32."""
+    import numpy as np
+    import scipy.sparse as sp
+
+    import workloads as W
+
+    n = 3001
+    rng = np.random.default_rng(17)
+    deg = rng.integers(1, 13, n)
+    empty = [0, 31, 32, 63, 2999, 3000] + list(range(64, 130))
+    deg[empty] = 0
+    rows = np.repeat(np.arange(n), deg)
+    cols = rng.integers(0, n, deg.sum())
+    a = sp.csr_matrix((rng.standard_normal(deg.sum()), (rows, cols)), shape=(n, n))
+    a.sum_duplicates()
+    a.sort_indices()
+    return W.CSRMatrix(n, a.indptr.astype(np.int64), a.indices.astype(np.int32), a.data, 1.0)

@@ -4,7 +4,7 @@ import pytest
 
 import oracle.solvers as OS
 import workloads as W
-from tests.gpu_util import gpu_ctx, to_dev
+from tests.gpu_util import gpu_ctx, matrix_with_empty_runs, to_dev
 
 pytestmark = pytest.mark.gpu
 
@@ -68,29 +68,11 @@ def test_spmm_empty_rows_and_hub_row(ctx):
     assert np.allclose(Y, ref, rtol=1e-13, atol=1e-12)
 
 
-def _matrix_with_empty_runs():
-    """Rows of 1-12 nonzeros with empty rows at the start and end of 32-row
-    runs, a fully empty run, an empty last row, n not a multiple of 32."""
-    import scipy.sparse as sp
-
-    n = 3001
-    rng = np.random.default_rng(17)
-    deg = rng.integers(1, 13, n)
-    empty = [0, 31, 32, 63, 2999, 3000] + list(range(64, 130))
-    deg[empty] = 0
-    rows = np.repeat(np.arange(n), deg)
-    cols = rng.integers(0, n, deg.sum())
-    a = sp.csr_matrix((rng.standard_normal(deg.sum()), (rows, cols)), shape=(n, n))
-    a.sum_duplicates()
-    a.sort_indices()
-    return W.CSRMatrix(n, a.indptr.astype(np.int64), a.indices.astype(np.int32), a.data, 1.0)
-
-
 @pytest.mark.parametrize("w", [1, 2, 3, 64, 96, 127, 128, 129, 250])
 def test_spmm_empty_rows_without_heavy_rows(ctx, w):
     from paper_2409_05572_amd import api
 
-    A = _matrix_with_empty_runs()
+    A = matrix_with_empty_runs()
     assert np.diff(A.rowptr).max() <= 64  # no heavy rows: the streaming kernel alone
     M = api.Matrix.from_csr(ctx, A)
     ld = w + (w % 2)

@@ -74,6 +74,29 @@ def test_spmm_lp_matches_product_of_stored_values(ctx, fmt, w):
 
 
 @pytest.mark.parametrize("fmt", ["fp32", "bf16"])
+@pytest.mark.parametrize("w", [1, 2, 7, 96, 129, 250])
+def test_spmm_lp_empty_rows(ctx, fmt, w):
+    import torch
+
+    from paper_2409_05572_amd import api
+    from tests.gpu_util import matrix_with_empty_runs
+
+    A = matrix_with_empty_runs()
+    rng = np.random.default_rng(w + 5)
+    X, Xs = _block(rng.standard_normal((A.n, w)), fmt)
+    Y = torch.full_like(X, 3.0)
+    api.spmm_lp(ctx, api.Matrix.from_csr(ctx, A), X, Y, w)
+    got = _read(Y, w)
+    A32 = A.to_scipy().astype(np.float32).astype(np.float64)
+    ref = A32 @ Xs
+    deg = np.diff(A.rowptr)
+    assert np.all(got[deg == 0] == 0.0)
+    bound = (deg.max() + 2) * U32 * (abs(A32) @ abs(Xs)) + UNIT[fmt] * abs(ref) + 1e-300
+    assert np.all(np.abs(got - ref) <= bound)
+    assert np.all(Y[:, w:].float().cpu().numpy() == 3.0)  # padding columns untouched
+
+
+@pytest.mark.parametrize("fmt", ["fp32", "bf16"])
 @pytest.mark.parametrize("w", [3, 48, 130])
 def test_spmm_lp_power_law_rows(ctx, fmt, w):
     import torch
