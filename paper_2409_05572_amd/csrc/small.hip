@@ -293,13 +293,15 @@ __global__ __launch_bounds__(kTri) void tridiag_kernel(int m, int kend, double* 
 // ---------------------------------------------------------------------------
 // Register-resident Householder tridiagonalization for m <= min(16 RR, 32 RC).
 // 512 threads form a 16 x 32 grid; thread (ty, tx) owns the elements (r, c)
-// with r = 16 i + ty, c = 32 j + tx (i < RR, j < RC) in registers. Per
-// reflector: the owners of column k publish it to LDS (barrier), every wave
-// reduces the Householder scalars itself, each thread forms its share of
-// p = tau A22 v and the 32 lanes of a row combine it by shuffles (barrier),
-// every wave reduces K = tau/2 p.v itself, and each thread applies the rank-2
-// update to its own registers. LDS vectors are double-buffered by step
-// parity, so three barriers per reflector suffice. Output as tridiag_kernel.
+// with r = 16 i + ty, c = 32 j + tx (i < RR, j < RC) in registers; elements
+// past m are zero. Per reflector k: the owners of column k publish it to LDS
+// (barrier), every wave reduces the Householder scalars itself, each thread
+// forms its share of p = tau A22 v and a row-partial sum per owned row
+// (barrier), one thread per row completes p (barrier), every wave reduces
+// K = tau/2 p.v, and each thread applies A22 -= v w^T + w v^T to all of its
+// elements. v and w are exactly zero outside rows k+1 .. m-1, so the update
+// needs no per-element test and leaves the reduced part and the padding
+// unchanged. LDS vectors are double-buffered by step parity.
 template <int RR, int RC>
 __global__ __launch_bounds__(512) void tridiag_reg_kernel(int mfull, int k0,
                                                           const double* __restrict__ Ag,
@@ -314,12 +316,18 @@ __global__ __launch_bounds__(512) void tridiag_reg_kernel(int mfull, int k0,
     double* e = eg + k0;
     double* tau = taug + k0;
     constexpr int NT = 512;
-    __shared__ double sx[2][32 * RC];  // column k (rows > k)
-    __shared__ double sp[2][32 * RC];  // tau * A22 v
-    __shared__ double rowpart[16 * RR][33];  // per-thread row partials of A22 v
+    constexpr int MR = 16 * RR, MC = 32 * RC;
+    constexpr int ML = MR > MC ? MR : MC;
+    __shared__ double sx[2][ML];      // column k (rows owned; zero past m)
+    __shared__ double sp[2][ML];      // tau A22 v, zero outside k+1 .. m-1
+    __shared__ double rowpart[MR][33];  // per-thread row partials of A22 v
     const int t = threadIdx.x;
     const int tx = t & 31, ty = t >> 5;
     const int lane = t & 63;
+    for (int q = t; q < 2 * ML; q += NT) {
+        (&sx[0][0])[q] = 0.0;
+        (&sp[0][0])[q] = 0.0;
+    }
     double a[RR][RC];
 #pragma unroll
     for (int i = 0; i < RR; ++i)
@@ -328,20 +336,19 @@ __global__ __launch_bounds__(512) void tridiag_reg_kernel(int mfull, int k0,
             const int r = 16 * i + ty, c = 32 * j + tx;
             a[i][j] = (r < m && c < m) ? Ag[(size_t)(k0 + r) * mfull + (k0 + c)] : 0.0;
         }
+    __syncthreads();
     for (int k = 0; k + 2 < m; ++k) {
         const int par = k & 1;
         const int kj = k >> 5;
-        // (1) column k and the diagonal element
+        // (1) column k (all owned rows) and the diagonal element
         if (tx == (k & 31)) {
 #pragma unroll
             for (int i = 0; i < RR; ++i) {
-                const int r = 16 * i + ty;
                 double x = 0.0;
 #pragma unroll
-                for (int j = 0; j < RC; ++j)
-                    if (j == kj) x = a[i][j];
-                if (r > k && r < m) sx[par][r] = x;
-                if (r == k) d[k] = x;
+                for (int j = 0; j < RC; ++j) x = (j == kj) ? a[i][j] : x;
+                sx[par][16 * i + ty] = x;
+                if (16 * i + ty == k) d[k] = x;
             }
         }
         __syncthreads();
@@ -366,14 +373,15 @@ __global__ __launch_bounds__(512) void tridiag_reg_kernel(int mfull, int k0,
             Vhg[(size_t)(k0 + k) * mfull + (k0 + r)] = (q == 0) ? 1.0 : (tk != 0.0 ? sx[par][r] * scale : 0.0);
         }
         if (tk == 0.0) continue;  // uniform; the next step uses the other buffers
-        // (3) p = tau A22 v: row partials over this thread's columns, then a
-        // 32-lane reduction per row
+        // v on this thread's columns: 1 at k+1, x scale on k+2 .. m-1, else 0
         double vc[RC];
 #pragma unroll
         for (int j = 0; j < RC; ++j) {
             const int c = 32 * j + tx;
-            vc[j] = (c > k && c < m) ? ((c == k + 1) ? 1.0 : sx[par][c] * scale) : 0.0;
+            const double xs = sx[par][c] * scale;
+            vc[j] = (c == k + 1) ? 1.0 : ((c > k + 1 && c < m) ? xs : 0.0);
         }
+        // (3) row partials of A22 v over this thread's columns
 #pragma unroll
         for (int i = 0; i < RR; ++i) {
             double sacc = 0.0;
@@ -382,11 +390,11 @@ __global__ __launch_bounds__(512) void tridiag_reg_kernel(int mfull, int k0,
             rowpart[16 * i + ty][tx] = sacc;
         }
         __syncthreads();
-        for (int r = k + 1 + t; r < m; r += NT) {
+        if (t < MR) {
             double sacc = 0.0;
 #pragma unroll
-            for (int q = 0; q < 32; ++q) sacc += rowpart[r][q];
-            sp[par][r] = tk * sacc;
+            for (int q = 0; q < 32; ++q) sacc += rowpart[t][q];
+            sp[par][t] = (t > k && t < m) ? tk * sacc : 0.0;
         }
         __syncthreads();
         // (4) K = tau/2 p.v, reduced redundantly by every wave
@@ -394,21 +402,18 @@ __global__ __launch_bounds__(512) void tridiag_reg_kernel(int mfull, int k0,
         for (int r = k + 1 + lane; r < m; r += 64)
             pv += sp[par][r] * ((r == k + 1) ? 1.0 : sx[par][r] * scale);
         const double Kc = 0.5 * tk * wave_sum(pv);
-        // (5) A22 -= v w^T + w v^T with w = p - K v (w_c re-read from LDS per
-        // element to keep the register block within budget)
+        // (5) A22 -= v w^T + w v^T with w = p - K v, on every owned element
+        double wc[RC];
+#pragma unroll
+        for (int j = 0; j < RC; ++j) wc[j] = sp[par][32 * j + tx] - Kc * vc[j];
 #pragma unroll
         for (int i = 0; i < RR; ++i) {
             const int r = 16 * i + ty;
-            if (r > k && r < m) {
-                const double vr = (r == k + 1) ? 1.0 : sx[par][r] * scale;
-                const double wr = sp[par][r] - Kc * vr;
+            const double xs = sx[par][r] * scale;
+            const double vr = (r == k + 1) ? 1.0 : ((r > k + 1 && r < m) ? xs : 0.0);
+            const double wr = sp[par][r] - Kc * vr;
 #pragma unroll
-                for (int j = 0; j < RC; ++j) {
-                    const int c = 32 * j + tx;
-                    const double wcj = (c > k && c < m) ? sp[par][c] - Kc * vc[j] : 0.0;
-                    a[i][j] -= vr * wcj + wr * vc[j];
-                }
-            }
+            for (int j = 0; j < RC; ++j) a[i][j] -= vr * wc[j] + wr * vc[j];
         }
     }
     // last 2 x 2 block
