@@ -742,7 +742,9 @@ void gram_plan(long long n, int mu, int mv, int sym, int& ntiles, int& nt_v, int
     const int nt_u = (mu + GT - 1) / GT;
     nt_v = (mv + GT - 1) / GT;
     ntiles = sym ? nt_u * (nt_u + 1) / 2 : nt_u * nt_v;
-    long long want = (640 + ntiles - 1) / ntiles;  // ~2.5 workgroups per CU
+    // Two full waves of resident workgroups (2 per CU x 256 CUs, twice), never
+    // more: a partly filled last wave leaves most CUs idle while it runs.
+    long long want = 1024 / ntiles;
     const long long maxc = (n + 255) / 256;        // at least 256 rows per chunk
     if (want > maxc) want = maxc;
     if (want < 1) want = 1;
