@@ -159,6 +159,7 @@ def main():
             "n_expands": infos[-1].n_expands, "max_stop_ratio": infos[-1].max_stop_ratio,
             "converged": infos[-1].converged, "low_precision_iterations": infos[-1].lp_iterations,
             "reprojections": infos[-1].n_reprojections,
+            "implicit_orthonormalizations": int(((infos[-1].history[:, 7].astype(int) & 8) != 0).sum()),
         },
     }
     lam_np = lam.cpu().numpy()

@@ -71,7 +71,9 @@ typedef struct se_matrix se_matrix;
 #define SE_HISTORY_FIELDS 8
 /* j, r(j) by eq. (rk), max stop ratio, width k, width p, active a, locked, flags
  * (bit 0 = expanded this iteration, bit 1 = shrunk this iteration, bit 2 = iteration of
- * the low-precision phase of a mixed-precision solve) */
+ * the low-precision phase of a mixed-precision solve, bit 3 = FP64 LOBPCG iteration whose
+ * residual block was orthonormalized implicitly, by whitening the Gram matrix of
+ * [X, P, W] in coefficient space) */
 
 /* Kernel classes of se_info.kern_* */
 #define SE_K_SPMM 0   /* CSR sparse x block */

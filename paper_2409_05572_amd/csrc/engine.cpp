@@ -84,7 +84,7 @@ struct Solver {
     double *Xn = nullptr, *Pn = nullptr, *AXn = nullptr, *APn = nullptr;
     double *Sd = nullptr, *ASd = nullptr, *T1 = nullptr, *T2 = nullptr;
 
-    int iters = 0, n_shr = 0, n_exp = 0, hist_len = 0, n_reproj = 0;
+    int iters = 0, n_shr = 0, n_exp = 0, hist_len = 0, n_reproj = 0, n_implicit = 0;
     int j_off = 0;       // iterations of an earlier (low-precision) phase
     int lp_iters = 0;    // iterations of the low-precision phase
     bool lp_done = false;  // the low-precision phase met the stopping test itself
@@ -162,7 +162,7 @@ struct Solver {
             for (DevBuf* b : cb) HC(b->ensure(sizeof(double) * mm));
             HC(ws.idx.ensure(sizeof(int) * (mmax + 8)));
         }
-        if (p.precision != SE_FP64) {
+        {
             DevBuf* lpb[] = {&ws.lpM, &ws.lpT, &ws.lpQ, &ws.lpB, &ws.lpE, &ws.lpC};
             for (DevBuf* b : lpb) HC(b->ensure(sizeof(double) * mm));
         }
@@ -540,6 +540,8 @@ struct Solver {
     // Every kAxpRefresh iterations the whole of A_p is recomputed over n, so
     // rounding in the carried [X, P] block cannot accumulate.
     static constexpr int kAxpRefresh = 10;
+    // Smallest scaled Schur-complement pivot for the implicit orthonormalization of W.
+    static constexpr double kImplicitPiv = 1e-2;
     // X0: FP64 column-major start block; k0 >= 0: the X panel already holds
     // k0 start columns (row-major), e.g. from the low-precision phase.
     // p0 > 0: the P panel holds p0 search directions to continue with (they
@@ -615,17 +617,54 @@ struct Solver {
             // suffices; a second one runs when a column lost more than half of
             // its squared norm (its squared norm is the residual norm above).
             const Segs XP = seg3(X, k, P, pw, nullptr, 0);
-            ST(gram(XP, seg1(W, a), 0, ws.G.as<double>()));
-            ST(update(XP, ws.G.as<double>(), a, seg1(W, a), -1.0, 1.0));
-            // In iterations that take the carried-A_p path (no expansion, no
-            // refresh), the last Cholesky-QR transform T of W is not applied:
-            // the orthonormal block is W T, and T enters the Gram S^T (A W) and
-            // the coefficients of the basis update instead.
-            const bool carried_path =
-                axp_q == k + pw && !(want_expand && have_drop) && j % kAxpRefresh != 0;
+            const bool expand_now = want_expand && have_drop;
+            // Implicit orthonormalization of W (iterations without an
+            // expansion): with G = [X, P]^T W and H = W^T W, the Gram matrix of
+            // S = [X, P, W] is M = [[I, G], [G^T, H]]; its whitening
+            // T_M = [[I, -G R^-1], [0, R^-1]] (R from the Schur complement
+            // H - G^T G) makes S T_M orthonormal, and the Rayleigh-Ritz step
+            // runs on T_M^T A_p T_M. W is neither projected nor
+            // orthonormalized over n. It is taken only when the smallest
+            // scaled pivot of the Schur complement is at least kImplicitPiv
+            // (one Cholesky pass then leaves an error of order u / pivot);
+            // otherwise W is projected and orthonormalized explicitly.
+            bool implicit = false;
+            int r_w = 0;
+            const int q0 = k + pw;
+            double* GH = ws.apc.as<double>();  // (q0 + a) x a: G on top of H (apc is free here)
+            if (!expand_now && a > 0) {
+                const int m0 = q0 + a;
+                ST(gram(XP, seg1(W, a), 0, GH));
+                ST(gram(seg1(W, a), seg1(W, a), 1, GH + (size_t)q0 * a));
+                double* I0 = ws.axq.as<double>();
+                HC(launch_fill(st, q0, q0, I0, q0, 0.0));
+                HC(launch_add_diag(st, q0, I0, q0, 1.0));
+                HC(launch_assemble_ap(st, m0, q0, I0, GH, ws.lpM.as<double>()));
+                double minpiv = 0.0;
+                ST(tic());
+                ST(whiten(m0, q0, 1e-13, r_w, &minpiv));
+                ST(toc(SE_K_SMALL, 16.0 * m0 * m0, 2.0 * m0 * m0 * (double)a));
+                implicit = minpiv >= kImplicitPiv && r_w >= n_ev;
+                if (implicit) {
+                    ++n_implicit;
+                    flags |= 8;
+                }
+            }
             bool folded = false;
-            double* fold_T = carried_path ? ws.wfold.as<double>() : nullptr;
-            {
+            if (!implicit) {
+                if (!expand_now && a > 0) {
+                    // G is in hand: W <- W - [X, P] G
+                    ST(update(XP, GH, a, seg1(W, a), -1.0, 1.0));
+                } else {
+                    ST(gram(XP, seg1(W, a), 0, ws.G.as<double>()));
+                    ST(update(XP, ws.G.as<double>(), a, seg1(W, a), -1.0, 1.0));
+                }
+                // In iterations that take the carried-A_p path (no expansion,
+                // no refresh), the last Cholesky-QR transform T of W is not
+                // applied: the orthonormal block is W T, and T enters the Gram
+                // S^T (A W) and the coefficients of the basis update instead.
+                const bool carried_path = axp_q == k + pw && !expand_now && j % kAxpRefresh != 0;
+                double* fold_T = carried_path ? ws.wfold.as<double>() : nullptr;
                 const double* nr = ws.h_norms.as<double>();
                 std::vector<double> wn2(a);
                 for (int q = 0; q < a; ++q) wn2[q] = nr[act[q]];
@@ -641,7 +680,7 @@ struct Solver {
             if (a > 0) ST(spmm(W, AW, a));
 
             act_hl = act;
-            if (want_expand && have_drop) {
+            if (expand_now) {
                 // S_drop <- S_drop - S (S^T S_drop), twice; orthonormalize;
                 // then its images A S_drop by one SpMM.
                 int d0 = dx + dp;
@@ -686,18 +725,32 @@ struct Solver {
                 ap_valid = true;
                 ST(gram(S, AS, 1, ws.G.as<double>()));
             }
-            HC(launch_copy_cols(st, m, ws.G.as<double>(), m, 0, ws.apc.as<double>(), m, 0, m));
-            ST(tic());
-            HC(launch_syev_lowest(st, m, k, ws.G.as<double>(), ws.theta.as<double>(), ws.Z.as<double>(),
-                                  ws.syev_work.as<double>()));
-            ST(toc(SE_K_EIG, 8.0 * m * m, 4.0 * m * m * (double)m / 3.0));
             const int ahl = (int)act_hl.size();
             std::memcpy(ws.h_act_hl.p, act_hl.data(), sizeof(int) * ahl);
             HC(hipMemcpyAsync(ws.act_hl.p, ws.h_act_hl.p, sizeof(int) * ahl, hipMemcpyHostToDevice, st));
             int rPv = 0;
-            ST(tic());
-            ST(hl_coefficients(m, k, ahl, rPv));
-            ST(toc(SE_K_SMALL, 16.0 * m * (k + ahl), 8.0 * m * (double)k * ahl));
+            int mr = m;  // order of the (whitened) Rayleigh-Ritz matrix kept in apc
+            const double* Cupd = ws.C.as<double>();
+            if (implicit) {
+                // generalized Rayleigh-Ritz in the whitened basis S T_M; the
+                // update coefficients T_M [Z1 | C_P] are in ws.lpC
+                ST(grr(m, k + pw, k, ahl, 1e-13, rPv, r_w, ws.apc.as<double>()));
+                mr = r_w;
+                Cupd = ws.lpC.as<double>();
+            } else {
+                HC(launch_copy_cols(st, m, ws.G.as<double>(), m, 0, ws.apc.as<double>(), m, 0, m));
+                ST(tic());
+                HC(launch_syev_lowest(st, m, k, ws.G.as<double>(), ws.theta.as<double>(), ws.Z.as<double>(),
+                                      ws.syev_work.as<double>()));
+                ST(toc(SE_K_EIG, 8.0 * m * m, 4.0 * m * m * (double)m / 3.0));
+                ST(tic());
+                ST(hl_coefficients(m, k, ahl, rPv));
+                ST(toc(SE_K_SMALL, 16.0 * m * (k + ahl), 8.0 * m * (double)k * ahl));
+                if (folded) {
+                    ST(fold_coefficients(m, k + pw, a, k + rPv));
+                    Cupd = ws.cfold.as<double>();
+                }
+            }
             const int rP = rPv;
             // New basis over n; its image A X by one SpMM (no carried images:
             // as cheap as updating them for sparse A, and exact each step).
@@ -705,23 +758,19 @@ struct Solver {
             Segs O = make_segs(ld);
             push_seg(O, Xn, k);
             push_seg(O, Pn, rP);
-            if (folded) {
-                ST(fold_coefficients(m, k + pw, a, k + rP));
-                ST(update(S, ws.cfold.as<double>(), k + rP, O, 1.0, 0.0));
-            } else {
-                ST(update(S, ws.C.as<double>(), k + rP, O, 1.0, 0.0));
-            }
+            ST(update(S, Cupd, k + rP, O, 1.0, 0.0));
             std::swap(X, Xn);
             std::swap(P, Pn);
             pw = rP;
             ST(spmm(X, AX, k));
             ap_valid = false;
-            // carried [X, P]^T A [X, P] = C^T A_p C (small products)
+            // carried [X, P]^T A [X, P] = C^T A_p C (small products in the
+            // orthonormal, possibly whitened, basis of order mr)
             {
                 const int q = k + rP;
-                ST(update_rows(m, segx(ws.apc.as<double>(), m, m), ws.C.as<double>(), q,
+                ST(update_rows(mr, segx(ws.apc.as<double>(), mr, mr), ws.C.as<double>(), q,
                                segx(ws.axq.as<double>(), q, q), 1.0, 0.0));
-                ST(gram_rows(m, segx(ws.C.as<double>(), q, q), segx(ws.axq.as<double>(), q, q), 1,
+                ST(gram_rows(mr, segx(ws.C.as<double>(), q, q), segx(ws.axq.as<double>(), q, q), 1,
                              ws.axp.as<double>()));
                 axp_q = q;
             }
@@ -922,7 +971,8 @@ struct Solver {
     //   T11 = M11^{-1/2} = I - E/2 + 3E^2/8 - 5E^3/16,
     //   T_M = [[T11, B T22], [0, T22]].
     // Otherwise (or when the check fails) the whole of M is factorized.
-    se_status whiten(int m, int q, double drop2, int& r) {
+    se_status whiten(int m, int q, double drop2, int& r, double* minpiv = nullptr) {
+        if (minpiv) *minpiv = 0.0;
         double* M = ws.lpM.as<double>();
         double* TM = ws.lpT.as<double>();
         int* info_i = ws.info.as<int>();
@@ -971,6 +1021,7 @@ struct Solver {
             ST(sync());
             const int r2 = ws.h_info.as<int>()[0];
             const double e2 = ws.h_info.as<double>()[doff + 1];
+            if (minpiv) *minpiv = ws.h_info.as<double>()[doff];
             if (e2 <= 1e-4) {
                 r = q + r2;
                 if (r2 > 0) ST(update_rows(q, segx(Fa, a2, a2), T22, r2, segx(BT, r2, r2), 1.0, 0.0));
@@ -996,18 +1047,23 @@ struct Solver {
     // act_hl (indices into S), whose coordinates there are E' = T_M^T M E.
     // Output: the coefficients C = T_M [Y | C_P'] in ws.lpC (m x (k + rP));
     // k is lowered to r if fewer columns survive.
-    se_status grr(int m, int q, int& k, int ahl, double drop2, int& rP) {
+    // r_given >= 0: T_M is already in ws.lpT with r columns (whiten was
+    // called by the caller). ap_copy: receives T_M^T A_p T_M (r x r) before
+    // the eigensolver overwrites it.
+    se_status grr(int m, int q, int& k, int ahl, double drop2, int& rP, int r_given = -1,
+                  double* ap_copy = nullptr) {
         double* M = ws.lpM.as<double>();
         double* TM = ws.lpT.as<double>();
         double* Q = ws.lpQ.as<double>();
         double* Ar = ws.lpB.as<double>();
         ST(tic());
-        int r = 0;
-        ST(whiten(m, q, drop2, r));
+        int r = r_given;
+        if (r < 0) ST(whiten(m, q, drop2, r));
         if (r < n_ev) return SE_ERR_BREAKDOWN;
         k = std::min(k, r);
         ST(update_rows(m, segx(ws.G.as<double>(), m, m), TM, r, segx(Q, r, r), 1.0, 0.0));
         ST(gram_rows(m, segx(TM, r, r), segx(Q, r, r), 1, Ar));
+        if (ap_copy) HC(launch_copy_cols(st, r, Ar, r, 0, ap_copy, r, 0, r));
         HC(launch_syev_lowest(st, r, k, Ar, ws.theta.as<double>(), ws.Z.as<double>(),
                               ws.syev_work.as<double>()));
         double* Cr = ws.C.as<double>();
@@ -1369,11 +1425,10 @@ size_t solve_workspace_bytes(long long n, long long nnz, int nb, int precision, 
     size_t bytes = sizeof(double) * (size_t)kNumPanels * n * ld;
     size_t small = 4 * mm + (mmax + 8) + (2 * mm + 8 * (size_t)mmax + 64) + syev_work_doubles(mmax) +
                    std::max(gram_scratch_doubles(n, mmax, mmax), (size_t)4096 * 2 * mmax) + 4 * mm +
-                   3 * (2 * (size_t)mmax + 16) + 6 * mm + (size_t)mmax + 8;
+                   3 * (2 * (size_t)mmax + 16) + 6 * mm + (size_t)mmax + 8 + 6 * mm;
     if (precision != SE_FP64) {
         const size_t es = precision == SE_FP32_MIXED ? 4 : 2;
         bytes += es * (size_t)kNumLpPanels * n * ld + sizeof(float) * ((size_t)nnz + kCsrPad);
-        small += 6 * mm;
     }
     return bytes + sizeof(double) * small;
 }
