@@ -152,6 +152,25 @@ def test_invalid_arguments_are_rejected(ctx):
         api.Matrix.from_csr(ctx, nanm)
 
 
+def test_residual_block_orthonormalized_implicitly_except_at_expansions(ctx):
+    """Most iterations whiten the Gram matrix of [X, P, W] in coefficient
+    space (history bit 3); expansion iterations (bit 0) project and
+    orthonormalize W explicitly. The pairs still meet the closed form, the
+    stopping test and orthonormality to 1e-12."""
+    m = 16
+    A = W.laplacian_3d(m)
+    X0 = W.gaussian_block(A.n, 48, 203)
+    lam, V, info = _gpu_solve(ctx, A, X0, 32, 16, strategy="fix")
+    fl = info.history[:, 7].astype(int)
+    assert info.converged and info.n_expands >= 1
+    assert ((fl & 8) != 0).sum() >= 0.6 * len(fl)
+    assert not np.any(((fl & 1) != 0) & ((fl & 8) != 0))
+    exact = pins.laplacian_spectrum(m, 3, 32)
+    assert np.max(np.abs(lam - exact) / exact) <= 1e-10
+    assert np.max(_residual_ratio(A, lam, V)) <= 1e-8 * 1.0001
+    assert np.abs(V.T @ V - np.eye(32)).max() <= 1e-12
+
+
 def test_full_config2_lobpcg_shrink_expand(ctx):
     """3-D 128^3 Laplacian, 64 wanted + 32 extra, fix strategy, at full size:
     every eigenvalue against the closed form; the stopping test recomputed on
