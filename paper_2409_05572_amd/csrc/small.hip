@@ -698,7 +698,9 @@ __device__ double block_sum_1024(double v, double* sh) {
     return s;
 }
 
-__global__ __launch_bounds__(kCoopThreads) void tridiag_coop_kernel(int m, int R, const double* __restrict__ Ag,
+// Reflectors 0 .. kend - 1 only; when it stops early (kend < m - 2) each
+// workgroup writes its updated rows back to Ag for the kernel that continues.
+__global__ __launch_bounds__(kCoopThreads) void tridiag_coop_kernel(int m, int R, int kend, double* __restrict__ Ag,
                                                                     double* __restrict__ d, double* __restrict__ e,
                                                                     double* __restrict__ tau,
                                                                     double* __restrict__ Vh,
@@ -718,7 +720,7 @@ __global__ __launch_bounds__(kCoopThreads) void tridiag_coop_kernel(int m, int R
     for (size_t q = t; q < (size_t)nr * m; q += kCoopThreads) Al[q] = Ag[(size_t)r0 * m + q];
     __syncthreads();
     const int row_sub = t >> 5, lane32 = t & 31;  // 32 row groups of 32 lanes
-    for (int k = 0; k + 2 < m; ++k) {
+    for (int k = 0; k < kend && k + 2 < m; ++k) {
         // A: column k of my rows below the diagonal, partial sigma^2
         double s = 0.0;
         for (int i = max(r0, k + 1) + t; i < r1; i += kCoopThreads) {
@@ -789,6 +791,10 @@ __global__ __launch_bounds__(kCoopThreads) void tridiag_coop_kernel(int m, int R
             }
         }
         __syncthreads();
+    }
+    if (kend < m - 2) {
+        for (size_t q = t; q < (size_t)nr * m; q += kCoopThreads) Ag[(size_t)r0 * m + q] = Al[q];
+        return;
     }
     if (t == 0 && m >= 2) {
         if (m - 2 >= r0 && m - 2 < r1) d[m - 2] = Al[(size_t)(m - 2 - r0) * m + (m - 2)];
@@ -975,31 +981,38 @@ hipError_t launch_syev_lowest(hipStream_t st, int m, int k, double* A, double* w
     int* infoi = reinterpret_cast<int*>(infod + 8);
     const size_t lds = (mm <= (size_t)kLdsDoubles) ? sizeof(double) * mm : 0;
     bool done = false;
-    if (m > 288) {
+    // The cooperative kernel (rows spread over workgroups, in LDS) takes all
+    // reflectors for m > 288 and the first m - kRegOrder ones for smaller m
+    // above kRegOrder; the register kernel takes the trailing block.
+    auto coop = [&](int kend) -> bool {
         // Rows per workgroup so that R m + 2m doubles fit 150 KB of LDS.
         const int R = std::max(1, (int)((150 * 1024 / sizeof(double) - 2 * (size_t)m) / m));
         const int G = (m + R - 1) / R;
+        if (G > 128) return false;
         double* xcol = infod + 64;
         double* xp = xcol + m;
         double* partA = xp + m;
         double* partB = partA + 128;
-        if (G <= 128) {
-            const size_t clds = sizeof(double) * ((size_t)R * m + 2 * (size_t)m);
-            int mm_i = m, R_i = R;
-            void* args[] = {&mm_i, &R_i, &A, &d, &e, &tau, &Vh, &xcol, &xp, &partA, &partB};
-            done = hipLaunchCooperativeKernel((void*)tridiag_coop_kernel, dim3(G), dim3(kCoopThreads), args, clds,
-                                              st) == hipSuccess;
-            if (!done) (void)hipGetLastError();  // fall back to the single-workgroup kernels
-        }
-    }
+        const size_t clds = sizeof(double) * ((size_t)R * m + 2 * (size_t)m);
+        int mm_i = m, R_i = R, kend_i = kend;
+        void* args[] = {&mm_i, &R_i, &kend_i, &A, &d, &e, &tau, &Vh, &xcol, &xp, &partA, &partB};
+        const bool ok = hipLaunchCooperativeKernel((void*)tridiag_coop_kernel, dim3(G), dim3(kCoopThreads), args,
+                                                   clds, st) == hipSuccess;
+        if (!ok) (void)hipGetLastError();  // fall back to the single-workgroup kernels
+        return ok;
+    };
+    constexpr int kRegOrder = 192;
+    if (m > 288) done = coop(m);
     if (done) {
     } else if (m <= 112) {
         hipLaunchKernelGGL(tridiag_kernel<true>, dim3(1), dim3(kTri), lds, st, m, m, A, d, e, tau, Vh);
     } else {
-        // the first m - 224 reflectors in L2, the trailing block (order <= 224)
-        // in registers
-        const int k0 = m > 224 ? m - 224 : 0;
-        if (k0 > 0)
+        // the first m - kRegOrder reflectors by the cooperative kernel (or in
+        // L2 by one workgroup), the trailing block in registers: below order
+        // 192 the register kernel is the faster per reflector, above it the
+        // cooperative one (measured at m = 160 .. 288)
+        const int k0 = m > kRegOrder ? m - kRegOrder : 0;
+        if (k0 > 0 && !coop(k0))
             hipLaunchKernelGGL(tridiag_kernel<false>, dim3(1), dim3(kTri), 0, st, m, k0, A, d, e, tau, Vh);
         switch ((m - k0 + 15) / 16) {
             case 8: hipLaunchKernelGGL((tridiag_reg_kernel<8, 4>), dim3(1), dim3(512), 0, st, m, k0, A, d, e, tau, Vh); break;
