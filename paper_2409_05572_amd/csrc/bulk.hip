@@ -255,6 +255,121 @@ __global__ __launch_bounds__(kThreads) void spmm_stream_kernel(int n, const int*
     }
 }
 
+// The streaming product followed by the residual of the rows it produced:
+// R = Y - X diag(lam) is written for the wave's rows and the per-column sums
+// of r^2 and x^2 over the workgroup's rows go to part[blockIdx.x * 2w + c]
+// (r^2) and part[blockIdx.x * 2w + w + c] (x^2), summed across the four waves
+// in a fixed order. Y and X rows are re-read right after the product, from
+// cache. Requires w <= 128.
+__global__ __launch_bounds__(kThreads) void spmm_resid_kernel(int n, const int* __restrict__ rowptr,
+                                                              const int* __restrict__ col,
+                                                              const double* __restrict__ val,
+                                                              const double* __restrict__ X, long long ldx,
+                                                              double* __restrict__ Y, long long ldy, int w,
+                                                              const double* __restrict__ lam,
+                                                              double* __restrict__ R, long long ldr,
+                                                              double* __restrict__ part) {
+    constexpr int NB = 16;
+    __shared__ double4 red[kThreads];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int wid = __builtin_amdgcn_readfirstlane((int)blockIdx.x * (kThreads / 64) + wv);
+    const int c0 = 2 * lane;
+    const bool has0 = c0 < w, has1 = c0 + 1 < w;
+    double sr0 = 0.0, sr1 = 0.0, sx0 = 0.0, sx1 = 0.0;
+    if ((long long)wid * kStreamRows < n) {
+        const int r0 = wid * kStreamRows;
+        const int r1 = min(n, r0 + kStreamRows);
+        const int rp = rowptr[min(r0 + lane, r1)];
+        const int pbeg = __builtin_amdgcn_readlane(rp, 0);
+        const int pend = __builtin_amdgcn_readlane(rp, r1 - r0);
+        const long long cc = has0 ? c0 : 0;
+        int r = r0;
+        int rend = __builtin_amdgcn_readlane(rp, 1);
+        double a0 = 0.0, a1 = 0.0;
+        auto flush = [&]() {
+            double* y = Y + (long long)r * ldy + c0;
+            if (has1)
+                *reinterpret_cast<double2*>(y) = make_double2(a0, a1);
+            else if (has0)
+                *y = a0;
+            a0 = 0.0;
+            a1 = 0.0;
+            ++r;
+            if (r < r1) rend = __builtin_amdgcn_readlane(rp, r - r0 + 1);
+        };
+        for (int p = pbeg; p < pend; p += NB) {
+            int j[NB];
+            double v[NB];
+#pragma unroll
+            for (int u = 0; u < NB; ++u) {
+                j[u] = col[p + u];
+                v[u] = val[p + u];
+            }
+            double2 x[NB];
+#pragma unroll
+            for (int u = 0; u < NB; ++u) x[u] = *reinterpret_cast<const double2*>(X + (long long)j[u] * ldx + cc);
+#pragma unroll
+            for (int u = 0; u < NB; ++u) {
+                if (p + u < pend) {
+                    while (p + u >= rend) flush();
+                    a0 = fma(v[u], x[u].x, a0);
+                    a1 = fma(v[u], x[u].y, a1);
+                }
+            }
+        }
+        while (r < r1) flush();
+        // residual of the rows just produced (the wave's own stores are
+        // visible to its later loads)
+        const double l0 = has0 ? lam[c0] : 0.0, l1 = has1 ? lam[c0 + 1] : 0.0;
+        for (int rr = r0; rr < r1; rr += 8) {
+            double2 yv[8], xv[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const long long row = min(rr + u, r1 - 1);
+                yv[u] = *reinterpret_cast<const double2*>(Y + row * ldy + cc);
+                xv[u] = *reinterpret_cast<const double2*>(X + row * ldx + cc);
+            }
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                if (rr + u < r1) {
+                    const double q0 = yv[u].x - l0 * xv[u].x, q1 = yv[u].y - l1 * xv[u].y;
+                    double* rp_ = R + (long long)(rr + u) * ldr + c0;
+                    if (has1)
+                        *reinterpret_cast<double2*>(rp_) = make_double2(q0, q1);
+                    else if (has0)
+                        *rp_ = q0;
+                    sr0 = fma(q0, q0, sr0);
+                    sr1 = fma(q1, q1, sr1);
+                    sx0 = fma(xv[u].x, xv[u].x, sx0);
+                    sx1 = fma(xv[u].y, xv[u].y, sx1);
+                }
+            }
+        }
+    }
+    red[threadIdx.x] = make_double4(sr0, sr1, sx0, sx1);
+    __syncthreads();
+    if (wv == 0) {
+        double4 t = red[lane];
+#pragma unroll
+        for (int q = 1; q < kThreads / 64; ++q) {
+            const double4 u = red[q * 64 + lane];
+            t.x += u.x;
+            t.y += u.y;
+            t.z += u.z;
+            t.w += u.w;
+        }
+        double* out = part + (long long)blockIdx.x * 2 * w;
+        if (has0) {
+            out[c0] = t.x;
+            out[w + c0] = t.z;
+        }
+        if (has1) {
+            out[c0 + 1] = t.y;
+            out[w + c0 + 1] = t.w;
+        }
+    }
+}
+
 template <int LPR>
 hipError_t spmm_launch(hipStream_t st, int n, const int* rowptr, const int* col, const double* val,
                        const double* X, long long ldx, double* Y, long long ldy, int w, const int* heavy,
@@ -898,6 +1013,22 @@ hipError_t launch_resid_norms(hipStream_t st, long long n, const double* X, cons
     hipLaunchKernelGGL(resid_norms_kernel, dim3((int)nchunks), dim3(kThreads), 0, st, n, X, AX, ld, k,
                        lam, rows, part, R, ldr);
     return launch_sum_partials(st, 2 * k, (int)nchunks, part, out);
+}
+
+long long spmm_resid_chunks(long long n) {
+    const long long waves = (n + kStreamRows - 1) / kStreamRows;
+    return (waves + kThreads / 64 - 1) / (kThreads / 64);
+}
+
+hipError_t launch_spmm_resid(hipStream_t st, int n, const int* rowptr, const int* col, const double* val,
+                             const double* X, long long ldx, double* Y, long long ldy, int w, const int* heavy,
+                             int n_heavy, const double* lam, double* R, long long ldr, double* part, double* out) {
+    if (n <= 0 || w <= 0 || w > 128 || n_heavy > 0) return hipErrorInvalidValue;
+    const long long grid = spmm_resid_chunks(n);
+    (void)heavy;
+    hipLaunchKernelGGL(spmm_resid_kernel, dim3((unsigned)grid), dim3(kThreads), 0, st, n, rowptr, col, val, X, ldx,
+                       Y, ldy, w, lam, R, ldr, part);
+    return launch_sum_partials(st, 2 * w, (int)grid, part, out);
 }
 
 hipError_t launch_gather_cols(hipStream_t st, long long n, const double* src, long long lds, const int* idx,

@@ -93,6 +93,15 @@ hipError_t launch_resid_norms(hipStream_t st, long long n, const double* X, cons
                               long long ld, int k, const double* lam, double* part, double* out,
                               double* R = nullptr, long long ldr = 0);
 
+// Y = A X (streaming product; matrices without heavy rows, w <= 128) and, for
+// the rows produced, R = Y - X diag(lam) with out[c] = ||r_c||^2 and
+// out[w + c] = ||x_c||^2 (as launch_resid_norms). part is scratch of
+// 2 w spmm_resid_chunks(n) doubles.
+long long spmm_resid_chunks(long long n);
+hipError_t launch_spmm_resid(hipStream_t st, int n, const int* rowptr, const int* col, const double* val,
+                             const double* X, long long ldx, double* Y, long long ldy, int w, const int* heavy,
+                             int n_heavy, const double* lam, double* R, long long ldr, double* part, double* out);
+
 // dst[:, q] = src[:, idx[q]] for q < a (dst must not overlap src).
 hipError_t launch_gather_cols(hipStream_t st, long long n, const double* src, long long lds, const int* idx,
                               int a, double* dst, long long ldd);

@@ -226,6 +226,28 @@ struct Solver {
         HC(launch_spmm(st, (int)n, A->rowptr, A->col, A->val, Xs, ld, Ys, ld, w, A->heavy, A->n_heavy));
         return toc(SE_K_SPMM, 12.0 * A->nnz + 4.0 * (n + 1) + 16.0 * n * w, 2.0 * A->nnz * w);
     }
+    // AX = A X and, in the same pass, W = AX - X Theta with the residual and
+    // column norms in ws.norms (the next residual check reads them). Falls
+    // back to the plain product plus the residual kernel for matrices with
+    // heavy rows or widths above 128.
+    se_status spmm_residual(int k) {
+        if (A->n_heavy > 0 || k > 128) {
+            ST(spmm(X, AX, k));
+            ST(tic());
+            HC(launch_resid_norms(st, n, X, AX, ld, k, ws.theta.as<double>(), ws.gram_part.as<double>(),
+                                  ws.norms.as<double>(), W, ld));
+            return toc(SE_K_RESID, 24.0 * n * k, 5.0 * n * k);
+        }
+        const size_t need = sizeof(double) * 2 * (size_t)k * (size_t)spmm_resid_chunks(n);
+        if (need > ws.gram_part.bytes) {
+            ST(sync());  // the old scratch may still be in use by queued kernels
+            HC(ws.gram_part.ensure(need));
+        }
+        ST(tic());
+        HC(launch_spmm_resid(st, (int)n, A->rowptr, A->col, A->val, X, ld, AX, ld, k, A->heavy, A->n_heavy,
+                             ws.theta.as<double>(), W, ld, ws.gram_part.as<double>(), ws.norms.as<double>()));
+        return toc(SE_K_SPMM, 12.0 * A->nnz + 4.0 * (n + 1) + 24.0 * n * k, 2.0 * A->nnz * k + 5.0 * n * k);
+    }
     se_status gram(const Segs& U, const Segs& V, int sym, double* C) {
         const size_t need = sizeof(double) * gram_scratch_doubles(n, segs_width(U), segs_width(V));
         if (need > ws.gram_part.bytes) {
@@ -573,9 +595,15 @@ struct Solver {
         std::vector<double> stop, paper, lam;
         std::vector<int> act, act_hl, kept;
 
+        int resid_k = -1;  // > 0: W and the norms already hold the residual of (X, AX, theta), width resid_k
         for (int j = 1; j <= p.max_iter; ++j) {
-            // W (dead since the last basis update) receives R = AX - X Theta.
-            ST(check(X, AX, k, stop, paper, lam, W));
+            // W (dead since the last basis update) receives R = AX - X Theta,
+            // unless the product that formed AX wrote it already.
+            if (resid_k == k)
+                ST(check_host(k, stop, paper, lam));
+            else
+                ST(check(X, AX, k, stop, paper, lam, W));
+            resid_k = -1;
             double r = 0.0, ms = 0.0;
             bool all = true;
             for (int i = 0; i < n_ev; ++i) {
@@ -762,7 +790,8 @@ struct Solver {
             std::swap(X, Xn);
             std::swap(P, Pn);
             pw = rP;
-            ST(spmm(X, AX, k));
+            ST(spmm_residual(k));
+            resid_k = k;
             ap_valid = false;
             // carried [X, P]^T A [X, P] = C^T A_p C (small products in the
             // orthonormal, possibly whitened, basis of order mr)
