@@ -107,6 +107,10 @@ typedef struct se_params {
     double time_limit_s; /* wall-clock cap; <= 0 = none */
     double r_switch;     /* mixed precision: leave the low-precision phase once r(j) <= r_switch
                             (or r(j) stops improving); 0 = 1e-5 (FP32), 1e-3 (BF16) */
+    double implicit_pivot; /* FP64 LOBPCG: smallest scaled pivot of the Schur complement of W^T W
+                              for which the residual block is orthonormalized implicitly (by
+                              whitening in coefficient space) rather than projected and
+                              orthonormalized over n; 0 = 1e-2; > 1 = always explicit */
     uint64_t seed;       /* reserved for generated starting blocks */
     double* history;     /* optional host buffer of history_cap x SE_HISTORY_FIELDS doubles */
     int32_t history_cap; /* rows available in history */

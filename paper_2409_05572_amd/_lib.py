@@ -35,7 +35,8 @@ class SeParams(C.Structure):
         ("j_s", C.c_int32), ("j_p", C.c_int32), ("j_warm", C.c_int32),
         ("max_iter", C.c_int32), ("profile", C.c_int32), ("mu", C.c_double),
         ("r_warm", C.c_double), ("tol", C.c_double), ("sigma", C.c_double),
-        ("time_limit_s", C.c_double), ("r_switch", C.c_double), ("seed", C.c_uint64),
+        ("time_limit_s", C.c_double), ("r_switch", C.c_double), ("implicit_pivot", C.c_double),
+        ("seed", C.c_uint64),
         ("history", C.POINTER(C.c_double)), ("history_cap", C.c_int32),
         ("reserved", C.c_int32),
     ]

@@ -120,12 +120,13 @@ PRECISIONS = {"fp64": _lib.SE_FP64, "fp32": _lib.SE_FP32_MIXED, "bf16": _lib.SE_
 
 def params(n_ev, n_extra, solver="lobpcg", strategy="none", tol=1e-8, n_es=0, max_iter=None,
            soft_lock=True, sigma=0.0, time_limit_s=0.0, precision="fp64", r_switch=0.0,
-           **strategy_params) -> SeParams:
+           implicit_pivot=0.0, **strategy_params) -> SeParams:
     p = SeParams()
     lib().se_params_default(C.byref(p))
     p.solver = _lib.SE_SI if solver == "si" else _lib.SE_LOBPCG
     p.precision = PRECISIONS[precision]
     p.r_switch = float(r_switch)
+    p.implicit_pivot = float(implicit_pivot)
     p.strategy = _lib.STRATEGIES[strategy]
     p.n_ev, p.n_extra, p.n_es = int(n_ev), int(n_extra), int(n_es)
     p.tol = float(tol)

@@ -55,6 +55,7 @@ se_status validate_solve(const se_matrix* A, const se_params* p) {
     if (p->precision != SE_FP64 && p->precision != SE_FP32_MIXED && p->precision != SE_BF16_MIXED)
         return SE_ERR_UNSUPPORTED;
     if (p->precision != SE_FP64 && !(p->r_switch >= 0.0)) return SE_ERR_INVALID_ARG;
+    if (!(p->implicit_pivot >= 0.0)) return SE_ERR_INVALID_ARG;
     if (p->ptr_mode != SE_PTR_HOST && p->ptr_mode != SE_PTR_DEVICE) return SE_ERR_INVALID_ARG;
     const int64_t nb = (int64_t)p->n_ev + p->n_extra;
     if (p->n_ev < 1 || p->n_extra < 0 || nb > A->n) return SE_ERR_INVALID_ARG;

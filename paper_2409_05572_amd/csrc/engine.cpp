@@ -562,7 +562,8 @@ struct Solver {
     // Every kAxpRefresh iterations the whole of A_p is recomputed over n, so
     // rounding in the carried [X, P] block cannot accumulate.
     static constexpr int kAxpRefresh = 10;
-    // Smallest scaled Schur-complement pivot for the implicit orthonormalization of W.
+    // Default smallest scaled Schur-complement pivot for the implicit
+    // orthonormalization of W (se_params.implicit_pivot).
     static constexpr double kImplicitPiv = 1e-2;
     // X0: FP64 column-major start block; k0 >= 0: the X panel already holds
     // k0 start columns (row-major), e.g. from the low-precision phase.
@@ -672,7 +673,8 @@ struct Solver {
                 ST(tic());
                 ST(whiten(m0, q0, 1e-13, r_w, &minpiv));
                 ST(toc(SE_K_SMALL, 16.0 * m0 * m0, 2.0 * m0 * m0 * (double)a));
-                implicit = minpiv >= kImplicitPiv && r_w >= n_ev;
+                const double piv_min = p.implicit_pivot > 0.0 ? p.implicit_pivot : kImplicitPiv;
+                implicit = piv_min <= 1.0 && minpiv >= piv_min && r_w >= n_ev;
                 if (implicit) {
                     ++n_implicit;
                     flags |= 8;

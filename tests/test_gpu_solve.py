@@ -171,6 +171,44 @@ def test_residual_block_orthonormalized_implicitly_except_at_expansions(ctx):
     assert np.abs(V.T @ V - np.eye(32)).max() <= 1e-12
 
 
+def test_explicit_and_implicit_orthonormalization_agree(ctx):
+    """implicit_pivot > 1 forces the explicit projection and Cholesky-QR of W
+    in every iteration (the path taken when the Schur pivots are small); a tiny
+    threshold takes the implicit path in every iteration without an
+    expansion. Both meet the same bars and find the same pairs."""
+    from tests.gpu_util import cluster_angles
+
+    m = 14
+    A = W.laplacian_3d(m)
+    X0 = W.gaussian_block(A.n, 40, 207)
+    exact = pins.laplacian_spectrum(m, 3, 28)
+    runs = {}
+    for piv in (2.0, 1e-12):
+        lam, V, info = _gpu_solve(ctx, A, X0, 28, 12, strategy="fix", implicit_pivot=piv)
+        fl = info.history[:, 7].astype(int)
+        assert info.converged and info.n_expands >= 1
+        if piv > 1:
+            assert not np.any(fl & 8)
+        else:
+            body = fl[:-1]  # the last row is the converged check, before any W is formed
+            assert np.all(((body & 8) != 0) | ((body & 1) != 0))
+        assert np.max(np.abs(lam - exact) / exact) <= 1e-10
+        assert np.max(_residual_ratio(A, lam, V)) <= 1e-8 * 1.0001
+        assert np.abs(V.T @ V - np.eye(28)).max() <= 1e-12
+        runs[piv] = (lam, V)
+    assert cluster_angles(runs[2.0][0], runs[2.0][1], runs[1e-12][1]) <= 1e-6
+
+
+def test_invalid_implicit_pivot_is_rejected(ctx):
+    from paper_2409_05572_amd._lib import SeError
+
+    A = W.laplacian_2d(8)
+    X0 = W.gaussian_block(A.n, 6, 1)
+    for bad in (-1.0, float("nan")):
+        with pytest.raises(SeError):
+            _gpu_solve(ctx, A, X0, 3, 3, implicit_pivot=bad)
+
+
 def test_full_config2_lobpcg_shrink_expand(ctx):
     """3-D 128^3 Laplacian, 64 wanted + 32 extra, fix strategy, at full size:
     every eigenvalue against the closed form; the stopping test recomputed on
