@@ -255,12 +255,13 @@ __global__ __launch_bounds__(kThreads) void spmm_stream_kernel(int n, const int*
     }
 }
 
-// The streaming product followed by the residual of the rows it produced:
-// R = Y - X diag(lam) is written for the wave's rows and the per-column sums
-// of r^2 and x^2 over the workgroup's rows go to part[blockIdx.x * 2w + c]
-// (r^2) and part[blockIdx.x * 2w + w + c] (x^2), summed across the four waves
-// in a fixed order. Y and X rows are re-read right after the product, from
-// cache. Requires w <= 128.
+// The streaming product with the residual of every row it produces: when row
+// r is complete, R[r] = Y[r] - lam X[r] is written and r^2, x^2 are
+// accumulated per column. X[r] is the row's own gather when the row stores
+// its diagonal entry (captured by a wave-uniform compare of the column index),
+// else it is loaded at that point. The per-column sums over the workgroup's
+// rows go to part[blockIdx.x * 2w + c] (r^2) and part[blockIdx.x * 2w + w + c]
+// (x^2), the four waves summed in a fixed order. Requires w <= 128.
 __global__ __launch_bounds__(kThreads) void spmm_resid_kernel(int n, const int* __restrict__ rowptr,
                                                               const int* __restrict__ col,
                                                               const double* __restrict__ val,
@@ -283,17 +284,34 @@ __global__ __launch_bounds__(kThreads) void spmm_resid_kernel(int n, const int* 
         const int pbeg = __builtin_amdgcn_readlane(rp, 0);
         const int pend = __builtin_amdgcn_readlane(rp, r1 - r0);
         const long long cc = has0 ? c0 : 0;
+        const double l0 = has0 ? lam[c0] : 0.0, l1 = has1 ? lam[c0 + 1] : 0.0;
         int r = r0;
         int rend = __builtin_amdgcn_readlane(rp, 1);
-        double a0 = 0.0, a1 = 0.0;
+        double a0 = 0.0, a1 = 0.0, xr0 = 0.0, xr1 = 0.0;
+        bool diag = false;  // uniform: X[r] captured from the row's own gather
         auto flush = [&]() {
+            if (!diag) {
+                const double2 xv = *reinterpret_cast<const double2*>(X + (long long)r * ldx + cc);
+                xr0 = xv.x;
+                xr1 = xv.y;
+            }
+            const double q0 = a0 - l0 * xr0, q1 = a1 - l1 * xr1;
             double* y = Y + (long long)r * ldy + c0;
-            if (has1)
+            double* rr = R + (long long)r * ldr + c0;
+            if (has1) {
                 *reinterpret_cast<double2*>(y) = make_double2(a0, a1);
-            else if (has0)
+                *reinterpret_cast<double2*>(rr) = make_double2(q0, q1);
+            } else if (has0) {
                 *y = a0;
+                *rr = q0;
+            }
+            sr0 = fma(q0, q0, sr0);
+            sr1 = fma(q1, q1, sr1);
+            sx0 = fma(xr0, xr0, sx0);
+            sx1 = fma(xr1, xr1, sx1);
             a0 = 0.0;
             a1 = 0.0;
+            diag = false;
             ++r;
             if (r < r1) rend = __builtin_amdgcn_readlane(rp, r - r0 + 1);
         };
@@ -314,37 +332,15 @@ __global__ __launch_bounds__(kThreads) void spmm_resid_kernel(int n, const int* 
                     while (p + u >= rend) flush();
                     a0 = fma(v[u], x[u].x, a0);
                     a1 = fma(v[u], x[u].y, a1);
+                    if (j[u] == r) {
+                        xr0 = x[u].x;
+                        xr1 = x[u].y;
+                        diag = true;
+                    }
                 }
             }
         }
         while (r < r1) flush();
-        // residual of the rows just produced (the wave's own stores are
-        // visible to its later loads)
-        const double l0 = has0 ? lam[c0] : 0.0, l1 = has1 ? lam[c0 + 1] : 0.0;
-        for (int rr = r0; rr < r1; rr += 8) {
-            double2 yv[8], xv[8];
-#pragma unroll
-            for (int u = 0; u < 8; ++u) {
-                const long long row = min(rr + u, r1 - 1);
-                yv[u] = *reinterpret_cast<const double2*>(Y + row * ldy + cc);
-                xv[u] = *reinterpret_cast<const double2*>(X + row * ldx + cc);
-            }
-#pragma unroll
-            for (int u = 0; u < 8; ++u) {
-                if (rr + u < r1) {
-                    const double q0 = yv[u].x - l0 * xv[u].x, q1 = yv[u].y - l1 * xv[u].y;
-                    double* rp_ = R + (long long)(rr + u) * ldr + c0;
-                    if (has1)
-                        *reinterpret_cast<double2*>(rp_) = make_double2(q0, q1);
-                    else if (has0)
-                        *rp_ = q0;
-                    sr0 = fma(q0, q0, sr0);
-                    sr1 = fma(q1, q1, sr1);
-                    sx0 = fma(xv[u].x, xv[u].x, sx0);
-                    sx1 = fma(xv[u].y, xv[u].y, sx1);
-                }
-            }
-        }
     }
     red[threadIdx.x] = make_double4(sr0, sr1, sx0, sx1);
     __syncthreads();
