@@ -111,7 +111,7 @@ typedef struct se_params {
                               for which the residual block is orthonormalized implicitly (by
                               whitening in coefficient space) rather than projected and
                               orthonormalized over n; 0 = 1e-2; > 1 = always explicit */
-    uint64_t seed;       /* reserved for generated starting blocks */
+    uint64_t seed;       /* start block generated when se_solve gets X0 = NULL */
     double* history;     /* optional host buffer of history_cap x SE_HISTORY_FIELDS doubles */
     int32_t history_cap; /* rows available in history */
     int32_t reserved;
@@ -175,7 +175,11 @@ int64_t se_matrix_n(const se_matrix* m);
 
 /* Solve for the n_ev smallest eigenpairs (Algorithms 1 / 3 with Algorithm 5).
  *   X0     n x nb starting block, column-major, leading dimension n,
- *          nb = n_ev + n_extra; must have full column rank
+ *          nb = n_ev + n_extra; must have full column rank. NULL: the library
+ *          generates it from params->seed: entry (i, j) = 2 u - 1 with
+ *          u = (z >> 11) 2^-53 and z the SplitMix64 output (Steele, Lea and
+ *          Flood 2014) of the state seed + (j n + i + 1) 0x9E3779B97F4A7C15
+ *          mod 2^64 (exact in FP64, so host copies of the block match)
  *   V      output n x n_ev eigenvectors, column-major, leading dimension n
  *   lambda output n_ev eigenvalues, ascending
  * X0, V and lambda are host or device pointers per params->ptr_mode and are
@@ -276,8 +280,9 @@ uint64_t se_solve_footprint(int64_t n, int64_t nnz, int32_t n_ev, int32_t n_extr
 /* 1 <= max_slots <= 16; hbm_budget_bytes > 0. The server uses ctx's device. */
 se_status se_server_create(se_ctx* ctx, uint64_t hbm_budget_bytes, int32_t max_slots, se_server** out);
 
-/* Queue one solve; never blocks on the GPU. Returns SE_ERR_INVALID_ARG like
- * se_solve, SE_ERR_REJECTED when its footprint alone exceeds the budget. */
+/* Queue one solve; never blocks on the GPU. X0 may be NULL (seeded start
+ * block, as in se_solve). Returns SE_ERR_INVALID_ARG like se_solve,
+ * SE_ERR_REJECTED when its footprint alone exceeds the budget. */
 se_status se_submit(se_server* srv, const se_matrix* A, const se_params* params, const double* X0,
                     double* V, double* lambda, se_ticket* ticket);
 

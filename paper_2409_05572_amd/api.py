@@ -142,10 +142,12 @@ def params(n_ev, n_extra, solver="lobpcg", strategy="none", tol=1e-8, n_es=0, ma
 def solve(ctx: Context, A: Matrix, X0, n_ev, n_extra, history_cap=0, **kw):
     """Run se_solve.
 
-    X0 is either a host numpy array (n, nb) in Fortran order, or a torch device
-    tensor of shape (nb, n) (column-major n x nb). Returns (lam, V, info) with V
-    on the same side as X0: numpy (n, n_ev) or a torch (n_ev, n) tensor whose
-    transpose is the eigenvector block.
+    X0 is either a host numpy array (n, nb) in Fortran order, a torch device
+    tensor of shape (nb, n) (column-major n x nb), or None (the library
+    generates the start block from `seed`, see workloads.seeded_uniform_block).
+    Returns (lam, V, info) with V on the same side as X0 (host for None): numpy
+    (n, n_ev) or a torch (n_ev, n) tensor whose transpose is the eigenvector
+    block.
     """
     p = params(n_ev, n_extra, **kw)
     hist = np.zeros((max(history_cap, 0), _lib.SE_HISTORY_FIELDS), dtype=np.float64)
@@ -154,7 +156,11 @@ def solve(ctx: Context, A: Matrix, X0, n_ev, n_extra, history_cap=0, **kw):
         p.history_cap = history_cap
     info = SeInfo()
     n = A.n
-    if isinstance(X0, np.ndarray):
+    if X0 is None:
+        V = np.zeros((n, n_ev), dtype=np.float64, order="F")
+        lam = np.zeros(n_ev, dtype=np.float64)
+        p.ptr_mode = _lib.SE_PTR_HOST
+    elif isinstance(X0, np.ndarray):
         X0 = np.asfortranarray(X0, dtype=np.float64)
         assert X0.shape == (n, n_ev + n_extra)
         V = np.zeros((n, n_ev), dtype=np.float64, order="F")
@@ -167,7 +173,7 @@ def solve(ctx: Context, A: Matrix, X0, n_ev, n_extra, history_cap=0, **kw):
         V = torch.empty((n_ev, n), dtype=torch.float64, device=X0.device)
         lam = torch.empty(n_ev, dtype=torch.float64, device=X0.device)
         p.ptr_mode = _lib.SE_PTR_DEVICE
-    st = lib().se_solve(ctx.handle, A.handle, C.byref(p), C.c_void_p(_ptr(X0)),
+    st = lib().se_solve(ctx.handle, A.handle, C.byref(p), C.c_void_p(None if X0 is None else _ptr(X0)),
                         C.c_void_p(_ptr(V)), C.c_void_p(_ptr(lam)), C.byref(info))
     if st < 0:
         err = _lib.SeError(st, f"se_solve (hip_error {info.hip_error}, {info.iterations} iterations)")

@@ -1027,6 +1027,33 @@ hipError_t launch_spmm_resid(hipStream_t st, int n, const int* rowptr, const int
     return launch_sum_partials(st, 2 * w, (int)grid, part, out);
 }
 
+namespace {
+__global__ __launch_bounds__(kThreads) void seeded_block_kernel(long long n, int nb, unsigned long long seed,
+                                                                double* __restrict__ X, long long ld,
+                                                                int col_major) {
+    const long long total = n * nb;
+    for (long long e = (long long)blockIdx.x * kThreads + threadIdx.x; e < total;
+         e += (long long)gridDim.x * kThreads) {
+        const long long i = e / nb;
+        const int j = (int)(e - i * nb);
+        const unsigned long long k = (unsigned long long)j * (unsigned long long)n + (unsigned long long)i;
+        unsigned long long z = seed + (k + 1ull) * 0x9E3779B97F4A7C15ull;
+        z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+        z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+        z ^= z >> 31;
+        X[col_major ? (long long)j * ld + i : i * ld + j] = (double)(z >> 11) * 0x1p-52 - 1.0;
+    }
+}
+}  // namespace
+
+hipError_t launch_seeded_block(hipStream_t st, long long n, int nb, unsigned long long seed, double* X,
+                               long long ld, bool col_major) {
+    if (n <= 0 || nb <= 0) return hipSuccess;
+    hipLaunchKernelGGL(seeded_block_kernel, dim3(grid_for(n * nb, kThreads, 16384)), dim3(kThreads), 0, st, n,
+                       nb, seed, X, ld, col_major ? 1 : 0);
+    return hipGetLastError();
+}
+
 hipError_t launch_gather_cols(hipStream_t st, long long n, const double* src, long long lds, const int* idx,
                               int a, double* dst, long long ldd) {
     if (a <= 0 || n <= 0) return hipSuccess;

@@ -213,7 +213,7 @@ int64_t se_matrix_n(const se_matrix* m) { return m ? m->n : 0; }
 
 se_status se_solve(se_ctx* ctx, const se_matrix* A, const se_params* p, const double* X0,
                    double* V, double* lambda, se_info* info) {
-    if (!ctx || !A || !p || !X0 || !V || !lambda) return SE_ERR_INVALID_ARG;
+    if (!ctx || !A || !p || !V || !lambda) return SE_ERR_INVALID_ARG;
     if (A->ctx != ctx) return SE_ERR_INVALID_ARG;
     const se_status v = se::validate_solve(A, p);
     if (v != SE_OK) return v;

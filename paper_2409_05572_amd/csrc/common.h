@@ -102,6 +102,12 @@ hipError_t launch_spmm_resid(hipStream_t st, int n, const int* rowptr, const int
                              const double* X, long long ldx, double* Y, long long ldy, int w, const int* heavy,
                              int n_heavy, const double* lam, double* R, long long ldr, double* part, double* out);
 
+// n x nb start block, entry (i, j) = 2 u - 1, u = (z >> 11) 2^-53, z =
+// SplitMix64 of the state seed + (j n + i + 1) 0x9E3779B97F4A7C15, stored at
+// X[i * ld + j] (row-major) or X[j * ld + i] (col_major).
+hipError_t launch_seeded_block(hipStream_t st, long long n, int nb, unsigned long long seed, double* X,
+                               long long ld, bool col_major);
+
 // dst[:, q] = src[:, idx[q]] for q < a (dst must not overlap src).
 hipError_t launch_gather_cols(hipStream_t st, long long n, const double* src, long long lds, const int* idx,
                               int a, double* dst, long long ldd);

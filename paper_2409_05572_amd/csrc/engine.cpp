@@ -489,6 +489,10 @@ struct Solver {
     }
 
     se_status load_x0(const double* X0) {
+        if (!X0) {
+            HC(launch_seeded_block(st, n, nb, (unsigned long long)p.seed, X, ld, false));
+            return SE_OK;
+        }
         if (p.ptr_mode == SE_PTR_HOST) {
             // T1 holds n * ld >= n * nb doubles
             HC(hipMemcpyAsync(T1, X0, sizeof(double) * (size_t)n * nb, hipMemcpyHostToDevice, st));
@@ -1148,7 +1152,10 @@ struct Solver {
         const double u = unit_roundoff<T>();
         const double drop2 = kLpDrop2;
         const double rsw = r_switch_value(u);
-        if (p.ptr_mode == SE_PTR_HOST) {
+        if (!X0) {
+            HC(launch_seeded_block(st, n, nb, (unsigned long long)p.seed, T1, n, true));
+            HC(launch_colmajor_to_rows_lp<T>(st, n, nb, T1, n, Xl, ld));
+        } else if (p.ptr_mode == SE_PTR_HOST) {
             HC(hipMemcpyAsync(T1, X0, sizeof(double) * (size_t)n * nb, hipMemcpyHostToDevice, st));
             HC(launch_colmajor_to_rows_lp<T>(st, n, nb, T1, n, Xl, ld));
         } else {
@@ -1296,7 +1303,10 @@ struct Solver {
         const double drop2 = kLpDrop2;
         const double rsw = r_switch_value(u);
         const double sigma = (p.sigma > 0.0) ? p.sigma : A->anorm;
-        if (p.ptr_mode == SE_PTR_HOST) {
+        if (!X0) {
+            HC(launch_seeded_block(st, n, nb, (unsigned long long)p.seed, T1, n, true));
+            HC(launch_colmajor_to_rows_lp<T>(st, n, nb, T1, n, Xl, ld));
+        } else if (p.ptr_mode == SE_PTR_HOST) {
             HC(hipMemcpyAsync(T1, X0, sizeof(double) * (size_t)n * nb, hipMemcpyHostToDevice, st));
             HC(launch_colmajor_to_rows_lp<T>(st, n, nb, T1, n, Xl, ld));
         } else {

@@ -199,6 +199,22 @@ def test_explicit_and_implicit_orthonormalization_agree(ctx):
     assert cluster_angles(runs[2.0][0], runs[2.0][1], runs[1e-12][1]) <= 1e-6
 
 
+@pytest.mark.parametrize("solver,precision", [("lobpcg", "fp64"), ("si", "fp64"), ("lobpcg", "fp32")])
+def test_seeded_start_block_matches_the_host_generator(ctx, solver, precision):
+    """X0 = NULL: the library's start block is the SplitMix64 block of
+    workloads.seeded_uniform_block (exact in FP64), so the solve is bitwise the
+    one started from the host copy of that block."""
+    A = W.laplacian_2d(24)
+    seed = 12345
+    lam_n, V_n, info_n = _gpu_solve(ctx, A, None, 6, 6, solver=solver, precision=precision, seed=seed,
+                                    strategy="fix")
+    X0 = W.seeded_uniform_block(A.n, 12, seed)
+    lam_h, V_h, info_h = _gpu_solve(ctx, A, X0, 6, 6, solver=solver, precision=precision, strategy="fix")
+    assert info_n.converged and info_n.iterations == info_h.iterations
+    assert np.array_equal(lam_n, lam_h) and np.array_equal(V_n, V_h)
+    assert np.max(np.abs(lam_n - pins.laplacian_spectrum(24, 2, 6)) / lam_n) <= 1e-10
+
+
 def test_invalid_implicit_pivot_is_rejected(ctx):
     from paper_2409_05572_amd._lib import SeError
 

@@ -77,3 +77,19 @@ def test_chung_lu_is_connected_normalized_laplacian():
     v = np.sqrt(deg) / np.linalg.norm(np.sqrt(deg))
     assert abs(abs(v @ V[:, 0]) - 1) < 1e-8
     assert 10 < deg.mean() < 22
+
+
+def test_splitmix64_published_outputs():
+    """First outputs of SplitMix64 seeded with 0 (Steele, Lea and Flood 2014)."""
+    z = W.splitmix64(np.array([0, 1], dtype=np.uint64), 0)
+    assert [int(v) for v in z] == [0xE220A8397B1DCDAF, 0x6E789E6AA1B965F4]
+
+
+def test_seeded_uniform_block_layout_and_range():
+    B = W.seeded_uniform_block(5, 3, 7)
+    assert B.shape == (5, 3) and B.flags.f_contiguous
+    assert np.all((B >= -1.0) & (B < 1.0))
+    # entry (i, j) uses counter j n + i
+    z = W.splitmix64(np.array([1 * 5 + 2], dtype=np.uint64), 7)
+    assert B[2, 1] == float(int(z[0]) >> 11) * 2.0 ** -52 - 1.0
+    assert np.linalg.matrix_rank(W.seeded_uniform_block(200, 12, 1)) == 12

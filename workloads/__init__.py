@@ -189,6 +189,25 @@ def gaussian_block(n: int, nb: int, seed: int) -> np.ndarray:
     return np.asfortranarray(rng.standard_normal((nb, n)).T)
 
 
+def splitmix64(counter: np.ndarray, seed: int) -> np.ndarray:
+    """SplitMix64 output for the Weyl-sequence states seed + (counter + 1) * 0x9E3779B97F4A7C15
+    (mod 2^64): the published mixer of Steele, Lea and Flood (2014)."""
+    with np.errstate(over="ignore"):
+        z = np.uint64(seed) + (counter.astype(np.uint64) + np.uint64(1)) * np.uint64(0x9E3779B97F4A7C15)
+        z = (z ^ (z >> np.uint64(30))) * np.uint64(0xBF58476D1CE4E5B9)
+        z = (z ^ (z >> np.uint64(27))) * np.uint64(0x94D049BB133111EB)
+        return z ^ (z >> np.uint64(31))
+
+
+def seeded_uniform_block(n: int, nb: int, seed: int) -> np.ndarray:
+    """The start block the library generates when se_solve gets X0 = NULL: entry
+    (i, j) is 2 u - 1 with u = (splitmix64(j n + i) >> 11) 2^-53, exact in FP64,
+    n x nb column-major."""
+    k = (np.arange(nb, dtype=np.uint64)[None, :] * np.uint64(n) + np.arange(n, dtype=np.uint64)[:, None])
+    z = splitmix64(k, seed)
+    return np.asfortranarray((z >> np.uint64(11)).astype(np.float64) * 2.0 ** -52 - 1.0)
+
+
 def random_sparse_spd(n: int, density: float, seed: int) -> CSRMatrix:
     """Small random sparse symmetric positive definite matrix (diagonally dominant)."""
     rng = np.random.default_rng(seed)
