@@ -162,7 +162,8 @@ void se_ctx_destroy(se_ctx* ctx);
  *   colind nnz int32 column indices in [0, n)
  *   val    nnz finite doubles
  *   anorm  ||A||_2 or an upper bound of it (used by the stopping test and as
- *          the default SI shift); must be > 0
+ *          the default SI shift); 0 = the library takes the Gershgorin bound
+ *          max_i sum_j |a_ij| (>= ||A||_2 for symmetric A); must be >= 0
  * The library copies the arrays (host or device per `flags`); the caller's
  * buffers may be freed after the call. Offsets, index range and finiteness are
  * validated on the host in both modes (device arrays are copied back for it).
@@ -172,6 +173,8 @@ se_status se_matrix_create_csr(se_ctx* ctx, int64_t n, int64_t nnz, const int64_
                                double anorm, se_matrix** out);
 void se_matrix_destroy(se_matrix* m);
 int64_t se_matrix_n(const se_matrix* m);
+/* The ||A||_2 bound the matrix uses (given or estimated). */
+double se_matrix_anorm(const se_matrix* m);
 
 /* Solve for the n_ev smallest eigenpairs (Algorithms 1 / 3 with Algorithm 5).
  *   X0     n x nb starting block, column-major, leading dimension n,

@@ -67,6 +67,7 @@ PROTOTYPES = {
                                         C.POINTER(C.c_void_p)]),
     "se_matrix_destroy": (None, [C.c_void_p]),
     "se_matrix_n": (C.c_int64, [C.c_void_p]),
+    "se_matrix_anorm": (C.c_double, [C.c_void_p]),
     "se_solve": (C.c_int, [C.c_void_p, C.c_void_p, C.POINTER(SeParams), C.c_void_p, C.c_void_p,
                            C.c_void_p, C.POINTER(SeInfo)]),
     "se_op_spmm": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p,

@@ -72,7 +72,7 @@ class Matrix:
                                          float(anorm), C.byref(h)), "se_matrix_create_csr")
         self._h = h
         self._keep = None
-        self.anorm = float(anorm)
+        self.anorm = float(lib().se_matrix_anorm(h))  # the given bound, or the Gershgorin estimate for 0
 
     @classmethod
     def from_csr(cls, ctx: Context, csr) -> "Matrix":

@@ -132,7 +132,7 @@ se_status se_matrix_create_csr(se_ctx* ctx, int64_t n, int64_t nnz, const int64_
     if (!ctx || !out || !rowptr || (!colind && nnz > 0) || (!val && nnz > 0)) return SE_ERR_INVALID_ARG;
     *out = nullptr;
     if (n < 1 || nnz < 0 || n > INT32_MAX - 1 || nnz > INT32_MAX) return SE_ERR_INVALID_ARG;
-    if (!(anorm > 0.0) || !std::isfinite(anorm)) return SE_ERR_INVALID_ARG;
+    if (!(anorm >= 0.0) || !std::isfinite(anorm)) return SE_ERR_INVALID_ARG;
     CAPI_HC(ctx, hipSetDevice(ctx->device));
     const bool on_device = (flags & SE_MATRIX_DEVICE) != 0;
     std::vector<int64_t> rp64(n + 1);
@@ -162,6 +162,14 @@ se_status se_matrix_create_csr(se_ctx* ctx, int64_t n, int64_t nnz, const int64_
         for (int64_t e = 0; e < nnz; ++e) {
             if (cp[e] < 0 || cp[e] >= n) return SE_ERR_INVALID_ARG;
             if (!std::isfinite(vp[e])) return SE_ERR_INVALID_ARG;
+        }
+        if (anorm == 0.0) {  // Gershgorin: max absolute row sum bounds ||A||_2 for symmetric A
+            for (int64_t i = 0; i < n; ++i) {
+                double s = 0.0;
+                for (int64_t e = rp64[i]; e < rp64[i + 1]; ++e) s += std::fabs(vp[e]);
+                anorm = std::max(anorm, s);
+            }
+            if (!(anorm > 0.0)) return SE_ERR_INVALID_ARG;  // the zero matrix has no scale
         }
     }
     std::vector<int> rp32(n + 1);
@@ -210,6 +218,8 @@ void se_matrix_destroy(se_matrix* m) {
 }
 
 int64_t se_matrix_n(const se_matrix* m) { return m ? m->n : 0; }
+
+double se_matrix_anorm(const se_matrix* m) { return m ? m->anorm : 0.0; }
 
 se_status se_solve(se_ctx* ctx, const se_matrix* A, const se_params* p, const double* X0,
                    double* V, double* lambda, se_info* info) {

@@ -215,6 +215,24 @@ def test_seeded_start_block_matches_the_host_generator(ctx, solver, precision):
     assert np.max(np.abs(lam_n - pins.laplacian_spectrum(24, 2, 6)) / lam_n) <= 1e-10
 
 
+def test_zero_anorm_takes_the_gershgorin_bound(ctx):
+    """anorm = 0 at matrix creation: the library uses max_i sum_j |a_ij|, the
+    bound the Anderson workload passes explicitly, and the solve is the same."""
+    from paper_2409_05572_amd import api
+
+    A = W.anderson_3d(10, 4.0, 9)
+    S = A.to_scipy()
+    gersh = float(abs(S).sum(axis=1).max())
+    M0 = api.Matrix(ctx, A.n, A.rowptr, A.colind, A.val, 0.0)
+    assert abs(M0.anorm - gersh) <= 1e-14 * gersh
+    X0 = W.gaussian_block(A.n, 16, 5)
+    r0 = api.solve(ctx, M0, X0, 10, 6, strategy="fix")
+    r1 = api.solve(ctx, api.Matrix(ctx, A.n, A.rowptr, A.colind, A.val, M0.anorm), X0, 10, 6, strategy="fix")
+    assert r0[2].converged and np.array_equal(r0[0], r1[0]) and np.array_equal(r0[1], r1[1])
+    with pytest.raises(Exception):
+        api.Matrix(ctx, A.n, A.rowptr, A.colind, A.val, -1.0)
+
+
 def test_invalid_implicit_pivot_is_rejected(ctx):
     from paper_2409_05572_amd._lib import SeError
 
