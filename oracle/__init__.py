@@ -36,6 +36,7 @@ from .solvers import (  # noqa: F401
     hl_basis,
     si_step,
     lobpcg,
+    steepest_descent,
     subspace_iteration,
 )
 from . import mixed  # noqa: F401,E402

@@ -2,6 +2,7 @@
 
 Follows the paper (arXiv 2409.05572):
 * subspace iteration, Algorithm 1 (Section 2.1);
+* steepest descent, Algorithm 2 (Section 2.2);
 * LOBPCG, Algorithm 3 (Section 2.3), with soft locking and the improved
   Hetmaniuk-Lehoucq choice of P (Section 2.3 text), preconditioner T = I as in
   the experiments (Section 6.2);
@@ -251,6 +252,102 @@ def lobpcg(
             Pdrop = P[:, n_es:]
             X = X[:, :n_es]
             P = P[:, :n_es]
+            lam = lam[:n_es]
+            ctl.did_shrink(j)
+            n_shr += 1
+            rec["shrink"] = True
+
+    ms = float(np.max(stop[:n_ev])) if stop is not None else np.inf
+    mp = float(np.max(paper[:n_ev])) if paper is not None else np.inf
+    return SolveResult(lam[:n_ev].copy(), X[:, :n_ev].copy(), len(history), False, history,
+                       n_shr, n_exp, ms, mp)
+
+
+def steepest_descent(
+    A,
+    X0,
+    n_ev,
+    anorm,
+    tol=1e-8,
+    n_es=None,
+    se: SEParams | None = None,
+    max_iter=1000,
+    soft_lock=True,
+    drop_tol=1e-12,
+    time_limit_s=None,
+):
+    """Block steepest descent with shrink-and-expand (Algorithm 2, Section 2.2),
+    T = I: X_new is the Ritz basis of span{X, R} for the current width.
+
+    Readings: soft locking as in LOBPCG (locked pairs leave W); at an
+    expansion X_drop is orthogonalized against X and orthonormalized before it
+    is appended (the algorithm appends it as is, but the Rayleigh-Ritz step
+    needs an orthonormal basis).
+    """
+    se = se or SEParams()
+    nb = X0.shape[1]
+    ctl = SEController(se if _se_enabled(se, n_ev, n_es, nb) else SEParams("none"))
+    t0 = time.perf_counter()
+
+    # X <- orth(X0); A_p = X^T A X = Z Lambda Z^T; X <- X Z
+    X, _ = orth(np.asarray(X0, dtype=np.float64), drop_tol)
+    lam, Z = rayleigh_ritz(X, _apply(A, X))
+    X = X @ Z
+    Xdrop = None
+    history = []
+    n_shr = n_exp = 0
+    stop = paper = None
+
+    for j in range(1, max_iter + 1):
+        # R <- A X - X Lambda; convergence of the n_ev smallest pairs
+        R, stop, paper = residual_measures(A, X, lam, anorm)
+        r_j = float(np.max(paper[:n_ev]))
+        ctl.observe(j, r_j)
+        conv = stop[:n_ev] <= tol
+        rec = dict(j=j, r=r_j, max_stop=float(np.max(stop[:n_ev])), k=X.shape[1], p=0,
+                   locked=0, a=0, expand=False, shrink=False)
+        history.append(rec)
+        if np.all(conv):
+            return SolveResult(lam[:n_ev].copy(), X[:, :n_ev].copy(), j, True, history,
+                               n_shr, n_exp, float(np.max(stop[:n_ev])), r_j)
+        if time_limit_s is not None and time.perf_counter() - t0 > time_limit_s:
+            break
+        k = X.shape[1]
+        locked = np.zeros(k, dtype=bool)
+        if soft_lock:
+            locked[:n_ev] = conv
+        active = np.flatnonzero(~locked)
+
+        # if ifexpand(): X <- [X, X_drop]
+        if ctl.ifexpand(j) and Xdrop is not None:
+            Xd = Xdrop
+            for _ in range(2):
+                Xd = Xd - X @ (X.T @ Xd)
+            Xd, _ = orth(Xd, drop_tol)
+            X = np.hstack([X, Xd])
+            Xdrop = None
+            ctl.did_expand(j)
+            n_exp += 1
+            rec["expand"] = True
+
+        # W <- T R (active columns); W <- W - X (X^T W), orthonormalized
+        W = R[:, active]
+        for _ in range(2):
+            W = W - X @ (X.T @ W)
+        W, _ = orth(W, drop_tol)
+
+        # S = [X, W]; A_p = S^T A S = Z Lambda Z^T; X <- S Z(:, 1:n_now)
+        S = np.hstack([X, W])
+        k = X.shape[1]
+        theta, Z = rayleigh_ritz(S, _apply(A, S))
+        X = S @ Z[:, :k]
+        lam = theta[:k].copy()
+        rec.update(locked=int(np.count_nonzero(locked)), a=W.shape[1], theta=lam[:n_ev].copy())
+
+        # if ifshrink(): X_drop <- X(:, n_es+1:end), X <- X(:, 1:n_es)
+        if ctl.ifshrink(j):
+            Xdrop = X[:, n_es:]
+            X = X[:, :n_es]
             lam = lam[:n_es]
             ctl.did_shrink(j)
             n_shr += 1

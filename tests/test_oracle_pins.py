@@ -113,6 +113,36 @@ def test_si_shrink_expand_matches_closed_form(strategy):
     assert _check(res, A, pins.laplacian_spectrum(m, 2, n_ev), lam_rtol=1e-9) == []
 
 
+@pytest.mark.parametrize("strategy", ["none", "fix", "slope", "slopek"])
+def test_steepest_descent_matches_closed_form(strategy):
+    m, n_ev, nb = 16, 6, 12
+    A = W.laplacian_2d(m)
+    X0 = W.gaussian_block(A.n, nb, 7)
+    res = O.steepest_descent(A.to_scipy(), X0, n_ev, A.anorm, tol=1e-8, n_es=n_ev + 2,
+                             se=O.SEParams(strategy), max_iter=3000)
+    assert res.converged
+    assert _check(res, A, pins.laplacian_spectrum(m, 2, n_ev), lam_rtol=1e-9) == []
+    if strategy != "none":
+        assert res.n_shrinks >= 1
+
+
+def test_steepest_descent_ritz_values_bound_from_above_and_decrease():
+    """span{X, R} contains X, so the Ritz values never increase (a shrink keeps
+    the first n_es), and they bound the eigenvalues from above (Courant-Fischer)."""
+    m, n_ev = 8, 6
+    A = W.laplacian_3d(m)
+    exact = pins.laplacian_spectrum(m, 3, n_ev)
+    X0 = W.gaussian_block(A.n, 12, 13)
+    res = O.steepest_descent(A.to_scipy(), X0, n_ev, A.anorm, tol=1e-9, n_es=n_ev + 2,
+                             se=O.SEParams("fix", r_warm=1e-2), max_iter=3000)
+    assert res.converged and res.n_shrinks >= 1
+    thetas = [h["theta"] for h in res.history if "theta" in h]
+    for t in thetas:
+        assert np.all(t >= exact * (1 - 1e-13) - 1e-15)
+    for a, b in zip(thetas, thetas[1:]):
+        assert np.all(b <= a + 1e-13 * np.abs(a))
+
+
 # --- Invariants -----------------------------------------------------------------
 
 def test_lobpcg_ritz_values_bound_from_above_and_decrease():
