@@ -45,7 +45,7 @@ def parse():
     ap.add_argument("--nodes", type=int, default=None, help="Chung-Lu graph size")
     ap.add_argument("--n-ev", type=int, default=None)
     ap.add_argument("--n-extra", type=int, default=None)
-    ap.add_argument("--solver", default="lobpcg", choices=["lobpcg", "si"])
+    ap.add_argument("--solver", default="lobpcg", choices=["lobpcg", "si", "sd"])
     ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32", "bf16"])
     ap.add_argument("--max-iter", type=int, default=None)
     ap.add_argument("--strategy", default="fix")
@@ -286,7 +286,7 @@ def cpu_baseline(A, X0, args, gpu_iters, log):
     except Exception:
         cores = os.cpu_count()
     t = time.perf_counter()
-    solver = O.subspace_iteration if args.solver == "si" else O.lobpcg
+    solver = {"si": O.subspace_iteration, "sd": O.steepest_descent}.get(args.solver, O.lobpcg)
     res = solver(A.to_scipy(), X0, args.n_ev, A.anorm, tol=1e-8,
                  n_es=args.n_ev + min(5, args.n_extra - 1), se=O.SEParams(args.strategy),
                  time_limit_s=args.cpu_seconds)

@@ -47,6 +47,8 @@ typedef struct se_matrix se_matrix;
 /* Solvers. */
 #define SE_LOBPCG 0 /* Algorithm 3 with soft locking and the Hetmaniuk-Lehoucq basis */
 #define SE_SI 1     /* Algorithm 1 with the shifted power step X <- sigma X - A X */
+#define SE_SD 2     /* Algorithm 2 (block steepest descent): S = [X, W], no P; soft locking
+                       and expansion as in LOBPCG (X_drop orthonormalized against S) */
 
 /* Shrink-and-expand strategies (Section 3.2). */
 #define SE_STRAT_NONE 0
@@ -86,7 +88,7 @@ typedef struct se_matrix se_matrix;
 #define SE_K_CLASSES 8
 
 typedef struct se_params {
-    int32_t solver;      /* SE_LOBPCG or SE_SI */
+    int32_t solver;      /* SE_LOBPCG, SE_SI or SE_SD */
     int32_t strategy;    /* SE_STRAT_* */
     int32_t precision;   /* SE_FP64, SE_FP32_MIXED or SE_BF16_MIXED */
     int32_t ptr_mode;    /* SE_PTR_HOST or SE_PTR_DEVICE for X0, V, lambda */

@@ -16,7 +16,8 @@ SE_ERR_BREAKDOWN = -4
 SE_ERR_REJECTED = -5
 SE_ERR_UNSUPPORTED = -6
 
-SE_LOBPCG, SE_SI = 0, 1
+SE_LOBPCG, SE_SI, SE_SD = 0, 1, 2
+SOLVERS = {"lobpcg": SE_LOBPCG, "si": SE_SI, "sd": SE_SD}
 STRATEGIES = {"none": 0, "fix": 1, "slope": 2, "slopek": 3}
 SE_FP64 = 0
 SE_FP32_MIXED = 1

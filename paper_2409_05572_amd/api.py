@@ -123,7 +123,7 @@ def params(n_ev, n_extra, solver="lobpcg", strategy="none", tol=1e-8, n_es=0, ma
            implicit_pivot=0.0, **strategy_params) -> SeParams:
     p = SeParams()
     lib().se_params_default(C.byref(p))
-    p.solver = _lib.SE_SI if solver == "si" else _lib.SE_LOBPCG
+    p.solver = _lib.SOLVERS[solver]
     p.precision = PRECISIONS[precision]
     p.r_switch = float(r_switch)
     p.implicit_pivot = float(implicit_pivot)
@@ -191,7 +191,7 @@ def solve(ctx: Context, A: Matrix, X0, n_ev, n_extra, history_cap=0, **kw):
 def footprint(n, nnz, n_ev, n_extra, precision="fp64", solver="lobpcg") -> int:
     """Device bytes a solve of this shape allocates (the serving admission size)."""
     return int(lib().se_solve_footprint(int(n), int(nnz), int(n_ev), int(n_extra), PRECISIONS[precision],
-                                        _lib.SE_SI if solver == "si" else _lib.SE_LOBPCG))
+                                        _lib.SOLVERS[solver]))
 
 
 def _info_of(st, info, hist):

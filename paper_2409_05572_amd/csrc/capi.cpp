@@ -50,7 +50,7 @@ hipError_t update_lp_call(se_ctx* ctx, int64_t n, const void* U, int64_t ldu, in
 namespace se {
 // Parameter checks shared by se_solve and se_submit.
 se_status validate_solve(const se_matrix* A, const se_params* p) {
-    if (p->solver != SE_LOBPCG && p->solver != SE_SI) return SE_ERR_INVALID_ARG;
+    if (p->solver != SE_LOBPCG && p->solver != SE_SI && p->solver != SE_SD) return SE_ERR_INVALID_ARG;
     if (p->strategy < SE_STRAT_NONE || p->strategy > SE_STRAT_SLOPEK) return SE_ERR_INVALID_ARG;
     if (p->precision != SE_FP64 && p->precision != SE_FP32_MIXED && p->precision != SE_BF16_MIXED)
         return SE_ERR_UNSUPPORTED;
@@ -59,7 +59,7 @@ se_status validate_solve(const se_matrix* A, const se_params* p) {
     if (p->ptr_mode != SE_PTR_HOST && p->ptr_mode != SE_PTR_DEVICE) return SE_ERR_INVALID_ARG;
     const int64_t nb = (int64_t)p->n_ev + p->n_extra;
     if (p->n_ev < 1 || p->n_extra < 0 || nb > A->n) return SE_ERR_INVALID_ARG;
-    if (p->solver == SE_LOBPCG && nb > 341) return SE_ERR_UNSUPPORTED;  // 3 nb <= 1024
+    if (p->solver != SE_SI && nb > 341) return SE_ERR_UNSUPPORTED;  // 3 nb <= 1024
     if (p->solver == SE_SI && nb > 1024) return SE_ERR_UNSUPPORTED;
     if (p->n_es != 0 && (p->n_es < p->n_ev || p->n_es > nb)) return SE_ERR_INVALID_ARG;
     if (!(p->tol > 0.0) || p->max_iter < 1) return SE_ERR_INVALID_ARG;

@@ -85,6 +85,7 @@ struct Solver {
     double *Sd = nullptr, *ASd = nullptr, *T1 = nullptr, *T2 = nullptr;
 
     int iters = 0, n_shr = 0, n_exp = 0, hist_len = 0, n_reproj = 0, n_implicit = 0;
+    bool no_p = false;  // steepest descent: the LOBPCG iteration without P
     int j_off = 0;       // iterations of an earlier (low-precision) phase
     int lp_iters = 0;    // iterations of the low-precision phase
     bool lp_done = false;  // the low-precision phase met the stopping test itself
@@ -713,7 +714,11 @@ struct Solver {
             }
             if (a > 0) ST(spmm(W, AW, a));
 
-            act_hl = act;
+            // steepest descent keeps no P: no HL columns
+            if (no_p)
+                act_hl.clear();
+            else
+                act_hl = act;
             if (expand_now) {
                 // S_drop <- S_drop - S (S^T S_drop), twice; orthonormalize;
                 // then its images A S_drop by one SpMM.
@@ -734,7 +739,8 @@ struct Solver {
                 HC(launch_copy_cols(st, n, ASd, ld, 0, AX, ld, k, dxk));
                 HC(launch_copy_cols(st, n, Sd, ld, dxk, P, ld, pw, dpk));
                 HC(launch_copy_cols(st, n, ASd, ld, dxk, AP, ld, pw, dpk));
-                for (int q = 0; q < dxk; ++q) act_hl.push_back(k + q);
+                if (!no_p)
+                    for (int q = 0; q < dxk; ++q) act_hl.push_back(k + q);
                 k += dxk;
                 pw += dpk;
                 ctl.did_expand(j);
@@ -1222,11 +1228,15 @@ struct Solver {
             // S = [X, P, S_drop (at an expansion), W]: X and P leave the
             // previous step whitened, so they lead (q columns); S_drop joins
             // the block that is factorized, and its X part is kept with X.
-            act_hl = act;
+            if (no_p)
+                act_hl.clear();
+            else
+                act_hl = act;
             const bool expand = want_expand && have_drop;
             const int dd = expand ? dx + dp : 0;
             if (expand) {
-                for (int q = 0; q < dx; ++q) act_hl.push_back(k + pw + q);
+                if (!no_p)
+                    for (int q = 0; q < dx; ++q) act_hl.push_back(k + pw + q);
                 ctl.did_expand(j);
                 have_drop = false;
                 ++n_exp;
@@ -1484,6 +1494,7 @@ se_status solve(se_ctx* ctx, const se_matrix* A, const se_params* prm, const dou
     int n_es = prm->n_es;
     if (n_es <= 0) n_es = prm->n_ev + std::min(5, prm->n_extra - 1);
     s.n_es = n_es;
+    s.no_p = prm->solver == SE_SD;
     s.ctl.kind = prm->strategy;
     s.ctl.j_e = prm->j_e;
     s.ctl.j_s = prm->j_s;

@@ -103,6 +103,36 @@ def test_anderson_small_matches_oracle(ctx):
     assert np.max(_residual_ratio(A, lam, V)) <= 1e-8 * 1.0001
 
 
+@pytest.mark.parametrize("strategy", ["none", "fix", "slopek"])
+def test_steepest_descent_matches_oracle(ctx, strategy):
+    """Algorithm 2 on the GPU (the LOBPCG engine without P) against the
+    oracle's steepest descent and the closed form."""
+    m, n_ev, nb = 16, 6, 12
+    A = W.laplacian_2d(m)
+    X0 = W.gaussian_block(A.n, nb, 7)
+    lam, V, info = _gpu_solve(ctx, A, X0, n_ev, nb - n_ev, solver="sd", strategy=strategy, n_es=n_ev + 2,
+                              max_iter=3000)
+    ref = O.steepest_descent(A.to_scipy(), X0, n_ev, A.anorm, tol=1e-8, n_es=n_ev + 2,
+                             se=O.SEParams(strategy), max_iter=3000)
+    assert info.converged and ref.converged
+    _assert_parity(A, lam, V, ref, pins.laplacian_spectrum(m, 2, n_ev))
+    assert abs(info.iterations - ref.iterations) <= max(5, ref.iterations // 7)
+    assert np.all(info.history[:, 4] == 0)  # no P block
+    if strategy != "none":
+        assert info.n_shrinks >= 1
+
+
+def test_steepest_descent_mixed_precision(ctx):
+    A = W.laplacian_2d(16)
+    X0 = W.gaussian_block(A.n, 12, 7)
+    lam, V, info = _gpu_solve(ctx, A, X0, 6, 6, solver="sd", precision="fp32", strategy="fix",
+                              max_iter=3000)
+    assert info.converged and info.lp_iterations >= 1
+    assert np.max(np.abs(lam - pins.laplacian_spectrum(16, 2, 6)) / lam) <= 1e-10
+    assert np.max(_residual_ratio(A, lam, V)) <= 1e-8 * 1.0001
+    assert np.abs(V.T @ V - np.eye(6)).max() <= 1e-12
+
+
 def test_device_pointers_give_identical_result(ctx):
     import torch
 
