@@ -39,7 +39,7 @@ typedef int se_status;
 #define SE_ERR_HIP (-3)         /* a HIP runtime call failed (see se_info.hip_error) */
 #define SE_ERR_BREAKDOWN (-4)   /* orthogonalization lost every column */
 #define SE_ERR_REJECTED (-5)    /* request larger than the configured memory budget */
-#define SE_ERR_UNSUPPORTED (-6) /* option not available in this build */
+#define SE_ERR_UNSUPPORTED (-6) /* option or size not supported */
 
 typedef struct se_ctx se_ctx;
 typedef struct se_matrix se_matrix;
