@@ -32,6 +32,15 @@ Readings of points the paper leaves open (each also listed in the design notes):
   orthonormalized; columns that come from X_drop go to X, the rest to P.
 * Orthogonalization drops columns whose norm after projection falls below
   ``drop_tol`` times their norm before it.
+* Expansion vectors (Section 6, the vectors appended in the expansion):
+  ``expand_vectors="xdrop"`` appends the vectors dropped at the last shrink;
+  ``"random"`` appends a normally distributed block of the same width,
+  ``random_block(e, d)`` for the e-th expansion (LOBPCG: its first columns
+  take the place of X_drop, the rest that of P_drop); ``"powered"`` (subspace
+  iteration only) applies the iteration operator to X_drop at every iteration
+  it is held, without orthogonalization, divided by ``sigma - theta_1``
+  (theta_1 the current smallest Ritz value) so that its largest component
+  stays of order one however long it waits.
 """
 from __future__ import annotations
 
@@ -147,6 +156,16 @@ def hl_basis(Z, k, active, drop_tol=1e-12):
     return Z1, Z2 @ QB
 
 
+def _expansion_source(expand_vectors, random_block, powered_ok):
+    if expand_vectors not in ("xdrop", "random", "powered"):
+        raise ValueError(f"unknown expand_vectors {expand_vectors!r}")
+    if expand_vectors == "powered" and not powered_ok:
+        raise ValueError("powered X_drop is defined for subspace iteration only")
+    if expand_vectors == "random" and random_block is None:
+        raise ValueError("random expansion vectors need random_block(e, d)")
+    return expand_vectors
+
+
 def _se_enabled(params: SEParams, n_ev: int, n_es, nb: int) -> bool:
     return params.strategy != "none" and n_es is not None and n_ev <= n_es < nb
 
@@ -164,12 +183,15 @@ def lobpcg(
     drop_tol=1e-12,
     time_limit_s=None,
     P0=None,
+    expand_vectors="xdrop",
+    random_block=None,
 ):
     """LOBPCG with soft locking, HL basis and shrink-and-expand (Algorithm 3).
 
     ``P0``: search directions to continue with (e.g. after a low-precision
     phase); they are orthogonalized against the starting X.
     """
+    _expansion_source(expand_vectors, random_block, False)
     se = se or SEParams()
     nb = X0.shape[1]
     ctl = SEController(se if _se_enabled(se, n_ev, n_es, nb) else SEParams("none"))
@@ -222,8 +244,11 @@ def lobpcg(
 
         if expand and Xdrop is not None:
             S = np.hstack([X, P, W])
-            Sd = np.hstack([Xdrop, Pdrop])
             d = Xdrop.shape[1]
+            if expand_vectors == "random":
+                Sd = random_block(n_exp + 1, d + Pdrop.shape[1])
+            else:
+                Sd = np.hstack([Xdrop, Pdrop])
             for _ in range(2):
                 Sd = Sd - S @ (S.T @ Sd)
             Sd, kept = orth(Sd, drop_tol)
@@ -275,6 +300,8 @@ def steepest_descent(
     soft_lock=True,
     drop_tol=1e-12,
     time_limit_s=None,
+    expand_vectors="xdrop",
+    random_block=None,
 ):
     """Block steepest descent with shrink-and-expand (Algorithm 2, Section 2.2),
     T = I: X_new is the Ritz basis of span{X, R} for the current width.
@@ -284,6 +311,7 @@ def steepest_descent(
     is appended (the algorithm appends it as is, but the Rayleigh-Ritz step
     needs an orthonormal basis).
     """
+    _expansion_source(expand_vectors, random_block, False)
     se = se or SEParams()
     nb = X0.shape[1]
     ctl = SEController(se if _se_enabled(se, n_ev, n_es, nb) else SEParams("none"))
@@ -320,7 +348,7 @@ def steepest_descent(
 
         # if ifexpand(): X <- [X, X_drop]
         if ctl.ifexpand(j) and Xdrop is not None:
-            Xd = Xdrop
+            Xd = random_block(n_exp + 1, Xdrop.shape[1]) if expand_vectors == "random" else Xdrop
             for _ in range(2):
                 Xd = Xd - X @ (X.T @ Xd)
             Xd, _ = orth(Xd, drop_tol)
@@ -372,17 +400,23 @@ def subspace_iteration(
     apply_op=None,
     drop_tol=1e-12,
     time_limit_s=None,
+    expand_vectors="xdrop",
+    random_block=None,
 ):
     """Subspace iteration with Rayleigh-Ritz and shrink-and-expand (Algorithm 1).
 
     ``apply_op`` defaults to the shifted power step X -> sigma X - A X with
-    ``sigma = anorm`` when not given.
+    ``sigma = anorm`` when not given. With a custom ``apply_op`` the powered
+    X_drop is not rescaled.
     """
+    _expansion_source(expand_vectors, random_block, True)
     se = se or SEParams()
     nb = X0.shape[1]
     ctl = SEController(se if _se_enabled(se, n_ev, n_es, nb) else SEParams("none"))
+    shift = None
     if apply_op is None:
         s = anorm if sigma is None else sigma
+        shift = s
         apply_op = lambda Y: s * Y - _apply(A, Y)  # noqa: E731
     t0 = time.perf_counter()
 
@@ -409,7 +443,15 @@ def subspace_iteration(
             break
 
         Y = apply_op(X)
+        if expand_vectors == "powered" and Xdrop is not None:
+            # one power step on the held X_drop, no orthogonalization
+            scale = 1.0
+            if shift is not None and shift - lam[0] > 0.0:
+                scale = 1.0 / (shift - lam[0])
+            Xdrop = apply_op(Xdrop) * scale
         if ctl.ifexpand(j) and Xdrop is not None:
+            if expand_vectors == "random":
+                Xdrop = random_block(n_exp + 1, Xdrop.shape[1])
             Y = np.hstack([Y, Xdrop])
             Xdrop = None
             ctl.did_expand(j)

@@ -251,3 +251,94 @@ def test_shrink_expand_does_not_change_the_answer():
         r = O.lobpcg(A.to_scipy(), X0, 16, A.anorm, tol=1e-9, n_es=19, se=O.SEParams(s))
         assert r.converged
         assert np.max(np.abs(r.lam - base.lam) / base.lam) < 1e-10
+
+
+# --- Vectors appended at an expansion (Section 6) --------------------------------------
+
+def _expand_case(m=40, n_ev=10, n_extra=10, seed=1):
+    A = W.laplacian_2d(m)
+    nb = n_ev + n_extra
+    X0 = W.gaussian_block(A.n, nb, seed)
+    draw = lambda e, d: W.seeded_expansion_block(A.n, d, nb, e, seed + 100)  # noqa: E731
+    return A, X0, nb, n_ev + min(5, n_extra - 1), draw
+
+
+@pytest.mark.parametrize("solver", ["si", "lobpcg", "sd"])
+@pytest.mark.parametrize("kind", ["random", "powered"])
+def test_expansion_vectors_reach_the_closed_form_spectrum(solver, kind):
+    if kind == "powered" and solver != "si":
+        pytest.skip("powered X_drop is defined for subspace iteration")
+    m, n_ev = 20, 6
+    A, X0, nb, n_es, draw = _expand_case(m, n_ev, 6, 5)
+    f = {"si": O.subspace_iteration, "lobpcg": O.lobpcg, "sd": O.steepest_descent}[solver]
+    res = f(A.to_scipy(), X0, n_ev, A.anorm, tol=1e-8, n_es=n_es, se=O.SEParams("fix"),
+            max_iter=20000, expand_vectors=kind, random_block=draw)
+    assert res.converged and res.n_expands >= 1
+    assert _check(res, A, pins.laplacian_spectrum(m, 2, n_ev), lam_rtol=1e-9) == []
+
+
+@pytest.mark.parametrize("seed", [1, 2, 3])
+def test_expansion_vector_choice_orders_as_the_paper_reports(seed):
+    """Section 6 (the vectors appended in the expansion, and its figure of SI
+    and LOBPCG under fix): reusing X_drop converges in fewer iterations than
+    appending random vectors, and powering X_drop (SI) in fewer still. Checked
+    on the 40 x 40 Dirichlet Laplacian, n_ev = 10, block 20, n_es = 15."""
+    A, X0, nb, n_es, draw = _expand_case(seed=seed)
+    it = {}
+    for kind in ("xdrop", "random", "powered"):
+        r = O.subspace_iteration(A.to_scipy(), X0, 10, A.anorm, tol=1e-8, n_es=n_es,
+                                 se=O.SEParams("fix"), expand_vectors=kind, random_block=draw)
+        assert r.converged
+        it["si", kind] = r.iterations
+    for kind in ("xdrop", "random"):
+        r = O.lobpcg(A.to_scipy(), X0, 10, A.anorm, tol=1e-8, n_es=n_es, se=O.SEParams("fix"),
+                     expand_vectors=kind, random_block=draw)
+        assert r.converged
+        it["lobpcg", kind] = r.iterations
+    assert it["si", "random"] > it["si", "xdrop"] > it["si", "powered"], it
+    assert it["lobpcg", "random"] > it["lobpcg", "xdrop"], it
+
+
+def test_expansion_vectors_leave_the_fix_schedule_unchanged():
+    """fix decides shrinks and expansions from the iteration count alone
+    (Algorithm 6), so every choice of vectors gives the same schedule over the
+    iterations both runs make."""
+    A, X0, nb, n_es, draw = _expand_case(16, 4, 4, 3)
+    runs = [O.subspace_iteration(A.to_scipy(), X0, 4, A.anorm, tol=1e-8, n_es=n_es,
+                                 se=O.SEParams("fix"), expand_vectors=k, random_block=draw)
+            for k in ("xdrop", "random", "powered")]
+    L = min(len(r.history) for r in runs)
+    sched = [[(h["expand"], h["shrink"]) for h in r.history[:L]] for r in runs]
+    assert sched[0] == sched[1] == sched[2]
+    assert any(e for e, _ in sched[0])
+
+
+def test_powered_xdrop_on_a_diagonal_matrix_is_a_scaled_power():
+    """On A = diag(a) the held X_drop after t power steps is, row by row,
+    X_drop(shrink) times prod over the steps of (sigma - a_i) / (sigma - theta_1):
+    the expansion then appends exactly that block. Checked through the first
+    expansion of a run whose expansion basis is recorded by the apply hook."""
+    rng = np.random.default_rng(4)
+    a = np.sort(rng.uniform(0.5, 10.0, 60))
+    A = sp.diags(a).tocsr()
+    sigma = 10.0
+    X0 = rng.standard_normal((60, 8))
+    seen = []
+
+    def op(Y):
+        seen.append(Y.copy())
+        return sigma * Y - A @ Y
+
+    r = O.subspace_iteration(A, X0, 3, sigma, tol=1e-13, n_es=5,
+                             se=O.SEParams("fix", r_warm=1.0, j_warm=2), apply_op=op,
+                             expand_vectors="powered", max_iter=40)
+    # With a custom operator the power step is not rescaled: X_drop(t) is
+    # (sigma I - A)^t X_drop(shrink), so consecutive held blocks differ by
+    # the row factors sigma - a_i exactly.
+    shr = next(h["j"] for h in r.history if h["shrink"])
+    exp = next(h["j"] for h in r.history if h["expand"])
+    assert exp > shr + 1
+    held = [Y for Y in seen if Y.shape[1] == 3][:exp - shr]  # the first wait
+    assert len(held) == exp - shr
+    for prev, nxt in zip(held, held[1:]):
+        np.testing.assert_allclose(nxt, (sigma - a)[:, None] * prev, rtol=1e-12, atol=1e-12)

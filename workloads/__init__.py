@@ -208,6 +208,22 @@ def seeded_uniform_block(n: int, nb: int, seed: int) -> np.ndarray:
     return np.asfortranarray((z >> np.uint64(11)).astype(np.float64) * 2.0 ** -52 - 1.0)
 
 
+def seeded_expansion_block(n: int, d: int, nb: int, e: int, seed: int) -> np.ndarray:
+    """The normally distributed block the library draws for the e-th expansion
+    (e = 1, 2, ...) when the expansion vectors are random: entry (i, j), j < d,
+    takes counters 2t and 2t + 1 with t = (e nb + j) n + i (past the start
+    block's n nb counters), u1 = ((z1 >> 11) + 1) 2^-53 in (0, 1],
+    u2 = (z2 >> 11) 2^-53 in [0, 1), and the Box-Muller (1958) value
+    sqrt(-2 ln u1) cos(2 pi u2). n x d column-major FP64."""
+    t = ((np.uint64(e) * np.uint64(nb) + np.arange(d, dtype=np.uint64)[None, :]) * np.uint64(n)
+         + np.arange(n, dtype=np.uint64)[:, None])
+    z1 = splitmix64(np.uint64(2) * t, seed)
+    z2 = splitmix64(np.uint64(2) * t + np.uint64(1), seed)
+    u1 = ((z1 >> np.uint64(11)) + np.uint64(1)).astype(np.float64) * 2.0 ** -53
+    u2 = (z2 >> np.uint64(11)).astype(np.float64) * 2.0 ** -53
+    return np.asfortranarray(np.sqrt(-2.0 * np.log(u1)) * np.cos(2.0 * np.pi * u2))
+
+
 def random_sparse_spd(n: int, density: float, seed: int) -> CSRMatrix:
     """Small random sparse symmetric positive definite matrix (diagonally dominant)."""
     rng = np.random.default_rng(seed)
