@@ -35,6 +35,7 @@ from .solvers import (  # noqa: F401
     rayleigh_ritz,
     hl_basis,
     si_step,
+    chebyshev_filter,
     lobpcg,
     steepest_descent,
     subspace_iteration,

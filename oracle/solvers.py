@@ -130,6 +130,26 @@ def rayleigh_ritz(S, AS):
     return theta, Z
 
 
+def chebyshev_filter(A, Y, degree, lower, cut, upper):
+    """p(A) Y with p(t) = T_d((t - c) / e) / T_d((lower - c) / e), the Chebyshev
+    filter of degree d >= 1 that damps [cut, upper] and is one at ``lower``
+    (c and e the centre and half-width of [cut, upper]; Zhou and Saad's filter
+    for subspace iteration, 2007). Written as its definition: the textbook
+    three-term recurrence T_{i+1}(L) = 2 L T_i(L) - T_{i-1}(L) on
+    L = (A - cI) / e applied to Y, divided by the same recurrence on the
+    scalar (lower - c) / e."""
+    c = 0.5 * (upper + cut)
+    e = 0.5 * (upper - cut)
+    L = lambda Z: (_apply(A, Z) - c * Z) / e  # noqa: E731
+    l0 = (lower - c) / e
+    T_prev, T = Y, L(Y)
+    t_prev, t = 1.0, l0
+    for _ in range(2, degree + 1):
+        T_prev, T = T, 2.0 * L(T) - T_prev
+        t_prev, t = t, 2.0 * l0 * t - t_prev
+    return T / t
+
+
 def si_step(apply_op, A, X):
     """One subspace-iteration step (Algorithm 1 body without shrink/expand).
 
@@ -402,12 +422,16 @@ def subspace_iteration(
     time_limit_s=None,
     expand_vectors="xdrop",
     random_block=None,
+    filter_degree=0,
 ):
     """Subspace iteration with Rayleigh-Ritz and shrink-and-expand (Algorithm 1).
 
     ``apply_op`` defaults to the shifted power step X -> sigma X - A X with
     ``sigma = anorm`` when not given. With a custom ``apply_op`` the powered
-    X_drop is not rescaled.
+    X_drop is not rescaled. ``filter_degree`` d >= 1 replaces the operator by
+    the Chebyshev filter of degree d that damps [theta_k, sigma] and is one at
+    theta_1 (theta the current Ritz values of the k-column X); the powered
+    X_drop then takes the same filter.
     """
     _expansion_source(expand_vectors, random_block, True)
     se = se or SEParams()
@@ -442,13 +466,21 @@ def subspace_iteration(
         if time_limit_s is not None and time.perf_counter() - t0 > time_limit_s:
             break
 
-        Y = apply_op(X)
+        if filter_degree > 0:
+            up = anorm if sigma is None else sigma
+            if up > lam[-1]:
+                step = lambda Z: chebyshev_filter(A, Z, filter_degree, lam[0], lam[-1], up)  # noqa: E731
+            else:  # no interval to damp: the plain shifted step
+                step = apply_op
+        else:
+            step = apply_op
+        Y = step(X)
         if expand_vectors == "powered" and Xdrop is not None:
             # one power step on the held X_drop, no orthogonalization
             scale = 1.0
-            if shift is not None and shift - lam[0] > 0.0:
+            if step is apply_op and shift is not None and shift - lam[0] > 0.0:
                 scale = 1.0 / (shift - lam[0])
-            Xdrop = apply_op(Xdrop) * scale
+            Xdrop = step(Xdrop) * scale
         if ctl.ifexpand(j) and Xdrop is not None:
             if expand_vectors == "random":
                 Xdrop = random_block(n_exp + 1, Xdrop.shape[1])

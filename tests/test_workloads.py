@@ -93,3 +93,23 @@ def test_seeded_uniform_block_layout_and_range():
     z = W.splitmix64(np.array([1 * 5 + 2], dtype=np.uint64), 7)
     assert B[2, 1] == float(int(z[0]) >> 11) * 2.0 ** -52 - 1.0
     assert np.linalg.matrix_rank(W.seeded_uniform_block(200, 12, 1)) == 12
+
+
+def test_seeded_expansion_block_is_standard_normal_and_independent():
+    """Box-Muller of uniform pairs gives independent standard normals: the
+    draws pass a Kolmogorov-Smirnov test against N(0, 1), and different
+    expansions, columns and seeds are uncorrelated."""
+    from scipy import stats
+
+    B = W.seeded_expansion_block(4000, 20, 40, 3, 9)
+    assert B.shape == (4000, 20) and B.flags.f_contiguous
+    assert stats.kstest(B.ravel(), "norm").pvalue > 1e-3
+    C = np.corrcoef(B.T)
+    assert np.abs(C - np.eye(20)).max() < 0.08
+    B4 = W.seeded_expansion_block(4000, 20, 40, 4, 9)
+    B9 = W.seeded_expansion_block(4000, 20, 40, 3, 10)
+    for other in (B4, B9):
+        assert abs(np.corrcoef(B.ravel(), other.ravel())[0, 1]) < 0.02
+    # column j of draw e is column nb + j of draw e - 1 (one counter space)
+    np.testing.assert_array_equal(W.seeded_expansion_block(50, 45, 40, 2, 1)[:, 0],
+                                  W.seeded_expansion_block(50, 45, 40, 1, 1)[:, 40])
