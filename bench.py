@@ -48,6 +48,10 @@ def parse():
     ap.add_argument("--solver", default="lobpcg", choices=["lobpcg", "si", "sd"])
     ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32", "bf16"])
     ap.add_argument("--max-iter", type=int, default=None)
+    ap.add_argument("--expand-vectors", default="xdrop", choices=["xdrop", "random", "powered"],
+                    help="vectors appended at an expansion (powered: subspace iteration only)")
+    ap.add_argument("--filter-degree", type=int, default=0,
+                    help="subspace iteration: Chebyshev filter degree (0 = shifted power step)")
     ap.add_argument("--strategy", default="fix")
     ap.add_argument("--no-fixed", action="store_true", help="skip the fixed-block comparison")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -117,6 +121,7 @@ def main():
     torch.cuda.synchronize()
 
     extra = {} if args.max_iter is None else {"max_iter": args.max_iter}
+    extra.update(expand_vectors=args.expand_vectors, seed=args.x0_seed, filter_degree=args.filter_degree)
 
     def run(strategy, profile=0):
         return api.solve(ctx, M, X0d, args.n_ev, args.n_extra, strategy=strategy, tol=1e-8,
@@ -151,7 +156,9 @@ def main():
         "data": "synthetic",
         "config": {
             "workload": f"{wname} {args.solver.upper()} n_ev={args.n_ev} n_extra={args.n_extra} "
-                        f"strategy={args.strategy} precision={args.precision} tol=1e-8",
+                        f"strategy={args.strategy} precision={args.precision} tol=1e-8"
+                        + ("" if args.expand_vectors == "xdrop" else f" expand={args.expand_vectors}")
+                        + (f" filter_degree={args.filter_degree}" if args.filter_degree else ""),
             "n": A.n, "nnz": A.nnz, "n_ev": args.n_ev, "block": nb,
         },
         "shrink_expand": {
@@ -278,6 +285,7 @@ def roofline(infos, workload=None, precision="fp64"):
 def cpu_baseline(A, X0, args, gpu_iters, log):
     """The FP64 oracle on the host cores, bounded sample of the same solve."""
     import oracle as O
+    import workloads as W
 
     try:
         from threadpoolctl import threadpool_info
@@ -287,9 +295,12 @@ def cpu_baseline(A, X0, args, gpu_iters, log):
         cores = os.cpu_count()
     t = time.perf_counter()
     solver = {"si": O.subspace_iteration, "sd": O.steepest_descent}.get(args.solver, O.lobpcg)
+    nb = args.n_ev + args.n_extra
+    draw = lambda e, d: W.seeded_expansion_block(A.n, d, nb, e, args.x0_seed)  # noqa: E731
     res = solver(A.to_scipy(), X0, args.n_ev, A.anorm, tol=1e-8,
                  n_es=args.n_ev + min(5, args.n_extra - 1), se=O.SEParams(args.strategy),
-                 time_limit_s=args.cpu_seconds)
+                 time_limit_s=args.cpu_seconds, expand_vectors=args.expand_vectors, random_block=draw,
+                 **({"filter_degree": args.filter_degree} if args.solver == "si" else {}))
     el = time.perf_counter() - t
     done = max(res.iterations - 1, 1)  # the last recorded iteration stopped at its check
     per_iter = el / done

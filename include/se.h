@@ -50,6 +50,19 @@ typedef struct se_matrix se_matrix;
 #define SE_SD 2     /* Algorithm 2 (block steepest descent): S = [X, W], no P; soft locking
                        and expansion as in LOBPCG (X_drop orthonormalized against S) */
 
+/* Vectors appended at an expansion (Section 6, the vectors appended in the
+ * expansion). FP64 only (SE_ERR_UNSUPPORTED with a mixed precision). */
+#define SE_EXPAND_XDROP 0   /* the vectors dropped at the last shrink (the paper's choice) */
+#define SE_EXPAND_RANDOM 1  /* a normally distributed block of the same width, drawn on the
+                               device: entry (i, j) of the e-th expansion (e = 1, 2, ...) is
+                               Box-Muller of SplitMix64 counters 2t, 2t + 1 with
+                               t = (e nb + j) n + i under params.seed (LOBPCG: the first
+                               columns replace X_drop, the rest P_drop) */
+#define SE_EXPAND_POWERED 2 /* subspace iteration only (SE_ERR_INVALID_ARG otherwise): the
+                               held X_drop takes one power step sigma X - A X per iteration,
+                               without orthogonalization, divided by sigma - theta_1
+                               (theta_1 the smallest current Ritz value) */
+
 /* Shrink-and-expand strategies (Section 3.2). */
 #define SE_STRAT_NONE 0
 #define SE_STRAT_FIX 1    /* Algorithm 6 */
@@ -113,10 +126,19 @@ typedef struct se_params {
                               for which the residual block is orthonormalized implicitly (by
                               whitening in coefficient space) rather than projected and
                               orthonormalized over n; 0 = 1e-2; > 1 = always explicit */
-    uint64_t seed;       /* start block generated when se_solve gets X0 = NULL */
+    uint64_t seed;       /* start block generated when se_solve gets X0 = NULL, and the
+                            blocks drawn by SE_EXPAND_RANDOM */
     double* history;     /* optional host buffer of history_cap x SE_HISTORY_FIELDS doubles */
     int32_t history_cap; /* rows available in history */
-    int32_t reserved;
+    int32_t expand_vectors; /* SE_EXPAND_XDROP (default), SE_EXPAND_RANDOM or SE_EXPAND_POWERED */
+    int32_t filter_degree;  /* subspace iteration, FP64: 0 = the shifted power step sigma X - A X;
+                               d in 1..64 = the Chebyshev filter of degree d (Zhou and Saad 2007)
+                               that damps [theta_k, sigma] and is one at theta_1 (theta the
+                               current Ritz values of the k-column block), by the scaled
+                               three-term recurrence: d - 1 extra sparse products per
+                               iteration. A powered X_drop takes the same filter. Falls back
+                               to the shifted step at an iteration where sigma <= theta_k. */
+    int32_t reserved;       /* must be 0 */
 } se_params;
 
 typedef struct se_info {

@@ -502,13 +502,14 @@ __global__ __launch_bounds__(kThreads) void gather_cols_kernel(long long n, cons
 
 __global__ __launch_bounds__(kThreads) void shift_sub_kernel(long long n, double* __restrict__ X,
                                                              const double* __restrict__ AX,
-                                                             long long ld, int k, double sigma) {
+                                                             long long ld, int k, double sigma,
+                                                             double scale) {
     const long long total = n * k;
     for (long long e = (long long)blockIdx.x * kThreads + threadIdx.x; e < total;
          e += (long long)gridDim.x * kThreads) {
         const long long r = e / k;
         const int c = (int)(e - r * k);
-        X[r * ld + c] = sigma * X[r * ld + c] - AX[r * ld + c];
+        X[r * ld + c] = scale * (sigma * X[r * ld + c] - AX[r * ld + c]);
     }
 }
 
@@ -1028,6 +1029,14 @@ hipError_t launch_spmm_resid(hipStream_t st, int n, const int* rowptr, const int
 }
 
 namespace {
+// SplitMix64 (Steele, Lea and Flood 2014) at Weyl state seed + (k + 1) * gamma.
+__device__ __forceinline__ unsigned long long splitmix64(unsigned long long seed, unsigned long long k) {
+    unsigned long long z = seed + (k + 1ull) * 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
 __global__ __launch_bounds__(kThreads) void seeded_block_kernel(long long n, int nb, unsigned long long seed,
                                                                 double* __restrict__ X, long long ld,
                                                                 int col_major) {
@@ -1036,12 +1045,29 @@ __global__ __launch_bounds__(kThreads) void seeded_block_kernel(long long n, int
          e += (long long)gridDim.x * kThreads) {
         const long long i = e / nb;
         const int j = (int)(e - i * nb);
-        const unsigned long long k = (unsigned long long)j * (unsigned long long)n + (unsigned long long)i;
-        unsigned long long z = seed + (k + 1ull) * 0x9E3779B97F4A7C15ull;
-        z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
-        z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
-        z ^= z >> 31;
+        const unsigned long long z = splitmix64(seed, (unsigned long long)j * (unsigned long long)n + (unsigned long long)i);
         X[col_major ? (long long)j * ld + i : i * ld + j] = (double)(z >> 11) * 0x1p-52 - 1.0;
+    }
+}
+
+// Columns c0 .. c0 + d - 1 of a row-major panel get the normally distributed
+// block of draw `draw`: entry (i, j) is Box-Muller (1958) of the SplitMix64
+// outputs at counters 2t and 2t + 1, t = (draw nb + j) n + i.
+__global__ __launch_bounds__(kThreads) void gaussian_cols_kernel(long long n, int d, int nb, long long draw,
+                                                                 unsigned long long seed, double* __restrict__ X,
+                                                                 long long ld, int c0) {
+    const long long total = n * d;
+    for (long long e = (long long)blockIdx.x * kThreads + threadIdx.x; e < total;
+         e += (long long)gridDim.x * kThreads) {
+        const long long i = e / d;
+        const int j = (int)(e - i * d);
+        const unsigned long long t =
+            ((unsigned long long)draw * (unsigned long long)nb + (unsigned long long)j) * (unsigned long long)n +
+            (unsigned long long)i;
+        const unsigned long long z1 = splitmix64(seed, 2ull * t), z2 = splitmix64(seed, 2ull * t + 1ull);
+        const double u1 = (double)((z1 >> 11) + 1ull) * 0x1p-53;  // (0, 1]
+        const double u2 = (double)(z2 >> 11) * 0x1p-53;           // [0, 1)
+        X[i * ld + c0 + j] = sqrt(-2.0 * log(u1)) * cos(6.283185307179586 * u2);
     }
 }
 }  // namespace
@@ -1051,6 +1077,14 @@ hipError_t launch_seeded_block(hipStream_t st, long long n, int nb, unsigned lon
     if (n <= 0 || nb <= 0) return hipSuccess;
     hipLaunchKernelGGL(seeded_block_kernel, dim3(grid_for(n * nb, kThreads, 16384)), dim3(kThreads), 0, st, n,
                        nb, seed, X, ld, col_major ? 1 : 0);
+    return hipGetLastError();
+}
+
+hipError_t launch_gaussian_cols(hipStream_t st, long long n, int d, int nb, long long draw, unsigned long long seed,
+                                double* X, long long ld, int c0) {
+    if (n <= 0 || d <= 0) return hipSuccess;
+    hipLaunchKernelGGL(gaussian_cols_kernel, dim3(grid_for(n * d, kThreads, 16384)), dim3(kThreads), 0, st, n, d,
+                       nb, draw, seed, X, ld, c0);
     return hipGetLastError();
 }
 
@@ -1072,10 +1106,10 @@ hipError_t launch_form_w(hipStream_t st, long long n, const double* X, const dou
 }
 
 hipError_t launch_shift_sub(hipStream_t st, long long n, double* X, const double* AX, long long ld,
-                            int k, double sigma) {
+                            int k, double sigma, double scale) {
     if (k <= 0 || n <= 0) return hipSuccess;
     hipLaunchKernelGGL(shift_sub_kernel, dim3(grid_for(n * k, kThreads, 16384)), dim3(kThreads), 0, st,
-                       n, X, AX, ld, k, sigma);
+                       n, X, AX, ld, k, sigma, scale);
     return hipGetLastError();
 }
 

@@ -68,6 +68,13 @@ se_status validate_solve(const se_matrix* A, const se_params* p) {
         return SE_ERR_INVALID_ARG;
     if (p->history && p->history_cap < 0) return SE_ERR_INVALID_ARG;
     if (p->solver == SE_SI && p->sigma < 0.0) return SE_ERR_INVALID_ARG;
+    if (p->expand_vectors < SE_EXPAND_XDROP || p->expand_vectors > SE_EXPAND_POWERED) return SE_ERR_INVALID_ARG;
+    if (p->expand_vectors == SE_EXPAND_POWERED && p->solver != SE_SI) return SE_ERR_INVALID_ARG;
+    if (p->expand_vectors != SE_EXPAND_XDROP && p->precision != SE_FP64) return SE_ERR_UNSUPPORTED;
+    if (p->filter_degree < 0 || p->filter_degree > 64) return SE_ERR_INVALID_ARG;
+    if (p->filter_degree > 0 && p->solver != SE_SI) return SE_ERR_INVALID_ARG;
+    if (p->filter_degree > 0 && p->precision != SE_FP64) return SE_ERR_UNSUPPORTED;
+    if (p->reserved != 0) return SE_ERR_INVALID_ARG;
     return SE_OK;
 }
 }  // namespace se
@@ -99,6 +106,7 @@ void se_params_default(se_params* p) {
     p->seed = 0;
     p->history = nullptr;
     p->history_cap = 0;
+    p->expand_vectors = SE_EXPAND_XDROP;
 }
 
 se_status se_ctx_create(int device, void* stream, se_ctx** out) {

@@ -108,6 +108,18 @@ hipError_t launch_spmm_resid(hipStream_t st, int n, const int* rowptr, const int
 hipError_t launch_seeded_block(hipStream_t st, long long n, int nb, unsigned long long seed, double* X,
                                long long ld, bool col_major);
 
+// Z[:, c] = alpha U[:, c] + beta V[:, c] + gamma Z[:, c] for c < k (Z is not
+// read when gamma = 0): one step of the Chebyshev filter recurrence. ld even.
+hipError_t launch_cheb_step(hipStream_t st, long long n, int k, double alpha, const double* U, double beta,
+                            const double* V, double gamma, double* Z, long long ld);
+
+// Columns c0 .. c0 + d - 1 of the row-major n-row panel X get the normally
+// distributed block of draw `draw`: entry (i, j) is sqrt(-2 ln u1) cos(2 pi u2)
+// (Box-Muller) with u1 = ((z1 >> 11) + 1) 2^-53, u2 = (z2 >> 11) 2^-53 and z1,
+// z2 the SplitMix64 outputs at counters 2t and 2t + 1, t = (draw nb + j) n + i.
+hipError_t launch_gaussian_cols(hipStream_t st, long long n, int d, int nb, long long draw, unsigned long long seed,
+                                double* X, long long ld, int c0);
+
 // dst[:, q] = src[:, idx[q]] for q < a (dst must not overlap src).
 hipError_t launch_gather_cols(hipStream_t st, long long n, const double* src, long long lds, const int* idx,
                               int a, double* dst, long long ldd);
@@ -117,9 +129,9 @@ hipError_t launch_form_w(hipStream_t st, long long n, const double* X, const dou
                          long long ld, const double* lam, const int* act, int a, double* W,
                          long long ldw);
 
-// X[:, c] = sigma X[:, c] - AX[:, c] for c < k.
+// X[:, c] = scale (sigma X[:, c] - AX[:, c]) for c < k.
 hipError_t launch_shift_sub(hipStream_t st, long long n, double* X, const double* AX, long long ld,
-                            int k, double sigma);
+                            int k, double sigma, double scale = 1.0);
 
 // dst[:, dc + c] = src[:, sc + c] for c < w.
 hipError_t launch_copy_cols(hipStream_t st, long long n, const double* src, long long lds, int sc,

@@ -721,8 +721,11 @@ struct Solver {
                 act_hl = act;
             if (expand_now) {
                 // S_drop <- S_drop - S (S^T S_drop), twice; orthonormalize;
-                // then its images A S_drop by one SpMM.
+                // then its images A S_drop by one SpMM. Random expansion
+                // vectors take the place of [X_drop, P_drop].
                 int d0 = dx + dp;
+                if (p.expand_vectors == SE_EXPAND_RANDOM)
+                    HC(launch_gaussian_cols(st, n, d0, nb, n_exp + 1, (unsigned long long)p.seed, Sd, ld, 0));
                 const Segs S = seg3(X, k, P, pw, W, a);
                 for (int pass = 0; pass < 2; ++pass) {
                     ST(gram(S, seg1(Sd, d0), 0, ws.G.as<double>()));
@@ -820,8 +823,10 @@ struct Solver {
                 dx = k - n_es;
                 dp = std::max(0, pw - n_es);
                 dp = std::min(dp, ld - dx);  // S_drop must fit one panel
-                HC(launch_copy_cols(st, n, X, ld, n_es, Sd, ld, 0, dx));
-                HC(launch_copy_cols(st, n, P, ld, n_es, Sd, ld, dx, dp));
+                if (p.expand_vectors == SE_EXPAND_XDROP) {
+                    HC(launch_copy_cols(st, n, X, ld, n_es, Sd, ld, 0, dx));
+                    HC(launch_copy_cols(st, n, P, ld, n_es, Sd, ld, dx, dp));
+                }
                 // keep the rows and columns of X(:, 0:n_es) and P(:, 0:pw') in Axp
                 const int pk = std::min(pw, n_es);
                 std::vector<int> keep;
@@ -843,6 +848,43 @@ struct Solver {
             }
             amend_flags(flags);
         }
+        return SE_OK;
+    }
+
+    // Chebyshev filter of degree p.filter_degree on the w columns of Y: damps
+    // [cut, up] and is one at `lower`, by the scaled three-term recurrence
+    // Y_1 = (s_1 / e) (A - cI) Y_0, Y_i = (2 s_i / e) (A - cI) Y_{i-1} -
+    // s_{i-1} s_i Y_{i-2}, s_1 = e / (lower - c), s_i = 1 / (2 / s_1 - s_{i-1})
+    // (c, e the centre and half-width of [cut, up]), which keeps the block of
+    // order one. AY0 = A Y when known (else one more product into tmp). Y and
+    // Yalt are two panels that rotate; on return Y holds the filtered block.
+    se_status cheb_filter(double*& Y, double*& Yalt, const double* AY0, double* tmp, int w, double lower,
+                          double cut, double up) {
+        const double c = 0.5 * (up + cut), e = 0.5 * (up - cut);
+        double s = e / (lower - c);
+        const double tau = 2.0 / s;
+        if (!AY0) {
+            ST(spmm(Y, tmp, w));
+            AY0 = tmp;
+        }
+        double alpha = s / e;
+        ST(tic());
+        HC(launch_cheb_step(st, n, w, alpha, AY0, -c * alpha, Y, 0.0, Yalt, ld));
+        ST(toc(SE_K_RESID, 24.0 * n * w, 3.0 * n * w));
+        double* prev = Y;
+        double* cur = Yalt;
+        for (int i = 2; i <= p.filter_degree; ++i) {
+            ST(spmm(cur, tmp, w));
+            const double s_new = 1.0 / (tau - s);
+            alpha = 2.0 * s_new / e;
+            ST(tic());
+            HC(launch_cheb_step(st, n, w, alpha, tmp, -c * alpha, cur, -s * s_new, prev, ld));
+            ST(toc(SE_K_RESID, 32.0 * n * w, 5.0 * n * w));
+            s = s_new;
+            std::swap(prev, cur);
+        }
+        Y = cur;
+        Yalt = prev;
         return SE_OK;
     }
 
@@ -881,12 +923,35 @@ struct Solver {
             if (out_of_time()) break;
             int flags = 0;
             const bool want_expand = ctl.ifexpand(j);
-            // Y <- sigma X - A X (AX is current), then append X_drop.
-            ST(tic());
-            HC(launch_shift_sub(st, n, X, AX, ld, k, sigma));
-            ST(toc(SE_K_RESID, 24.0 * n * k, 2.0 * n * k));
+            // Y <- sigma X - A X, or the Chebyshev filter on [theta_k, sigma]
+            // (AX is current), then append X_drop.
+            const bool filt = p.filter_degree > 0 && sigma > lam[k - 1];
+            if (filt) {
+                ST(cheb_filter(X, Xn, AX, AW, k, lam[0], lam[k - 1], sigma));
+            } else {
+                ST(tic());
+                HC(launch_shift_sub(st, n, X, AX, ld, k, sigma));
+                ST(toc(SE_K_RESID, 24.0 * n * k, 2.0 * n * k));
+            }
+            if (have_drop && p.expand_vectors == SE_EXPAND_POWERED) {
+                // one power step on the held X_drop, without orthogonalization:
+                // the same filter, or the shifted step divided by
+                // sigma - theta_1 to keep it of order one
+                if (filt) {
+                    ST(cheb_filter(Sd, T1, nullptr, ASd, dx, lam[0], lam[k - 1], sigma));
+                } else {
+                    ST(spmm(Sd, ASd, dx));
+                    const double gap = sigma - lam[0];
+                    ST(tic());
+                    HC(launch_shift_sub(st, n, Sd, ASd, ld, dx, sigma, gap > 0.0 ? 1.0 / gap : 1.0));
+                    ST(toc(SE_K_RESID, 24.0 * n * dx, 3.0 * n * dx));
+                }
+            }
             if (want_expand && have_drop) {
-                HC(launch_copy_cols(st, n, Sd, ld, 0, X, ld, k, dx));
+                if (p.expand_vectors == SE_EXPAND_RANDOM)
+                    HC(launch_gaussian_cols(st, n, dx, nb, n_exp + 1, (unsigned long long)p.seed, X, ld, k));
+                else
+                    HC(launch_copy_cols(st, n, Sd, ld, 0, X, ld, k, dx));
                 k += dx;
                 have_drop = false;
                 ctl.did_expand(j);
@@ -899,7 +964,8 @@ struct Solver {
             ST(rr_plain(k));
             if (ctl.ifshrink(j)) {
                 dx = k - n_es;
-                HC(launch_copy_cols(st, n, X, ld, n_es, Sd, ld, 0, dx));
+                if (p.expand_vectors != SE_EXPAND_RANDOM)
+                    HC(launch_copy_cols(st, n, X, ld, n_es, Sd, ld, 0, dx));
                 k = n_es;
                 have_drop = true;
                 ctl.did_shrink(j);
