@@ -39,5 +39,7 @@ from .solvers import (  # noqa: F401
     lobpcg,
     steepest_descent,
     subspace_iteration,
+    projected_cg,
+    tracemin,
 )
 from . import mixed  # noqa: F401,E402

@@ -407,6 +407,104 @@ def steepest_descent(
                        n_shr, n_exp, ms, mp)
 
 
+def projected_cg(A, X, B, steps):
+    """Approximate solution of P A P D = P B, P = I - X X^T (X orthonormal), by
+    ``steps`` conjugate-gradient iterations from D = 0, each column on its own
+    (TraceMIN's inexact inner solve, Section 2.4). A column stops (its step
+    length is zero) once its residual vanishes or its curvature d^T P A P d is
+    not positive."""
+    P = lambda Z: Z - X @ (X.T @ Z)  # noqa: E731
+    r = P(B)
+    d = r.copy()
+    D = np.zeros_like(B)
+    rr = np.einsum("ij,ij->j", r, r)
+    for _ in range(steps):
+        q = P(_apply(A, d))
+        dq = np.einsum("ij,ij->j", d, q)
+        ok = (dq > 0.0) & (rr > 0.0)
+        alpha = np.where(ok, rr / np.where(ok, dq, 1.0), 0.0)
+        D = D + d * alpha
+        r = r - q * alpha
+        rr_new = np.einsum("ij,ij->j", r, r)
+        beta = np.where(rr > 0.0, rr_new / np.where(rr > 0.0, rr, 1.0), 0.0)
+        d = r + d * beta
+        rr = rr_new
+    return D
+
+
+def tracemin(
+    A,
+    X0,
+    n_ev,
+    anorm,
+    tol=1e-8,
+    n_es=None,
+    se: SEParams | None = None,
+    max_iter=1000,
+    cg_steps=5,
+    drop_tol=1e-12,
+    time_limit_s=None,
+):
+    """TraceMIN with shrink-and-expand (Algorithm 4, Section 2.4): X <- X - D
+    with D from ``cg_steps`` projected CG iterations on P A P D = P R (five in
+    the paper's experiments), then [X, X_drop] at an expansion, orthonormalize,
+    Rayleigh-Ritz, shrink.
+
+    Reading: the projector written I - X^H X in Algorithm 4 is I - X X^H (the
+    one in the text above it); the inner solve needs P A P positive definite on
+    range(P), i.e. A positive definite (as in the paper's experiments)."""
+    se = se or SEParams()
+    nb = X0.shape[1]
+    ctl = SEController(se if _se_enabled(se, n_ev, n_es, nb) else SEParams("none"))
+    t0 = time.perf_counter()
+
+    X, _ = orth(np.asarray(X0, dtype=np.float64), drop_tol)
+    lam, Z = rayleigh_ritz(X, _apply(A, X))
+    X = X @ Z
+    Xdrop = None
+    history = []
+    n_shr = n_exp = 0
+    stop = paper = None
+
+    for j in range(1, max_iter + 1):
+        R, stop, paper = residual_measures(A, X, lam, anorm)
+        r_j = float(np.max(paper[:n_ev]))
+        ctl.observe(j, r_j)
+        rec = dict(j=j, r=r_j, max_stop=float(np.max(stop[:n_ev])), k=X.shape[1],
+                   trace=float(np.sum(lam)), expand=False, shrink=False)
+        history.append(rec)
+        if np.all(stop[:n_ev] <= tol):
+            return SolveResult(lam[:n_ev].copy(), X[:, :n_ev].copy(), j, True, history,
+                               n_shr, n_exp, float(np.max(stop[:n_ev])), r_j)
+        if time_limit_s is not None and time.perf_counter() - t0 > time_limit_s:
+            break
+
+        # X <- X - D, P A P D = P R solved inexactly
+        X = X - projected_cg(A, X, R, cg_steps)
+        if ctl.ifexpand(j) and Xdrop is not None:
+            X = np.hstack([X, Xdrop])
+            Xdrop = None
+            ctl.did_expand(j)
+            n_exp += 1
+            rec["expand"] = True
+        X, _ = orth(X, drop_tol)
+        lam, Z = rayleigh_ritz(X, _apply(A, X))
+        X = X @ Z
+
+        if ctl.ifshrink(j):
+            Xdrop = X[:, n_es:]
+            X = X[:, :n_es]
+            lam = lam[:n_es]
+            ctl.did_shrink(j)
+            n_shr += 1
+            rec["shrink"] = True
+
+    ms = float(np.max(stop[:n_ev])) if stop is not None else np.inf
+    mp = float(np.max(paper[:n_ev])) if paper is not None else np.inf
+    return SolveResult(lam[:n_ev].copy(), X[:, :n_ev].copy(), len(history), False, history,
+                       n_shr, n_exp, ms, mp)
+
+
 def subspace_iteration(
     A,
     X0,

@@ -388,3 +388,64 @@ def test_filtered_subspace_iteration_matches_closed_form_in_fewer_iterations(str
     assert filt.converged and plain.converged
     assert _check(filt, A, pins.laplacian_spectrum(m, 2, n_ev), lam_rtol=1e-9) == []
     assert 8 * filt.iterations < plain.iterations
+
+
+# --- TraceMIN (Algorithm 4) ------------------------------------------------------------
+
+def test_projected_cg_reaches_the_projected_solution():
+    """Enough CG steps solve P A P D = P B on range(P) exactly: compare with the
+    solution in an orthonormal basis Q of range(P), D = Q (Q^T A Q)^-1 Q^T B."""
+    rng = np.random.default_rng(3)
+    n = 30
+    M = rng.standard_normal((n, n))
+    A = M @ M.T + n * np.eye(n)
+    X, _ = np.linalg.qr(rng.standard_normal((n, 3)))
+    B = rng.standard_normal((n, 4))
+    D = O.projected_cg(sp.csr_matrix(A), X, B, n)
+    Qf, _ = np.linalg.qr(np.hstack([X, rng.standard_normal((n, n - 3))]))
+    Q = Qf[:, 3:]
+    ref = Q @ np.linalg.solve(Q.T @ A @ Q, Q.T @ B)
+    np.testing.assert_allclose(D, ref, rtol=1e-8, atol=1e-10)
+    assert np.abs(X.T @ D).max() < 1e-10
+    # one step is the steepest-descent step along the projected right-hand side
+    r = B - X @ (X.T @ B)
+    q = A @ r - X @ (X.T @ (A @ r))
+    np.testing.assert_allclose(O.projected_cg(sp.csr_matrix(A), X, B, 1),
+                               r * (np.sum(r * r, 0) / np.sum(r * q, 0)), rtol=1e-12)
+
+
+@pytest.mark.parametrize("strategy", ["none", "fix", "slopek"])
+def test_tracemin_matches_closed_form(strategy):
+    m, n_ev, nb = 20, 6, 12
+    A = W.laplacian_2d(m)
+    X0 = W.gaussian_block(A.n, nb, 5)
+    res = O.tracemin(A.to_scipy(), X0, n_ev, A.anorm, tol=1e-8, n_es=n_ev + 2,
+                     se=O.SEParams(strategy, r_warm=1e-2))
+    assert res.converged
+    assert _check(res, A, pins.laplacian_spectrum(m, 2, n_ev), lam_rtol=1e-9) == []
+    if strategy != "none":
+        assert res.n_shrinks >= 1
+
+
+def test_tracemin_trace_decreases_and_bounds_from_above():
+    """Sameh and Wisniewski: each TraceMIN step lowers the trace of the Ritz
+    values (a CG solve from zero lowers the quadratic, and orthonormalizing
+    X - D with X^T D = 0 lowers it further); Courant-Fischer bounds every
+    Ritz value from below by the exact eigenvalue."""
+    A = W.laplacian_3d(10)
+    X0 = W.gaussian_block(A.n, 14, 2)
+    res = O.tracemin(A.to_scipy(), X0, 10, A.anorm, tol=1e-10)
+    tr = np.array([h["trace"] for h in res.history])
+    assert res.converged and np.all(np.diff(tr) <= 1e-12 * abs(tr[0]))
+    exact = np.sort(np.linalg.eigvalsh(A.to_scipy().toarray()))[:10]
+    assert np.all(res.lam >= exact - 1e-12)
+
+
+@pytest.mark.parametrize("seed", [0, 1])
+def test_tracemin_brute_force_random_sparse_spd(seed):
+    A = W.random_sparse_spd(150, 0.04, seed)
+    X0 = W.gaussian_block(A.n, 10, seed + 30)
+    res = O.tracemin(A.to_scipy(), X0, 6, A.anorm, tol=1e-9, max_iter=3000)
+    exact = np.sort(np.linalg.eigvalsh(A.to_scipy().toarray()))[:6]
+    assert res.converged
+    np.testing.assert_allclose(res.lam, exact, rtol=1e-10)
