@@ -45,7 +45,7 @@ def parse():
     ap.add_argument("--nodes", type=int, default=None, help="Chung-Lu graph size")
     ap.add_argument("--n-ev", type=int, default=None)
     ap.add_argument("--n-extra", type=int, default=None)
-    ap.add_argument("--solver", default="lobpcg", choices=["lobpcg", "si", "sd"])
+    ap.add_argument("--solver", default="lobpcg", choices=["lobpcg", "si", "sd", "tracemin"])
     ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32", "bf16"])
     ap.add_argument("--max-iter", type=int, default=None)
     ap.add_argument("--expand-vectors", default="xdrop", choices=["xdrop", "random", "powered"],
@@ -294,7 +294,8 @@ def cpu_baseline(A, X0, args, gpu_iters, log):
     except Exception:
         cores = os.cpu_count()
     t = time.perf_counter()
-    solver = {"si": O.subspace_iteration, "sd": O.steepest_descent}.get(args.solver, O.lobpcg)
+    solver = {"si": O.subspace_iteration, "sd": O.steepest_descent,
+              "tracemin": O.tracemin}.get(args.solver, O.lobpcg)
     nb = args.n_ev + args.n_extra
     draw = lambda e, d: W.seeded_expansion_block(A.n, d, nb, e, args.x0_seed)  # noqa: E731
     res = solver(A.to_scipy(), X0, args.n_ev, A.anorm, tol=1e-8,

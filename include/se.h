@@ -49,6 +49,9 @@ typedef struct se_matrix se_matrix;
 #define SE_SI 1     /* Algorithm 1 with the shifted power step X <- sigma X - A X */
 #define SE_SD 2     /* Algorithm 2 (block steepest descent): S = [X, W], no P; soft locking
                        and expansion as in LOBPCG (X_drop orthonormalized against S) */
+#define SE_TRACEMIN 3 /* Algorithm 4 (TraceMIN): X <- X - D with D from params.cg_steps
+                         conjugate-gradient steps on P A P D = P R, P = I - X X^T, per column;
+                         FP64; A must be positive definite */
 
 /* Vectors appended at an expansion (Section 6, the vectors appended in the
  * expansion). FP64 only (SE_ERR_UNSUPPORTED with a mixed precision). */
@@ -101,7 +104,7 @@ typedef struct se_matrix se_matrix;
 #define SE_K_CLASSES 8
 
 typedef struct se_params {
-    int32_t solver;      /* SE_LOBPCG, SE_SI or SE_SD */
+    int32_t solver;      /* SE_LOBPCG, SE_SI, SE_SD or SE_TRACEMIN */
     int32_t strategy;    /* SE_STRAT_* */
     int32_t precision;   /* SE_FP64, SE_FP32_MIXED or SE_BF16_MIXED */
     int32_t ptr_mode;    /* SE_PTR_HOST or SE_PTR_DEVICE for X0, V, lambda */
@@ -138,7 +141,7 @@ typedef struct se_params {
                                three-term recurrence: d - 1 extra sparse products per
                                iteration. A powered X_drop takes the same filter. Falls back
                                to the shifted step at an iteration where sigma <= theta_k. */
-    int32_t reserved;       /* must be 0 */
+    int32_t cg_steps;       /* SE_TRACEMIN: inner CG steps per iteration (0 = 5, the paper's) */
 } se_params;
 
 typedef struct se_info {
@@ -195,6 +198,8 @@ void se_ctx_destroy(se_ctx* ctx);
 se_status se_matrix_create_csr(se_ctx* ctx, int64_t n, int64_t nnz, const int64_t* rowptr,
                                const int32_t* colind, const double* val, uint32_t flags,
                                double anorm, se_matrix** out);
+/* Release the matrix. It may be called before or after se_ctx_destroy of the
+ * context it was created with (it uses only the device id). NULL is ignored. */
 void se_matrix_destroy(se_matrix* m);
 int64_t se_matrix_n(const se_matrix* m);
 /* The ||A||_2 bound the matrix uses (given or estimated). */

@@ -444,6 +444,8 @@ def tracemin(
     cg_steps=5,
     drop_tol=1e-12,
     time_limit_s=None,
+    expand_vectors="xdrop",
+    random_block=None,
 ):
     """TraceMIN with shrink-and-expand (Algorithm 4, Section 2.4): X <- X - D
     with D from ``cg_steps`` projected CG iterations on P A P D = P R (five in
@@ -452,7 +454,9 @@ def tracemin(
 
     Reading: the projector written I - X^H X in Algorithm 4 is I - X X^H (the
     one in the text above it); the inner solve needs P A P positive definite on
-    range(P), i.e. A positive definite (as in the paper's experiments)."""
+    range(P), i.e. A positive definite (as in the paper's experiments).
+    ``expand_vectors="random"`` appends ``random_block(e, d)`` instead of X_drop."""
+    _expansion_source(expand_vectors, random_block, False)
     se = se or SEParams()
     nb = X0.shape[1]
     ctl = SEController(se if _se_enabled(se, n_ev, n_es, nb) else SEParams("none"))
@@ -482,6 +486,8 @@ def tracemin(
         # X <- X - D, P A P D = P R solved inexactly
         X = X - projected_cg(A, X, R, cg_steps)
         if ctl.ifexpand(j) and Xdrop is not None:
+            if expand_vectors == "random":
+                Xdrop = random_block(n_exp + 1, Xdrop.shape[1])
             X = np.hstack([X, Xdrop])
             Xdrop = None
             ctl.did_expand(j)

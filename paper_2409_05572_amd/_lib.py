@@ -16,8 +16,8 @@ SE_ERR_BREAKDOWN = -4
 SE_ERR_REJECTED = -5
 SE_ERR_UNSUPPORTED = -6
 
-SE_LOBPCG, SE_SI, SE_SD = 0, 1, 2
-SOLVERS = {"lobpcg": SE_LOBPCG, "si": SE_SI, "sd": SE_SD}
+SE_LOBPCG, SE_SI, SE_SD, SE_TRACEMIN = 0, 1, 2, 3
+SOLVERS = {"lobpcg": SE_LOBPCG, "si": SE_SI, "sd": SE_SD, "tracemin": SE_TRACEMIN}
 STRATEGIES = {"none": 0, "fix": 1, "slope": 2, "slopek": 3}
 EXPAND_VECTORS = {"xdrop": 0, "random": 1, "powered": 2}
 SE_FP64 = 0
@@ -40,7 +40,7 @@ class SeParams(C.Structure):
         ("time_limit_s", C.c_double), ("r_switch", C.c_double), ("implicit_pivot", C.c_double),
         ("seed", C.c_uint64),
         ("history", C.POINTER(C.c_double)), ("history_cap", C.c_int32),
-        ("expand_vectors", C.c_int32), ("filter_degree", C.c_int32), ("reserved", C.c_int32),
+        ("expand_vectors", C.c_int32), ("filter_degree", C.c_int32), ("cg_steps", C.c_int32),
     ]
 
 

@@ -50,7 +50,10 @@ hipError_t update_lp_call(se_ctx* ctx, int64_t n, const void* U, int64_t ldu, in
 namespace se {
 // Parameter checks shared by se_solve and se_submit.
 se_status validate_solve(const se_matrix* A, const se_params* p) {
-    if (p->solver != SE_LOBPCG && p->solver != SE_SI && p->solver != SE_SD) return SE_ERR_INVALID_ARG;
+    if (p->solver != SE_LOBPCG && p->solver != SE_SI && p->solver != SE_SD && p->solver != SE_TRACEMIN)
+        return SE_ERR_INVALID_ARG;
+    if (p->solver == SE_TRACEMIN && p->precision != SE_FP64) return SE_ERR_UNSUPPORTED;
+    if (p->cg_steps < 0 || p->cg_steps > 100) return SE_ERR_INVALID_ARG;
     if (p->strategy < SE_STRAT_NONE || p->strategy > SE_STRAT_SLOPEK) return SE_ERR_INVALID_ARG;
     if (p->precision != SE_FP64 && p->precision != SE_FP32_MIXED && p->precision != SE_BF16_MIXED)
         return SE_ERR_UNSUPPORTED;
@@ -59,8 +62,9 @@ se_status validate_solve(const se_matrix* A, const se_params* p) {
     if (p->ptr_mode != SE_PTR_HOST && p->ptr_mode != SE_PTR_DEVICE) return SE_ERR_INVALID_ARG;
     const int64_t nb = (int64_t)p->n_ev + p->n_extra;
     if (p->n_ev < 1 || p->n_extra < 0 || nb > A->n) return SE_ERR_INVALID_ARG;
-    if (p->solver != SE_SI && nb > 341) return SE_ERR_UNSUPPORTED;  // 3 nb <= 1024
-    if (p->solver == SE_SI && nb > 1024) return SE_ERR_UNSUPPORTED;
+    const bool single_block = p->solver == SE_SI || p->solver == SE_TRACEMIN;  // m = nb
+    if (!single_block && nb > 341) return SE_ERR_UNSUPPORTED;  // 3 nb <= 1024
+    if (single_block && nb > 1024) return SE_ERR_UNSUPPORTED;
     if (p->n_es != 0 && (p->n_es < p->n_ev || p->n_es > nb)) return SE_ERR_INVALID_ARG;
     if (!(p->tol > 0.0) || p->max_iter < 1) return SE_ERR_INVALID_ARG;
     if (p->strategy != SE_STRAT_NONE &&
@@ -74,7 +78,6 @@ se_status validate_solve(const se_matrix* A, const se_params* p) {
     if (p->filter_degree < 0 || p->filter_degree > 64) return SE_ERR_INVALID_ARG;
     if (p->filter_degree > 0 && p->solver != SE_SI) return SE_ERR_INVALID_ARG;
     if (p->filter_degree > 0 && p->precision != SE_FP64) return SE_ERR_UNSUPPORTED;
-    if (p->reserved != 0) return SE_ERR_INVALID_ARG;
     return SE_OK;
 }
 }  // namespace se
@@ -131,6 +134,7 @@ void se_ctx_destroy(se_ctx* ctx) {
     (void)hipSetDevice(ctx->device);
     (void)hipStreamSynchronize(ctx->stream);
     ctx->ws.release();
+    (void)hipGetLastError();  // nothing reported here may linger for a later launch check
     delete ctx;
 }
 
@@ -188,6 +192,7 @@ se_status se_matrix_create_csr(se_ctx* ctx, int64_t n, int64_t nnz, const int64_
     se_matrix* m = new (std::nothrow) se_matrix();
     if (!m) return SE_ERR_OOM;
     m->ctx = ctx;
+    m->device = ctx->device;
     m->n = n;
     m->nnz = nnz;
     m->anorm = anorm;
@@ -216,12 +221,16 @@ se_status se_matrix_create_csr(se_ctx* ctx, int64_t n, int64_t nnz, const int64_
 
 void se_matrix_destroy(se_matrix* m) {
     if (!m) return;
-    if (m->ctx) (void)hipSetDevice(m->ctx->device);
+    // The context may already be gone: only the stored device id is used.
+    // Errors of these calls are not reported and must not linger as the
+    // thread's last HIP error for a later launch check to pick up.
+    (void)hipSetDevice(m->device);
     if (m->rowptr) (void)hipFree(m->rowptr);
     if (m->val32) (void)hipFree(m->val32);
     if (m->heavy) (void)hipFree(m->heavy);
     if (m->col) (void)hipFree(m->col);
     if (m->val) (void)hipFree(m->val);
+    (void)hipGetLastError();
     delete m;
 }
 
@@ -237,6 +246,9 @@ se_status se_solve(se_ctx* ctx, const se_matrix* A, const se_params* p, const do
     if (v != SE_OK) return v;
     hipError_t e = hipSetDevice(ctx->device);
     if (e != hipSuccess) return hip_fail(ctx, e);
+    // Launch checks read the thread's last HIP error: drop one left by an
+    // unrelated earlier call so that it cannot fail this solve.
+    (void)hipGetLastError();
     if (info) std::memset(info, 0, sizeof(*info));
     return se::solve(ctx, A, p, X0, V, lambda, info);
 }

@@ -108,6 +108,20 @@ hipError_t launch_spmm_resid(hipStream_t st, int n, const int* rowptr, const int
 hipError_t launch_seeded_block(hipStream_t st, long long n, int nb, unsigned long long seed, double* X,
                                long long ld, bool col_major);
 
+// Column-wise CG for TraceMIN's inner solve (per-column scalars on the device):
+// out[c] = U[:, c] . V[:, c];
+// D += alpha d (D = alpha d when first), R -= alpha Q, rr_new[c] = R[:, c] . R[:, c],
+//   alpha_c = rr_c / dq_c (0 if rr_c = 0 or dq_c <= 0);
+// Dir[:, c] = R[:, c] + (rr_new_c / rr_c) Dir[:, c] (beta 0 if rr_c = 0).
+// `part` holds 4096 k doubles.
+hipError_t launch_col_dots(hipStream_t st, long long n, int k, const double* U, const double* V, long long ld,
+                           double* part, double* out);
+hipError_t launch_cg_step(hipStream_t st, long long n, int k, const double* rr, const double* dq, const double* Dir,
+                          const double* Q, double* D, double* R, long long ld, bool first, double* part,
+                          double* rr_new);
+hipError_t launch_cg_dir(hipStream_t st, long long n, int k, const double* rr_new, const double* rr, const double* R,
+                         double* Dir, long long ld);
+
 // Z[:, c] = alpha U[:, c] + beta V[:, c] + gamma Z[:, c] for c < k (Z is not
 // read when gamma = 0): one step of the Chebyshev filter recurrence. ld even.
 hipError_t launch_cheb_step(hipStream_t st, long long n, int k, double alpha, const double* U, double beta,

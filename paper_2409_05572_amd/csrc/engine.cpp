@@ -977,6 +977,108 @@ struct Solver {
         return SE_OK;
     }
 
+    // ------------------------------------------------------------ TraceMIN --
+    // Algorithm 4: R = AX - X Theta; D from p.cg_steps conjugate-gradient
+    // steps on P A P D = P R (P = I - X X^T, every column at once with its own
+    // step lengths, from D = 0); X <- X - D; [X, X_drop] at an expansion;
+    // Cholesky-QR; Rayleigh-Ritz; shrink. Panels: R in W, D in P, the CG
+    // direction in Pn, its image (A d, then projected) in AW.
+    se_status tracemin(const double* X0) {
+        ST(alloc_panels(14));
+        ST(alloc_small(nb));
+        HC(ws.cg.ensure(sizeof(double) * (3 * (size_t)nb + 8)));
+        ST(load_x0(X0));
+        const int steps = p.cg_steps > 0 ? p.cg_steps : 5;
+        int k = nb;
+        ST(cholqr(X, k, nullptr, nullptr));
+        if (k < n_ev) return SE_ERR_BREAKDOWN;
+        ST(spmm(X, AX, k));
+        ST(rr_plain(k));
+        double* rr = ws.cg.as<double>();
+        double* rr_new = rr + nb;
+        double* dq = rr + 2 * nb;
+        double* part = ws.gram_part.as<double>();
+        bool have_drop = false;
+        int dx = 0;
+        std::vector<double> stop, paper, lam;
+        for (int j = 1; j <= p.max_iter; ++j) {
+            ST(check(X, AX, k, stop, paper, lam, W));  // W = R = AX - X Theta
+            double r = 0.0, ms = 0.0;
+            bool all = true;
+            for (int i = 0; i < n_ev; ++i) {
+                r = std::max(r, paper[i]);
+                ms = std::max(ms, stop[i]);
+                all = all && (stop[i] <= p.tol);
+            }
+            iters = j + j_off;
+            last_r = r;
+            last_stop = ms;
+            ctl.observe(j, r);
+            record(j, r, ms, k, 0, k, 0, 0);
+            if (all) {
+                converged = true;
+                break;
+            }
+            if (out_of_time()) break;
+            int flags = 0;
+
+            // projected CG from D = 0: r = P R, d = r
+            const Segs Xs = seg1(X, k);
+            ST(gram(Xs, seg1(W, k), 0, ws.G.as<double>()));
+            ST(update(Xs, ws.G.as<double>(), k, seg1(W, k), -1.0, 1.0));
+            HC(launch_copy_cols(st, n, W, ld, 0, Pn, ld, 0, k));
+            ST(tic());
+            HC(launch_col_dots(st, n, k, W, W, ld, part, rr));
+            ST(toc(SE_K_RESID, 8.0 * n * k, 2.0 * n * k));
+            for (int s = 0; s < steps; ++s) {
+                ST(spmm(Pn, AW, k));  // q = A d
+                ST(gram(Xs, seg1(AW, k), 0, ws.G.as<double>()));
+                ST(update(Xs, ws.G.as<double>(), k, seg1(AW, k), -1.0, 1.0));  // q = P q
+                ST(tic());
+                HC(launch_col_dots(st, n, k, Pn, AW, ld, part, dq));
+                HC(launch_cg_step(st, n, k, rr, dq, Pn, AW, P, W, ld, s == 0, part, rr_new));
+                ST(toc(SE_K_RESID, 56.0 * n * k, 8.0 * n * k));
+                if (s + 1 < steps) {
+                    ST(tic());
+                    HC(launch_cg_dir(st, n, k, rr_new, rr, W, Pn, ld));
+                    ST(toc(SE_K_RESID, 24.0 * n * k, 2.0 * n * k));
+                }
+                std::swap(rr, rr_new);
+            }
+            // X <- X - D
+            ST(tic());
+            HC(launch_cheb_step(st, n, k, -1.0, P, 0.0, P, 1.0, X, ld));
+            ST(toc(SE_K_RESID, 24.0 * n * k, 2.0 * n * k));
+            if (ctl.ifexpand(j) && have_drop) {
+                if (p.expand_vectors == SE_EXPAND_RANDOM)
+                    HC(launch_gaussian_cols(st, n, dx, nb, n_exp + 1, (unsigned long long)p.seed, X, ld, k));
+                else
+                    HC(launch_copy_cols(st, n, Sd, ld, 0, X, ld, k, dx));
+                k += dx;
+                have_drop = false;
+                ctl.did_expand(j);
+                ++n_exp;
+                flags |= 1;
+            }
+            ST(cholqr(X, k, nullptr, nullptr));
+            if (k < n_ev) return SE_ERR_BREAKDOWN;
+            ST(spmm(X, AX, k));
+            ST(rr_plain(k));
+            if (ctl.ifshrink(j)) {
+                dx = k - n_es;
+                if (p.expand_vectors != SE_EXPAND_RANDOM)
+                    HC(launch_copy_cols(st, n, X, ld, n_es, Sd, ld, 0, dx));
+                k = n_es;
+                have_drop = true;
+                ctl.did_shrink(j);
+                ++n_shr;
+                flags |= 2;
+            }
+            amend_flags(flags);
+        }
+        return SE_OK;
+    }
+
     // ----------------------------------------------------- mixed precision --
     // The low-precision phase keeps every n-length block in FP32 or BF16
     // panels and does its arithmetic in FP32 with FP64 reductions; all small
@@ -1537,12 +1639,13 @@ hipError_t make_val32(hipStream_t st, const se_matrix* A) {
 
 size_t solve_workspace_bytes(long long n, long long nnz, int nb, int precision, int solver) {
     const long long ld = round_up(nb, 8);
-    const int mmax = solver == SE_SI ? nb : 3 * nb;
+    const int mmax = (solver == SE_SI || solver == SE_TRACEMIN) ? nb : 3 * nb;
     const size_t mm = (size_t)mmax * mmax;
     size_t bytes = sizeof(double) * (size_t)kNumPanels * n * ld;
     size_t small = 4 * mm + (mmax + 8) + (2 * mm + 8 * (size_t)mmax + 64) + syev_work_doubles(mmax) +
                    std::max(gram_scratch_doubles(n, mmax, mmax), (size_t)4096 * 2 * mmax) + 4 * mm +
-                   3 * (2 * (size_t)mmax + 16) + 6 * mm + (size_t)mmax + 8 + 6 * mm;
+                   3 * (2 * (size_t)mmax + 16) + 6 * mm + (size_t)mmax + 8 + 6 * mm +
+                   (solver == SE_TRACEMIN ? 3 * (size_t)mmax + 8 : 0);
     if (precision != SE_FP64) {
         const size_t es = precision == SE_FP32_MIXED ? 4 : 2;
         bytes += es * (size_t)kNumLpPanels * n * ld + sizeof(float) * ((size_t)nnz + kCsrPad);
@@ -1581,7 +1684,7 @@ se_status solve(se_ctx* ctx, const se_matrix* A, const se_params* prm, const dou
     else if (prm->precision == SE_BF16_MIXED)
         st = s.mixed<bf16_t>(X0);
     else
-        st = (prm->solver == SE_SI) ? s.si(X0) : s.lobpcg(X0);
+        st = (prm->solver == SE_SI) ? s.si(X0) : (prm->solver == SE_TRACEMIN) ? s.tracemin(X0) : s.lobpcg(X0);
     if (st >= 0) st = s.finish(V, lambda, info);
     s.summarize(info);
     (void)hipEventRecord(e1, ctx->stream);

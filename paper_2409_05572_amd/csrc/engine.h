@@ -71,6 +71,7 @@ struct Workspace {
     DevBuf lpM, lpT, lpQ, lpB, lpE, lpC;  // generalized Rayleigh-Ritz (m x m each)
     DevBuf apc, axp, axq, gw, idx;        // carried [X, P]^T A [X, P] (m x m each; idx ints)
     DevBuf wfold, cfold;                  // last Cholesky-QR transform of W, folded coefficients
+    DevBuf cg;                            // TraceMIN inner CG: per-column rr, rr_new, d^T q
     HostBuf h_norms, h_info, h_act, h_act_hl, h_theta, h_diag;
     std::vector<hipEvent_t> events;  // pool for per-launch timing
     size_t device_bytes() const {
@@ -80,7 +81,7 @@ struct Workspace {
         const DevBuf* all[] = {&gram_part, &G, &T, &Z, &theta, &C, &small_work, &syev_work,
                                &lam, &act, &act_hl, &norms, &info, &hlB, &hlY, &hlG, &hlQ,
                                &lpM, &lpT, &lpQ, &lpB, &lpE, &lpC, &apc, &axp, &axq, &gw, &idx,
-                               &wfold, &cfold};
+                               &wfold, &cfold, &cg};
         for (auto* b : all) s += b->bytes;
         return s;
     }
@@ -90,7 +91,7 @@ struct Workspace {
         DevBuf* all[] = {&gram_part, &G, &T, &Z, &theta, &C, &small_work, &syev_work,
                          &lam, &act, &act_hl, &norms, &info, &hlB, &hlY, &hlG, &hlQ,
                          &lpM, &lpT, &lpQ, &lpB, &lpE, &lpC, &apc, &axp, &axq, &gw, &idx,
-                         &wfold, &cfold};
+                         &wfold, &cfold, &cg};
         for (auto* b : all) b->release();
         h_norms.release();
         h_info.release();
@@ -146,7 +147,8 @@ struct se_ctx {
 };
 
 struct se_matrix {
-    se_ctx* ctx = nullptr;
+    se_ctx* ctx = nullptr;  // identity only: never dereferenced after creation
+    int device = 0;         // the creating context's device (destroy does not need the context)
     int64_t n = 0, nnz = 0;
     int* rowptr = nullptr;  // int32 offsets on the device
     int* col = nullptr;

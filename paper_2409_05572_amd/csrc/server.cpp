@@ -100,6 +100,7 @@ struct se_server {
             if (!r) return;  // stop with nothing assigned
             lk.unlock();
             std::memset(&r->info, 0, sizeof(r->info));
+            (void)hipGetLastError();  // a stale error of this thread must not fail the solve
             const se_status st = se::solve(slots[i].ctx, r->A, &r->p, r->X0, r->V, r->lambda, &r->info);
             const uint64_t held = slots[i].ctx->ws.device_bytes();
             lk.lock();

@@ -287,3 +287,18 @@ def test_full_config2_lobpcg_shrink_expand(ctx):
     r = _residual_ratio(A, lam[cols], V[:, cols])
     assert np.max(r) <= 1e-8 * 1.0001
     assert np.abs(V.T @ V - np.eye(64)).max() <= 1e-11
+
+
+def test_matrix_released_after_its_context(ctx):
+    """Finalizers can run in any order (a garbage cycle holding both): a
+    matrix destroyed after its context must release cleanly and leave no HIP
+    error behind for the next solve on another context."""
+    from paper_2409_05572_amd import api
+
+    other = api.Context(0)
+    A = W.laplacian_2d(8)
+    M = api.Matrix.from_csr(other, A)
+    other.close()
+    M.close()
+    lam, V, info = _gpu_solve(ctx, A, W.gaussian_block(A.n, 8, 1), 4, 4)
+    assert info.converged and info.status == 0
