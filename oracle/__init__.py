@@ -41,5 +41,6 @@ from .solvers import (  # noqa: F401
     subspace_iteration,
     projected_cg,
     tracemin,
+    jacobi_preconditioner,
 )
 from . import mixed  # noqa: F401,E402

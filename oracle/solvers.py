@@ -97,9 +97,10 @@ def orth(Y, drop_tol=1e-12):
     if k == 0:
         return Y.copy(), np.zeros(0, dtype=np.int64)
     norms = np.linalg.norm(Y, axis=0)
-    Q, R = np.linalg.qr(Y, mode="reduced")
-    if np.all(np.abs(np.diag(R)) > drop_tol * norms) and np.all(norms > 0):
-        return Q, np.arange(k)
+    if k <= Y.shape[0]:  # a wider block has dependent columns: no fast path
+        Q, R = np.linalg.qr(Y, mode="reduced")
+        if np.all(np.abs(np.diag(R)) > drop_tol * norms) and np.all(norms > 0):
+            return Q, np.arange(k)
     basis = []
     kept = []
     for i in range(k):
@@ -186,6 +187,14 @@ def _expansion_source(expand_vectors, random_block, powered_ok):
     return expand_vectors
 
 
+def jacobi_preconditioner(A):
+    """T = diag(1 / |a_ii|) (1 where a_ii = 0): a symmetric positive definite
+    diagonal preconditioner for the W <- T R step of Algorithms 2 and 3."""
+    d = np.asarray(A.diagonal(), dtype=np.float64)
+    t = np.where(d != 0.0, 1.0 / np.where(d != 0.0, np.abs(d), 1.0), 1.0)
+    return lambda R: t[:, None] * R  # noqa: E731
+
+
 def _se_enabled(params: SEParams, n_ev: int, n_es, nb: int) -> bool:
     return params.strategy != "none" and n_es is not None and n_ev <= n_es < nb
 
@@ -205,11 +214,14 @@ def lobpcg(
     P0=None,
     expand_vectors="xdrop",
     random_block=None,
+    precond=None,
 ):
     """LOBPCG with soft locking, HL basis and shrink-and-expand (Algorithm 3).
 
     ``P0``: search directions to continue with (e.g. after a low-precision
-    phase); they are orthogonalized against the starting X.
+    phase); they are orthogonalized against the starting X. ``precond``: the
+    preconditioner T of W <- T R as a function of the residual block (None is
+    T = I, the paper's experiments).
     """
     _expansion_source(expand_vectors, random_block, False)
     se = se or SEParams()
@@ -254,9 +266,9 @@ def lobpcg(
         active = np.flatnonzero(~locked)
         expand = ctl.ifexpand(j)
 
-        # W <- T R with T = I, restricted to the active columns; orthogonalize
-        # against [X, P] (projection applied twice) and orthonormalize.
-        W = R[:, active]
+        # W <- T R, restricted to the active columns; orthogonalize against
+        # [X, P] (projection applied twice) and orthonormalize.
+        W = R[:, active] if precond is None else precond(R[:, active])
         XP = np.hstack([X, P])
         for _ in range(2):
             W = W - XP @ (XP.T @ W)
@@ -322,9 +334,11 @@ def steepest_descent(
     time_limit_s=None,
     expand_vectors="xdrop",
     random_block=None,
+    precond=None,
 ):
-    """Block steepest descent with shrink-and-expand (Algorithm 2, Section 2.2),
-    T = I: X_new is the Ritz basis of span{X, R} for the current width.
+    """Block steepest descent with shrink-and-expand (Algorithm 2, Section 2.2):
+    X_new is the Ritz basis of span{X, T R} for the current width (T = I unless
+    ``precond`` gives it as a function of the residual block).
 
     Readings: soft locking as in LOBPCG (locked pairs leave W); at an
     expansion X_drop is orthogonalized against X and orthonormalized before it
@@ -379,7 +393,7 @@ def steepest_descent(
             rec["expand"] = True
 
         # W <- T R (active columns); W <- W - X (X^T W), orthonormalized
-        W = R[:, active]
+        W = R[:, active] if precond is None else precond(R[:, active])
         for _ in range(2):
             W = W - X @ (X.T @ W)
         W, _ = orth(W, drop_tol)

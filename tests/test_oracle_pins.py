@@ -449,3 +449,49 @@ def test_tracemin_brute_force_random_sparse_spd(seed):
     exact = np.sort(np.linalg.eigvalsh(A.to_scipy().toarray()))[:6]
     assert res.converged
     np.testing.assert_allclose(res.lam, exact, rtol=1e-10)
+
+
+# --- Preconditioned LOBPCG / SD (W <- T R, Algorithms 2 and 3) -----------------------------
+
+def _scaled_laplacian(m=24, seed=3):
+    """D^1/2 L D^1/2 with log-uniform D over e^[-2, 2]: badly scaled, SPD."""
+    L = W.laplacian_2d(m).to_scipy()
+    d = np.exp(np.random.default_rng(seed).uniform(-2.0, 2.0, L.shape[0]))
+    S = (sp.diags(np.sqrt(d)) @ L @ sp.diags(np.sqrt(d))).tocsr()
+    return S, float(abs(S).sum(axis=1).max())
+
+
+def test_orth_of_a_wide_block_keeps_a_basis():
+    Y = np.random.default_rng(0).standard_normal((5, 8))
+    Q, kept = O.orth(Y)
+    assert Q.shape == (5, 5) and list(kept) == [0, 1, 2, 3, 4]
+    assert np.abs(Q.T @ Q - np.eye(5)).max() < 1e-14
+
+
+@pytest.mark.parametrize("solver", ["lobpcg", "sd"])
+def test_jacobi_preconditioning_speeds_up_a_badly_scaled_problem(solver):
+    """With T = diag(A)^-1 on D^1/2 L D^1/2 the iteration needs far fewer
+    steps and still reaches the brute-force spectrum."""
+    S, anorm = _scaled_laplacian()
+    f = O.lobpcg if solver == "lobpcg" else O.steepest_descent
+    X0 = W.gaussian_block(S.shape[0], 12, 5)
+    exact = np.sort(np.linalg.eigvalsh(S.toarray()))[:6]
+    plain = f(S, X0, 6, anorm, tol=1e-8, n_es=8, se=O.SEParams("fix"), max_iter=3000)
+    pre = f(S, X0, 6, anorm, tol=1e-8, n_es=8, se=O.SEParams("fix"), max_iter=3000,
+            precond=O.jacobi_preconditioner(S))
+    assert pre.converged
+    np.testing.assert_allclose(pre.lam, exact, rtol=1e-10)
+    assert 2 * pre.iterations < plain.iterations
+
+
+def test_scalar_preconditioner_leaves_lobpcg_unchanged():
+    """T = c I changes no subspace: the residual history is that of T = I."""
+    A = W.laplacian_2d(16)
+    X0 = W.gaussian_block(A.n, 12, 4)
+    a = O.lobpcg(A.to_scipy(), X0, 6, A.anorm, tol=1e-8, n_es=8, se=O.SEParams("fix"))
+    b = O.lobpcg(A.to_scipy(), X0, 6, A.anorm, tol=1e-8, n_es=8, se=O.SEParams("fix"),
+                 precond=O.jacobi_preconditioner(A.to_scipy()))  # the diagonal is 4 everywhere
+    ra = np.array([h["r"] for h in a.history])
+    rb = np.array([h["r"] for h in b.history])
+    assert len(ra) == len(rb)
+    np.testing.assert_allclose(ra, rb, rtol=1e-6)
