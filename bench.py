@@ -50,6 +50,8 @@ def parse():
     ap.add_argument("--max-iter", type=int, default=None)
     ap.add_argument("--expand-vectors", default="xdrop", choices=["xdrop", "random", "powered"],
                     help="vectors appended at an expansion (powered: subspace iteration only)")
+    ap.add_argument("--precond", default="none", choices=["none", "jacobi"],
+                    help="LOBPCG / SD preconditioner T of W <- T R")
     ap.add_argument("--filter-degree", type=int, default=0,
                     help="subspace iteration: Chebyshev filter degree (0 = shifted power step)")
     ap.add_argument("--strategy", default="fix")
@@ -121,7 +123,8 @@ def main():
     torch.cuda.synchronize()
 
     extra = {} if args.max_iter is None else {"max_iter": args.max_iter}
-    extra.update(expand_vectors=args.expand_vectors, seed=args.x0_seed, filter_degree=args.filter_degree)
+    extra.update(expand_vectors=args.expand_vectors, seed=args.x0_seed, filter_degree=args.filter_degree,
+                 precond=args.precond)
 
     def run(strategy, profile=0):
         return api.solve(ctx, M, X0d, args.n_ev, args.n_extra, strategy=strategy, tol=1e-8,
@@ -158,7 +161,8 @@ def main():
             "workload": f"{wname} {args.solver.upper()} n_ev={args.n_ev} n_extra={args.n_extra} "
                         f"strategy={args.strategy} precision={args.precision} tol=1e-8"
                         + ("" if args.expand_vectors == "xdrop" else f" expand={args.expand_vectors}")
-                        + (f" filter_degree={args.filter_degree}" if args.filter_degree else ""),
+                        + (f" filter_degree={args.filter_degree}" if args.filter_degree else "")
+                        + (f" precond={args.precond}" if args.precond != "none" else ""),
             "n": A.n, "nnz": A.nnz, "n_ev": args.n_ev, "block": nb,
         },
         "shrink_expand": {
@@ -301,7 +305,9 @@ def cpu_baseline(A, X0, args, gpu_iters, log):
     res = solver(A.to_scipy(), X0, args.n_ev, A.anorm, tol=1e-8,
                  n_es=args.n_ev + min(5, args.n_extra - 1), se=O.SEParams(args.strategy),
                  time_limit_s=args.cpu_seconds, expand_vectors=args.expand_vectors, random_block=draw,
-                 **({"filter_degree": args.filter_degree} if args.solver == "si" else {}))
+                 **({"filter_degree": args.filter_degree} if args.solver == "si" else {}),
+                 **({"precond": O.jacobi_preconditioner(A.to_scipy())}
+                    if args.precond == "jacobi" else {}))
     el = time.perf_counter() - t
     done = max(res.iterations - 1, 1)  # the last recorded iteration stopped at its check
     per_iter = el / done

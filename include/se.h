@@ -66,6 +66,11 @@ typedef struct se_matrix se_matrix;
                                without orthogonalization, divided by sigma - theta_1
                                (theta_1 the smallest current Ritz value) */
 
+/* Preconditioner T of W <- T R (Algorithms 2 and 3; LOBPCG and SD, FP64). */
+#define SE_PRECOND_NONE 0   /* T = I (the paper's experiments) */
+#define SE_PRECOND_JACOBI 1 /* T = diag(1 / |a_ii|) (1 where a_ii = 0); W is then projected
+                               against [X, P] twice before it is orthonormalized */
+
 /* Shrink-and-expand strategies (Section 3.2). */
 #define SE_STRAT_NONE 0
 #define SE_STRAT_FIX 1    /* Algorithm 6 */
@@ -142,6 +147,8 @@ typedef struct se_params {
                                iteration. A powered X_drop takes the same filter. Falls back
                                to the shifted step at an iteration where sigma <= theta_k. */
     int32_t cg_steps;       /* SE_TRACEMIN: inner CG steps per iteration (0 = 5, the paper's) */
+    int32_t precond;        /* SE_PRECOND_NONE (default) or SE_PRECOND_JACOBI */
+    int32_t reserved;       /* must be 0 */
 } se_params;
 
 typedef struct se_info {

@@ -20,6 +20,7 @@ SE_LOBPCG, SE_SI, SE_SD, SE_TRACEMIN = 0, 1, 2, 3
 SOLVERS = {"lobpcg": SE_LOBPCG, "si": SE_SI, "sd": SE_SD, "tracemin": SE_TRACEMIN}
 STRATEGIES = {"none": 0, "fix": 1, "slope": 2, "slopek": 3}
 EXPAND_VECTORS = {"xdrop": 0, "random": 1, "powered": 2}
+PRECONDS = {"none": 0, "jacobi": 1}
 SE_FP64 = 0
 SE_FP32_MIXED = 1
 SE_BF16_MIXED = 2
@@ -41,6 +42,7 @@ class SeParams(C.Structure):
         ("seed", C.c_uint64),
         ("history", C.POINTER(C.c_double)), ("history_cap", C.c_int32),
         ("expand_vectors", C.c_int32), ("filter_degree", C.c_int32), ("cg_steps", C.c_int32),
+        ("precond", C.c_int32), ("reserved", C.c_int32),
     ]
 
 

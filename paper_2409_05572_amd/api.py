@@ -120,13 +120,14 @@ PRECISIONS = {"fp64": _lib.SE_FP64, "fp32": _lib.SE_FP32_MIXED, "bf16": _lib.SE_
 
 def params(n_ev, n_extra, solver="lobpcg", strategy="none", tol=1e-8, n_es=0, max_iter=None,
            soft_lock=True, sigma=0.0, time_limit_s=0.0, precision="fp64", r_switch=0.0,
-           implicit_pivot=0.0, expand_vectors="xdrop", filter_degree=0,
+           implicit_pivot=0.0, expand_vectors="xdrop", filter_degree=0, precond="none",
            **strategy_params) -> SeParams:
     p = SeParams()
     lib().se_params_default(C.byref(p))
     p.solver = _lib.SOLVERS[solver]
     p.expand_vectors = _lib.EXPAND_VECTORS[expand_vectors]
     p.filter_degree = int(filter_degree)
+    p.precond = _lib.PRECONDS[precond]
     p.precision = PRECISIONS[precision]
     p.r_switch = float(r_switch)
     p.implicit_pivot = float(implicit_pivot)

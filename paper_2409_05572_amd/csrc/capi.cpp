@@ -78,6 +78,10 @@ se_status validate_solve(const se_matrix* A, const se_params* p) {
     if (p->filter_degree < 0 || p->filter_degree > 64) return SE_ERR_INVALID_ARG;
     if (p->filter_degree > 0 && p->solver != SE_SI) return SE_ERR_INVALID_ARG;
     if (p->filter_degree > 0 && p->precision != SE_FP64) return SE_ERR_UNSUPPORTED;
+    if (p->precond != SE_PRECOND_NONE && p->precond != SE_PRECOND_JACOBI) return SE_ERR_INVALID_ARG;
+    if (p->precond != SE_PRECOND_NONE && p->solver != SE_LOBPCG && p->solver != SE_SD) return SE_ERR_INVALID_ARG;
+    if (p->precond != SE_PRECOND_NONE && p->precision != SE_FP64) return SE_ERR_UNSUPPORTED;
+    if (p->reserved != 0) return SE_ERR_INVALID_ARG;
     return SE_OK;
 }
 }  // namespace se

@@ -108,6 +108,11 @@ hipError_t launch_spmm_resid(hipStream_t st, int n, const int* rowptr, const int
 hipError_t launch_seeded_block(hipStream_t st, long long n, int nb, unsigned long long seed, double* X,
                                long long ld, bool col_major);
 
+// Jacobi preconditioner: dinv[r] = 1 / |a_rr| (1 for a missing or zero
+// diagonal); W[r, c] *= dinv[r] for c < a (ld even).
+hipError_t launch_jacobi(hipStream_t st, int n, const int* rowptr, const int* col, const double* val, double* dinv);
+hipError_t launch_row_scale(hipStream_t st, long long n, int a, const double* dinv, double* W, long long ld);
+
 // Column-wise CG for TraceMIN's inner solve (per-column scalars on the device):
 // out[c] = U[:, c] . V[:, c];
 // D += alpha d (D = alpha d when first), R -= alpha Q, rr_new[c] = R[:, c] . R[:, c],

@@ -577,6 +577,10 @@ struct Solver {
     se_status lobpcg(const double* X0, int k0 = -1, int p0 = 0) {
         ST(alloc_panels(14));
         ST(alloc_small(3 * nb));
+        if (p.precond == SE_PRECOND_JACOBI) {
+            HC(ws.pc.ensure(sizeof(double) * (size_t)n));
+            HC(launch_jacobi(st, (int)n, A->rowptr, A->col, A->val, ws.pc.as<double>()));
+        }
         if (k0 < 0) ST(load_x0(X0));
         int k = k0 < 0 ? nb : k0;
         ST(cholqr(X, k, nullptr, nullptr));
@@ -635,8 +639,8 @@ struct Solver {
             const bool want_expand = ctl.ifexpand(j);
             int flags = 0;
 
-            // W <- R(:, active) (T = I): R is already in W; locked columns
-            // are gathered out.
+            // W <- T R(:, active): R is already in W; locked columns are
+            // gathered out, then the rows are scaled by T (Jacobi).
             int a = (int)act.size();
             if (a < k) {
                 std::memcpy(ws.h_act.p, act.data(), sizeof(int) * a);
@@ -645,6 +649,12 @@ struct Solver {
                 HC(launch_gather_cols(st, n, W, ld, ws.act.as<int>(), a, T1, ld));
                 ST(toc(SE_K_RESID, 16.0 * n * a, 0.0));
                 std::swap(W, T1);
+            }
+            const bool precond = p.precond == SE_PRECOND_JACOBI;
+            if (precond && a > 0) {
+                ST(tic());
+                HC(launch_row_scale(st, n, a, ws.pc.as<double>(), W, ld));
+                ST(toc(SE_K_RESID, 16.0 * n * a + 8.0 * n, 1.0 * n * a));
             }
             // By the Galerkin condition of the last Rayleigh-Ritz step R is
             // orthogonal to [X, P] up to rounding, so one projection usually
@@ -704,7 +714,14 @@ struct Solver {
                 std::vector<double> wn2(a);
                 for (int q = 0; q < a; ++q) wn2[q] = nr[act[q]];
                 bool again = false;
-                ST(cholqr(W, a, nullptr, nullptr, &XP, nullptr, wn2.data(), &again, fold_T, &folded));
+                if (precond) {
+                    // T R is not orthogonal to [X, P]: project a second time
+                    // (the residual norms are not those of T R)
+                    ST(gram(XP, seg1(W, a), 0, ws.G.as<double>()));
+                    ST(update(XP, ws.G.as<double>(), a, seg1(W, a), -1.0, 1.0));
+                }
+                ST(cholqr(W, a, nullptr, nullptr, &XP, nullptr, precond ? nullptr : wn2.data(),
+                          precond ? nullptr : &again, fold_T, &folded));
                 if (again) {
                     ++n_reproj;
                     ST(gram(XP, seg1(W, a), 0, ws.G.as<double>()));
@@ -1645,7 +1662,8 @@ size_t solve_workspace_bytes(long long n, long long nnz, int nb, int precision, 
     size_t small = 4 * mm + (mmax + 8) + (2 * mm + 8 * (size_t)mmax + 64) + syev_work_doubles(mmax) +
                    std::max(gram_scratch_doubles(n, mmax, mmax), (size_t)4096 * 2 * mmax) + 4 * mm +
                    3 * (2 * (size_t)mmax + 16) + 6 * mm + (size_t)mmax + 8 + 6 * mm +
-                   (solver == SE_TRACEMIN ? 3 * (size_t)mmax + 8 : 0);
+                   (solver == SE_TRACEMIN ? 3 * (size_t)mmax + 8 : 0) +
+                   (solver == SE_LOBPCG || solver == SE_SD ? (size_t)n : 0);  // Jacobi diagonal
     if (precision != SE_FP64) {
         const size_t es = precision == SE_FP32_MIXED ? 4 : 2;
         bytes += es * (size_t)kNumLpPanels * n * ld + sizeof(float) * ((size_t)nnz + kCsrPad);

@@ -72,6 +72,7 @@ struct Workspace {
     DevBuf apc, axp, axq, gw, idx;        // carried [X, P]^T A [X, P] (m x m each; idx ints)
     DevBuf wfold, cfold;                  // last Cholesky-QR transform of W, folded coefficients
     DevBuf cg;                            // TraceMIN inner CG: per-column rr, rr_new, d^T q
+    DevBuf pc;                            // Jacobi preconditioner diag(1 / |a_ii|) (n doubles)
     HostBuf h_norms, h_info, h_act, h_act_hl, h_theta, h_diag;
     std::vector<hipEvent_t> events;  // pool for per-launch timing
     size_t device_bytes() const {
@@ -81,7 +82,7 @@ struct Workspace {
         const DevBuf* all[] = {&gram_part, &G, &T, &Z, &theta, &C, &small_work, &syev_work,
                                &lam, &act, &act_hl, &norms, &info, &hlB, &hlY, &hlG, &hlQ,
                                &lpM, &lpT, &lpQ, &lpB, &lpE, &lpC, &apc, &axp, &axq, &gw, &idx,
-                               &wfold, &cfold, &cg};
+                               &wfold, &cfold, &cg, &pc};
         for (auto* b : all) s += b->bytes;
         return s;
     }
@@ -91,7 +92,7 @@ struct Workspace {
         DevBuf* all[] = {&gram_part, &G, &T, &Z, &theta, &C, &small_work, &syev_work,
                          &lam, &act, &act_hl, &norms, &info, &hlB, &hlY, &hlG, &hlQ,
                          &lpM, &lpT, &lpQ, &lpB, &lpE, &lpC, &apc, &axp, &axq, &gw, &idx,
-                         &wfold, &cfold, &cg};
+                         &wfold, &cfold, &cg, &pc};
         for (auto* b : all) b->release();
         h_norms.release();
         h_info.release();

@@ -33,7 +33,7 @@ def test_params_defaults_are_the_papers():
     assert (p.j_e, p.j_s, p.j_p, p.j_warm) == (12, 2, 10, 5)
     assert p.mu == pytest.approx(1.1) and p.r_warm == pytest.approx(1e-4)
     assert p.tol == pytest.approx(1e-8) and p.soft_lock == 1 and p.max_iter == 1000
-    assert ctypes.sizeof(_lib.SeParams) == 14 * 4 + 7 * 8 + 8 + 8 + 8 + 8
+    assert ctypes.sizeof(_lib.SeParams) == 14 * 4 + 7 * 8 + 8 + 8 + 8 + 8 + 8
     assert ctypes.sizeof(_lib.SeInfo) == 4 * 4 + 3 * 8 + 3 * 8 * 8 + 8 * 4 + 8 + 8 + 8
 
 
