@@ -129,3 +129,107 @@ def test_slope_sign_error_is_caught(monkeypatch):
         if ctl.ifshrink(j):
             ctl.did_shrink(j)
     assert exp != [13]
+
+
+# --- Chebyshev filter, TraceMIN's inner CG, Jacobi preconditioner -------------------------
+
+def _cheb_pin_failures(filt):
+    """The diagonal closed form of T_d (as in the oracle pins) against `filt`."""
+    import scipy.sparse as sp
+
+    rng = np.random.default_rng(5)
+    a = np.sort(rng.uniform(0.0, 8.0, 40))
+    A = sp.diags(a).tocsr()
+    Y = rng.standard_normal((40, 3))
+    lower, cut, upper, d = a[0], a[8], 8.0, 5
+    c, e = 0.5 * (upper + cut), 0.5 * (upper - cut)
+
+    def T(x):
+        x = np.asarray(x, dtype=np.float64)
+        return np.where(np.abs(x) <= 1, np.cos(d * np.arccos(np.clip(x, -1, 1))),
+                        np.sign(x) ** d * np.cosh(d * np.arccosh(np.maximum(np.abs(x), 1))))
+
+    rho = T((a - c) / e) / T((lower - c) / e)
+    return not np.allclose(filt(A, Y, d, lower, cut, upper), rho[:, None] * Y, rtol=1e-10, atol=1e-12)
+
+
+def test_unmutated_chebyshev_filter_passes():
+    assert not _cheb_pin_failures(O.chebyshev_filter)
+
+
+@pytest.mark.parametrize("mistake", ["centre", "normalization", "recurrence_sign"])
+def test_chebyshev_filter_mistakes_are_caught(mistake):
+    def bad(A, Y, degree, lower, cut, upper):
+        c = 0.5 * (upper + cut) if mistake != "centre" else 0.5 * (upper - cut)
+        e = 0.5 * (upper - cut)
+        L = lambda Z: (A @ Z - c * Z) / e  # noqa: E731
+        l0 = (lower - c) / e
+        T_prev, T_ = Y, L(Y)
+        t_prev, t = 1.0, l0
+        sgn = -1.0 if mistake == "recurrence_sign" else 1.0
+        for _ in range(2, degree + 1):
+            T_prev, T_ = T_, 2.0 * L(T_) - sgn * T_prev
+            t_prev, t = t, 2.0 * l0 * t - sgn * t_prev
+        return T_ if mistake == "normalization" else T_ / t
+
+    assert _cheb_pin_failures(bad)
+
+
+def _projected_cg_pin_failures(cg):
+    import scipy.sparse as sp
+
+    rng = np.random.default_rng(3)
+    n = 30
+    M = rng.standard_normal((n, n))
+    A = M @ M.T + n * np.eye(n)
+    X, _ = np.linalg.qr(rng.standard_normal((n, 3)))
+    B = rng.standard_normal((n, 4))
+    D = cg(sp.csr_matrix(A), X, B, n)
+    Qf, _ = np.linalg.qr(np.hstack([X, rng.standard_normal((n, n - 3))]))
+    Q = Qf[:, 3:]
+    ref = Q @ np.linalg.solve(Q.T @ A @ Q, Q.T @ B)
+    return not (np.allclose(D, ref, rtol=1e-8, atol=1e-10) and np.abs(X.T @ D).max() < 1e-10)
+
+
+def test_unmutated_projected_cg_passes():
+    assert not _projected_cg_pin_failures(O.projected_cg)
+
+
+@pytest.mark.parametrize("mistake", ["no_projection", "no_conjugation"])
+def test_projected_cg_mistakes_are_caught(mistake):
+    def bad(A, X, B, steps):
+        P = lambda Z: Z - X @ (X.T @ Z)  # noqa: E731
+        r = P(B)
+        d = r.copy()
+        D = np.zeros_like(B)
+        rr = np.einsum("ij,ij->j", r, r)
+        for _ in range(steps):
+            q = A @ d if mistake == "no_projection" else P(A @ d)
+            dq = np.einsum("ij,ij->j", d, q)
+            alpha = np.where(dq > 0, rr / np.where(dq > 0, dq, 1.0), 0.0)
+            D = D + d * alpha
+            r = r - q * alpha
+            rr_new = np.einsum("ij,ij->j", r, r)
+            beta = 0.0 if mistake == "no_conjugation" else rr_new / np.where(rr > 0, rr, 1.0)
+            d = r + d * beta
+            rr = rr_new
+        return D
+
+    assert _projected_cg_pin_failures(bad)
+
+
+def test_inverted_jacobi_preconditioner_is_caught(monkeypatch):
+    """T = diag(|a_ii|) instead of its inverse no longer pays on the badly
+    scaled Laplacian (the preconditioning pin's speed-up fails)."""
+    import scipy.sparse as sp
+
+    L = W.laplacian_2d(24).to_scipy()
+    d = np.exp(np.random.default_rng(3).uniform(-2.0, 2.0, L.shape[0]))
+    S = (sp.diags(np.sqrt(d)) @ L @ sp.diags(np.sqrt(d))).tocsr()
+    anorm = float(abs(S).sum(axis=1).max())
+    X0 = W.gaussian_block(S.shape[0], 12, 5)
+    plain = O.lobpcg(S, X0, 6, anorm, tol=1e-8, n_es=8, se=O.SEParams("fix"), max_iter=600)
+    diag = np.abs(S.diagonal())
+    bad = O.lobpcg(S, X0, 6, anorm, tol=1e-8, n_es=8, se=O.SEParams("fix"), max_iter=600,
+                   precond=lambda R: diag[:, None] * R)
+    assert not (bad.converged and 2 * bad.iterations < plain.iterations)
