@@ -51,7 +51,7 @@ typedef struct se_matrix se_matrix;
                        and expansion as in LOBPCG (X_drop orthonormalized against S) */
 #define SE_TRACEMIN 3 /* Algorithm 4 (TraceMIN): X <- X - D with D from params.cg_steps
                          conjugate-gradient steps on P A P D = P R, P = I - X X^T, per column;
-                         FP64; A must be positive definite */
+                         FP64, block <= 512; A must be positive definite */
 
 /* Vectors appended at an expansion (Section 6, the vectors appended in the
  * expansion). FP64 only (SE_ERR_UNSUPPORTED with a mixed precision). */

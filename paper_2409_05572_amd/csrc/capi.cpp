@@ -65,6 +65,7 @@ se_status validate_solve(const se_matrix* A, const se_params* p) {
     const bool single_block = p->solver == SE_SI || p->solver == SE_TRACEMIN;  // m = nb
     if (!single_block && nb > 341) return SE_ERR_UNSUPPORTED;  // 3 nb <= 1024
     if (single_block && nb > 1024) return SE_ERR_UNSUPPORTED;
+    if (p->solver == SE_TRACEMIN && nb > 512) return SE_ERR_UNSUPPORTED;  // column CG kernels
     if (p->n_es != 0 && (p->n_es < p->n_ev || p->n_es > nb)) return SE_ERR_INVALID_ARG;
     if (!(p->tol > 0.0) || p->max_iter < 1) return SE_ERR_INVALID_ARG;
     if (p->strategy != SE_STRAT_NONE &&
