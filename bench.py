@@ -50,6 +50,8 @@ def parse():
     ap.add_argument("--max-iter", type=int, default=None)
     ap.add_argument("--expand-vectors", default="xdrop", choices=["xdrop", "random", "powered"],
                     help="vectors appended at an expansion (powered: subspace iteration only)")
+    ap.add_argument("--host-io", action="store_true",
+                    help="pass X0, V and lambda as host pointers (PCIe copies inside the timed solves)")
     ap.add_argument("--precond", default="none", choices=["none", "jacobi"],
                     help="LOBPCG / SD preconditioner T of W <- T R")
     ap.add_argument("--filter-degree", type=int, default=0,
@@ -119,7 +121,9 @@ def main():
 
     ctx = api.Context(0)
     M = api.Matrix.from_csr(ctx, A)
-    X0d = torch.from_numpy(np.ascontiguousarray(X0.T)).cuda()
+    # device X0 (n x nb column-major = a contiguous nb x n tensor), or the host
+    # array itself with --host-io
+    X0d = X0 if args.host_io else torch.from_numpy(np.ascontiguousarray(X0.T)).cuda()
     torch.cuda.synchronize()
 
     extra = {} if args.max_iter is None else {"max_iter": args.max_iter}
@@ -162,7 +166,8 @@ def main():
                         f"strategy={args.strategy} precision={args.precision} tol=1e-8"
                         + ("" if args.expand_vectors == "xdrop" else f" expand={args.expand_vectors}")
                         + (f" filter_degree={args.filter_degree}" if args.filter_degree else "")
-                        + (f" precond={args.precond}" if args.precond != "none" else ""),
+                        + (f" precond={args.precond}" if args.precond != "none" else "")
+                        + (" host_io" if args.host_io else ""),
             "n": A.n, "nnz": A.nnz, "n_ev": args.n_ev, "block": nb,
         },
         "shrink_expand": {
@@ -173,7 +178,7 @@ def main():
             "implicit_orthonormalizations": int(((infos[-1].history[:, 7].astype(int) & 8) != 0).sum()),
         },
     }
-    lam_np = lam.cpu().numpy()
+    lam_np = lam.cpu().numpy() if hasattr(lam, "cpu") else np.asarray(lam)
     out["parity"] = {"max_stop_ratio": infos[-1].max_stop_ratio}
     if args.workload == "laplace3d":
         m = args.grid

@@ -103,3 +103,16 @@ def test_filter_options_are_validated(ctx):
         api.solve(ctx, M, X0, 4, 4, solver="si", filter_degree=65)
     with pytest.raises(SeError, match="unsupported"):
         api.solve(ctx, M, X0, 4, 4, solver="si", filter_degree=4, precision="fp32")
+
+
+def test_filter_of_the_largest_degree(ctx):
+    """Degree 64: the scaled recurrence stays of order one (the unscaled
+    T_64 reaches ~1e40 here) and the solve matches the oracle in one or two
+    iterations."""
+    A = W.laplacian_2d(20)
+    lam, V, info, ref = _run(ctx, A, 6, 6, 64)
+    assert info.converged and ref.converged and info.iterations <= 3
+    assert abs(info.iterations - ref.iterations) <= 1
+    exact = pins.laplacian_spectrum(20, 2, 6)
+    assert np.max(np.abs(lam - exact) / exact) <= 1e-9
+    assert cluster_angles(lam, V, ref.V) <= 1e-6
