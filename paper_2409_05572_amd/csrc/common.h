@@ -132,6 +132,14 @@ hipError_t launch_cg_dir(hipStream_t st, long long n, int k, const double* rr_ne
 hipError_t launch_cheb_step(hipStream_t st, long long n, int k, double alpha, const double* U, double beta,
                             const double* V, double gamma, double* Z, long long ld);
 
+// Z <- alpha A Y + beta Y + gamma Z over the first w columns in one pass over
+// the CSR rows (the product is never stored); matrices without heavy rows only
+// (n_heavy must be 0), CSR arrays padded by kCsrPad entries, ld even and
+// >= w + 1 for odd w.
+hipError_t launch_spmm_cheb(hipStream_t st, int n, const int* rowptr, const int* col, const double* val,
+                            const double* Y, double* Z, long long ld, int w, int n_heavy, double alpha, double beta,
+                            double gamma);
+
 // Columns c0 .. c0 + d - 1 of the row-major n-row panel X get the normally
 // distributed block of draw `draw`: entry (i, j) is sqrt(-2 ln u1) cos(2 pi u2)
 // (Box-Muller) with u1 = ((z1 >> 11) + 1) 2^-53, u2 = (z2 >> 11) 2^-53 and z1,

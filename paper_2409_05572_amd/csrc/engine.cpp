@@ -875,6 +875,7 @@ struct Solver {
     // (c, e the centre and half-width of [cut, up]), which keeps the block of
     // order one. AY0 = A Y when known (else one more product into tmp). Y and
     // Yalt are two panels that rotate; on return Y holds the filtered block.
+    // Without heavy rows each later step is one fused product-and-step pass.
     se_status cheb_filter(double*& Y, double*& Yalt, const double* AY0, double* tmp, int w, double lower,
                           double cut, double up) {
         const double c = 0.5 * (up + cut), e = 0.5 * (up - cut);
@@ -891,12 +892,20 @@ struct Solver {
         double* prev = Y;
         double* cur = Yalt;
         for (int i = 2; i <= p.filter_degree; ++i) {
-            ST(spmm(cur, tmp, w));
             const double s_new = 1.0 / (tau - s);
             alpha = 2.0 * s_new / e;
-            ST(tic());
-            HC(launch_cheb_step(st, n, w, alpha, tmp, -c * alpha, cur, -s * s_new, prev, ld));
-            ST(toc(SE_K_RESID, 32.0 * n * w, 5.0 * n * w));
+            if (A->n_heavy == 0) {
+                // product and step in one pass: A Y never goes to memory
+                ST(tic());
+                HC(launch_spmm_cheb(st, (int)n, A->rowptr, A->col, A->val, cur, prev, ld, w, 0, alpha, -c * alpha,
+                                    -s * s_new));
+                ST(toc(SE_K_SPMM, 12.0 * A->nnz + 4.0 * (n + 1) + 32.0 * n * w, 2.0 * A->nnz * w + 5.0 * n * w));
+            } else {
+                ST(spmm(cur, tmp, w));
+                ST(tic());
+                HC(launch_cheb_step(st, n, w, alpha, tmp, -c * alpha, cur, -s * s_new, prev, ld));
+                ST(toc(SE_K_RESID, 32.0 * n * w, 5.0 * n * w));
+            }
             s = s_new;
             std::swap(prev, cur);
         }

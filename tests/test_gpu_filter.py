@@ -116,3 +116,26 @@ def test_filter_of_the_largest_degree(ctx):
     exact = pins.laplacian_spectrum(20, 2, 6)
     assert np.max(np.abs(lam - exact) / exact) <= 1e-9
     assert cluster_angles(lam, V, ref.V) <= 1e-6
+
+
+def test_filtered_si_on_a_power_law_graph(ctx):
+    """Rows longer than 64 nonzeros: the filter runs the row and hub-row
+    products and the separate step kernel instead of the fused pass. Chung-Lu
+    normalized Laplacian, n = 20,000 (lambda_1 = 0 exactly)."""
+    from paper_2409_05572_amd import api
+
+    A = W.chung_lu_laplacian(20000, 16.0, 2.5, 7)
+    assert np.max(np.diff(A.rowptr)) > 64
+    X0 = W.gaussian_block(A.n, 16, 5)
+    M = api.Matrix.from_csr(ctx, A)
+    lam, V, info = api.solve(ctx, M, X0, 8, 8, history_cap=4000, solver="si", n_es=13, max_iter=4000,
+                             filter_degree=8)
+    ref = O.subspace_iteration(A.to_scipy(), X0, 8, A.anorm, tol=1e-8, n_es=13, max_iter=4000,
+                               filter_degree=8)
+    assert info.converged and ref.converged
+    assert abs(info.iterations - ref.iterations) <= 1
+    assert np.max(np.abs(lam - ref.lam)) <= 1e-10 * A.anorm
+    assert abs(lam[0]) <= 1e-10
+    R = O.solvers._apply(A.to_scipy(), V) - V * lam[None, :]
+    assert np.max(np.linalg.norm(R, axis=0) / (A.anorm * np.linalg.norm(V, axis=0))) <= 1e-8 * 1.0001
+    assert cluster_angles(lam, V, ref.V) <= 1e-6
