@@ -20,7 +20,14 @@ implements, in plain NumPy:
   15 iterations; then the FP64 solver continues from [X, X_drop] (LOBPCG also
   keeps P).
 * Subspace iteration: Y = sigma X - A X (plus X_drop at an expansion), then
-  the same generalized Rayleigh-Ritz step on span(Y).
+  the same generalized Rayleigh-Ritz step on span(Y). With a Chebyshev filter
+  of degree d (``filter_degree``) Y is p(A) X for the filter of
+  ``solvers.chebyshev_filter``; every intermediate block Y_i = T_i(L) X /
+  T_i(l0) (normalized at each degree so that it stays of order one in the
+  storage format) is stored rounded, and A Y_i uses the rounded matrix. A
+  powered X_drop (``expand_vectors="powered"``) takes the same step (or the
+  shifted step divided by sigma - theta_1) while it is held, also stored
+  rounded.
 
 Shrink-and-expand follows Algorithm 5 with the strategies of Section 3.2, as
 in ``solvers.py``. The final result is that of the FP64 solver and so has the
@@ -182,9 +189,29 @@ def lobpcg_mixed(A, X0, n_ev, anorm, fmt="fp32", tol=1e-8, n_es=None, se: SEPara
     return res, j, hist
 
 
+def _filter_rounded(A32, Y, degree, lower, cut, upper, rd):
+    """p(A) Y for the Chebyshev filter damping [cut, upper], one at `lower`,
+    with each normalized intermediate T_i(L) Y / T_i(l0) stored rounded:
+    Y_{i+1} = (2 t_i L Y_i - t_{i-1} Y_{i-1}) / t_{i+1}, t_i = T_i(l0)."""
+    c = 0.5 * (upper + cut)
+    e = 0.5 * (upper - cut)
+    l0 = (lower - c) / e
+    L = lambda Z: (rd(A32 @ Z) - c * Z) / e  # noqa: E731
+    t_prev, t = 1.0, l0
+    Y_prev, Yc = Y, rd(L(Y) / t)
+    for _ in range(2, degree + 1):
+        t_next = 2.0 * l0 * t - t_prev
+        Y_prev, Yc = Yc, rd((2.0 * t * L(Yc) - t_prev * Y_prev) / t_next)
+        t_prev, t = t, t_next
+    return Yc
+
+
 def subspace_iteration_mixed(A, X0, n_ev, anorm, fmt="fp32", sigma=None, tol=1e-8, n_es=None,
-                             se: SEParams | None = None, r_switch=None, max_iter=20000):
+                             se: SEParams | None = None, r_switch=None, max_iter=20000,
+                             filter_degree=0, expand_vectors="xdrop"):
     """Subspace iteration (Algorithm 1) with a low-precision phase, then FP64."""
+    if expand_vectors not in ("xdrop", "powered"):
+        raise ValueError("mixed precision appends X_drop or the powered X_drop")
     se = se or SEParams()
     r_switch = DEFAULT_SWITCH[fmt] if r_switch is None else r_switch
     sigma = anorm if sigma is None else sigma
@@ -215,7 +242,17 @@ def subspace_iteration_mixed(A, X0, n_ev, anorm, fmt="fp32", sigma=None, tol=1e-
         if _should_switch(r, best, j, j_best, r_switch):
             break
         expand = ctl.ifexpand(j)
-        Y = rd(sigma * X - AX)
+        filt = filter_degree > 0 and sigma > lam[-1]
+        if filt:
+            Y = _filter_rounded(A32, X, filter_degree, lam[0], lam[-1], sigma, rd)
+        else:
+            Y = rd(sigma * X - AX)
+        if expand_vectors == "powered" and Xd is not None:
+            if filt:
+                Xd = _filter_rounded(A32, Xd, filter_degree, lam[0], lam[-1], sigma, rd)
+            else:
+                scale = 1.0 / (sigma - lam[0]) if sigma - lam[0] > 0.0 else 1.0
+                Xd = rd(scale * (sigma * Xd - rd(A32 @ Xd)))
         if expand and Xd is not None:
             Y = np.hstack([Y, Xd])
             Xd = None
@@ -227,5 +264,6 @@ def subspace_iteration_mixed(A, X0, n_ev, anorm, fmt="fp32", sigma=None, tol=1e-
             ctl.did_shrink(j)
     X0_64 = X if Xd is None else np.hstack([X, Xd[:, : nb - X.shape[1]]])
     res = S_.subspace_iteration(A, X0_64, n_ev, anorm, sigma=sigma, tol=tol, n_es=n_es, se=se,
-                                max_iter=max_iter)
+                                max_iter=max_iter, filter_degree=filter_degree,
+                                expand_vectors=expand_vectors)
     return res, j, hist

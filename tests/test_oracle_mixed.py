@@ -113,3 +113,33 @@ def test_mixed_lobpcg_with_shrink_expand_and_si():
     res2, lp2, _ = M_.subspace_iteration_mixed(A2.to_scipy(), X2, 8, A2.anorm, fmt="fp32")
     ex2 = pins.laplacian_spectrum(32, 2, 8)
     assert res2.converged and lp2 >= 1 and np.max(np.abs(res2.lam - ex2) / ex2) <= 1e-10
+
+
+@pytest.mark.parametrize("degree", [1, 2, 7])
+def test_normalized_filter_recurrence_is_the_filter_definition(degree):
+    """Without rounding, the per-degree normalized recurrence of the mixed
+    oracle is the filter as defined (T_d(L) Y / T_d(l0) by the textbook
+    recurrence)."""
+    from oracle import mixed as OM
+
+    A = W.laplacian_2d(12).to_scipy()
+    Y = np.random.default_rng(degree).standard_normal((A.shape[0], 5))
+    lo, cut, up = 0.06, 1.2, 8.0
+    got = OM._filter_rounded(A, Y, degree, lo, cut, up, lambda Z: Z)
+    np.testing.assert_allclose(got, O.chebyshev_filter(A, Y, degree, lo, cut, up), rtol=1e-11, atol=1e-12)
+
+
+@pytest.mark.parametrize("fmt", ["fp32", "bf16"])
+@pytest.mark.parametrize("degree,kind", [(8, "xdrop"), (3, "powered"), (0, "powered")])
+def test_mixed_filtered_and_powered_si_reach_closed_form(fmt, degree, kind):
+    from oracle import mixed as OM
+
+    m, n_ev = 20, 6
+    A = W.laplacian_2d(m)
+    X0 = W.gaussian_block(A.n, 12, 5)
+    res, j_lp, _ = OM.subspace_iteration_mixed(A.to_scipy(), X0, n_ev, A.anorm, fmt=fmt, n_es=8,
+                                               se=O.SEParams("fix"), filter_degree=degree,
+                                               expand_vectors=kind)
+    assert res.converged and j_lp >= 2
+    exact = pins.laplacian_spectrum(m, 2, n_ev)
+    np.testing.assert_allclose(res.lam, exact, rtol=1e-9)
