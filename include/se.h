@@ -54,7 +54,8 @@ typedef struct se_matrix se_matrix;
                          FP64, block <= 512; A must be positive definite */
 
 /* Vectors appended at an expansion (Section 6, the vectors appended in the
- * expansion). FP64 only (SE_ERR_UNSUPPORTED with a mixed precision). */
+ * expansion). SE_EXPAND_RANDOM is FP64 only (SE_ERR_UNSUPPORTED with a mixed
+ * precision); the powered X_drop also runs in the low-precision phase. */
 #define SE_EXPAND_XDROP 0   /* the vectors dropped at the last shrink (the paper's choice) */
 #define SE_EXPAND_RANDOM 1  /* a normally distributed block of the same width, drawn on the
                                device: entry (i, j) of the e-th expansion (e = 1, 2, ...) is
@@ -139,13 +140,15 @@ typedef struct se_params {
     double* history;     /* optional host buffer of history_cap x SE_HISTORY_FIELDS doubles */
     int32_t history_cap; /* rows available in history */
     int32_t expand_vectors; /* SE_EXPAND_XDROP (default), SE_EXPAND_RANDOM or SE_EXPAND_POWERED */
-    int32_t filter_degree;  /* subspace iteration, FP64: 0 = the shifted power step sigma X - A X;
+    int32_t filter_degree;  /* subspace iteration: 0 = the shifted power step sigma X - A X;
                                d in 1..64 = the Chebyshev filter of degree d (Zhou and Saad 2007)
                                that damps [theta_k, sigma] and is one at theta_1 (theta the
                                current Ritz values of the k-column block), by the scaled
                                three-term recurrence: d - 1 extra sparse products per
                                iteration. A powered X_drop takes the same filter. Falls back
-                               to the shifted step at an iteration where sigma <= theta_k. */
+                               to the shifted step at an iteration where sigma <= theta_k. In
+                               the low-precision phase of a mixed solve every intermediate
+                               block is stored in FP32 / BF16 (steps formed in FP64). */
     int32_t cg_steps;       /* SE_TRACEMIN: inner CG steps per iteration (0 = 5, the paper's) */
     int32_t precond;        /* SE_PRECOND_NONE (default) or SE_PRECOND_JACOBI */
     int32_t reserved;       /* must be 0 */

@@ -398,14 +398,34 @@ __global__ __launch_bounds__(kThreads) void form_w_lp_kernel(long long n, const 
 template <class T>
 __global__ __launch_bounds__(kThreads) void shift_sub_lp_kernel(long long n, T* __restrict__ X,
                                                                 const T* __restrict__ AX, long long ld,
-                                                                int k, double sigma) {
+                                                                int k, double sigma, double scale) {
     const long long total = n * k;
     for (long long e = (long long)blockIdx.x * kThreads + threadIdx.x; e < total;
          e += (long long)gridDim.x * kThreads) {
         const long long r = e / k;
         const int c = (int)(e - r * k);
         T* px = X + r * ld + c;
-        st1(px, (float)(sigma * (double)ld1(px) - (double)ld1(AX + r * ld + c)));
+        st1(px, (float)(scale * (sigma * (double)ld1(px) - (double)ld1(AX + r * ld + c))));
+    }
+}
+
+// One step of the Chebyshev filter recurrence on stored blocks: Z = alpha U +
+// beta V + gamma Z over the first k columns (Z not read when gamma = 0),
+// formed in FP64 from the stored values and rounded once.
+template <class T>
+__global__ __launch_bounds__(kThreads) void cheb_step_lp_kernel(long long n, int k, double alpha,
+                                                                const T* __restrict__ U, double beta,
+                                                                const T* __restrict__ V, double gamma,
+                                                                T* __restrict__ Z, long long ld) {
+    const long long total = n * k;
+    const bool with_z = gamma != 0.0;
+    for (long long e = (long long)blockIdx.x * kThreads + threadIdx.x; e < total;
+         e += (long long)gridDim.x * kThreads) {
+        const long long r = e / k;
+        const int c = (int)(e - r * k);
+        const long long o = r * ld + c;
+        const double z = with_z ? (double)ld1(Z + o) : 0.0;
+        st1(Z + o, (float)(alpha * (double)ld1(U + o) + beta * (double)ld1(V + o) + gamma * z));
     }
 }
 
@@ -807,10 +827,19 @@ hipError_t launch_form_w_lp(hipStream_t st, long long n, const T* X, const T* AX
 
 template <class T>
 hipError_t launch_shift_sub_lp(hipStream_t st, long long n, T* X, const T* AX, long long ld, int k,
-                               double sigma) {
+                               double sigma, double scale) {
     if (k <= 0 || n <= 0) return hipSuccess;
     hipLaunchKernelGGL(shift_sub_lp_kernel<T>, dim3(grid_for(n * k, kThreads, 16384)), dim3(kThreads), 0, st,
-                       n, X, AX, ld, k, sigma);
+                       n, X, AX, ld, k, sigma, scale);
+    return hipGetLastError();
+}
+
+template <class T>
+hipError_t launch_cheb_step_lp(hipStream_t st, long long n, int k, double alpha, const T* U, double beta,
+                               const T* V, double gamma, T* Z, long long ld) {
+    if (k <= 0 || n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(cheb_step_lp_kernel<T>, dim3(grid_for(n * k, kThreads, 16384)), dim3(kThreads), 0, st,
+                       n, k, alpha, U, beta, V, gamma, Z, ld);
     return hipGetLastError();
 }
 
@@ -891,7 +920,10 @@ hipError_t launch_f64_to_f32(hipStream_t st, long long count, const double* src,
                                                  const double*, double*, double*);                        \
     template hipError_t launch_form_w_lp<T>(hipStream_t, long long, const T*, const T*, long long,         \
                                             const double*, const int*, int, T*, long long);               \
-    template hipError_t launch_shift_sub_lp<T>(hipStream_t, long long, T*, const T*, long long, int, double); \
+    template hipError_t launch_shift_sub_lp<T>(hipStream_t, long long, T*, const T*, long long, int, double, \
+                                               double);                                                  \
+    template hipError_t launch_cheb_step_lp<T>(hipStream_t, long long, int, double, const T*, double,     \
+                                               const T*, double, T*, long long);                         \
     template hipError_t launch_copy_cols_lp<T>(hipStream_t, long long, const T*, long long, int, T*,       \
                                                long long, int, int);                                     \
     template hipError_t launch_colmajor_to_rows_lp<T>(hipStream_t, long long, int, const double*,          \

@@ -75,10 +75,9 @@ se_status validate_solve(const se_matrix* A, const se_params* p) {
     if (p->solver == SE_SI && p->sigma < 0.0) return SE_ERR_INVALID_ARG;
     if (p->expand_vectors < SE_EXPAND_XDROP || p->expand_vectors > SE_EXPAND_POWERED) return SE_ERR_INVALID_ARG;
     if (p->expand_vectors == SE_EXPAND_POWERED && p->solver != SE_SI) return SE_ERR_INVALID_ARG;
-    if (p->expand_vectors != SE_EXPAND_XDROP && p->precision != SE_FP64) return SE_ERR_UNSUPPORTED;
+    if (p->expand_vectors == SE_EXPAND_RANDOM && p->precision != SE_FP64) return SE_ERR_UNSUPPORTED;
     if (p->filter_degree < 0 || p->filter_degree > 64) return SE_ERR_INVALID_ARG;
     if (p->filter_degree > 0 && p->solver != SE_SI) return SE_ERR_INVALID_ARG;
-    if (p->filter_degree > 0 && p->precision != SE_FP64) return SE_ERR_UNSUPPORTED;
     if (p->precond != SE_PRECOND_NONE && p->precond != SE_PRECOND_JACOBI) return SE_ERR_INVALID_ARG;
     if (p->precond != SE_PRECOND_NONE && p->solver != SE_LOBPCG && p->solver != SE_SD) return SE_ERR_INVALID_ARG;
     if (p->precond != SE_PRECOND_NONE && p->precision != SE_FP64) return SE_ERR_UNSUPPORTED;

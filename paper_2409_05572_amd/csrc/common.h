@@ -213,9 +213,14 @@ hipError_t launch_resid_norms_lp(hipStream_t st, long long n, const T* X, const 
 template <class T>
 hipError_t launch_form_w_lp(hipStream_t st, long long n, const T* X, const T* AX, long long ld,
                             const double* lam, const int* act, int a, T* W, long long ldw);
+// X = scale (sigma X - AX) and the Chebyshev filter step Z = alpha U + beta V +
+// gamma Z, both formed in FP64 from the stored values and rounded once.
 template <class T>
 hipError_t launch_shift_sub_lp(hipStream_t st, long long n, T* X, const T* AX, long long ld, int k,
-                               double sigma);
+                               double sigma, double scale = 1.0);
+template <class T>
+hipError_t launch_cheb_step_lp(hipStream_t st, long long n, int k, double alpha, const T* U, double beta,
+                               const T* V, double gamma, T* Z, long long ld);
 template <class T>
 hipError_t launch_copy_cols_lp(hipStream_t st, long long n, const T* src, long long lds, int sc, T* dst,
                                long long ldd, int dc, int w);

@@ -1492,6 +1492,39 @@ struct Solver {
     // Subspace iteration (Algorithm 1) with shrink-and-expand on
     // low-precision panels: Y = sigma X - A X (plus X_drop at an expansion),
     // then the generalized Rayleigh-Ritz step on span(Y).
+    // The Chebyshev filter of cheb_filter on low-precision blocks: each step's
+    // product A Y is stored, and the step is formed in FP64 and rounded once.
+    template <class T>
+    se_status cheb_filter_lp(T*& Y, T*& Yalt, const T* AY0, T* tmp, int w, double lower, double cut,
+                             double up) {
+        const double c = 0.5 * (up + cut), e = 0.5 * (up - cut);
+        double s = e / (lower - c);
+        const double tau = 2.0 / s;
+        if (!AY0) {
+            ST(lp_spmm(Y, tmp, w));
+            AY0 = tmp;
+        }
+        double alpha = s / e;
+        ST(tic());
+        HC(launch_cheb_step_lp<T>(st, n, w, alpha, AY0, -c * alpha, Y, 0.0, Yalt, ld));
+        ST(toc(SE_K_RESID, 3.0 * sizeof(T) * n * w, 3.0 * n * w));
+        T* prev = Y;
+        T* cur = Yalt;
+        for (int i = 2; i <= p.filter_degree; ++i) {
+            ST(lp_spmm(cur, tmp, w));
+            const double s_new = 1.0 / (tau - s);
+            alpha = 2.0 * s_new / e;
+            ST(tic());
+            HC(launch_cheb_step_lp<T>(st, n, w, alpha, tmp, -c * alpha, cur, -s * s_new, prev, ld));
+            ST(toc(SE_K_RESID, 4.0 * sizeof(T) * n * w, 5.0 * n * w));
+            s = s_new;
+            std::swap(prev, cur);
+        }
+        Y = cur;
+        Yalt = prev;
+        return SE_OK;
+    }
+
     template <class T>
     se_status si_lp(const double* X0, int& k0) {
         int p0 = 0;
@@ -1503,6 +1536,8 @@ struct Solver {
         T* Xnl = static_cast<T*>(lp[6]);
         T* AXnl = static_cast<T*>(lp[8]);
         T* Sdl = static_cast<T*>(lp[10]);
+        T* T1l = static_cast<T*>(lp[1]);  // filter products
+        T* T2l = static_cast<T*>(lp[2]);  // rotation panel of the powered X_drop
         const double u = unit_roundoff<T>();
         const double drop2 = kLpDrop2;
         const double rsw = r_switch_value(u);
@@ -1565,9 +1600,27 @@ struct Solver {
                 break;
             int flags = 4;
             const bool want_expand = ctl.ifexpand(j);
-            ST(tic());
-            HC(launch_shift_sub_lp<T>(st, n, Xl, AXl, ld, k, sigma));
-            ST(toc(SE_K_RESID, 3.0 * sizeof(T) * n * k, 2.0 * n * k));
+            // Y <- sigma X - A X or the Chebyshev filter; a powered X_drop
+            // takes the same step
+            const bool filt = p.filter_degree > 0 && sigma > lam[k - 1];
+            if (filt) {
+                ST(cheb_filter_lp<T>(Xl, Xnl, AXl, T1l, k, lam[0], lam[k - 1], sigma));
+            } else {
+                ST(tic());
+                HC(launch_shift_sub_lp<T>(st, n, Xl, AXl, ld, k, sigma));
+                ST(toc(SE_K_RESID, 3.0 * sizeof(T) * n * k, 2.0 * n * k));
+            }
+            if (have_drop && p.expand_vectors == SE_EXPAND_POWERED) {
+                if (filt) {
+                    ST(cheb_filter_lp<T>(Sdl, T2l, nullptr, T1l, dx, lam[0], lam[k - 1], sigma));
+                } else {
+                    ST(lp_spmm(Sdl, T1l, dx));
+                    const double gap = sigma - lam[0];
+                    ST(tic());
+                    HC(launch_shift_sub_lp<T>(st, n, Sdl, T1l, ld, dx, sigma, gap > 0.0 ? 1.0 / gap : 1.0));
+                    ST(toc(SE_K_RESID, 3.0 * sizeof(T) * n * dx, 3.0 * n * dx));
+                }
+            }
             if (want_expand && have_drop) {
                 HC(launch_copy_cols_lp<T>(st, n, Sdl, ld, 0, Xl, ld, k, dx));
                 k += dx;

@@ -101,8 +101,8 @@ def test_filter_options_are_validated(ctx):
         api.solve(ctx, M, X0, 4, 4, filter_degree=4)  # LOBPCG
     with pytest.raises(SeError, match="invalid"):
         api.solve(ctx, M, X0, 4, 4, solver="si", filter_degree=65)
-    with pytest.raises(SeError, match="unsupported"):
-        api.solve(ctx, M, X0, 4, 4, solver="si", filter_degree=4, precision="fp32")
+    with pytest.raises(SeError, match="invalid"):
+        api.solve(ctx, M, X0, 4, 4, solver="si", filter_degree=-1)
 
 
 def test_filter_of_the_largest_degree(ctx):

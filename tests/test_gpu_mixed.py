@@ -286,3 +286,38 @@ def test_mixed_matches_mixed_oracle(ctx, fmt, solver):
     assert np.all((ratio > 0.8) & (ratio < 1.25))
     if fmt == "fp32":
         assert abs(info.lp_iterations - lp_ref) <= max(5, 0.3 * lp_ref)
+
+
+@pytest.mark.parametrize("fmt,degree,kind,strategy", [("fp32", 3, "xdrop", "fix"), ("fp32", 3, "powered", "fix"),
+                                                      ("bf16", 3, "powered", "fix"), ("fp32", 8, "xdrop", "none"),
+                                                      ("fp32", 0, "powered", "fix")])
+def test_mixed_filtered_and_powered_si_match_mixed_oracle(ctx, fmt, degree, kind, strategy):
+    """Chebyshev-filtered SI and the powered X_drop with a low-precision phase
+    (every intermediate block stored in FP32 / BF16) against the mixed
+    oracle: the final pairs to the FP64 bar and the closed form; r(j) of the
+    two low-precision phases agrees while it is well above r_switch, and the
+    GPU's phase ends where the switch rule fires on its own history."""
+    from tests.gpu_util import cluster_angles
+
+    A = W.laplacian_2d(20)
+    X0 = W.gaussian_block(A.n, 12, 5)
+    lam, V, info = _solve(ctx, A, X0, 6, 6, solver="si", precision=fmt, strategy=strategy, n_es=8,
+                          filter_degree=degree, expand_vectors=kind)
+    ref, lp_ref, hist = O.mixed.subspace_iteration_mixed(A.to_scipy(), X0, 6, A.anorm, fmt=fmt, n_es=8,
+                                                         se=O.SEParams(strategy), filter_degree=degree,
+                                                         expand_vectors=kind)
+    assert info.converged and ref.converged and info.lp_iterations >= 2
+    exact = pins.laplacian_spectrum(20, 2, 6)
+    assert np.max(np.abs(lam - exact) / exact) <= 1e-9
+    assert np.max(np.abs(lam - ref.lam) / np.abs(ref.lam)) <= 1e-10
+    assert cluster_angles(lam, V, ref.V) <= 1e-6
+    rsw = O.mixed.DEFAULT_SWITCH[fmt]
+    h = info.history
+    r_gpu = h[(h[:, 7].astype(int) & 4) != 0, 1]
+    r_ref = np.array([q["r"] for q in hist])[:lp_ref]
+    assert _switch_iteration(r_gpu, rsw) == info.lp_iterations
+    both = min(len(r_gpu), len(r_ref))
+    above = (r_gpu[:both] > 10 * rsw) & (r_ref[:both] > 10 * rsw)
+    assert above.sum() >= 3
+    ratio = r_gpu[:both][above] / r_ref[:both][above]
+    assert np.all((ratio > 0.8) & (ratio < 1.25))
