@@ -308,6 +308,79 @@ __global__ __launch_bounds__(kThreads) void spmm_lp_stream_kernel(int n, const i
     }
 }
 
+// The streaming product fused with one step of the Chebyshev filter, for
+// matrices without heavy rows: at a row's end the lane rounds its two sums to
+// the storage format (as the separate product would store them), forms
+// alpha (A Y) + beta Y + gamma Z in FP64 from the stored Y and Z of the row,
+// and stores Z rounded once. A Y never goes to memory.
+__device__ __forceinline__ float stored(const float*, float x) { return x; }
+__device__ __forceinline__ float stored(const bf16_t*, float x) { return bf2f(f2bf(x)); }
+
+template <class T, int NB>
+__global__ __launch_bounds__(kThreads) void spmm_cheb_lp_kernel(int n, const int* __restrict__ rowptr,
+                                                                const int* __restrict__ col,
+                                                                const float* __restrict__ val,
+                                                                const T* __restrict__ Y, T* __restrict__ Z,
+                                                                long long ld, int w, double alpha, double beta,
+                                                                double gamma) {
+    const int lane = threadIdx.x & 63;
+    const int wid = __builtin_amdgcn_readfirstlane((int)blockIdx.x * (kThreads / 64) + (int)(threadIdx.x >> 6));
+    if ((long long)wid * kStreamRows >= n) return;
+    const int r0 = wid * kStreamRows;
+    const int r1 = min(n, r0 + kStreamRows);
+    const int rp = rowptr[min(r0 + lane, r1)];
+    const int pbeg = __builtin_amdgcn_readlane(rp, 0);
+    const int pend = __builtin_amdgcn_readlane(rp, r1 - r0);
+    const bool with_z = gamma != 0.0;
+    for (int cb = 0; cb < w; cb += 128) {
+        const int c0 = cb + 2 * lane;
+        const bool has0 = c0 < w, has1 = c0 + 1 < w;
+        const long long cc = has0 ? c0 : cb;
+        int r = r0;
+        int rend = __builtin_amdgcn_readlane(rp, 1);
+        float a0 = 0.f, a1 = 0.f;
+        auto flush = [&]() {
+            const long long o = (long long)r * ld + c0;
+            if (has0) {
+                float y0, y1, z0 = 0.f, z1 = 0.f;
+                ld2(Y + o, y0, y1);  // y1 is the padding column when only has0
+                if (with_z) ld2(Z + o, z0, z1);
+                const float v0 = (float)(alpha * (double)stored(Y, a0) + beta * (double)y0 + gamma * (double)z0);
+                const float v1 = (float)(alpha * (double)stored(Y, a1) + beta * (double)y1 + gamma * (double)z1);
+                if (has1)
+                    st2(Z + o, v0, v1);
+                else
+                    st1(Z + o, v0);
+            }
+            a0 = 0.f;
+            a1 = 0.f;
+            ++r;
+            if (r < r1) rend = __builtin_amdgcn_readlane(rp, r - r0 + 1);
+        };
+        for (int p = pbeg; p < pend; p += NB) {
+            int j[NB];
+            float v[NB];
+#pragma unroll
+            for (int u = 0; u < NB; ++u) {
+                j[u] = col[p + u];
+                v[u] = val[p + u];
+            }
+            float x0[NB], x1[NB];
+#pragma unroll
+            for (int u = 0; u < NB; ++u) ld2(Y + (long long)j[u] * ld + cc, x0[u], x1[u]);
+#pragma unroll
+            for (int u = 0; u < NB; ++u) {
+                if (p + u < pend) {
+                    while (p + u >= rend) flush();
+                    a0 = fmaf(v[u], x0[u], a0);
+                    a1 = fmaf(v[u], x1[u], a1);
+                }
+            }
+        }
+        while (r < r1) flush();
+    }
+}
+
 template <class T, int LPR>
 hipError_t spmm_lp_launch(hipStream_t st, int n, const int* rowptr, const int* col, const float* val,
                           const T* X, long long ldx, T* Y, long long ldy, int w, const int* heavy,
@@ -835,6 +908,19 @@ hipError_t launch_shift_sub_lp(hipStream_t st, long long n, T* X, const T* AX, l
 }
 
 template <class T>
+hipError_t launch_spmm_cheb_lp(hipStream_t st, int n, const int* rowptr, const int* col, const float* val,
+                               const T* Y, T* Z, long long ld, int w, int n_heavy, double alpha, double beta,
+                               double gamma) {
+    if (n <= 0 || w <= 0) return hipSuccess;
+    if (n_heavy > 0 || !ld_ok(ld, w)) return hipErrorInvalidValue;
+    const long long waves = ((long long)n + kStreamRows - 1) / kStreamRows;
+    const int grid = (int)((waves + kThreads / 64 - 1) / (kThreads / 64));
+    hipLaunchKernelGGL((spmm_cheb_lp_kernel<T, 16>), dim3(grid), dim3(kThreads), 0, st, n, rowptr, col, val, Y, Z,
+                       ld, w, alpha, beta, gamma);
+    return hipGetLastError();
+}
+
+template <class T>
 hipError_t launch_cheb_step_lp(hipStream_t st, long long n, int k, double alpha, const T* U, double beta,
                                const T* V, double gamma, T* Z, long long ld) {
     if (k <= 0 || n <= 0) return hipSuccess;
@@ -924,6 +1010,8 @@ hipError_t launch_f64_to_f32(hipStream_t st, long long count, const double* src,
                                                double);                                                  \
     template hipError_t launch_cheb_step_lp<T>(hipStream_t, long long, int, double, const T*, double,     \
                                                const T*, double, T*, long long);                         \
+    template hipError_t launch_spmm_cheb_lp<T>(hipStream_t, int, const int*, const int*, const float*,    \
+                                               const T*, T*, long long, int, int, double, double, double); \
     template hipError_t launch_copy_cols_lp<T>(hipStream_t, long long, const T*, long long, int, T*,       \
                                                long long, int, int);                                     \
     template hipError_t launch_colmajor_to_rows_lp<T>(hipStream_t, long long, int, const double*,          \

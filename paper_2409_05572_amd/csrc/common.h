@@ -221,6 +221,11 @@ hipError_t launch_shift_sub_lp(hipStream_t st, long long n, T* X, const T* AX, l
 template <class T>
 hipError_t launch_cheb_step_lp(hipStream_t st, long long n, int k, double alpha, const T* U, double beta,
                                const T* V, double gamma, T* Z, long long ld);
+// The product A Y fused with that step (no heavy rows; FP32 values val32).
+template <class T>
+hipError_t launch_spmm_cheb_lp(hipStream_t st, int n, const int* rowptr, const int* col, const float* val,
+                               const T* Y, T* Z, long long ld, int w, int n_heavy, double alpha, double beta,
+                               double gamma);
 template <class T>
 hipError_t launch_copy_cols_lp(hipStream_t st, long long n, const T* src, long long lds, int sc, T* dst,
                                long long ldd, int dc, int w);

@@ -1511,12 +1511,20 @@ struct Solver {
         T* prev = Y;
         T* cur = Yalt;
         for (int i = 2; i <= p.filter_degree; ++i) {
-            ST(lp_spmm(cur, tmp, w));
             const double s_new = 1.0 / (tau - s);
             alpha = 2.0 * s_new / e;
-            ST(tic());
-            HC(launch_cheb_step_lp<T>(st, n, w, alpha, tmp, -c * alpha, cur, -s * s_new, prev, ld));
-            ST(toc(SE_K_RESID, 4.0 * sizeof(T) * n * w, 5.0 * n * w));
+            if (A->n_heavy == 0) {
+                ST(tic());
+                HC(launch_spmm_cheb_lp<T>(st, (int)n, A->rowptr, A->col, A->val32, cur, prev, ld, w, 0, alpha,
+                                          -c * alpha, -s * s_new));
+                ST(toc(SE_K_SPMM, 8.0 * A->nnz + 4.0 * (n + 1) + 4.0 * sizeof(T) * n * w,
+                       2.0 * A->nnz * w + 5.0 * n * w));
+            } else {
+                ST(lp_spmm(cur, tmp, w));
+                ST(tic());
+                HC(launch_cheb_step_lp<T>(st, n, w, alpha, tmp, -c * alpha, cur, -s * s_new, prev, ld));
+                ST(toc(SE_K_RESID, 4.0 * sizeof(T) * n * w, 5.0 * n * w));
+            }
             s = s_new;
             std::swap(prev, cur);
         }
