@@ -321,3 +321,23 @@ def test_mixed_filtered_and_powered_si_match_mixed_oracle(ctx, fmt, degree, kind
     assert above.sum() >= 3
     ratio = r_gpu[:both][above] / r_ref[:both][above]
     assert np.all((ratio > 0.8) & (ratio < 1.25))
+
+
+def test_full_size_fp32_filtered_si(ctx):
+    """The 128^3 Laplacian with a degree-32 filter and an FP32 phase (fused
+    low-precision product-and-step), fixed block: every eigenvalue against the
+    closed form, sampled stopping test on the host, orthonormality."""
+    from paper_2409_05572_amd import api
+
+    A = W.laplacian_3d(128)
+    X0 = W.gaussian_block(A.n, 96, 202)
+    M = api.Matrix.from_csr(ctx, A)
+    lam, V, info = api.solve(ctx, M, X0, 64, 32, solver="si", precision="fp32", filter_degree=32,
+                             max_iter=500)
+    assert info.converged and info.lp_iterations >= 2
+    exact = pins.laplacian_spectrum(128, 3, 64)
+    assert np.max(np.abs(lam - exact) / exact) <= 1e-9
+    cols = np.array([0, 1, 17, 40, 63])
+    R = A.to_scipy() @ V[:, cols] - V[:, cols] * lam[cols][None, :]
+    assert np.max(np.linalg.norm(R, axis=0) / (A.anorm * np.linalg.norm(V[:, cols], axis=0))) <= 1e-8 * 1.0001
+    assert np.abs(V.T @ V - np.eye(64)).max() <= 1e-11

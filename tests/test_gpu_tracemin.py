@@ -119,3 +119,22 @@ def test_tracemin_options_are_validated(ctx):
         api.solve(ctx, M, X0, 4, 4, solver="tracemin", cg_steps=101)
     with pytest.raises(SeError, match="invalid"):
         api.solve(ctx, M, X0, 4, 4, solver="tracemin", filter_degree=3)
+
+
+def test_tracemin_on_the_64_cubed_laplacian(ctx):
+    """A larger solve (n = 262,144, block 48, fix): every eigenvalue against
+    the closed form and the stopping test recomputed on the host for sampled
+    eigenvectors."""
+    from paper_2409_05572_amd import api
+
+    A = W.laplacian_3d(64)
+    X0 = W.gaussian_block(A.n, 48, 7)
+    M = api.Matrix.from_csr(ctx, A)
+    lam, V, info = api.solve(ctx, M, X0, 32, 16, solver="tracemin", strategy="fix", max_iter=3000)
+    assert info.converged
+    exact = pins.laplacian_spectrum(64, 3, 32)
+    assert np.max(np.abs(lam - exact) / exact) <= 1e-9
+    cols = np.array([0, 5, 19, 31])
+    R = O.solvers._apply(A.to_scipy(), V[:, cols]) - V[:, cols] * lam[cols][None, :]
+    assert np.max(np.linalg.norm(R, axis=0) / (A.anorm * np.linalg.norm(V[:, cols], axis=0))) <= 1e-8 * 1.0001
+    assert np.abs(V.T @ V - np.eye(32)).max() <= 1e-11
