@@ -495,3 +495,11 @@ def test_scalar_preconditioner_leaves_lobpcg_unchanged():
     rb = np.array([h["r"] for h in b.history])
     assert len(ra) == len(rb)
     np.testing.assert_allclose(ra, rb, rtol=1e-6)
+
+
+def test_tracemin_with_random_expansion_vectors_reaches_the_closed_form():
+    A, X0, nb, n_es, draw = _expand_case(20, 6, 6, 5)
+    res = O.tracemin(A.to_scipy(), X0, 6, A.anorm, tol=1e-8, n_es=n_es,
+                     se=O.SEParams("fix", r_warm=1e-2), expand_vectors="random", random_block=draw)
+    assert res.converged and res.n_expands >= 1
+    assert _check(res, A, pins.laplacian_spectrum(20, 2, 6), lam_rtol=1e-9) == []
