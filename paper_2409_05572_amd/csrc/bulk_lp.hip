@@ -724,17 +724,18 @@ __global__ __launch_bounds__(kThreads, 2) void gram_lp_kernel(long long n, SegsT
 }
 
 // ---------------------------------------------------------------------------
-// Basis update Out = beta Out + alpha U C (C in FP64, rounded to FP32 in LDS):
-// the FP64 kernel's tiling (64 rows x 16 NT columns per workgroup, K streamed
-// UK at a time with register prefetch), FP32 MFMAs folded into FP64 every
-// UFLUSH stages.
+// Basis update Out = beta Out + alpha U C (C given in FP64, rounded to FP32
+// once per call into a K x N scratch that every workgroup streams): the FP64
+// kernel's tiling (64 rows x 16 NT columns per workgroup, K streamed UK at a
+// time with register prefetch), FP32 MFMAs folded into FP64 every UFLUSH
+// stages.
 constexpr int UM = 64;
 constexpr int UK = 32;
 constexpr int UFLUSH = 2;
 
 template <class T, int NT>
 __global__ __launch_bounds__(kThreads, 2) void update_lp_kernel(long long n, SegsT<T> U, int K,
-                                                             const double* __restrict__ C, int N,
+                                                             const float* __restrict__ C, int N,
                                                              SegsT<T> O, float alpha, float beta,
                                                              int ntn) {
     constexpr int BN = 16 * NT;
@@ -778,7 +779,7 @@ __global__ __launch_bounds__(kThreads, 2) void update_lp_kernel(long long n, Seg
             const int e = threadIdx.x + kThreads * q;
             const int kk = e / BN, c = e % BN;
             const int kc = k0 + kk;
-            rc[q] = (kc < K && n0 + c < N) ? (float)C[(long long)kc * N + n0 + c] : 0.f;
+            rc[q] = (kc < K && n0 + c < N) ? C[(long long)kc * N + n0 + c] : 0.f;
         }
     };
     auto stash = [&]() {
@@ -831,7 +832,7 @@ __global__ __launch_bounds__(kThreads, 2) void update_lp_kernel(long long n, Seg
 }
 
 template <class T, int NT>
-void update_lp_launch(hipStream_t st, long long n, const SegsT<T>& U, int K, const double* C, int N,
+void update_lp_launch(hipStream_t st, long long n, const SegsT<T>& U, int K, const float* C, int N,
                       const SegsT<T>& O, double alpha, double beta) {
     constexpr int BN = 16 * NT;
     const int ntn = (N + BN - 1) / BN;
@@ -973,10 +974,15 @@ hipError_t launch_gram_lp(hipStream_t st, long long n, const SegsT<T>& U, const 
 }
 
 template <class T>
-hipError_t launch_update_lp(hipStream_t st, long long n, const SegsT<T>& U, const double* C, int N,
-                            const SegsT<T>& O, double alpha, double beta) {
+hipError_t launch_update_lp(hipStream_t st, long long n, const SegsT<T>& U, const double* C64, int N,
+                            const SegsT<T>& O, double alpha, double beta, float* C) {
     const int K = segs_width(U);
     if (N <= 0 || n <= 0 || K <= 0) return hipSuccess;
+    if (!C) return hipErrorInvalidValue;
+    {
+        const hipError_t e = launch_f64_to_f32(st, (long long)K * N, C64, C);
+        if (e != hipSuccess) return e;
+    }
     const int need = (N + 15) / 16;
     const int nct = (need + 7) / 8;
     switch ((need + nct - 1) / nct) {
@@ -1021,7 +1027,7 @@ hipError_t launch_f64_to_f32(hipStream_t st, long long count, const double* src,
     template hipError_t launch_gram_lp<T>(hipStream_t, long long, const SegsT<T>&, const SegsT<T>&, int,    \
                                           double*, double*);                                              \
     template hipError_t launch_update_lp<T>(hipStream_t, long long, const SegsT<T>&, const double*, int,   \
-                                            const SegsT<T>&, double, double);
+                                            const SegsT<T>&, double, double, float*);
 
 SE_LP_INSTANTIATE(float)
 SE_LP_INSTANTIATE(bf16_t)

@@ -43,7 +43,9 @@ hipError_t update_lp_call(se_ctx* ctx, int64_t n, const void* U, int64_t ldu, in
     se::SegsT<T> Us = se::make_segs_t<T>(ldu), Os = se::make_segs_t<T>(ldo);
     se::push_seg_t(Us, static_cast<const T*>(U), K);
     se::push_seg_t(Os, static_cast<const T*>(Out), N);
-    return se::launch_update_lp<T>(ctx->stream, n, Us, C, N, Os, 1.0, beta);
+    const hipError_t e = ctx->ws.c32.ensure(sizeof(float) * (size_t)K * N);
+    if (e != hipSuccess) return e;
+    return se::launch_update_lp<T>(ctx->stream, n, Us, C, N, Os, 1.0, beta, ctx->ws.c32.as<float>());
 }
 }  // namespace
 

@@ -239,9 +239,10 @@ hipError_t launch_rows_lp_to_f64(hipStream_t st, long long n, int w, const T* sr
 template <class T>
 hipError_t launch_gram_lp(hipStream_t st, long long n, const SegsT<T>& U, const SegsT<T>& V, int sym,
                           double* part, double* C);
+// c32: scratch of K x N floats (K = width of U) that receives C rounded to FP32.
 template <class T>
 hipError_t launch_update_lp(hipStream_t st, long long n, const SegsT<T>& U, const double* C, int N,
-                            const SegsT<T>& O, double alpha, double beta);
+                            const SegsT<T>& O, double alpha, double beta, float* c32);
 hipError_t launch_f64_to_f32(hipStream_t st, long long count, const double* src, float* dst);
 
 // ---- small dense kernels (small.hip), one matrix per call, FP64 ----

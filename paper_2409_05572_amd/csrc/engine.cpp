@@ -1153,6 +1153,8 @@ struct Solver {
             lp[i] = ws.lp_panel[i].p;
         }
         HC(make_val32(st, A));
+        const size_t mm = (size_t)3 * nb * 3 * nb;  // largest K x N of an update
+        HC(ws.c32.ensure(sizeof(float) * mm));
         return SE_OK;
     }
     template <class T>
@@ -1179,7 +1181,7 @@ struct Solver {
     se_status lp_update(const SegsT<T>& U, const double* C, int N, const SegsT<T>& O, double alpha,
                         double beta) {
         ST(tic());
-        HC(launch_update_lp<T>(st, n, U, C, N, O, alpha, beta));
+        HC(launch_update_lp<T>(st, n, U, C, N, O, alpha, beta, ws.c32.as<float>()));
         const double K = segs_width(U);
         return toc(SE_K_UPDATE, (double)sizeof(T) * n * (K + N * (beta != 0.0 ? 2.0 : 1.0)),
                    2.0 * n * K * N);
@@ -1736,7 +1738,8 @@ size_t solve_workspace_bytes(long long n, long long nnz, int nb, int precision, 
                    (solver == SE_LOBPCG || solver == SE_SD ? (size_t)n : 0);  // Jacobi diagonal
     if (precision != SE_FP64) {
         const size_t es = precision == SE_FP32_MIXED ? 4 : 2;
-        bytes += es * (size_t)kNumLpPanels * n * ld + sizeof(float) * ((size_t)nnz + kCsrPad);
+        bytes += es * (size_t)kNumLpPanels * n * ld + sizeof(float) * ((size_t)nnz + kCsrPad) +
+                 sizeof(float) * (size_t)9 * nb * nb;
     }
     return bytes + sizeof(double) * small;
 }

@@ -73,6 +73,7 @@ struct Workspace {
     DevBuf wfold, cfold;                  // last Cholesky-QR transform of W, folded coefficients
     DevBuf cg;                            // TraceMIN inner CG: per-column rr, rr_new, d^T q
     DevBuf pc;                            // Jacobi preconditioner diag(1 / |a_ii|) (n doubles)
+    DevBuf c32;                           // coefficients of a low-precision update rounded to FP32
     HostBuf h_norms, h_info, h_act, h_act_hl, h_theta, h_diag;
     std::vector<hipEvent_t> events;  // pool for per-launch timing
     size_t device_bytes() const {
@@ -82,7 +83,7 @@ struct Workspace {
         const DevBuf* all[] = {&gram_part, &G, &T, &Z, &theta, &C, &small_work, &syev_work,
                                &lam, &act, &act_hl, &norms, &info, &hlB, &hlY, &hlG, &hlQ,
                                &lpM, &lpT, &lpQ, &lpB, &lpE, &lpC, &apc, &axp, &axq, &gw, &idx,
-                               &wfold, &cfold, &cg, &pc};
+                               &wfold, &cfold, &cg, &pc, &c32};
         for (auto* b : all) s += b->bytes;
         return s;
     }
@@ -92,7 +93,7 @@ struct Workspace {
         DevBuf* all[] = {&gram_part, &G, &T, &Z, &theta, &C, &small_work, &syev_work,
                          &lam, &act, &act_hl, &norms, &info, &hlB, &hlY, &hlG, &hlQ,
                          &lpM, &lpT, &lpQ, &lpB, &lpE, &lpC, &apc, &axp, &axq, &gw, &idx,
-                         &wfold, &cfold, &cg, &pc};
+                         &wfold, &cfold, &cg, &pc, &c32};
         for (auto* b : all) b->release();
         h_norms.release();
         h_info.release();
