@@ -35,7 +35,8 @@ hipError_t gram_lp_call(se_ctx* ctx, int64_t n, const void* U, int64_t ldu, int3
     se::SegsT<T> Us = se::make_segs_t<T>(ldu), Vs = se::make_segs_t<T>(ldv);
     se::push_seg_t(Us, static_cast<const T*>(U), mu);
     se::push_seg_t(Vs, static_cast<const T*>(V), mv);
-    return se::launch_gram_lp<T>(ctx->stream, n, Us, Vs, 0, ctx->ws.gram_part.as<double>(), C);
+    const int sym = (U == V && ldu == ldv && mu == mv) ? 1 : 0;  // U^T U: upper tiles only, mirrored
+    return se::launch_gram_lp<T>(ctx->stream, n, Us, Vs, sym, ctx->ws.gram_part.as<double>(), C);
 }
 template <class T>
 hipError_t update_lp_call(se_ctx* ctx, int64_t n, const void* U, int64_t ldu, int32_t K, const double* C,

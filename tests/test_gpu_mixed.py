@@ -133,6 +133,26 @@ def test_gram_lp_within_fp32_accumulation_bound(ctx, fmt, n, mu, mv):
     assert np.all(np.abs(C.cpu().numpy() - ref) <= bound)
 
 
+@pytest.mark.parametrize("fmt", ["fp32", "bf16"])
+@pytest.mark.parametrize("n,m", [(1000, 5), (20001, 96), (20001, 150), (30001, 250)])
+def test_symmetric_gram_lp_within_bound(ctx, fmt, n, m):
+    """U^T U (the same block twice): only output tiles on or above the
+    diagonal are formed and the reduction mirrors them; the result is
+    symmetric and within the FP32 accumulation bound of the stored values."""
+    import torch
+
+    from paper_2409_05572_amd import api
+
+    rng = np.random.default_rng(n + m)
+    U, Us = _block(rng.standard_normal((n, m)), fmt)
+    C = torch.zeros((m, m), dtype=torch.float64, device="cuda")
+    api.gram_lp(ctx, U, m, U, m, C)
+    got = C.cpu().numpy()
+    ref = Us.T @ Us
+    assert np.all(np.abs(got - ref) <= 70 * U32 * (abs(Us).T @ abs(Us)))
+    assert np.array_equal(got, got.T)
+
+
 def test_gram_lp_is_deterministic(ctx):
     import torch
 
