@@ -49,3 +49,25 @@ def test_traffic_figure_only_for_unchanged_kernel_source(tmp_path, monkeypatch):
     src.write_text("kernel v2\n")
     assert bench.measured_traffic("update", "w") is None
     assert bench.measured_traffic("gram", "w") is None
+
+
+def test_cpu_baseline_leg_runs_every_solver_option():
+    """The oracle leg of the benchmark accepts each solver with the options it
+    forwards (expansion vectors, filter degree, preconditioner) and reports a
+    bounded sample in the contract's fields."""
+    import argparse
+
+    import workloads as W
+
+    A = W.laplacian_2d(12)
+    X0 = W.gaussian_block(A.n, 8, 3)
+    cases = [dict(solver="lobpcg", precond="jacobi"), dict(solver="sd", expand_vectors="random"),
+             dict(solver="si", filter_degree=4, expand_vectors="powered"), dict(solver="tracemin")]
+    for c in cases:
+        args = argparse.Namespace(n_ev=4, n_extra=4, strategy="fix", cpu_seconds=0.5, x0_seed=3,
+                                  expand_vectors="xdrop", filter_degree=0, precond="none")
+        for k, v in c.items():
+            setattr(args, k, v)
+        out = bench.cpu_baseline(A, X0, args, 20, lambda *a: None)
+        assert out["kind"] == "oracle" and out["value"] >= 0 and out["cores"] >= 1, c
+        assert "iteration" in out["sample"]
