@@ -100,10 +100,11 @@ typedef struct se_matrix se_matrix;
  * [X, P, W] in coefficient space) */
 
 /* Kernel classes of se_info.kern_* */
-#define SE_K_SPMM 0   /* CSR sparse x block */
+#define SE_K_SPMM 0   /* CSR sparse x block (also fused with a Chebyshev filter step) */
 #define SE_K_GRAM 1   /* tall-skinny Gram products and their fixed-order reduction */
 #define SE_K_UPDATE 2 /* basis updates X <- S C, W <- W - [X,P] G, Cholesky-QR apply */
-#define SE_K_RESID 3  /* residual norms, forming W, shifted power step */
+#define SE_K_RESID 3  /* residual norms, forming W, shifted power step, Chebyshev filter steps,
+                         TraceMIN's column CG kernels, Jacobi scaling */
 #define SE_K_EIG 4    /* dense eigensolve of the projected matrix */
 #define SE_K_SMALL 5  /* Cholesky-QR transform and Hetmaniuk-Lehoucq coefficients */
 #define SE_K_COPY 6   /* layout changes and column copies */
