@@ -130,3 +130,37 @@ def test_destroy_with_queued_requests_returns(ctx):
         keep.append((M, x0, srv.submit(M, x0, s["n_ev"], s["n_extra"])))
     srv.close()  # finishes the running solve, drops the queued ones
     torch.cuda.synchronize()
+
+
+def test_every_solver_served_identically_to_a_lone_solve(ctx):
+    """Requests for each solver and option (Chebyshev-filtered SI with a
+    powered X_drop, TraceMIN, Jacobi-preconditioned LOBPCG, SD with random
+    expansions) share the server and return bitwise what a lone se_solve
+    returns."""
+    import torch
+
+    from paper_2409_05572_amd import api
+
+    A = W.laplacian_3d(16)  # positive definite (TraceMIN needs it)
+    M = api.Matrix.from_csr(ctx, A)
+    opts = [dict(solver="si", filter_degree=6, expand_vectors="powered"), dict(solver="tracemin"),
+            dict(solver="lobpcg", precond="jacobi"), dict(solver="sd", expand_vectors="random", seed=5)]
+    alone = []
+    for i, o in enumerate(opts):
+        lam, V, info = api.solve(ctx, M, _x0(A.n, 16, 40 + i), 10, 6, strategy="fix", n_es=12,
+                                 max_iter=4000, **o)
+        assert info.converged, o
+        alone.append((lam.cpu().numpy(), V.cpu().numpy()))
+    srv = api.Server(ctx, hbm_budget_bytes=16 << 30, max_slots=4)
+    try:
+        tickets = []
+        for i, o in enumerate(opts):
+            x0 = _x0(A.n, 16, 40 + i)
+            torch.cuda.synchronize()
+            tickets.append(srv.submit(M, x0, 10, 6, strategy="fix", n_es=12, max_iter=4000, **o))
+        for (t, lam, V), (lam0, V0), o in zip(tickets, alone, opts):
+            info, _, _ = srv.wait(t)
+            assert info.converged, o
+            assert np.array_equal(lam.cpu().numpy(), lam0) and np.array_equal(V.cpu().numpy(), V0), o
+    finally:
+        srv.close()
