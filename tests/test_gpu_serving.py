@@ -37,6 +37,20 @@ def test_footprint_covers_the_workspace_of_a_solve(ctx):
         assert info.workspace_bytes <= fp <= 1.3 * info.workspace_bytes + (1 << 20)
 
 
+@pytest.mark.parametrize("solver,opts", [("si", dict(filter_degree=4, expand_vectors="powered")),
+                                         ("tracemin", {}), ("lobpcg", dict(precond="jacobi")),
+                                         ("sd", dict(precond="jacobi"))])
+def test_footprint_covers_every_solver(ctx, solver, opts):
+    from paper_2409_05572_amd import api
+
+    c = api.Context(0)  # fresh workspace
+    A = W.laplacian_3d(14)
+    M = api.Matrix.from_csr(c, A)
+    _, _, info = api.solve(c, M, _x0(A.n, 12, 3), 8, 4, strategy="fix", solver=solver, max_iter=4000, **opts)
+    fp = api.footprint(A.n, A.nnz, 8, 4, solver=solver)
+    assert info.workspace_bytes <= fp <= 1.3 * info.workspace_bytes + (1 << 20)
+
+
 def test_results_identical_alone_and_in_the_mix(ctx):
     import torch
 
