@@ -16,11 +16,14 @@ Modules:
   decisions (Algorithms 6 and 7, Section 3.2) with the warm-up rule.
 * ``solvers``  - convergence measures (eqs. (conv) and (rk), Section 6.1),
   LOBPCG with soft locking and the Hetmaniuk-Lehoucq basis (Algorithm 3),
-  and subspace iteration (Algorithm 1), both with shrink-and-expand
-  (Algorithm 5).
-* ``mixed``    - the same solvers with a low-precision phase (blocks stored in
-  FP32 or BF16, Rayleigh-Ritz with the FP64 Gram matrix M = S^T S) followed by
-  the FP64 solver.
+  subspace iteration (Algorithm 1, optionally with a Chebyshev filter), block
+  steepest descent (Algorithm 2) and TraceMIN with its projected CG
+  (Algorithm 4), all with shrink-and-expand (Algorithm 5), the three kinds of
+  expansion vectors of Section 6 and, for LOBPCG and SD, a preconditioner.
+* ``mixed``    - LOBPCG and subspace iteration (with the filter and the powered
+  X_drop) with a low-precision phase (blocks stored in FP32 or BF16,
+  Rayleigh-Ritz with the FP64 Gram matrix M = S^T S) followed by the FP64
+  solver.
 
 Pins: see ``tests/test_oracle_*.py``. Parity unpinned (no closed form, checked
 only by invariants and by agreement with brute force at small sizes): the
