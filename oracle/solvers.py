@@ -6,6 +6,8 @@ Follows the paper (arXiv 2409.05572):
 * LOBPCG, Algorithm 3 (Section 2.3), with soft locking and the improved
   Hetmaniuk-Lehoucq choice of P (Section 2.3 text), preconditioner T = I as in
   the experiments (Section 6.2);
+* TraceMIN, Algorithm 4 (Section 2.4), with a projected conjugate-gradient
+  inner solve;
 * the shrink-and-expand framework, Algorithm 5 (Section 3.1), with the
   strategies of Section 3.2 (see ``strategy.py``);
 * the per-pair stopping test, eq. (conv), and the overall relative residual
@@ -32,6 +34,9 @@ Readings of points the paper leaves open (each also listed in the design notes):
   orthonormalized; columns that come from X_drop go to X, the rest to P.
 * Orthogonalization drops columns whose norm after projection falls below
   ``drop_tol`` times their norm before it.
+* Beyond the paper's experiments: a Chebyshev filter for subspace iteration
+  (Zhou and Saad) in place of its shift-invert operator, and a diagonal
+  (Jacobi) preconditioner T for the W <- T R step of LOBPCG and SD.
 * Expansion vectors (Section 6, the vectors appended in the expansion):
   ``expand_vectors="xdrop"`` appends the vectors dropped at the last shrink;
   ``"random"`` appends a normally distributed block of the same width,
