@@ -252,6 +252,18 @@ se_status se_op_spmm(se_ctx* ctx, const se_matrix* A, const double* X, int64_t l
 se_status se_op_gram(se_ctx* ctx, int64_t n, const double* U, int64_t ldu, int32_t mu,
                      const double* V, int64_t ldv, int32_t mv, double* C);
 
+/* se_op_gram for callers that cannot allocate device memory (code under
+ * stream capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * same product C = U^T V with the same arguments, limits and errors, but the
+ * per-chunk partial products live in a fixed 32 MiB device array of the
+ * library (one per device, held until the process ends) instead of the
+ * context's workspace; the call never allocates. The row chunking is limited
+ * to what that array holds, so the summation order (not the accuracy) may
+ * differ from se_op_gram's for large n. Calls that overlap on one device
+ * (any context, any stream) share the array and race: serialize them. */
+se_status se_op_gram_noalloc(se_ctx* ctx, int64_t n, const double* U, int64_t ldu, int32_t mu,
+                             const double* V, int64_t ldv, int32_t mv, double* C);
+
 /* Out = beta * Out + U C: the basis updates X <- S Z, W <- W - [X,P] G and the
  * Cholesky-QR apply. U is n x K, C is K x N row-major (leading dimension N),
  * Out is n x N; 1 <= K, N <= 1024; beta is 0 or 1; Out must not overlap U. */

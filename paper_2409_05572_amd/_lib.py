@@ -78,6 +78,8 @@ PROTOTYPES = {
                              C.c_int64, C.c_int32]),
     "se_op_gram": (C.c_int, [C.c_void_p, C.c_int64, C.c_void_p, C.c_int64, C.c_int32,
                              C.c_void_p, C.c_int64, C.c_int32, C.c_void_p]),
+    "se_op_gram_noalloc": (C.c_int, [C.c_void_p, C.c_int64, C.c_void_p, C.c_int64, C.c_int32,
+                                     C.c_void_p, C.c_int64, C.c_int32, C.c_void_p]),
     "se_op_update": (C.c_int, [C.c_void_p, C.c_int64, C.c_void_p, C.c_int64, C.c_int32,
                                C.c_void_p, C.c_int32, C.c_void_p, C.c_int64, C.c_double]),
     "se_op_syev": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p]),

@@ -277,6 +277,13 @@ def gram(ctx: Context, U, mu: int, V, mv: int, out):
           "se_op_gram")
 
 
+def gram_noalloc(ctx: Context, U, mu: int, V, mv: int, out):
+    """C = U^T V through the entry point that allocates nothing (library-held scratch)."""
+    check(lib().se_op_gram_noalloc(ctx.handle, U.shape[0], C.c_void_p(_ptr(U)), U.stride(0), int(mu),
+                                   C.c_void_p(_ptr(V)), V.stride(0), int(mv), C.c_void_p(_ptr(out))),
+          "se_op_gram_noalloc")
+
+
 def update(ctx: Context, U, K: int, Cm, N: int, Out, beta: float = 0.0):
     check(lib().se_op_update(ctx.handle, U.shape[0], C.c_void_p(_ptr(U)), U.stride(0), int(K),
                              C.c_void_p(_ptr(Cm)), int(N), C.c_void_p(_ptr(Out)), Out.stride(0),

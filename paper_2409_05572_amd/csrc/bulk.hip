@@ -850,7 +850,7 @@ __global__ __launch_bounds__(kThreads) void gram_reduce_kernel(int mu, int mv, i
 }  // namespace
 
 void gram_plan(long long n, int mu, int mv, int sym, int& ntiles, int& nt_v, int& nchunks,
-               long long& rows) {
+               long long& rows, long long max_chunks) {
     const int nt_u = (mu + GT - 1) / GT;
     nt_v = (mv + GT - 1) / GT;
     ntiles = sym ? nt_u * (nt_u + 1) / 2 : nt_u * nt_v;
@@ -859,6 +859,7 @@ void gram_plan(long long n, int mu, int mv, int sym, int& ntiles, int& nt_v, int
     long long want = 1024 / ntiles;
     const long long maxc = (n + 255) / 256;        // at least 256 rows per chunk
     if (want > maxc) want = maxc;
+    if (max_chunks > 0 && want > max_chunks) want = max_chunks;  // bounded scratch
     if (want < 1) want = 1;
     rows = (n + want - 1) / want;
     rows = (rows + GK - 1) / GK * GK;
@@ -1170,13 +1171,15 @@ size_t gram_scratch_doubles(long long n, int mu, int mv) {
 }
 
 hipError_t launch_gram(hipStream_t st, long long n, const Segs& U, const Segs& V, int sym,
-                       double* part, double* C) {
+                       double* part, double* C, size_t part_cap) {
     const int mu = segs_width(U), mv = segs_width(V);
     if (mu <= 0 || mv <= 0) return hipSuccess;
     if (sym && mu != mv) sym = 0;
     int ntiles, nt_v, nchunks;
     long long rows;
-    gram_plan(n, mu, mv, sym, ntiles, nt_v, nchunks, rows);
+    const long long max_chunks = part_cap ? (long long)(part_cap / ((size_t)mu * (size_t)mv)) : 0;
+    if (part_cap && max_chunks < 1) return hipErrorInvalidValue;
+    gram_plan(n, mu, mv, sym, ntiles, nt_v, nchunks, rows, max_chunks);
     if (n <= 0) {
         hipMemsetAsync(C, 0, sizeof(double) * (size_t)mu * mv, st);
         return hipGetLastError();

@@ -173,10 +173,13 @@ hipError_t launch_rowmajor_to_colmajor(hipStream_t st, long long n, int w, const
 // Gram product C = U^T V (mu x mv row-major). With sym != 0 the result is
 // taken as symmetric (mu == mv): only upper tiles are formed, the lower
 // triangle mirrors the upper and diagonal tiles are averaged with their
-// transpose. part is scratch of gram_scratch_doubles(n, mu, mv) doubles.
+// transpose. part is scratch of gram_scratch_doubles(n, mu, mv) doubles, or,
+// with part_cap > 0, of part_cap doubles: the row chunks are then limited to
+// part_cap / (mu mv) (hipErrorInvalidValue when mu mv > part_cap), which only
+// changes the chunking (and so the summation order), not the result's bound.
 size_t gram_scratch_doubles(long long n, int mu, int mv);
 hipError_t launch_gram(hipStream_t st, long long n, const Segs& U, const Segs& V, int sym,
-                       double* part, double* C);
+                       double* part, double* C, size_t part_cap = 0);
 
 // Out = beta Out + alpha U C with C (K x N row-major, leading dimension N).
 // Out segments must not alias U segments.
@@ -195,7 +198,7 @@ constexpr int kGramRows = 32;
 // fixed-order FP64 sum of their per-chunk partials (C is mu x mv; with sym
 // the lower tile triangle mirrors the upper one).
 void gram_plan(long long n, int mu, int mv, int sym, int& ntiles, int& nt_v, int& nchunks,
-               long long& rows);
+               long long& rows, long long max_chunks = 0);
 hipError_t launch_gram_reduce(hipStream_t st, int mu, int mv, int nchunks, int sym, const double* part,
                               double* C);
 
