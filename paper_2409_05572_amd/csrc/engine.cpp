@@ -1710,15 +1710,20 @@ struct Solver {
 // Device workspace a solve of this shape allocates (the sizes of
 // Solver::alloc_panels, alloc_small and lp_alloc), plus the FP32 copy of the
 // matrix values for mixed precision.
+// The copy is made under the matrix's lock and published only once the
+// conversion on `st` has finished, so solves on other streams (serving slots)
+// that find it can use it at once.
 hipError_t make_val32(hipStream_t st, const se_matrix* A) {
+    std::lock_guard<std::mutex> lk(A->val32_mu);
     if (A->val32) return hipSuccess;
     float* v = nullptr;
     hipError_t e = hipMalloc(&v, sizeof(float) * ((size_t)A->nnz + kCsrPad));
     if (e != hipSuccess) return e;
     e = hipMemsetAsync(v + A->nnz, 0, sizeof(float) * kCsrPad, st);
     if (e == hipSuccess) e = launch_f64_to_f32(st, A->nnz, A->val, v);
+    const hipError_t es = hipStreamSynchronize(st);
+    if (e == hipSuccess) e = es;
     if (e != hipSuccess) {
-        (void)hipStreamSynchronize(st);
         (void)hipFree(v);
         return e;
     }

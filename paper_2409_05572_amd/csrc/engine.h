@@ -5,6 +5,7 @@
 
 #include <cmath>
 #include <cstdint>
+#include <mutex>
 #include <vector>
 
 #include "../../include/se.h"
@@ -156,6 +157,7 @@ struct se_matrix {
     int* col = nullptr;
     double* val = nullptr;
     mutable float* val32 = nullptr;  // FP32 copy for the mixed-precision phase, made on first use
+    mutable std::mutex val32_mu;     // guards the first-use creation of val32
     int* heavy = nullptr;  // rows with more than kHeavyRow nonzeros (one workgroup each in SpMM)
     int n_heavy = 0;
     double anorm = 0.0;

@@ -5,9 +5,12 @@
 // queue; the head request starts on a free slot as soon as the device
 // workspace held by all slots, after that slot grows to the request's
 // footprint, fits the HBM budget (the slot with the largest workspace that
-// needs the least growth is chosen). Different slots run their kernels on
-// different streams, so small solves overlap on the GPU; a solve's arithmetic
-// does not depend on what else runs, so results match a lone se_solve.
+// needs the least growth is chosen). When it does not fit, the other idle
+// slots give their workspace back (each on its own worker thread) and the
+// request is tried again; a request never waits on memory that only idle
+// slots hold. Different slots run their kernels on different streams, so
+// small solves overlap on the GPU; a solve's arithmetic does not depend on
+// what else runs, so results match a lone se_solve.
 #include <chrono>
 #include <condition_variable>
 #include <cstring>
@@ -43,6 +46,7 @@ struct Slot {
     std::thread worker;
     Request* job = nullptr;  // assigned request (nullptr = idle)
     uint64_t held = 0;       // device workspace held by the slot's context
+    bool trim = false;       // idle slot asked to release its workspace
 };
 
 }  // namespace
@@ -65,15 +69,19 @@ struct se_server {
         return s;
     }
 
-    // Assign queued requests to idle slots while the budget allows. Caller
-    // holds mu.
+    // Assign queued requests to idle slots while the budget allows. When the
+    // head request does not fit, the other idle slots are asked to release
+    // their workspace; each does so on its own thread and schedules again.
+    // Otherwise a running solve's end schedules again. Since a request's
+    // footprint is at most the budget, the head request always fits once
+    // nothing runs and the idle slots are trimmed. Caller holds mu.
     void schedule() {
         while (!queue.empty()) {
             Request* r = queue.front();
             int best = -1;
             uint64_t best_growth = UINT64_MAX;
             for (int i = 0; i < (int)slots.size(); ++i) {
-                if (slots[i].job) continue;
+                if (slots[i].job || slots[i].trim) continue;
                 const uint64_t growth = r->footprint > slots[i].held ? r->footprint - slots[i].held : 0;
                 if (growth < best_growth || (growth == best_growth && best >= 0 &&
                                              slots[i].held > slots[best].held)) {
@@ -81,8 +89,17 @@ struct se_server {
                     best_growth = growth;
                 }
             }
-            if (best < 0) return;                                // no idle slot
-            if (held_total() + best_growth > budget) return;     // wait for memory
+            if (best < 0) return;  // no idle slot (or only slots being trimmed)
+            if (best_growth > 0 && held_total() + best_growth > budget) {
+                bool asked = false;
+                for (int i = 0; i < (int)slots.size(); ++i)
+                    if (i != best && !slots[i].job && !slots[i].trim && slots[i].held > 0) {
+                        slots[i].trim = true;
+                        asked = true;
+                    }
+                if (asked) cv_work.notify_all();
+                return;  // wait for trimmed or finishing slots
+            }
             slots[best].held += best_growth;
             slots[best].job = r;
             queue.pop_front();
@@ -95,7 +112,19 @@ struct se_server {
         (void)hipSetDevice(device);
         std::unique_lock<std::mutex> lk(mu);
         for (;;) {
-            cv_work.wait(lk, [&] { return stop || slots[i].job != nullptr; });
+            cv_work.wait(lk, [&] { return stop || slots[i].job != nullptr || slots[i].trim; });
+            if (slots[i].trim && !slots[i].job) {
+                // give the workspace back (the slot's last solve has
+                // synchronized its stream), then retry the queue
+                lk.unlock();
+                (void)hipStreamSynchronize(slots[i].ctx->stream);
+                slots[i].ctx->ws.release();
+                lk.lock();
+                slots[i].held = 0;
+                slots[i].trim = false;
+                schedule();
+                continue;
+            }
             Request* r = slots[i].job;
             if (!r) return;  // stop with nothing assigned
             lk.unlock();
@@ -174,13 +203,8 @@ se_status se_submit(se_server* srv, const se_matrix* A, const se_params* params,
     r->footprint = se_solve_footprint(A->n, A->nnz, params->n_ev, params->n_extra, params->precision,
                                       params->solver);
     if (r->footprint > srv->budget) return SE_ERR_REJECTED;
-    if (params->precision != SE_FP64 && !A->val32) {
-        // the FP32 copy of the values is made here, once, not by concurrent solves
-        if (hipSetDevice(srv->device) != hipSuccess) return SE_ERR_HIP;
-        const hipError_t e = se::make_val32(nullptr, A);
-        if (e == hipErrorOutOfMemory) return SE_ERR_OOM;
-        if (e != hipSuccess || hipStreamSynchronize(nullptr) != hipSuccess) return SE_ERR_HIP;
-    }
+    // (a mixed-precision solve makes the matrix's FP32 values on its own slot
+    // stream, once per matrix, under the matrix's lock)
     std::lock_guard<std::mutex> lk(srv->mu);
     if (srv->stop) return SE_ERR_REJECTED;
     r->id = srv->next++;

@@ -178,3 +178,52 @@ def test_every_solver_served_identically_to_a_lone_solve(ctx):
             assert np.array_equal(lam.cpu().numpy(), lam0) and np.array_equal(V.cpu().numpy(), V0), o
     finally:
         srv.close()
+
+
+def test_idle_workspace_is_released_for_a_larger_request(ctx):
+    """Two small requests run at once and leave both slots holding workspace;
+    a larger request then fits the budget only if the other idle slot gives
+    its workspace back. It must start (no wait on memory only idle slots
+    hold) and converge."""
+    import time
+
+    import torch
+
+    import oracle as O
+    from paper_2409_05572_amd import api
+
+    small = [W.potential_laplacian(40, 2, 2.0, s) for s in (1, 2)]
+    big = W.potential_laplacian(56, 2, 2.0, 3)
+    fs = api.footprint(small[0].n, small[0].nnz, 8, 4)
+    fb = api.footprint(big.n, big.nnz, 8, 4)
+    budget = int(2.05 * fs)
+    assert fs < fb <= budget < fs + fb
+    srv = api.Server(ctx, hbm_budget_bytes=budget, max_slots=2)
+    try:
+        keep = []
+        for i, A in enumerate(small):
+            M = api.Matrix.from_csr(ctx, A)
+            x0 = _x0(A.n, 12, 10 + i)
+            torch.cuda.synchronize()
+            keep.append((M, x0, srv.submit(M, x0, 8, 4)))
+        for _, _, (t, _, _) in keep:
+            assert srv.wait(t)[0].converged
+        Mb = api.Matrix.from_csr(ctx, big)
+        xb = _x0(big.n, 12, 12)
+        torch.cuda.synchronize()
+        t, lam, V = srv.submit(Mb, xb, 8, 4)
+        deadline = time.monotonic() + 60.0
+        while not srv.poll(t):
+            assert time.monotonic() < deadline, "request waited on workspace held by idle slots"
+            time.sleep(0.01)
+        info, _, _ = srv.wait(t)
+        assert info.converged
+        lam, V = lam.cpu().numpy(), V.cpu().numpy().T
+        R = big.to_scipy() @ V - V * lam[None, :]
+        ratio = np.linalg.norm(R, axis=0) / (big.anorm * np.linalg.norm(V, axis=0))
+        assert ratio.max() <= 1e-8
+        ref = O.lobpcg(big.to_scipy(), W.gaussian_block(big.n, 12, 12), 8, big.anorm, tol=1e-8)
+        scale = np.maximum(np.abs(ref.lam), 1e-3 * big.anorm)
+        assert np.max(np.abs(lam - ref.lam) / scale) <= 1e-10
+    finally:
+        srv.close()
