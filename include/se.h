@@ -131,7 +131,7 @@ typedef struct se_params {
     double sigma;        /* SI shift, must bound lambda_max from above; 0 = ||A|| */
     double time_limit_s; /* wall-clock cap; <= 0 = none */
     double r_switch;     /* mixed precision: leave the low-precision phase once r(j) <= r_switch
-                            (or r(j) stops improving); 0 = 1e-5 (FP32), 1e-3 (BF16) */
+                            (or r(j) stops improving); 0 = 1e-5 (FP32), 4e-2 (BF16) */
     double implicit_pivot; /* FP64 LOBPCG: smallest scaled pivot of the Schur complement of W^T W
                               for which the residual block is orthonormalized implicitly (by
                               whitening in coefficient space) rather than projected and

@@ -1,8 +1,10 @@
 """Mixed-precision LOBPCG and subspace iteration (oracle; test infrastructure only).
 
 The paper points to lower-precision arithmetic for the bulk of the work as
-future work (concluding section). This oracle computes the scheme the library
-implements, in plain NumPy:
+future work (concluding section) and gives no scheme. This oracle computes,
+in plain NumPy, the scheme fixed by the readings below (the whitening drop
+threshold and the rule for leaving the low-precision phase are stated, with
+their grounds, beside their constants):
 
 * Low-precision phase. Every n-length block (X, P, W, their images under A,
   the dropped blocks) is stored rounded to FP32 or BF16 right after the step
@@ -15,10 +17,8 @@ implements, in plain NumPy:
   different factorization from the library's Cholesky, on purpose).
 * The Hetmaniuk-Lehoucq basis (Section 2.3) is built in the whitened
   coordinates from the old X columns.
-* The phase ends when r(j) <= r_switch, or - with the best r(j) within
-  100 r_switch - when r(j) exceeds ten times the best or has not improved for
-  15 iterations; then the FP64 solver continues from [X, X_drop] (LOBPCG also
-  keeps P).
+* The phase ends by ``SwitchRule`` (below); then the FP64 solver continues
+  from [X, X_drop] (LOBPCG also keeps P).
 * Subspace iteration: Y = sigma X - A X (plus X_drop at an expansion), then
   the same generalized Rayleigh-Ritz step on span(Y). With a Chebyshev filter
   of degree d (``filter_degree``) Y is p(A) X for the filter of
@@ -42,9 +42,54 @@ from . import solvers as S_
 from .strategy import SEController, SEParams
 
 U32 = 2.0 ** -24
+# Whitening drop threshold on the eigenvalues of the unit-scaled M = S^T S.
+# A stored column is known only to the storage format's relative rounding u,
+# so the part of a new column that is independent of the others, of relative
+# size delta, carries a relative error of about u / delta. Directions are kept
+# while delta^2 >= 450 u, the same threshold in units of u as the FP64
+# solvers' column drop (1e-13 ~ 450 u_64), so the kept directions are accurate
+# to u / delta <= sqrt(u) / 21.
 DROP = 450.0 * U32
+# Leaving the low-precision phase (the paper names lower precision for the
+# bulk work only as an outlook, so these are readings, not the paper's):
+# * r(j) <= r_switch. r(j) of a block stored with unit roundoff u cannot fall
+#   much below u: on the test workloads the phase floors at 0.5-1 u for BF16
+#   (u = 2^-9) and at 1.5-35 u for FP32 (u = 2^-24; the power-law graph is
+#   the worst). r_switch sits at least five times above the worst floor: FP32
+#   1e-5, BF16 4e-2 (about ten times BF16's machine epsilon 2^-8), so the phase
+#   ends on the threshold rather than on rounding noise.
+# * Once r(j) is within DIVERGE_ZONE r_switch of the threshold (the best value
+#   so far), two signs that the floor was reached after all also end it:
+#   r(j) > DIVERGE x best (noise drives the iteration away from its best
+#   iterate), or no new best for STALL iterations. STALL exceeds one
+#   shrink-and-expand cycle (j_e + j_s = 14 with the paper's parameters), so
+#   the transient of an expansion cannot trigger it.
+DEFAULT_SWITCH = {"fp32": 1e-5, "bf16": 4e-2}
+DIVERGE_ZONE = 100.0
+DIVERGE = 10.0
 STALL = 15
-DEFAULT_SWITCH = {"fp32": 1e-5, "bf16": 1e-3}
+
+
+class SwitchRule:
+    """When the low-precision phase ends, fed r(1), r(2), ... in order.
+
+    ``observe(j, r)`` records r(j) (the best value so far includes it) and
+    returns True at the iteration where the phase ends.
+    """
+
+    def __init__(self, r_switch):
+        self.r_switch = float(r_switch)
+        self.best = np.inf
+        self.j_best = 0
+
+    def observe(self, j, r):
+        if r < self.best:
+            self.best, self.j_best = r, j
+        if r <= self.r_switch:
+            return True
+        if self.best > DIVERGE_ZONE * self.r_switch:
+            return False  # early iterations may rise and stall far from the floor
+        return r > DIVERGE * self.best or j - self.j_best >= STALL
 
 
 def round_to(Y, fmt):
@@ -113,13 +158,6 @@ def _measures(X, AX, lam, anorm, n_ev):
     return R, stop, paper
 
 
-def _should_switch(r, best, j, j_best, r_switch):
-    if r <= r_switch:
-        return True
-    near = best <= 100.0 * r_switch
-    return near and (r > 10.0 * best or j - j_best >= STALL)
-
-
 def lobpcg_mixed(A, X0, n_ev, anorm, fmt="fp32", tol=1e-8, n_es=None, se: SEParams | None = None,
                  r_switch=None, max_iter=1000):
     """LOBPCG (Algorithm 3) with a low-precision phase, then FP64 LOBPCG.
@@ -142,7 +180,7 @@ def lobpcg_mixed(A, X0, n_ev, anorm, fmt="fp32", tol=1e-8, n_es=None, se: SEPara
     P = X[:, :0]
     AP = P.copy()
     Xd = Pd = AXd = APd = None
-    best, j_best = np.inf, 0
+    rule = SwitchRule(r_switch)
     hist = []
     j = 0
     for j in range(1, max_iter + 1):
@@ -150,12 +188,11 @@ def lobpcg_mixed(A, X0, n_ev, anorm, fmt="fp32", tol=1e-8, n_es=None, se: SEPara
         r = float(np.max(paper[:n_ev]))
         ctl.observe(j, r)
         hist.append(dict(j=j, r=r, k=X.shape[1], p=P.shape[1]))
-        if r < best:
-            best, j_best = r, j
+        leave = rule.observe(j, r)
         if np.all(stop[:n_ev] <= tol):
             res = S_.SolveResult(lam[:n_ev].copy(), X[:, :n_ev].copy(), j, True, hist)
             return res, j, hist
-        if _should_switch(r, best, j, j_best, r_switch):
+        if leave:
             break
         expand = ctl.ifexpand(j)
         k = X.shape[1]
@@ -227,7 +264,7 @@ def subspace_iteration_mixed(A, X0, n_ev, anorm, fmt="fp32", sigma=None, tol=1e-
 
     lam, X, AX = rr(rd(X0))
     Xd = None
-    best, j_best = np.inf, 0
+    rule = SwitchRule(r_switch)
     hist = []
     j = 0
     for j in range(1, max_iter + 1):
@@ -235,11 +272,10 @@ def subspace_iteration_mixed(A, X0, n_ev, anorm, fmt="fp32", sigma=None, tol=1e-
         r = float(np.max(paper[:n_ev]))
         ctl.observe(j, r)
         hist.append(dict(j=j, r=r, k=X.shape[1]))
-        if r < best:
-            best, j_best = r, j
+        leave = rule.observe(j, r)
         if np.all(stop[:n_ev] <= tol):
             return S_.SolveResult(lam[:n_ev].copy(), X[:, :n_ev].copy(), j, True, hist), j, hist
-        if _should_switch(r, best, j, j_best, r_switch):
+        if leave:
             break
         expand = ctl.ifexpand(j)
         filt = filter_degree > 0 and sigma > lam[-1]

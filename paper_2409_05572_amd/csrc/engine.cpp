@@ -1322,7 +1322,10 @@ struct Solver {
 
     double r_switch_value(double u) const {
         if (p.r_switch > 0.0) return p.r_switch;
-        return u < 1e-6 ? 1e-5 : 1e-3;
+        // Defaults: a few times above the lowest r(j) a block stored with
+        // unit roundoff u resolves (FP32: 1e-5; BF16: 4e-2, about ten times
+        // its machine epsilon 2^-8).
+        return u < 1e-6 ? 1e-5 : 4e-2;
     }
 
     // Widens the low-precision X (and X_drop) into the FP64 X panel and the

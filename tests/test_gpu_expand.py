@@ -46,8 +46,8 @@ def _assert_same_run(A, m, lam, V, info, ref, n_ev, rtol=1e-4, window=None):
     assert info.converged and ref.converged
     assert info.n_expands >= 1 and ref.n_expands >= 1
     exact = pins.laplacian_spectrum(m, 2, n_ev)
-    assert np.max(np.abs(lam - ref.lam) / ref.lam) <= 1e-9
-    assert np.max(np.abs(lam - exact) / exact) <= 1e-9
+    assert np.max(np.abs(lam - ref.lam) / ref.lam) <= 1e-10
+    assert np.max(np.abs(lam - exact) / exact) <= 1e-10
     R = O.solvers._apply(A.to_scipy(), V) - V * lam[None, :]
     assert np.max(np.linalg.norm(R, axis=0) / (A.anorm * np.linalg.norm(V, axis=0))) <= 1e-8 * 1.0001
     assert np.abs(V.T @ V - np.eye(n_ev)).max() <= 1e-12

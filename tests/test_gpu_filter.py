@@ -41,9 +41,9 @@ def _run(ctx, A, n_ev, n_extra, degree, strategy="none", n_es=0, kind="xdrop", x
 
 def _assert_same(A, lam, V, info, ref, exact, n_ev):
     assert info.converged and ref.converged
-    assert np.max(np.abs(lam - ref.lam) / np.abs(ref.lam)) <= 1e-9
+    assert np.max(np.abs(lam - ref.lam) / np.abs(ref.lam)) <= 1e-10
     if exact is not None:
-        assert np.max(np.abs(lam - exact) / np.abs(exact)) <= 1e-9
+        assert np.max(np.abs(lam - exact) / np.abs(exact)) <= 1e-10
     R = O.solvers._apply(A.to_scipy(), V) - V * lam[None, :]
     assert np.max(np.linalg.norm(R, axis=0) / (A.anorm * np.linalg.norm(V, axis=0))) <= 1e-8 * 1.0001
     assert np.abs(V.T @ V - np.eye(n_ev)).max() <= 1e-12
@@ -114,7 +114,7 @@ def test_filter_of_the_largest_degree(ctx):
     assert info.converged and ref.converged and info.iterations <= 3
     assert abs(info.iterations - ref.iterations) <= 1
     exact = pins.laplacian_spectrum(20, 2, 6)
-    assert np.max(np.abs(lam - exact) / exact) <= 1e-9
+    assert np.max(np.abs(lam - exact) / exact) <= 1e-10
     assert cluster_angles(lam, V, ref.V) <= 1e-6
 
 
@@ -154,8 +154,8 @@ def test_full_size_filtered_si_on_the_3d_laplacian(ctx):
     lam, V, info = api.solve(ctx, M, X0, 64, 32, solver="si", filter_degree=32, max_iter=500)
     assert info.converged
     exact = pins.laplacian_spectrum(128, 3, 64)
-    assert np.max(np.abs(lam - exact) / exact) <= 1e-9
+    assert np.max(np.abs(lam - exact) / exact) <= 1e-10
     cols = np.array([0, 1, 17, 40, 63])
     R = O.solvers._apply(A.to_scipy(), V[:, cols]) - V[:, cols] * lam[cols][None, :]
     assert np.max(np.linalg.norm(R, axis=0) / (A.anorm * np.linalg.norm(V[:, cols], axis=0))) <= 1e-8 * 1.0001
-    assert np.abs(V.T @ V - np.eye(64)).max() <= 1e-11
+    assert np.abs(V.T @ V - np.eye(64)).max() <= 1e-12

@@ -213,7 +213,7 @@ def test_config1_mixed_matches_closed_form(ctx, fmt, solver):
     assert np.all(lp_rows[: info.lp_iterations]) and not lp_rows[info.lp_iterations:].any()
     # the low-precision phase got r(j) down to r_switch or stalled there
     r_lp = h[lp_rows, 1]
-    assert r_lp.min() <= (1e-5 if fmt == "fp32" else 1e-3) * 100
+    assert r_lp.min() <= O.mixed.DEFAULT_SWITCH[fmt] * 100
 
 
 @pytest.mark.parametrize("fmt,strategy", [("fp32", "fix"), ("fp32", "slopek"), ("bf16", "fix")])
@@ -229,14 +229,18 @@ def test_3d_laplacian_mixed_with_shrink_expand(ctx, fmt, strategy):
         assert ((info.history[lp, 7].astype(int) & 2) != 0).any()
 
 
-def test_anderson_fp32_mixed_matches_fp64_oracle(ctx):
+@pytest.mark.parametrize("fmt", ["fp32", "bf16"])
+def test_anderson_mixed_matches_fp64_oracle(ctx, fmt):
+    """The indefinite Anderson matrix (3-D Laplacian plus a diagonal potential
+    U[-4, 4]) with a low-precision phase in FP32 or BF16: the pairs against
+    the FP64 oracle at the FP64 bars."""
     A = W.anderson_3d(14, 4.0, 103)
     X0 = W.gaussian_block(A.n, 30, 204)
-    lam, V, info = _solve(ctx, A, X0, 20, 10, precision="fp32", strategy="fix")
+    lam, V, info = _solve(ctx, A, X0, 20, 10, precision=fmt, strategy="fix")
     ref = O.lobpcg(A.to_scipy(), X0, 20, A.anorm, tol=1e-8)
-    assert info.converged
+    assert info.converged and info.lp_iterations >= 1
     scale = np.maximum(np.abs(ref.lam), 1e-3 * A.anorm)
-    assert np.max(np.abs(lam - ref.lam) / scale) <= 1e-9
+    assert np.max(np.abs(lam - ref.lam) / scale) <= 1e-10
     R = A.to_scipy() @ V - V * lam[None, :]
     assert np.max(np.linalg.norm(R, axis=0) / (A.anorm * np.linalg.norm(V, axis=0))) <= 1e-8 * 1.0001
 
@@ -259,29 +263,32 @@ def test_mixed_rejects_negative_switch_threshold(ctx):
         _solve(ctx, A, X0, 3, 3, precision="fp32", r_switch=-1.0)
 
 
-def _switch_iteration(r, r_switch, stall=15):
-    """First iteration (1-based) at which the rule for leaving the
-    low-precision phase fires on the sequence r(1), r(2), ...: r <= r_switch,
-    or, once the best r is within 100 r_switch, r > 10 x best or no new best
-    for `stall` iterations."""
-    best, j_best = np.inf, 0
+def _switch_iteration(r, r_switch):
+    """First iteration (1-based) at which the oracle's rule for leaving the
+    low-precision phase (pinned on scripted histories in the CPU tests) fires
+    on the sequence r(1), r(2), ..."""
+    rule = O.mixed.SwitchRule(r_switch)
     for j, v in enumerate(r, start=1):
-        if v < best:
-            best, j_best = v, j
-        if v <= r_switch or (best <= 100 * r_switch and (v > 10 * best or j - j_best >= stall)):
+        if rule.observe(j, v):
             return j
     return None
+
+
+# r(j) of the GPU and the oracle are compared where both lie well above the
+# floor of the stored format (FP32 <= 2e-6, BF16 <= 2e-3 on these workloads),
+# so that rounding differences between the two whitening factorizations do
+# not matter.
+ABOVE_FLOOR = {"fp32": 1e-4, "bf16": 2e-2}
 
 
 @pytest.mark.parametrize("fmt,solver", [("fp32", "lobpcg"), ("bf16", "lobpcg"), ("fp32", "si")])
 def test_mixed_matches_mixed_oracle(ctx, fmt, solver):
     """Same scheme on both sides (different whitening factorizations): the
     final pairs agree to the FP64 bar; r(j) of the two low-precision phases
-    agrees while it is well above r_switch, and each phase ends exactly where
-    the switch rule fires on its own history. The BF16 threshold (1e-3) lies
-    below BF16's unit roundoff, so where that phase ends depends on rounding
-    noise and its length is not compared; the FP32 phase ends well above
-    FP32's noise, so its length is."""
+    agrees while it is well above the format's floor, each phase ends exactly
+    where the switch rule fires on its own history, and the two phases have
+    the same length up to the iteration at which r(j) crosses r_switch (both
+    thresholds lie well above the floor)."""
     from tests.gpu_util import cluster_angles
 
     A = W.laplacian_2d(32)
@@ -300,12 +307,14 @@ def test_mixed_matches_mixed_oracle(ctx, fmt, solver):
     assert _switch_iteration(r_gpu, rsw) == info.lp_iterations
     assert _switch_iteration(r_ref, rsw) == lp_ref
     both = min(len(r_gpu), len(r_ref))
-    above = (r_gpu[:both] > 10 * rsw) & (r_ref[:both] > 10 * rsw)
+    above = (r_gpu[:both] > ABOVE_FLOOR[fmt]) & (r_ref[:both] > ABOVE_FLOOR[fmt])
     assert above.sum() >= 5
     ratio = r_gpu[:both][above] / r_ref[:both][above]
     assert np.all((ratio > 0.8) & (ratio < 1.25))
     if fmt == "fp32":
         assert abs(info.lp_iterations - lp_ref) <= max(5, 0.3 * lp_ref)
+    else:
+        assert abs(info.lp_iterations - lp_ref) <= 1
 
 
 @pytest.mark.parametrize("fmt,degree,kind,strategy", [("fp32", 3, "xdrop", "fix"), ("fp32", 3, "powered", "fix"),
@@ -328,7 +337,7 @@ def test_mixed_filtered_and_powered_si_match_mixed_oracle(ctx, fmt, degree, kind
                                                          expand_vectors=kind)
     assert info.converged and ref.converged and info.lp_iterations >= 2
     exact = pins.laplacian_spectrum(20, 2, 6)
-    assert np.max(np.abs(lam - exact) / exact) <= 1e-9
+    assert np.max(np.abs(lam - exact) / exact) <= 1e-10
     assert np.max(np.abs(lam - ref.lam) / np.abs(ref.lam)) <= 1e-10
     assert cluster_angles(lam, V, ref.V) <= 1e-6
     rsw = O.mixed.DEFAULT_SWITCH[fmt]
@@ -337,7 +346,7 @@ def test_mixed_filtered_and_powered_si_match_mixed_oracle(ctx, fmt, degree, kind
     r_ref = np.array([q["r"] for q in hist])[:lp_ref]
     assert _switch_iteration(r_gpu, rsw) == info.lp_iterations
     both = min(len(r_gpu), len(r_ref))
-    above = (r_gpu[:both] > 10 * rsw) & (r_ref[:both] > 10 * rsw)
+    above = (r_gpu[:both] > ABOVE_FLOOR[fmt]) & (r_ref[:both] > ABOVE_FLOOR[fmt])
     assert above.sum() >= 3
     ratio = r_gpu[:both][above] / r_ref[:both][above]
     assert np.all((ratio > 0.8) & (ratio < 1.25))
@@ -356,8 +365,8 @@ def test_full_size_fp32_filtered_si(ctx):
                              max_iter=500)
     assert info.converged and info.lp_iterations >= 2
     exact = pins.laplacian_spectrum(128, 3, 64)
-    assert np.max(np.abs(lam - exact) / exact) <= 1e-9
+    assert np.max(np.abs(lam - exact) / exact) <= 1e-10
     cols = np.array([0, 1, 17, 40, 63])
     R = A.to_scipy() @ V[:, cols] - V[:, cols] * lam[cols][None, :]
     assert np.max(np.linalg.norm(R, axis=0) / (A.anorm * np.linalg.norm(V[:, cols], axis=0))) <= 1e-8 * 1.0001
-    assert np.abs(V.T @ V - np.eye(64)).max() <= 1e-11
+    assert np.abs(V.T @ V - np.eye(64)).max() <= 1e-12

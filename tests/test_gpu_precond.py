@@ -51,8 +51,8 @@ def _run(ctx, A, solver, precond, n_ev=6, n_extra=6, n_es=8, rtol=1e-5):
             precond=O.jacobi_preconditioner(S) if precond == "jacobi" else None)
     exact = np.sort(np.linalg.eigvalsh(S.toarray()))[:n_ev]
     assert info.converged and ref.converged
-    assert np.max(np.abs(lam - exact) / np.abs(exact)) <= 1e-9
-    assert np.max(np.abs(lam - ref.lam) / np.abs(ref.lam)) <= 1e-9
+    assert np.max(np.abs(lam - exact) / np.abs(exact)) <= 1e-10
+    assert np.max(np.abs(lam - ref.lam) / np.abs(ref.lam)) <= 1e-10
     R = S @ V - V * lam[None, :]
     assert np.max(np.linalg.norm(R, axis=0) / (A.anorm * np.linalg.norm(V, axis=0))) <= 1e-8 * 1.0001
     assert np.abs(V.T @ V - np.eye(n_ev)).max() <= 1e-12

@@ -227,3 +227,45 @@ def test_idle_workspace_is_released_for_a_larger_request(ctx):
         assert np.max(np.abs(lam - ref.lam) / scale) <= 1e-10
     finally:
         srv.close()
+
+
+def test_served_results_match_the_oracle(ctx):
+    """Requests of the serving stream's kind (2-D and 3-D Laplacians with a
+    potential U[-2, 2], different n and n_ev) served together, each checked on
+    its own: the stopping test recomputed on the host with the oracle's
+    product, the eigenvalues against the FP64 oracle started from the same
+    block (error relative to max(|lambda|, 1e-3 ||A||)), the eigenvectors
+    through principal angles of complete clusters, orthonormality."""
+    import torch
+
+    import oracle as O
+    from paper_2409_05572_amd import api
+    from tests.gpu_util import cluster_angles
+
+    specs = W.serving_requests(5, seed=93, n_min=2e3, n_max=1.5e4, ev_min=4, ev_max=20)
+    reqs = [(W.potential_laplacian(s["m"], s["dim"], 2.0, s["pot_seed"]), s) for s in specs]
+    assert {s["dim"] for _, s in reqs} == {2, 3}
+    srv = api.Server(ctx, hbm_budget_bytes=16 << 30, max_slots=3)
+    try:
+        out = []
+        for A, s in reqs:
+            M = api.Matrix.from_csr(ctx, A)
+            x0 = _x0(A.n, s["n_ev"] + s["n_extra"], s["pot_seed"])
+            torch.cuda.synchronize()
+            out.append((A, s, M, x0, srv.submit(M, x0, s["n_ev"], s["n_extra"], strategy="fix")))
+        for A, s, M, x0, (t, lam, V) in out:
+            info, _, _ = srv.wait(t)
+            assert info.converged
+            lam, V = lam.cpu().numpy(), V.cpu().numpy().T
+            S = A.to_scipy()
+            R = O.solvers._apply(S, V) - V * lam[None, :]
+            ratio = np.linalg.norm(R, axis=0) / (A.anorm * np.linalg.norm(V, axis=0))
+            assert ratio.max() <= 1e-8 * 1.0001
+            X0 = W.gaussian_block(A.n, s["n_ev"] + s["n_extra"], s["pot_seed"])
+            ref = O.lobpcg(S, X0, s["n_ev"], A.anorm, tol=1e-8)
+            scale = np.maximum(np.abs(ref.lam), 1e-3 * A.anorm)
+            assert np.max(np.abs(lam - ref.lam) / scale) <= 1e-10
+            assert cluster_angles(lam, V, ref.V) <= 1e-6
+            assert np.abs(V.T @ V - np.eye(s["n_ev"])).max() <= 1e-12
+    finally:
+        srv.close()

@@ -58,7 +58,7 @@ def test_config1_subspace_iteration_matches_oracle(ctx):
     lam, V, info = _gpu_solve(ctx, A, X0, 8, 8, solver="si")
     ref = O.subspace_iteration(A.to_scipy(), X0, 8, A.anorm, tol=1e-8)
     assert info.converged
-    _assert_parity(A, lam, V, ref, pins.laplacian_spectrum(32, 2, 8), lam_rtol=1e-9)
+    _assert_parity(A, lam, V, ref, pins.laplacian_spectrum(32, 2, 8), lam_rtol=1e-10)
     assert abs(info.iterations - ref.iterations) <= max(3, ref.iterations // 20)
 
 
@@ -71,7 +71,7 @@ def test_lobpcg_shrink_expand_3d_matches_oracle(ctx, strategy):
     ref = O.lobpcg(A.to_scipy(), X0, n_ev, A.anorm, tol=1e-8, n_es=n_ev + 5,
                    se=O.SEParams(strategy))
     assert info.converged
-    _assert_parity(A, lam, V, ref, pins.laplacian_spectrum(m, 3, n_ev), lam_rtol=1e-9)
+    _assert_parity(A, lam, V, ref, pins.laplacian_spectrum(m, 3, n_ev), lam_rtol=1e-10)
     if strategy != "none":
         assert info.n_shrinks >= 1
         hist = info.history
@@ -89,7 +89,7 @@ def test_si_shrink_expand_matches_oracle(ctx, strategy):
     ref = O.subspace_iteration(A.to_scipy(), X0, n_ev, A.anorm, tol=1e-8, n_es=n_ev + 2,
                                se=O.SEParams(strategy))
     assert info.converged and info.n_shrinks >= 1
-    _assert_parity(A, lam, V, ref, pins.laplacian_spectrum(m, 2, n_ev), lam_rtol=1e-9)
+    _assert_parity(A, lam, V, ref, pins.laplacian_spectrum(m, 2, n_ev), lam_rtol=1e-10)
 
 
 def test_anderson_small_matches_oracle(ctx):
@@ -274,19 +274,32 @@ def test_invalid_implicit_pivot_is_rejected(ctx):
 
 
 def test_full_config2_lobpcg_shrink_expand(ctx):
-    """3-D 128^3 Laplacian, 64 wanted + 32 extra, fix strategy, at full size:
-    every eigenvalue against the closed form; the stopping test recomputed on
-    the host with the oracle's product for sampled eigenvectors."""
+    """3-D 128^3 Laplacian, 64 wanted + 32 extra, fix strategy, at full size
+    and in the launch configuration the benchmark times: every eigenvalue
+    against the closed form, within 1e-10 and within the per-pair bound
+    |theta - lambda| <= ||r||^2 / gap (gap to the nearest eigenvalue outside
+    the pair's cluster, from the closed form); the stopping test recomputed
+    on the host with the oracle's product for all 64 eigenvectors (in row
+    chunks); orthonormality of the returned block."""
     A = W.laplacian_3d(128)
     X0 = W.gaussian_block(A.n, 96, 202)
     lam, V, info = _gpu_solve(ctx, A, X0, 64, 32, strategy="fix")
     assert info.converged and info.n_shrinks >= 1
-    exact = pins.laplacian_spectrum(128, 3, 64)
-    assert np.max(np.abs(lam - exact) / exact) <= 1e-9
-    cols = np.array([0, 1, 17, 40, 63])
-    r = _residual_ratio(A, lam[cols], V[:, cols])
-    assert np.max(r) <= 1e-8 * 1.0001
-    assert np.abs(V.T @ V - np.eye(64)).max() <= 1e-11
+    exact_all = pins.laplacian_spectrum(128, 3, 100)
+    exact = exact_all[:64]
+    assert np.max(np.abs(lam - exact) / exact) <= 1e-10
+    S = A.to_scipy()
+    rn = np.zeros(64)
+    for c0 in range(0, 64, 16):  # column chunks keep the host copy of A V small
+        R = S @ V[:, c0:c0 + 16] - V[:, c0:c0 + 16] * lam[None, c0:c0 + 16]
+        rn[c0:c0 + 16] = np.linalg.norm(R, axis=0)
+    xn = np.linalg.norm(V, axis=0)
+    assert np.max(rn / (A.anorm * xn)) <= 1e-8 * 1.0001
+    for i in range(64):
+        others = exact_all[np.abs(exact_all - exact[i]) > 1e-9 * exact[i]]
+        gap = np.min(np.abs(others - lam[i]))
+        assert abs(lam[i] - exact[i]) <= max(1e-13 * exact[i], (rn[i] / xn[i]) ** 2 / gap)
+    assert np.abs(V.T @ V - np.eye(64)).max() <= 1e-12
 
 
 def test_matrix_released_after_its_context(ctx):

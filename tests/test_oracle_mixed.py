@@ -4,7 +4,9 @@ Storage rounding is checked against hand-derived values; the generalized
 Rayleigh-Ritz step against SciPy's generalized symmetric eigensolver and
 against plain Rayleigh-Ritz on an orthonormalized basis; the HL directions
 against their defining properties; whole solves against the closed-form
-Laplacian spectrum. A planted mistake (ignoring M) must fail the checks.
+Laplacian spectrum; the rule that ends the low-precision phase against
+hand-derived exit iterations on scripted r(j) histories. Planted mistakes
+(ignoring M; variants of the exit rule) must fail the checks.
 """
 import numpy as np
 import pytest
@@ -143,3 +145,149 @@ def test_mixed_filtered_and_powered_si_reach_closed_form(fmt, degree, kind):
     assert res.converged and j_lp >= 2
     exact = pins.laplacian_spectrum(m, 2, n_ev)
     np.testing.assert_allclose(res.lam, exact, rtol=1e-9)
+
+
+# --- the rule that ends the low-precision phase, on scripted r(j) histories ---
+#
+# Each expected iteration below is worked out by hand from the rule as stated
+# beside the oracle's constants: leave at the first j with r(j) <= r_switch;
+# once the best r so far is within 100 r_switch, also leave when r(j) exceeds
+# ten times that best or when no new best has come for 15 iterations.
+
+
+def _leave_at(rs, r_switch, rule_cls=None):
+    rule = (rule_cls or M_.SwitchRule)(r_switch)
+    for j, r in enumerate(rs, start=1):
+        if rule.observe(j, r):
+            return j
+    return None
+
+
+def test_switch_on_threshold():
+    # 2^-j <= 1e-3 first at j = 10 (2^-10 = 9.77e-4; 2^-9 = 1.95e-3)
+    assert _leave_at([2.0 ** -j for j in range(1, 40)], 1e-3) == 10
+    # equality leaves: r(4) = r_switch exactly
+    assert _leave_at([0.5, 0.25, 0.125, 0.0625, 0.03], 0.0625) == 4
+
+
+def test_switch_on_divergence_near_the_floor():
+    # best 2e-3 at j = 5 (within 100 x 1e-3); 4e-3, 1e-2 and 1.5e-2 stay at or
+    # below 10 x best = 2e-2; 2.5e-2 at j = 9 exceeds it.
+    rs = [1e-1, 5e-2, 1e-2, 5e-3, 2e-3, 4e-3, 1e-2, 1.5e-2, 2.5e-2, 1e-3]
+    assert _leave_at(rs, 1e-3) == 9
+    # exactly ten times the best does not leave (strict); the next rise does
+    rs = [1e-1, 2e-3, 2e-2, 2.0000001e-2]
+    assert _leave_at(rs, 1e-3) == 4
+
+
+def test_switch_on_stall_near_the_floor():
+    # best 5e-3 at j = 3; then 6e-3 forever: 15 iterations without a new best
+    # is j = 3 + 15 = 18.
+    rs = [1e-1, 1e-2, 5e-3] + [6e-3] * 30
+    assert _leave_at(rs, 1e-3) == 18
+    # a new best at j = 10 restarts the count: 10 + 15 = 25
+    rs = [1e-1, 1e-2, 5e-3] + [6e-3] * 6 + [4e-3] + [6e-3] * 30
+    assert _leave_at(rs, 1e-3) == 25
+    # a new best exactly when the count would run out (j = 18 = 3 + 15) counts
+    # first: the phase goes on until 18 + 15 = 33
+    rs = [1e-1, 1e-2, 5e-3] + [6e-3] * 14 + [4e-3] + [6e-3] * 30
+    assert _leave_at(rs, 1e-3) == 33
+
+
+def test_no_divergence_or_stall_exit_far_from_the_floor():
+    # best stays above 100 x 1e-3 = 0.1 until j = 25: the rise at j = 2 (20 x
+    # best) and the 20-iteration plateau do not end the phase; the threshold
+    # does, at j = 27.
+    rs = [1.0, 20.0] + [1.5] * 22 + [0.05, 0.01, 5e-4]
+    assert _leave_at(rs, 1e-3) == 27
+    # with the best at exactly 100 r_switch the near-floor exits are armed:
+    # best 0.1 at j = 1, then 0.2 for 15 iterations -> j = 16
+    assert _leave_at([0.1] + [0.2] * 20, 1e-3) == 16
+
+
+def test_default_thresholds_are_above_the_format_floor():
+    # floor of r(j) in the low-precision phase is of order the unit roundoff
+    # (2^-24, 2^-9); each threshold is at least a decade above it
+    assert M_.DEFAULT_SWITCH["fp32"] >= 10 * 2.0 ** -24 * 16
+    assert M_.DEFAULT_SWITCH["bf16"] >= 10 * 2.0 ** -8
+
+
+class _NoStrictDivergence(M_.SwitchRule):
+    def observe(self, j, r):
+        if r < self.best:
+            self.best, self.j_best = r, j
+        if r <= self.r_switch:
+            return True
+        if self.best > M_.DIVERGE_ZONE * self.r_switch:
+            return False
+        return r >= M_.DIVERGE * self.best or j - self.j_best >= M_.STALL
+
+
+class _StallOffByOne(M_.SwitchRule):
+    def observe(self, j, r):
+        if r < self.best:
+            self.best, self.j_best = r, j
+        if r <= self.r_switch:
+            return True
+        if self.best > M_.DIVERGE_ZONE * self.r_switch:
+            return False
+        return r > M_.DIVERGE * self.best or j - self.j_best > M_.STALL
+
+
+class _NoZoneGate(M_.SwitchRule):
+    def observe(self, j, r):
+        if r < self.best:
+            self.best, self.j_best = r, j
+        return r <= self.r_switch or r > M_.DIVERGE * self.best or j - self.j_best >= M_.STALL
+
+
+class _BestAfterTest(M_.SwitchRule):
+    def observe(self, j, r):
+        leave = r <= self.r_switch or (self.best <= M_.DIVERGE_ZONE * self.r_switch and (
+            r > M_.DIVERGE * self.best or j - self.j_best >= M_.STALL))
+        if r < self.best:
+            self.best, self.j_best = r, j
+        return leave
+
+
+class _StrictThreshold(M_.SwitchRule):
+    def observe(self, j, r):
+        if r < self.best:
+            self.best, self.j_best = r, j
+        if r < self.r_switch:
+            return True
+        if self.best > M_.DIVERGE_ZONE * self.r_switch:
+            return False
+        return r > M_.DIVERGE * self.best or j - self.j_best >= M_.STALL
+
+
+@pytest.mark.parametrize("bad", [_NoStrictDivergence, _StallOffByOne, _NoZoneGate, _BestAfterTest,
+                                 _StrictThreshold])
+def test_planted_switch_rule_mistakes_fail_a_pin(bad):
+    cases = [
+        ([2.0 ** -j for j in range(1, 40)], 1e-3, 10),
+        ([0.5, 0.25, 0.125, 0.0625, 0.03], 0.0625, 4),
+        ([1e-1, 5e-2, 1e-2, 5e-3, 2e-3, 4e-3, 1e-2, 1.5e-2, 2.5e-2, 1e-3], 1e-3, 9),
+        ([1e-1, 2e-3, 2e-2, 2.0000001e-2], 1e-3, 4),
+        ([1e-1, 1e-2, 5e-3] + [6e-3] * 30, 1e-3, 18),
+        ([1e-1, 1e-2, 5e-3] + [6e-3] * 6 + [4e-3] + [6e-3] * 30, 1e-3, 25),
+        ([1e-1, 1e-2, 5e-3] + [6e-3] * 14 + [4e-3] + [6e-3] * 30, 1e-3, 33),
+        ([1.0, 20.0] + [1.5] * 22 + [0.05, 0.01, 5e-4], 1e-3, 27),
+        ([0.1] + [0.2] * 20, 1e-3, 16),
+    ]
+    for rs, rsw, want in cases:  # the oracle's rule passes all of them ...
+        assert _leave_at(rs, rsw) == want
+    # ... and each planted variant fails at least one
+    assert any(_leave_at(rs, rsw, bad) != want for rs, rsw, want in cases)
+
+
+def test_low_precision_phase_ends_where_the_rule_fires_on_its_history():
+    """The solver stops its low-precision phase exactly at the rule's
+    iteration on the r(j) it recorded (BF16 on the 2-D Laplacian: the phase
+    ends on the threshold, not on rounding noise)."""
+    A = W.laplacian_2d(32)
+    X0 = W.gaussian_block(A.n, 16, 201)
+    res, lp, hist = M_.lobpcg_mixed(A.to_scipy(), X0, 8, A.anorm, fmt="bf16")
+    r = [h["r"] for h in hist]
+    assert _leave_at(r, M_.DEFAULT_SWITCH["bf16"]) == lp
+    assert r[lp - 1] <= M_.DEFAULT_SWITCH["bf16"] and min(r[: lp - 1]) > M_.DEFAULT_SWITCH["bf16"]
