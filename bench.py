@@ -4,8 +4,12 @@ Workload (default): 3-D 7-point Dirichlet Laplacian on a 128^3 grid
 (n = 2,097,152, 14,581,760 nonzeros, FP64 CSR), the 64 smallest eigenpairs
 with 32 extra block columns (block 96, n_es = 69), tol 1e-8, Gaussian starting
 block from a fixed seed. One step = one complete solve with the `fix`
-shrink-and-expand strategy (inputs resident in HBM before timing). The
-fixed-block solve (no strategy) on the same input is timed beside it.
+shrink-and-expand strategy (inputs resident in HBM before timing). After the
+timed solves: one solve with HIP events around every launch (the per-kernel
+table and the roofline), the fixed-block solve (no strategy) on the same input
+(median of up to three runs), a short serving leg (Poisson arrivals of the
+serving stream: p50 / p99 latency and solves/s), and the FP64 oracle on the
+host cores for a few iterations (the CPU baseline).
 
 Prints one JSON line (see the contract in the repository's design notes).
 """
@@ -29,6 +33,7 @@ METRIC = "time-to-solution & HBM GB/s, shrink-expand vs fixed block; p50/p99 lat
 # Workloads: matrix family and default sizes (n_ev, n_extra, solver, precision).
 WORKLOADS = {
     "laplace3d": dict(grid=128, n_ev=64, n_extra=32, x0_seed=202),
+    "laplace2d": dict(grid=32, n_ev=8, n_extra=8, x0_seed=201),
     "anderson": dict(grid=100, n_ev=200, n_extra=50, x0_seed=203),
     "chunglu": dict(nodes=500000, n_ev=32, n_extra=16, x0_seed=204),
     "serving": dict(x0_seed=305),
@@ -59,7 +64,13 @@ def parse():
     ap.add_argument("--strategy", default="fix")
     ap.add_argument("--no-fixed", action="store_true", help="skip the fixed-block comparison")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-seconds", type=float, default=20.0)
+    ap.add_argument("--cpu-iterations", type=int, default=5,
+                    help="oracle iterations timed after its initial Rayleigh-Ritz step")
+    ap.add_argument("--cpu-seconds", type=float, default=120.0, help="cap on the oracle sample")
+    ap.add_argument("--fixed-runs", type=int, default=3, help="fixed-block solves (median; at most --steps)")
+    ap.add_argument("--serve-requests", type=int, default=40,
+                    help="serving leg of the default run: measured Poisson requests (0 = none)")
+    ap.add_argument("--serve-pilot", type=int, default=8, help="serving leg: closed-loop warm-up requests")
     ap.add_argument("--requests", type=int, default=200, help="serving: measured requests")
     ap.add_argument("--pilot", type=int, default=20, help="serving: warm-up requests (closed loop)")
     ap.add_argument("--load", type=float, default=0.7, help="serving: arrival rate / saturated rate")
@@ -79,6 +90,8 @@ def build_matrix(args):
 
     if args.workload == "laplace3d":
         return W.laplacian_3d(args.grid), f"laplace3d_{args.grid}^3"
+    if args.workload == "laplace2d":
+        return W.laplacian_2d(args.grid), f"laplace2d_{args.grid}^2"
     if args.workload == "anderson":
         return W.anderson_3d(args.grid, 4.0, 103), f"anderson3d_{args.grid}^3_w4"
     return W.chung_lu_laplacian(args.nodes, 16.0, 2.5, 104), f"chunglu_n{args.nodes}_d16_b2.5"
@@ -138,15 +151,19 @@ def main():
     for i in range(args.warmup):
         lam, V, info = run(args.strategy)
         log(f"warmup {i}: {info.time_ms / 1e3:.3f}s iters={info.iterations} conv={info.converged}")
+    # timed region: K whole solves, no per-launch events
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     infos = []
     for i in range(args.steps):
-        lam, V, info = run(args.strategy, profile=1)
+        lam, V, info = run(args.strategy)
         infos.append(info)
     torch.cuda.synchronize()
     wall = (time.perf_counter() - t0) / max(args.steps, 1)
     log(f"timed {args.steps} solve(s): {wall:.3f}s each, iters={infos[-1].iterations}")
+    # one more solve with HIP events around every launch: the per-kernel table
+    _, _, pinfo = run(args.strategy, profile=1)
+    log(f"profiled solve: {pinfo.time_ms / 1e3:.3f}s iters={pinfo.iterations}")
 
     out = {
         "metric": METRIC,
@@ -176,32 +193,53 @@ def main():
             "converged": infos[-1].converged, "low_precision_iterations": infos[-1].lp_iterations,
             "reprojections": infos[-1].n_reprojections,
             "implicit_orthonormalizations": int(((infos[-1].history[:, 7].astype(int) & 8) != 0).sum()),
+            "median_solve_s": round(float(np.median([i.time_ms for i in infos])) / 1e3, 4),
         },
     }
     lam_np = lam.cpu().numpy() if hasattr(lam, "cpu") else np.asarray(lam)
     out["parity"] = {"max_stop_ratio": infos[-1].max_stop_ratio}
-    if args.workload == "laplace3d":
+    if args.workload in ("laplace3d", "laplace2d"):
+        # Dirichlet Laplacian eigenvalues: sums of 2 - 2 cos(k pi / (m + 1))
         m = args.grid
         one = 2.0 - 2.0 * np.cos(np.arange(1, m + 1) * np.pi / (m + 1))
-        ex = np.sort((one[:, None, None] + one[None, :, None] + one[None, None, :]).ravel())[: args.n_ev]
+        if args.workload == "laplace3d":
+            ex = (one[:, None, None] + one[None, :, None] + one[None, None, :]).ravel()
+        else:
+            ex = (one[:, None] + one[None, :]).ravel()
+        ex = np.sort(ex)[: args.n_ev]
         out["parity"]["max_eig_rel_err_vs_closed_form"] = float(np.max(np.abs(lam_np - ex) / ex))
     out["lambda_head"] = [float(v) for v in lam_np[:4]]
     out["lambda_tail"] = [float(v) for v in lam_np[-2:]]
 
-    if not args.no_fixed:
-        t1 = time.perf_counter()
-        _, _, finfo = run("none")
-        torch.cuda.synchronize()
-        fwall = time.perf_counter() - t1
-        out["fixed_block"] = {"time_s": round(fwall, 4), "iterations": finfo.iterations,
-                              "converged": finfo.converged,
-                              "low_precision_iterations": finfo.lp_iterations}
-        out["speedup_vs_fixed"] = round(fwall / wall, 3)
-        log(f"fixed block: {fwall:.3f}s iters={finfo.iterations}")
+    if not args.no_fixed and args.strategy != "none":
+        # the fixed block, unprofiled like the timed solves; medians of both
+        runs = max(1, min(args.fixed_runs, args.steps))
+        finfos = [run("none")[2] for _ in range(runs)]
+        fmed = float(np.median([i.time_ms for i in finfos])) / 1e3
+        smed = out["shrink_expand"]["median_solve_s"]
+        out["fixed_block"] = {"time_s": round(fmed, 4), "runs": runs,
+                              "iterations": [i.iterations for i in finfos],
+                              "converged": all(i.converged for i in finfos),
+                              "low_precision_iterations": finfos[-1].lp_iterations}
+        out["speedup_vs_fixed"] = round(fmed / smed, 3)
+        log(f"fixed block: median {fmed:.3f}s of {runs} iters={[i.iterations for i in finfos]}")
 
-    tag = {"laplace3d": f"laplace3d_{args.grid}", "anderson": f"anderson_{args.grid}",
-           "chunglu": f"chunglu_{args.nodes}"}[args.workload]
-    out["roofline"], out["kernels"] = roofline(infos, f"{tag}_{args.precision}", args.precision)
+    tag = {"laplace3d": f"laplace3d_{args.grid}", "laplace2d": f"laplace2d_{args.grid}",
+           "anderson": f"anderson_{args.grid}", "chunglu": f"chunglu_{args.nodes}"}[args.workload]
+    out["roofline"], out["kernels"] = roofline([pinfo], f"{tag}_{args.precision}", args.precision)
+    # release the solve's device memory before the serving leg and before exit
+    del lam, V, X0d
+    M.close()
+    ctx.close()
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+    out["serving"] = None
+    if args.serve_requests > 0 and args.workload == "laplace3d":
+        sargs = argparse.Namespace(**vars(args))
+        sargs.requests, sargs.pilot = args.serve_requests, args.serve_pilot
+        leg = serving(sargs, log)
+        out["serving"] = dict(leg["serving"], requests=args.serve_requests, pilot=args.serve_pilot,
+                              workload=leg["config"]["workload"], slots=args.slots)
     out["cpu_baseline"] = None
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(A, X0, args, infos[-1].iterations, log)
@@ -291,17 +329,37 @@ def roofline(infos, workload=None, precision="fp64"):
     return roof, table
 
 
-def cpu_baseline(A, X0, args, gpu_iters, log):
-    """The FP64 oracle on the host cores, bounded sample of the same solve."""
-    import oracle as O
-    import workloads as W
-
+def host_cpu():
+    """Host facts for the CPU baseline: logical CPUs, those this process may
+    run on, the CPU model, and the thread counts of the BLAS pools."""
+    info = {"nproc": os.cpu_count(), "affinity": len(os.sched_getaffinity(0)),
+            "omp_num_threads": os.environ.get("OMP_NUM_THREADS")}
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    info["model"] = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
     try:
         from threadpoolctl import threadpool_info
 
-        cores = max((d.get("num_threads", 1) for d in threadpool_info()), default=os.cpu_count())
+        info["blas_threads"] = max((d.get("num_threads", 1) for d in threadpool_info()), default=1)
     except Exception:
-        cores = os.cpu_count()
+        info["blas_threads"] = None
+    return info
+
+
+def cpu_baseline(A, X0, args, gpu_iters, log):
+    """The FP64 oracle as it stands on the host cores: its initial
+    Rayleigh-Ritz step, then --cpu-iterations iterations of the same solve
+    timed from the start of the first (from the oracle's per-iteration
+    timestamps); time-to-solution extrapolated to the GPU's iteration count."""
+    import oracle as O
+    import workloads as W
+
+    host = host_cpu()
     t = time.perf_counter()
     solver = {"si": O.subspace_iteration, "sd": O.steepest_descent,
               "tracemin": O.tracemin}.get(args.solver, O.lobpcg)
@@ -309,20 +367,26 @@ def cpu_baseline(A, X0, args, gpu_iters, log):
     draw = lambda e, d: W.seeded_expansion_block(A.n, d, nb, e, args.x0_seed)  # noqa: E731
     res = solver(A.to_scipy(), X0, args.n_ev, A.anorm, tol=1e-8,
                  n_es=args.n_ev + min(5, args.n_extra - 1), se=O.SEParams(args.strategy),
+                 max_iter=args.cpu_iterations,
                  time_limit_s=args.cpu_seconds, expand_vectors=args.expand_vectors, random_block=draw,
                  **({"filter_degree": args.filter_degree} if args.solver == "si" else {}),
                  **({"precond": O.jacobi_preconditioner(A.to_scipy())}
                     if args.precond == "jacobi" else {}))
     el = time.perf_counter() - t
-    done = max(res.iterations - 1, 1)  # the last recorded iteration stopped at its check
-    per_iter = el / done
+    t_first = res.history[0]["t"]  # end of the initial Rayleigh-Ritz step
+    done = len(res.history) - (1 if res.converged else 0)  # iterations that took a full step
+    per_iter = (el - t_first) / max(done, 1)
     est = per_iter * gpu_iters
-    log(f"cpu oracle: {done} iteration(s) in {el:.1f}s on {cores} threads")
-    return {"value": round(est, 1), "unit": "s", "cores": int(cores), "kind": "oracle",
-            "sample": f"initial Rayleigh-Ritz + {done} FP64 {args.solver.upper()} iteration(s) of the same workload in "
-                      f"{el:.1f}s; time-to-solution extrapolated as {per_iter:.2f}s/iteration x "
-                      f"{gpu_iters} iterations (GPU count)",
-            "extrapolated": True}
+    threads = host["blas_threads"] or host["affinity"]
+    log(f"cpu oracle: initial RR {t_first:.1f}s, {done} iteration(s) in {el - t_first:.1f}s "
+        f"({per_iter:.2f}s each) on {threads} BLAS threads; host {host}")
+    return {"value": round(est, 1), "unit": "s", "cores": int(threads), "kind": "oracle",
+            "sample": f"{done} FP64 {args.solver.upper()} iteration(s) of the same workload after the "
+                      f"initial Rayleigh-Ritz step ({t_first:.1f}s, not counted): {el - t_first:.1f}s, "
+                      f"{per_iter:.2f}s/iteration; time-to-solution extrapolated x {gpu_iters} iterations "
+                      f"(GPU count). Dense steps use {threads} BLAS threads; the oracle's sparse "
+                      "products are single-threaded SciPy",
+            "extrapolated": True, "host": host}
 
 
 def serving(args, log):
@@ -390,6 +454,9 @@ def serving(args, log):
             log(f"submitted {k + 1}/{args.requests}")
     res = collect(subs)
     srv.close()
+    for M in mats:
+        M.close()
+    ctx.close()
     lat = np.array([r["lat_ms"] for r in res])
     span = max(r["done"] for r in res) - min(r["arrival"] for r in res)
     ok = all(r["converged"] and r["stop"] <= 1e-8 for r in res + pilot)

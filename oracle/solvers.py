@@ -255,7 +255,8 @@ def lobpcg(
         r_j = float(np.max(paper[:n_ev]))
         ctl.observe(j, r_j)
         conv = stop[:n_ev] <= tol
-        rec = dict(j=j, r=r_j, max_stop=float(np.max(stop[:n_ev])), k=X.shape[1],
+        rec = dict(j=j, t=time.perf_counter() - t0,  # seconds since the call began
+                   r=r_j, max_stop=float(np.max(stop[:n_ev])), k=X.shape[1],
                    p=P.shape[1], locked=0, a=0, expand=False, shrink=False)
         history.append(rec)
         if np.all(conv):
@@ -371,7 +372,8 @@ def steepest_descent(
         r_j = float(np.max(paper[:n_ev]))
         ctl.observe(j, r_j)
         conv = stop[:n_ev] <= tol
-        rec = dict(j=j, r=r_j, max_stop=float(np.max(stop[:n_ev])), k=X.shape[1], p=0,
+        rec = dict(j=j, t=time.perf_counter() - t0,  # seconds since the call began
+                   r=r_j, max_stop=float(np.max(stop[:n_ev])), k=X.shape[1], p=0,
                    locked=0, a=0, expand=False, shrink=False)
         history.append(rec)
         if np.all(conv):
@@ -493,7 +495,8 @@ def tracemin(
         R, stop, paper = residual_measures(A, X, lam, anorm)
         r_j = float(np.max(paper[:n_ev]))
         ctl.observe(j, r_j)
-        rec = dict(j=j, r=r_j, max_stop=float(np.max(stop[:n_ev])), k=X.shape[1],
+        rec = dict(j=j, t=time.perf_counter() - t0,  # seconds since the call began
+                   r=r_j, max_stop=float(np.max(stop[:n_ev])), k=X.shape[1],
                    trace=float(np.sum(lam)), expand=False, shrink=False)
         history.append(rec)
         if np.all(stop[:n_ev] <= tol):
@@ -580,7 +583,8 @@ def subspace_iteration(
         _, stop, paper = residual_measures(A, X, lam, anorm)
         r_j = float(np.max(paper[:n_ev]))
         ctl.observe(j, r_j)
-        rec = dict(j=j, r=r_j, max_stop=float(np.max(stop[:n_ev])), k=X.shape[1],
+        rec = dict(j=j, t=time.perf_counter() - t0,  # seconds since the call began
+                   r=r_j, max_stop=float(np.max(stop[:n_ev])), k=X.shape[1],
                    expand=False, shrink=False)
         history.append(rec)
         if np.all(stop[:n_ev] <= tol):

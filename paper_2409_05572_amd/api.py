@@ -11,8 +11,24 @@ from dataclasses import dataclass, field
 
 import numpy as np
 
+import atexit
+
 from . import _lib
 from ._lib import SeInfo, SeParams, check, lib
+
+# Objects still alive when the interpreter exits are not destroyed through
+# the library: at that point the HIP runtime, torch and an attached profiler
+# finalize in an order this module does not control, and the process exit
+# returns the device memory anyway. Explicit close() calls are unaffected.
+_EXITING = False
+
+
+def _mark_exiting():
+    global _EXITING
+    _EXITING = True
+
+
+atexit.register(_mark_exiting)
 
 
 def _ptr(x) -> int:
@@ -47,6 +63,8 @@ class Context:
             self._h = C.c_void_p()
 
     def __del__(self):
+        if _EXITING:
+            return
         try:
             self.close()
         except Exception:
@@ -89,6 +107,8 @@ class Matrix:
             self._h = C.c_void_p()
 
     def __del__(self):
+        if _EXITING:
+            return
         try:
             self.close()
         except Exception:
@@ -258,6 +278,8 @@ class Server:
             self._keep.clear()
 
     def __del__(self):
+        if _EXITING:
+            return
         try:
             self.close()
         except Exception:

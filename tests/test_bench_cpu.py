@@ -64,10 +64,29 @@ def test_cpu_baseline_leg_runs_every_solver_option():
     cases = [dict(solver="lobpcg", precond="jacobi"), dict(solver="sd", expand_vectors="random"),
              dict(solver="si", filter_degree=4, expand_vectors="powered"), dict(solver="tracemin")]
     for c in cases:
-        args = argparse.Namespace(n_ev=4, n_extra=4, strategy="fix", cpu_seconds=0.5, x0_seed=3,
-                                  expand_vectors="xdrop", filter_degree=0, precond="none")
+        args = argparse.Namespace(n_ev=4, n_extra=4, strategy="fix", cpu_seconds=5.0, cpu_iterations=5,
+                                  x0_seed=3, expand_vectors="xdrop", filter_degree=0, precond="none")
         for k, v in c.items():
             setattr(args, k, v)
         out = bench.cpu_baseline(A, X0, args, 20, lambda *a: None)
         assert out["kind"] == "oracle" and out["value"] >= 0 and out["cores"] >= 1, c
         assert "iteration" in out["sample"]
+        host = out["host"]
+        assert host["nproc"] >= 1 and host["affinity"] >= 1 and out["cores"] >= 1, c
+
+
+def test_cpu_baseline_times_iterations_after_the_initial_rayleigh_ritz():
+    """The sample is the requested number of full iterations, timed from the
+    oracle's timestamp at the start of the first one."""
+    import argparse
+
+    import workloads as W
+
+    A = W.laplacian_3d(20)
+    X0 = W.gaussian_block(A.n, 24, 3)
+    args = argparse.Namespace(n_ev=16, n_extra=8, strategy="none", cpu_seconds=60.0, cpu_iterations=5,
+                              x0_seed=3, expand_vectors="xdrop", filter_degree=0, precond="none",
+                              solver="lobpcg")
+    out = bench.cpu_baseline(A, X0, args, 100, lambda *a: None)
+    assert out["sample"].startswith("5 FP64 LOBPCG iteration(s)")
+    assert out["value"] > 0

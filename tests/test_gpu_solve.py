@@ -315,3 +315,23 @@ def test_matrix_released_after_its_context(ctx):
     M.close()
     lam, V, info = _gpu_solve(ctx, A, W.gaussian_block(A.n, 8, 1), 4, 4)
     assert info.converged and info.status == 0
+
+
+@pytest.mark.parametrize("strategy", ["none", "fix"])
+def test_iteration_counts_on_the_benchmark_shape_match_the_oracle(ctx, strategy):
+    """The benchmark's block shape (64 wanted + 32 extra, start seed 202) on a
+    32^3 Laplacian: the fixed-block and the shrink-and-expand iteration counts
+    agree with the oracle's (98 and 103 there: at this size shrink-and-expand
+    takes a few more iterations, as the paper reports about 10% more), so the
+    GPU's fixed-vs-S&E comparison runs the same iteration as the oracle."""
+    m = 32
+    A = W.laplacian_3d(m)
+    X0 = W.gaussian_block(A.n, 96, 202)
+    lam, V, info = _gpu_solve(ctx, A, X0, 64, 32, strategy=strategy)
+    ref = O.lobpcg(A.to_scipy(), X0, 64, A.anorm, tol=1e-8, n_es=69, se=O.SEParams(strategy))
+    assert info.converged and ref.converged
+    assert abs(info.iterations - ref.iterations) <= max(3, ref.iterations // 20)
+    assert abs(info.n_shrinks - ref.n_shrinks) <= 1
+    exact = pins.laplacian_spectrum(m, 3, 64)
+    assert np.max(np.abs(lam - exact) / exact) <= 1e-10
+    assert np.max(_residual_ratio(A, lam, V)) <= 1e-8 * 1.0001
