@@ -75,6 +75,18 @@ def _apply(A, X):
     return A @ X
 
 
+def _H(M):
+    """Conjugate transpose. The paper states the problem for Hermitian A in
+    C^{n x n} (Section 1) and writes X^H in its algorithms; for real blocks
+    this is the plain transpose."""
+    return M.conj().T
+
+
+def _block(X0):
+    """The start block in FP64: complex128 when X0 is complex, else float64."""
+    return np.asarray(X0, dtype=np.complex128 if np.iscomplexobj(X0) else np.float64)
+
+
 def residual_measures(A, X, lam, anorm):
     """Residual block R = A X - X diag(lam) and the two per-column ratios.
 
@@ -115,7 +127,7 @@ def orth(Y, drop_tol=1e-12):
         for _ in range(2):
             if basis:
                 Bm = np.stack(basis, axis=1)
-                v -= Bm @ (Bm.T @ v)
+                v -= Bm @ (_H(Bm) @ v)
         nv = np.linalg.norm(v)
         if nv > drop_tol * norms[i]:
             basis.append(v / nv)
@@ -130,8 +142,8 @@ def rayleigh_ritz(S, AS):
 
     Theta ascending (LAPACK ``eigh``); returns (theta, Z).
     """
-    Ap = S.T @ AS
-    Ap = 0.5 * (Ap + Ap.T)
+    Ap = _H(S) @ AS
+    Ap = 0.5 * (Ap + _H(Ap))
     theta, Z = np.linalg.eigh(Ap)
     return theta, Z
 
@@ -177,7 +189,7 @@ def hl_basis(Z, k, active, drop_tol=1e-12):
     """
     Z1 = Z[:, :k]
     Z2 = Z[:, k:]
-    B = Z2[np.asarray(active, dtype=np.int64), :].T
+    B = _H(Z2[np.asarray(active, dtype=np.int64), :])
     QB, _ = orth(B, drop_tol)
     return Z1, Z2 @ QB
 
@@ -235,7 +247,7 @@ def lobpcg(
     t0 = time.perf_counter()
 
     # Initial Rayleigh-Ritz on the orthogonalized starting block.
-    X, _ = orth(np.asarray(X0, dtype=np.float64), drop_tol)
+    X, _ = orth(_block(X0), drop_tol)
     theta, Z = rayleigh_ritz(X, _apply(A, X))
     X = X @ Z
     lam = theta
@@ -243,7 +255,7 @@ def lobpcg(
     if P0 is not None and P0.shape[1] > 0:
         P = np.asarray(P0, dtype=np.float64)
         for _ in range(2):
-            P = P - X @ (X.T @ P)
+            P = P - X @ (_H(X) @ P)
         P, _ = orth(P, drop_tol)
     Xdrop = Pdrop = None
     history = []
@@ -277,7 +289,7 @@ def lobpcg(
         W = R[:, active] if precond is None else precond(R[:, active])
         XP = np.hstack([X, P])
         for _ in range(2):
-            W = W - XP @ (XP.T @ W)
+            W = W - XP @ (_H(XP) @ W)
         W, _ = orth(W, drop_tol)
 
         if expand and Xdrop is not None:
@@ -288,7 +300,7 @@ def lobpcg(
             else:
                 Sd = np.hstack([Xdrop, Pdrop])
             for _ in range(2):
-                Sd = Sd - S @ (S.T @ Sd)
+                Sd = Sd - S @ (_H(S) @ Sd)
             Sd, kept = orth(Sd, drop_tol)
             to_x = kept < d
             new_x = np.arange(k, k + int(np.count_nonzero(to_x)))
@@ -358,7 +370,7 @@ def steepest_descent(
     t0 = time.perf_counter()
 
     # X <- orth(X0); A_p = X^T A X = Z Lambda Z^T; X <- X Z
-    X, _ = orth(np.asarray(X0, dtype=np.float64), drop_tol)
+    X, _ = orth(_block(X0), drop_tol)
     lam, Z = rayleigh_ritz(X, _apply(A, X))
     X = X @ Z
     Xdrop = None
@@ -391,7 +403,7 @@ def steepest_descent(
         if ctl.ifexpand(j) and Xdrop is not None:
             Xd = random_block(n_exp + 1, Xdrop.shape[1]) if expand_vectors == "random" else Xdrop
             for _ in range(2):
-                Xd = Xd - X @ (X.T @ Xd)
+                Xd = Xd - X @ (_H(X) @ Xd)
             Xd, _ = orth(Xd, drop_tol)
             X = np.hstack([X, Xd])
             Xdrop = None
@@ -402,7 +414,7 @@ def steepest_descent(
         # W <- T R (active columns); W <- W - X (X^T W), orthonormalized
         W = R[:, active] if precond is None else precond(R[:, active])
         for _ in range(2):
-            W = W - X @ (X.T @ W)
+            W = W - X @ (_H(X) @ W)
         W, _ = orth(W, drop_tol)
 
         # S = [X, W]; A_p = S^T A S = Z Lambda Z^T; X <- S Z(:, 1:n_now)
@@ -483,7 +495,7 @@ def tracemin(
     ctl = SEController(se if _se_enabled(se, n_ev, n_es, nb) else SEParams("none"))
     t0 = time.perf_counter()
 
-    X, _ = orth(np.asarray(X0, dtype=np.float64), drop_tol)
+    X, _ = orth(_block(X0), drop_tol)
     lam, Z = rayleigh_ritz(X, _apply(A, X))
     X = X @ Z
     Xdrop = None
@@ -570,7 +582,7 @@ def subspace_iteration(
         apply_op = lambda Y: s * Y - _apply(A, Y)  # noqa: E731
     t0 = time.perf_counter()
 
-    X, _ = orth(np.asarray(X0, dtype=np.float64), drop_tol)
+    X, _ = orth(_block(X0), drop_tol)
     theta, Z = rayleigh_ritz(X, _apply(A, X))
     X = X @ Z
     lam = theta

@@ -17,6 +17,12 @@ Matrix families (shapes of the workloads the solvers are measured on):
 * ``chung_lu_laplacian(n, mean_degree, exponent, seed)``: normalized graph
   Laplacian ``I - D^{-1/2} A_g D^{-1/2}`` of a connected Chung-Lu power-law
   graph with unit weights.
+* ``magnetic_laplacian(m, phases)``: complex Hermitian Laplacian of a periodic
+  grid (torus) with a uniform phase per step in each direction (a uniform
+  vector potential); its spectrum is known in closed form (``magnetic_spectrum``).
+* ``random_sparse_hermitian(n, density, seed)``: small complex Hermitian
+  matrices for brute-force checks.
+Complex matrices come as ``CSRMatrix`` with complex128 values.
 """
 from __future__ import annotations
 
@@ -29,18 +35,23 @@ import scipy.sparse as sp
 
 @dataclass
 class CSRMatrix:
-    """Real symmetric sparse matrix in CSR form with its full pattern stored."""
+    """Real symmetric or complex Hermitian sparse matrix in CSR form with its
+    full pattern stored."""
 
     n: int
     rowptr: np.ndarray  # int64, n + 1
     colind: np.ndarray  # int32, nnz, sorted within each row
-    val: np.ndarray  # float64, nnz
+    val: np.ndarray  # float64 (or complex128 for a Hermitian matrix), nnz
     anorm: float  # an upper bound of ||A||_2 (exact where a closed form exists)
     name: str = ""
 
     @property
     def nnz(self) -> int:
         return int(self.rowptr[-1])
+
+    @property
+    def is_complex(self) -> bool:
+        return np.iscomplexobj(self.val)
 
     def to_scipy(self) -> sp.csr_matrix:
         return sp.csr_matrix(
@@ -60,6 +71,83 @@ def _from_scipy(a: sp.spmatrix, anorm: float, name: str) -> CSRMatrix:
         anorm=float(anorm),
         name=name,
     )
+
+
+def _from_scipy_complex(a: sp.spmatrix, anorm: float, name: str) -> CSRMatrix:
+    a = sp.csr_matrix(a, dtype=np.complex128)
+    a.sum_duplicates()
+    a.sort_indices()
+    return CSRMatrix(
+        n=a.shape[0],
+        rowptr=np.ascontiguousarray(a.indptr, dtype=np.int64),
+        colind=np.ascontiguousarray(a.indices, dtype=np.int32),
+        val=np.ascontiguousarray(a.data, dtype=np.complex128),
+        anorm=float(anorm),
+        name=name,
+    )
+
+
+def _magnetic_ring(m: int, phi: float) -> sp.csr_matrix:
+    """m-point periodic ring: 2 on the diagonal, -e^{i phi} at (j, j + 1) and
+    -e^{-i phi} at (j + 1, j), indices mod m (m >= 3)."""
+    j = np.arange(m)
+    rows = np.concatenate([j, j, (j + 1) % m])
+    cols = np.concatenate([j, (j + 1) % m, j])
+    vals = np.concatenate([np.full(m, 2.0 + 0j), np.full(m, -np.exp(1j * phi)),
+                           np.full(m, -np.exp(-1j * phi))])
+    return sp.csr_matrix((vals, (rows, cols)), shape=(m, m))
+
+
+def magnetic_laplacian(m: int, phases) -> CSRMatrix:
+    """Complex Hermitian Laplacian of the periodic m^d grid (d = len(phases),
+    1 to 3) with phase phases[a] on every step in direction a (first grid
+    index fastest): the Kronecker sum of ``_magnetic_ring(m, phases[a])``.
+    Eigenvalues sum_a (2 - 2 cos(2 pi k_a / m + phases[a])), k_a = 0..m-1
+    (``magnetic_spectrum``); ``anorm`` is the exact largest one."""
+    d = len(phases)
+    a = None
+    for ax, phi in enumerate(phases):
+        slow = sp.identity(m ** (d - 1 - ax), format="csr", dtype=np.complex128)
+        fast = sp.identity(m ** ax, format="csr", dtype=np.complex128)
+        term = sp.kron(sp.kron(slow, _magnetic_ring(m, phi)), fast)
+        a = term if a is None else a + term
+    lam_max = float(magnetic_spectrum(m, phases)[-1])
+    return _from_scipy_complex(a, lam_max, f"magnetic{d}d_{m}")
+
+
+def magnetic_spectrum(m: int, phases) -> np.ndarray:
+    """All eigenvalues of ``magnetic_laplacian(m, phases)``, ascending."""
+    k = 2.0 * np.pi * np.arange(m) / m
+    total = np.zeros(1)
+    for phi in phases:
+        one = 2.0 - 2.0 * np.cos(k + phi)
+        total = (total[:, None] + one[None, :]).ravel()
+    return np.sort(total)
+
+
+def random_sparse_hermitian(n: int, density: float, seed: int) -> CSRMatrix:
+    """Random sparse complex Hermitian matrix (B + B^H) / 2 + a real diagonal,
+    entries normal; ``anorm`` is the Gershgorin bound."""
+    rng = np.random.default_rng(seed)
+    nnz = max(1, int(density * n * n))
+    r = rng.integers(0, n, nnz)
+    c = rng.integers(0, n, nnz)
+    v = rng.standard_normal(nnz) + 1j * rng.standard_normal(nnz)
+    b = sp.csr_matrix((v, (r, c)), shape=(n, n))
+    a = 0.5 * (b + b.conj().T) + sp.diags(rng.standard_normal(n).astype(np.complex128), 0)
+    a = sp.csr_matrix(a)
+    gersh = float(np.max(np.asarray(abs(a).sum(axis=1)).ravel()))
+    return _from_scipy_complex(a, gersh, f"randherm_{n}")
+
+
+def gaussian_block_complex(n: int, nb: int, seed: int) -> np.ndarray:
+    """n x nb complex start block: real and imaginary parts independent
+    standard normals (``default_rng(seed)``, real part drawn first), scaled
+    by 1/sqrt(2)."""
+    rng = np.random.default_rng(seed)
+    re = rng.standard_normal((n, nb))
+    im = rng.standard_normal((n, nb))
+    return np.asfortranarray((re + 1j * im) / math.sqrt(2.0))
 
 
 def _second_difference(m: int) -> sp.csr_matrix:
