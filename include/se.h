@@ -305,6 +305,51 @@ se_status se_op_syev_lowest(se_ctx* ctx, int32_t m, int32_t k, double* A, double
  * they are compacted to the front. Synchronizes the stream. */
 se_status se_op_cholqr(se_ctx* ctx, int64_t n, double* W, int64_t ldw, int32_t w, int32_t* rank);
 
+/* ---- Complex Hermitian A (Section 1 states the problem for Hermitian
+ * A in C^{n x n}; Algorithms 1 and 3 with X^H for the transposes) ----
+ * Complex values are interleaved (re, im) doubles throughout. FP64 only. */
+
+/* Create a complex Hermitian CSR matrix (full pattern, a_ji = conj(a_ij)).
+ * As se_matrix_create_csr, with val holding 2 nnz doubles (entry e is
+ * val[2e] + i val[2e + 1]); anorm 0 = the Gershgorin bound max_i sum_j |a_ij|.
+ * The matrix is usable with se_solve_z and the *_z building blocks only. */
+se_status se_matrix_create_csr_z(se_ctx* ctx, int64_t n, int64_t nnz, const int64_t* rowptr,
+                                 const int32_t* colind, const double* val, uint32_t flags,
+                                 double anorm, se_matrix** out);
+
+/* The n_ev smallest eigenpairs of a complex Hermitian matrix: LOBPCG
+ * (Algorithm 3, soft locking, HL basis) or SI (Algorithm 1, the shifted power
+ * step X <- sigma X - A X), shrink-and-expand with any strategy, X_drop as
+ * the expansion vectors. params as se_solve; precision must be SE_FP64,
+ * expand_vectors SE_EXPAND_XDROP, filter_degree 0 and precond none
+ * (otherwise SE_ERR_UNSUPPORTED); nb <= 170 for LOBPCG, <= 512 for SI.
+ *   X0     n x nb complex start block, column-major (leading dimension n
+ *          complex entries, 2 n nb doubles); NULL: the real seeded block of
+ *          se_solve (imaginary parts zero)
+ *   V      output n x n_ev complex eigenvectors, column-major
+ *   lambda output n_ev real eigenvalues, ascending
+ * Pointers per params->ptr_mode; return values as se_solve. */
+se_status se_solve_z(se_ctx* ctx, const se_matrix* A, const se_params* params, const double* X0,
+                     double* V, double* lambda, se_info* info);
+
+/* Complex building blocks on device pointers: complex row-major blocks with
+ * leading dimensions counted in complex entries (even), 16-byte aligned.
+ * se_op_spmm_z: Y = A X (w in [1, 512]).
+ * se_op_gram_z: C = U^H V (mu x mv complex, leading dimension mv; mu, mv <=
+ *   512); exactly Hermitian when V is U.
+ * se_op_update_z: Out = beta Out + U C (C K x N complex, leading dimension
+ *   N; K, N <= 512; beta 0 or 1; Out must not overlap U).
+ * se_op_heev_lowest_z: the k lowest eigenpairs of the Hermitian m x m
+ *   complex matrix A (m <= 512; overwritten): w (k real) ascending, Z (m x k
+ *   complex, leading dimension k) orthonormal. Synchronizes the stream. */
+se_status se_op_spmm_z(se_ctx* ctx, const se_matrix* A, const double* X, int64_t ldx, double* Y,
+                       int64_t ldy, int32_t w);
+se_status se_op_gram_z(se_ctx* ctx, int64_t n, const double* U, int64_t ldu, int32_t mu,
+                       const double* V, int64_t ldv, int32_t mv, double* C);
+se_status se_op_update_z(se_ctx* ctx, int64_t n, const double* U, int64_t ldu, int32_t K,
+                         const double* C, int32_t N, double* Out, int64_t ldo, double beta);
+se_status se_op_heev_lowest_z(se_ctx* ctx, int32_t m, int32_t k, double* A, double* w, double* Z);
+
 /* Replay the shrink-and-expand controller (the strategy and warm-up rule of
  * Section 3.2 selected in params) on a scripted sequence r(1..count) of
  * eq. (rk) values, without a matrix or a GPU. flags[j-1] receives bit 0 when

@@ -105,6 +105,19 @@ PROTOTYPES = {
     "se_strategy_replay": (C.c_int, [C.POINTER(SeParams), C.c_int32, C.POINTER(C.c_double),
                                      C.POINTER(C.c_int32)]),
     "se_status_string": (C.c_char_p, [C.c_int]),
+    "se_matrix_create_csr_z": (C.c_int, [C.c_void_p, C.c_int64, C.c_int64, C.c_void_p, C.c_void_p,
+                                          C.c_void_p, C.c_uint32, C.c_double,
+                                          C.POINTER(C.c_void_p)]),
+    "se_solve_z": (C.c_int, [C.c_void_p, C.c_void_p, C.POINTER(SeParams), C.c_void_p, C.c_void_p,
+                             C.c_void_p, C.POINTER(SeInfo)]),
+    "se_op_spmm_z": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p,
+                               C.c_int64, C.c_int32]),
+    "se_op_gram_z": (C.c_int, [C.c_void_p, C.c_int64, C.c_void_p, C.c_int64, C.c_int32,
+                               C.c_void_p, C.c_int64, C.c_int32, C.c_void_p]),
+    "se_op_update_z": (C.c_int, [C.c_void_p, C.c_int64, C.c_void_p, C.c_int64, C.c_int32,
+                                 C.c_void_p, C.c_int32, C.c_void_p, C.c_int64, C.c_double]),
+    "se_op_heev_lowest_z": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_void_p, C.c_void_p,
+                                      C.c_void_p]),
 }
 
 

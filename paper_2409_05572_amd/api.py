@@ -72,22 +72,28 @@ class Context:
 
 
 class Matrix:
-    """Symmetric CSR matrix copied to the device (se_matrix_create_csr)."""
+    """Symmetric (or, with complex values, Hermitian) CSR matrix copied to the
+    device (se_matrix_create_csr / se_matrix_create_csr_z)."""
 
     def __init__(self, ctx: Context, n, rowptr, colind, val, anorm, on_device=False):
         self.ctx = ctx
         self.n = int(n)
-        if not on_device:
+        if on_device:
+            import torch
+
+            self.is_complex = val.dtype == torch.complex128
+        else:
+            self.is_complex = np.iscomplexobj(val)
             rowptr = np.ascontiguousarray(rowptr, dtype=np.int64)
             colind = np.ascontiguousarray(colind, dtype=np.int32)
-            val = np.ascontiguousarray(val, dtype=np.float64)
+            val = np.ascontiguousarray(val, dtype=np.complex128 if self.is_complex else np.float64)
         self._keep = (rowptr, colind, val)
         h = C.c_void_p()
         flags = _lib.SE_MATRIX_DEVICE if on_device else _lib.SE_MATRIX_HOST
         nnz = int(rowptr[-1]) if not on_device else int(colind.numel())
-        check(lib().se_matrix_create_csr(ctx.handle, self.n, nnz, C.c_void_p(_ptr(rowptr)),
-                                         C.c_void_p(_ptr(colind)), C.c_void_p(_ptr(val)), flags,
-                                         float(anorm), C.byref(h)), "se_matrix_create_csr")
+        create = lib().se_matrix_create_csr_z if self.is_complex else lib().se_matrix_create_csr
+        check(create(ctx.handle, self.n, nnz, C.c_void_p(_ptr(rowptr)), C.c_void_p(_ptr(colind)),
+                     C.c_void_p(_ptr(val)), flags, float(anorm), C.byref(h)), "se_matrix_create_csr")
         self._h = h
         self._keep = None
         self.anorm = float(lib().se_matrix_anorm(h))  # the given bound, or the Gershgorin estimate for 0
@@ -210,6 +216,45 @@ def solve(ctx: Context, A: Matrix, X0, n_ev, n_extra, history_cap=0, **kw):
                     tuple(info.kern_ms), tuple(info.kern_bytes), tuple(info.kern_flops),
                     tuple(info.kern_calls), info.lp_iterations, info.n_reprojections)
     return lam, V, out
+
+
+def solve_z(ctx: Context, A: Matrix, X0, n_ev, n_extra, history_cap=0, **kw):
+    """Run se_solve_z on a complex Hermitian matrix.
+
+    X0: a host numpy complex array (n, nb) (Fortran order is taken), a torch
+    complex128 device tensor of shape (nb, n) (column-major n x nb), or None
+    (the real seeded block). Returns (lam, V, info) as solve(), V complex.
+    """
+    assert A.is_complex, "solve_z needs a matrix with complex values"
+    p = params(n_ev, n_extra, **kw)
+    hist = np.zeros((max(history_cap, 0), _lib.SE_HISTORY_FIELDS), dtype=np.float64)
+    if history_cap > 0:
+        p.history = hist.ctypes.data_as(C.POINTER(C.c_double))
+        p.history_cap = history_cap
+    info = SeInfo()
+    n = A.n
+    if X0 is None or isinstance(X0, np.ndarray):
+        if X0 is not None:
+            X0 = np.asfortranarray(X0, dtype=np.complex128)
+            assert X0.shape == (n, n_ev + n_extra)
+        V = np.zeros((n, n_ev), dtype=np.complex128, order="F")
+        lam = np.zeros(n_ev, dtype=np.float64)
+        p.ptr_mode = _lib.SE_PTR_HOST
+    else:
+        import torch
+
+        assert X0.dtype == torch.complex128 and X0.is_contiguous() and X0.shape == (n_ev + n_extra, n)
+        V = torch.empty((n_ev, n), dtype=torch.complex128, device=X0.device)
+        lam = torch.empty(n_ev, dtype=torch.float64, device=X0.device)
+        p.ptr_mode = _lib.SE_PTR_DEVICE
+    st = lib().se_solve_z(ctx.handle, A.handle, C.byref(p), C.c_void_p(None if X0 is None else _ptr(X0)),
+                          C.c_void_p(_ptr(V)), C.c_void_p(_ptr(lam)), C.byref(info))
+    if st < 0:
+        err = _lib.SeError(st, f"se_solve_z (hip_error {info.hip_error}, {info.iterations} iterations)")
+        err.hip_error = info.hip_error
+        err.history = hist[: info.history_len].copy()
+        raise err
+    return lam, V, _info_of(st, info, hist)
 
 
 def footprint(n, nnz, n_ev, n_extra, precision="fp64", solver="lobpcg") -> int:
@@ -340,6 +385,32 @@ def update_lp(ctx: Context, U, K: int, Cm, N: int, Out, beta: float = 0.0):
     check(lib().se_op_update_lp(ctx.handle, _lp_code(U), U.shape[0], C.c_void_p(_ptr(U)), U.stride(0),
                                 int(K), C.c_void_p(_ptr(Cm)), int(N), C.c_void_p(_ptr(Out)),
                                 Out.stride(0), float(beta)), "se_op_update_lp")
+
+
+def spmm_z(ctx: Context, A: Matrix, X, Y, w: int):
+    """Y = A X on complex128 row-major device blocks."""
+    check(lib().se_op_spmm_z(ctx.handle, A.handle, C.c_void_p(_ptr(X)), X.stride(0),
+                             C.c_void_p(_ptr(Y)), Y.stride(0), int(w)), "se_op_spmm_z")
+
+
+def gram_z(ctx: Context, U, mu: int, V, mv: int, out):
+    """out (complex128, mu x mv) = U^H V."""
+    check(lib().se_op_gram_z(ctx.handle, U.shape[0], C.c_void_p(_ptr(U)), U.stride(0), int(mu),
+                             C.c_void_p(_ptr(V)), V.stride(0), int(mv), C.c_void_p(_ptr(out))),
+          "se_op_gram_z")
+
+
+def update_z(ctx: Context, U, K: int, Cm, N: int, Out, beta: float = 0.0):
+    """Out = beta Out + U Cm on complex128 blocks."""
+    check(lib().se_op_update_z(ctx.handle, U.shape[0], C.c_void_p(_ptr(U)), U.stride(0), int(K),
+                               C.c_void_p(_ptr(Cm)), int(N), C.c_void_p(_ptr(Out)), Out.stride(0),
+                               float(beta)), "se_op_update_z")
+
+
+def heev_lowest_z(ctx: Context, A, k: int, w, Z):
+    """The k lowest eigenpairs of the Hermitian complex128 m x m matrix A (overwritten)."""
+    check(lib().se_op_heev_lowest_z(ctx.handle, A.shape[0], int(k), C.c_void_p(_ptr(A)),
+                                    C.c_void_p(_ptr(w)), C.c_void_p(_ptr(Z))), "se_op_heev_lowest_z")
 
 
 def syev(ctx: Context, A, w, Z):

@@ -248,7 +248,7 @@ double se_matrix_anorm(const se_matrix* m) { return m ? m->anorm : 0.0; }
 se_status se_solve(se_ctx* ctx, const se_matrix* A, const se_params* p, const double* X0,
                    double* V, double* lambda, se_info* info) {
     if (!ctx || !A || !p || !V || !lambda) return SE_ERR_INVALID_ARG;
-    if (A->ctx != ctx) return SE_ERR_INVALID_ARG;
+    if (A->ctx != ctx || A->is_complex) return SE_ERR_INVALID_ARG;
     const se_status v = se::validate_solve(A, p);
     if (v != SE_OK) return v;
     hipError_t e = hipSetDevice(ctx->device);
@@ -262,7 +262,7 @@ se_status se_solve(se_ctx* ctx, const se_matrix* A, const se_params* p, const do
 
 se_status se_op_spmm(se_ctx* ctx, const se_matrix* A, const double* X, int64_t ldx, double* Y,
                      int64_t ldy, int32_t w) {
-    if (!ctx || !A || !X || !Y || w < 1 || w > 256 || !valid_ld(ldx, w) || !valid_ld(ldy, w))
+    if (!ctx || !A || !X || !Y || w < 1 || w > 256 || !valid_ld(ldx, w) || !valid_ld(ldy, w) || A->is_complex)
         return SE_ERR_INVALID_ARG;
     if (!aligned16(X) || !aligned16(Y)) return SE_ERR_INVALID_ARG;
     CAPI_HC(ctx, hipSetDevice(ctx->device));
@@ -312,7 +312,8 @@ se_status se_op_update(se_ctx* ctx, int64_t n, const double* U, int64_t ldu, int
 
 se_status se_op_spmm_lp(se_ctx* ctx, int32_t precision, const se_matrix* A, const void* X, int64_t ldx,
                         void* Y, int64_t ldy, int32_t w) {
-    if (!ctx || !A || !X || !Y || w < 1 || w > 1024 || !lp_precision(precision)) return SE_ERR_INVALID_ARG;
+    if (!ctx || !A || !X || !Y || w < 1 || w > 1024 || !lp_precision(precision) || A->is_complex)
+        return SE_ERR_INVALID_ARG;
     if (!valid_ld_lp(ldx, w) || !valid_ld_lp(ldy, w) || !aligned16(X) || !aligned16(Y))
         return SE_ERR_INVALID_ARG;
     CAPI_HC(ctx, hipSetDevice(ctx->device));
@@ -429,6 +430,160 @@ se_status se_op_cholqr(se_ctx* ctx, int64_t n, double* W, int64_t ldw, int32_t w
     CAPI_HC(ctx, hipStreamSynchronize(ctx->stream));
     *rank = cur;
     return cur > 0 ? SE_OK : SE_ERR_BREAKDOWN;
+}
+
+se_status se_matrix_create_csr_z(se_ctx* ctx, int64_t n, int64_t nnz, const int64_t* rowptr,
+                                 const int32_t* colind, const double* val, uint32_t flags,
+                                 double anorm, se_matrix** out) {
+    if (!ctx || !out || !rowptr || (!colind && nnz > 0) || (!val && nnz > 0)) return SE_ERR_INVALID_ARG;
+    *out = nullptr;
+    if (n < 1 || nnz < 0 || n > INT32_MAX - 1 || nnz > INT32_MAX / 2) return SE_ERR_INVALID_ARG;
+    if (!(anorm >= 0.0) || !std::isfinite(anorm)) return SE_ERR_INVALID_ARG;
+    CAPI_HC(ctx, hipSetDevice(ctx->device));
+    const bool on_device = (flags & SE_MATRIX_DEVICE) != 0;
+    std::vector<int64_t> rp64(n + 1);
+    if (on_device)
+        CAPI_HC(ctx, hipMemcpy(rp64.data(), rowptr, sizeof(int64_t) * (n + 1), hipMemcpyDeviceToHost));
+    else
+        std::memcpy(rp64.data(), rowptr, sizeof(int64_t) * (n + 1));
+    if (rp64[0] != 0 || rp64[n] != nnz) return SE_ERR_INVALID_ARG;
+    for (int64_t i = 0; i < n; ++i)
+        if (rp64[i + 1] < rp64[i]) return SE_ERR_INVALID_ARG;
+    std::vector<int32_t> ci;
+    std::vector<double> vv;
+    const int32_t* cp = colind;
+    const double* vp = val;
+    if (on_device && nnz > 0) {
+        ci.resize(nnz);
+        vv.resize(2 * nnz);
+        CAPI_HC(ctx, hipMemcpy(ci.data(), colind, sizeof(int32_t) * nnz, hipMemcpyDeviceToHost));
+        CAPI_HC(ctx, hipMemcpy(vv.data(), val, sizeof(double) * 2 * nnz, hipMemcpyDeviceToHost));
+        cp = ci.data();
+        vp = vv.data();
+    }
+    for (int64_t e = 0; e < nnz; ++e) {
+        if (cp[e] < 0 || cp[e] >= n) return SE_ERR_INVALID_ARG;
+        if (!std::isfinite(vp[2 * e]) || !std::isfinite(vp[2 * e + 1])) return SE_ERR_INVALID_ARG;
+    }
+    if (anorm == 0.0) {  // Gershgorin: max_i sum_j |a_ij| bounds ||A||_2
+        for (int64_t i = 0; i < n; ++i) {
+            double s = 0.0;
+            for (int64_t e = rp64[i]; e < rp64[i + 1]; ++e) s += std::hypot(vp[2 * e], vp[2 * e + 1]);
+            anorm = std::max(anorm, s);
+        }
+        if (!(anorm > 0.0)) return SE_ERR_INVALID_ARG;
+    }
+    std::vector<int> rp32(n + 1);
+    for (int64_t i = 0; i <= n; ++i) rp32[i] = (int)rp64[i];
+    se_matrix* m = new (std::nothrow) se_matrix();
+    if (!m) return SE_ERR_OOM;
+    m->ctx = ctx;
+    m->device = ctx->device;
+    m->n = n;
+    m->nnz = nnz;
+    m->anorm = anorm;
+    m->is_complex = 1;
+    hipError_t e = hipMalloc(&m->rowptr, sizeof(int) * (n + 1));
+    if (e == hipSuccess) e = hipMalloc(&m->col, sizeof(int) * (nnz + se::kCsrPad));
+    if (e == hipSuccess) e = hipMalloc(&m->val, sizeof(double) * 2 * (nnz + se::kCsrPad));
+    if (e == hipSuccess) e = hipMemset(m->col + nnz, 0, sizeof(int) * se::kCsrPad);
+    if (e == hipSuccess) e = hipMemset(m->val + 2 * nnz, 0, sizeof(double) * 2 * se::kCsrPad);
+    if (e == hipSuccess) e = hipMemcpy(m->rowptr, rp32.data(), sizeof(int) * (n + 1), hipMemcpyHostToDevice);
+    if (e == hipSuccess && nnz > 0) e = hipMemcpy(m->col, cp, sizeof(int) * nnz, hipMemcpyHostToDevice);
+    if (e == hipSuccess && nnz > 0) e = hipMemcpy(m->val, vp, sizeof(double) * 2 * nnz, hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        se_matrix_destroy(m);
+        return hip_fail(ctx, e);
+    }
+    *out = m;
+    return SE_OK;
+}
+
+se_status se_solve_z(se_ctx* ctx, const se_matrix* A, const se_params* p, const double* X0, double* V,
+                     double* lambda, se_info* info) {
+    if (!ctx || !A || !p || !V || !lambda) return SE_ERR_INVALID_ARG;
+    if (A->ctx != ctx || !A->is_complex) return SE_ERR_INVALID_ARG;
+    if (p->solver != SE_LOBPCG && p->solver != SE_SI) {
+        return (p->solver == SE_SD || p->solver == SE_TRACEMIN) ? SE_ERR_UNSUPPORTED : SE_ERR_INVALID_ARG;
+    }
+    const se_status v = se::validate_solve(A, p);
+    if (v != SE_OK) return v;
+    if (p->precision != SE_FP64 || p->expand_vectors != SE_EXPAND_XDROP || p->filter_degree != 0 ||
+        p->precond != SE_PRECOND_NONE)
+        return SE_ERR_UNSUPPORTED;
+    const int64_t nb = (int64_t)p->n_ev + p->n_extra;
+    if (p->solver == SE_LOBPCG && nb > 170) return SE_ERR_UNSUPPORTED;  // 3 nb <= 512
+    if (p->solver == SE_SI && nb > 512) return SE_ERR_UNSUPPORTED;
+    CAPI_HC(ctx, hipSetDevice(ctx->device));
+    (void)hipGetLastError();
+    if (info) std::memset(info, 0, sizeof(*info));
+    return se::solve_z(ctx, A, p, X0, V, lambda, info);
+}
+
+se_status se_op_spmm_z(se_ctx* ctx, const se_matrix* A, const double* X, int64_t ldx, double* Y, int64_t ldy,
+                       int32_t w) {
+    if (!ctx || !A || !X || !Y || !A->is_complex || w < 1 || w > 512 || !valid_ld(ldx, w) || !valid_ld(ldy, w))
+        return SE_ERR_INVALID_ARG;
+    if (!aligned16(X) || !aligned16(Y)) return SE_ERR_INVALID_ARG;
+    CAPI_HC(ctx, hipSetDevice(ctx->device));
+    CAPI_HC(ctx, se::launch_spmm_z(ctx->stream, (int)A->n, A->rowptr, A->col, A->val, X, ldx, Y, ldy, w));
+    return SE_OK;
+}
+
+se_status se_op_gram_z(se_ctx* ctx, int64_t n, const double* U, int64_t ldu, int32_t mu, const double* V,
+                       int64_t ldv, int32_t mv, double* C) {
+    if (!ctx || !U || !V || !C || n < 1 || mu < 1 || mv < 1 || mu > 512 || mv > 512) return SE_ERR_INVALID_ARG;
+    if (!valid_ld(ldu, mu) || !valid_ld(ldv, mv)) return SE_ERR_INVALID_ARG;
+    CAPI_HC(ctx, hipSetDevice(ctx->device));
+    se::Workspace& ws = ctx->ws;
+    const size_t need = sizeof(double) * se::gram_scratch_doubles(n, 2 * mu, 2 * mv);
+    const size_t pbytes = sizeof(double) * 4 * (size_t)mu * mv;
+    if (need > ws.gram_part.bytes || pbytes > ws.lpM.bytes) {
+        CAPI_HC(ctx, hipStreamSynchronize(ctx->stream));
+        CAPI_HC(ctx, ws.gram_part.ensure(need));
+        CAPI_HC(ctx, ws.lpM.ensure(pbytes));
+    }
+    se::Segs Us = se::make_segs(2 * ldu), Vs = se::make_segs(2 * ldv);
+    se::push_seg(Us, U, 2 * mu);
+    se::push_seg(Vs, V, 2 * mv);
+    const int sym = (U == V && ldu == ldv && mu == mv) ? 1 : 0;
+    CAPI_HC(ctx, se::launch_gram(ctx->stream, n, Us, Vs, sym, ws.gram_part.as<double>(), ws.lpM.as<double>()));
+    CAPI_HC(ctx, se::launch_zgram_combine(ctx->stream, mu, mv, ws.lpM.as<double>(), C));
+    return SE_OK;
+}
+
+se_status se_op_update_z(se_ctx* ctx, int64_t n, const double* U, int64_t ldu, int32_t K, const double* C,
+                         int32_t N, double* Out, int64_t ldo, double beta) {
+    if (!ctx || !U || !C || !Out || n < 1 || K < 1 || N < 1 || K > 512 || N > 512) return SE_ERR_INVALID_ARG;
+    if (!valid_ld(ldu, K) || !valid_ld(ldo, N) || !(beta == 0.0 || beta == 1.0)) return SE_ERR_INVALID_ARG;
+    const char* u0 = reinterpret_cast<const char*>(U);
+    const char* u1 = u0 + 16 * (size_t)((n - 1) * ldu + K);
+    const char* o0 = reinterpret_cast<const char*>(Out);
+    const char* o1 = o0 + 16 * (size_t)((n - 1) * ldo + N);
+    if (o0 < u1 && u0 < o1) return SE_ERR_INVALID_ARG;
+    CAPI_HC(ctx, hipSetDevice(ctx->device));
+    se::Workspace& ws = ctx->ws;
+    const size_t ebytes = sizeof(double) * 4 * (size_t)K * N;
+    if (ebytes > ws.lpT.bytes) {
+        CAPI_HC(ctx, hipStreamSynchronize(ctx->stream));
+        CAPI_HC(ctx, ws.lpT.ensure(ebytes));
+    }
+    CAPI_HC(ctx, se::launch_zembed(ctx->stream, K, N, C, ws.lpT.as<double>()));
+    se::Segs Us = se::make_segs(2 * ldu), Os = se::make_segs(2 * ldo);
+    se::push_seg(Us, U, 2 * K);
+    se::push_seg(Os, Out, 2 * N);
+    CAPI_HC(ctx, se::launch_update(ctx->stream, n, Us, ws.lpT.as<double>(), 2 * N, Os, 1.0, beta));
+    return SE_OK;
+}
+
+se_status se_op_heev_lowest_z(se_ctx* ctx, int32_t m, int32_t k, double* A, double* w, double* Z) {
+    if (!ctx || !A || !w || !Z || m < 1 || m > 512 || k < 1 || k > m) return SE_ERR_INVALID_ARG;
+    CAPI_HC(ctx, hipSetDevice(ctx->device));
+    CAPI_HC(ctx, hipStreamSynchronize(ctx->stream));
+    CAPI_HC(ctx, ctx->ws.syev_work.ensure(sizeof(double) * se::heev_z_work_doubles(m)));
+    CAPI_HC(ctx, se::launch_heev_lowest_z(ctx->stream, m, k, A, w, Z, ctx->ws.syev_work.as<double>()));
+    CAPI_HC(ctx, hipStreamSynchronize(ctx->stream));
+    return SE_OK;
 }
 
 se_status se_strategy_replay(const se_params* p, int32_t count, const double* r, int32_t* flags) {

@@ -281,6 +281,46 @@ hipError_t launch_syev_lowest(hipStream_t st, int m, int k, double* A, double* w
                               double* work);
 hipError_t launch_syev(hipStream_t st, int m, double* A, double* w, double* Z, double* work);
 
+// The k lowest eigenpairs of the real symmetric tridiagonal (d, e) of order
+// m: w ascending, ZT (m x k row-major, leading dimension k) orthonormal
+// eigenvectors (bisection, inverse iteration, orthonormalization as in
+// launch_syev_lowest). work needs tridiag_vectors_work_doubles(m).
+size_t tridiag_vectors_work_doubles(int m);
+hipError_t launch_tridiag_lowest_vectors(hipStream_t st, int m, int k, const double* d, const double* e,
+                                         double* w, double* ZT, double* work);
+
+// ---- complex Hermitian kernels (complex.hip), FP64, interleaved (re, im) ----
+// Y = A X for complex CSR A (2 nnz + 2 kCsrPad values) and complex row-major
+// blocks (leading dimensions in complex entries; 16-byte aligned).
+hipError_t launch_spmm_z(hipStream_t st, int n, const int* rowptr, const int* col, const double* val,
+                         const double* X, long long ldx, double* Y, long long ldy, int w);
+// C (mu x mv complex) = U^H V from the real Gram product P (2mu x 2mv) of the
+// interleaved views of U and V.
+hipError_t launch_zgram_combine(hipStream_t st, int mu, int mv, const double* P, double* C);
+// E (2K x 2N real) = the real embedding of the complex K x N matrix C, so
+// that a real update of an interleaved view by E is the complex update by C.
+hipError_t launch_zembed(hipStream_t st, int K, int N, const double* C, double* E);
+// A <- (A + A^H) / 2 (complex m x m).
+hipError_t launch_zherm(hipStream_t st, int m, double* A);
+// Hetmaniuk-Lehoucq start block in complex coefficients (as launch_hl_init,
+// with Y = Z1^H E).
+hipError_t launch_hl_init_z(hipStream_t st, int m, int k, const double* Z1, const int* act, int a, double* B,
+                            double* Y);
+// Complex Cholesky-QR transform with column drop (a <= 512): T (a x r complex,
+// leading dimension r) with W T orthonormal for G = W^H W; info as
+// launch_chol_drop. work holds 2 a^2 doubles.
+hipError_t launch_cholz(hipStream_t st, int a, const double* G, double* T, double* work, int* info_i,
+                        double* info_d, double drop_tol2);
+// Complex column-major (leading dimension n) <-> complex rows (leading
+// dimension ldc); a real column-major block into complex rows (imaginary 0).
+hipError_t launch_zcol_to_rows(hipStream_t st, long long n, int w, const double* src, double* dst, long long ldc);
+hipError_t launch_zrows_to_col(hipStream_t st, long long n, int w, const double* src, long long ldc, double* dst);
+hipError_t launch_rcol_to_zrows(hipStream_t st, long long n, int w, const double* src, double* dst, long long ldc);
+// The k lowest eigenpairs of the Hermitian m x m complex matrix A (m <= 512;
+// overwritten): w ascending (real), Z (m x k complex, leading dimension k).
+size_t heev_z_work_doubles(int m);
+hipError_t launch_heev_lowest_z(hipStream_t st, int m, int k, double* A, double* w, double* Z, double* work);
+
 // Hetmaniuk-Lehoucq start block from Z1 (m x k, ld k) and the positions
 // act[0..a) of the unlocked old X columns: B (m x a, ld a) = unit columns
 // e_{act[c]}, Y (k x a, ld a) = rows act[c] of Z1, transposed.

@@ -158,6 +158,7 @@ struct se_matrix {
     double* val = nullptr;
     mutable float* val32 = nullptr;  // FP32 copy for the mixed-precision phase, made on first use
     mutable std::mutex val32_mu;     // guards the first-use creation of val32
+    int is_complex = 0;  // Hermitian with complex values: val holds 2 (nnz + kCsrPad) interleaved doubles
     int* heavy = nullptr;  // rows with more than kHeavyRow nonzeros (one workgroup each in SpMM)
     int n_heavy = 0;
     double anorm = 0.0;
@@ -171,4 +172,8 @@ size_t solve_workspace_bytes(long long n, long long nnz, int nb, int precision, 
 // the last), made once per matrix, ordered on `st`.
 hipError_t make_val32(hipStream_t st, const se_matrix* A);
 se_status validate_solve(const se_matrix* A, const se_params* p);
+// Complex Hermitian A (A->is_complex): LOBPCG or SI, FP64; X0, V complex
+// column-major interleaved.
+se_status solve_z(se_ctx* ctx, const se_matrix* A, const se_params* p, const double* X0, double* V,
+                  double* lambda, se_info* info);
 }

@@ -191,7 +191,7 @@ se_status se_server_create(se_ctx* ctx, uint64_t hbm_budget_bytes, int32_t max_s
 se_status se_submit(se_server* srv, const se_matrix* A, const se_params* params, const double* X0,
                     double* V, double* lambda, se_ticket* ticket) {
     if (!srv || !A || !params || !V || !lambda || !ticket) return SE_ERR_INVALID_ARG;
-    if (!A->ctx || A->ctx->device != srv->device) return SE_ERR_INVALID_ARG;
+    if (!A->ctx || A->ctx->device != srv->device || A->is_complex) return SE_ERR_INVALID_ARG;
     const se_status v = se::validate_solve(A, params);
     if (v != SE_OK) return v;
     auto r = std::make_unique<Request>();

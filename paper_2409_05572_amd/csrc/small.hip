@@ -1053,6 +1053,50 @@ hipError_t launch_syev_lowest(hipStream_t st, int m, int k, double* A, double* w
     return hipGetLastError();
 }
 
+size_t tridiag_vectors_work_doubles(int m) {
+    const size_t mm = (size_t)m * m;
+    // scal (16), two vector blocks (2 m^2), inverse-iteration factors (5 m^2),
+    // Gram and transform (2 m^2), Gram scratch, Cholesky work (2 m^2 + 2m),
+    // info words
+    return 16 + 2 * mm + 5 * mm + 2 * mm + gram_scratch_doubles(m, m, m) + 2 * mm + 2 * (size_t)m + 64 +
+           2 * (size_t)m + 256;
+}
+
+hipError_t launch_tridiag_lowest_vectors(hipStream_t st, int m, int k, const double* d, const double* e,
+                                         double* w, double* ZT, double* work) {
+    if (m <= 0 || m > 1024 || k <= 0 || k > m) return hipErrorInvalidValue;
+    const size_t mm = (size_t)m * m;
+    double* scal = work;
+    double* B0 = scal + 16;
+    double* B1 = B0 + mm;
+    double* fac = B1 + mm;
+    double* Gk = fac + 5 * mm;
+    double* Tk = Gk + mm;
+    double* gpart = Tk + mm;
+    double* cwork = gpart + gram_scratch_doubles(m, m, m);
+    double* infod = cwork + 2 * mm + 2 * (size_t)m;
+    int* infoi = reinterpret_cast<int*>(infod + 8);
+    hipLaunchKernelGGL(bisect_kernel, dim3((k + 3) / 4), dim3(256), 0, st, m, k, d, e, w, scal);
+    hipLaunchKernelGGL(invit_kernel, dim3((k + 255) / 256), dim3(256), 0, st, m, k, d, e, w, scal, B0, fac);
+    // the same three orthonormalization passes as launch_syev_lowest, the
+    // last one writing ZT
+    double* src[3] = {B0, B1, B0};
+    double* dst[3] = {B1, B0, ZT};
+    for (int pass = 0; pass < 3; ++pass) {
+        Segs Zs = make_segs(k);
+        push_seg(Zs, src[pass], k);
+        hipError_t err = launch_gram(st, m, Zs, Zs, 1, gpart, Gk);
+        if (err != hipSuccess) return err;
+        err = launch_chol_drop(st, k, Gk, Tk, cwork, infoi, infod, -1.0, pass == 0 ? 0.0 : 1e-8);
+        if (err != hipSuccess) return err;
+        Segs Os = make_segs(k);
+        push_seg(Os, dst[pass], k);
+        err = launch_update(st, m, Zs, Tk, k, Os, 1.0, 0.0);
+        if (err != hipSuccess) return err;
+    }
+    return hipGetLastError();
+}
+
 hipError_t launch_syev(hipStream_t st, int m, double* A, double* w, double* Z, double* work) {
     return launch_syev_lowest(st, m, m, A, w, Z, work);
 }

@@ -33,7 +33,7 @@ def cluster_angles(lam, V, W, rtol=1e-6):
         while j < n_ev and abs(lam[j] - lam[j - 1]) <= rtol * max(abs(lam[j]), 1e-300):
             j += 1
         if j < n_ev:  # complete cluster [i, j)
-            s = np.linalg.svd(V[:, i:j].T @ W[:, i:j], compute_uv=False)
+            s = np.linalg.svd(V[:, i:j].conj().T @ W[:, i:j], compute_uv=False)
             worst = max(worst, float(np.sqrt(max(0.0, 1.0 - min(1.0, s.min()) ** 2))))
         i = j
     return worst
