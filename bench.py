@@ -28,12 +28,14 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 METRIC = "time-to-solution & HBM GB/s, shrink-expand vs fixed block; p50/p99 latency"
+MAGNETIC_PHASES = (0.3, 0.7, 1.1)  # phase per grid step of the complex Hermitian workload
 
 
 # Workloads: matrix family and default sizes (n_ev, n_extra, solver, precision).
 WORKLOADS = {
     "laplace3d": dict(grid=128, n_ev=64, n_extra=32, x0_seed=202),
     "laplace2d": dict(grid=32, n_ev=8, n_extra=8, x0_seed=201),
+    "magnetic": dict(grid=128, n_ev=64, n_extra=32, x0_seed=207),
     "anderson": dict(grid=100, n_ev=200, n_extra=50, x0_seed=203),
     "chunglu": dict(nodes=500000, n_ev=32, n_extra=16, x0_seed=204),
     "serving": dict(x0_seed=305),
@@ -92,6 +94,8 @@ def build_matrix(args):
         return W.laplacian_3d(args.grid), f"laplace3d_{args.grid}^3"
     if args.workload == "laplace2d":
         return W.laplacian_2d(args.grid), f"laplace2d_{args.grid}^2"
+    if args.workload == "magnetic":
+        return W.magnetic_laplacian(args.grid, MAGNETIC_PHASES), f"magnetic3d_torus_{args.grid}^3"
     if args.workload == "anderson":
         return W.anderson_3d(args.grid, 4.0, 103), f"anderson3d_{args.grid}^3_w4"
     return W.chung_lu_laplacian(args.nodes, 16.0, 2.5, 104), f"chunglu_n{args.nodes}_d16_b2.5"
@@ -119,7 +123,8 @@ def main():
     t = time.time()
     A, wname = build_matrix(args)
     nb = args.n_ev + args.n_extra
-    X0 = W.gaussian_block(A.n, nb, args.x0_seed)
+    cplx = A.is_complex
+    X0 = (W.gaussian_block_complex if cplx else W.gaussian_block)(A.n, nb, args.x0_seed)
     log(f"inputs n={A.n} nnz={A.nnz} nb={nb} built in {time.time() - t:.1f}s")
 
     if args.calibrate_copy:
@@ -143,10 +148,13 @@ def main():
     extra.update(expand_vectors=args.expand_vectors, seed=args.x0_seed, filter_degree=args.filter_degree,
                  precond=args.precond)
 
+    if cplx:  # complex Hermitian: FP64 LOBPCG / SI with X_drop expansions only
+        extra = {} if args.max_iter is None else {"max_iter": args.max_iter}
+
     def run(strategy, profile=0):
-        return api.solve(ctx, M, X0d, args.n_ev, args.n_extra, strategy=strategy, tol=1e-8,
-                         history_cap=30000, profile=profile, solver=args.solver,
-                         precision=args.precision, **extra)
+        return (api.solve_z if cplx else api.solve)(
+            ctx, M, X0d, args.n_ev, args.n_extra, strategy=strategy, tol=1e-8, history_cap=30000,
+            profile=profile, solver=args.solver, precision=args.precision, **extra)
 
     for i in range(args.warmup):
         lam, V, info = run(args.strategy)
@@ -176,7 +184,7 @@ def main():
         "higher_is_better": False,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": {"fp64": "f64", "fp32": "f32+f64", "bf16": "bf16+f64"}[args.precision],
+        "dtype": "c128" if cplx else {"fp64": "f64", "fp32": "f32+f64", "bf16": "bf16+f64"}[args.precision],
         "data": "synthetic",
         "config": {
             "workload": f"{wname} {args.solver.upper()} n_ev={args.n_ev} n_extra={args.n_extra} "
@@ -198,6 +206,9 @@ def main():
     }
     lam_np = lam.cpu().numpy() if hasattr(lam, "cpu") else np.asarray(lam)
     out["parity"] = {"max_stop_ratio": infos[-1].max_stop_ratio}
+    if args.workload == "magnetic":
+        ex = W.magnetic_spectrum(args.grid, MAGNETIC_PHASES)[: args.n_ev]
+        out["parity"]["max_eig_rel_err_vs_closed_form"] = float(np.max(np.abs(lam_np - ex) / ex))
     if args.workload in ("laplace3d", "laplace2d"):
         # Dirichlet Laplacian eigenvalues: sums of 2 - 2 cos(k pi / (m + 1))
         m = args.grid
@@ -225,6 +236,7 @@ def main():
         log(f"fixed block: median {fmed:.3f}s of {runs} iters={[i.iterations for i in finfos]}")
 
     tag = {"laplace3d": f"laplace3d_{args.grid}", "laplace2d": f"laplace2d_{args.grid}",
+           "magnetic": f"magnetic_{args.grid}",
            "anderson": f"anderson_{args.grid}", "chunglu": f"chunglu_{args.nodes}"}[args.workload]
     out["roofline"], out["kernels"] = roofline([pinfo], f"{tag}_{args.precision}", args.precision)
     # release the solve's device memory before the serving leg and before exit
