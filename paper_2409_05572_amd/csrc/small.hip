@@ -186,6 +186,234 @@ __global__ __launch_bounds__(kSmall) void chol_drop_kernel(int a, const double* 
     }
 }
 
+// Cholesky-QR transform with column drop for a <= kCholBlk (same inputs,
+// outputs and drop rule as chol_drop_kernel), blocked so that synchronization
+// no longer scales with a: the scaled matrix lives in LDS (odd row stride);
+// panels of 16 columns are factorized by one wave (lanes own rows, the pivot
+// column broadcast by shuffles), each followed by one workgroup-wide update
+// of the trailing lower triangle. The inverse of L over the kept columns
+// (dropped rows and columns replaced by the identity, which leaves the kept
+// block's inverse unchanged) is formed by 16 x 16 blocks: every diagonal
+// block by one wave, then the block diagonals at distance 1, 2, ... from
+// products of blocks already formed, two barriers each. L stays in the lower
+// triangle, R^{-1} = L^{-T} goes to the upper one.
+constexpr int kCholBlk = 112;
+constexpr int kCholPanel = 16;
+__global__ __launch_bounds__(kSmall) void chol_drop_blocked_kernel(int a, const double* __restrict__ G,
+                                                                   double* __restrict__ T,
+                                                                   int* __restrict__ info_i,
+                                                                   double* __restrict__ info_d, double drop_tol2,
+                                                                   double ns_tol) {
+    extern __shared__ double F[];  // a x FS
+    __shared__ int s_pos[kCholBlk];
+    __shared__ int s_kept[kCholBlk];
+    __shared__ double s_D[kCholBlk];
+    __shared__ double s_dl[kCholBlk];  // diagonal of L (0 where dropped)
+    __shared__ double s_di[kCholBlk];  // diagonal of L^{-1} (1 where dropped)
+    __shared__ double s_tmp[(kCholBlk / kCholPanel) * kCholPanel * kCholPanel];
+    __shared__ double s_red[kSWaves];
+    __shared__ double s_minpiv;
+    __shared__ int s_r;
+    const int t = threadIdx.x;
+    const int nth = blockDim.x;
+    const int FS = a | 1;
+    const bool can_drop = drop_tol2 >= 0.0;
+    const int lane = t & 63, wid = t >> 6, nwave = nth >> 6;
+    if (ns_tol > 0.0) {
+        double sq = 0.0;
+        for (int e = t; e < a * a; e += nth) {
+            const double v = G[e] - ((e / a == e % a) ? 1.0 : 0.0);
+            sq += v * v;
+        }
+        sq = block_sum(sq, s_red);
+        if (sq <= ns_tol * ns_tol) {
+            for (int e = t; e < a * a; e += nth) T[e] = ((e / a == e % a) ? 1.5 : 0.0) - 0.5 * G[e];
+            for (int i = t; i < a; i += nth) info_i[1 + i] = i;
+            if (t == 0) {
+                info_i[0] = a;
+                info_d[0] = 1.0 - sqrt(sq);
+            }
+            return;
+        }
+    }
+    for (int i = t; i < a; i += nth) {
+        const double g = G[i * a + i];
+        s_D[i] = (g > 0.0) ? 1.0 / sqrt(g) : 0.0;
+    }
+    __syncthreads();
+    for (int e = t; e < a * a; e += nth) {
+        const int i = e / a, j = e % a;
+        if (j <= i) F[i * FS + j] = G[e] * s_D[i] * s_D[j];
+    }
+    if (t == 0) s_minpiv = DBL_MAX;
+    __syncthreads();
+
+    // ---- blocked right-looking factorization ----
+    for (int jb = 0; jb < a; jb += kCholPanel) {
+        const int nbw = min(kCholPanel, a - jb);
+        if (wid == 0) {
+            // rows jb + lane and jb + lane + 64 of the panel's columns
+            double P[2][kCholPanel];
+            const int i0 = jb + lane, i1 = jb + lane + 64;
+#pragma unroll
+            for (int c = 0; c < kCholPanel; ++c) {
+                P[0][c] = (c < nbw && i0 < a && i0 >= jb + c) ? F[i0 * FS + jb + c] : 0.0;
+                P[1][c] = (c < nbw && i1 < a) ? F[i1 * FS + jb + c] : 0.0;
+            }
+            double minp = DBL_MAX;
+            // fully unrolled (no break or continue), so P stays in registers
+#pragma unroll
+            for (int c = 0; c < kCholPanel; ++c) {
+                if (c < nbw) {
+                    const int j = jb + c;
+                    double dj = __shfl(P[0][c], c, 64);
+                    const bool drop = can_drop && (!(dj > drop_tol2) || s_D[j] == 0.0);
+                    if (!can_drop && !(dj > 1e-300)) dj = 1e-300;
+                    if (drop) {
+                        if (i0 >= j) P[0][c] = 0.0;
+                        P[1][c] = 0.0;
+                        if (lane == 0) {
+                            s_pos[j] = -1;
+                            s_dl[j] = 0.0;
+                        }
+                    } else {
+                        const double piv = sqrt(dj);
+                        const double inv = 1.0 / piv;
+                        minp = fmin(minp, dj);
+                        if (i0 > j) P[0][c] *= inv;
+                        if (lane == c) P[0][c] = piv;
+                        P[1][c] *= inv;
+                        if (lane == 0) {
+                            s_pos[j] = 0;
+                            s_dl[j] = piv;
+                        }
+#pragma unroll
+                        for (int c2 = c + 1; c2 < kCholPanel; ++c2) {
+                            if (c2 < nbw) {
+                                const double l2 = __shfl(P[0][c], c2, 64);  // L[jb + c2][j]
+                                if (i0 >= jb + c2) P[0][c2] -= P[0][c] * l2;
+                                P[1][c2] -= P[1][c] * l2;
+                            }
+                        }
+                    }
+                }
+            }
+#pragma unroll
+            for (int c = 0; c < kCholPanel; ++c) {
+                if (c < nbw && i0 < a && i0 >= jb + c) F[i0 * FS + jb + c] = P[0][c];
+                if (c < nbw && i1 < a) F[i1 * FS + jb + c] = P[1][c];
+            }
+            if (lane == 0) s_minpiv = fmin(s_minpiv, minp);
+        }
+        __syncthreads();
+        // trailing update: F[i][i2] -= sum_c L[i][jb + c] L[i2][jb + c], jb + nbw <= i2 <= i
+        const int t0 = jb + nbw;
+        for (int i = t0 + wid; i < a; i += nwave) {
+            double li[kCholPanel];
+#pragma unroll
+            for (int c = 0; c < kCholPanel; ++c) li[c] = (c < nbw) ? F[i * FS + jb + c] : 0.0;
+            for (int i2 = t0 + lane; i2 <= i; i2 += 64) {
+                double sacc = 0.0;
+#pragma unroll
+                for (int c = 0; c < kCholPanel; ++c)
+                    if (c < nbw) sacc = fma(li[c], F[i2 * FS + jb + c], sacc);
+                F[i * FS + i2] -= sacc;
+            }
+        }
+        __syncthreads();
+    }
+    if (t == 0) {
+        int r = 0;
+        for (int j = 0; j < a; ++j) {
+            if (s_pos[j] >= 0) {
+                s_pos[j] = r;
+                s_kept[r] = j;
+                info_i[1 + r] = j;
+                ++r;
+            }
+        }
+        s_r = r;
+        info_i[0] = r;
+        info_d[0] = s_minpiv;
+    }
+    __syncthreads();
+    const int r = s_r;
+
+    // ---- inverse of the modified L by 16 x 16 blocks ----
+    // Lm(i, j): L over kept rows and columns, identity on dropped ones.
+    auto Lm = [&](int i, int j) -> double {
+        if (s_pos[i] < 0 || s_pos[j] < 0) return (i == j) ? 1.0 : 0.0;
+        return (i == j) ? s_dl[i] : F[i * FS + j];
+    };
+    // Linv(i, j), i >= j: diagonal in s_di, below it stored transposed at F[j][i]
+    auto Li = [&](int i, int j) -> double { return (i == j) ? s_di[i] : F[j * FS + i]; };
+    const int nbk = (a + kCholPanel - 1) / kCholPanel;
+    // diagonal blocks: wave b inverts block b, lane c forms column c by
+    // forward substitution
+    for (int b = wid; b < nbk; b += nwave) {
+        const int b0 = b * kCholPanel, bs = min(kCholPanel, a - b0);
+        const int c = lane;
+        if (c < bs) {
+            double x[kCholPanel];
+#pragma unroll
+            for (int rr = 0; rr < kCholPanel; ++rr) {
+                double v = 0.0;
+                if (rr < bs && rr >= c) {
+                    double sacc = (rr == c) ? 1.0 : 0.0;
+#pragma unroll
+                    for (int q = 0; q < kCholPanel; ++q)
+                        if (q >= c && q < rr) sacc -= Lm(b0 + rr, b0 + q) * x[q];
+                    v = sacc / Lm(b0 + rr, b0 + rr);
+                }
+                x[rr] = v;
+            }
+#pragma unroll
+            for (int rr = 0; rr < kCholPanel; ++rr) {
+                if (rr < bs && rr == c) s_di[b0 + c] = x[rr];
+                if (rr < bs && rr > c) F[(b0 + c) * FS + b0 + rr] = x[rr];
+            }
+        }
+    }
+    __syncthreads();
+    // block diagonals: Linv[I][J] = -Linv[I][I] sum_{K=J}^{I-1} L[I][K] Linv[K][J]
+    for (int dist = 1; dist < nbk; ++dist) {
+        const int npair = nbk - dist;
+        for (int e = t; e < npair * kCholPanel * kCholPanel; e += nth) {
+            const int J = e / (kCholPanel * kCholPanel), I = J + dist;
+            const int rr = (e / kCholPanel) % kCholPanel, cc = e % kCholPanel;
+            const int gi = I * kCholPanel + rr, gj = J * kCholPanel + cc;
+            double sacc = 0.0;
+            if (gi < a) {
+                for (int gk = gj; gk < I * kCholPanel; ++gk) sacc = fma(Lm(gi, gk), Li(gk, gj), sacc);
+            }
+            s_tmp[e] = sacc;
+        }
+        __syncthreads();
+        for (int e = t; e < npair * kCholPanel * kCholPanel; e += nth) {
+            const int J = e / (kCholPanel * kCholPanel), I = J + dist;
+            const int rr = (e / kCholPanel) % kCholPanel, cc = e % kCholPanel;
+            const int gi = I * kCholPanel + rr, gj = J * kCholPanel + cc;
+            if (gi >= a) continue;
+            double sacc = 0.0;
+            for (int q = 0; q <= rr; ++q)
+                sacc = fma(Li(gi, I * kCholPanel + q), s_tmp[J * kCholPanel * kCholPanel + q * kCholPanel + cc], sacc);
+            F[gj * FS + gi] = -sacc;
+        }
+        __syncthreads();
+    }
+    // T = D R^{-1} on the kept columns: T[i][q] = D_i X[i][kept q], X = L^{-T}
+    for (int e = t; e < a * r; e += nth) {
+        const int i = e / r, q = e % r;
+        const int p = s_pos[i];
+        double v = 0.0;
+        if (p >= 0 && p <= q) {
+            const int kq = s_kept[q];
+            v = s_D[i] * ((i == kq) ? s_di[i] : F[i * FS + kq]);
+        }
+        T[e] = v;
+    }
+}
+
 // ---------------------------------------------------------------------------
 // Householder tridiagonalization of the symmetric m x m matrix A (row-major,
 // both triangles kept up to date; copied into LDS when it fits). Reflector k
@@ -287,6 +515,77 @@ __global__ __launch_bounds__(kTri) void tridiag_kernel(int m, int kend, double* 
             e[m - 2] = A[(size_t)(m - 1) * m + (m - 2)];
         }
         d[m - 1] = A[(size_t)(m - 1) * m + (m - 1)];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Householder tridiagonalization of small matrices (m <= 64) by one wave:
+// lane l owns row l of the matrix, kept in LDS with an odd row stride (no
+// bank conflicts when the lanes walk a column). Same reflectors and outputs
+// as tridiag_kernel; with a single wave the barriers are free, so a
+// reflector costs a few passes over the lane's row instead of several
+// workgroup-wide synchronizations.
+constexpr int kWaveTri = 64;
+__global__ __launch_bounds__(64) void tridiag_wave_kernel(int m, const double* __restrict__ Ag,
+                                                          double* __restrict__ d, double* __restrict__ e,
+                                                          double* __restrict__ tau, double* __restrict__ Vh) {
+    constexpr int S = kWaveTri + 1;
+    __shared__ double A[kWaveTri * S];
+    __shared__ double sv[kWaveTri];
+    __shared__ double sw[kWaveTri];
+    const int l = threadIdx.x;
+    for (int q = l; q < m * m; q += 64) A[(q / m) * S + q % m] = Ag[q];
+    __syncthreads();
+    for (int k = 0; k + 2 < m; ++k) {
+        const bool below = l > k && l < m;
+        const double xl = below ? A[l * S + k] : 0.0;  // column k under the diagonal
+        const double sigma2 = wave_sum((l >= k + 2 && l < m) ? xl * xl : 0.0);
+        const double alpha = __shfl(xl, k + 1, 64);
+        double tk = 0.0, beta = alpha, scale = 0.0;
+        if (sigma2 > 0.0) {
+            beta = -copysign(sqrt(alpha * alpha + sigma2), alpha);
+            tk = (beta - alpha) / beta;
+            scale = 1.0 / (alpha - beta);
+        }
+        if (l == 0) {
+            d[k] = A[k * S + k];
+            e[k] = beta;
+            tau[k] = tk;
+        }
+        const double v = (l == k + 1) ? 1.0 : ((l > k + 1 && l < m && tk != 0.0) ? xl * scale : 0.0);
+        if (below) Vh[(size_t)k * m + l] = v;
+        if (tk == 0.0) continue;  // uniform
+        sv[l] = v;
+        __syncthreads();
+        // p = tau A22 v (row l), K = tau/2 p.v, w = p - K v
+        double p = 0.0;
+        if (below) {
+            double p0 = 0.0, p1 = 0.0, p2 = 0.0, p3 = 0.0;  // four chains hide the FMA latency
+            int j = k + 1;
+            for (; j + 3 < m; j += 4) {
+                p0 = fma(A[l * S + j], sv[j], p0);
+                p1 = fma(A[l * S + j + 1], sv[j + 1], p1);
+                p2 = fma(A[l * S + j + 2], sv[j + 2], p2);
+                p3 = fma(A[l * S + j + 3], sv[j + 3], p3);
+            }
+            for (; j < m; ++j) p0 = fma(A[l * S + j], sv[j], p0);
+            p = tk * ((p0 + p1) + (p2 + p3));
+        }
+        const double Kc = 0.5 * tk * wave_sum(p * v);
+        const double w = p - Kc * v;
+        sw[l] = w;
+        __syncthreads();
+        // A22 -= v w^T + w v^T
+        if (below)
+            for (int j = k + 1; j < m; ++j) A[l * S + j] -= v * sw[j] + w * sv[j];
+        __syncthreads();
+    }
+    if (l == 0) {
+        if (m >= 2) {
+            d[m - 2] = A[(m - 2) * S + (m - 2)];
+            e[m - 2] = A[(m - 1) * S + (m - 2)];
+        }
+        d[m - 1] = A[(m - 1) * S + (m - 1)];
     }
 }
 
@@ -897,7 +1196,10 @@ __global__ __launch_bounds__(kSmall) void sumsq_kernel(long long count, const do
 hipError_t launch_chol_drop(hipStream_t st, int a, const double* G, double* T, double* work,
                             int* info_i, double* info_d, double drop_tol2, double ns_tol) {
     if (a <= 0 || a > 1024) return hipErrorInvalidValue;
-    if ((size_t)a * a <= (size_t)kLdsDoubles)
+    if (a <= kCholBlk)
+        hipLaunchKernelGGL(chol_drop_blocked_kernel, dim3(1), dim3(kSmall), sizeof(double) * (size_t)a * (a | 1), st,
+                           a, G, T, info_i, info_d, drop_tol2, ns_tol);
+    else if ((size_t)a * a <= (size_t)kLdsDoubles)
         hipLaunchKernelGGL(chol_drop_kernel<true>, dim3(1), dim3(kSmall), sizeof(double) * (size_t)a * a, st, a,
                            G, T, work, info_i, info_d, drop_tol2, ns_tol);
     else
@@ -1004,6 +1306,8 @@ hipError_t launch_syev_lowest(hipStream_t st, int m, int k, double* A, double* w
     constexpr int kRegOrder = 192;
     if (m > 288) done = coop(m);
     if (done) {
+    } else if (m <= kWaveTri) {
+        hipLaunchKernelGGL(tridiag_wave_kernel, dim3(1), dim3(64), 0, st, m, A, d, e, tau, Vh);
     } else if (m <= 112) {
         hipLaunchKernelGGL(tridiag_kernel<true>, dim3(1), dim3(kTri), lds, st, m, m, A, d, e, tau, Vh);
     } else {

@@ -42,7 +42,7 @@ def _run(ctx, solver, kind, strategy="fix", m=20, n_ev=6, n_extra=6, n_es=8, x0_
     return A, lam, V, info, ref
 
 
-def _assert_same_run(A, m, lam, V, info, ref, n_ev, rtol=1e-4, window=None):
+def _assert_same_run(A, m, lam, V, info, ref, n_ev, rtol=1e-4, window=None, it_frac=20):
     assert info.converged and ref.converged
     assert info.n_expands >= 1 and ref.n_expands >= 1
     exact = pins.laplacian_spectrum(m, 2, n_ev)
@@ -62,7 +62,7 @@ def _assert_same_run(A, m, lam, V, info, ref, n_ev, rtol=1e-4, window=None):
     big = r_ref[:L] > 1e-6
     assert big.sum() >= 10
     np.testing.assert_allclose(r_gpu[:L][big], r_ref[:L][big], rtol=rtol)
-    assert abs(info.iterations - ref.iterations) <= max(3, ref.iterations // 20)
+    assert abs(info.iterations - ref.iterations) <= max(3, ref.iterations // it_frac)
 
 
 @pytest.mark.parametrize("solver,kind", [("si", "random"), ("si", "powered"), ("lobpcg", "random"),
@@ -74,7 +74,10 @@ def test_expansion_vectors_match_oracle(ctx, solver, kind):
         # blocks differ by 1e-13 drift apart by up to 3e-4 in r(j) within
         # twenty iterations of the first expansion, while a different random
         # block moves r(j) by 0.15 - 0.3 there. Compare through that window.
-        _assert_same_run(A, 20, lam, V, info, ref, 6, rtol=3e-2, window=20)
+        # Its final iteration count is rounding-decided on the GPU: start
+        # blocks perturbed by 1e-14 (relative) end after 220 to 232
+        # iterations (measured), so the count is held to 10% of the oracle's.
+        _assert_same_run(A, 20, lam, V, info, ref, 6, rtol=3e-2, window=20, it_frac=10)
     else:
         _assert_same_run(A, 20, lam, V, info, ref, 6)
 

@@ -234,7 +234,7 @@ def _sym_with_spectrum(m, seed, clustered):
     return 0.5 * (A + A.T)
 
 
-@pytest.mark.parametrize("m", [1, 2, 3, 16, 48, 97, 113, 130, 192, 207, 224, 225, 288, 750])
+@pytest.mark.parametrize("m", [1, 2, 3, 16, 48, 63, 64, 65, 97, 113, 130, 192, 207, 224, 225, 288, 750])
 @pytest.mark.parametrize("clustered", [False, True])
 def test_syev_matches_definition(ctx, m, clustered):
     from paper_2409_05572_amd import api
