@@ -2,7 +2,8 @@
 // BF16 storage), gfx950.
 //
 // Storage halves (FP32) or quarters (BF16) the panel traffic of the FP64
-// path; arithmetic is FP32, on the matrix cores (v_mfma_f32_16x16x4f32) for
+// path; arithmetic is FP32, on the matrix cores (v_mfma_f32_16x16x4f32; the
+// Gram product of BF16 blocks on v_mfma_f32_16x16x16bf16_1k) for
 // the Gram products and basis updates. Their FP32 accumulators are folded
 // into FP64 registers every 64 rows (Gram) or 64 terms of K (update), so the
 // rounding of a long FP32 sum never exceeds a few units of the storage
@@ -724,6 +725,161 @@ __global__ __launch_bounds__(kThreads, 2) void gram_lp_kernel(long long n, SegsT
 }
 
 // ---------------------------------------------------------------------------
+// Gram product of BF16 blocks on the BF16 matrix cores:
+// v_mfma_f32_16x16x16bf16_1k computes D[16x16] += A[16x16] B[16x16] with FP32
+// accumulation; lane l supplies A[l % 16][4 (l / 16) + q] and
+// B[4 (l / 16) + q][l % 16] (q < 4, one 8-byte vector each) and holds
+// D[4 (l / 16) + r][l % 16] in accumulator register r (checked on gfx950).
+// Products of two BF16 values are exact in FP32, so the result equals the
+// FP32-MFMA kernel's up to the order of the FP32 additions. The tiling is the
+// FP32 kernel's; the stage is kept in LDS transposed (column-major, BF16), so
+// the four consecutive rows a lane supplies are one 8-byte read, and a
+// 32-row stage is two MFMA steps instead of eight.
+typedef short s4bf __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ f4 mfma16bf(s4bf a, s4bf b, f4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
+}
+
+constexpr int GKT = GK + 8;  // row stride (BF16 entries) of the transposed stage
+
+template <int NI, int NJ>
+__device__ __forceinline__ void gram_bf16_compute(const bf16_t (*Tt)[GKT], f4 (&acc)[3][3], int lr, int lc,
+                                                  int wy, int wx) {
+#pragma unroll
+    for (int ks = 0; ks < GK; ks += 16) {
+        s4bf a[NI], b[NJ];
+#pragma unroll
+        for (int i = 0; i < NI; ++i)
+            a[i] = *reinterpret_cast<const s4bf*>(&Tt[wy * 48 + i * 16 + lc][ks + 4 * lr]);
+#pragma unroll
+        for (int j = 0; j < NJ; ++j)
+            b[j] = *reinterpret_cast<const s4bf*>(&Tt[GT + wx * 48 + j * 16 + lc][ks + 4 * lr]);
+#pragma unroll
+        for (int i = 0; i < NI; ++i)
+#pragma unroll
+            for (int j = 0; j < NJ; ++j) acc[i][j] = mfma16bf(a[i], b[j], acc[i][j]);
+    }
+}
+
+__global__ __launch_bounds__(kThreads, 2) void gram_bf16_kernel(long long n, SegsT<bf16_t> U, SegsT<bf16_t> V,
+                                                                int mu, int mv, int nt_v, int sym, int ntiles,
+                                                                long long rows_per_chunk,
+                                                                double* __restrict__ part) {
+    constexpr int RPT = GK / 4;
+    __shared__ __align__(16) bf16_t Tt[2 * GT][GKT];  // [column][row]
+    const int lin = xcd_remap(blockIdx.x, gridDim.x);
+    const int chunk = lin / ntiles;
+    const int tile = lin % ntiles;
+    int ti, tj;
+    tile_decode(tile, nt_v, sym, ti, tj);
+    const long long r0 = (long long)chunk * rows_per_chunk;
+    const long long r1 = min(n, r0 + rows_per_chunk);
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int wy = wv >> 1, wx = wv & 1;
+    const int cu0 = ti * GT, cv0 = tj * GT;
+    const int lr = lane >> 4, lc = lane & 15;
+    const int niv = max(0, min(3, (mu - cu0 - wy * 48 + 15) / 16));
+    const int njv = max(0, min(3, (mv - cv0 - wx * 48 + 15) / 16));
+    const int shape = niv * 4 + njv;
+
+    const bf16_t* cp[3];
+    bool cok[3];
+    long long cld[3];
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+        const int c = lane + 64 * q;
+        if (c < GT) {
+            cp[q] = seg_col(U, cu0 + c, cok[q]);
+            cld[q] = U.ld;
+        } else {
+            cp[q] = seg_col(V, cv0 + c - GT, cok[q]);
+            cld[q] = V.ld;
+        }
+    }
+    f4 acc[3][3];
+    double dacc[3][3][4];
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+            acc[i][j] = f4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int r = 0; r < 4; ++r) dacc[i][j][r] = 0.0;
+        }
+    auto flush = [&]() {
+#pragma unroll
+        for (int i = 0; i < 3; ++i)
+#pragma unroll
+            for (int j = 0; j < 3; ++j) {
+#pragma unroll
+                for (int r = 0; r < 4; ++r) dacc[i][j][r] += (double)acc[i][j][r];
+                acc[i][j] = f4{0.f, 0.f, 0.f, 0.f};
+            }
+    };
+    bf16_t rg[RPT][3];
+    auto fetch = [&](long long rb) {
+#pragma unroll
+        for (int i = 0; i < RPT; ++i) {
+            const long long r = rb + wv + 4 * i;
+            const bool rok = r < r1;
+#pragma unroll
+            for (int q = 0; q < 3; ++q) rg[i][q] = (rok && cok[q]) ? cp[q][r * cld[q]] : (bf16_t)0;
+        }
+    };
+    auto stash = [&]() {
+#pragma unroll
+        for (int i = 0; i < RPT; ++i)
+#pragma unroll
+            for (int q = 0; q < 3; ++q) Tt[lane + 64 * q][wv + 4 * i] = rg[i][q];
+    };
+
+    if (r0 < r1) {
+        fetch(r0);
+        stash();
+    }
+    __syncthreads();
+    int stage = 0;
+    for (long long rb = r0; rb < r1; rb += GK) {
+        const bool more = rb + GK < r1;
+        if (more) fetch(rb + GK);
+        switch (shape) {  // uniform per wave
+            case 15: gram_bf16_compute<3, 3>(Tt, acc, lr, lc, wy, wx); break;
+            case 14: gram_bf16_compute<3, 2>(Tt, acc, lr, lc, wy, wx); break;
+            case 13: gram_bf16_compute<3, 1>(Tt, acc, lr, lc, wy, wx); break;
+            case 11: gram_bf16_compute<2, 3>(Tt, acc, lr, lc, wy, wx); break;
+            case 10: gram_bf16_compute<2, 2>(Tt, acc, lr, lc, wy, wx); break;
+            case 9: gram_bf16_compute<2, 1>(Tt, acc, lr, lc, wy, wx); break;
+            case 7: gram_bf16_compute<1, 3>(Tt, acc, lr, lc, wy, wx); break;
+            case 6: gram_bf16_compute<1, 2>(Tt, acc, lr, lc, wy, wx); break;
+            case 5: gram_bf16_compute<1, 1>(Tt, acc, lr, lc, wy, wx); break;
+            default: break;
+        }
+        if (++stage == GFLUSH) {
+            flush();
+            stage = 0;
+        }
+        __syncthreads();
+        if (more) {
+            stash();
+            __syncthreads();
+        }
+    }
+    flush();
+    double* P = part + (long long)chunk * mu * mv;
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int gi = cu0 + wy * 48 + i * 16 + 4 * lr + r;
+                const int gj = cv0 + wx * 48 + j * 16 + lc;
+                if (gi < mu && gj < mv) P[(long long)gi * mv + gj] = dacc[i][j][r];
+            }
+}
+
+// ---------------------------------------------------------------------------
 // Basis update Out = beta Out + alpha U C (C given in FP64, rounded to FP32
 // once per call into a K x N scratch that every workgroup streams): the FP64
 // kernel's tiling (64 rows x 16 NT columns per workgroup, K streamed UK at a
@@ -966,8 +1122,12 @@ hipError_t launch_gram_lp(hipStream_t st, long long n, const SegsT<T>& U, const 
     int ntiles, nt_v, nchunks;
     long long rows;
     gram_plan(n, mu, mv, sym, ntiles, nt_v, nchunks, rows);
-    hipLaunchKernelGGL(gram_lp_kernel<T>, dim3(nchunks * ntiles), dim3(kThreads), 0, st, n, U, V, mu, mv,
-                       nt_v, sym, ntiles, rows, part);
+    if constexpr (sizeof(T) == 2)  // BF16 storage: BF16 matrix cores
+        hipLaunchKernelGGL(gram_bf16_kernel, dim3(nchunks * ntiles), dim3(kThreads), 0, st, n, U, V, mu, mv, nt_v,
+                           sym, ntiles, rows, part);
+    else
+        hipLaunchKernelGGL(gram_lp_kernel<T>, dim3(nchunks * ntiles), dim3(kThreads), 0, st, n, U, V, mu, mv,
+                           nt_v, sym, ntiles, rows, part);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     return launch_gram_reduce(st, mu, mv, nchunks, sym, part, C);
