@@ -184,6 +184,11 @@ typedef struct se_info {
  * j_warm = 5, r_warm = 1e-4, tol = 1e-8, max_iter = 1000, host pointers. */
 void se_params_default(se_params* p);
 
+/* The last failing hipError_t of a call on this context (0 if none), and the
+ * runtime's name for a hipError_t value (for messages). */
+int32_t se_ctx_last_hip_error(const se_ctx* ctx);
+const char* se_hip_error_name(int32_t e);
+
 /* Create a context bound to HIP device `device` and stream `stream`
  * (a hipStream_t; NULL = the device's null stream). The stream is borrowed:
  * it must outlive the context. Errors: SE_ERR_INVALID_ARG (bad device or
@@ -379,6 +384,33 @@ uint64_t se_solve_footprint(int64_t n, int64_t nnz, int32_t n_ev, int32_t n_extr
 
 /* 1 <= max_slots <= 16; hbm_budget_bytes > 0. The server uses ctx's device. */
 se_status se_server_create(se_ctx* ctx, uint64_t hbm_budget_bytes, int32_t max_slots, se_server** out);
+
+/* Batched server (1 <= max_slots <= 16): one engine thread advances every
+ * resident solve by one LOBPCG iteration per step, each phase of the step one
+ * launch over the work of all of them (Algorithm 3 with soft locking, the
+ * Hetmaniuk-Lehoucq basis of Section 2.3 and the shrink-and-expand controller
+ * of Section 3), the step's launches captured once in a graph and replayed
+ * (sizes that change inside a step are read on the device). New requests join
+ * at step boundaries; one host synchronization per step serves every solve.
+ * Takes FP64 LOBPCG requests with nb <= 96, no preconditioner, X_drop
+ * expansion and a matrix without rows of more than 64 nonzeros; se_submit
+ * returns SE_ERR_UNSUPPORTED for others. Admission by se_batched_footprint
+ * against hbm_budget_bytes. A solve's arithmetic depends only on its own
+ * inputs (its work split and reduction order are fixed by its own size), so it
+ * is bitwise the same alone and in any mix. It follows the reference
+ * algorithm's steps directly (the residual block projected twice against
+ * [X, P], two Cholesky-QR passes, Rayleigh-Ritz on [X, P, W]) rather than
+ * se_solve's implicit variants, so its iterates match se_solve's to rounding,
+ * not bitwise. se_submit, se_poll, se_wait and se_server_destroy work on both
+ * kinds of server. */
+se_status se_server_create_batched(se_ctx* ctx, uint64_t hbm_budget_bytes, int32_t max_slots, se_server** out);
+/* Device memory a batched solve of this shape holds. */
+uint64_t se_batched_footprint(int64_t n, int32_t n_ev, int32_t n_extra);
+/* Steps run so far by a batched server's engine, and how many of them were
+ * replays of the captured graph (the rest ran as direct launches, after a
+ * capture failed). Either pointer may be NULL. SE_ERR_INVALID_ARG for a
+ * server not made by se_server_create_batched. */
+se_status se_server_batch_stats(se_server* srv, int64_t* steps, int64_t* graph_steps);
 
 /* Queue one solve; never blocks on the GPU. X0 may be NULL (seeded start
  * block, as in se_solve). Returns SE_ERR_INVALID_ARG like se_solve,

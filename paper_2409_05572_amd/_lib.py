@@ -96,6 +96,11 @@ PROTOTYPES = {
     "se_solve_footprint": (C.c_uint64, [C.c_int64, C.c_int64, C.c_int32, C.c_int32, C.c_int32,
                                         C.c_int32]),
     "se_server_create": (C.c_int, [C.c_void_p, C.c_uint64, C.c_int32, C.POINTER(C.c_void_p)]),
+    "se_ctx_last_hip_error": (C.c_int32, [C.c_void_p]),
+    "se_hip_error_name": (C.c_char_p, [C.c_int32]),
+    "se_server_create_batched": (C.c_int, [C.c_void_p, C.c_uint64, C.c_int32, C.POINTER(C.c_void_p)]),
+    "se_batched_footprint": (C.c_uint64, [C.c_int64, C.c_int32, C.c_int32]),
+    "se_server_batch_stats": (C.c_int, [C.c_void_p, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]),
     "se_submit": (C.c_int, [C.c_void_p, C.c_void_p, C.POINTER(SeParams), C.c_void_p, C.c_void_p,
                             C.c_void_p, C.POINTER(C.c_uint64)]),
     "se_poll": (C.c_int, [C.c_void_p, C.c_uint64, C.POINTER(C.c_int32)]),

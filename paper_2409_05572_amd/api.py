@@ -92,8 +92,12 @@ class Matrix:
         flags = _lib.SE_MATRIX_DEVICE if on_device else _lib.SE_MATRIX_HOST
         nnz = int(rowptr[-1]) if not on_device else int(colind.numel())
         create = lib().se_matrix_create_csr_z if self.is_complex else lib().se_matrix_create_csr
-        check(create(ctx.handle, self.n, nnz, C.c_void_p(_ptr(rowptr)), C.c_void_p(_ptr(colind)),
-                     C.c_void_p(_ptr(val)), flags, float(anorm), C.byref(h)), "se_matrix_create_csr")
+        st = create(ctx.handle, self.n, nnz, C.c_void_p(_ptr(rowptr)), C.c_void_p(_ptr(colind)),
+                    C.c_void_p(_ptr(val)), flags, float(anorm), C.byref(h))
+        if st == _lib.SE_ERR_HIP:
+            e = lib().se_ctx_last_hip_error(ctx.handle)
+            check(st, f"se_matrix_create_csr ({lib().se_hip_error_name(e).decode()})")
+        check(st, "se_matrix_create_csr")
         self._h = h
         self._keep = None
         self.anorm = float(lib().se_matrix_anorm(h))  # the given bound, or the Gershgorin estimate for 0
@@ -279,10 +283,13 @@ class Server:
     output tensors alive until wait() returns.
     """
 
-    def __init__(self, ctx: Context, hbm_budget_bytes: int, max_slots: int = 4):
+    def __init__(self, ctx: Context, hbm_budget_bytes: int, max_slots: int = 4, batched: bool = False):
+        """batched: one engine advances all resident solves in lockstep
+        (se_server_create_batched); else one worker and stream per slot."""
         self._h = C.c_void_p()
-        check(lib().se_server_create(ctx.handle, int(hbm_budget_bytes), int(max_slots), C.byref(self._h)),
-              "se_server_create")
+        fn = "se_server_create_batched" if batched else "se_server_create"
+        check(getattr(lib(), fn)(ctx.handle, int(hbm_budget_bytes), int(max_slots), C.byref(self._h)), fn)
+        self.batched = batched
         self._keep = {}
 
     def submit(self, A: Matrix, X0, n_ev, n_extra, **kw):
@@ -300,6 +307,12 @@ class Server:
                               C.c_void_p(_ptr(lam)), C.byref(t)), "se_submit")
         self._keep[t.value] = (A, X0, V, lam)
         return t.value, lam, V
+
+    def batch_stats(self):
+        """(steps, graph_steps) of a batched server's engine."""
+        a, b = C.c_int64(), C.c_int64()
+        check(lib().se_server_batch_stats(self._h, C.byref(a), C.byref(b)), "se_server_batch_stats")
+        return a.value, b.value
 
     def poll(self, ticket) -> bool:
         d = C.c_int32()

@@ -12,7 +12,7 @@ CSRC = os.path.join(HERE, "csrc")
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libse.so")
 SOURCES = ["bulk.hip", "bulk_lp.hip", "small.hip", "filter.hip", "cg.hip", "precond.hip", "noalloc.hip",
-           "complex.hip", "engine.cpp", "engine_z.cpp", "capi.cpp", "server.cpp"]
+           "complex.hip", "batch.hip", "engine.cpp", "engine_z.cpp", "capi.cpp", "server.cpp"]
 ARCH = "gfx950"
 
 

@@ -199,14 +199,14 @@ __global__ __launch_bounds__(kThreads) void spmm_kernel(int n, const int* __rest
 // padding column, ld >= w + 1, and stores one value).
 constexpr int kStreamRows = 32;
 
+// Body of one wave; `wid_in` is the wave's index over the row runs.
 template <int NB>
-__global__ __launch_bounds__(kThreads) void spmm_stream_kernel(int n, const int* __restrict__ rowptr,
-                                                               const int* __restrict__ col,
-                                                               const double* __restrict__ val,
-                                                               const double* __restrict__ X, long long ldx,
-                                                               double* __restrict__ Y, long long ldy, int w) {
+__device__ __forceinline__ void spmm_stream_body(int wid_in, int n, const int* __restrict__ rowptr,
+                                                 const int* __restrict__ col, const double* __restrict__ val,
+                                                 const double* __restrict__ X, long long ldx,
+                                                 double* __restrict__ Y, long long ldy, int w) {
     const int lane = threadIdx.x & 63;
-    const int wid = __builtin_amdgcn_readfirstlane((int)blockIdx.x * (kThreads / 64) + (int)(threadIdx.x >> 6));
+    const int wid = __builtin_amdgcn_readfirstlane(wid_in);
     if ((long long)wid * kStreamRows >= n) return;
     const int r0 = wid * kStreamRows;
     const int r1 = min(n, r0 + kStreamRows);
@@ -253,6 +253,16 @@ __global__ __launch_bounds__(kThreads) void spmm_stream_kernel(int n, const int*
         }
         while (r < r1) flush();
     }
+}
+
+template <int NB>
+__global__ __launch_bounds__(kThreads) void spmm_stream_kernel(int n, const int* __restrict__ rowptr,
+                                                               const int* __restrict__ col,
+                                                               const double* __restrict__ val,
+                                                               const double* __restrict__ X, long long ldx,
+                                                               double* __restrict__ Y, long long ldy, int w) {
+    spmm_stream_body<NB>((int)blockIdx.x * (kThreads / 64) + (int)(threadIdx.x >> 6), n, rowptr, col, val, X, ldx,
+                         Y, ldy, w);
 }
 
 // The streaming product with the residual of every row it produces: when row
@@ -387,13 +397,12 @@ hipError_t spmm_launch(hipStream_t st, int n, const int* rowptr, const int* col,
 // read is contiguous): thread g sums chunks g, g + 32, ... in increasing
 // order and a fixed tree combines the 32 sums (deterministic).
 constexpr int kSumG = 32;
-__global__ __launch_bounds__(kThreads) void sum_partials_kernel(int L, int nchunks,
-                                                                const double* __restrict__ part,
-                                                                double* __restrict__ out) {
+__device__ __forceinline__ void sum_partials_body(int bx, int L, int nchunks, const double* __restrict__ part,
+                                                  double* __restrict__ out) {
     constexpr int OPB = kThreads / kSumG;
     __shared__ double sh[kThreads];
     const int o = threadIdx.x % OPB, g = threadIdx.x / OPB;
-    const int i = blockIdx.x * OPB + o;
+    const int i = bx * OPB + o;
     double s0 = 0.0, s1 = 0.0;
     if (i < L) {
         int c = g;
@@ -413,18 +422,21 @@ __global__ __launch_bounds__(kThreads) void sum_partials_kernel(int L, int nchun
     if (g == 0 && i < L) out[i] = sh[o];
 }
 
+__global__ __launch_bounds__(kThreads) void sum_partials_kernel(int L, int nchunks,
+                                                                const double* __restrict__ part,
+                                                                double* __restrict__ out) {
+    sum_partials_body(blockIdx.x, L, nchunks, part, out);
+}
+
 // Residual and column norms: per chunk of rows, sum (ax - lam x)^2 and x^2.
 // With R != nullptr the residual rows are written there as well.
-__global__ __launch_bounds__(kThreads) void resid_norms_kernel(long long n, const double* __restrict__ X,
-                                                               const double* __restrict__ AX,
-                                                               long long ld, int k,
-                                                               const double* __restrict__ lam,
-                                                               long long rows_per_chunk,
-                                                               double* __restrict__ part,
-                                                               double* __restrict__ R, long long ldr) {
+__device__ __forceinline__ void resid_norms_body(int chunk, long long n, const double* __restrict__ X,
+                                                 const double* __restrict__ AX, long long ld, int k,
+                                                 const double* __restrict__ lam, long long rows_per_chunk,
+                                                 double* __restrict__ part, double* __restrict__ R,
+                                                 long long ldr) {
     __shared__ double sr[kThreads];
     __shared__ double sx[kThreads];
-    const int chunk = blockIdx.x;
     const long long r0 = (long long)chunk * rows_per_chunk;
     const long long r1 = min(n, r0 + rows_per_chunk);
     const int t = threadIdx.x;
@@ -470,6 +482,16 @@ __global__ __launch_bounds__(kThreads) void resid_norms_kernel(long long n, cons
             out[k + c] = axx;
         }
     }
+}
+
+__global__ __launch_bounds__(kThreads) void resid_norms_kernel(long long n, const double* __restrict__ X,
+                                                               const double* __restrict__ AX,
+                                                               long long ld, int k,
+                                                               const double* __restrict__ lam,
+                                                               long long rows_per_chunk,
+                                                               double* __restrict__ part,
+                                                               double* __restrict__ R, long long ldr) {
+    resid_norms_body(blockIdx.x, n, X, AX, ld, k, lam, rows_per_chunk, part, R, ldr);
 }
 
 __global__ __launch_bounds__(kThreads) void form_w_kernel(long long n, const double* __restrict__ X,
@@ -678,15 +700,11 @@ __device__ __forceinline__ bool gram_diag_slot(int wv, int s, int& I, int& J) {
 // a GK x 192 array. Thread t owns columns t%64, t%64+64, t%64+128 and rows
 // t/64 + 4i, so its three column pointers are fixed for the whole chunk and a
 // wave reads 64 consecutive columns of one row.
-__global__ __launch_bounds__(kThreads, 2) void gram_kernel(long long n, Segs U, Segs V, int mu, int mv,
-                                                        int nt_v, int sym, int ntiles,
-                                                        long long rows_per_chunk,
-                                                        double* __restrict__ part) {
+__device__ __forceinline__ void gram_body(int chunk, int tile, long long n, const Segs& U, const Segs& V, int mu,
+                                          int mv, int nt_v, int sym, long long rows_per_chunk,
+                                          double* __restrict__ part) {
     constexpr int RPT = GK / 4;  // rows per thread per stage (8)
     __shared__ double Ts[GK][2 * GT + 4];  // [row][0..95 U | 96..191 V]
-    const int lin = xcd_remap(blockIdx.x, gridDim.x);
-    const int chunk = lin / ntiles;
-    const int tile = lin % ntiles;
     int ti, tj;
     tile_decode(tile, nt_v, sym, ti, tj);
     const long long r0 = (long long)chunk * rows_per_chunk;
@@ -797,6 +815,14 @@ __global__ __launch_bounds__(kThreads, 2) void gram_kernel(long long n, Segs U, 
             }
 }
 
+__global__ __launch_bounds__(kThreads, 2) void gram_kernel(long long n, Segs U, Segs V, int mu, int mv,
+                                                        int nt_v, int sym, int ntiles,
+                                                        long long rows_per_chunk,
+                                                        double* __restrict__ part) {
+    const int lin = xcd_remap(blockIdx.x, gridDim.x);
+    gram_body(lin / ntiles, lin % ntiles, n, U, V, mu, mv, nt_v, sym, rows_per_chunk, part);
+}
+
 // C = sum over chunks of the partial Gram products. 16 threads per output
 // and 16 outputs per workgroup (consecutive threads on consecutive outputs):
 // thread g sums chunks g, g + 16, ... in increasing order and a fixed tree
@@ -805,15 +831,14 @@ __global__ __launch_bounds__(kThreads, 2) void gram_kernel(long long n, Segs U, 
 // diagonal blocks take the mirrored sum, diagonal 16 x 16 blocks average
 // (i, j) and (j, i).
 constexpr int kRedG = 16;
-__global__ __launch_bounds__(kThreads) void gram_reduce_kernel(int mu, int mv, int nchunks, int sym,
-                                                               const double* __restrict__ part,
-                                                               double* __restrict__ C) {
+__device__ __forceinline__ void gram_reduce_body(int bx, int mu, int mv, int nchunks, int sym,
+                                                 const double* __restrict__ part, double* __restrict__ C) {
     constexpr int OPB = kThreads / kRedG;
     __shared__ double sa[kThreads];
     __shared__ double sb[kThreads];
     const int o = threadIdx.x % OPB, g = threadIdx.x / OPB;
     const long long total = (long long)mu * mv;
-    const long long idx = (long long)blockIdx.x * OPB + o;
+    const long long idx = (long long)bx * OPB + o;
     const bool valid = idx < total;
     int mode = 0;  // 0: sum (i, j); 1: sum (j, i); 2: average of both
     long long p1 = idx, p2 = idx;
@@ -845,6 +870,12 @@ __global__ __launch_bounds__(kThreads) void gram_reduce_kernel(int mu, int mv, i
         __syncthreads();
     }
     if (g == 0 && valid) C[idx] = (mode == 2) ? 0.5 * (sa[o] + sb[o]) : sa[o];
+}
+
+__global__ __launch_bounds__(kThreads) void gram_reduce_kernel(int mu, int mv, int nchunks, int sym,
+                                                               const double* __restrict__ part,
+                                                               double* __restrict__ C) {
+    gram_reduce_body(blockIdx.x, mu, mv, nchunks, sym, part, C);
 }
 
 }  // namespace
@@ -882,17 +913,14 @@ constexpr int UM = 64;
 constexpr int UK = 32;
 
 template <int NT>
-__global__ __launch_bounds__(kThreads, (NT > 8 ? 1 : (NT > 6 ? 2 : 3))) void update_kernel(long long n, Segs U, int K,
-                                                          const double* __restrict__ C, int N,
-                                                          Segs O, double alpha, double beta,
-                                                          int ntn) {
+__device__ __forceinline__ void update_body(int rb, int tn, long long n, const Segs& U, int K,
+                                            const double* __restrict__ C, int N, const Segs& O, double alpha,
+                                            double beta) {
     constexpr int BN = 16 * NT;
     constexpr int UQ = (UM * UK) / kThreads;  // U elements per thread per stage (8)
     constexpr int CQ = (UK * BN) / kThreads;  // C elements per thread per stage (2 NT)
     __shared__ double Us[UK][UM + 4];
     __shared__ double Cs[UK][BN + 4];
-    const int lin = xcd_remap(blockIdx.x, gridDim.x);
-    const int rb = lin / ntn, tn = lin % ntn;
     const long long r0 = (long long)rb * UM;
     const int n0 = tn * BN;
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
@@ -960,6 +988,15 @@ __global__ __launch_bounds__(kThreads, (NT > 8 ? 1 : (NT > 6 ? 2 : 3))) void upd
                 *p = (beta != 0.0) ? fma(beta, *p, alpha * acc[t][r]) : alpha * acc[t][r];
             }
         }
+}
+
+template <int NT>
+__global__ __launch_bounds__(kThreads, (NT > 8 ? 1 : (NT > 6 ? 2 : 3))) void update_kernel(long long n, Segs U, int K,
+                                                          const double* __restrict__ C, int N,
+                                                          Segs O, double alpha, double beta,
+                                                          int ntn) {
+    const int lin = xcd_remap(blockIdx.x, gridDim.x);
+    update_body<NT>(lin / ntn, lin % ntn, n, U, K, C, N, O, alpha, beta);
 }
 
 template <int NT>
@@ -1181,7 +1218,7 @@ hipError_t launch_gram(hipStream_t st, long long n, const Segs& U, const Segs& V
     if (part_cap && max_chunks < 1) return hipErrorInvalidValue;
     gram_plan(n, mu, mv, sym, ntiles, nt_v, nchunks, rows, max_chunks);
     if (n <= 0) {
-        hipMemsetAsync(C, 0, sizeof(double) * (size_t)mu * mv, st);
+        (void)hipMemsetAsync(C, 0, sizeof(double) * (size_t)mu * mv, st);
         return hipGetLastError();
     }
     hipLaunchKernelGGL(gram_kernel, dim3(nchunks * ntiles), dim3(kThreads), 0, st, n, U, V, mu, mv,
@@ -1212,6 +1249,187 @@ hipError_t launch_update(hipStream_t st, long long n, const Segs& U, const doubl
         default: update_launch<8>(st, n, U, K, C, N, O, alpha, beta); break;
     }
     return hipGetLastError();
+}
+
+
+// ---------------------------------------------------------------------------
+// Batched products: the single-solve bodies above, driven by a work list. Each
+// workgroup forms the prefix sums of the jobs' item counts in LDS and loops
+// over items blockIdx.x, blockIdx.x + gridDim.x, ...
+namespace {
+
+__device__ __forceinline__ int gram_tiles(int mu, int mv, int sym, int& nt_v) {
+    const int nt_u = (mu + GT - 1) / GT;
+    nt_v = (mv + GT - 1) / GT;
+    return sym ? nt_u * (nt_u + 1) / 2 : nt_u * nt_v;
+}
+
+template <class F>
+__device__ __forceinline__ void for_items(int nj, F&& count, int* s_start) {
+    if (threadIdx.x == 0) {
+        int acc = 0;
+        for (int j = 0; j < nj; ++j) {
+            s_start[j] = acc;
+            acc += count(j);
+        }
+        s_start[nj] = acc;
+    }
+    __syncthreads();
+}
+
+// Job of item `it` (uniform over the workgroup, so that the job's fields are
+// read with scalar loads).
+__device__ __forceinline__ int item_job(int it, int nj, const int* s_start) {
+    int j = 0;
+    while (j + 1 < nj && it >= s_start[j + 1]) ++j;
+    return __builtin_amdgcn_readfirstlane(j);
+}
+
+__global__ __launch_bounds__(kThreads, 2) void gram_batched_kernel(const BGramJob* __restrict__ jobs, int nj) {
+    __shared__ int s_start[kMaxBatch + 1];
+    for_items(
+        nj,
+        [&](int j) {
+            const BGramJob& J = jobs[j];
+            if (J.n <= 0 || J.mu <= 0 || J.mv <= 0) return 0;
+            int ntv;
+            return J.nchunks * gram_tiles(J.mu, J.mv, J.sym, ntv);
+        },
+        s_start);
+    const int total = __builtin_amdgcn_readfirstlane(s_start[nj]);
+    for (int it = blockIdx.x; it < total; it += gridDim.x) {
+        const int j = item_job(it, nj, s_start);
+        const BGramJob& J = jobs[j];
+        int ntv;
+        const int nt = gram_tiles(J.mu, J.mv, J.sym, ntv);
+        const int loc = __builtin_amdgcn_readfirstlane(it - s_start[j]);
+        gram_body(loc / nt, loc % nt, J.n, J.U, J.V, J.mu, J.mv, ntv, J.sym, J.rows, J.part);
+        __syncthreads();
+    }
+}
+
+__global__ __launch_bounds__(kThreads) void gram_reduce_batched_kernel(const BGramJob* __restrict__ jobs, int nj) {
+    constexpr int OPB = kThreads / kRedG;
+    __shared__ int s_start[kMaxBatch + 1];
+    for_items(
+        nj,
+        [&](int j) {
+            const BGramJob& J = jobs[j];
+            if (J.n <= 0 || J.mu <= 0 || J.mv <= 0) return 0;
+            return (J.mu * J.mv + OPB - 1) / OPB;
+        },
+        s_start);
+    const int total = __builtin_amdgcn_readfirstlane(s_start[nj]);
+    for (int it = blockIdx.x; it < total; it += gridDim.x) {
+        const int j = item_job(it, nj, s_start);
+        const BGramJob& J = jobs[j];
+        gram_reduce_body(it - s_start[j], J.mu, J.mv, J.nchunks, J.sym, J.part, J.C);
+        __syncthreads();
+    }
+}
+
+constexpr int kBatchNT = 6;  // update column tile: 96 columns
+
+__global__ __launch_bounds__(kThreads, 2) void update_batched_kernel(const BUpdJob* __restrict__ jobs, int nj) {
+    constexpr int BN = 16 * kBatchNT;
+    __shared__ int s_start[kMaxBatch + 1];
+    for_items(
+        nj,
+        [&](int j) {
+            const BUpdJob& J = jobs[j];
+            if (J.n <= 0 || J.N <= 0) return 0;
+            return (int)((J.n + UM - 1) / UM) * ((J.N + BN - 1) / BN);
+        },
+        s_start);
+    // one item per workgroup: the grid covers every item (launch_update_batched)
+    const int it = blockIdx.x;
+    if (it >= s_start[nj]) return;
+    const int j = item_job(it, nj, s_start);
+    const BUpdJob& J = jobs[j];
+    const int ntn = (J.N + BN - 1) / BN;
+    const int loc = __builtin_amdgcn_readfirstlane(it - s_start[j]);
+    update_body<kBatchNT>(loc / ntn, loc % ntn, J.n, J.U, J.K, J.C, J.N, J.O, J.alpha, J.beta);
+}
+
+__global__ __launch_bounds__(kThreads) void spmm_batched_kernel(const BSpmmJob* __restrict__ jobs, int nj) {
+    constexpr int RPB = kStreamRows * (kThreads / 64);  // rows per work item
+    __shared__ int s_start[kMaxBatch + 1];
+    for_items(
+        nj,
+        [&](int j) {
+            const BSpmmJob& J = jobs[j];
+            if (J.n <= 0 || J.w <= 0) return 0;
+            return (J.n + RPB - 1) / RPB;
+        },
+        s_start);
+    const int total = __builtin_amdgcn_readfirstlane(s_start[nj]);
+    for (int it = blockIdx.x; it < total; it += gridDim.x) {
+        const int j = item_job(it, nj, s_start);
+        const BSpmmJob& J = jobs[j];
+        spmm_stream_body<16>((it - s_start[j]) * (kThreads / 64) + (int)(threadIdx.x >> 6), J.n, J.rowptr, J.col,
+                             J.val, J.X, J.ldx, J.Y, J.ldy, J.w);
+    }
+}
+
+__global__ __launch_bounds__(kThreads) void resid_batched_kernel(const BResidJob* __restrict__ jobs, int nj) {
+    __shared__ int s_start[kMaxBatch + 1];
+    for_items(
+        nj,
+        [&](int j) {
+            const BResidJob& J = jobs[j];
+            return (J.n <= 0 || J.k <= 0) ? 0 : J.nchunks;
+        },
+        s_start);
+    const int total = __builtin_amdgcn_readfirstlane(s_start[nj]);
+    for (int it = blockIdx.x; it < total; it += gridDim.x) {
+        const int j = item_job(it, nj, s_start);
+        const BResidJob& J = jobs[j];
+        resid_norms_body(it - s_start[j], J.n, J.X, J.AX, J.ld, J.k, J.lam, J.rows, J.part, J.R, J.ldr);
+        __syncthreads();
+    }
+}
+
+__global__ __launch_bounds__(kThreads) void resid_sum_batched_kernel(const BResidJob* __restrict__ jobs, int nj) {
+    constexpr int OPB = kThreads / kSumG;
+    __shared__ int s_start[kMaxBatch + 1];
+    for_items(
+        nj,
+        [&](int j) {
+            const BResidJob& J = jobs[j];
+            return (J.n <= 0 || J.k <= 0) ? 0 : (2 * J.k + OPB - 1) / OPB;
+        },
+        s_start);
+    const int total = __builtin_amdgcn_readfirstlane(s_start[nj]);
+    for (int it = blockIdx.x; it < total; it += gridDim.x) {
+        const int j = item_job(it, nj, s_start);
+        const BResidJob& J = jobs[j];
+        sum_partials_body(it - s_start[j], 2 * J.k, J.nchunks, J.part, J.out);
+        __syncthreads();
+    }
+}
+
+}  // namespace
+
+void launch_gram_batched(Launcher& L, const BGramJob* jobs, int nj, int grid) {
+    if (nj <= 0 || nj > kMaxBatch || grid <= 0) L.err = hipErrorInvalidValue;
+    L(gram_batched_kernel, dim3(grid), dim3(kThreads), 0, jobs, nj);
+    L(gram_reduce_batched_kernel, dim3(grid), dim3(kThreads), 0, jobs, nj);
+}
+
+void launch_update_batched(Launcher& L, const BUpdJob* jobs, int nj, int grid) {
+    if (nj <= 0 || nj > kMaxBatch || grid <= 0) L.err = hipErrorInvalidValue;
+    L(update_batched_kernel, dim3(grid), dim3(kThreads), 0, jobs, nj);
+}
+
+void launch_spmm_batched(Launcher& L, const BSpmmJob* jobs, int nj, int grid) {
+    if (nj <= 0 || nj > kMaxBatch || grid <= 0) L.err = hipErrorInvalidValue;
+    L(spmm_batched_kernel, dim3(grid), dim3(kThreads), 0, jobs, nj);
+}
+
+void launch_resid_batched(Launcher& L, const BResidJob* jobs, int nj, int grid) {
+    if (nj <= 0 || nj > kMaxBatch || grid <= 0) L.err = hipErrorInvalidValue;
+    L(resid_batched_kernel, dim3(grid), dim3(kThreads), 0, jobs, nj);
+    L(resid_sum_batched_kernel, dim3(grid), dim3(kThreads), 0, jobs, nj);
 }
 
 }  // namespace se

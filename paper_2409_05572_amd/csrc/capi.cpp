@@ -136,6 +136,10 @@ se_status se_ctx_create(int device, void* stream, se_ctx** out) {
     return SE_OK;
 }
 
+int32_t se_ctx_last_hip_error(const se_ctx* ctx) { return ctx ? ctx->last_hip_error : 0; }
+
+const char* se_hip_error_name(int32_t e) { return hipGetErrorName((hipError_t)e); }
+
 void se_ctx_destroy(se_ctx* ctx) {
     if (!ctx) return;
     (void)hipSetDevice(ctx->device);

@@ -4,8 +4,51 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <tuple>
+#include <utility>
 
 namespace se {
+
+// Issues kernel launches on a stream, or appends them to a graph as a chain of
+// kernel nodes (each depending on the one before). The graph is built
+// explicitly rather than captured from a stream: a capture in progress makes
+// other threads' work on the null stream fail, and a serving engine cannot
+// keep its callers from using the null stream.
+struct Launcher {
+    hipStream_t st = nullptr;
+    hipGraph_t graph = nullptr;  // nullptr: launch on st
+    hipGraphNode_t last = nullptr;
+    hipError_t err = hipSuccess;
+
+    template <class... P, class... A>
+    void operator()(void (*kernel)(P...), dim3 grid, dim3 block, size_t shmem, A... args) {
+        if (err != hipSuccess) return;
+        if (!graph) {
+            hipLaunchKernelGGL(kernel, grid, block, shmem, st, static_cast<P>(args)...);
+            err = hipGetLastError();
+            return;
+        }
+        std::tuple<P...> vals(static_cast<P>(args)...);
+        void* argv[sizeof...(P) > 0 ? sizeof...(P) : 1];
+        fill_args(vals, argv, std::index_sequence_for<P...>{});
+        hipKernelNodeParams kp{};
+        kp.func = reinterpret_cast<void*>(kernel);
+        kp.gridDim = grid;
+        kp.blockDim = block;
+        kp.sharedMemBytes = (unsigned)shmem;
+        kp.kernelParams = argv;
+        kp.extra = nullptr;
+        hipGraphNode_t node = nullptr;
+        err = hipGraphAddKernelNode(&node, graph, last ? &last : nullptr, last ? 1 : 0, &kp);
+        if (err == hipSuccess) last = node;
+    }
+
+  private:
+    template <class T, size_t... I>
+    static void fill_args(T& vals, void** argv, std::index_sequence<I...>) {
+        ((argv[I] = static_cast<void*>(&std::get<I>(vals))), ...);
+    }
+};
 
 // Up to four column segments of row-major n-row blocks that share one leading
 // dimension. Segment s covers logical columns [off[s], off[s] + w[s]) and
@@ -326,5 +369,89 @@ hipError_t launch_heev_lowest_z(hipStream_t st, int m, int k, double* A, double*
 // e_{act[c]}, Y (k x a, ld a) = rows act[c] of Z1, transposed.
 hipError_t launch_hl_init(hipStream_t st, int m, int k, const double* Z1, const int* act, int a,
                           double* B, double* Y);
+
+// ---------------------------------------------------------------------------
+// Batched products for several resident solves. One launch serves a list of
+// jobs (one per solve, at most kMaxBatch), each with its own sizes and
+// pointers, read from device memory when the launch runs: a job's sizes may
+// be written by an earlier kernel of the same stream, so a captured sequence
+// of launches stays valid while the widths change. A job with no rows or no
+// columns does nothing. Workgroups loop over the (job, row range, tile) work
+// items of all jobs; each job's items and their reduction order depend only
+// on that job, so its result does not depend on the others.
+constexpr int kMaxBatch = 16;
+
+struct BGramJob {  // C = U^T V (mu x mv); sym: U and V are the same block
+    Segs U, V;
+    long long n, rows;  // rows of U and V; rows per chunk (multiple of kGramRows)
+    int mu, mv, sym, nchunks;
+    double* part;  // nchunks x mu x mv partials
+    double* C;
+};
+struct BUpdJob {  // O = beta O + alpha U C, C is K x N with leading dimension N
+    Segs U, O;
+    long long n;
+    int K, N;
+    const double* C;
+    double alpha, beta;
+};
+struct BSpmmJob {  // Y = A X (w columns); CSR padded by kCsrPad, ldx >= w + 1 for odd w
+    const int* rowptr;
+    const int* col;
+    const double* val;
+    const double* X;
+    double* Y;
+    long long ldx, ldy;
+    int n, w;
+};
+struct BResidJob {  // R = AX - X diag(lam) (k columns); out = [sum r^2, sum x^2] per column
+    const double* X;
+    const double* AX;
+    const double* lam;
+    double* R;
+    double* part;  // nchunks x 2k
+    double* out;   // 2k
+    long long n, ld, ldr, rows;
+    int k, nchunks;
+};
+// `grid` workgroups loop over the work items of the first nj jobs (the
+// update takes one item per workgroup: grid must cover them all). Errors are
+// left in L.err (1 <= nj <= kMaxBatch).
+void launch_gram_batched(Launcher& L, const BGramJob* jobs, int nj, int grid);
+void launch_update_batched(Launcher& L, const BUpdJob* jobs, int nj, int grid);
+void launch_spmm_batched(Launcher& L, const BSpmmJob* jobs, int nj, int grid);
+void launch_resid_batched(Launcher& L, const BResidJob* jobs, int nj, int grid);
+
+// Batched small dense operations (one workgroup or a few per job).
+struct SmallMMJob {  // C = alpha op(A) B + beta C; op(A) = A^T when transA (A: rows x ca), else A (rows x ca, B: ca x cb)
+    const double* A;
+    const double* B;
+    double* C;
+    double alpha, beta;
+    int rows, ca, cb, lda, ldb, ldc, transA;
+};
+struct CholJob {  // launch_chol_drop's operation on one a x a Gram matrix (a <= 1024; work: 2 a^2 + 2a doubles)
+    const double* G;
+    double* T;
+    double* work;
+    int* info_i;
+    double* info_d;
+    double drop_tol2, ns_tol;
+    int a;
+};
+struct EigJob {  // launch_syev_lowest's operation; work holds syev_work_doubles(m) doubles; m <= 288
+    double* A;
+    double* w;
+    double* Z;
+    double* work;
+    int m, k;
+};
+constexpr int kBatchEigMax = 288;
+void launch_small_mm_batched(Launcher& L, const SmallMMJob* jobs, int nj);
+void launch_chol_batched(Launcher& L, const CholJob* jobs, int nj);
+// `jobspace`: device memory of syev_batched_jobspace_bytes() for the
+// orthonormalization passes' job lists.
+size_t syev_batched_jobspace_bytes();
+void launch_syev_lowest_batched(Launcher& L, const EigJob* jobs, int nj, void* jobspace);
 
 }  // namespace se

@@ -11,8 +11,21 @@
 // slots hold. Different slots run their kernels on different streams, so
 // small solves overlap on the GPU; a solve's arithmetic does not depend on
 // what else runs, so results match a lone se_solve.
+//
+// Batched mode (se_server_create_batched): one engine thread advances all
+// resident solves together, one LOBPCG iteration per step, with one launch per
+// phase for all of them (batch.hip). A step is a fixed sequence of launches,
+// captured once in a graph and replayed; the host uploads the step's
+// decisions, replays the graph, reads back every solve's residual ratios and
+// decides the next step (one synchronization per step for all solves). New
+// requests join at step boundaries.
+#include <algorithm>
+#include <atomic>
 #include <chrono>
+#include <cmath>
 #include <condition_variable>
+#include <cstddef>
+#include <cstdlib>
 #include <cstring>
 #include <deque>
 #include <memory>
@@ -21,6 +34,7 @@
 #include <unordered_map>
 #include <vector>
 
+#include "batch.h"
 #include "engine.h"
 
 namespace {
@@ -49,6 +63,40 @@ struct Slot {
     bool trim = false;       // idle slot asked to release its workspace
 };
 
+// A resident solve of the batched engine (host side).
+struct BSlot {
+    Request* r = nullptr;
+    se::DevBuf mem;  // panels, partials and small matrices (grow-only)
+    se::Strategy ctl;
+    int n_ev = 0, nb = 0, j = 0, n_shr = 0, n_exp = 0;
+    bool init = false, have_drop = false;
+    // decisions for the next step
+    int a = 0, expand = 0, shrink = 0;
+    std::vector<int> act;
+};
+
+// Sizes of a batched solve of order n and block width nb.
+struct BPlan {
+    int poff, nch_g, nch_r;
+    long long ldw, rows_g, rows_r;
+    size_t doubles;
+};
+BPlan bplan(long long n, int nb) {
+    BPlan b;
+    b.poff = nb + (nb & 1);
+    b.ldw = 2 * (long long)b.poff + 2;
+    // Gram chunks: about 64 per solve, at least 256 rows, multiples of 32
+    long long rg = (n + 63) / 64;
+    rg = std::max(256LL, (rg + 31) / 32 * 32);
+    b.rows_g = rg;
+    b.nch_g = (int)((n + rg - 1) / rg);
+    b.rows_r = 2048;  // as launch_resid_norms (its chunk count is used for the final check too)
+    b.nch_r = (int)std::max(1LL, (n + b.rows_r - 1) / b.rows_r);
+    b.doubles = 8 * (size_t)n * b.ldw + (size_t)b.nch_g * se::kBMMax * se::kBMMax +
+                (size_t)b.nch_r * 2 * se::kBNbMax + se::bsmall_doubles() + 64;
+    return b;
+}
+
 }  // namespace
 
 struct se_server {
@@ -62,6 +110,20 @@ struct se_server {
     std::unordered_map<se_ticket, std::unique_ptr<Request>> reqs;
     se_ticket next = 1;
     bool stop = false;
+
+    // batched mode
+    bool batched = false;
+    bool use_graph = true;
+    std::atomic<long long> steps{0};          // steps run by the engine
+    std::atomic<long long> graph_steps{0};    // of which replayed from the captured graph
+    std::thread engine;
+    hipStream_t bst = nullptr;
+    std::vector<BSlot> bslots;
+    se::DevBuf d_fix, d_ctl, d_dyn, d_jobs;
+    se::HostBuf h_fix, h_ctl, h_dyn, h_out;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t gexec = nullptr;
+    int graph_grid = 0;
 
     uint64_t held_total() const {
         uint64_t s = 0;
@@ -147,6 +209,351 @@ struct se_server {
             }
         }
     }
+
+    // ---- batched mode ----
+    uint64_t held_batched() const {
+        uint64_t h = 0;
+        for (const BSlot& b : bslots) h += b.mem.bytes;
+        return h;
+    }
+
+    // Start queued requests on free slots while the budget allows (idle slots
+    // give their memory back when the head request does not fit). Caller
+    // holds mu; runs on the engine thread, which owns every slot's memory.
+    void admit_batched(std::vector<int>& fresh) {
+        while (!queue.empty()) {
+            Request* r = queue.front();
+            int best = -1;
+            for (int i = 0; i < (int)bslots.size(); ++i)
+                if (!bslots[i].r && (best < 0 || bslots[i].mem.bytes > bslots[best].mem.bytes)) best = i;
+            if (best < 0) return;
+            const uint64_t growth = r->footprint > bslots[best].mem.bytes ? r->footprint - bslots[best].mem.bytes : 0;
+            if (growth > 0 && held_batched() + growth > budget) {
+                bool freed = false;
+                for (int i = 0; i < (int)bslots.size(); ++i)
+                    if (i != best && !bslots[i].r && bslots[i].mem.bytes > 0) {
+                        bslots[i].mem.release();
+                        freed = true;
+                    }
+                if (!freed || held_batched() + growth > budget) return;  // wait for running solves
+            }
+            bslots[best].r = r;
+            queue.pop_front();
+            r->t_start = Clock::now();
+            fresh.push_back(best);
+        }
+    }
+
+    se::BFix* hfix() { return h_fix.as<se::BFix>(); }
+    se::BCtl* hctl() { return h_ctl.as<se::BCtl>(); }
+    se::BDyn* hdyn() { return h_dyn.as<se::BDyn>(); }
+    const double* dev_lam(int s) const {
+        return reinterpret_cast<const double*>(d_dyn.as<char>() + sizeof(se::BDyn) * s + offsetof(se::BDyn, lam));
+    }
+
+    // Device memory, constants, state and start block of a new solve.
+    se_status setup_slot(int s) {
+        BSlot& b = bslots[s];
+        Request* r = b.r;
+        const se_matrix* A = r->A;
+        const long long n = A->n;
+        b.n_ev = r->p.n_ev;
+        b.nb = r->p.n_ev + r->p.n_extra;
+        const BPlan pl = bplan(n, b.nb);
+        if (b.mem.ensure(sizeof(double) * pl.doubles) != hipSuccess) return SE_ERR_OOM;
+        double* q = b.mem.as<double>();
+        const size_t panel = (size_t)n * pl.ldw;
+        se::BFix F{};
+        F.rowptr = A->rowptr;
+        F.col = A->col;
+        F.val = A->val;
+        F.xp[0] = q;
+        F.xp[1] = q + panel;
+        F.axp[0] = q + 2 * panel;
+        F.axp[1] = q + 3 * panel;
+        F.xpd = q + 4 * panel;
+        F.w[0] = q + 5 * panel;
+        F.w[1] = q + 6 * panel;
+        F.aw = q + 7 * panel;
+        F.part = q + 8 * panel;
+        F.rpart = F.part + (size_t)pl.nch_g * se::kBMMax * se::kBMMax;
+        F.sm = F.rpart + (size_t)pl.nch_r * 2 * se::kBNbMax;
+        F.anorm = A->anorm;
+        F.rows_g = pl.rows_g;
+        F.rows_r = pl.rows_r;
+        F.n = (int)n;
+        F.nb = b.nb;
+        int n_es = r->p.n_es;
+        if (n_es <= 0) n_es = b.n_ev + std::min(5, r->p.n_extra - 1);
+        F.n_es = n_es;
+        F.ldw = (int)pl.ldw;
+        F.poff = pl.poff;
+        F.nch_g = pl.nch_g;
+        F.nch_r = pl.nch_r;
+        hfix()[s] = F;
+        se::BDyn& D = hdyn()[s];
+        std::memset(&D, 0, sizeof(D));
+        D.w = b.nb;
+        if (hipMemcpyAsync(d_fix.as<se::BFix>() + s, &hfix()[s], sizeof(se::BFix), hipMemcpyHostToDevice, bst) !=
+                hipSuccess ||
+            hipMemcpyAsync(d_dyn.as<se::BDyn>() + s, &D, sizeof(se::BDyn), hipMemcpyHostToDevice, bst) != hipSuccess)
+            return SE_ERR_HIP;
+        hipError_t e;
+        if (!r->X0)
+            e = se::launch_seeded_block(bst, n, b.nb, (unsigned long long)r->p.seed, F.w[0], pl.ldw, false);
+        else if (r->p.ptr_mode == SE_PTR_HOST) {
+            e = hipMemcpyAsync(F.w[1], r->X0, sizeof(double) * (size_t)n * b.nb, hipMemcpyHostToDevice, bst);
+            if (e == hipSuccess) e = se::launch_colmajor_to_rowmajor(bst, n, b.nb, F.w[1], n, F.w[0], pl.ldw);
+        } else {
+            e = se::launch_colmajor_to_rowmajor(bst, n, b.nb, r->X0, n, F.w[0], pl.ldw);
+        }
+        if (e != hipSuccess) return SE_ERR_HIP;
+        // the host's copies must not change before the copies above ran
+        if (hipStreamSynchronize(bst) != hipSuccess) return SE_ERR_HIP;
+        b.ctl = se::Strategy{};
+        b.ctl.kind = r->p.strategy;
+        b.ctl.j_e = r->p.j_e;
+        b.ctl.j_s = r->p.j_s;
+        b.ctl.j_p = r->p.j_p;
+        b.ctl.j_warm = r->p.j_warm;
+        b.ctl.mu = r->p.mu;
+        b.ctl.r_warm = r->p.r_warm;
+        const bool se_on = b.ctl.enabled() && r->p.n_extra >= 2 && n_es >= b.n_ev && n_es < b.nb;
+        if (!se_on) b.ctl.kind = SE_STRAT_NONE;
+        b.j = b.n_shr = b.n_exp = 0;
+        b.have_drop = false;
+        b.init = true;
+        b.a = b.expand = b.shrink = 0;
+        std::memset(&r->info, 0, sizeof(r->info));
+        return SE_OK;
+    }
+
+    // Fresh residual of the returned pairs, results to the caller's buffers.
+    se_status finish_slot(int s, bool conv) {
+        BSlot& b = bslots[s];
+        Request* r = b.r;
+        const se::BFix& F = hfix()[s];
+        const se::BDyn& D = hdyn()[s];
+        const long long n = F.n;
+        const int k = b.n_ev;
+        const double* X = F.xp[D.cur];
+        double* out = F.sm + se::BSmall::G;
+        hipError_t e = se::launch_spmm(bst, (int)n, F.rowptr, F.col, F.val, X, F.ldw, F.aw, F.ldw, k, nullptr, 0);
+        if (e == hipSuccess)
+            e = se::launch_resid_norms(bst, n, X, F.aw, F.ldw, k, dev_lam(s), F.rpart, out, nullptr, 0);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(h_out.p, out, sizeof(double) * 2 * k, hipMemcpyDeviceToHost, bst);
+        if (e == hipSuccess) {
+            if (r->p.ptr_mode == SE_PTR_HOST) {
+                e = se::launch_rowmajor_to_colmajor(bst, n, k, X, F.ldw, F.w[1], n);
+                if (e == hipSuccess)
+                    e = hipMemcpyAsync(r->V, F.w[1], sizeof(double) * (size_t)n * k, hipMemcpyDeviceToHost, bst);
+            } else {
+                e = se::launch_rowmajor_to_colmajor(bst, n, k, X, F.ldw, r->V, n);
+                if (e == hipSuccess)
+                    e = hipMemcpyAsync(r->lambda, dev_lam(s), sizeof(double) * k, hipMemcpyDeviceToDevice, bst);
+            }
+        }
+        if (e == hipSuccess) e = hipStreamSynchronize(bst);
+        if (e != hipSuccess) {
+            r->info.hip_error = (int)e;
+            return SE_ERR_HIP;
+        }
+        if (r->p.ptr_mode == SE_PTR_HOST) std::memcpy(r->lambda, D.lam, sizeof(double) * k);
+        const double* o = h_out.as<double>();
+        double ms = 0.0, mp = 0.0;
+        for (int i = 0; i < k; ++i) {
+            const double rn = std::sqrt(o[i]), xn = std::sqrt(o[k + i]);
+            ms = std::max(ms, rn / (F.anorm * xn));
+            mp = std::max(mp, rn / (F.anorm * xn + xn * std::fabs(D.lam[i])));
+        }
+        se_info& I = r->info;
+        I.iterations = b.j;
+        I.n_shrinks = b.n_shr;
+        I.n_expands = b.n_exp;
+        I.max_stop_ratio = ms;
+        I.max_paper_ratio = mp;
+        I.converged = (conv && ms <= r->p.tol * 1.01) ? 1 : 0;
+        I.workspace_bytes = b.mem.bytes;
+        return I.converged ? SE_OK : SE_NOT_CONVERGED;
+    }
+
+    // Decisions after the residual check of iteration j (as se_solve's LOBPCG
+    // loop): returns true when the solve ends here (*conv: all pairs passed).
+    bool decide(int s, bool* conv) {
+        BSlot& b = bslots[s];
+        const Request* r = b.r;
+        const se::BDyn& D = hdyn()[s];
+        const int j = ++b.j;
+        const int k = D.k;
+        double rr = 0.0;
+        bool all = true;
+        for (int i = 0; i < b.n_ev; ++i) {
+            rr = std::max(rr, D.paper[i]);
+            all = all && D.stop[i] <= r->p.tol;
+        }
+        b.ctl.observe(j, rr);
+        *conv = all;
+        if (all || j >= r->p.max_iter) return true;
+        if (r->p.time_limit_s > 0 &&
+            std::chrono::duration<double>(Clock::now() - r->t_start).count() > r->p.time_limit_s)
+            return true;
+        b.act.clear();
+        for (int i = 0; i < k; ++i) {
+            const bool locked = r->p.soft_lock && i < b.n_ev && D.stop[i] <= r->p.tol;
+            if (!locked) b.act.push_back(i);
+        }
+        b.a = (int)b.act.size();
+        const bool want = b.ctl.ifexpand(j);
+        b.expand = 0;
+        if (want && b.have_drop) {
+            b.expand = 1;
+            b.have_drop = false;
+            b.ctl.did_expand(j);
+            ++b.n_exp;
+        }
+        b.shrink = 0;
+        if (b.ctl.ifshrink(j)) {
+            b.shrink = 1;
+            b.have_drop = true;
+            b.ctl.did_shrink(j);
+            ++b.n_shr;
+        }
+        return false;
+    }
+
+    hipError_t launch_step(int grid) {
+        const int ns = (int)bslots.size();
+        auto step = [&](se::Launcher& L) {
+            return se::launch_batch_step(L, ns, d_fix.as<se::BFix>(), d_ctl.as<se::BCtl>(), d_dyn.as<se::BDyn>(),
+                                         d_jobs.p, grid);
+        };
+        if (use_graph && (!gexec || grid > graph_grid)) {
+            // (re)build the step's graph: node by node, not by stream capture
+            if (gexec) (void)hipGraphExecDestroy(gexec);
+            if (graph) (void)hipGraphDestroy(graph);
+            gexec = nullptr;
+            graph = nullptr;
+            hipError_t e = hipGraphCreate(&graph, 0);
+            if (e == hipSuccess) {
+                se::Launcher G;
+                G.graph = graph;
+                e = step(G);
+            }
+            if (e == hipSuccess) e = hipGraphInstantiate(&gexec, graph, nullptr, nullptr, 0);
+            if (e != hipSuccess) {
+                // no graph: the same launches, issued directly from now on
+                (void)hipGetLastError();
+                if (graph) (void)hipGraphDestroy(graph);
+                graph = nullptr;
+                gexec = nullptr;
+                use_graph = false;
+            } else {
+                graph_grid = grid;
+            }
+        }
+        if (!use_graph) {
+            se::Launcher D;
+            D.st = bst;
+            return step(D);
+        }
+        ++graph_steps;
+        return hipGraphLaunch(gexec, bst);
+    }
+
+    void run_batched() {
+        (void)hipSetDevice(device);
+        const int ns = (int)bslots.size();
+        std::vector<int> fresh;
+        std::vector<std::pair<int, se_status>> ended;
+        std::unique_lock<std::mutex> lk(mu);
+        for (;;) {
+            fresh.clear();
+            admit_batched(fresh);
+            bool any = false;
+            for (const BSlot& b : bslots) any = any || b.r;
+            if (!any) {
+                if (stop && queue.empty()) return;
+                cv_work.wait(lk);
+                continue;
+            }
+            lk.unlock();
+            ended.clear();
+            for (int s : fresh) {
+                const se_status st = setup_slot(s);
+                if (st != SE_OK) ended.emplace_back(s, st);
+            }
+            // a failed setup leaves its slot idle for this step
+            auto is_ended = [&](int s) {
+                for (auto& e : ended)
+                    if (e.first == s) return true;
+                return false;
+            };
+            long long grid = 0;
+            for (int s = 0; s < ns; ++s) {
+                se::BCtl& C = hctl()[s];
+                BSlot& b = bslots[s];
+                C.mode = se::BMODE_IDLE;
+                if (!b.r || is_ended(s)) continue;
+                grid += 2 * ((hfix()[s].n + 63) / 64);
+                if (b.init) {
+                    C.mode = se::BMODE_INIT;
+                    C.a = C.expand = C.shrink = 0;
+                } else {
+                    C.mode = se::BMODE_ITER;
+                    C.a = b.a;
+                    C.expand = b.expand;
+                    C.shrink = b.shrink;
+                    for (int i = 0; i < b.a; ++i) C.act[i] = b.act[i];
+                }
+            }
+            bool stepped = false;
+            if (grid > 0) {
+                int g = 256;
+                while (g < grid) g *= 2;
+                hipError_t e = hipMemcpyAsync(d_ctl.p, h_ctl.p, sizeof(se::BCtl) * ns, hipMemcpyHostToDevice, bst);
+                if (e == hipSuccess) e = launch_step(g);
+                ++steps;
+                if (e == hipSuccess)
+                    e = hipMemcpyAsync(h_dyn.p, d_dyn.p, sizeof(se::BDyn) * ns, hipMemcpyDeviceToHost, bst);
+                if (e == hipSuccess) e = hipStreamSynchronize(bst);
+                if (e != hipSuccess) {
+                    // every resident solve fails; the engine goes on with new requests
+                    (void)hipGetLastError();
+                    for (int s = 0; s < ns; ++s)
+                        if (bslots[s].r && !is_ended(s)) {
+                            bslots[s].r->info.hip_error = (int)e;
+                            ended.emplace_back(s, SE_ERR_HIP);
+                        }
+                } else {
+                    stepped = true;
+                }
+            }
+            if (stepped) {
+                for (int s = 0; s < ns; ++s) {
+                    BSlot& b = bslots[s];
+                    if (!b.r || is_ended(s)) continue;
+                    b.init = false;
+                    if (hdyn()[s].k < b.n_ev) {
+                        ended.emplace_back(s, SE_ERR_BREAKDOWN);
+                        continue;
+                    }
+                    bool conv = false;
+                    if (decide(s, &conv)) ended.emplace_back(s, finish_slot(s, conv));
+                }
+            }
+            lk.lock();
+            for (auto& e : ended) {
+                Request* r = bslots[e.first].r;
+                r->status = e.second;
+                r->t_end = Clock::now();
+                r->info.time_ms = std::chrono::duration<double, std::milli>(r->t_end - r->t_start).count();
+                r->done = true;
+                bslots[e.first].r = nullptr;
+            }
+            if (!ended.empty()) cv_done.notify_all();
+        }
+    }
 };
 
 extern "C" {
@@ -188,20 +595,89 @@ se_status se_server_create(se_ctx* ctx, uint64_t hbm_budget_bytes, int32_t max_s
     return SE_OK;
 }
 
+se_status se_server_create_batched(se_ctx* ctx, uint64_t hbm_budget_bytes, int32_t max_slots, se_server** out) {
+    if (!ctx || !out || max_slots < 1 || max_slots > se::kMaxBatch || hbm_budget_bytes == 0)
+        return SE_ERR_INVALID_ARG;
+    *out = nullptr;
+    if (hipSetDevice(ctx->device) != hipSuccess) return SE_ERR_HIP;
+    auto* s = new (std::nothrow) se_server();
+    if (!s) return SE_ERR_OOM;
+    s->device = ctx->device;
+    s->budget = hbm_budget_bytes;
+    s->batched = true;
+    const char* ng = std::getenv("SE_BATCH_NO_GRAPH");
+    s->use_graph = !(ng && ng[0] == '1');
+    s->bslots.resize(max_slots);
+    const size_t ns = (size_t)max_slots;
+    // Non-blocking: legacy null-stream work of other threads (a matrix being
+    // created while a step is captured) must not synchronize with this stream.
+    bool ok = hipStreamCreateWithFlags(&s->bst, hipStreamNonBlocking) == hipSuccess;
+    ok = ok && s->d_fix.ensure(sizeof(se::BFix) * ns) == hipSuccess;
+    ok = ok && s->d_ctl.ensure(sizeof(se::BCtl) * ns) == hipSuccess;
+    ok = ok && s->d_dyn.ensure(sizeof(se::BDyn) * ns) == hipSuccess;
+    ok = ok && s->d_jobs.ensure(se::batch_jobs_bytes()) == hipSuccess;
+    ok = ok && s->h_fix.ensure(sizeof(se::BFix) * ns) == hipSuccess;
+    ok = ok && s->h_ctl.ensure(sizeof(se::BCtl) * ns) == hipSuccess;
+    ok = ok && s->h_dyn.ensure(sizeof(se::BDyn) * ns) == hipSuccess;
+    ok = ok && s->h_out.ensure(sizeof(double) * 2 * se::kBNbMax) == hipSuccess;
+    if (ok) {
+        std::memset(s->h_fix.p, 0, sizeof(se::BFix) * ns);
+        std::memset(s->h_dyn.p, 0, sizeof(se::BDyn) * ns);
+        ok = hipMemcpy(s->d_fix.p, s->h_fix.p, sizeof(se::BFix) * ns, hipMemcpyHostToDevice) == hipSuccess &&
+             hipMemcpy(s->d_dyn.p, s->h_dyn.p, sizeof(se::BDyn) * ns, hipMemcpyHostToDevice) == hipSuccess;
+    }
+    if (!ok) {
+        s->d_fix.release();
+        s->d_ctl.release();
+        s->d_dyn.release();
+        s->d_jobs.release();
+        s->h_fix.release();
+        s->h_ctl.release();
+        s->h_dyn.release();
+        s->h_out.release();
+        if (s->bst) (void)hipStreamDestroy(s->bst);
+        delete s;
+        return SE_ERR_HIP;
+    }
+    s->engine = std::thread([s] { s->run_batched(); });
+    *out = s;
+    return SE_OK;
+}
+
+se_status se_server_batch_stats(se_server* srv, int64_t* steps, int64_t* graph_steps) {
+    if (!srv || !srv->batched) return SE_ERR_INVALID_ARG;
+    if (steps) *steps = srv->steps.load();
+    if (graph_steps) *graph_steps = srv->graph_steps.load();
+    return SE_OK;
+}
+
+uint64_t se_batched_footprint(int64_t n, int32_t n_ev, int32_t n_extra) {
+    if (n < 1 || n_ev < 1 || n_extra < 0) return 0;
+    return sizeof(double) * (uint64_t)bplan(n, n_ev + n_extra).doubles;
+}
+
 se_status se_submit(se_server* srv, const se_matrix* A, const se_params* params, const double* X0,
                     double* V, double* lambda, se_ticket* ticket) {
     if (!srv || !A || !params || !V || !lambda || !ticket) return SE_ERR_INVALID_ARG;
     if (!A->ctx || A->ctx->device != srv->device || A->is_complex) return SE_ERR_INVALID_ARG;
     const se_status v = se::validate_solve(A, params);
     if (v != SE_OK) return v;
+    if (srv->batched) {
+        const int nb = params->n_ev + params->n_extra;
+        if (params->solver != SE_LOBPCG || params->precision != SE_FP64 || params->precond != SE_PRECOND_NONE ||
+            params->expand_vectors != SE_EXPAND_XDROP || nb > se::kBNbMax || A->n_heavy > 0 ||
+            A->n > (int64_t)INT32_MAX / 2)
+            return SE_ERR_UNSUPPORTED;
+    }
     auto r = std::make_unique<Request>();
     r->A = A;
     r->p = *params;
     r->X0 = X0;
     r->V = V;
     r->lambda = lambda;
-    r->footprint = se_solve_footprint(A->n, A->nnz, params->n_ev, params->n_extra, params->precision,
-                                      params->solver);
+    r->footprint = srv->batched ? se_batched_footprint(A->n, params->n_ev, params->n_extra)
+                                : se_solve_footprint(A->n, A->nnz, params->n_ev, params->n_extra,
+                                                     params->precision, params->solver);
     if (r->footprint > srv->budget) return SE_ERR_REJECTED;
     // (a mixed-precision solve makes the matrix's FP32 values on its own slot
     // stream, once per matrix, under the matrix's lock)
@@ -212,7 +688,10 @@ se_status se_submit(se_server* srv, const se_matrix* A, const se_params* params,
     *ticket = r->id;
     srv->queue.push_back(r.get());
     srv->reqs.emplace(r->id, std::move(r));
-    srv->schedule();
+    if (srv->batched)
+        srv->cv_work.notify_all();
+    else
+        srv->schedule();
     return SE_OK;
 }
 
@@ -257,7 +736,24 @@ void se_server_destroy(se_server* srv) {
     }
     for (Slot& sl : srv->slots)
         if (sl.worker.joinable()) sl.worker.join();
+    if (srv->engine.joinable()) srv->engine.join();
     (void)hipSetDevice(srv->device);
+    if (srv->batched) {
+        (void)hipStreamSynchronize(srv->bst);
+        if (srv->gexec) (void)hipGraphExecDestroy(srv->gexec);
+        if (srv->graph) (void)hipGraphDestroy(srv->graph);
+        for (BSlot& b : srv->bslots) b.mem.release();
+        srv->d_fix.release();
+        srv->d_ctl.release();
+        srv->d_dyn.release();
+        srv->d_jobs.release();
+        srv->h_fix.release();
+        srv->h_ctl.release();
+        srv->h_dyn.release();
+        srv->h_out.release();
+        (void)hipStreamDestroy(srv->bst);
+    }
+    (void)hipGetLastError();  // nothing reported here may linger for a later launch check
     for (Slot& sl : srv->slots) {
         if (!sl.ctx) continue;
         (void)hipStreamSynchronize(sl.ctx->stream);

@@ -57,7 +57,7 @@ __device__ double block_sum(double v, double* sh) {
 // in `work`; fixed at compile time so every access is a plain LDS or global
 // instruction rather than a generic (flat) one.
 template <bool kLds>
-__global__ __launch_bounds__(kSmall) void chol_drop_kernel(int a, const double* __restrict__ G,
+__device__ __forceinline__ void chol_drop_kernel_body(int bx, int a, const double* __restrict__ G,
                                                            double* __restrict__ T,
                                                            double* __restrict__ work,
                                                            int* __restrict__ info_i,
@@ -186,6 +186,17 @@ __global__ __launch_bounds__(kSmall) void chol_drop_kernel(int a, const double* 
     }
 }
 
+template <bool kLds>
+__global__ __launch_bounds__(kSmall) void chol_drop_kernel(int a, const double* __restrict__ G,
+                                                           double* __restrict__ T,
+                                                           double* __restrict__ work,
+                                                           int* __restrict__ info_i,
+                                                           double* __restrict__ info_d,
+                                                           double drop_tol2, double ns_tol) {
+    chol_drop_kernel_body<kLds>(blockIdx.x, a, G, T, work, info_i, info_d, drop_tol2, ns_tol);
+}
+
+
 // Cholesky-QR transform with column drop for a <= kCholBlk (same inputs,
 // outputs and drop rule as chol_drop_kernel), blocked so that synchronization
 // no longer scales with a: the scaled matrix lives in LDS (odd row stride);
@@ -199,7 +210,7 @@ __global__ __launch_bounds__(kSmall) void chol_drop_kernel(int a, const double* 
 // triangle, R^{-1} = L^{-T} goes to the upper one.
 constexpr int kCholBlk = 112;
 constexpr int kCholPanel = 16;
-__global__ __launch_bounds__(kSmall) void chol_drop_blocked_kernel(int a, const double* __restrict__ G,
+__device__ __forceinline__ void chol_drop_blocked_kernel_body(int bx, int a, const double* __restrict__ G,
                                                                    double* __restrict__ T,
                                                                    int* __restrict__ info_i,
                                                                    double* __restrict__ info_d, double drop_tol2,
@@ -414,6 +425,15 @@ __global__ __launch_bounds__(kSmall) void chol_drop_blocked_kernel(int a, const 
     }
 }
 
+__global__ __launch_bounds__(kSmall) void chol_drop_blocked_kernel(int a, const double* __restrict__ G,
+                                                                   double* __restrict__ T,
+                                                                   int* __restrict__ info_i,
+                                                                   double* __restrict__ info_d, double drop_tol2,
+                                                                   double ns_tol) {
+    chol_drop_blocked_kernel_body(blockIdx.x, a, G, T, info_i, info_d, drop_tol2, ns_tol);
+}
+
+
 // ---------------------------------------------------------------------------
 // Householder tridiagonalization of the symmetric m x m matrix A (row-major,
 // both triangles kept up to date; copied into LDS when it fits). Reflector k
@@ -421,7 +441,7 @@ __global__ __launch_bounds__(kSmall) void chol_drop_blocked_kernel(int a, const 
 // Vh row k from column k+1 (leading 1 explicit). d / e = diagonal /
 // off-diagonal of the result.
 template <bool kInLds>  // the matrix is copied into dynamic LDS (m^2 <= kLdsDoubles)
-__global__ __launch_bounds__(kTri) void tridiag_kernel(int m, int kend, double* __restrict__ Ag,
+__device__ __forceinline__ void tridiag_kernel_body(int bx, int m, int kend, double* __restrict__ Ag,
                                                        double* __restrict__ d,
                                                        double* __restrict__ e,
                                                        double* __restrict__ tau,
@@ -518,6 +538,16 @@ __global__ __launch_bounds__(kTri) void tridiag_kernel(int m, int kend, double* 
     }
 }
 
+template <bool kInLds>
+__global__ __launch_bounds__(kTri) void tridiag_kernel(int m, int kend, double* __restrict__ Ag,
+                                                       double* __restrict__ d,
+                                                       double* __restrict__ e,
+                                                       double* __restrict__ tau,
+                                                       double* __restrict__ Vh) {
+    tridiag_kernel_body<kInLds>(blockIdx.x, m, kend, Ag, d, e, tau, Vh);
+}
+
+
 // ---------------------------------------------------------------------------
 // Householder tridiagonalization of small matrices (m <= 64) by one wave:
 // lane l owns row l of the matrix, kept in LDS with an odd row stride (no
@@ -526,7 +556,7 @@ __global__ __launch_bounds__(kTri) void tridiag_kernel(int m, int kend, double* 
 // reflector costs a few passes over the lane's row instead of several
 // workgroup-wide synchronizations.
 constexpr int kWaveTri = 64;
-__global__ __launch_bounds__(64) void tridiag_wave_kernel(int m, const double* __restrict__ Ag,
+__device__ __forceinline__ void tridiag_wave_kernel_body(int bx, int m, const double* __restrict__ Ag,
                                                           double* __restrict__ d, double* __restrict__ e,
                                                           double* __restrict__ tau, double* __restrict__ Vh) {
     constexpr int S = kWaveTri + 1;
@@ -588,6 +618,13 @@ __global__ __launch_bounds__(64) void tridiag_wave_kernel(int m, const double* _
         d[m - 1] = A[(m - 1) * S + (m - 1)];
     }
 }
+
+__global__ __launch_bounds__(64) void tridiag_wave_kernel(int m, const double* __restrict__ Ag,
+                                                          double* __restrict__ d, double* __restrict__ e,
+                                                          double* __restrict__ tau, double* __restrict__ Vh) {
+    tridiag_wave_kernel_body(blockIdx.x, m, Ag, d, e, tau, Vh);
+}
+
 
 // ---------------------------------------------------------------------------
 // Register-resident Householder tridiagonalization for m <= min(16 RR, 32 RC).
@@ -744,7 +781,7 @@ __device__ __forceinline__ int sturm_count(int m, const double* d, const double*
     return cnt;
 }
 
-__global__ __launch_bounds__(256) void bisect_kernel(int m, int k, const double* __restrict__ dg,
+__device__ __forceinline__ void bisect_kernel_body(int bx, int m, int k, const double* __restrict__ dg,
                                                      const double* __restrict__ eg,
                                                      double* __restrict__ w,
                                                      double* __restrict__ scal) {
@@ -771,11 +808,11 @@ __global__ __launch_bounds__(256) void bisect_kernel(int m, int k, const double*
         s_gl[0] = gl;
         s_gu[0] = gu;
         s_pm[0] = pivmin;
-        if (blockIdx.x == 0) scal[0] = tnorm;
+        if (bx == 0) scal[0] = tnorm;
     }
     __syncthreads();
     const int lane = threadIdx.x & 63;
-    const int idx = blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int idx = bx * 4 + (threadIdx.x >> 6);
     if (idx >= k) return;
     double lo = s_gl[0], hi = s_gu[0];
     const double pivmin = s_pm[0];
@@ -800,6 +837,14 @@ __global__ __launch_bounds__(256) void bisect_kernel(int m, int k, const double*
     if (lane == 0) w[idx] = 0.5 * (lo + hi);
 }
 
+__global__ __launch_bounds__(256) void bisect_kernel(int m, int k, const double* __restrict__ dg,
+                                                     const double* __restrict__ eg,
+                                                     double* __restrict__ w,
+                                                     double* __restrict__ scal) {
+    bisect_kernel_body(blockIdx.x, m, k, dg, eg, w, scal);
+}
+
+
 // ---------------------------------------------------------------------------
 // Eigenvectors of the tridiagonal for the k computed eigenvalues by inverse
 // iteration (one thread per eigenvalue, two steps from a pseudo-random start,
@@ -817,13 +862,13 @@ __device__ __forceinline__ double hash_unit(unsigned i, unsigned j) {
     return (double)(h & 0xFFFFFF) / 8388608.0 - 1.0;
 }
 
-__global__ __launch_bounds__(256) void invit_kernel(int m, int k, const double* __restrict__ dg,
+__device__ __forceinline__ void invit_kernel_body(int bx, int m, int k, const double* __restrict__ dg,
                                                     const double* __restrict__ eg,
                                                     const double* __restrict__ w,
                                                     const double* __restrict__ scal,
                                                     double* __restrict__ ZT,
                                                     double* __restrict__ work) {
-    const int i = blockIdx.x * 256 + threadIdx.x;
+    const int i = bx * 256 + threadIdx.x;
     if (i >= k) return;
     double* DL = work;
     double* DD = DL + (size_t)m * k;
@@ -921,15 +966,25 @@ __global__ __launch_bounds__(256) void invit_kernel(int m, int k, const double* 
 #undef AT
 }
 
+__global__ __launch_bounds__(256) void invit_kernel(int m, int k, const double* __restrict__ dg,
+                                                    const double* __restrict__ eg,
+                                                    const double* __restrict__ w,
+                                                    const double* __restrict__ scal,
+                                                    double* __restrict__ ZT,
+                                                    double* __restrict__ work) {
+    invit_kernel_body(blockIdx.x, m, k, dg, eg, w, scal, ZT, work);
+}
+
+
 // Z = Q ZT with Q = H_0 H_1 ... H_{m-3}; one wave per eigenvector, kept in
 // registers (m <= 1024 -> 16 values per lane). ZT and Z are m x k (ld k).
-__global__ __launch_bounds__(256) void backtransform_kernel(int m, int k, const double* __restrict__ tau,
+__device__ __forceinline__ void backtransform_kernel_body(int bx, int m, int k, const double* __restrict__ tau,
                                                             const double* __restrict__ Vh,
                                                             const double* __restrict__ ZT,
                                                             double* __restrict__ Z) {
     constexpr int MAXQ = 1024 / 64;
     const int lane = threadIdx.x & 63;
-    const int i = blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int i = bx * 4 + (threadIdx.x >> 6);
     if (i >= k) return;
     double z[MAXQ];
 #pragma unroll
@@ -969,6 +1024,14 @@ __global__ __launch_bounds__(256) void backtransform_kernel(int m, int k, const 
         if (j < m) Z[(size_t)j * k + i] = z[q];
     }
 }
+
+__global__ __launch_bounds__(256) void backtransform_kernel(int m, int k, const double* __restrict__ tau,
+                                                            const double* __restrict__ Vh,
+                                                            const double* __restrict__ ZT,
+                                                            double* __restrict__ Z) {
+    backtransform_kernel_body(blockIdx.x, m, k, tau, Vh, ZT, Z);
+}
+
 
 // ---------------------------------------------------------------------------
 // Householder tridiagonalization by G cooperating workgroups (a cooperative
@@ -1412,6 +1475,188 @@ hipError_t launch_hl_init(hipStream_t st, int m, int k, const double* Z1, const 
     hipLaunchKernelGGL(hl_init_kernel, dim3((total + 255) / 256), dim3(256), 0, st, m, k, Z1, act, a,
                        B, Y);
     return hipGetLastError();
+}
+
+
+// ---------------------------------------------------------------------------
+// Batched small dense operations: the single-workgroup bodies above with one
+// job per workgroup row (blockIdx.y). A workgroup whose job has nothing for
+// it returns before its first barrier.
+namespace {
+
+// C = op(A) B by 32 x 32 output tiles; 256 threads, 4 outputs each.
+__global__ __launch_bounds__(256) void small_mm_batched_kernel(const SmallMMJob* __restrict__ jobs) {
+    __shared__ double As[32][33];
+    __shared__ double Bs[32][33];
+    const SmallMMJob& J = jobs[blockIdx.y];
+    const int R = J.transA ? J.ca : J.rows;  // output rows
+    const int K = J.transA ? J.rows : J.ca;  // contraction
+    if (R <= 0 || J.cb <= 0) return;
+    const int ntj = (J.cb + 31) / 32;
+    const int ntiles = ((R + 31) / 32) * ntj;
+    const int t = threadIdx.x, tx = t & 31, ty = t >> 5;
+    for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+        const int i0 = (tile / ntj) * 32, j0 = (tile % ntj) * 32;
+        double acc[4] = {0.0, 0.0, 0.0, 0.0};
+        for (int k0 = 0; k0 < K; k0 += 32) {
+            for (int q = t; q < 32 * 32; q += 256) {
+                const int kk = q >> 5, c = q & 31;  // consecutive threads: consecutive columns
+                const int kr = k0 + kk;
+                double av = 0.0;
+                if (J.transA) {
+                    if (kr < K && i0 + c < R) av = J.A[(size_t)kr * J.lda + i0 + c];
+                    As[kk][c] = av;
+                } else {
+                    // A row i0 + kk, contraction index k0 + c
+                    if (i0 + kk < R && k0 + c < K) av = J.A[(size_t)(i0 + kk) * J.lda + k0 + c];
+                    As[c][kk] = av;
+                }
+                Bs[kk][c] = (kr < K && j0 + c < J.cb) ? J.B[(size_t)kr * J.ldb + j0 + c] : 0.0;
+            }
+            __syncthreads();
+#pragma unroll 8
+            for (int kk = 0; kk < 32; ++kk) {
+                const double b = Bs[kk][tx];
+#pragma unroll
+                for (int q = 0; q < 4; ++q) acc[q] = fma(As[kk][ty + 8 * q], b, acc[q]);
+            }
+            __syncthreads();
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int i = i0 + ty + 8 * q, j = j0 + tx;
+            if (i < R && j < J.cb) {
+                double* c = J.C + (size_t)i * J.ldc + j;
+                *c = (J.beta != 0.0) ? fma(J.beta, *c, J.alpha * acc[q]) : J.alpha * acc[q];
+            }
+        }
+    }
+}
+
+__global__ __launch_bounds__(kSmall) void chol_batched_kernel(const CholJob* __restrict__ jobs) {
+    const CholJob& J = jobs[blockIdx.x];
+    if (J.a <= 0) return;
+    if (J.a <= kCholBlk)
+        chol_drop_blocked_kernel_body(0, J.a, J.G, J.T, J.info_i, J.info_d, J.drop_tol2, J.ns_tol);
+    else
+        chol_drop_kernel_body<false>(0, J.a, J.G, J.T, J.work, J.info_i, J.info_d, J.drop_tol2, J.ns_tol);
+}
+
+// Work layout of the batched path for order m (within syev_work_doubles(m)).
+struct EigWork {
+    double *d, *e, *tau, *scal, *Vh, *ZT, *ZT2, *fac, *Gk, *Tk, *cwork, *infod;
+    int* infoi;
+};
+__device__ __forceinline__ EigWork eig_work(double* work, int m) {
+    const size_t mm = (size_t)m * m;
+    EigWork W;
+    W.d = work;
+    W.e = W.d + m;
+    W.tau = W.e + m;
+    W.scal = W.tau + m;
+    W.Vh = W.scal + m + 16;
+    W.ZT = W.Vh + mm;
+    W.ZT2 = W.ZT + mm;
+    W.fac = W.ZT2 + mm;
+    W.Gk = W.fac + 5 * mm;
+    W.Tk = W.Gk + mm;
+    W.cwork = W.Tk + mm;
+    W.infod = W.cwork + 2 * mm + 2 * (size_t)m;
+    W.infoi = reinterpret_cast<int*>(W.infod + 8);
+    return W;
+}
+
+// Jobs of the three orthonormalization passes (gram, Cholesky, update) of the
+// k inverse-iteration vectors: pass p maps ZT -> ZT2 -> ZT -> ZT2.
+__global__ void eig_plan_kernel(const EigJob* __restrict__ jobs, int nj, SmallMMJob* __restrict__ mm,
+                                CholJob* __restrict__ ch) {
+    const int j = threadIdx.x;
+    if (j >= nj) return;
+    const EigJob J = jobs[j];
+    const bool on = J.m > 0 && J.k > 0;
+    const EigWork W = eig_work(J.work, on ? J.m : 1);
+    for (int p = 0; p < 3; ++p) {
+        double* cur = (p & 1) ? W.ZT2 : W.ZT;
+        double* nxt = (p & 1) ? W.ZT : W.ZT2;
+        SmallMMJob g{cur, cur, W.Gk, 1.0, 0.0, on ? J.m : 0, J.k, J.k, J.k, J.k, J.k, 1};
+        SmallMMJob u{cur, W.Tk, nxt, 1.0, 0.0, on ? J.m : 0, J.k, J.k, J.k, J.k, J.k, 0};
+        mm[(2 * p) * kMaxBatch + j] = g;
+        mm[(2 * p + 1) * kMaxBatch + j] = u;
+        CholJob c{W.Gk, W.Tk, W.cwork, W.infoi, W.infod, -1.0, p == 0 ? 0.0 : 1e-8, on ? J.k : 0};
+        ch[p * kMaxBatch + j] = c;
+    }
+}
+
+__global__ __launch_bounds__(64) void tridiag_wave_batched_kernel(const EigJob* __restrict__ jobs) {
+    const EigJob& J = jobs[blockIdx.x];
+    if (J.m <= 0 || J.m > kWaveTri || J.k <= 0) return;
+    const EigWork W = eig_work(J.work, J.m);
+    tridiag_wave_kernel_body(0, J.m, J.A, W.d, W.e, W.tau, W.Vh);
+}
+
+template <bool kInLds>
+__global__ __launch_bounds__(kTri) void tridiag_batched_kernel(const EigJob* __restrict__ jobs) {
+    const EigJob& J = jobs[blockIdx.x];
+    if (J.m <= kWaveTri || J.k <= 0) return;
+    if (kInLds != ((size_t)J.m * J.m <= (size_t)kLdsDoubles)) return;
+    const EigWork W = eig_work(J.work, J.m);
+    tridiag_kernel_body<kInLds>(0, J.m, J.m, J.A, W.d, W.e, W.tau, W.Vh);
+}
+
+__global__ __launch_bounds__(256) void bisect_batched_kernel(const EigJob* __restrict__ jobs) {
+    const EigJob& J = jobs[blockIdx.y];
+    if (J.m <= 0 || (int)blockIdx.x * 4 >= J.k) return;
+    const EigWork W = eig_work(J.work, J.m);
+    bisect_kernel_body(blockIdx.x, J.m, J.k, W.d, W.e, J.w, W.scal);
+}
+
+__global__ __launch_bounds__(256) void invit_batched_kernel(const EigJob* __restrict__ jobs) {
+    const EigJob& J = jobs[blockIdx.y];
+    if (J.m <= 0 || (int)blockIdx.x * 256 >= J.k) return;
+    const EigWork W = eig_work(J.work, J.m);
+    invit_kernel_body(blockIdx.x, J.m, J.k, W.d, W.e, J.w, W.scal, W.ZT, W.fac);
+}
+
+__global__ __launch_bounds__(256) void backtransform_batched_kernel(const EigJob* __restrict__ jobs) {
+    const EigJob& J = jobs[blockIdx.y];
+    if (J.m <= 0 || (int)blockIdx.x * 4 >= J.k) return;
+    const EigWork W = eig_work(J.work, J.m);
+    backtransform_kernel_body(blockIdx.x, J.m, J.k, W.tau, W.Vh, W.ZT2, J.Z);
+}
+
+}  // namespace
+
+void launch_small_mm_batched(Launcher& L, const SmallMMJob* jobs, int nj) {
+    if (nj <= 0 || nj > kMaxBatch) L.err = hipErrorInvalidValue;
+    L(small_mm_batched_kernel, dim3(64, nj), dim3(256), 0, jobs);
+}
+
+void launch_chol_batched(Launcher& L, const CholJob* jobs, int nj) {
+    if (nj <= 0 || nj > kMaxBatch) L.err = hipErrorInvalidValue;
+    L(chol_batched_kernel, dim3(nj), dim3(kSmall), sizeof(double) * (size_t)kCholBlk * (kCholBlk | 1), jobs);
+}
+
+size_t syev_batched_jobspace_bytes() {
+    return sizeof(SmallMMJob) * 6 * kMaxBatch + sizeof(CholJob) * 3 * kMaxBatch;
+}
+
+void launch_syev_lowest_batched(Launcher& L, const EigJob* jobs, int nj, void* jobspace) {
+    if (nj <= 0 || nj > kMaxBatch) L.err = hipErrorInvalidValue;
+    SmallMMJob* mm = static_cast<SmallMMJob*>(jobspace);
+    CholJob* ch = reinterpret_cast<CholJob*>(mm + 6 * kMaxBatch);
+    L(eig_plan_kernel, dim3(1), dim3(64), 0, jobs, nj, mm, ch);
+    L(tridiag_wave_batched_kernel, dim3(nj), dim3(64), 0, jobs);
+    L(tridiag_batched_kernel<true>, dim3(nj), dim3(kTri), sizeof(double) * (size_t)kLdsDoubles, jobs);
+    L(tridiag_batched_kernel<false>, dim3(nj), dim3(kTri), 0, jobs);
+    constexpr int kb = (kBatchEigMax + 3) / 4;
+    L(bisect_batched_kernel, dim3(kb, nj), dim3(256), 0, jobs);
+    L(invit_batched_kernel, dim3((kBatchEigMax + 255) / 256, nj), dim3(256), 0, jobs);
+    for (int p = 0; p < 3; ++p) {
+        launch_small_mm_batched(L, mm + (2 * p) * kMaxBatch, nj);
+        launch_chol_batched(L, ch + p * kMaxBatch, nj);
+        launch_small_mm_batched(L, mm + (2 * p + 1) * kMaxBatch, nj);
+    }
+    L(backtransform_batched_kernel, dim3(kb, nj), dim3(256), 0, jobs);
 }
 
 }  // namespace se
