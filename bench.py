@@ -77,6 +77,11 @@ def parse():
     ap.add_argument("--pilot", type=int, default=20, help="serving: warm-up requests (closed loop)")
     ap.add_argument("--load", type=float, default=0.7, help="serving: arrival rate / saturated rate")
     ap.add_argument("--slots", type=int, default=4, help="serving: concurrent solves")
+    ap.add_argument("--serve-n", type=float, nargs=2, default=[1e4, 1e6], metavar=("MIN", "MAX"),
+                    help="serving: range of the log-uniform matrix order")
+    ap.add_argument("--serve-engine", choices=["batched", "slots"], default="slots",
+                    help="serving: one lockstep engine for all resident solves (batched) or a stream and "
+                         "worker per slot (slots)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run one plain 1 GiB device copy first (the reference for HBM counters)")
     args = ap.parse_args()
@@ -252,6 +257,7 @@ def main():
         leg = serving(sargs, log)
         out["serving"] = dict(leg["serving"], requests=args.serve_requests, pilot=args.serve_pilot,
                               workload=leg["config"]["workload"], slots=args.slots)
+        log(f"serving leg ({args.serve_engine}): {out['serving']}")
     out["cpu_baseline"] = None
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(A, X0, args, infos[-1].iterations, log)
@@ -413,7 +419,7 @@ def serving(args, log):
     from paper_2409_05572_amd import api
 
     total = args.pilot + args.requests
-    specs = W.serving_requests(total, seed=305)
+    specs = W.serving_requests(total, seed=305, n_min=args.serve_n[0], n_max=args.serve_n[1])
     t = time.time()
     ctx = api.Context(0)
     mats = []
@@ -424,7 +430,7 @@ def serving(args, log):
         f"(n {min(x['n'] for x in specs)}..{max(x['n'] for x in specs)})")
     free, _ = torch.cuda.mem_get_info()
     budget = int(free * 0.6)
-    srv = api.Server(ctx, hbm_budget_bytes=budget, max_slots=args.slots)
+    srv = api.Server(ctx, hbm_budget_bytes=budget, max_slots=args.slots, batched=args.serve_engine == "batched")
 
     def submit(i):
         sp = specs[i]
@@ -465,6 +471,7 @@ def serving(args, log):
         if (k + 1) % 50 == 0:
             log(f"submitted {k + 1}/{args.requests}")
     res = collect(subs)
+    steps = srv.batch_stats() if srv.batched else None
     srv.close()
     for M in mats:
         M.close()
@@ -480,14 +487,16 @@ def serving(args, log):
         "ms_per_step": round(span * 1e3 / len(res), 2), "higher_is_better": False, "scaling": "weak",
         "vs_baseline": None, "dtype": "f64", "data": "synthetic",
         "config": {"workload": f"serving: {args.requests} Poisson requests at {args.load:g}x saturation, "
-                               "2-D/3-D Laplacian + U[-2,2] potential, n log-uniform 1e4..1e6, "
+                               "2-D/3-D Laplacian + U[-2,2] potential, "
+                               f"n log-uniform {args.serve_n[0]:.0e}..{args.serve_n[1]:.0e}, "
                                "n_ev U{4..64}, n_extra n_ev/2, LOBPCG fix, tol 1e-8",
-                   "slots": args.slots, "hbm_budget_bytes": budget},
+                   "slots": args.slots, "engine": args.serve_engine, "hbm_budget_bytes": budget},
         "serving": {"p50_ms": round(float(np.percentile(lat, 50)), 2),
                     "p99_ms": round(float(np.percentile(lat, 99)), 2),
                     "mean_ms": round(float(lat.mean()), 2), "solves_per_s": round(len(res) / span, 3),
                     "saturated_solves_per_s": round(sat, 3), "arrival_rate_per_s": round(rate, 3),
-                    "all_converged": ok,
+                    "all_converged": ok, "engine": args.serve_engine,
+                    "engine_steps": steps[0] if steps else None,
                     "max_stop_ratio": max(r["stop"] for r in res)},
         "roofline": None, "cpu_baseline": None,
     }

@@ -389,9 +389,13 @@ se_status se_server_create(se_ctx* ctx, uint64_t hbm_budget_bytes, int32_t max_s
  * resident solve by one LOBPCG iteration per step, each phase of the step one
  * launch over the work of all of them (Algorithm 3 with soft locking, the
  * Hetmaniuk-Lehoucq basis of Section 2.3 and the shrink-and-expand controller
- * of Section 3), the step's launches captured once in a graph and replayed
- * (sizes that change inside a step are read on the device). New requests join
- * at step boundaries; one host synchronization per step serves every solve.
+ * of Section 3). Sizes that change inside a step (dropped columns, the rank
+ * of the HL block) are planned on the device, so a step is a fixed sequence
+ * of launches: issued directly, or (environment SE_BATCH_GRAPH=1 at creation)
+ * replayed from a graph built once per server. The slots form two lanes on
+ * two streams, so one lane's small dense phase overlaps the other's products
+ * over n. New requests join at step boundaries; one host synchronization per
+ * step serves every solve.
  * Takes FP64 LOBPCG requests with nb <= 96, no preconditioner, X_drop
  * expansion and a matrix without rows of more than 64 nonzeros; se_submit
  * returns SE_ERR_UNSUPPORTED for others. Admission by se_batched_footprint

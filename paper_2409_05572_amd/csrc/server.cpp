@@ -14,11 +14,11 @@
 //
 // Batched mode (se_server_create_batched): one engine thread advances all
 // resident solves together, one LOBPCG iteration per step, with one launch per
-// phase for all of them (batch.hip). A step is a fixed sequence of launches,
-// captured once in a graph and replayed; the host uploads the step's
-// decisions, replays the graph, reads back every solve's residual ratios and
-// decides the next step (one synchronization per step for all solves). New
-// requests join at step boundaries.
+// phase for all of them (batch.hip). A step is a fixed sequence of launches
+// (issued directly or replayed from a graph built once); the host uploads the
+// step's decisions, runs the step, reads back every solve's residual ratios
+// and decides the next step (one synchronization per step for all solves).
+// New requests join at step boundaries.
 #include <algorithm>
 #include <atomic>
 #include <chrono>
@@ -113,16 +113,18 @@ struct se_server {
 
     // batched mode
     bool batched = false;
-    bool use_graph = true;
+    bool use_graph = false;
     std::atomic<long long> steps{0};          // steps run by the engine
     std::atomic<long long> graph_steps{0};    // of which replayed from the captured graph
     std::thread engine;
-    hipStream_t bst = nullptr;
+    hipStream_t bst = nullptr;   // lane 0, admission and result copies
+    hipStream_t bst2 = nullptr;  // lane 1
+    hipEvent_t ev_ctl = nullptr;
     std::vector<BSlot> bslots;
     se::DevBuf d_fix, d_ctl, d_dyn, d_jobs;
     se::HostBuf h_fix, h_ctl, h_dyn, h_out;
-    hipGraph_t graph = nullptr;
-    hipGraphExec_t gexec = nullptr;
+    hipGraph_t graph[2] = {nullptr, nullptr};
+    hipGraphExec_t gexec[2] = {nullptr, nullptr};
     int graph_grid = 0;
 
     uint64_t held_total() const {
@@ -223,9 +225,22 @@ struct se_server {
     void admit_batched(std::vector<int>& fresh) {
         while (!queue.empty()) {
             Request* r = queue.front();
-            int best = -1;
-            for (int i = 0; i < (int)bslots.size(); ++i)
-                if (!bslots[i].r && (best < 0 || bslots[i].mem.bytes > bslots[best].mem.bytes)) best = i;
+            // a free slot of the lane with the least resident work (sum of n),
+            // then the one holding the most memory
+            long long load[2] = {0, 0};
+            for (int l = 0; l < lanes(); ++l)
+                for (int i = lane_begin(l); i < lane_end(l); ++i)
+                    if (bslots[i].r) load[l] += bslots[i].r->A->n;
+            int best = -1, best_lane = 0;
+            for (int l = 0; l < lanes(); ++l)
+                for (int i = lane_begin(l); i < lane_end(l); ++i) {
+                    if (bslots[i].r) continue;
+                    if (best < 0 || load[l] < load[best_lane] ||
+                        (l == best_lane && bslots[i].mem.bytes > bslots[best].mem.bytes)) {
+                        best = i;
+                        best_lane = l;
+                    }
+                }
             if (best < 0) return;
             const uint64_t growth = r->footprint > bslots[best].mem.bytes ? r->footprint - bslots[best].mem.bytes : 0;
             if (growth > 0 && held_batched() + growth > budget) {
@@ -422,43 +437,76 @@ struct se_server {
         return false;
     }
 
-    hipError_t launch_step(int grid) {
+    // Slots are split into two lanes, each with its own stream and graph, so
+    // that one lane's small dense phase overlaps the other lane's products
+    // over n.
+    int nlanes = 2;
+    int lanes() const { return bslots.size() >= 2 ? nlanes : 1; }
+    int lane_begin(int l) const { return l == 0 ? 0 : ((int)bslots.size() + 1) / 2; }
+    int lane_end(int l) const { return l + 1 == lanes() ? (int)bslots.size() : lane_begin(l + 1); }
+    hipStream_t lane_stream(int l) const { return l == 0 ? bst : bst2; }
+    static size_t jobs_stride() { return (se::batch_jobs_bytes() + 255) / 256 * 256; }
+
+    void drop_graphs() {
+        for (int l = 0; l < 2; ++l) {
+            if (gexec[l]) (void)hipGraphExecDestroy(gexec[l]);
+            if (graph[l]) (void)hipGraphDestroy(graph[l]);
+            gexec[l] = nullptr;
+            graph[l] = nullptr;
+        }
+    }
+
+    // One step: the decisions go up, every lane runs its launches (a graph
+    // replay, or direct launches), the lanes' states come back.
+    hipError_t run_step(int grid) {
         const int ns = (int)bslots.size();
-        auto step = [&](se::Launcher& L) {
-            return se::launch_batch_step(L, ns, d_fix.as<se::BFix>(), d_ctl.as<se::BCtl>(), d_dyn.as<se::BDyn>(),
-                                         d_jobs.p, grid);
+        auto step = [&](se::Launcher& L, int l) {
+            const int s0 = lane_begin(l), n = lane_end(l) - s0;
+            return se::launch_batch_step(L, n, d_fix.as<se::BFix>() + s0, d_ctl.as<se::BCtl>() + s0,
+                                         d_dyn.as<se::BDyn>() + s0, d_jobs.as<char>() + jobs_stride() * l, grid);
         };
-        if (use_graph && (!gexec || grid > graph_grid)) {
-            // (re)build the step's graph: node by node, not by stream capture
-            if (gexec) (void)hipGraphExecDestroy(gexec);
-            if (graph) (void)hipGraphDestroy(graph);
-            gexec = nullptr;
-            graph = nullptr;
-            hipError_t e = hipGraphCreate(&graph, 0);
-            if (e == hipSuccess) {
-                se::Launcher G;
-                G.graph = graph;
-                e = step(G);
+        if (use_graph && (!gexec[0] || grid > graph_grid)) {
+            // (re)build the lanes' graphs node by node (no stream capture)
+            drop_graphs();
+            hipError_t e = hipSuccess;
+            for (int l = 0; l < lanes() && e == hipSuccess; ++l) {
+                e = hipGraphCreate(&graph[l], 0);
+                if (e == hipSuccess) {
+                    se::Launcher G;
+                    G.graph = graph[l];
+                    e = step(G, l);
+                }
+                if (e == hipSuccess) e = hipGraphInstantiate(&gexec[l], graph[l], nullptr, nullptr, 0);
             }
-            if (e == hipSuccess) e = hipGraphInstantiate(&gexec, graph, nullptr, nullptr, 0);
             if (e != hipSuccess) {
                 // no graph: the same launches, issued directly from now on
                 (void)hipGetLastError();
-                if (graph) (void)hipGraphDestroy(graph);
-                graph = nullptr;
-                gexec = nullptr;
+                drop_graphs();
                 use_graph = false;
             } else {
                 graph_grid = grid;
             }
         }
-        if (!use_graph) {
-            se::Launcher D;
-            D.st = bst;
-            return step(D);
+        hipError_t e = hipMemcpyAsync(d_ctl.p, h_ctl.p, sizeof(se::BCtl) * ns, hipMemcpyHostToDevice, bst);
+        if (e == hipSuccess && lanes() > 1) e = hipEventRecord(ev_ctl, bst);
+        if (e == hipSuccess && lanes() > 1) e = hipStreamWaitEvent(bst2, ev_ctl, 0);
+        for (int l = 0; l < lanes() && e == hipSuccess; ++l) {
+            hipStream_t st = lane_stream(l);
+            if (use_graph) {
+                e = hipGraphLaunch(gexec[l], st);
+            } else {
+                se::Launcher D;
+                D.st = st;
+                e = step(D, l);
+            }
+            const int s0 = lane_begin(l), n = lane_end(l) - s0;
+            if (e == hipSuccess)
+                e = hipMemcpyAsync(hdyn() + s0, d_dyn.as<se::BDyn>() + s0, sizeof(se::BDyn) * n,
+                                   hipMemcpyDeviceToHost, st);
         }
-        ++graph_steps;
-        return hipGraphLaunch(gexec, bst);
+        for (int l = 0; l < lanes() && e == hipSuccess; ++l) e = hipStreamSynchronize(lane_stream(l));
+        if (e == hipSuccess && use_graph) ++graph_steps;
+        return e;
     }
 
     void run_batched() {
@@ -511,12 +559,8 @@ struct se_server {
             if (grid > 0) {
                 int g = 256;
                 while (g < grid) g *= 2;
-                hipError_t e = hipMemcpyAsync(d_ctl.p, h_ctl.p, sizeof(se::BCtl) * ns, hipMemcpyHostToDevice, bst);
-                if (e == hipSuccess) e = launch_step(g);
+                const hipError_t e = run_step(g);
                 ++steps;
-                if (e == hipSuccess)
-                    e = hipMemcpyAsync(h_dyn.p, d_dyn.p, sizeof(se::BDyn) * ns, hipMemcpyDeviceToHost, bst);
-                if (e == hipSuccess) e = hipStreamSynchronize(bst);
                 if (e != hipSuccess) {
                     // every resident solve fails; the engine goes on with new requests
                     (void)hipGetLastError();
@@ -605,17 +649,24 @@ se_status se_server_create_batched(se_ctx* ctx, uint64_t hbm_budget_bytes, int32
     s->device = ctx->device;
     s->budget = hbm_budget_bytes;
     s->batched = true;
-    const char* ng = std::getenv("SE_BATCH_NO_GRAPH");
-    s->use_graph = !(ng && ng[0] == '1');
+    // Direct launches by default (measured faster than graph replays of the
+    // same step on MI355X: each graph node adds about 10 us); SE_BATCH_GRAPH=1
+    // replays a graph built once per server.
+    const char* gr = std::getenv("SE_BATCH_GRAPH");
+    s->use_graph = gr && gr[0] == '1';
+    const char* nl = std::getenv("SE_BATCH_LANES");
+    s->nlanes = (nl && nl[0] == '1') ? 1 : 2;
     s->bslots.resize(max_slots);
     const size_t ns = (size_t)max_slots;
     // Non-blocking: legacy null-stream work of other threads (a matrix being
     // created while a step is captured) must not synchronize with this stream.
-    bool ok = hipStreamCreateWithFlags(&s->bst, hipStreamNonBlocking) == hipSuccess;
+    bool ok = hipStreamCreateWithFlags(&s->bst, hipStreamNonBlocking) == hipSuccess &&
+              hipStreamCreateWithFlags(&s->bst2, hipStreamNonBlocking) == hipSuccess &&
+              hipEventCreateWithFlags(&s->ev_ctl, hipEventDisableTiming) == hipSuccess;
     ok = ok && s->d_fix.ensure(sizeof(se::BFix) * ns) == hipSuccess;
     ok = ok && s->d_ctl.ensure(sizeof(se::BCtl) * ns) == hipSuccess;
     ok = ok && s->d_dyn.ensure(sizeof(se::BDyn) * ns) == hipSuccess;
-    ok = ok && s->d_jobs.ensure(se::batch_jobs_bytes()) == hipSuccess;
+    ok = ok && s->d_jobs.ensure(se_server::jobs_stride() * 2) == hipSuccess;
     ok = ok && s->h_fix.ensure(sizeof(se::BFix) * ns) == hipSuccess;
     ok = ok && s->h_ctl.ensure(sizeof(se::BCtl) * ns) == hipSuccess;
     ok = ok && s->h_dyn.ensure(sizeof(se::BDyn) * ns) == hipSuccess;
@@ -636,6 +687,8 @@ se_status se_server_create_batched(se_ctx* ctx, uint64_t hbm_budget_bytes, int32
         s->h_dyn.release();
         s->h_out.release();
         if (s->bst) (void)hipStreamDestroy(s->bst);
+        if (s->bst2) (void)hipStreamDestroy(s->bst2);
+        if (s->ev_ctl) (void)hipEventDestroy(s->ev_ctl);
         delete s;
         return SE_ERR_HIP;
     }
@@ -740,8 +793,8 @@ void se_server_destroy(se_server* srv) {
     (void)hipSetDevice(srv->device);
     if (srv->batched) {
         (void)hipStreamSynchronize(srv->bst);
-        if (srv->gexec) (void)hipGraphExecDestroy(srv->gexec);
-        if (srv->graph) (void)hipGraphDestroy(srv->graph);
+        (void)hipStreamSynchronize(srv->bst2);
+        srv->drop_graphs();
         for (BSlot& b : srv->bslots) b.mem.release();
         srv->d_fix.release();
         srv->d_ctl.release();
@@ -752,6 +805,8 @@ void se_server_destroy(se_server* srv) {
         srv->h_dyn.release();
         srv->h_out.release();
         (void)hipStreamDestroy(srv->bst);
+        (void)hipStreamDestroy(srv->bst2);
+        (void)hipEventDestroy(srv->ev_ctl);
     }
     (void)hipGetLastError();  // nothing reported here may linger for a later launch check
     for (Slot& sl : srv->slots) {

@@ -127,12 +127,12 @@ def test_graph_and_direct_launches_agree_bitwise(ctx):
     reqs = [(W.potential_laplacian(s["m"], s["dim"], 2.0, s["pot_seed"]), s) for s in specs]
     print("batched: graph vs direct", flush=True)
     st = []
-    with_graph = _serve(ctx, reqs, 3, stats=st)
-    os.environ["SE_BATCH_NO_GRAPH"] = "1"
+    os.environ["SE_BATCH_GRAPH"] = "1"
     try:
-        direct = _serve(ctx, reqs, 3, stats=st)
+        with_graph = _serve(ctx, reqs, 3, stats=st)
     finally:
-        del os.environ["SE_BATCH_NO_GRAPH"]
+        del os.environ["SE_BATCH_GRAPH"]
+    direct = _serve(ctx, reqs, 3, stats=st)
     # every step of the first server replayed the graph, none of the second
     assert st[0][0] > 0 and st[0][1] == st[0][0] and st[1][0] > 0 and st[1][1] == 0, st
     for a, b in zip(with_graph, direct):
