@@ -51,7 +51,7 @@ __device__ __forceinline__ void dpush(Segs& s, const double* p, int w) {
     s.nseg++;
 }
 
-enum Stage { ST_GATHERED, ST_CHOL1, ST_CHOL2, ST_EIG, ST_HL1, ST_HL2, ST_HL3, ST_UPD };
+enum Stage { ST_GATHERED, ST_REPROJ, ST_CHOL1, ST_CHOL2, ST_EIG, ST_HL1, ST_HL2, ST_HL3, ST_UPD };
 
 // Job lists of the phases up to the next planning point, one thread per slot.
 __global__ void bplan_kernel(int stage, int ns, const BFix* __restrict__ fix, const BCtl* __restrict__ ctl,
@@ -71,8 +71,8 @@ __global__ void bplan_kernel(int stage, int ns, const BFix* __restrict__ fix, co
     double* AP = AX + F.poff;
     int* ii = info_i(F);
 
-    // W <- W - [X, P] ([X, P]^T W)
-    auto plan_proj = [&]() {
+    // W <- W - [X, P] ([X, P]^T W) (go = false: an empty job)
+    auto plan_proj = [&](bool want) {
         const double* W = F.w[D.wcur];
         Segs Q = dsegs(ld);
         dpush(Q, X, D.k);
@@ -80,17 +80,20 @@ __global__ void bplan_kernel(int stage, int ns, const BFix* __restrict__ fix, co
         Segs Ws = dsegs(ld);
         dpush(Ws, W, D.w);
         const int q = D.k + D.p;
-        const bool go = on && q > 0 && D.w > 0;
+        const bool go = want && on && q > 0 && D.w > 0;
         J->gproj[s] = BGramJob{Q, Ws, go ? n : 0, F.rows_g, q, D.w, 0, F.nch_g, F.part, sm + BSmall::G};
         J->uproj[s] = BUpdJob{Q, Ws, go ? n : 0, q, go ? D.w : 0, sm + BSmall::G, -1.0, 1.0};
     };
-    // W^T W and its Cholesky-QR transform with column drop
-    auto plan_chol = [&](double ns_tol) {
+    // W^T W, and its Cholesky-QR transform with column drop
+    auto plan_gram = [&](bool want) {
         const double* W = F.w[D.wcur];
         Segs Ws = dsegs(ld);
         dpush(Ws, W, D.w);
-        const bool go = on && D.w > 0;
+        const bool go = want && on && D.w > 0;
         J->gch[s] = BGramJob{Ws, Ws, go ? n : 0, F.rows_g, D.w, D.w, 1, F.nch_g, F.part, sm + BSmall::GW};
+    };
+    auto plan_chol = [&](double ns_tol) {
+        const bool go = on && D.w > 0;
         J->cch[s] = CholJob{sm + BSmall::GW, sm + BSmall::T, sm + BSmall::CW, ii, info_d(F), kDrop, ns_tol,
                             go ? D.w : 0};
     };
@@ -118,15 +121,37 @@ __global__ void bplan_kernel(int stage, int ns, const BFix* __restrict__ fix, co
                 D.wa = D.w;  // the start block (k = p = 0)
             }
             for (int i = 0; i < D.w; ++i) D.map[i] = i;
-            plan_proj();
+            plan_proj(true);
+            plan_gram(true);
+            break;
+        }
+        case ST_REPROJ: {
+            // One projection suffices unless a column kept less than half of
+            // its squared norm (the criterion of Kahan and Parlett for
+            // classical Gram-Schmidt); the norms before it are the residual
+            // norms of the last check. Appended dropped columns always take
+            // the second projection.
+            bool again = C.mode == BMODE_ITER && C.expand && D.w > D.wa;
+            if (C.mode == BMODE_ITER && D.k + D.p > 0) {
+                const double* GW = sm + BSmall::GW;
+                for (int i = 0; i < D.wa && !again; ++i)
+                    again = GW[(size_t)i * D.w + i] < 0.5 * D.sums[C.act[i]];
+            }
+            plan_proj(again);
+            plan_gram(again);
             plan_chol(0.0);
             break;
         }
-        case ST_CHOL1:
+        case ST_CHOL1: {
+            // after a pass with a pivot below 1e-8 the kept columns carry
+            // amplified rounding along [X, P]: project once more
+            const bool low = on && D.w > 0 && (info_d(F)[0] < 1e-8 || ii[0] < D.w);
             plan_apply();
-            plan_proj();
+            plan_proj(low);
+            plan_gram(true);
             plan_chol(kNs);
             break;
+        }
         case ST_CHOL2: {
             plan_apply();
             // the kept block is [W (cw) | X_drop (cx) | P_drop (cp)], in this order
@@ -319,12 +344,12 @@ __global__ __launch_bounds__(kT) void bsym_kernel(const BFix* __restrict__ fix, 
 // HL start block B = (I - Z1 Z1^T) E, E the unit columns at the HL positions.
 __global__ __launch_bounds__(kT) void bhl_kernel(const BFix* __restrict__ fix, const BCtl* __restrict__ ctl,
                                                  const BDyn* __restrict__ dyn) {
-    const BDyn& D = dyn[blockIdx.x];
-    if (ctl[blockIdx.x].mode == BMODE_IDLE) return;
+    const BDyn& D = dyn[blockIdx.y];
+    if (ctl[blockIdx.y].mode == BMODE_IDLE) return;
     const int m = D.m, kk = D.kk, h = D.nhl;
-    const double* Z = fix[blockIdx.x].sm + BSmall::Z;
-    double* B = fix[blockIdx.x].sm + BSmall::B;
-    for (int e = threadIdx.x; e < m * h; e += kT) {
+    const double* Z = fix[blockIdx.y].sm + BSmall::Z;
+    double* B = fix[blockIdx.y].sm + BSmall::B;
+    for (int e = blockIdx.x * kT + threadIdx.x; e < m * h; e += gridDim.x * kT) {
         const int r = e / h, c = e % h;
         const int q = D.hlpos[c];
         double s = 0.0;
@@ -377,14 +402,16 @@ hipError_t launch_batch_step(Launcher& L, int ns, const BFix* fix, const BCtl* c
     // W block, projected twice against [X, P], Cholesky-QR with drop
     L(bgather_kernel, dim3(G), dim3(kT), 0, ns, fix, ctl, dyn);
     plan(ST_GATHERED);
-    for (int q = 0; q < 2; ++q) {
-        launch_gram_batched(L, J->gproj, ns, G);
-        launch_update_batched(L, J->uproj, ns, upd_grid);
-    }
+    launch_gram_batched(L, J->gproj, ns, G);
+    launch_update_batched(L, J->uproj, ns, upd_grid);
+    launch_gram_batched(L, J->gch, ns, G);
+    plan(ST_REPROJ);  // a second projection only where needed
+    launch_gram_batched(L, J->gproj, ns, G);
+    launch_update_batched(L, J->uproj, ns, upd_grid);
     launch_gram_batched(L, J->gch, ns, G);
     launch_chol_batched(L, J->cch, ns);
     plan(ST_CHOL1);
-    // second pass: apply, project once more, Cholesky-QR (or Newton-Schulz)
+    // second pass: apply, project again after a low pivot, Cholesky-QR (or Newton-Schulz)
     launch_update_batched(L, J->uch, ns, upd_grid);
     launch_gram_batched(L, J->gproj, ns, G);
     launch_update_batched(L, J->uproj, ns, upd_grid);
@@ -399,7 +426,7 @@ hipError_t launch_batch_step(Launcher& L, int ns, const BFix* fix, const BCtl* c
     launch_syev_lowest_batched(L, J->eig, ns, J->eigspace);
     // HL basis: two Cholesky-QR passes, each after a projection against Z1
     plan(ST_EIG);
-    L(bhl_kernel, dim3(ns), dim3(kT), 0, fix, ctl, dyn);
+    L(bhl_kernel, dim3(16, ns), dim3(kT), 0, fix, ctl, dyn);
     launch_small_mm_batched(L, J->mzt, ns);
     launch_small_mm_batched(L, J->mzu, ns);
     launch_small_mm_batched(L, J->mg, ns);

@@ -14,11 +14,21 @@ namespace se {
 // explicitly rather than captured from a stream: a capture in progress makes
 // other threads' work on the null stream fail, and a serving engine cannot
 // keep its callers from using the null stream.
+// Between fork() and join() the launches are independent branches (graph
+// nodes that depend only on the node before the fork; on a stream they run in
+// order); the launch after join() depends on all of them.
 struct Launcher {
     hipStream_t st = nullptr;
     hipGraph_t graph = nullptr;  // nullptr: launch on st
     hipGraphNode_t last = nullptr;
     hipError_t err = hipSuccess;
+
+    void fork() {
+        forking = true;
+        base = last;
+        nbranch = 0;
+    }
+    void join() { forking = false; }
 
     template <class... P, class... A>
     void operator()(void (*kernel)(P...), dim3 grid, dim3 block, size_t shmem, A... args) {
@@ -39,11 +49,28 @@ struct Launcher {
         kp.kernelParams = argv;
         kp.extra = nullptr;
         hipGraphNode_t node = nullptr;
-        err = hipGraphAddKernelNode(&node, graph, last ? &last : nullptr, last ? 1 : 0, &kp);
+        if (forking) {
+            err = hipGraphAddKernelNode(&node, graph, base ? &base : nullptr, base ? 1 : 0, &kp);
+            if (err == hipSuccess && nbranch < kMaxBranch) branch[nbranch++] = node;
+            if (nbranch == kMaxBranch) err = hipErrorInvalidValue;
+            return;
+        }
+        if (nbranch > 0) {  // first launch after a join
+            err = hipGraphAddKernelNode(&node, graph, branch, (size_t)nbranch, &kp);
+            nbranch = 0;
+        } else {
+            err = hipGraphAddKernelNode(&node, graph, last ? &last : nullptr, last ? 1 : 0, &kp);
+        }
         if (err == hipSuccess) last = node;
     }
 
   private:
+    static constexpr int kMaxBranch = 16;
+    bool forking = false;
+    hipGraphNode_t base = nullptr;
+    hipGraphNode_t branch[kMaxBranch] = {};
+    int nbranch = 0;
+
     template <class T, size_t... I>
     static void fill_args(T& vals, void** argv, std::index_sequence<I...>) {
         ((argv[I] = static_cast<void*>(&std::get<I>(vals))), ...);

@@ -639,7 +639,7 @@ __global__ __launch_bounds__(64) void tridiag_wave_kernel(int m, const double* _
 // needs no per-element test and leaves the reduced part and the padding
 // unchanged. LDS vectors are double-buffered by step parity.
 template <int RR, int RC>
-__global__ __launch_bounds__(512) void tridiag_reg_kernel(int mfull, int k0,
+__device__ __forceinline__ void tridiag_reg_kernel_body(int bx, int mfull, int k0,
                                                           const double* __restrict__ Ag,
                                                           double* __restrict__ dg,
                                                           double* __restrict__ eg,
@@ -763,6 +763,17 @@ __global__ __launch_bounds__(512) void tridiag_reg_kernel(int mfull, int k0,
             if (r == m - 1 && c == m - 1) d[m - 1] = a[i][j];
         }
 }
+
+template <int RR, int RC>
+__global__ __launch_bounds__(512) void tridiag_reg_kernel(int mfull, int k0,
+                                                          const double* __restrict__ Ag,
+                                                          double* __restrict__ dg,
+                                                          double* __restrict__ eg,
+                                                          double* __restrict__ taug,
+                                                          double* __restrict__ Vhg) {
+    tridiag_reg_kernel_body<RR, RC>(blockIdx.x, mfull, k0, Ag, dg, eg, taug, Vhg);
+}
+
 
 // ---------------------------------------------------------------------------
 // The k smallest eigenvalues of the symmetric tridiagonal (d, e) by
@@ -1594,13 +1605,32 @@ __global__ __launch_bounds__(64) void tridiag_wave_batched_kernel(const EigJob* 
     tridiag_wave_kernel_body(0, J.m, J.A, W.d, W.e, W.tau, W.Vh);
 }
 
+// Orders up to 112: the in-LDS kernel; above: the register kernel takes the
+// trailing 192 (or fewer) reflectors, the global-memory kernel the ones before
+// (as launch_syev_lowest without the cooperative kernel).
+constexpr int kBatchRegOrder = 192;
 template <bool kInLds>
 __global__ __launch_bounds__(kTri) void tridiag_batched_kernel(const EigJob* __restrict__ jobs) {
     const EigJob& J = jobs[blockIdx.x];
     if (J.m <= kWaveTri || J.k <= 0) return;
-    if (kInLds != ((size_t)J.m * J.m <= (size_t)kLdsDoubles)) return;
     const EigWork W = eig_work(J.work, J.m);
-    tridiag_kernel_body<kInLds>(0, J.m, J.m, J.A, W.d, W.e, W.tau, W.Vh);
+    if (kInLds) {
+        if (J.m > 112) return;
+        tridiag_kernel_body<true>(0, J.m, J.m, J.A, W.d, W.e, W.tau, W.Vh);
+    } else {
+        if (J.m <= kBatchRegOrder) return;
+        tridiag_kernel_body<false>(0, J.m, J.m - kBatchRegOrder, J.A, W.d, W.e, W.tau, W.Vh);
+    }
+}
+
+template <int RR, int RC>
+__global__ __launch_bounds__(512) void tridiag_reg_batched_kernel(const EigJob* __restrict__ jobs) {
+    const EigJob& J = jobs[blockIdx.x];
+    if (J.m <= 112 || J.k <= 0) return;
+    const int k0 = J.m > kBatchRegOrder ? J.m - kBatchRegOrder : 0;
+    if ((J.m - k0 + 15) / 16 != RR) return;
+    const EigWork W = eig_work(J.work, J.m);
+    tridiag_reg_kernel_body<RR, RC>(0, J.m, k0, J.A, W.d, W.e, W.tau, W.Vh);
 }
 
 __global__ __launch_bounds__(256) void bisect_batched_kernel(const EigJob* __restrict__ jobs) {
@@ -1645,9 +1675,17 @@ void launch_syev_lowest_batched(Launcher& L, const EigJob* jobs, int nj, void* j
     SmallMMJob* mm = static_cast<SmallMMJob*>(jobspace);
     CholJob* ch = reinterpret_cast<CholJob*>(mm + 6 * kMaxBatch);
     L(eig_plan_kernel, dim3(1), dim3(64), 0, jobs, nj, mm, ch);
+    // the leading reflectors of orders above 192, then one branch per order class
+    L(tridiag_batched_kernel<false>, dim3(nj), dim3(kTri), 0, jobs);
+    L.fork();
     L(tridiag_wave_batched_kernel, dim3(nj), dim3(64), 0, jobs);
     L(tridiag_batched_kernel<true>, dim3(nj), dim3(kTri), sizeof(double) * (size_t)kLdsDoubles, jobs);
-    L(tridiag_batched_kernel<false>, dim3(nj), dim3(kTri), 0, jobs);
+    L(tridiag_reg_batched_kernel<8, 4>, dim3(nj), dim3(512), 0, jobs);
+    L(tridiag_reg_batched_kernel<9, 5>, dim3(nj), dim3(512), 0, jobs);
+    L(tridiag_reg_batched_kernel<10, 5>, dim3(nj), dim3(512), 0, jobs);
+    L(tridiag_reg_batched_kernel<11, 6>, dim3(nj), dim3(512), 0, jobs);
+    L(tridiag_reg_batched_kernel<12, 6>, dim3(nj), dim3(512), 0, jobs);
+    L.join();
     constexpr int kb = (kBatchEigMax + 3) / 4;
     L(bisect_batched_kernel, dim3(kb, nj), dim3(256), 0, jobs);
     L(invit_batched_kernel, dim3((kBatchEigMax + 255) / 256, nj), dim3(256), 0, jobs);
