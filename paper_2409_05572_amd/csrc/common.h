@@ -457,7 +457,7 @@ struct SmallMMJob {  // C = alpha op(A) B + beta C; op(A) = A^T when transA (A: 
     double alpha, beta;
     int rows, ca, cb, lda, ldb, ldc, transA;
 };
-struct CholJob {  // launch_chol_drop's operation on one a x a Gram matrix (a <= 1024; work: 2 a^2 + 2a doubles)
+struct CholJob {  // launch_chol_drop's operation on one a x a Gram matrix (a <= 896; work: 2 a^2 + 2a doubles)
     const double* G;
     double* T;
     double* work;

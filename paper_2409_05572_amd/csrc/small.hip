@@ -987,6 +987,117 @@ __global__ __launch_bounds__(256) void invit_kernel(int m, int k, const double* 
 }
 
 
+// The same inverse iteration with the factors and the iterate of each
+// eigenvalue in LDS (E eigenvalues per workgroup, one per lane of a single
+// wave): the recurrences read LDS instead of waiting on L2 at every step.
+// Arithmetic identical to invit_kernel. LDS: E (5 m doubles + m bytes).
+__global__ __launch_bounds__(64) void invit_lds_kernel(int m, int k, int E, const double* __restrict__ dg,
+                                                       const double* __restrict__ eg,
+                                                       const double* __restrict__ w,
+                                                       const double* __restrict__ scal,
+                                                       double* __restrict__ ZT) {
+    extern __shared__ double sm[];
+    const int lane = threadIdx.x;
+    const int i = blockIdx.x * E + lane;
+    double* DL = sm;                      // [j][E]
+    double* DD = DL + (size_t)m * E;
+    double* DU = DD + (size_t)m * E;
+    double* DU2 = DU + (size_t)m * E;
+    double* Z = DU2 + (size_t)m * E;
+    unsigned char* IP = reinterpret_cast<unsigned char*>(Z + (size_t)m * E);
+    if (lane >= E || i >= k) return;
+    const double tnorm = fmax(scal[0], DBL_MIN);
+    const double tiny = DBL_EPSILON * tnorm;
+    const double sep = 10.0 * DBL_EPSILON * tnorm;
+    int run = 0;
+    for (int q = i; q > 0 && w[q] - w[q - 1] <= sep; --q) ++run;
+    const double lam = w[i] + run * sep;
+    auto guard = [&](double x) { return fabs(x) < tiny ? copysign(tiny, x == 0.0 ? 1.0 : x) : x; };
+#define AT(arr, j) arr[(size_t)(j) * E + lane]
+    double dcur = dg[0] - lam;
+    double ucur = (m > 1) ? eg[0] : 0.0;
+#pragma unroll 4
+    for (int j = 0; j + 1 < m; ++j) {
+        const double lj = eg[j];
+        const double dn = dg[j + 1] - lam;
+        const double un = (j + 2 < m) ? eg[j + 1] : 0.0;
+        if (fabs(dcur) >= fabs(lj)) {
+            const double f = (dcur != 0.0) ? lj / dcur : 0.0;
+            AT(IP, j) = 0;
+            AT(DL, j) = (dcur != 0.0) ? f : lj;
+            AT(DD, j) = guard(dcur);
+            AT(DU, j) = ucur;
+            AT(DU2, j) = 0.0;
+            dcur = (dcur != 0.0) ? dn - f * ucur : dn;
+            ucur = un;
+        } else {
+            const double f = dcur / lj;
+            AT(IP, j) = 1;
+            AT(DD, j) = guard(lj);
+            AT(DL, j) = f;
+            AT(DU, j) = dn;
+            AT(DU2, j) = un;
+            dcur = ucur - f * dn;
+            ucur = -f * un;
+        }
+    }
+    AT(DD, m - 1) = guard(dcur);
+    for (int j = 0; j < m; ++j) AT(Z, j) = hash_unit((unsigned)i, (unsigned)j);
+    for (int it = 0; it < 2; ++it) {
+        double bcur = AT(Z, 0);
+#pragma unroll 8
+        for (int j = 0; j + 1 < m; ++j) {
+            const double bn = AT(Z, j + 1);
+            const double l = AT(DL, j);
+            if (AT(IP, j) == 0) {
+                AT(Z, j) = bcur;
+                bcur = bn - l * bcur;
+            } else {
+                AT(Z, j) = bn;
+                bcur = bcur - l * bn;
+            }
+        }
+        double z1 = bcur / AT(DD, m - 1);
+        AT(Z, m - 1) = z1;
+        double z2 = 0.0;
+        if (m >= 2) {
+            const double zz = (AT(Z, m - 2) - AT(DU, m - 2) * z1) / AT(DD, m - 2);
+            AT(Z, m - 2) = zz;
+            z2 = z1;
+            z1 = zz;
+        }
+        double mx = fmax(fabs(z1), fabs(z2));
+#pragma unroll 8
+        for (int j = m - 3; j >= 0; --j) {
+            const double zz = (AT(Z, j) - AT(DU, j) * z1 - AT(DU2, j) * z2) / AT(DD, j);
+            AT(Z, j) = zz;
+            z2 = z1;
+            z1 = zz;
+            mx = fmax(mx, fabs(zz));
+        }
+        const double sc = (mx > 0.0) ? 1.0 / mx : 1.0;
+        double nr = 0.0;
+        for (int j = 0; j < m; ++j) {
+            const double v = AT(Z, j) * sc;
+            AT(Z, j) = v;
+            nr += v * v;
+        }
+        if (it == 1) {
+            const double inv = 1.0 / sqrt(nr);
+            for (int j = 0; j < m; ++j) ZT[(size_t)j * k + i] = AT(Z, j) * inv;
+        }
+    }
+#undef AT
+}
+
+// Eigenvalues per workgroup of invit_lds_kernel for order m (0: the matrix is
+// too large for its LDS; use invit_kernel).
+int invit_lds_per_block(int m) {
+    const size_t per = (size_t)m * (5 * sizeof(double) + 1);
+    const int E = (int)std::min<size_t>(64, (150 * 1024) / per);
+    return E >= 2 ? E : 0;
+}
+
 // Z = Q ZT with Q = H_0 H_1 ... H_{m-3}; one wave per eigenvector, kept in
 // registers (m <= 1024 -> 16 values per lane). ZT and Z are m x k (ld k).
 __device__ __forceinline__ void backtransform_kernel_body(int bx, int m, int k, const double* __restrict__ tau,
@@ -1265,6 +1376,254 @@ __global__ __launch_bounds__(kSmall) void sumsq_kernel(long long count, const do
     if (threadIdx.x == 0) out[0] = s;
 }
 
+// Cholesky-QR transform with column drop for 112 < a <= kCholBig (same
+// inputs, outputs and drop rule as chol_drop_kernel): blocked right-looking
+// factorization with the scaled matrix in `work` (global memory, L2
+// resident). Per panel of 16 columns, one wave factorizes the diagonal block
+// (drop decisions and pivots), every thread then solves its rows below the
+// block against it (dropped columns give zero entries), and the trailing lower
+// triangle takes the rank-16 update with the panel's columns staged in LDS.
+// The inverse of L follows by 16 x 16 blocks as in chol_drop_blocked_kernel,
+// with the block products in `work` after the matrix. work: a (a | 1) +
+// 16 a + 256 doubles.
+constexpr int kCholBig = 896;
+constexpr int kBigLP = kCholPanel + 1;  // LDS panel row stride (odd: no bank conflicts)
+__device__ __forceinline__ void chol_drop_big_body(int a, const double* __restrict__ G, double* __restrict__ T,
+                                                   double* __restrict__ work, int* __restrict__ info_i,
+                                                   double* __restrict__ info_d, double drop_tol2, double ns_tol) {
+    extern __shared__ double lp[];  // a x kBigLP: L's rows in the current panel's columns
+    __shared__ int b_pos[kCholBig];
+    __shared__ int b_kept[kCholBig];
+    __shared__ double b_D[kCholBig];
+    __shared__ double b_dl[kCholBig];  // diagonal of L (0 where dropped)
+    __shared__ double b_di[kCholBig];  // diagonal of L^{-1} (1 where dropped)
+    __shared__ double b_red[kSWaves];
+    __shared__ double b_minpiv;
+    __shared__ int b_r;
+    const int t = threadIdx.x;
+    const int nth = blockDim.x;
+    const int FS = a | 1;
+    double* F = work;
+    double* tmp = work + (size_t)a * FS;
+    const bool can_drop = drop_tol2 >= 0.0;
+    const int lane = t & 63, wid = t >> 6, nwave = nth >> 6;
+    if (ns_tol > 0.0) {
+        double sq = 0.0;
+        for (int e = t; e < a * a; e += nth) {
+            const double v = G[e] - ((e / a == e % a) ? 1.0 : 0.0);
+            sq += v * v;
+        }
+        sq = block_sum(sq, b_red);
+        if (sq <= ns_tol * ns_tol) {
+            for (int e = t; e < a * a; e += nth) T[e] = ((e / a == e % a) ? 1.5 : 0.0) - 0.5 * G[e];
+            for (int i = t; i < a; i += nth) info_i[1 + i] = i;
+            if (t == 0) {
+                info_i[0] = a;
+                info_d[0] = 1.0 - sqrt(sq);
+            }
+            return;
+        }
+    }
+    for (int i = t; i < a; i += nth) {
+        const double g = G[(size_t)i * a + i];
+        b_D[i] = (g > 0.0) ? 1.0 / sqrt(g) : 0.0;
+    }
+    __syncthreads();
+    for (int e = t; e < a * a; e += nth) {
+        const int i = e / a, j = e % a;
+        if (j <= i) F[(size_t)i * FS + j] = G[e] * b_D[i] * b_D[j];
+    }
+    if (t == 0) b_minpiv = DBL_MAX;
+    __syncthreads();
+
+    for (int jb = 0; jb < a; jb += kCholPanel) {
+        const int nbw = min(kCholPanel, a - jb);
+        // diagonal block: lane c < nbw holds row jb + c
+        if (wid == 0) {
+            double P[kCholPanel];
+#pragma unroll
+            for (int c = 0; c < kCholPanel; ++c)
+                P[c] = (lane < nbw && c <= lane) ? F[(size_t)(jb + lane) * FS + jb + c] : 0.0;
+            double minp = DBL_MAX;
+#pragma unroll
+            for (int c = 0; c < kCholPanel; ++c) {
+                if (c < nbw) {
+                    const int j = jb + c;
+                    double dj = __shfl(P[c], c, 64);
+                    const bool drop = can_drop && (!(dj > drop_tol2) || b_D[j] == 0.0);
+                    if (!can_drop && !(dj > 1e-300)) dj = 1e-300;
+                    if (drop) {
+                        if (lane >= c) P[c] = 0.0;
+                        if (lane == 0) {
+                            b_pos[j] = -1;
+                            b_dl[j] = 0.0;
+                        }
+                    } else {
+                        const double piv = sqrt(dj);
+                        const double inv = 1.0 / piv;
+                        minp = fmin(minp, dj);
+                        if (lane > c) P[c] *= inv;
+                        if (lane == c) P[c] = piv;
+                        if (lane == 0) {
+                            b_pos[j] = 0;
+                            b_dl[j] = piv;
+                        }
+#pragma unroll
+                        for (int c2 = c + 1; c2 < kCholPanel; ++c2) {
+                            if (c2 < nbw) {
+                                const double l2 = __shfl(P[c], c2, 64);  // L[jb + c2][j]
+                                if (lane >= c2) P[c2] -= P[c] * l2;
+                            }
+                        }
+                    }
+                }
+            }
+            if (lane < nbw) {
+#pragma unroll
+                for (int c = 0; c < kCholPanel; ++c) {
+                    if (c <= lane) F[(size_t)(jb + lane) * FS + jb + c] = P[c];
+                    lp[(jb + lane) * kBigLP + c] = (c <= lane) ? P[c] : 0.0;
+                }
+            }
+            if (lane == 0) b_minpiv = fmin(b_minpiv, minp);
+        }
+        __syncthreads();
+        // rows below the block: x L_D^T = f by forward substitution
+        const int t0 = jb + nbw;
+        for (int i = t0 + t; i < a; i += nth) {
+            double x[kCholPanel];
+#pragma unroll
+            for (int c = 0; c < kCholPanel; ++c) x[c] = (c < nbw) ? F[(size_t)i * FS + jb + c] : 0.0;
+#pragma unroll
+            for (int c = 0; c < kCholPanel; ++c) {
+                if (c < nbw) {
+                    if (b_pos[jb + c] < 0) {
+                        x[c] = 0.0;
+                    } else {
+                        double sacc = x[c];
+#pragma unroll
+                        for (int q = 0; q < kCholPanel; ++q)
+                            if (q < c) sacc -= x[q] * lp[(jb + c) * kBigLP + q];
+                        x[c] = sacc / b_dl[jb + c];
+                    }
+                }
+            }
+#pragma unroll
+            for (int c = 0; c < kCholPanel; ++c) {
+                if (c < nbw) F[(size_t)i * FS + jb + c] = x[c];
+                lp[i * kBigLP + c] = (c < nbw) ? x[c] : 0.0;
+            }
+        }
+        __syncthreads();
+        // trailing update: F[i][i2] -= sum_c L[i][jb + c] L[i2][jb + c], t0 <= i2 <= i
+        for (int i = t0 + wid; i < a; i += nwave) {
+            double li[kCholPanel];
+#pragma unroll
+            for (int c = 0; c < kCholPanel; ++c) li[c] = lp[i * kBigLP + c];
+            for (int i2 = t0 + lane; i2 <= i; i2 += 64) {
+                double sacc = 0.0;
+#pragma unroll
+                for (int c = 0; c < kCholPanel; ++c) sacc = fma(li[c], lp[i2 * kBigLP + c], sacc);
+                F[(size_t)i * FS + i2] -= sacc;
+            }
+        }
+        __syncthreads();
+    }
+    if (t == 0) {
+        int r = 0;
+        for (int j = 0; j < a; ++j) {
+            if (b_pos[j] >= 0) {
+                b_pos[j] = r;
+                b_kept[r] = j;
+                info_i[1 + r] = j;
+                ++r;
+            }
+        }
+        b_r = r;
+        info_i[0] = r;
+        info_d[0] = b_minpiv;
+    }
+    __syncthreads();
+    const int r = b_r;
+
+    // inverse of the modified L (identity on dropped rows and columns) by
+    // 16 x 16 blocks; L^{-1} below the diagonal is stored transposed at F[j][i]
+    auto Lm = [&](int i, int j) -> double {
+        if (b_pos[i] < 0 || b_pos[j] < 0) return (i == j) ? 1.0 : 0.0;
+        return (i == j) ? b_dl[i] : F[(size_t)i * FS + j];
+    };
+    auto Li = [&](int i, int j) -> double { return (i == j) ? b_di[i] : F[(size_t)j * FS + i]; };
+    const int nbk = (a + kCholPanel - 1) / kCholPanel;
+    for (int b = wid; b < nbk; b += nwave) {
+        const int b0 = b * kCholPanel, bs = min(kCholPanel, a - b0);
+        const int c = lane;
+        if (c < bs) {
+            double x[kCholPanel];
+#pragma unroll
+            for (int rr = 0; rr < kCholPanel; ++rr) {
+                double v = 0.0;
+                if (rr < bs && rr >= c) {
+                    double sacc = (rr == c) ? 1.0 : 0.0;
+#pragma unroll
+                    for (int q = 0; q < kCholPanel; ++q)
+                        if (q >= c && q < rr) sacc -= Lm(b0 + rr, b0 + q) * x[q];
+                    v = sacc / Lm(b0 + rr, b0 + rr);
+                }
+                x[rr] = v;
+            }
+#pragma unroll
+            for (int rr = 0; rr < kCholPanel; ++rr) {
+                if (rr < bs && rr == c) b_di[b0 + c] = x[rr];
+                if (rr < bs && rr > c) F[(size_t)(b0 + c) * FS + b0 + rr] = x[rr];
+            }
+        }
+    }
+    __syncthreads();
+    for (int dist = 1; dist < nbk; ++dist) {
+        const int npair = nbk - dist;
+        for (int e = t; e < npair * kCholPanel * kCholPanel; e += nth) {
+            const int J = e / (kCholPanel * kCholPanel), I = J + dist;
+            const int rr = (e / kCholPanel) % kCholPanel, cc = e % kCholPanel;
+            const int gi = I * kCholPanel + rr, gj = J * kCholPanel + cc;
+            double sacc = 0.0;
+            if (gi < a) {
+                for (int gk = gj; gk < I * kCholPanel; ++gk) sacc = fma(Lm(gi, gk), Li(gk, gj), sacc);
+            }
+            tmp[e] = sacc;
+        }
+        __syncthreads();
+        for (int e = t; e < npair * kCholPanel * kCholPanel; e += nth) {
+            const int J = e / (kCholPanel * kCholPanel), I = J + dist;
+            const int rr = (e / kCholPanel) % kCholPanel, cc = e % kCholPanel;
+            const int gi = I * kCholPanel + rr, gj = J * kCholPanel + cc;
+            if (gi >= a) continue;
+            double sacc = 0.0;
+            for (int q = 0; q <= rr; ++q)
+                sacc = fma(Li(gi, I * kCholPanel + q), tmp[J * kCholPanel * kCholPanel + q * kCholPanel + cc], sacc);
+            F[(size_t)gj * FS + gi] = -sacc;
+        }
+        __syncthreads();
+    }
+    for (int e = t; e < a * r; e += nth) {
+        const int i = e / r, q = e % r;
+        const int p = b_pos[i];
+        double v = 0.0;
+        if (p >= 0 && p <= q) {
+            const int kq = b_kept[q];
+            v = b_D[i] * ((i == kq) ? b_di[i] : F[(size_t)i * FS + kq]);
+        }
+        T[e] = v;
+    }
+}
+
+__global__ __launch_bounds__(kSmall) void chol_drop_big_kernel(int a, const double* __restrict__ G,
+                                                               double* __restrict__ T, double* __restrict__ work,
+                                                               int* __restrict__ info_i,
+                                                               double* __restrict__ info_d, double drop_tol2,
+                                                               double ns_tol) {
+    chol_drop_big_body(a, G, T, work, info_i, info_d, drop_tol2, ns_tol);
+}
+
 }  // namespace
 
 hipError_t launch_chol_drop(hipStream_t st, int a, const double* G, double* T, double* work,
@@ -1273,8 +1632,8 @@ hipError_t launch_chol_drop(hipStream_t st, int a, const double* G, double* T, d
     if (a <= kCholBlk)
         hipLaunchKernelGGL(chol_drop_blocked_kernel, dim3(1), dim3(kSmall), sizeof(double) * (size_t)a * (a | 1), st,
                            a, G, T, info_i, info_d, drop_tol2, ns_tol);
-    else if ((size_t)a * a <= (size_t)kLdsDoubles)
-        hipLaunchKernelGGL(chol_drop_kernel<true>, dim3(1), dim3(kSmall), sizeof(double) * (size_t)a * a, st, a,
+    else if (a <= kCholBig)
+        hipLaunchKernelGGL(chol_drop_big_kernel, dim3(1), dim3(kSmall), sizeof(double) * (size_t)a * kBigLP, st, a,
                            G, T, work, info_i, info_d, drop_tol2, ns_tol);
     else
         hipLaunchKernelGGL(chol_drop_kernel<false>, dim3(1), dim3(kSmall), 0, st, a, G, T, work, info_i, info_d,
@@ -1335,6 +1694,17 @@ size_t syev_work_doubles(int m) {
     // + the cooperative tridiagonalization's exchange vectors (2m + 2 x 128)
     return 4 * (size_t)m + 16 + mm + 2 * mm + 5 * mm + 2 * mm + gram_scratch_doubles(m, m, m) +
            2 * mm + 2 * (size_t)m + 2 * (size_t)m + 64 + 2 * (size_t)m + 256;
+}
+
+static void launch_invit(hipStream_t st, int m, int k, const double* d, const double* e, const double* w,
+                         const double* scal, double* ZT, double* fac) {
+    const int E = invit_lds_per_block(m);
+    if (E > 0) {
+        const size_t lds = (size_t)E * m * (5 * sizeof(double) + 1);
+        hipLaunchKernelGGL(invit_lds_kernel, dim3((k + E - 1) / E), dim3(64), lds, st, m, k, E, d, e, w, scal, ZT);
+    } else {
+        hipLaunchKernelGGL(invit_kernel, dim3((k + 255) / 256), dim3(256), 0, st, m, k, d, e, w, scal, ZT, fac);
+    }
 }
 
 hipError_t launch_syev_lowest(hipStream_t st, int m, int k, double* A, double* w, double* Z,
@@ -1403,8 +1773,7 @@ hipError_t launch_syev_lowest(hipStream_t st, int m, int k, double* A, double* w
         }
     }
     hipLaunchKernelGGL(bisect_kernel, dim3((k + 3) / 4), dim3(256), 0, st, m, k, d, e, w, scal);
-    hipLaunchKernelGGL(invit_kernel, dim3((k + 255) / 256), dim3(256), 0, st, m, k, d, e, w, scal, ZT,
-                       fac);
+    launch_invit(st, m, k, d, e, w, scal, ZT, fac);
     // Orthonormalize the k vectors (an m x k block whose rows are vector
     // components): one Cholesky-QR pass without column drop, then two passes
     // that take a Newton-Schulz step when the block is orthonormal to 1e-8
@@ -1455,7 +1824,7 @@ hipError_t launch_tridiag_lowest_vectors(hipStream_t st, int m, int k, const dou
     double* infod = cwork + 2 * mm + 2 * (size_t)m;
     int* infoi = reinterpret_cast<int*>(infod + 8);
     hipLaunchKernelGGL(bisect_kernel, dim3((k + 3) / 4), dim3(256), 0, st, m, k, d, e, w, scal);
-    hipLaunchKernelGGL(invit_kernel, dim3((k + 255) / 256), dim3(256), 0, st, m, k, d, e, w, scal, B0, fac);
+    launch_invit(st, m, k, d, e, w, scal, B0, fac);
     // the same three orthonormalization passes as launch_syev_lowest, the
     // last one writing ZT
     double* src[3] = {B0, B1, B0};
@@ -1550,7 +1919,7 @@ __global__ __launch_bounds__(kSmall) void chol_batched_kernel(const CholJob* __r
     if (J.a <= kCholBlk)
         chol_drop_blocked_kernel_body(0, J.a, J.G, J.T, J.info_i, J.info_d, J.drop_tol2, J.ns_tol);
     else
-        chol_drop_kernel_body<false>(0, J.a, J.G, J.T, J.work, J.info_i, J.info_d, J.drop_tol2, J.ns_tol);
+        chol_drop_big_body(J.a, J.G, J.T, J.work, J.info_i, J.info_d, J.drop_tol2, J.ns_tol);
 }
 
 // Work layout of the batched path for order m (within syev_work_doubles(m)).

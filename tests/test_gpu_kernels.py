@@ -296,18 +296,25 @@ def test_syev_lowest_degenerate_clusters(ctx, g, extra, k):
     assert np.abs(Z.T @ Z - np.eye(k)).max() <= 1e-12
 
 
-def test_cholqr_orthonormalizes_and_drops_dependent_columns(ctx):
+@pytest.mark.parametrize("w", [24, 130, 250])
+def test_cholqr_orthonormalizes_and_drops_dependent_columns(ctx, w):
+    """Widths up to 112 take the in-LDS blocked transform, wider ones the
+    blocked transform in global memory; both drop the dependent columns."""
     from paper_2409_05572_amd import api
 
     rng = np.random.default_rng(11)
-    n, w = 20001, 24
+    n = 20001
     U, _ = np.linalg.qr(rng.standard_normal((n, w)))
     Vt, _ = np.linalg.qr(rng.standard_normal((w, w)))
     Wm = U @ np.diag(np.logspace(0, -5, w)) @ Vt
-    Wm[:, 10] = 2 * Wm[:, 3] - Wm[:, 4]  # exactly dependent column
+    Wm[:, 10] = 2 * Wm[:, 3] - Wm[:, 4]  # exactly dependent columns
+    dep = 1
+    if w > 112:
+        Wm[:, w - 3] = Wm[:, 0] + 0.5 * Wm[:, w - 10]
+        dep = 2
     Wd = to_dev(Wm)
     r = api.cholqr(ctx, Wd, w)
     Q = Wd.cpu().numpy()[:, :r]
-    assert r == w - 1
+    assert r == w - dep
     assert np.abs(Q.T @ Q - np.eye(r)).max() <= 1e-13
     assert np.linalg.norm(Wm - Q @ (Q.T @ Wm)) <= 1e-9 * np.linalg.norm(Wm)
