@@ -1184,7 +1184,13 @@ __device__ double block_sum_1024(double v, double* sh) {
 
 // Reflectors 0 .. kend - 1 only; when it stops early (kend < m - 2) each
 // workgroup writes its updated rows back to Ag for the kernel that continues.
-__global__ __launch_bounds__(kCoopThreads) void tridiag_coop_kernel(int m, int R, int kend, double* __restrict__ Ag,
+// Works on the trailing block A[k0:, k0:] (order m = mfull - k0) of the
+// mfull x mfull matrix; reflector k of the block is reflector k0 + k of the
+// whole (outputs at the global positions). A launch that stops before the end
+// (kend < m - 2) writes its updated rows back, so that a later launch with
+// fewer workgroups continues on the smaller trailing block.
+__global__ __launch_bounds__(kCoopThreads) void tridiag_coop_kernel(int mfull, int k0, int R, int kend,
+                                                                    double* __restrict__ Ag,
                                                                     double* __restrict__ d, double* __restrict__ e,
                                                                     double* __restrict__ tau,
                                                                     double* __restrict__ Vh,
@@ -1196,12 +1202,20 @@ __global__ __launch_bounds__(kCoopThreads) void tridiag_coop_kernel(int m, int R
     extern __shared__ double lds[];
     __shared__ double sred[kCoopThreads / 64];
     cg::grid_group grid = cg::this_grid();
+    const int m = mfull - k0;
+    d += k0;
+    e += k0;
+    tau += k0;
+    Vh += (size_t)k0 * mfull + k0;  // row stride mfull
     const int g = blockIdx.x, G = gridDim.x, t = threadIdx.x;
     const int r0 = g * R, r1 = min(m, r0 + R), nr = max(0, r1 - r0);
     double* Al = lds;                    // nr x m, row-major
     double* v = Al + (size_t)R * m;      // m
     double* w = v + m;                   // m
-    for (size_t q = t; q < (size_t)nr * m; q += kCoopThreads) Al[q] = Ag[(size_t)r0 * m + q];
+    for (size_t q = t; q < (size_t)nr * m; q += kCoopThreads) {
+        const size_t i = q / m, j = q % m;
+        Al[q] = Ag[(size_t)(k0 + r0 + i) * mfull + k0 + j];
+    }
     __syncthreads();
     const int row_sub = t >> 5, lane32 = t & 31;  // 32 row groups of 32 lanes
     for (int k = 0; k < kend && k + 2 < m; ++k) {
@@ -1237,7 +1251,7 @@ __global__ __launch_bounds__(kCoopThreads) void tridiag_coop_kernel(int m, int R
                 e[k] = beta;
                 tau[k] = tk;
             }
-            for (int i = k + 1 + t; i < m; i += kCoopThreads) Vh[(size_t)k * m + i] = v[i];
+            for (int i = k + 1 + t; i < m; i += kCoopThreads) Vh[(size_t)k * mfull + i] = v[i];
         }
         double pv = 0.0;
         const int rb = max(r0, k + 1);
@@ -1277,7 +1291,10 @@ __global__ __launch_bounds__(kCoopThreads) void tridiag_coop_kernel(int m, int R
         __syncthreads();
     }
     if (kend < m - 2) {
-        for (size_t q = t; q < (size_t)nr * m; q += kCoopThreads) Ag[(size_t)r0 * m + q] = Al[q];
+        for (size_t q = t; q < (size_t)nr * m; q += kCoopThreads) {
+            const size_t i = q / m, j = q % m;
+            Ag[(size_t)(k0 + r0 + i) * mfull + k0 + j] = Al[q];
+        }
         return;
     }
     if (t == 0 && m >= 2) {
@@ -1726,50 +1743,55 @@ hipError_t launch_syev_lowest(hipStream_t st, int m, int k, double* A, double* w
     double* infod = cwork + 2 * mm + 2 * (size_t)m;
     int* infoi = reinterpret_cast<int*>(infod + 8);
     const size_t lds = (mm <= (size_t)kLdsDoubles) ? sizeof(double) * mm : 0;
-    bool done = false;
-    // The cooperative kernel (rows spread over workgroups, in LDS) takes all
-    // reflectors for m > 288 and the first m - kRegOrder ones for smaller m
-    // above kRegOrder; the register kernel takes the trailing block.
-    auto coop = [&](int kend) -> bool {
-        // Rows per workgroup so that R m + 2m doubles fit 150 KB of LDS.
-        const int R = std::max(1, (int)((150 * 1024 / sizeof(double) - 2 * (size_t)m) / m));
-        const int G = (m + R - 1) / R;
+    // Above order 112: the cooperative kernel (rows spread over workgroups, in
+    // LDS) takes the leading reflectors in chunks of kCoopChunk, each chunk
+    // on the current trailing block with as few workgroups as its order
+    // needs (the grid-wide synchronizations of a reflector cost more with more
+    // workgroups); the register kernel takes the last kRegOrder reflectors
+    // (below order 192 the faster per reflector, measured at m = 160 .. 288).
+    auto coop = [&](int k0, int nref) -> bool {
+        const int mt = m - k0;
+        // Rows per workgroup so that R mt + 2 mt doubles fit 150 KB of LDS.
+        const int R = std::max(1, (int)((150 * 1024 / sizeof(double) - 2 * (size_t)mt) / mt));
+        const int G = (mt + R - 1) / R;
         if (G > 128) return false;
         double* xcol = infod + 64;
         double* xp = xcol + m;
         double* partA = xp + m;
         double* partB = partA + 128;
-        const size_t clds = sizeof(double) * ((size_t)R * m + 2 * (size_t)m);
-        int mm_i = m, R_i = R, kend_i = kend;
-        void* args[] = {&mm_i, &R_i, &kend_i, &A, &d, &e, &tau, &Vh, &xcol, &xp, &partA, &partB};
+        const size_t clds = sizeof(double) * ((size_t)R * mt + 2 * (size_t)mt);
+        int mf_i = m, k0_i = k0, R_i = R, kend_i = nref;
+        void* args[] = {&mf_i, &k0_i, &R_i, &kend_i, &A, &d, &e, &tau, &Vh, &xcol, &xp, &partA, &partB};
         const bool ok = hipLaunchCooperativeKernel((void*)tridiag_coop_kernel, dim3(G), dim3(kCoopThreads), args,
                                                    clds, st) == hipSuccess;
         if (!ok) (void)hipGetLastError();  // fall back to the single-workgroup kernels
         return ok;
     };
     constexpr int kRegOrder = 192;
-    if (m > 288) done = coop(m);
-    if (done) {
-    } else if (m <= kWaveTri) {
+    constexpr int kCoopChunk = 64;
+    if (m <= kWaveTri) {
         hipLaunchKernelGGL(tridiag_wave_kernel, dim3(1), dim3(64), 0, st, m, A, d, e, tau, Vh);
     } else if (m <= 112) {
         hipLaunchKernelGGL(tridiag_kernel<true>, dim3(1), dim3(kTri), lds, st, m, m, A, d, e, tau, Vh);
     } else {
-        // the first m - kRegOrder reflectors by the cooperative kernel (or in
-        // L2 by one workgroup), the trailing block in registers: below order
-        // 192 the register kernel is the faster per reflector, above it the
-        // cooperative one (measured at m = 160 .. 288)
-        const int k0 = m > kRegOrder ? m - kRegOrder : 0;
-        if (k0 > 0 && !coop(k0))
+        int k0 = 0;
+        while (m - k0 > kRegOrder) {
+            const int nref = std::min(kCoopChunk, m - k0 - kRegOrder);
+            if (!coop(k0, nref)) break;
+            k0 += nref;
+        }
+        if (m - k0 > kRegOrder) {
+            if (k0 > 0) return hipErrorLaunchFailure;  // a later chunk is never larger than the first
+            // no cooperative launch: the leading reflectors in L2 by one workgroup
+            k0 = m - kRegOrder;
             hipLaunchKernelGGL(tridiag_kernel<false>, dim3(1), dim3(kTri), 0, st, m, k0, A, d, e, tau, Vh);
+        }
         switch ((m - k0 + 15) / 16) {
             case 8: hipLaunchKernelGGL((tridiag_reg_kernel<8, 4>), dim3(1), dim3(512), 0, st, m, k0, A, d, e, tau, Vh); break;
             case 9: hipLaunchKernelGGL((tridiag_reg_kernel<9, 5>), dim3(1), dim3(512), 0, st, m, k0, A, d, e, tau, Vh); break;
             case 10: hipLaunchKernelGGL((tridiag_reg_kernel<10, 5>), dim3(1), dim3(512), 0, st, m, k0, A, d, e, tau, Vh); break;
             case 11: hipLaunchKernelGGL((tridiag_reg_kernel<11, 6>), dim3(1), dim3(512), 0, st, m, k0, A, d, e, tau, Vh); break;
-            case 12: hipLaunchKernelGGL((tridiag_reg_kernel<12, 6>), dim3(1), dim3(512), 0, st, m, k0, A, d, e, tau, Vh); break;
-            case 13: hipLaunchKernelGGL((tridiag_reg_kernel<13, 7>), dim3(1), dim3(512), 0, st, m, k0, A, d, e, tau, Vh); break;
-            default: hipLaunchKernelGGL((tridiag_reg_kernel<14, 7>), dim3(1), dim3(512), 0, st, m, k0, A, d, e, tau, Vh); break;
+            default: hipLaunchKernelGGL((tridiag_reg_kernel<12, 6>), dim3(1), dim3(512), 0, st, m, k0, A, d, e, tau, Vh); break;
         }
     }
     hipLaunchKernelGGL(bisect_kernel, dim3((k + 3) / 4), dim3(256), 0, st, m, k, d, e, w, scal);
