@@ -919,7 +919,9 @@ __device__ __forceinline__ void update_body(int rb, int tn, long long n, const S
     constexpr int BN = 16 * NT;
     constexpr int UQ = (UM * UK) / kThreads;  // U elements per thread per stage (8)
     constexpr int CQ = (UK * BN) / kThreads;  // C elements per thread per stage (2 NT)
-    __shared__ double Us[UK][UM + 4];
+    // odd row stride: the transposing stores of a stage (32 lanes on 32
+    // consecutive k rows, one column) then fall on distinct bank pairs
+    __shared__ double Us[UK][UM + 1];
     __shared__ double Cs[UK][BN + 4];
     const long long r0 = (long long)rb * UM;
     const int n0 = tn * BN;
