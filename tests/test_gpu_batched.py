@@ -180,3 +180,16 @@ def test_tight_budget_runs_requests_one_at_a_time(ctx):
     alone = [_serve(ctx, [r], 1)[0] for r in reqs]
     for a, b in zip(res, alone):
         assert a[2].converged and np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+
+
+def test_widest_block_matches_the_oracle(ctx):
+    """nb = 96, the engine's limit: the gathered W block reaches past 112
+    columns after an expansion (the global-memory Cholesky-QR transform) and
+    the Rayleigh-Ritz order reaches 288 (the register tridiagonalization of
+    the trailing 192 reflectors after the leading ones in L2)."""
+    s = {"dim": 3, "m": 16, "n": 16 ** 3, "n_ev": 64, "n_extra": 32, "pot_seed": 10077}
+    A = W.potential_laplacian(s["m"], s["dim"], 2.0, s["pot_seed"])
+    print("batched: nb = 96", flush=True)
+    (lam, V, info), = _serve(ctx, [(A, s)], 2)
+    assert info.n_shrinks > 0 and info.n_expands > 0
+    _check_against_oracle(A, s, lam, V, info)
