@@ -32,7 +32,9 @@ constexpr int kZNB = 8;     // nonzeros per batch
 
 __device__ __forceinline__ double zwave_sum(double v) {
     for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
-    return __shfl(v, 0, 64);
+    const int lo = __builtin_amdgcn_readlane(__double2loint(v), 0);  // lane 0 to every lane
+    const int hi = __builtin_amdgcn_readlane(__double2hiint(v), 0);
+    return __hiloint2double(hi, lo);
 }
 
 // ---------------------------------------------------------------------------

@@ -20,9 +20,17 @@ constexpr int kTri = 1024;   // threads of the global-memory tridiagonalization
 constexpr int kSWaves = kSmall / 64;
 constexpr int kLdsDoubles = 12800;  // 100 KB of dynamic LDS for an in-LDS matrix
 
+// Value of lane `lane` (wave-uniform) in every lane: two v_readlane_b32,
+// where __shfl goes through the LDS crossbar (ds_bpermute) and its latency.
+__device__ __forceinline__ double bcast_lane(double v, int lane) {
+    const int lo = __builtin_amdgcn_readlane(__double2loint(v), lane);
+    const int hi = __builtin_amdgcn_readlane(__double2hiint(v), lane);
+    return __hiloint2double(hi, lo);
+}
+
 __device__ __forceinline__ double wave_sum(double v) {
     for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
-    return __shfl(v, 0, 64);
+    return bcast_lane(v, 0);
 }
 
 // Workgroup sum in a fixed order; `sh` holds kSWaves doubles. Two barriers.
@@ -277,7 +285,7 @@ __device__ __forceinline__ void chol_drop_blocked_kernel_body(int bx, int a, con
             for (int c = 0; c < kCholPanel; ++c) {
                 if (c < nbw) {
                     const int j = jb + c;
-                    double dj = __shfl(P[0][c], c, 64);
+                    double dj = bcast_lane(P[0][c], c);
                     const bool drop = can_drop && (!(dj > drop_tol2) || s_D[j] == 0.0);
                     if (!can_drop && !(dj > 1e-300)) dj = 1e-300;
                     if (drop) {
@@ -301,7 +309,7 @@ __device__ __forceinline__ void chol_drop_blocked_kernel_body(int bx, int a, con
 #pragma unroll
                         for (int c2 = c + 1; c2 < kCholPanel; ++c2) {
                             if (c2 < nbw) {
-                                const double l2 = __shfl(P[0][c], c2, 64);  // L[jb + c2][j]
+                                const double l2 = bcast_lane(P[0][c], c2);  // L[jb + c2][j]
                                 if (i0 >= jb + c2) P[0][c2] -= P[0][c] * l2;
                                 P[1][c2] -= P[1][c] * l2;
                             }
@@ -570,7 +578,7 @@ __device__ __forceinline__ void tridiag_wave_kernel_body(int bx, int m, const do
         const bool below = l > k && l < m;
         const double xl = below ? A[l * S + k] : 0.0;  // column k under the diagonal
         const double sigma2 = wave_sum((l >= k + 2 && l < m) ? xl * xl : 0.0);
-        const double alpha = __shfl(xl, k + 1, 64);
+        const double alpha = bcast_lane(xl, k + 1);
         double tk = 0.0, beta = alpha, scale = 0.0;
         if (sigma2 > 0.0) {
             beta = -copysign(sqrt(alpha * alpha + sigma2), alpha);
@@ -835,12 +843,12 @@ __device__ __forceinline__ void bisect_kernel_body(int bx, int m, int k, const d
         const unsigned long long mask = __ballot(c > idx);
         double nlo, nhi;
         if (mask == 0ull) {
-            nlo = __shfl(x, 63, 64);
+            nlo = bcast_lane(x, 63);
             nhi = hi;
         } else {
             const int first = __ffsll((long long)mask) - 1;
-            nhi = __shfl(x, first, 64);
-            nlo = (first > 0) ? __shfl(x, first - 1, 64) : lo;
+            nhi = bcast_lane(x, first);
+            nlo = (first > 0) ? bcast_lane(x, first - 1) : lo;
         }
         lo = nlo;
         hi = nhi;
@@ -1500,7 +1508,7 @@ __device__ __forceinline__ void chol_drop_big_body(int a, const double* __restri
             for (int c = 0; c < kCholPanel; ++c) {
                 if (c < nbw) {
                     const int j = jb + c;
-                    double dj = __shfl(P[c], c, 64);
+                    double dj = bcast_lane(P[c], c);
                     const bool drop = can_drop && (!(dj > drop_tol2) || b_D[j] == 0.0);
                     if (!can_drop && !(dj > 1e-300)) dj = 1e-300;
                     if (drop) {
@@ -1522,7 +1530,7 @@ __device__ __forceinline__ void chol_drop_big_body(int a, const double* __restri
 #pragma unroll
                         for (int c2 = c + 1; c2 < kCholPanel; ++c2) {
                             if (c2 < nbw) {
-                                const double l2 = __shfl(P[c], c2, 64);  // L[jb + c2][j]
+                                const double l2 = bcast_lane(P[c], c2);  // L[jb + c2][j]
                                 if (lane >= c2) P[c2] -= P[c] * l2;
                             }
                         }
