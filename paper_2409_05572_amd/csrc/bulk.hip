@@ -392,13 +392,14 @@ hipError_t spmm_launch(hipStream_t st, int n, const int* rowptr, const int* col,
 
 // ---------------------------------------------------------------------------
 // Fixed-order sum of per-chunk partial vectors: out[i] = sum_c part[c * L + i].
-// out[i] = sum_c part[c L + i]. 32 threads per output, 8 outputs per
-// workgroup (consecutive threads take consecutive outputs, so each chunk's
-// read is contiguous): thread g sums chunks g, g + 32, ... in increasing
-// order and a fixed tree combines the 32 sums (deterministic).
+// out[i] = sum_c part[c rs + i] (rs: row stride of the partials, at least L).
+// 32 threads per output, 8 outputs per workgroup (consecutive threads take
+// consecutive outputs, so each chunk's read is contiguous): thread g sums
+// chunks g, g + 32, ... in increasing order and a fixed tree combines the 32
+// sums (deterministic).
 constexpr int kSumG = 32;
 __device__ __forceinline__ void sum_partials_body(int bx, int L, int nchunks, const double* __restrict__ part,
-                                                  double* __restrict__ out) {
+                                                  double* __restrict__ out, long long rs) {
     constexpr int OPB = kThreads / kSumG;
     __shared__ double sh[kThreads];
     const int o = threadIdx.x % OPB, g = threadIdx.x / OPB;
@@ -407,10 +408,10 @@ __device__ __forceinline__ void sum_partials_body(int bx, int L, int nchunks, co
     if (i < L) {
         int c = g;
         for (; c + kSumG < nchunks; c += 2 * kSumG) {
-            s0 += part[(long long)c * L + i];
-            s1 += part[(long long)(c + kSumG) * L + i];
+            s0 += part[(long long)c * rs + i];
+            s1 += part[(long long)(c + kSumG) * rs + i];
         }
-        if (c < nchunks) s0 += part[(long long)c * L + i];
+        if (c < nchunks) s0 += part[(long long)c * rs + i];
     }
     sh[threadIdx.x] = s0 + s1;
     __syncthreads();
@@ -424,8 +425,44 @@ __device__ __forceinline__ void sum_partials_body(int bx, int L, int nchunks, co
 
 __global__ __launch_bounds__(kThreads) void sum_partials_kernel(int L, int nchunks,
                                                                 const double* __restrict__ part,
-                                                                double* __restrict__ out) {
-    sum_partials_body(blockIdx.x, L, nchunks, part, out);
+                                                                double* __restrict__ out, long long rs) {
+    sum_partials_body(blockIdx.x, L, nchunks, part, out, rs);
+}
+
+// First level for many chunks: workgroup (x, y) sums chunks y kSumBlk ..
+// y kSumBlk + kSumBlk - 1 of outputs 16 x .. 16 x + 15 and overwrites that
+// block's first partial row with the result. 16 threads per output, each
+// with four running sums over its chunks g, g + 16, ... (in increasing order,
+// chunk 64 u + 16 q + g into sum q), combined by a fixed tree: the same
+// inputs always give the same bits. Only this workgroup reads the block's
+// rows in these columns, so the write after its last read is safe.
+constexpr int kSumBlk = 512;
+__global__ __launch_bounds__(kThreads) void sum_blocks_kernel(int L, int nchunks, double* __restrict__ part) {
+    constexpr int OPB = 16, G = kThreads / OPB;
+    __shared__ double sh[kThreads];
+    const int o = threadIdx.x % OPB, g = threadIdx.x / OPB;
+    const int i = (int)blockIdx.x * OPB + o;
+    const long long c0 = (long long)blockIdx.y * kSumBlk;
+    const int cn = (int)min((long long)kSumBlk, (long long)nchunks - c0);
+    double s[4] = {0.0, 0.0, 0.0, 0.0};
+    if (i < L) {
+        int c = g;
+        for (; c + 3 * G < cn; c += 4 * G) {
+#pragma unroll
+            for (int q = 0; q < 4; ++q) s[q] += part[(c0 + c + q * G) * L + i];
+        }
+#pragma unroll
+        for (int q = 0; q < 3; ++q)
+            if (c + q * G < cn) s[q] += part[(c0 + c + q * G) * L + i];
+    }
+    sh[threadIdx.x] = (s[0] + s[1]) + (s[2] + s[3]);
+    __syncthreads();
+#pragma unroll
+    for (int h = G / 2; h > 0; h >>= 1) {
+        if (g < h) sh[g * OPB + o] += sh[(g + h) * OPB + o];
+        __syncthreads();
+    }
+    if (g == 0 && i < L) part[c0 * L + i] = sh[o];
 }
 
 // Residual and column norms: per chunk of rows, sum (ax - lam x)^2 and x^2.
@@ -654,13 +691,13 @@ __device__ __forceinline__ void gram_compute(const double (*Ts)[2 * GT + 4], d4 
 // accumulates in slot S0 + q of acc; nv = tile rows/columns holding data.
 template <int I, int J0, int NJ, int S0>
 __device__ __forceinline__ void gram_diag_row(const double (*Ts)[2 * GT + 4], d4 (&acc)[3][3], int ks, int lr,
-                                              int lc, int nv) {
+                                              int lc, int nv, int boff) {
     if (I >= nv) return;
     const double a = Ts[ks + lr][I * 16 + lc];
 #pragma unroll
     for (int q = 0; q < NJ; ++q) {
         if (J0 + q < nv) {
-            const double b = Ts[ks + lr][GT + (J0 + q) * 16 + lc];
+            const double b = Ts[ks + lr][boff + (J0 + q) * 16 + lc];
             acc[(S0 + q) / 3][(S0 + q) % 3] = mfma16(a, b, acc[(S0 + q) / 3][(S0 + q) % 3]);
         }
     }
@@ -668,20 +705,29 @@ __device__ __forceinline__ void gram_diag_row(const double (*Ts)[2 * GT + 4], d4
 
 template <int WV>
 __device__ __forceinline__ void gram_diag_stage(const double (*Ts)[2 * GT + 4], d4 (&acc)[3][3], int lr, int lc,
-                                                int nv) {
+                                                int nv, int boff) {
 #pragma unroll
     for (int ks = 0; ks < GK; ks += 4) {
-        if (WV == 0) gram_diag_row<0, 0, 6, 0>(Ts, acc, ks, lr, lc, nv);
-        if (WV == 1) gram_diag_row<1, 1, 5, 0>(Ts, acc, ks, lr, lc, nv);
+        if (WV == 0) gram_diag_row<0, 0, 6, 0>(Ts, acc, ks, lr, lc, nv, boff);
+        if (WV == 1) gram_diag_row<1, 1, 5, 0>(Ts, acc, ks, lr, lc, nv, boff);
         if (WV == 2) {
-            gram_diag_row<2, 2, 4, 0>(Ts, acc, ks, lr, lc, nv);
-            gram_diag_row<5, 5, 1, 4>(Ts, acc, ks, lr, lc, nv);
+            gram_diag_row<2, 2, 4, 0>(Ts, acc, ks, lr, lc, nv, boff);
+            gram_diag_row<5, 5, 1, 4>(Ts, acc, ks, lr, lc, nv, boff);
         }
         if (WV == 3) {
-            gram_diag_row<3, 3, 3, 0>(Ts, acc, ks, lr, lc, nv);
-            gram_diag_row<4, 4, 2, 3>(Ts, acc, ks, lr, lc, nv);
+            gram_diag_row<3, 3, 3, 0>(Ts, acc, ks, lr, lc, nv, boff);
+            gram_diag_row<4, 4, 2, 3>(Ts, acc, ks, lr, lc, nv, boff);
         }
     }
+}
+
+// U and V are the same blocks (W^T W): a diagonal tile then needs one operand.
+__device__ __forceinline__ bool segs_same(const Segs& A, const Segs& B) {
+    if (A.nseg != B.nseg || A.ld != B.ld) return false;
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+        if (q < A.nseg && (A.p[q] != B.p[q] || A.off[q + 1] != B.off[q + 1])) return false;
+    return true;
 }
 
 // (I, J) of slot s of wave wv in a diagonal tile; false if the slot is unused.
@@ -719,6 +765,10 @@ __device__ __forceinline__ void gram_body(int chunk, int tile, long long n, cons
     const bool diag = sym && ti == tj;
     const int nv = min(6, (mu - cu0 + 15) / 16);
     const int shape = diag ? -1 - wv : niv * 4 + njv;
+    // same operand on a diagonal tile: only the U half is loaded, and the
+    // MFMAs read both operands from it
+    const bool dup = diag && segs_same(U, V);
+    const int boff = dup ? 0 : GT;
 
     // fixed column pointers of this thread (c < 96: U, else V)
     const double* cp[3];
@@ -732,6 +782,7 @@ __device__ __forceinline__ void gram_body(int chunk, int tile, long long n, cons
             cld[q] = U.ld;
         } else {
             cp[q] = seg_col(V, cv0 + c - GT, cok[q]);
+            cok[q] = cok[q] && !dup;
             cld[q] = V.ld;
         }
     }
@@ -776,10 +827,10 @@ __device__ __forceinline__ void gram_body(int chunk, int tile, long long n, cons
             case 7: gram_compute<1, 3>(Ts, acc, lr, lc, wy, wx); break;
             case 6: gram_compute<1, 2>(Ts, acc, lr, lc, wy, wx); break;
             case 5: gram_compute<1, 1>(Ts, acc, lr, lc, wy, wx); break;
-            case -1: gram_diag_stage<0>(Ts, acc, lr, lc, nv); break;
-            case -2: gram_diag_stage<1>(Ts, acc, lr, lc, nv); break;
-            case -3: gram_diag_stage<2>(Ts, acc, lr, lc, nv); break;
-            case -4: gram_diag_stage<3>(Ts, acc, lr, lc, nv); break;
+            case -1: gram_diag_stage<0>(Ts, acc, lr, lc, nv, boff); break;
+            case -2: gram_diag_stage<1>(Ts, acc, lr, lc, nv, boff); break;
+            case -3: gram_diag_stage<2>(Ts, acc, lr, lc, nv, boff); break;
+            case -4: gram_diag_stage<3>(Ts, acc, lr, lc, nv, boff); break;
             default: break;
         }
         __syncthreads();
@@ -1179,11 +1230,18 @@ hipError_t launch_rowmajor_to_colmajor(hipStream_t st, long long n, int w, const
     return hipGetLastError();
 }
 
-hipError_t launch_sum_partials(hipStream_t st, int L, int nchunks, const double* part, double* out) {
+hipError_t launch_sum_partials(hipStream_t st, int L, int nchunks, double* part, double* out) {
     if (L <= 0) return hipSuccess;
     constexpr int OPB = kThreads / kSumG;
+    long long rs = L;
+    if (nchunks > 2 * kSumBlk) {  // two levels: block sums first, in place
+        const int nb = (nchunks + kSumBlk - 1) / kSumBlk;
+        hipLaunchKernelGGL(sum_blocks_kernel, dim3((L + 15) / 16, nb), dim3(kThreads), 0, st, L, nchunks, part);
+        nchunks = nb;
+        rs = (long long)kSumBlk * L;
+    }
     hipLaunchKernelGGL(sum_partials_kernel, dim3((L + OPB - 1) / OPB), dim3(kThreads), 0, st, L, nchunks, part,
-                       out);
+                       out, rs);
     return hipGetLastError();
 }
 
@@ -1405,7 +1463,7 @@ __global__ __launch_bounds__(kThreads) void resid_sum_batched_kernel(const BResi
     for (int it = blockIdx.x; it < total; it += gridDim.x) {
         const int j = item_job(it, nj, s_start);
         const BResidJob& J = jobs[j];
-        sum_partials_body(it - s_start[j], 2 * J.k, J.nchunks, J.part, J.out);
+        sum_partials_body(it - s_start[j], 2 * J.k, J.nchunks, J.part, J.out, 2 * J.k);
         __syncthreads();
     }
 }

@@ -257,7 +257,9 @@ hipError_t launch_update(hipStream_t st, long long n, const Segs& U, const doubl
                          const Segs& Out, double alpha, double beta);
 
 // Fixed-order sum of per-chunk partial vectors: out[i] = sum_c part[c L + i].
-hipError_t launch_sum_partials(hipStream_t st, int L, int nchunks, const double* part, double* out);
+// part is scratch: with more than 1024 chunks, block sums overwrite some of
+// its rows.
+hipError_t launch_sum_partials(hipStream_t st, int L, int nchunks, double* part, double* out);
 
 // Gram output tile (columns of U and of V per workgroup) and rows per stage,
 // shared by the FP64 and low-precision Gram kernels.
