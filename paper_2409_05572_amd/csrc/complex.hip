@@ -30,11 +30,26 @@ constexpr int kZThreads = 256;
 constexpr int kZRows = 32;  // rows per wave of the complex CSR product
 constexpr int kZNB = 8;     // nonzeros per batch
 
-__device__ __forceinline__ double zwave_sum(double v) {
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
-    const int lo = __builtin_amdgcn_readlane(__double2loint(v), 0);  // lane 0 to every lane
-    const int hi = __builtin_amdgcn_readlane(__double2hiint(v), 0);
+// Sum over the 64 lanes, in every lane (whole wave active): DPP butterflies
+// within each row of 16 lanes (quad_perm 1,0,3,2 and 2,3,0,1, half-row mirror,
+// row mirror), then the four row sums by v_readlane in a fixed order.
+template <int CTRL>
+__device__ __forceinline__ double zdpp(double v) {
+    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xF, 0xF, false);
     return __hiloint2double(hi, lo);
+}
+__device__ __forceinline__ double zlane(double v, int lane) {
+    const int lo = __builtin_amdgcn_readlane(__double2loint(v), lane);
+    const int hi = __builtin_amdgcn_readlane(__double2hiint(v), lane);
+    return __hiloint2double(hi, lo);
+}
+__device__ __forceinline__ double zwave_sum(double v) {
+    v += zdpp<0xB1>(v);
+    v += zdpp<0x4E>(v);
+    v += zdpp<0x141>(v);
+    v += zdpp<0x140>(v);
+    return (zlane(v, 0) + zlane(v, 16)) + (zlane(v, 32) + zlane(v, 48));
 }
 
 // ---------------------------------------------------------------------------

@@ -28,9 +28,25 @@ __device__ __forceinline__ double bcast_lane(double v, int lane) {
     return __hiloint2double(hi, lo);
 }
 
+// Lane-permuted copy of v by a DPP move of each 32-bit half (no LDS).
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double v) {
+    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xF, 0xF, false);
+    return __hiloint2double(hi, lo);
+}
+
+// Sum over the 64 lanes, in every lane; the whole wave must be active. Within
+// each row of 16 lanes: swap neighbours (quad_perm 1,0,3,2), then pairs
+// (quad_perm 2,3,0,1), then the half-row mirror and the row mirror, after
+// which every lane holds its row's sum; the four row sums are read with
+// v_readlane and added in a fixed order (deterministic).
 __device__ __forceinline__ double wave_sum(double v) {
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
-    return bcast_lane(v, 0);
+    v += dpp_f64<0xB1>(v);
+    v += dpp_f64<0x4E>(v);
+    v += dpp_f64<0x141>(v);
+    v += dpp_f64<0x140>(v);
+    return (bcast_lane(v, 0) + bcast_lane(v, 16)) + (bcast_lane(v, 32) + bcast_lane(v, 48));
 }
 
 // Workgroup sum in a fixed order; `sh` holds kSWaves doubles. Two barriers.
@@ -684,15 +700,24 @@ __device__ __forceinline__ void tridiag_reg_kernel_body(int bx, int mfull, int k
     for (int k = 0; k + 2 < m; ++k) {
         const int par = k & 1;
         const int kj = k >> 5;
-        // (1) column k (all owned rows) and the diagonal element
+        // (1) column k (all owned rows) and the diagonal element; kj is
+        // uniform, so the register column is chosen by a scalar branch
         if (tx == (k & 31)) {
-#pragma unroll
-            for (int i = 0; i < RR; ++i) {
-                double x = 0.0;
-#pragma unroll
-                for (int j = 0; j < RC; ++j) x = (j == kj) ? a[i][j] : x;
-                sx[par][16 * i + ty] = x;
-                if (16 * i + ty == k) d[k] = x;
+            switch (kj) {
+#define SE_REG_PUB(J)                                              \
+    case J:                                                        \
+        if (J < RC) {                                              \
+            _Pragma("unroll") for (int i = 0; i < RR; ++i) {       \
+                const double x = a[i][J < RC ? J : 0];             \
+                sx[par][16 * i + ty] = x;                          \
+                if (16 * i + ty == k) d[k] = x;                    \
+            }                                                      \
+        }                                                          \
+        break;
+                SE_REG_PUB(0) SE_REG_PUB(1) SE_REG_PUB(2) SE_REG_PUB(3)
+                SE_REG_PUB(4) SE_REG_PUB(5) SE_REG_PUB(6) SE_REG_PUB(7)
+#undef SE_REG_PUB
+                default: break;
             }
         }
         __syncthreads();
@@ -757,7 +782,7 @@ __device__ __forceinline__ void tridiag_reg_kernel_body(int bx, int mfull, int k
             const double vr = (r == k + 1) ? 1.0 : ((r > k + 1 && r < m) ? xs : 0.0);
             const double wr = sp[par][r] - Kc * vr;
 #pragma unroll
-            for (int j = 0; j < RC; ++j) a[i][j] -= vr * wc[j] + wr * vc[j];
+            for (int j = 0; j < RC; ++j) a[i][j] = fma(-wr, vc[j], fma(-vr, wc[j], a[i][j]));
         }
     }
     // last 2 x 2 block
