@@ -244,7 +244,7 @@ __device__ __forceinline__ void chol_drop_blocked_kernel_body(int bx, int a, con
     __shared__ int s_kept[kCholBlk];
     __shared__ double s_D[kCholBlk];
     __shared__ double s_dl[kCholBlk];  // diagonal of L (0 where dropped)
-    __shared__ double s_di[kCholBlk];  // diagonal of L^{-1} (1 where dropped)
+    __shared__ double s_dm[kCholBlk];  // diagonal of the modified L (1 where dropped)
     __shared__ double s_tmp[(kCholBlk / kCholPanel) * kCholPanel * kCholPanel];
     __shared__ double s_red[kSWaves];
     __shared__ double s_minpiv;
@@ -375,13 +375,18 @@ __device__ __forceinline__ void chol_drop_blocked_kernel_body(int bx, int a, con
     const int r = s_r;
 
     // ---- inverse of the modified L by 16 x 16 blocks ----
-    // Lm(i, j): L over kept rows and columns, identity on dropped ones.
-    auto Lm = [&](int i, int j) -> double {
-        if (s_pos[i] < 0 || s_pos[j] < 0) return (i == j) ? 1.0 : 0.0;
-        return (i == j) ? s_dl[i] : F[i * FS + j];
-    };
-    // Linv(i, j), i >= j: diagonal in s_di, below it stored transposed at F[j][i]
-    auto Li = [&](int i, int j) -> double { return (i == j) ? s_di[i] : F[j * FS + i]; };
+    // Lm: L over kept rows and columns, identity on dropped ones. Dropped
+    // columns are already zero below the diagonal; the rows of dropped
+    // columns are zeroed here and the diagonal of Lm goes to s_dm, so that
+    // every strictly lower Lm(i, j) is the plain LDS read F[i][j].
+    for (int i = t; i < a; i += nth) s_dm[i] = (s_pos[i] < 0) ? 1.0 : s_dl[i];
+    for (int e = t; e < a * a; e += nth) {
+        const int i = e / a, j = e % a;
+        if (j < i && s_pos[i] < 0) F[i * FS + j] = 0.0;
+    }
+    __syncthreads();
+    // Linv(i, j), i >= j, is stored transposed at F[j][i] (its diagonal on
+    // F's diagonal, which Lm no longer needs).
     const int nbk = (a + kCholPanel - 1) / kCholPanel;
     // diagonal blocks: wave b inverts block b, lane c forms column c by
     // forward substitution
@@ -397,16 +402,14 @@ __device__ __forceinline__ void chol_drop_blocked_kernel_body(int bx, int a, con
                     double sacc = (rr == c) ? 1.0 : 0.0;
 #pragma unroll
                     for (int q = 0; q < kCholPanel; ++q)
-                        if (q >= c && q < rr) sacc -= Lm(b0 + rr, b0 + q) * x[q];
-                    v = sacc / Lm(b0 + rr, b0 + rr);
+                        if (q >= c && q < rr) sacc -= F[(b0 + rr) * FS + b0 + q] * x[q];
+                    v = sacc / s_dm[b0 + rr];
                 }
                 x[rr] = v;
             }
 #pragma unroll
-            for (int rr = 0; rr < kCholPanel; ++rr) {
-                if (rr < bs && rr == c) s_di[b0 + c] = x[rr];
-                if (rr < bs && rr > c) F[(b0 + c) * FS + b0 + rr] = x[rr];
-            }
+            for (int rr = 0; rr < kCholPanel; ++rr)
+                if (rr < bs && rr >= c) F[(b0 + c) * FS + b0 + rr] = x[rr];
         }
     }
     __syncthreads();
@@ -419,7 +422,9 @@ __device__ __forceinline__ void chol_drop_blocked_kernel_body(int bx, int a, con
             const int gi = I * kCholPanel + rr, gj = J * kCholPanel + cc;
             double sacc = 0.0;
             if (gi < a) {
-                for (int gk = gj; gk < I * kCholPanel; ++gk) sacc = fma(Lm(gi, gk), Li(gk, gj), sacc);
+                const double* li = F + (size_t)gi * FS;
+                const double* lj = F + (size_t)gj * FS;
+                for (int gk = gj; gk < I * kCholPanel; ++gk) sacc = fma(li[gk], lj[gk], sacc);
             }
             s_tmp[e] = sacc;
         }
@@ -431,7 +436,8 @@ __device__ __forceinline__ void chol_drop_blocked_kernel_body(int bx, int a, con
             if (gi >= a) continue;
             double sacc = 0.0;
             for (int q = 0; q <= rr; ++q)
-                sacc = fma(Li(gi, I * kCholPanel + q), s_tmp[J * kCholPanel * kCholPanel + q * kCholPanel + cc], sacc);
+                sacc = fma(F[(I * kCholPanel + q) * FS + gi], s_tmp[J * kCholPanel * kCholPanel + q * kCholPanel + cc],
+                           sacc);
             F[gj * FS + gi] = -sacc;
         }
         __syncthreads();
@@ -441,10 +447,7 @@ __device__ __forceinline__ void chol_drop_blocked_kernel_body(int bx, int a, con
         const int i = e / r, q = e % r;
         const int p = s_pos[i];
         double v = 0.0;
-        if (p >= 0 && p <= q) {
-            const int kq = s_kept[q];
-            v = s_D[i] * ((i == kq) ? s_di[i] : F[i * FS + kq]);
-        }
+        if (p >= 0 && p <= q) v = s_D[i] * F[i * FS + s_kept[q]];
         T[e] = v;
     }
 }
