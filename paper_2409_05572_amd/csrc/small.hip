@@ -1483,7 +1483,7 @@ __device__ __forceinline__ void chol_drop_big_body(int a, const double* __restri
     __shared__ int b_kept[kCholBig];
     __shared__ double b_D[kCholBig];
     __shared__ double b_dl[kCholBig];  // diagonal of L (0 where dropped)
-    __shared__ double b_di[kCholBig];  // diagonal of L^{-1} (1 where dropped)
+    __shared__ double b_dm[kCholBig];  // diagonal of the modified L (1 where dropped)
     __shared__ double b_red[kSWaves];
     __shared__ double b_minpiv;
     __shared__ int b_r;
@@ -1634,12 +1634,16 @@ __device__ __forceinline__ void chol_drop_big_body(int a, const double* __restri
     const int r = b_r;
 
     // inverse of the modified L (identity on dropped rows and columns) by
-    // 16 x 16 blocks; L^{-1} below the diagonal is stored transposed at F[j][i]
-    auto Lm = [&](int i, int j) -> double {
-        if (b_pos[i] < 0 || b_pos[j] < 0) return (i == j) ? 1.0 : 0.0;
-        return (i == j) ? b_dl[i] : F[(size_t)i * FS + j];
-    };
-    auto Li = [&](int i, int j) -> double { return (i == j) ? b_di[i] : F[(size_t)j * FS + i]; };
+    // 16 x 16 blocks. Dropped columns are already zero below the diagonal;
+    // the rows of dropped columns are zeroed here and the modified diagonal
+    // goes to b_dm, so every strictly lower entry is a plain read of F.
+    // L^{-1} is stored transposed at F[j][i], its diagonal on F's diagonal.
+    for (int i = t; i < a; i += nth) b_dm[i] = (b_pos[i] < 0) ? 1.0 : b_dl[i];
+    for (int e = t; e < a * a; e += nth) {
+        const int i = e / a, j = e % a;
+        if (j < i && b_pos[i] < 0) F[(size_t)i * FS + j] = 0.0;
+    }
+    __syncthreads();
     const int nbk = (a + kCholPanel - 1) / kCholPanel;
     for (int b = wid; b < nbk; b += nwave) {
         const int b0 = b * kCholPanel, bs = min(kCholPanel, a - b0);
@@ -1653,16 +1657,14 @@ __device__ __forceinline__ void chol_drop_big_body(int a, const double* __restri
                     double sacc = (rr == c) ? 1.0 : 0.0;
 #pragma unroll
                     for (int q = 0; q < kCholPanel; ++q)
-                        if (q >= c && q < rr) sacc -= Lm(b0 + rr, b0 + q) * x[q];
-                    v = sacc / Lm(b0 + rr, b0 + rr);
+                        if (q >= c && q < rr) sacc -= F[(size_t)(b0 + rr) * FS + b0 + q] * x[q];
+                    v = sacc / b_dm[b0 + rr];
                 }
                 x[rr] = v;
             }
 #pragma unroll
-            for (int rr = 0; rr < kCholPanel; ++rr) {
-                if (rr < bs && rr == c) b_di[b0 + c] = x[rr];
-                if (rr < bs && rr > c) F[(size_t)(b0 + c) * FS + b0 + rr] = x[rr];
-            }
+            for (int rr = 0; rr < kCholPanel; ++rr)
+                if (rr < bs && rr >= c) F[(size_t)(b0 + c) * FS + b0 + rr] = x[rr];
         }
     }
     __syncthreads();
@@ -1674,7 +1676,9 @@ __device__ __forceinline__ void chol_drop_big_body(int a, const double* __restri
             const int gi = I * kCholPanel + rr, gj = J * kCholPanel + cc;
             double sacc = 0.0;
             if (gi < a) {
-                for (int gk = gj; gk < I * kCholPanel; ++gk) sacc = fma(Lm(gi, gk), Li(gk, gj), sacc);
+                const double* li = F + (size_t)gi * FS;
+                const double* lj = F + (size_t)gj * FS;
+                for (int gk = gj; gk < I * kCholPanel; ++gk) sacc = fma(li[gk], lj[gk], sacc);
             }
             tmp[e] = sacc;
         }
@@ -1686,7 +1690,8 @@ __device__ __forceinline__ void chol_drop_big_body(int a, const double* __restri
             if (gi >= a) continue;
             double sacc = 0.0;
             for (int q = 0; q <= rr; ++q)
-                sacc = fma(Li(gi, I * kCholPanel + q), tmp[J * kCholPanel * kCholPanel + q * kCholPanel + cc], sacc);
+                sacc = fma(F[(size_t)(I * kCholPanel + q) * FS + gi],
+                           tmp[J * kCholPanel * kCholPanel + q * kCholPanel + cc], sacc);
             F[(size_t)gj * FS + gi] = -sacc;
         }
         __syncthreads();
@@ -1695,10 +1700,7 @@ __device__ __forceinline__ void chol_drop_big_body(int a, const double* __restri
         const int i = e / r, q = e % r;
         const int p = b_pos[i];
         double v = 0.0;
-        if (p >= 0 && p <= q) {
-            const int kq = b_kept[q];
-            v = b_D[i] * ((i == kq) ? b_di[i] : F[(size_t)i * FS + kq]);
-        }
+        if (p >= 0 && p <= q) v = b_D[i] * F[(size_t)i * FS + b_kept[q]];
         T[e] = v;
     }
 }
