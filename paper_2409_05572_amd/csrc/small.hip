@@ -422,9 +422,33 @@ __device__ __forceinline__ void chol_drop_blocked_kernel_body(int bx, int a, con
             const int gi = I * kCholPanel + rr, gj = J * kCholPanel + cc;
             double sacc = 0.0;
             if (gi < a) {
+                // reads of 8 steps issued before their FMAs (same order of the sum)
                 const double* li = F + (size_t)gi * FS;
                 const double* lj = F + (size_t)gj * FS;
-                for (int gk = gj; gk < I * kCholPanel; ++gk) sacc = fma(li[gk], lj[gk], sacc);
+                const int gend = I * kCholPanel;
+                int gk = gj;
+                for (; gk + 8 <= gend; gk += 8) {
+                    double lv[8], xv[8];
+#pragma unroll
+                    for (int u = 0; u < 8; ++u) {
+                        lv[u] = li[gk + u];
+                        xv[u] = lj[gk + u];
+                    }
+#pragma unroll
+                    for (int u = 0; u < 8; ++u) sacc = fma(lv[u], xv[u], sacc);
+                }
+                if (gk < gend) {  // fewer than 8 steps left
+                    double lv[8], xv[8];
+#pragma unroll
+                    for (int u = 0; u < 8; ++u) {
+                        const bool ok = gk + u < gend;
+                        lv[u] = ok ? li[gk + u] : 0.0;
+                        xv[u] = ok ? lj[gk + u] : 0.0;
+                    }
+#pragma unroll
+                    for (int u = 0; u < 8; ++u)
+                        if (gk + u < gend) sacc = fma(lv[u], xv[u], sacc);
+                }
             }
             s_tmp[e] = sacc;
         }
@@ -434,10 +458,18 @@ __device__ __forceinline__ void chol_drop_blocked_kernel_body(int bx, int a, con
             const int rr = (e / kCholPanel) % kCholPanel, cc = e % kCholPanel;
             const int gi = I * kCholPanel + rr, gj = J * kCholPanel + cc;
             if (gi >= a) continue;
+            // the rr + 1 <= 16 terms read first, then summed in order
+            double xv[kCholPanel], tv[kCholPanel];
+#pragma unroll
+            for (int q = 0; q < kCholPanel; ++q) {
+                const bool ok = q <= rr;
+                xv[q] = ok ? F[(I * kCholPanel + q) * FS + gi] : 0.0;
+                tv[q] = ok ? s_tmp[J * kCholPanel * kCholPanel + q * kCholPanel + cc] : 0.0;
+            }
             double sacc = 0.0;
-            for (int q = 0; q <= rr; ++q)
-                sacc = fma(F[(I * kCholPanel + q) * FS + gi], s_tmp[J * kCholPanel * kCholPanel + q * kCholPanel + cc],
-                           sacc);
+#pragma unroll
+            for (int q = 0; q < kCholPanel; ++q)
+                if (q <= rr) sacc = fma(xv[q], tv[q], sacc);
             F[gj * FS + gi] = -sacc;
         }
         __syncthreads();
@@ -1491,7 +1523,6 @@ __device__ __forceinline__ void chol_drop_big_body(int a, const double* __restri
     const int nth = blockDim.x;
     const int FS = a | 1;
     double* F = work;
-    double* tmp = work + (size_t)a * FS;
     const bool can_drop = drop_tol2 >= 0.0;
     const int lane = t & 63, wid = t >> 6, nwave = nth >> 6;
     if (ns_tol > 0.0) {
@@ -1602,16 +1633,30 @@ __device__ __forceinline__ void chol_drop_big_body(int a, const double* __restri
             }
         }
         __syncthreads();
-        // trailing update: F[i][i2] -= sum_c L[i][jb + c] L[i2][jb + c], t0 <= i2 <= i
-        for (int i = t0 + wid; i < a; i += nwave) {
-            double li[kCholPanel];
+        // trailing update: F[i][i2] -= sum_c L[i][jb + c] L[i2][jb + c], t0 <= i2 <= i.
+        // A wave takes rows i and i + nwave together, so the read-modify-writes
+        // of F (in L2) of the two rows overlap and each panel row read from
+        // LDS serves both.
+        for (int i = t0 + wid; i < a; i += 2 * nwave) {
+            const int ib = i + nwave;
+            const bool two = ib < a;
+            double li[kCholPanel], lb[kCholPanel];
 #pragma unroll
-            for (int c = 0; c < kCholPanel; ++c) li[c] = lp[i * kBigLP + c];
-            for (int i2 = t0 + lane; i2 <= i; i2 += 64) {
-                double sacc = 0.0;
+            for (int c = 0; c < kCholPanel; ++c) {
+                li[c] = lp[i * kBigLP + c];
+                lb[c] = two ? lp[ib * kBigLP + c] : 0.0;
+            }
+            const int iend = two ? ib : i;
+            for (int i2 = t0 + lane; i2 <= iend; i2 += 64) {
+                double s1 = 0.0, s2 = 0.0;
 #pragma unroll
-                for (int c = 0; c < kCholPanel; ++c) sacc = fma(li[c], lp[i2 * kBigLP + c], sacc);
-                F[(size_t)i * FS + i2] -= sacc;
+                for (int c = 0; c < kCholPanel; ++c) {
+                    const double l2 = lp[i2 * kBigLP + c];
+                    s1 = fma(li[c], l2, s1);
+                    s2 = fma(lb[c], l2, s2);
+                }
+                if (i2 <= i) F[(size_t)i * FS + i2] -= s1;
+                if (two) F[(size_t)ib * FS + i2] -= s2;
             }
         }
         __syncthreads();
@@ -1637,13 +1682,19 @@ __device__ __forceinline__ void chol_drop_big_body(int a, const double* __restri
     // 16 x 16 blocks. Dropped columns are already zero below the diagonal;
     // the rows of dropped columns are zeroed here and the modified diagonal
     // goes to b_dm, so every strictly lower entry is a plain read of F.
-    // L^{-1} is stored transposed at F[j][i], its diagonal on F's diagonal.
     for (int i = t; i < a; i += nth) b_dm[i] = (b_pos[i] < 0) ? 1.0 : b_dl[i];
     for (int e = t; e < a * a; e += nth) {
         const int i = e / a, j = e % a;
         if (j < i && b_pos[i] < 0) F[(size_t)i * FS + j] = 0.0;
     }
     __syncthreads();
+    // X = Lm^{-1}, lower part, row-major in its own array after F (work holds
+    // a (a | 1) + a^2 <= 2 a^2 + 2 a doubles): the block products read it
+    // along rows, so the lanes of a wave (consecutive columns) read
+    // consecutive addresses. Their partial sums use the panel's LDS rows,
+    // free once the factorization is done ((nbk - 1) 256 <= a kBigLP).
+    double* X = F + (size_t)a * FS;
+    double* tmp = lp;
     const int nbk = (a + kCholPanel - 1) / kCholPanel;
     for (int b = wid; b < nbk; b += nwave) {
         const int b0 = b * kCholPanel, bs = min(kCholPanel, a - b0);
@@ -1664,7 +1715,7 @@ __device__ __forceinline__ void chol_drop_big_body(int a, const double* __restri
             }
 #pragma unroll
             for (int rr = 0; rr < kCholPanel; ++rr)
-                if (rr < bs && rr >= c) F[(size_t)(b0 + c) * FS + b0 + rr] = x[rr];
+                if (rr < bs && rr >= c) X[(size_t)(b0 + rr) * a + b0 + c] = x[rr];
         }
     }
     __syncthreads();
@@ -1676,9 +1727,32 @@ __device__ __forceinline__ void chol_drop_big_body(int a, const double* __restri
             const int gi = I * kCholPanel + rr, gj = J * kCholPanel + cc;
             double sacc = 0.0;
             if (gi < a) {
+                // loads of 8 steps issued before their FMAs (same order of the sum)
                 const double* li = F + (size_t)gi * FS;
-                const double* lj = F + (size_t)gj * FS;
-                for (int gk = gj; gk < I * kCholPanel; ++gk) sacc = fma(li[gk], lj[gk], sacc);
+                const int gend = I * kCholPanel;
+                int gk = gj;
+                for (; gk + 8 <= gend; gk += 8) {
+                    double lv[8], xv[8];
+#pragma unroll
+                    for (int u = 0; u < 8; ++u) {
+                        lv[u] = li[gk + u];
+                        xv[u] = X[(size_t)(gk + u) * a + gj];
+                    }
+#pragma unroll
+                    for (int u = 0; u < 8; ++u) sacc = fma(lv[u], xv[u], sacc);
+                }
+                if (gk < gend) {  // fewer than 8 steps left
+                    double lv[8], xv[8];
+#pragma unroll
+                    for (int u = 0; u < 8; ++u) {
+                        const bool ok = gk + u < gend;
+                        lv[u] = ok ? li[gk + u] : 0.0;
+                        xv[u] = ok ? X[(size_t)(gk + u) * a + gj] : 0.0;
+                    }
+#pragma unroll
+                    for (int u = 0; u < 8; ++u)
+                        if (gk + u < gend) sacc = fma(lv[u], xv[u], sacc);
+                }
             }
             tmp[e] = sacc;
         }
@@ -1688,11 +1762,19 @@ __device__ __forceinline__ void chol_drop_big_body(int a, const double* __restri
             const int rr = (e / kCholPanel) % kCholPanel, cc = e % kCholPanel;
             const int gi = I * kCholPanel + rr, gj = J * kCholPanel + cc;
             if (gi >= a) continue;
+            // the rr + 1 <= 16 terms loaded first, then summed in order
+            double xv[kCholPanel], tv[kCholPanel];
+#pragma unroll
+            for (int q = 0; q < kCholPanel; ++q) {
+                const bool ok = q <= rr;
+                xv[q] = ok ? X[(size_t)gi * a + I * kCholPanel + q] : 0.0;
+                tv[q] = ok ? tmp[J * kCholPanel * kCholPanel + q * kCholPanel + cc] : 0.0;
+            }
             double sacc = 0.0;
-            for (int q = 0; q <= rr; ++q)
-                sacc = fma(F[(size_t)(I * kCholPanel + q) * FS + gi],
-                           tmp[J * kCholPanel * kCholPanel + q * kCholPanel + cc], sacc);
-            F[(size_t)gj * FS + gi] = -sacc;
+#pragma unroll
+            for (int q = 0; q < kCholPanel; ++q)
+                if (q <= rr) sacc = fma(xv[q], tv[q], sacc);
+            X[(size_t)gi * a + gj] = -sacc;
         }
         __syncthreads();
     }
@@ -1700,7 +1782,7 @@ __device__ __forceinline__ void chol_drop_big_body(int a, const double* __restri
         const int i = e / r, q = e % r;
         const int p = b_pos[i];
         double v = 0.0;
-        if (p >= 0 && p <= q) v = b_D[i] * F[(size_t)i * FS + b_kept[q]];
+        if (p >= 0 && p <= q) v = b_D[i] * X[(size_t)b_kept[q] * a + i];
         T[e] = v;
     }
 }
