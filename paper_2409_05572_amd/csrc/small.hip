@@ -36,6 +36,14 @@ __device__ __forceinline__ double dpp_f64(double v) {
     return __hiloint2double(hi, lo);
 }
 
+// row_bcast15: rows 1 and 3 of the wave receive lane 15 of rows 0 and 2;
+// rows 0 and 2 receive zero (the DPP write is masked and `old` is 0).
+__device__ __forceinline__ double dpp_row_bcast15(double v) {
+    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), 0x142, 0xA, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), 0x142, 0xA, 0xF, false);
+    return __hiloint2double(hi, lo);
+}
+
 // Sum over the 64 lanes, in every lane; the whole wave must be active. Within
 // each row of 16 lanes: swap neighbours (quad_perm 1,0,3,2), then pairs
 // (quad_perm 2,3,0,1), then the half-row mirror and the row mirror, after
@@ -1362,9 +1370,15 @@ __global__ __launch_bounds__(kCoopThreads) void tridiag_coop_kernel(int mfull, i
                 const double* arow = Al + (size_t)(i - r0) * m;
                 for (int j = k + 1 + lane32; j < m; j += 32) acc = fma(arow[j], v[j], acc);
             }
-#pragma unroll
-            for (int o = 16; o > 0; o >>= 1) acc += __shfl_down(acc, o, 32);
-            if (lane32 == 0 && i < r1) {
+            // sum over the 32 lanes of the row group: DPP butterflies within
+            // each row of 16 lanes, then row_bcast15 adds row 0's (2's) sum
+            // into row 1 (3), so lane 31 of the group holds the total
+            acc += dpp_f64<0xB1>(acc);
+            acc += dpp_f64<0x4E>(acc);
+            acc += dpp_f64<0x141>(acc);
+            acc += dpp_f64<0x140>(acc);
+            acc += dpp_row_bcast15(acc);
+            if (lane32 == 31 && i < r1) {
                 const double pi = tk * acc;
                 w[i] = pi;
                 pv = fma(pi, v[i], pv);
