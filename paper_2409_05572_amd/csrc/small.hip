@@ -1342,8 +1342,12 @@ __global__ __launch_bounds__(kCoopThreads) void tridiag_coop_kernel(int mfull, i
         }
         coop_grid_barrier(ctr, target);
         // B: scalars, v, p = tau A22 v on my rows
-        double sigma2 = 0.0;
-        for (int q = 0; q < G; ++q) sigma2 += partA[q];
+        // the G <= 128 partial sums: at most two per lane, then a wave sum
+        // (one round trip to L2 instead of G dependent ones)
+        const int lane = t & 63;
+        double sa = 0.0;
+        for (int q = lane; q < G; q += 64) sa += partA[q];
+        const double sigma2 = wave_sum(sa);
         const double alpha = xcol[k + 1];
         double tk = 0.0, beta = alpha, scale = 0.0;
         if (sigma2 > 0.0) {
@@ -1392,9 +1396,9 @@ __global__ __launch_bounds__(kCoopThreads) void tridiag_coop_kernel(int mfull, i
         coop_grid_barrier(ctr, target);
         // C: w = p - K v and the rank-2 update of my rows
         if (tk != 0.0) {
-            double pvs = 0.0;
-            for (int q = 0; q < G; ++q) pvs += partB[q];
-            const double Kc = 0.5 * tk * pvs;
+            double sb = 0.0;
+            for (int q = lane; q < G; q += 64) sb += partB[q];
+            const double Kc = 0.5 * tk * wave_sum(sb);
             for (int j = k + 1 + t; j < m; j += kCoopThreads) w[j] = xp[j] - Kc * v[j];
             __syncthreads();
             // 32 x 32 thread tile over (my rows, columns > k)
