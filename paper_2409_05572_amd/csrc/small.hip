@@ -874,20 +874,45 @@ __device__ __forceinline__ void bisect_kernel_body(int bx, int m, int k, const d
                                                      double* __restrict__ scal) {
     __shared__ double d[1024];
     __shared__ double e2[1024];
+    __shared__ double ae[1024];
+    __shared__ double s_lo[256], s_hi[256], s_em[256];
     __shared__ double s_gl[1], s_gu[1], s_pm[1];
-    for (int i = threadIdx.x; i < m; i += 256) {
+    const int tt = threadIdx.x;
+    for (int i = tt; i < m; i += 256) {
         d[i] = dg[i];
-        if (i + 1 < m) e2[i] = eg[i] * eg[i];
+        if (i + 1 < m) {
+            const double ei = eg[i];
+            e2[i] = ei * ei;
+            ae[i] = fabs(ei);
+        }
     }
     __syncthreads();
-    if (threadIdx.x == 0) {
+    // Gershgorin bounds and the largest e^2 by all threads (min and max are
+    // exact in any order, so this equals the sequential scan)
+    {
         double gl = DBL_MAX, gu = -DBL_MAX, emax2 = 0.0;
-        for (int i = 0; i < m; ++i) {
-            const double ea = (i > 0 ? fabs(eg[i - 1]) : 0.0) + (i + 1 < m ? fabs(eg[i]) : 0.0);
+        for (int i = tt; i < m; i += 256) {
+            const double ea = (i > 0 ? ae[i - 1] : 0.0) + (i + 1 < m ? ae[i] : 0.0);
             gl = fmin(gl, d[i] - ea);
             gu = fmax(gu, d[i] + ea);
             if (i + 1 < m) emax2 = fmax(emax2, e2[i]);
         }
+        s_lo[tt] = gl;
+        s_hi[tt] = gu;
+        s_em[tt] = emax2;
+    }
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+        if (tt < h) {
+            s_lo[tt] = fmin(s_lo[tt], s_lo[tt + h]);
+            s_hi[tt] = fmax(s_hi[tt], s_hi[tt + h]);
+            s_em[tt] = fmax(s_em[tt], s_em[tt + h]);
+        }
+        __syncthreads();
+    }
+    if (tt == 0) {
+        double gl = s_lo[0], gu = s_hi[0];
+        const double emax2 = s_em[0];
         const double pivmin = DBL_MIN * fmax(1.0, emax2);
         const double tnorm = fmax(fabs(gl), fabs(gu));
         gl -= 2.0 * DBL_EPSILON * tnorm * m + 4.0 * pivmin;
