@@ -296,10 +296,11 @@ def test_syev_lowest_degenerate_clusters(ctx, g, extra, k):
     assert np.abs(Z.T @ Z - np.eye(k)).max() <= 1e-12
 
 
-@pytest.mark.parametrize("w", [24, 130, 250])
+@pytest.mark.parametrize("w", [24, 130, 250, 500, 896])
 def test_cholqr_orthonormalizes_and_drops_dependent_columns(ctx, w):
-    """Widths up to 112 take the in-LDS blocked transform, wider ones the
-    blocked transform in global memory; both drop the dependent columns."""
+    """Widths up to 112 take the in-LDS blocked transform, wider ones (up to
+    896) the blocked transform in global memory; both drop the dependent
+    columns."""
     from paper_2409_05572_amd import api
 
     rng = np.random.default_rng(11)
