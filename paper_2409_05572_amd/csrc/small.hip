@@ -1201,11 +1201,12 @@ int invit_lds_per_block(int m) {
 
 // Z = Q ZT with Q = H_0 H_1 ... H_{m-3}; one wave per eigenvector, kept in
 // registers (m <= 1024 -> 16 values per lane). ZT and Z are m x k (ld k).
-__device__ __forceinline__ void backtransform_kernel_body(int bx, int m, int k, const double* __restrict__ tau,
-                                                            const double* __restrict__ Vh,
-                                                            const double* __restrict__ ZT,
-                                                            double* __restrict__ Z) {
-    constexpr int MAXQ = 1024 / 64;
+// MAXQ = values of a column per lane (rows lane + 64 q < m); tau comes from
+// LDS, filled by the whole workgroup.
+template <int MAXQ>
+__device__ __forceinline__ void backtransform_q(int bx, int m, int k, const double* s_tau,
+                                                const double* __restrict__ Vh, const double* __restrict__ ZT,
+                                                double* __restrict__ Z) {
     const int lane = threadIdx.x & 63;
     const int i = bx * 4 + (threadIdx.x >> 6);
     if (i >= k) return;
@@ -1229,7 +1230,7 @@ __device__ __forceinline__ void backtransform_kernel_body(int bx, int m, int k, 
     if (m >= 3) load_v(m - 3, vc);
     for (int kk = m - 3; kk >= 0; --kk) {
         if (kk > 0) load_v(kk - 1, vn);
-        const double tk = tau[kk];
+        const double tk = s_tau[kk];
         if (tk != 0.0) {
             double s = 0.0;
 #pragma unroll
@@ -1246,6 +1247,29 @@ __device__ __forceinline__ void backtransform_kernel_body(int bx, int m, int k, 
         const int j = lane + 64 * q;
         if (j < m) Z[(size_t)j * k + i] = z[q];
     }
+}
+
+// Z = Q ZT for Q = H_0 ... H_{m-3}: one wave per eigenvector, 256 threads.
+// tau is staged in LDS first (each step's scalar was otherwise a dependent
+// L2 load), and the per-lane arrays are sized for m (the rows past m are
+// zero and added nothing).
+__device__ __forceinline__ void backtransform_kernel_body(int bx, int m, int k, const double* __restrict__ tau,
+                                                            const double* __restrict__ Vh,
+                                                            const double* __restrict__ ZT,
+                                                            double* __restrict__ Z) {
+    __shared__ double s_tau[1024];
+    for (int q = threadIdx.x; q + 2 < m; q += 256) s_tau[q] = tau[q];
+    __syncthreads();
+    if (m <= 256)
+        backtransform_q<4>(bx, m, k, s_tau, Vh, ZT, Z);
+    else if (m <= 320)
+        backtransform_q<5>(bx, m, k, s_tau, Vh, ZT, Z);
+    else if (m <= 512)
+        backtransform_q<8>(bx, m, k, s_tau, Vh, ZT, Z);
+    else if (m <= 768)
+        backtransform_q<12>(bx, m, k, s_tau, Vh, ZT, Z);
+    else
+        backtransform_q<16>(bx, m, k, s_tau, Vh, ZT, Z);
 }
 
 __global__ __launch_bounds__(256) void backtransform_kernel(int m, int k, const double* __restrict__ tau,
